@@ -1,0 +1,239 @@
+"""FP64 CPU oracle for PCG with M^-1 = G G^T + eps I (paper Sec. 3.2.1 and
+Appendix A, Algorithm 1).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by ``__graft_entry__.smoke()``
+and by the benchmark's ``cpu_baseline`` leg, never by the library. It wraps
+``oracle.c`` (built to ``liboracle.so`` with gcc, contraction off) with numpy
+arrays and shares no code with the HIP path.
+
+Every function names the passage it follows; see ``oracle.c`` for the
+readings of Algorithm 1 (replacement branch, stopping rule, restart on a
+failed true-residual check).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK = 0
+NOT_CONVERGED = 2
+EINVAL = -1
+EBREAKDOWN = -4
+
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    src = os.path.join(_HERE, "oracle.c")
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", src, "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    global _lib
+    _lib = None
+    return LIB_PATH
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("rr_period", ctypes.c_int32), ("delta_form", ctypes.c_int32), ("stop_rule", ctypes.c_int32),
+                ("threads", ctypes.c_int32)]
+
+
+class _Res(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("relres_rec", ctypes.c_double), ("relres_true", ctypes.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.or_spmv.argtypes = [i32, P, P, P, P, P, ctypes.c_int]
+    lib.or_spmv_t.argtypes = [i32, i32, P, P, P, P, P]
+    lib.or_transpose.argtypes = [i32, i32, P, P, P, P, P, P]
+    lib.or_dot.restype = ctypes.c_double
+    lib.or_dot.argtypes = [i32, P, P]
+    lib.or_apply_precond.argtypes = [i32, P, P, P, ctypes.c_double, P, P]
+    lib.or_pcg.restype = ctypes.c_int
+    lib.or_pcg.argtypes = [i32, P, P, P, P, P, P, P, P, ctypes.POINTER(_Opts), ctypes.POINTER(_Res), P, P]
+    lib.or_tril_nnz.restype = ctypes.c_int64
+    lib.or_tril_nnz.argtypes = [i32, P, P]
+    lib.or_fsai_lower.restype = ctypes.c_int
+    lib.or_fsai_lower.argtypes = [i32, P, P, P, P, P, P]
+    lib.or_g_cfg1.restype = ctypes.c_int
+    lib.or_g_cfg1.argtypes = [i32, P, P, P, P, P, P]
+    lib.or_max_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+@dataclass
+class Mat:
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def n(self):
+        return int(self.rowptr.shape[0] - 1)
+
+    @property
+    def nnz(self):
+        return int(self.col.shape[0])
+
+
+def _mat(m) -> Mat:
+    return Mat(_c(m.rowptr, np.int32), _c(m.col, np.int32), _c(m.val, np.float64))
+
+
+def spmv(A, x, threads: int = 1) -> np.ndarray:
+    """y = A x, rows summed left to right (plain CSR definition)."""
+    A = _mat(A)
+    x = _c(x, np.float64)
+    y = np.empty(A.n, np.float64)
+    _load().or_spmv(A.n, _p(A.rowptr), _p(A.col), _p(A.val), _p(x), _p(y), threads)
+    return y
+
+
+def spmv_t(G, x, ncols: int | None = None) -> np.ndarray:
+    """y = G^T x by scattering rows of G (definition of the transpose product)."""
+    G = _mat(G)
+    ncols = G.n if ncols is None else ncols
+    x = _c(x, np.float64)
+    y = np.empty(ncols, np.float64)
+    _load().or_spmv_t(G.n, ncols, _p(G.rowptr), _p(G.col), _p(G.val), _p(x), _p(y))
+    return y
+
+
+def transpose(G, ncols: int | None = None) -> Mat:
+    G = _mat(G)
+    ncols = G.n if ncols is None else ncols
+    trp = np.empty(ncols + 1, np.int32)
+    tci = np.empty(G.nnz, np.int32)
+    tv = np.empty(G.nnz, np.float64)
+    _load().or_transpose(G.n, ncols, _p(G.rowptr), _p(G.col), _p(G.val), _p(trp), _p(tci), _p(tv))
+    return Mat(trp, tci, tv)
+
+
+def dot(a, b) -> float:
+    a = _c(a, np.float64)
+    b = _c(b, np.float64)
+    return float(_load().or_dot(a.shape[0], _p(a), _p(b)))
+
+
+def apply_precond(G, r, eps: float = 0.0) -> np.ndarray:
+    """s = G (G^T r) + eps r  (Eq. "major": M^-1 = G G^T + eps I)."""
+    G = _mat(G)
+    r = _c(r, np.float64)
+    s = np.empty(G.n, np.float64)
+    _load().or_apply_precond(G.n, _p(G.rowptr), _p(G.col), _p(G.val), float(eps), _p(r), _p(s))
+    return s
+
+
+@dataclass
+class PCGResult:
+    x: np.ndarray
+    status: int
+    iters: int
+    restarts: int
+    relres_rec: float
+    relres_true: float
+    rhist: np.ndarray | None = None
+    xhist: np.ndarray | None = None
+
+
+def pcg(A, G, b, x0=None, *, eps: float = 0.0, tol: float = 1e-8, maxit: int = 2000, rr_period: int = 50,
+        delta_form: int = 0, stop_rule: int = 0, threads: int = 1, history: bool = False,
+        x_history: bool = False) -> PCGResult:
+    """Preconditioned CG, Algorithm 1 (Appendix A) with M^-1 = G G^T + eps I."""
+    A = _mat(A)
+    G = _mat(G)
+    b = _c(b, np.float64)
+    n = A.n
+    x = np.zeros(n, np.float64) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    opts = _Opts(float(eps), float(tol), int(maxit), int(rr_period), int(delta_form), int(stop_rule), int(threads))
+    res = _Res()
+    rh = np.full(maxit + 1, np.nan) if history else None
+    xh = np.full((maxit + 1, n), np.nan) if x_history else None
+    _load().or_pcg(n, _p(A.rowptr), _p(A.col), _p(A.val), _p(G.rowptr), _p(G.col), _p(G.val), _p(b), _p(x),
+                   ctypes.byref(opts), ctypes.byref(res), _p(rh), _p(xh))
+    k = res.iters
+    return PCGResult(x, res.status, k, res.restarts, res.relres_rec, res.relres_true,
+                     None if rh is None else rh[: k + 1], None if xh is None else xh[: k + 1])
+
+
+def tril_nnz(A) -> int:
+    A = _mat(A)
+    return int(_load().or_tril_nnz(A.n, _p(A.rowptr), _p(A.col)))
+
+
+def fsai_lower(A) -> Mat:
+    """Classic FSAI G_L on tril(A)'s pattern (A^-1 ~ G_L^T G_L)."""
+    A = _mat(A)
+    m = tril_nnz(A)
+    grp = np.empty(A.n + 1, np.int32)
+    gci = np.empty(m, np.int32)
+    gv = np.empty(m, np.float64)
+    rc = _load().or_fsai_lower(A.n, _p(A.rowptr), _p(A.col), _p(A.val), _p(grp), _p(gci), _p(gv))
+    if rc != OK:
+        raise ValueError(f"or_fsai_lower failed with {rc}")
+    return Mat(grp, gci, gv)
+
+
+def fsai_g(A) -> Mat:
+    """G = G_L^T, so that M^-1 = G G^T = G_L^T G_L ~ A^-1."""
+    return transpose(fsai_lower(A))
+
+
+def g_cfg1(A) -> Mat:
+    A = _mat(A)
+    m = tril_nnz(A)
+    grp = np.empty(A.n + 1, np.int32)
+    gci = np.empty(m, np.int32)
+    gv = np.empty(m, np.float64)
+    rc = _load().or_g_cfg1(A.n, _p(A.rowptr), _p(A.col), _p(A.val), _p(grp), _p(gci), _p(gv))
+    if rc != OK:
+        raise ValueError(f"or_g_cfg1 failed with {rc}")
+    return Mat(grp, gci, gv)
+
+
+def identity(n: int) -> Mat:
+    return Mat(np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+
+
+def diag_inv_sqrt(A) -> Mat:
+    """G = D^-1/2 (Jacobi: M^-1 = D^-1)."""
+    A = _mat(A)
+    d = np.zeros(A.n)
+    for i in range(A.n):
+        for k in range(A.rowptr[i], A.rowptr[i + 1]):
+            if A.col[k] == i:
+                d[i] = A.val[k]
+    return Mat(np.arange(A.n + 1, dtype=np.int32), np.arange(A.n, dtype=np.int32), 1.0 / np.sqrt(d))
+
+
+def max_threads() -> int:
+    return int(_load().or_max_threads())

@@ -1,0 +1,361 @@
+/*
+ * FP64 CPU oracle for preconditioned CG with a factorized sparse approximate
+ * inverse, M^-1 = G G^T + eps I (paper Sec. 3.2.1, Eq. "major"; PCG in
+ * Appendix A, Algorithm 1).
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the slow, plain reference that the
+ * HIP library is checked against. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it. It shares no code with the HIP
+ * path: its own CSR SpMV, transpose, FSAI and PCG loop, written for obvious
+ * correctness (plain loops, FP64 throughout, no blocking or fusion).
+ *
+ * Build with floating-point contraction off (-ffp-contract=off), so each
+ * product and each sum is rounded on its own, in the order written here.
+ *
+ * Pins (tests/test_oracle.py): dense brute-force matvec, adjoint identity,
+ * the paper's two-hop locality formula for the apply (Eq. "spai-locality"),
+ * finite termination, one-iteration convergence with G = L^-T, monotone
+ * A-norm error, agreement with scipy's CG for G = I and G = D^-1/2,
+ * power-of-two scale invariance, and the FSAI invariants.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* status codes (same numeric meaning as the library's public ones) */
+#define OR_OK 0
+#define OR_NOT_CONVERGED 2
+#define OR_EINVAL (-1)
+#define OR_EBREAKDOWN (-4)
+
+/* ---------------------------------------------------------------- SpMV */
+
+/* y = A x. Each row is summed left to right in CSR order, starting at 0. */
+void or_spmv(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
+             int threads) {
+#pragma omp parallel for num_threads(threads) schedule(static)
+  for (int32_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * x[ci[k]];
+    y[i] = s;
+  }
+}
+
+/* y = G^T x for an nrows x ncols CSR matrix G, by scattering row i of G
+ * scaled by x_i: (G^T x)_j = sum_i G_ij x_i, with i ascending. */
+void or_spmv_t(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t *ci, const double *v,
+               const double *x, double *y) {
+  for (int32_t j = 0; j < ncols; ++j) y[j] = 0.0;
+  for (int32_t i = 0; i < nrows; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) y[ci[k]] += v[k] * x[i];
+}
+
+/* CSR of the transpose by counting: out arrays sized ncols+1 / nnz. */
+void or_transpose(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t *ci, const double *v,
+                  int32_t *trp, int32_t *tci, double *tv) {
+  for (int32_t j = 0; j <= ncols; ++j) trp[j] = 0;
+  for (int32_t k = 0; k < rp[nrows]; ++k) trp[ci[k] + 1]++;
+  for (int32_t j = 0; j < ncols; ++j) trp[j + 1] += trp[j];
+  int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (ncols > 0 ? ncols : 1));
+  for (int32_t j = 0; j < ncols; ++j) pos[j] = trp[j];
+  for (int32_t i = 0; i < nrows; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      int32_t p = pos[ci[k]]++;
+      tci[p] = i;
+      tv[p] = v[k];
+    }
+  free(pos);
+}
+
+/* ------------------------------------------------------------ vectors */
+
+static double dot(int32_t n, const double *a, const double *b, int threads) {
+  double s = 0.0;
+  if (threads <= 1) {
+    for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+  }
+#pragma omp parallel for num_threads(threads) reduction(+ : s) schedule(static)
+  for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+double or_dot(int32_t n, const double *a, const double *b) { return dot(n, a, b, 1); }
+
+/* s = G (G^T r) + eps r, with t = G^T r returned too (Eq. "major"). */
+static void apply_precond(int32_t n, const int32_t *grp, const int32_t *gci, const double *gv, double eps,
+                          const double *r, double *t, double *s, int threads) {
+  or_spmv_t(n, n, grp, gci, gv, r, t);
+  or_spmv(n, grp, gci, gv, t, s, threads);
+#pragma omp parallel for num_threads(threads) schedule(static)
+  for (int32_t i = 0; i < n; ++i) s[i] = s[i] + eps * r[i];
+}
+
+void or_apply_precond(int32_t n, const int32_t *grp, const int32_t *gci, const double *gv, double eps,
+                      const double *r, double *s) {
+  double *t = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+  apply_precond(n, grp, gci, gv, eps, r, t, s, 1);
+  free(t);
+}
+
+/* r = b - A x */
+static void residual(int32_t n, const int32_t *arp, const int32_t *aci, const double *av, const double *b,
+                     const double *x, double *r, int threads) {
+  or_spmv(n, arp, aci, av, x, r, threads);
+#pragma omp parallel for num_threads(threads) schedule(static)
+  for (int32_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+}
+
+/* ----------------------------------------------------------------- PCG */
+
+typedef struct {
+  double eps;      /* shift of M^-1 = G G^T + eps I (absolute units) */
+  double tol;      /* relative tolerance on ||b - A x|| / ||b|| (Sec. 4.1 metric) */
+  int32_t maxit;   /* i_max of Algorithm 1 */
+  int32_t rr_period; /* residual replacement period of Algorithm 1 (50); 0 = never */
+  int32_t delta_form; /* 0: delta = r^T s;  1: delta = ||G^T r||^2 + eps ||r||^2 (same value) */
+  int32_t stop_rule;  /* 0: ||r|| <= tol ||b||, confirmed on the true residual;
+                         1: Algorithm 1's delta_new <= tol^2 delta_0 */
+  int32_t threads;
+} or_opts;
+
+typedef struct {
+  int32_t status;   /* OR_OK, OR_NOT_CONVERGED, OR_EBREAKDOWN, OR_EINVAL */
+  int32_t iters;
+  int32_t restarts; /* times the recurrence claimed convergence but the true residual did not */
+  int32_t pad;
+  double relres_rec;  /* ||r|| / ||b|| of the recurrence residual at exit */
+  double relres_true; /* ||b - A x|| / ||b|| at exit */
+} or_result;
+
+static int finite(double v) { return isfinite(v); }
+
+static double precond_delta(int32_t n, const double *r, const double *t, const double *s, double eps, int form,
+                            int threads) {
+  if (form == 0) return dot(n, r, s, threads);
+  return dot(n, t, t, threads) + eps * dot(n, r, r, threads);
+}
+
+/*
+ * Preconditioned CG (Algorithm 1), read as the standard method of the template
+ * it cites:
+ *   - the "i divisible by 50" branch only chooses how r is formed (recomputed
+ *     as b - A x, or updated as r - alpha q); s, delta, beta and d are updated
+ *     on every iteration; replacement happens for i > 0 only;
+ *   - stopping (stop_rule 0) uses the evaluation metric of Sec. 4.1,
+ *     ||r|| <= tol ||b|| on the recurrence residual, checked at the top of the
+ *     loop; when it holds, the true residual b - A x is formed; if that fails
+ *     the test, r is replaced by it, s and delta are recomputed, d restarts
+ *     from s, and the iteration continues;
+ *   - x0 is whatever x holds on entry; b = 0 returns x = 0 with 0 iterations.
+ * Optional histories: rhist[k] = ||r_k|| (recurrence, k = 0..iters) and
+ * xhist[k*n .. k*n+n) = x_k.
+ */
+int or_pcg(int32_t n, const int32_t *arp, const int32_t *aci, const double *av, const int32_t *grp,
+           const int32_t *gci, const double *gv, const double *b, double *x, const or_opts *o, or_result *res,
+           double *rhist, double *xhist) {
+  memset(res, 0, sizeof(*res));
+  if (n < 0 || o->tol < 0 || o->maxit < 0) { res->status = OR_EINVAL; return OR_EINVAL; }
+  const int th = o->threads > 0 ? o->threads : 1;
+  const double nb = sqrt(dot(n, b, b, th));
+  if (nb == 0.0) {
+    for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+    if (xhist) memcpy(xhist, x, sizeof(double) * n);
+    if (rhist) rhist[0] = 0.0;
+    res->status = OR_OK;
+    return OR_OK;
+  }
+  size_t bytes = sizeof(double) * (size_t)n;
+  double *r = (double *)malloc(bytes), *t = (double *)malloc(bytes), *s = (double *)malloc(bytes);
+  double *d = (double *)malloc(bytes), *q = (double *)malloc(bytes);
+  int status = OR_NOT_CONVERGED;
+  int32_t i = 0;
+
+  residual(n, arp, aci, av, b, x, r, th);
+  apply_precond(n, grp, gci, gv, o->eps, r, t, s, th);
+  memcpy(d, s, bytes);
+  double delta = precond_delta(n, r, t, s, o->eps, o->delta_form, th);
+  const double delta0 = delta;
+  double rnorm = sqrt(dot(n, r, r, th));
+  if (rhist) rhist[0] = rnorm;
+  if (xhist) memcpy(xhist, x, bytes);
+
+  for (;;) {
+    if (o->stop_rule == 0) {
+      if (rnorm <= o->tol * nb) {
+        residual(n, arp, aci, av, b, x, q, th); /* q as scratch: true residual */
+        double tn = sqrt(dot(n, q, q, th));
+        if (tn <= o->tol * nb) { status = OR_OK; break; }
+        /* recurrence drifted: restart from the true residual */
+        memcpy(r, q, bytes);
+        rnorm = tn;
+        apply_precond(n, grp, gci, gv, o->eps, r, t, s, th);
+        delta = precond_delta(n, r, t, s, o->eps, o->delta_form, th);
+        memcpy(d, s, bytes);
+        res->restarts++;
+      }
+    } else {
+      if (!(delta > o->tol * o->tol * delta0)) { status = OR_OK; break; }
+    }
+    if (i >= o->maxit) break;
+
+    or_spmv(n, arp, aci, av, d, q, th);
+    const double gamma = dot(n, d, q, th);
+    if (!(gamma > 0.0) || !finite(gamma)) { status = OR_EBREAKDOWN; break; }
+    const double alpha = delta / gamma;
+#pragma omp parallel for num_threads(th) schedule(static)
+    for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * d[j];
+    if (o->rr_period > 0 && i > 0 && i % o->rr_period == 0) {
+      residual(n, arp, aci, av, b, x, r, th);
+    } else {
+#pragma omp parallel for num_threads(th) schedule(static)
+      for (int32_t j = 0; j < n; ++j) r[j] = r[j] - alpha * q[j];
+    }
+    rnorm = sqrt(dot(n, r, r, th));
+    apply_precond(n, grp, gci, gv, o->eps, r, t, s, th);
+    const double delta_old = delta;
+    delta = precond_delta(n, r, t, s, o->eps, o->delta_form, th);
+    if (!(delta >= 0.0) || !finite(delta)) { status = OR_EBREAKDOWN; i++; break; }
+    const double beta = delta / delta_old;
+#pragma omp parallel for num_threads(th) schedule(static)
+    for (int32_t j = 0; j < n; ++j) d[j] = s[j] + beta * d[j];
+    i++;
+    if (rhist) rhist[i] = rnorm;
+    if (xhist) memcpy(xhist + (size_t)i * n, x, bytes);
+  }
+
+  residual(n, arp, aci, av, b, x, q, th);
+  res->relres_true = sqrt(dot(n, q, q, th)) / nb;
+  res->relres_rec = rnorm / nb;
+  res->iters = i;
+  res->status = status;
+  free(r); free(t); free(s); free(d); free(q);
+  return status;
+}
+
+/* -------------------------------------------------- preconditioner builders */
+
+/* Entry A_ij of a CSR matrix with sorted columns, or 0. */
+static double csr_get(const int32_t *rp, const int32_t *ci, const double *v, int32_t i, int32_t j) {
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] == j) return v[k];
+  return 0.0;
+}
+
+/* Number of entries with column <= row: the size of tril(A)'s pattern. */
+int64_t or_tril_nnz(int32_t n, const int32_t *rp, const int32_t *ci) {
+  int64_t c = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] <= i) c++;
+  return c;
+}
+
+/*
+ * Classic factorized sparse approximate inverse (FSAI, Kolotilina and
+ * Yeremin 1993, cited by the paper as a factorized SPAI): a lower-triangular
+ * G_L on the pattern of tril(A) such that A^-1 ~ G_L^T G_L. For row i with
+ * J = { j <= i : A_ij != 0 } (ascending, so i is last), solve A[J,J] y = e_i
+ * by dense Cholesky and set row i of G_L on J to y / sqrt(y_i).
+ * Output arrays are sized n+1 / or_tril_nnz. Returns OR_OK, or OR_EBREAKDOWN
+ * when a local matrix is not positive definite.
+ */
+int or_fsai_lower(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *grp, int32_t *gci,
+                  double *gv) {
+  int cap = 64;
+  int32_t *J = (int32_t *)malloc(sizeof(int32_t) * cap);
+  double *S = (double *)malloc(sizeof(double) * cap * cap);
+  double *y = (double *)malloc(sizeof(double) * cap);
+  int rc = OR_OK;
+  grp[0] = 0;
+  for (int32_t i = 0; i < n && rc == OR_OK; ++i) {
+    int m = 0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] <= i) {
+        if (m == cap) {
+          cap *= 2;
+          J = (int32_t *)realloc(J, sizeof(int32_t) * cap);
+          S = (double *)realloc(S, sizeof(double) * cap * cap);
+          y = (double *)realloc(y, sizeof(double) * cap);
+        }
+        J[m++] = ci[k];
+      }
+    if (m == 0 || J[m - 1] != i) { rc = OR_EINVAL; break; }
+    for (int a = 0; a < m; ++a)
+      for (int c = 0; c < m; ++c) S[a * m + c] = csr_get(rp, ci, v, J[a], J[c]);
+    /* Cholesky S = L L^T, L stored in the lower triangle of S */
+    for (int c = 0; c < m && rc == OR_OK; ++c) {
+      double dsum = S[c * m + c];
+      for (int k = 0; k < c; ++k) dsum -= S[c * m + k] * S[c * m + k];
+      if (!(dsum > 0.0)) { rc = OR_EBREAKDOWN; break; }
+      double l = sqrt(dsum);
+      S[c * m + c] = l;
+      for (int a = c + 1; a < m; ++a) {
+        double e = S[a * m + c];
+        for (int k = 0; k < c; ++k) e -= S[a * m + k] * S[c * m + k];
+        S[a * m + c] = e / l;
+      }
+    }
+    if (rc != OR_OK) break;
+    /* forward: L z = e_last ; backward: L^T y = z */
+    for (int a = 0; a < m; ++a) {
+      double e = (a == m - 1) ? 1.0 : 0.0;
+      for (int k = 0; k < a; ++k) e -= S[a * m + k] * y[k];
+      y[a] = e / S[a * m + a];
+    }
+    for (int a = m - 1; a >= 0; --a) {
+      double e = y[a];
+      for (int k = a + 1; k < m; ++k) e -= S[k * m + a] * y[k];
+      y[a] = e / S[a * m + a];
+    }
+    if (!(y[m - 1] > 0.0)) { rc = OR_EBREAKDOWN; break; }
+    const double sc = sqrt(y[m - 1]);
+    for (int a = 0; a < m; ++a) {
+      gci[grp[i] + a] = J[a];
+      gv[grp[i] + a] = y[a] / sc;
+    }
+    grp[i + 1] = grp[i] + m;
+  }
+  free(J); free(S); free(y);
+  return rc;
+}
+
+/*
+ * The fixed lower-triangular G of the small 2D Poisson workload: on tril(A)'s
+ * pattern, G_ii = 1/sqrt(A_ii) and G_ij = -0.25 A_ij / sqrt(A_ii A_jj) for
+ * j < i. Output arrays sized n+1 / or_tril_nnz.
+ */
+int or_g_cfg1(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *grp, int32_t *gci,
+              double *gv) {
+  double *dg = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+  for (int32_t i = 0; i < n; ++i) {
+    dg[i] = csr_get(rp, ci, v, i, i);
+    if (!(dg[i] > 0.0)) { free(dg); return OR_EINVAL; }
+  }
+  int64_t p = 0;
+  grp[0] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      int32_t j = ci[k];
+      if (j > i) continue;
+      gci[p] = j;
+      gv[p] = (j == i) ? 1.0 / sqrt(dg[i]) : -0.25 * v[k] / sqrt(dg[i] * dg[j]);
+      p++;
+    }
+    grp[i + 1] = (int32_t)p;
+  }
+  free(dg);
+  return OR_OK;
+}
+
+int or_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

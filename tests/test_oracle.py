@@ -1,0 +1,386 @@
+"""Pins for the FP64 oracle, against facts that do not come from the oracle
+itself: dense brute force, exact rational arithmetic, closed forms, textbook
+special cases (scipy's CG), and invariants of CG and FSAI."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+from paper_2510_27517_amd import inputs
+from paper_2510_27517_amd.inputs import CSR
+
+
+def _random_csr(n, m, density, seed, empty_rows=()):
+    rng = np.random.default_rng(seed)
+    d = np.where(rng.random((n, m)) < density, rng.standard_normal((n, m)), 0.0)
+    for r in empty_rows:
+        d[r, :] = 0.0
+    rp, cols, vals = [0], [], []
+    for i in range(n):
+        for j in range(m):
+            if d[i, j] != 0.0:
+                cols.append(j)
+                vals.append(d[i, j])
+        rp.append(len(cols))
+    return CSR(np.array(rp, np.int32), np.array(cols, np.int32), np.array(vals)), d
+
+
+def _dense_spd(n, seed, cond=50.0):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.geomspace(1.0, cond, n)
+    return (Q * lam) @ Q.T
+
+
+# ------------------------------------------------------------------ SpMV (P1, P2)
+
+@pytest.mark.parametrize("n,density,seed", [(1, 1.0, 0), (17, 0.3, 1), (64, 0.1, 2), (200, 0.03, 3)])
+def test_spmv_matches_dense(n, density, seed):
+    A, d = _random_csr(n, n, density, seed, empty_rows=(0,) if n > 1 else ())
+    x = np.random.default_rng(seed + 100).standard_normal(n)
+    y = oracle.spmv(A, x)
+    bound = (np.diff(A.rowptr).max(initial=0) + 1) * 2.0 ** -53 * (np.abs(d) @ np.abs(x))
+    assert np.all(np.abs(y - d @ x) <= bound + 1e-300)
+    if n > 1:
+        assert y[0] == 0.0
+
+
+def test_spmv_exact_on_integers():
+    A, d = _random_csr(50, 50, 0.2, 9)
+    A.val[:] = np.round(A.val * 8)
+    d = A.to_dense()
+    x = np.arange(50, dtype=np.float64) - 20
+    assert np.array_equal(oracle.spmv(A, x), d @ x)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (33, 4), (150, 5)])
+def test_spmv_t_dense_and_adjoint(n, seed):
+    G, d = _random_csr(n, n, 0.15 if n > 1 else 1.0, seed)
+    rng = np.random.default_rng(seed)
+    r, y = rng.standard_normal(n), rng.standard_normal(n)
+    gt = oracle.spmv_t(G, r)
+    assert np.allclose(gt, d.T @ r, rtol=0, atol=1e-13 * (np.abs(d.T) @ np.abs(r) + 1))
+    assert abs(gt @ y - r @ oracle.spmv(G, y)) <= 1e-12 * (np.abs(gt) @ np.abs(y) + 1)
+
+
+def test_transpose_dense_and_involution():
+    G, d = _random_csr(40, 40, 0.2, 6, empty_rows=(3, 7))
+    T = oracle.transpose(G)
+    assert np.array_equal(CSR(T.rowptr, T.col, T.val).to_dense(), d.T)
+    TT = oracle.transpose(T)
+    assert np.array_equal(TT.rowptr, G.rowptr) and np.array_equal(TT.col, G.col) and np.array_equal(TT.val, G.val)
+    for i in range(40):
+        assert np.all(np.diff(T.col[T.rowptr[i]:T.rowptr[i + 1]]) > 0)
+
+
+# --------------------------------------------------------- apply, locality (P3)
+
+@pytest.mark.parametrize("eps", [0.0, 0.37])
+def test_apply_matches_locality_formula(eps):
+    """Eq. "spai-locality": s_j = eps r_j + sum_l G_jl sum_k G_kl r_k, with
+    G on A's pattern, evaluated as the literal double sum over the graph."""
+    A = inputs.poisson(2, 5, sigma=0.5, seed=1)
+    rng = np.random.default_rng(2)
+    G = CSR(A.rowptr.copy(), A.col.copy(), rng.standard_normal(A.nnz))
+    r = rng.standard_normal(A.n)
+    Gd = G.to_dense()
+    n = A.n
+    s_ref = np.empty(n)
+    for j in range(n):
+        acc = eps * r[j]
+        for l in range(n):
+            if Gd[j, l] == 0.0:
+                continue
+            inner = sum(Gd[k, l] * r[k] for k in range(n) if Gd[k, l] != 0.0)
+            acc += Gd[j, l] * inner
+        s_ref[j] = acc
+    s = oracle.apply_precond(G, r, eps)
+    assert np.allclose(s, s_ref, rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------------------ PCG (P4-P8)
+
+def _exact_pcg(Ad, Gd, b, eps, steps):
+    """CG of Algorithm 1 in exact rational arithmetic (no replacement needed)."""
+    n = len(b)
+    A = [[Fraction(v) for v in row] for row in Ad]
+    G = [[Fraction(v) for v in row] for row in Gd]
+    e = Fraction(eps)
+    Minv = [[sum(G[i][k] * G[j][k] for k in range(n)) + (e if i == j else 0) for j in range(n)] for i in range(n)]
+    mv = lambda M, v: [sum(M[i][j] * v[j] for j in range(n)) for i in range(n)]
+    dotf = lambda a, c: sum(ai * ci for ai, ci in zip(a, c))
+    x = [Fraction(0)] * n
+    r = [Fraction(v) for v in b]
+    d = mv(Minv, r)
+    delta = dotf(r, d)
+    xs, rs = [list(x)], [dotf(r, r)]
+    for _ in range(steps):
+        if delta == 0:
+            break
+        q = mv(A, d)
+        alpha = delta / dotf(d, q)
+        x = [xi + alpha * di for xi, di in zip(x, d)]
+        r = [ri - alpha * qi for ri, qi in zip(r, q)]
+        s = mv(Minv, r)
+        dnew = dotf(r, s)
+        beta = dnew / delta
+        delta = dnew
+        d = [si + beta * di for si, di in zip(s, d)]
+        xs.append(list(x))
+        rs.append(dotf(r, r))
+    return xs, rs
+
+
+@pytest.mark.parametrize("gkind,eps", [("identity", 0.0), ("diag", 0.0), ("lower", 0.25)])
+def test_pcg_matches_exact_rational_cg(gkind, eps):
+    Ad = np.array([[6, -1, 0, 2, 0], [-1, 5, -2, 0, 0], [0, -2, 7, -1, 1], [2, 0, -1, 4, 0], [0, 0, 1, 0, 3]], float)
+    b = np.array([1.0, -2.0, 0.5, 3.0, -1.0])
+    if gkind == "identity":
+        Gd = np.eye(5)
+    elif gkind == "diag":
+        Gd = np.diag([0.5, 0.25, 1.0, 0.5, 0.5])
+    else:
+        Gd = np.tril(np.array([[1, 0, 0, 0, 0], [-0.25, 0.5, 0, 0, 0], [0, 0.125, 1, 0, 0],
+                               [0.5, 0, -0.25, 1, 0], [0, 0, 0.25, 0, 0.5]], float))
+    xs, rs = _exact_pcg(Ad, Gd, b, eps, 5)
+    assert rs[-1] == 0  # exact CG terminates in n steps
+    res = oracle.pcg(CSR.from_dense(Ad), CSR.from_dense(Gd), b, eps=eps, tol=1e-13, maxit=20,
+                     history=True, x_history=True)
+    assert res.status == oracle.OK
+    for k in range(len(xs) - 1):
+        xk = np.array([float(v) for v in xs[k]])
+        assert np.allclose(res.xhist[k], xk, rtol=1e-12, atol=1e-13)
+        assert abs(res.rhist[k] - np.sqrt(float(rs[k]))) <= 1e-12 * np.sqrt(float(rs[0]))
+    xstar = np.linalg.solve(Ad, b)
+    assert np.allclose(res.x, xstar, rtol=1e-12, atol=1e-13)
+    assert res.iters <= 6
+
+
+@pytest.mark.parametrize("n,seed", [(12, 0), (30, 1)])
+def test_finite_termination(n, seed):
+    Ad = _dense_spd(n, seed, cond=30.0)
+    b = np.random.default_rng(seed).standard_normal(n)
+    res = oracle.pcg(CSR.from_dense(Ad), oracle.identity(n), b, tol=1e-12, maxit=10 * n)
+    # exact CG stops after n steps (pinned exactly by the rational test); in
+    # FP64 the Krylov basis loses orthogonality, so allow a few extra steps
+    assert res.status == oracle.OK and res.iters <= n + n // 4 + 2
+    assert np.allclose(res.x, np.linalg.solve(Ad, b), rtol=1e-10)
+
+
+def test_distinct_eigenvalues_terminate_early():
+    n, m = 40, 5
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.repeat([1.0, 2.0, 3.5, 5.0, 9.0], n // m)
+    Ad = (Q * lam) @ Q.T
+    Ad = (Ad + Ad.T) / 2
+    res = oracle.pcg(CSR.from_dense(Ad), oracle.identity(n), rng.standard_normal(n), tol=1e-10, maxit=100)
+    assert res.status == oracle.OK and res.iters <= m + 1
+
+
+def test_exact_inverse_preconditioner_one_iteration():
+    """G = L^-T for A = L L^T gives M^-1 = A^-1: one iteration. The other
+    orientation, G = L^-1 (G G^T != A^-1), must not."""
+    n = 12
+    Ad = _dense_spd(n, 4, cond=1e3)
+    L = np.linalg.cholesky(Ad)
+    Linv = np.linalg.inv(L)
+    b = np.random.default_rng(4).standard_normal(n)
+    A = CSR.from_dense(Ad)
+    good = oracle.pcg(A, CSR.from_dense(Linv.T), b, tol=1e-8, maxit=50)
+    assert good.status == oracle.OK and good.iters == 1
+    bad = oracle.pcg(A, CSR.from_dense(Linv), b, tol=1e-8, maxit=50)
+    assert bad.iters > 3
+
+
+def test_monotone_energy_error():
+    A = inputs.poisson(2, 12, sigma=1.0, seed=2)
+    b = inputs.rhs(A.n, 1)
+    Ad = A.to_dense()
+    xstar = np.linalg.solve(Ad, b)
+    for G in (oracle.fsai_g(A), oracle.identity(A.n)):
+        res = oracle.pcg(A, G, b, tol=1e-10, maxit=500, x_history=True)
+        e = res.xhist - xstar
+        en = np.sqrt(np.einsum("ki,ij,kj->k", e, Ad, e))
+        assert np.all(np.diff(en) <= 1e-12 * en[0])
+        assert en[-1] < 1e-6 * en[0]
+
+
+@pytest.mark.parametrize("gkind", ["identity", "jacobi"])
+def test_matches_scipy_cg(gkind):
+    A = inputs.poisson(2, 20, sigma=0.5, seed=7)
+    b = inputs.rhs(A.n, 3)
+    G = oracle.identity(A.n) if gkind == "identity" else oracle.diag_inv_sqrt(A)
+    Gs = CSR(G.rowptr, G.col, G.val).to_scipy()
+    M = spla.aslinearoperator(Gs @ Gs.T)
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+
+    xs, info = spla.cg(A.to_scipy(), b, rtol=1e-8, atol=0.0, maxiter=2000, M=M, callback=cb)
+    assert info == 0
+    res = oracle.pcg(A, G, b, tol=1e-8, maxit=2000, rr_period=0)
+    assert res.status == oracle.OK
+    assert abs(res.iters - count[0]) <= 1
+    assert np.linalg.norm(res.x - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_power_of_two_scale_invariance_bitwise():
+    """CG is invariant to the scale of A (Sec. 3.3): A -> 4A, G -> G/2 leaves
+    every step's rounding unchanged, so x scales by exactly 1/4."""
+    A = inputs.poisson(3, 6, sigma=1.0, seed=8)
+    b = inputs.rhs(A.n, 8)
+    G = oracle.fsai_g(A)
+    r1 = oracle.pcg(A, G, b, tol=1e-10, maxit=500)
+    A4 = CSR(A.rowptr, A.col, A.val * 4.0)
+    G2 = oracle.Mat(G.rowptr, G.col, G.val * 0.5)
+    r2 = oracle.pcg(A4, G2, b, tol=1e-10, maxit=500)
+    assert r1.iters == r2.iters
+    assert np.array_equal(r2.x * 4.0, r1.x)
+
+
+def test_delta_forms_agree():
+    A = inputs.poisson(3, 8, sigma=1.0, seed=9)
+    b = inputs.rhs(A.n, 9)
+    G = oracle.fsai_g(A)
+    for eps in (0.0, 1e-3):
+        a = oracle.pcg(A, G, b, eps=eps, delta_form=0)
+        c = oracle.pcg(A, G, b, eps=eps, delta_form=1)
+        assert a.status == c.status == oracle.OK
+        assert abs(a.iters - c.iters) <= 1
+        assert np.linalg.norm(a.x - c.x) <= 1e-9 * np.linalg.norm(a.x)
+
+
+def test_cg_iteration_bound_closed_form():
+    """Constant 2D Poisson, N=64: lambda_jk = 4 - 2cos(j pi/65) - 2cos(k pi/65).
+    The classical CG bound ||r_k||/||b|| <= sqrt(kappa) 2 rho^k caps the
+    iteration count of plain CG."""
+    N = 64
+    A = inputs.poisson(2, N)
+    b = inputs.rhs(A.n, 0)
+    th = np.arange(1, N + 1) * np.pi / (N + 1)
+    lam = (2 - 2 * np.cos(th))[:, None] + (2 - 2 * np.cos(th))[None, :]
+    kappa = lam.max() / lam.min()
+    assert abs(kappa - 1711.6) < 0.5
+    rho = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    bound = np.log(2 * np.sqrt(kappa) / 1e-8) / -np.log(rho)
+    res = oracle.pcg(A, oracle.identity(A.n), b, tol=1e-8)
+    assert res.status == oracle.OK and res.iters <= bound
+    g1 = oracle.pcg(A, oracle.g_cfg1(A), b, tol=1e-8)
+    assert g1.status == oracle.OK and g1.iters < res.iters
+
+
+def test_edge_cases():
+    A = inputs.poisson(2, 4)
+    G = oracle.identity(A.n)
+    z = oracle.pcg(A, G, np.zeros(A.n), x0=np.ones(A.n))
+    assert z.status == oracle.OK and z.iters == 0 and np.all(z.x == 0)
+    b = inputs.rhs(A.n)
+    x0 = np.full(A.n, 0.5)
+    m0 = oracle.pcg(A, G, b, x0=x0, maxit=0)
+    assert m0.status == oracle.NOT_CONVERGED and m0.iters == 0 and np.array_equal(m0.x, x0)
+    one = oracle.pcg(CSR(np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0])),
+                     oracle.identity(1), np.array([2.0]))
+    assert one.status == oracle.OK and one.iters == 1 and one.x[0] == 0.5
+    neg = CSR(A.rowptr, A.col, -A.val)
+    br = oracle.pcg(neg, G, b)
+    assert br.status == oracle.EBREAKDOWN
+    nanb = b.copy()
+    nanb[3] = np.nan
+    assert oracle.pcg(A, G, nanb).status != oracle.OK
+
+
+def test_restart_on_drifted_recurrence_terminates():
+    A = inputs.poisson(2, 32, sigma=1.0, seed=4)
+    b = inputs.rhs(A.n, 4)
+    res = oracle.pcg(A, oracle.identity(A.n), b, tol=1e-15, maxit=600, rr_period=0)
+    assert res.iters <= 600
+    if res.status == oracle.OK:
+        assert res.relres_true <= 1e-15
+    else:
+        assert res.status == oracle.NOT_CONVERGED
+
+
+# ------------------------------------------------------------------ FSAI (P9)
+
+def test_fsai_invariants_on_tril_pattern():
+    A = inputs.poisson(3, 6, sigma=1.0, seed=5)
+    GL = oracle.fsai_lower(A)
+    Ld = CSR(GL.rowptr, GL.col, GL.val).to_dense()
+    Ad = A.to_dense()
+    assert np.array_equal(Ld != 0, np.tril(Ad) != 0)
+    P = Ld @ Ad @ Ld.T
+    assert np.allclose(np.diag(P), 1.0, atol=1e-13)
+    GA = Ld @ Ad
+    for i in range(A.n):
+        for j in GL.col[GL.rowptr[i]:GL.rowptr[i + 1]]:
+            if j != i:
+                assert abs(GA[i, j]) < 1e-13 * np.abs(Ad).max()
+
+    def kaporin(M):
+        ev = np.linalg.eigvalsh(M)
+        return ev.mean() / np.exp(np.log(ev).mean())
+
+    dinv = 1 / np.sqrt(np.diag(Ad))
+    assert kaporin(P) <= kaporin(Ad * dinv[:, None] * dinv[None, :]) + 1e-12
+
+
+def test_fsai_full_pattern_is_inverse_cholesky():
+    n = 12
+    Ad = _dense_spd(n, 7, cond=1e3)
+    GL = oracle.fsai_lower(CSR.from_dense(Ad))
+    Ld = CSR(GL.rowptr, GL.col, GL.val).to_dense()
+    assert np.allclose(Ld, np.linalg.inv(np.linalg.cholesky(Ad)), atol=1e-10)
+
+
+def test_fsai_orientation_beats_flipped_on_variable_coefficients():
+    A = inputs.poisson(3, 16, sigma=1.0, seed=0)
+    b = inputs.rhs(A.n, 0)
+    good = oracle.pcg(A, oracle.fsai_g(A), b)
+    flipped = oracle.pcg(A, oracle.fsai_lower(A), b)
+    jac = oracle.pcg(A, oracle.diag_inv_sqrt(A), b)
+    assert good.status == flipped.status == jac.status == oracle.OK
+    assert good.iters < flipped.iters and good.iters < jac.iters
+
+
+def test_cfg1_g_closed_form_values():
+    A = inputs.poisson(2, 8)
+    G = oracle.g_cfg1(A)
+    for i in range(A.n):
+        for k in range(G.rowptr[i], G.rowptr[i + 1]):
+            j = G.col[k]
+            assert j <= i
+            assert G.val[k] == (0.5 if j == i else 0.0625)
+    assert G.nnz == (A.nnz + A.n) // 2
+
+
+@pytest.mark.parametrize("period", [1, 5])
+def test_residual_replacement_schedule(period):
+    """Algorithm 1 recomputes r = b - A x when the iteration index i is a
+    positive multiple of the period (read: i > 0). After such an iteration the
+    recurrence residual is bit-identical to b - A x formed from the stored
+    iterate; after the others it is the updated r - alpha q."""
+    A = inputs.poisson(2, 16, sigma=1.0, seed=3)
+    b = inputs.rhs(A.n, 3)
+    res = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-12, maxit=40, rr_period=period, history=True,
+                     x_history=True)
+    assert res.iters >= 12
+    replaced, updated = 0, 0
+    for k in range(1, 12):
+        i = k - 1
+        rt = b - oracle.spmv(A, res.xhist[k])
+        tn = np.sqrt(oracle.dot(rt, rt))
+        if i > 0 and i % period == 0:
+            assert res.rhist[k] == tn
+            replaced += 1
+        else:
+            updated += res.rhist[k] != tn  # the update r - alpha q rounds differently
+            if i == 0:
+                assert res.rhist[k] != tn  # no replacement at i = 0
+    assert replaced >= 2
+    if period > 1:
+        assert updated >= 3
