@@ -1,0 +1,156 @@
+/*
+ * pcg.h - C ABI of the MI355X (gfx950) preconditioned conjugate-gradient
+ * library with a factorized sparse approximate inverse preconditioner
+ *
+ *     M^-1 = G G^T + eps I                      (paper Sec. 3.2.1, Eq. "major")
+ *
+ * applied as two sparse matrix-vector products (t = G^T r, then
+ * s = G t + eps r) with no triangular solve (Sec. 3.2.1, the paragraph after
+ * Eq. "major"), inside the standard PCG iteration of Appendix A,
+ * Algorithm 1. The solver's stopping metric is the relative residual
+ * ||b - A x|| / ||b|| of Sec. 4.1.
+ *
+ * Conventions for every entry point
+ *   - Return value: PCG_OK (0) or a status code below. No C++ exception
+ *     crosses this interface. pcg_last_error() gives a message for the
+ *     context's most recent failure.
+ *   - Matrices are square CSR: int32 row pointers (n+1 entries, rowptr[0] = 0,
+ *     non-decreasing), int32 column indices (nnz entries, strictly ascending
+ *     within each row, in [0, n)), float64 values. nnz < 2^31.
+ *   - Input pointers are borrowed for the duration of the call only: the
+ *     library copies what it needs into its own device memory (cast to the
+ *     storage types of pcg_config). `on_device` = 0 means host pointers,
+ *     1 means device pointers of the context's GPU.
+ *   - Vectors at the boundary are float64 (length n). The solution pointer x
+ *     is owned by the caller; it is read as x0 and written before return.
+ *   - One context serves one device and one HIP stream; calls on one context
+ *     must not overlap.
+ */
+#ifndef PCG_H
+#define PCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PCG_OK 0
+#define PCG_PENDING 1        /* (batch) request queued or running */
+#define PCG_NOT_CONVERGED 2  /* maxit reached; x holds the last iterate */
+#define PCG_EINVAL (-1)      /* bad argument or malformed CSR */
+#define PCG_ESTATE (-2)      /* call out of order (e.g. solve before set_matrix) or size mismatch */
+#define PCG_ENOMEM (-3)      /* device allocation failed or budget exceeded */
+#define PCG_EBREAKDOWN (-4)  /* d^T A d <= 0, r^T M^-1 r < 0, or NaN/Inf: A or M not SPD */
+#define PCG_EDEVICE (-5)     /* HIP runtime error; the context must be destroyed */
+
+/* storage types */
+#define PCG_F64 0
+#define PCG_F32 1
+#define PCG_BF16 2
+#define PCG_F16 3
+
+/* preconditioner kinds for pcg_build_precond / pcg_build_g_host */
+#define PCG_G_FSAI 1     /* classic FSAI (Kolotilina-Yeremin, cited in Sec. 3.2.1): G = G_L^T, G_L lower on tril(A) */
+#define PCG_G_FIXED 2    /* lower G on tril(A): G_ii = 1/sqrt(A_ii), G_ij = -0.25 A_ij / sqrt(A_ii A_jj) */
+#define PCG_G_JACOBI 3   /* G = D^-1/2, so M^-1 = D^-1 */
+#define PCG_G_IDENTITY 4 /* G = I: plain CG */
+
+/* operators for pcg_matvec */
+#define PCG_OP_A 0    /* y = A x */
+#define PCG_OP_GT 1   /* y = G^T x */
+#define PCG_OP_G 2    /* y = G x */
+#define PCG_OP_MINV 3 /* y = G (G^T x) + eps x  (the preconditioner apply, Eq. "major") */
+
+typedef struct pcg_ctx pcg_ctx;
+
+typedef struct {
+  int device;        /* HIP device ordinal */
+  void *stream;      /* hipStream_t to run on; NULL: the library creates its own */
+  int vec_dtype;     /* PCG_F64 or PCG_F32: Krylov vectors and SpMV accumulation */
+  int a_dtype;       /* PCG_F64 or PCG_F32: stored values of A (must equal vec_dtype) */
+  int g_dtype;       /* PCG_F64, PCG_F32, PCG_BF16 or PCG_F16: stored values of G and G^T
+                        (F64 only with F64 vectors; half types with F32 vectors) */
+  int rr_period;     /* recompute r = b - A x every rr_period iterations (Algorithm 1 uses 50); 0 = never */
+  double eps;        /* shift of M^-1 = G G^T + eps I, absolute units (default 0) */
+  int refine;        /* 1: FP64 iterative refinement around a vec_dtype = F32 inner PCG */
+  double inner_tol;  /* relative tolerance of each inner solve under refinement (default 1e-4) */
+  int max_outer;     /* refinement steps at most (default 30) */
+  int graph_iters;   /* iterations per captured HIP graph replay (default 10; 0 = plain launches) */
+  int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */
+  int reserved[8];
+} pcg_config;
+
+typedef struct {
+  int status;          /* PCG_OK, PCG_NOT_CONVERGED or a negative code */
+  int iters;           /* CG iterations (summed over refinement steps) */
+  int outer_iters;     /* refinement steps (0 without refinement) */
+  int restarts;        /* times the recurrence residual met tol but b - A x did not (restart from it) */
+  double relres_true;  /* ||b - A x|| / ||b|| at exit, formed in the vector precision (FP64 under refinement) */
+  double relres_rec;   /* recurrence ||r|| / ||b|| at exit */
+  double t_solve_ms;   /* wall time of the solve on the device stream */
+  double bytes_per_iter; /* algorithmic HBM bytes of one iteration (A, G^T, G once; 12 vector streams) */
+} pcg_result;
+
+/* Fills cfg with the defaults: device 0, own stream, all FP64, rr_period 50,
+ * eps 0, no refinement, inner_tol 1e-4, max_outer 30, graph_iters 10,
+ * grid_mult 8. */
+void pcg_config_default(pcg_config *cfg);
+
+/* Creates a context on cfg->device. Returns PCG_EDEVICE if no usable GPU,
+ * PCG_EINVAL for an unsupported dtype combination. *out is NULL on failure. */
+int pcg_create(const pcg_config *cfg, pcg_ctx **out);
+void pcg_destroy(pcg_ctx *ctx);
+
+/* Sets the SPD matrix A (validated; see conventions). Replaces any previous A
+ * and drops a preconditioner of another size. */
+int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                   const double *val, int on_device);
+
+/* Sets G of M^-1 = G G^T + eps I (Eq. "major"), any sparsity pattern
+ * (the paper's learned G uses A's full pattern, Sec. 3.2.2). The library also
+ * stores G^T as CSR so both products are row-wise. n must equal A's n. */
+int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                    const double *val, int on_device);
+
+/* Builds G from the current A on the host (PCG_G_FSAI, PCG_G_FIXED,
+ * PCG_G_JACOBI, PCG_G_IDENTITY) and sets it. A must have been set from host
+ * memory or will be downloaded once. */
+int pcg_build_precond(pcg_ctx *ctx, int kind);
+
+/* Solves A x = b by PCG (Algorithm 1) to ||b - A x|| <= tol ||b||, at most
+ * maxit iterations (per refinement step under refinement). x holds x0 on
+ * entry. b = 0 gives x = 0. res may be NULL. Returns PCG_OK,
+ * PCG_NOT_CONVERGED, PCG_EBREAKDOWN, or an error code. */
+int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, int on_device, pcg_result *res);
+
+/* y = op(x) with the stored A, G or G^T, or the preconditioner apply, in the
+ * context's vector precision (values at the boundary are float64). */
+int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device);
+
+/* Host-only helpers (no GPU needed). */
+
+/* Checks a CSR matrix against the conventions above; require_diag = 1 also
+ * demands a stored diagonal entry in every row. */
+int pcg_validate_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col, int require_diag);
+
+/* Number of nonzeros of G for kind on A's pattern (-1 on error). */
+int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col);
+
+/* Builds G of kind from A into caller arrays sized n+1 / pcg_g_nnz. */
+int pcg_build_g_host(int kind, int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                     int32_t *g_rowptr, int32_t *g_col, double *g_val);
+
+/* Algorithmic device bytes of one PCG iteration: A, G^T and G read once,
+ * their row pointers, and 12 vector streams of n entries (vec bytes each). */
+double pcg_bytes_per_iter(int32_t n, int64_t nnz_a, int64_t nnz_g, int a_dtype, int g_dtype, int vec_dtype);
+
+const char *pcg_last_error(const pcg_ctx *ctx);
+const char *pcg_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCG_H */

@@ -1,0 +1,261 @@
+"""Python binding of the gfx950 PCG library (include/pcg.h).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels. Arrays may be numpy (host) or torch tensors on the GPU (device
+pointers are passed straight through). Importing works anywhere; the first
+call that needs the library raises if ``libpcg.so`` is missing, and creating
+a solver raises if no GPU is usable. There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcg.so")
+
+OK, PENDING, NOT_CONVERGED = 0, 1, 2
+EINVAL, ESTATE, ENOMEM, EBREAKDOWN, EDEVICE = -1, -2, -3, -4, -5
+F64, F32, BF16, F16 = 0, 1, 2, 3
+G_FSAI, G_FIXED, G_JACOBI, G_IDENTITY = 1, 2, 3, 4
+OP_A, OP_GT, OP_G, OP_MINV = 0, 1, 2, 3
+
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
+
+# every symbol include/pcg.h declares
+EXPORTS = [
+    "pcg_config_default", "pcg_create", "pcg_destroy", "pcg_set_matrix", "pcg_set_precond", "pcg_build_precond",
+    "pcg_solve", "pcg_matvec", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
+    "pcg_last_error", "pcg_strerror",
+]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("vec_dtype", ctypes.c_int),
+        ("a_dtype", ctypes.c_int), ("g_dtype", ctypes.c_int), ("rr_period", ctypes.c_int),
+        ("eps", ctypes.c_double), ("refine", ctypes.c_int), ("inner_tol", ctypes.c_double),
+        ("max_outer", ctypes.c_int), ("graph_iters", ctypes.c_int), ("grid_mult", ctypes.c_int),
+        ("reserved", ctypes.c_int * 8),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
+        ("restarts", ctypes.c_int), ("relres_true", ctypes.c_double), ("relres_rec", ctypes.c_double),
+        ("t_solve_ms", ctypes.c_double), ("bytes_per_iter", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libpcg.so (raises RuntimeError when it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, dbl, c_int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.pcg_config_default.argtypes = [ctypes.POINTER(Config)]
+    lib.pcg_config_default.restype = None
+    lib.pcg_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(P)]
+    lib.pcg_destroy.argtypes = [P]
+    lib.pcg_destroy.restype = None
+    lib.pcg_set_matrix.argtypes = [P, i32, i64, P, P, P, c_int]
+    lib.pcg_set_precond.argtypes = [P, i32, i64, P, P, P, c_int]
+    lib.pcg_build_precond.argtypes = [P, c_int]
+    lib.pcg_solve.argtypes = [P, P, P, dbl, c_int, c_int, ctypes.POINTER(Result)]
+    lib.pcg_matvec.argtypes = [P, c_int, P, P, c_int]
+    lib.pcg_validate_csr.argtypes = [i32, i64, P, P, c_int]
+    lib.pcg_g_nnz.argtypes = [c_int, i32, P, P]
+    lib.pcg_g_nnz.restype = i64
+    lib.pcg_build_g_host.argtypes = [c_int, i32, P, P, P, P, P, P]
+    lib.pcg_bytes_per_iter.argtypes = [i32, i64, i64, c_int, c_int, c_int]
+    lib.pcg_bytes_per_iter.restype = dbl
+    lib.pcg_last_error.argtypes = [P]
+    lib.pcg_last_error.restype = ctypes.c_char_p
+    lib.pcg_strerror.argtypes = [c_int]
+    lib.pcg_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class PCGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def default_config(**kw) -> Config:
+    cfg = Config()
+    load().pcg_config_default(ctypes.byref(cfg))
+    for k, v in kw.items():
+        if k in ("vec_dtype", "a_dtype", "g_dtype") and isinstance(v, str):
+            v = DTYPES[v]
+        setattr(cfg, k, v)
+    return cfg
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """(pointer, on_device) of a numpy array or a torch tensor."""
+    if _is_torch(a):
+        return a.data_ptr(), int(a.is_cuda)
+    return a.ctypes.data, 0
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------- host-only
+
+def validate_csr(rowptr, col, n=None, require_diag=True) -> int:
+    rp = _host(rowptr, np.int32)
+    ci = _host(col, np.int32)
+    n = rp.shape[0] - 1 if n is None else n
+    return int(load().pcg_validate_csr(n, ci.shape[0], rp.ctypes.data, ci.ctypes.data, int(require_diag)))
+
+
+def build_g_host(kind: int, A):
+    """G of `kind` from A, built by the library's host code: (rowptr, col, val)."""
+    lib = load()
+    rp, ci, v = _host(A.rowptr, np.int32), _host(A.col, np.int32), _host(A.val, np.float64)
+    n = rp.shape[0] - 1
+    m = int(lib.pcg_g_nnz(kind, n, rp.ctypes.data, ci.ctypes.data))
+    if m < 0:
+        raise PCGError(EINVAL, "pcg_g_nnz")
+    grp = np.empty(n + 1, np.int32)
+    gci = np.empty(m, np.int32)
+    gv = np.empty(m, np.float64)
+    st = lib.pcg_build_g_host(kind, n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, grp.ctypes.data,
+                              gci.ctypes.data, gv.ctypes.data)
+    if st != OK:
+        raise PCGError(st, "pcg_build_g_host")
+    return grp, gci, gv
+
+
+def bytes_per_iter(n, nnz_a, nnz_g, a_dtype=F64, g_dtype=F64, vec_dtype=F64) -> float:
+    return float(load().pcg_bytes_per_iter(n, nnz_a, nnz_g, a_dtype, g_dtype, vec_dtype))
+
+
+# ------------------------------------------------------------------ solver
+
+@dataclass
+class SolveOut:
+    x: object
+    status: int
+    iters: int
+    outer_iters: int
+    restarts: int
+    relres_true: float
+    relres_rec: float
+    t_solve_ms: float
+    bytes_per_iter: float
+
+
+class Solver:
+    """One library context (one device, one stream)."""
+
+    def __init__(self, config: Config | None = None, **kw):
+        self._lib = load()
+        self.cfg = config if config is not None else default_config(**kw)
+        h = ctypes.c_void_p()
+        st = self._lib.pcg_create(ctypes.byref(self.cfg), ctypes.byref(h))
+        if st != OK:
+            raise PCGError(st, "pcg_create: " + self._lib.pcg_strerror(st).decode())
+        self._h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, what, allow=(OK,)):
+        if st not in allow:
+            msg = self._lib.pcg_last_error(self._h).decode()
+            raise PCGError(st, f"{what}: {msg or self._lib.pcg_strerror(st).decode()}")
+        return st
+
+    def _csr_args(self, rowptr, col, val):
+        if _is_torch(rowptr):
+            n = rowptr.shape[0] - 1
+            return n, col.shape[0], rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), int(rowptr.is_cuda), None
+        rp, ci, v = _host(rowptr, np.int32), _host(col, np.int32), _host(val, np.float64)
+        keep = (rp, ci, v)
+        return rp.shape[0] - 1, ci.shape[0], rp.ctypes.data, ci.ctypes.data, v.ctypes.data, 0, keep
+
+    def set_matrix(self, A=None, *, rowptr=None, col=None, val=None):
+        if A is not None:
+            rowptr, col, val = A.rowptr, A.col, A.val
+        n, nnz, prp, pci, pv, dev, _keep = self._csr_args(rowptr, col, val)
+        self._check(self._lib.pcg_set_matrix(self._h, n, nnz, prp, pci, pv, dev), "pcg_set_matrix")
+        self.n = n
+
+    def set_precond(self, G=None, *, rowptr=None, col=None, val=None):
+        if G is not None:
+            rowptr, col, val = G.rowptr, G.col, G.val
+        n, nnz, prp, pci, pv, dev, _keep = self._csr_args(rowptr, col, val)
+        self._check(self._lib.pcg_set_precond(self._h, n, nnz, prp, pci, pv, dev), "pcg_set_precond")
+
+    def build_precond(self, kind: int = G_FSAI):
+        self._check(self._lib.pcg_build_precond(self._h, kind), "pcg_build_precond")
+
+    def solve(self, b, x0=None, *, tol=1e-8, maxit=2000, allow_failure=False) -> SolveOut:
+        """Solve A x = b; returns the solution (same kind of array as b)."""
+        if _is_torch(b):
+            import torch
+
+            x = torch.zeros_like(b, dtype=torch.float64) if x0 is None else x0.to(torch.float64).clone()
+            bb = b.to(torch.float64).contiguous()
+        else:
+            bb = _host(b, np.float64)
+            x = np.zeros(bb.shape[0]) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        pb, dev = _ptr(bb)
+        px, _ = _ptr(x)
+        res = Result()
+        st = self._lib.pcg_solve(self._h, pb, px, float(tol), int(maxit), dev, ctypes.byref(res))
+        allow = (OK, NOT_CONVERGED, EBREAKDOWN) if allow_failure else (OK, NOT_CONVERGED)
+        self._check(st, "pcg_solve", allow)
+        return SolveOut(x, res.status, res.iters, res.outer_iters, res.restarts, res.relres_true, res.relres_rec,
+                        res.t_solve_ms, res.bytes_per_iter)
+
+    def matvec(self, op: int, x):
+        if _is_torch(x):
+            import torch
+
+            xx = x.to(torch.float64).contiguous()
+            y = torch.empty_like(xx)
+        else:
+            xx = _host(x, np.float64)
+            y = np.empty_like(xx)
+        px, dev = _ptr(xx)
+        py, _ = _ptr(y)
+        self._check(self._lib.pcg_matvec(self._h, op, px, py, dev), "pcg_matvec")
+        return y

@@ -1,0 +1,269 @@
+"""GPU parity of the FP64 path against the FP64 oracle, through the C ABI.
+
+Operator products are bit-identical to the oracle's (both add each row's
+products left to right from zero, contraction off, and the transposed
+product sums rows of G in ascending order on both sides). Whole solves
+differ only in the order of the dot-product sums, so they are held to
+trajectory parity: relative difference in x <= 1e-10 and iteration counts
+within one."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_27517_amd import inputs
+from paper_2510_27517_amd.inputs import CSR
+
+pytestmark = pytest.mark.gpu
+
+XTOL = 1e-10
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(pcg, **kw):
+    return pcg.Solver(pcg.default_config(**kw))
+
+
+def _random_spd_pattern(n, seed, long_rows=()):
+    """Symmetric random sparse matrix with a dominant diagonal (SPD), ragged
+    row lengths, and optional very long rows (beyond one LDS window)."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    deg = rng.integers(0, 12, n)
+    for i in range(n):
+        js = rng.integers(0, n, deg[i])
+        rows += [i] * len(js)
+        cols += list(js)
+    for i in long_rows:
+        js = rng.choice(n, size=min(n - 1, 3000), replace=False)
+        rows += [i] * len(js)
+        cols += list(js)
+    import scipy.sparse as sp
+
+    m = sp.coo_matrix((rng.uniform(-1, 1, len(rows)), (rows, cols)), shape=(n, n)).tocsr()
+    m = m + m.T
+    m.setdiag(0)
+    m.eliminate_zeros()
+    d = np.asarray(abs(m).sum(axis=1)).ravel() + 1.0 + rng.uniform(0, 1, n)
+    m = m + sp.diags(d)
+    return CSR.from_scipy(m)
+
+
+def _random_g(A, seed):
+    rng = np.random.default_rng(seed)
+    return CSR(A.rowptr.copy(), A.col.copy(), rng.uniform(-1, 1, A.nnz))
+
+
+@pytest.mark.parametrize("case", ["ragged", "longrows", "poisson3d"])
+def test_operator_products_bitwise(gpu_lib, case):
+    pcg = gpu_lib
+    if case == "ragged":
+        A = _random_spd_pattern(1537, 1)
+    elif case == "longrows":
+        A = _random_spd_pattern(5000, 2, long_rows=(0, 17, 4999))
+    else:
+        A = inputs.poisson(3, 40, 1.0, 2)
+    G = _random_g(A, 3)
+    x = np.random.default_rng(4).standard_normal(A.n)
+    eps = 0.37
+    say("operator products", case, A.n, A.nnz)
+    with _solver(pcg, eps=eps) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        assert np.array_equal(s.matvec(pcg.OP_A, x), oracle.spmv(A, x))
+        assert np.array_equal(s.matvec(pcg.OP_GT, x), oracle.spmv_t(G, x))
+        assert np.array_equal(s.matvec(pcg.OP_G, x), oracle.spmv(G, x))
+        assert np.array_equal(s.matvec(pcg.OP_MINV, x), oracle.apply_precond(G, x, eps))
+
+
+def _parity(pcg, A, kind, b, *, tol=1e-8, maxit=2000, eps=0.0, rr=50, graph=10, x0=None):
+    with _solver(pcg, eps=eps, rr_period=rr, graph_iters=graph) as s:
+        s.set_matrix(A)
+        s.build_precond(kind)
+        got = s.solve(b, x0, tol=tol, maxit=maxit)
+    G = {pcg.G_FSAI: oracle.fsai_g, pcg.G_FIXED: oracle.g_cfg1, pcg.G_JACOBI: oracle.diag_inv_sqrt,
+         pcg.G_IDENTITY: lambda A: oracle.identity(A.n)}[kind](A)
+    ref = oracle.pcg(A, G, b, x0, eps=eps, tol=tol, maxit=maxit, rr_period=rr, delta_form=1)
+    return got, ref
+
+
+def _check(got, ref):
+    assert got.status == ref.status
+    assert abs(got.iters - ref.iters) <= 1, (got.iters, ref.iters)
+    err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
+    assert err <= XTOL, err
+    return err
+
+
+def test_pcg_fixed_g_poisson2d_64(gpu_lib):
+    """2D Poisson 64x64, fixed lower G, b ~ N(0,1) seed 0, tol 1e-8."""
+    pcg = gpu_lib
+    A = inputs.poisson(2, 64)
+    b = inputs.rhs(A.n, 0)
+    say("pcg fixed G 2D 64^2")
+    got, ref = _parity(pcg, A, pcg.G_FIXED, b)
+    err = _check(got, ref)
+    assert got.status == pcg.OK and got.relres_true <= 1e-8
+    say("iters", got.iters, ref.iters, "xerr", err)
+
+
+@pytest.mark.parametrize("N", [16, 24])
+def test_pcg_fsai_poisson3d_lognormal(gpu_lib, N):
+    pcg = gpu_lib
+    A = inputs.poisson(3, N, 1.0, 0)
+    b = inputs.rhs(A.n, 0)
+    say("pcg fsai 3D", N)
+    got, ref = _parity(pcg, A, pcg.G_FSAI, b)
+    _check(got, ref)
+    assert got.status == pcg.OK
+
+
+def test_pcg_fsai_rgg(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.rgg_laplacian(20000, 3)
+    b = inputs.rhs(A.n, 3)
+    say("pcg fsai rgg 20000")
+    got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=1e-8, maxit=5000)
+    _check(got, ref)
+
+
+def test_pcg_random_spd_long_rows(gpu_lib):
+    pcg = gpu_lib
+    A = _random_spd_pattern(6000, 5, long_rows=(3, 4000))
+    b = np.random.default_rng(5).standard_normal(A.n)
+    say("pcg random spd long rows")
+    got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=1e-10)
+    _check(got, ref)
+
+
+def test_pcg_eps_replacement_and_graph_settings(gpu_lib):
+    """eps > 0, replacement every 7 iterations, nonzero x0; identical results
+    with and without graphs and with chunk lengths that do not divide 7."""
+    pcg = gpu_lib
+    A = inputs.poisson(2, 40, 0.5, 9)
+    b = inputs.rhs(A.n, 9)
+    x0 = np.random.default_rng(9).standard_normal(A.n)
+    say("pcg eps/rr/graph")
+    outs = []
+    for graph in (0, 1, 3, 10):
+        got, ref = _parity(pcg, A, pcg.G_JACOBI, b, eps=0.05, rr=7, graph=graph, x0=x0, tol=1e-9)
+        _check(got, ref)
+        outs.append(got)
+    for o in outs[1:]:
+        assert o.iters == outs[0].iters and np.array_equal(o.x, outs[0].x)
+
+
+def test_pcg_deterministic(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.poisson(3, 20, 1.0, 4)
+    b = inputs.rhs(A.n, 4)
+    say("determinism")
+    with _solver(pcg) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        r1 = s.solve(b)
+        r2 = s.solve(b)
+    assert r1.iters == r2.iters and np.array_equal(r1.x, r2.x)
+
+
+def test_edge_cases(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.poisson(2, 8)
+    say("edge cases")
+    with _solver(pcg) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FIXED)
+        z = s.solve(np.zeros(A.n), np.ones(A.n))
+        assert z.status == pcg.OK and z.iters == 0 and np.all(z.x == 0)
+        b = inputs.rhs(A.n, 1)
+        x0 = np.full(A.n, 0.25)
+        m0 = s.solve(b, x0, maxit=0)
+        assert m0.status == pcg.NOT_CONVERGED and m0.iters == 0 and np.array_equal(m0.x, x0)
+        m3 = s.solve(b, maxit=3)
+        ref = oracle.pcg(A, oracle.g_cfg1(A), b, maxit=3, delta_form=1)
+        assert m3.status == ref.status == pcg.NOT_CONVERGED and m3.iters == 3
+        assert np.linalg.norm(m3.x - ref.x) <= 1e-13 * np.linalg.norm(ref.x)
+        nanb = b.copy()
+        nanb[5] = np.nan
+        br = s.solve(nanb, allow_failure=True)
+        assert br.status == pcg.EBREAKDOWN
+    with _solver(pcg) as s:
+        one = CSR(np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+        s.set_matrix(one)
+        s.build_precond(pcg.G_IDENTITY)
+        r = s.solve(np.array([2.0]))
+        assert r.status == pcg.OK and r.iters == 1 and r.x[0] == 0.5
+    with _solver(pcg) as s:
+        neg = CSR(A.rowptr, A.col, -A.val)
+        s.set_matrix(neg)
+        s.set_precond(oracle.identity(A.n))
+        br = s.solve(inputs.rhs(A.n, 2), allow_failure=True)
+        assert br.status == pcg.EBREAKDOWN
+        assert oracle.pcg(neg, oracle.identity(A.n), inputs.rhs(A.n, 2)).status == oracle.EBREAKDOWN
+
+
+def test_errors_and_state(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.poisson(2, 6)
+    with _solver(pcg) as s:
+        with pytest.raises(pcg.PCGError) as e:
+            s.solve(np.ones(A.n))
+        assert e.value.status == pcg.ESTATE
+        bad = CSR(A.rowptr, A.col.copy(), A.val)
+        bad.col[2] = A.n + 5
+        with pytest.raises(pcg.PCGError) as e:
+            s.set_matrix(bad)
+        assert e.value.status == pcg.EINVAL
+        s.set_matrix(A)
+        with pytest.raises(pcg.PCGError) as e:
+            s.set_precond(oracle.identity(A.n + 1))
+        assert e.value.status == pcg.ESTATE
+
+
+def test_device_pointers_torch(gpu_lib):
+    import torch
+
+    pcg = gpu_lib
+    A = inputs.poisson(3, 12, 1.0, 6)
+    b = inputs.rhs(A.n, 6)
+    say("device pointers")
+    dev = torch.device("cuda:0")
+    with _solver(pcg) as s:
+        s.set_matrix(rowptr=torch.from_numpy(A.rowptr).to(dev), col=torch.from_numpy(A.col).to(dev),
+                     val=torch.from_numpy(A.val).to(dev))
+        s.build_precond(pcg.G_FSAI)
+        r_dev = s.solve(torch.from_numpy(b).to(dev))
+        r_host = s.solve(b)
+    assert np.array_equal(r_dev.x.cpu().numpy(), r_host.x)
+
+
+@pytest.mark.slow
+def test_full_size_poisson3d_128(gpu_lib):
+    """3D lognormal (sigma 1) Poisson on 128^3 with FSAI, the benchmark's
+    single-system workload and launch configuration: A x bit-identical to the
+    oracle, the first iterations match the oracle's, and the converged
+    solution's residual, recomputed by the oracle's SpMV, meets 1e-8."""
+    pcg = gpu_lib
+    A = inputs.poisson(3, 128, 1.0, 0)
+    b = inputs.rhs(A.n, 0)
+    say("full size 128^3", A.n, A.nnz)
+    with _solver(pcg) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        xs = np.random.default_rng(0).standard_normal(A.n)
+        assert np.array_equal(s.matvec(pcg.OP_A, xs), oracle.spmv(A, xs, threads=8))
+        few = s.solve(b, maxit=4)
+        full = s.solve(b, tol=1e-8, maxit=5000)
+    G = oracle.fsai_g(A)
+    ref = oracle.pcg(A, G, b, maxit=4, delta_form=1, threads=8)
+    assert few.iters == ref.iters == 4
+    assert np.linalg.norm(few.x - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+    assert full.status == pcg.OK
+    r = b - oracle.spmv(A, full.x, threads=8)
+    assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(b)
+    say("iters", full.iters, "ms", full.t_solve_ms)
