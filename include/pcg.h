@@ -130,6 +130,23 @@ int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, i
  * context's vector precision (values at the boundary are float64). */
 int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device);
 
+/* Measurement. Runs `iters` CG iterations of the stored system (a fresh
+ * solve of the last right-hand side from x0 = 0 that never stops; the
+ * context's vectors are overwritten) as plain launches on the context's
+ * stream, with HIP events around each kernel. ms[0..2]: average duration of
+ * the A-, G^T- and G-kernel launches; ms[3]: average iteration. bytes[0..3]
+ * (may be NULL): their algorithmic device bytes per launch (A: A's values,
+ * columns and row pointers plus 6 vector streams; G^T: G^T plus 4; G: G plus
+ * 2, 3 with eps). Needs one prior pcg_solve with b != 0. */
+int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes);
+
+/* Device-to-device copy of `bytes` (rounded down to 16) repeated `reps`
+ * times with a plain 16-byte-access kernel; *gbps = 2 bytes reps / time (read
+ * plus write), *ms_per_copy the average launch (may be NULL). Allocates and
+ * frees its own buffers. The measured HBM ceiling and the reference for
+ * calibrating memory-traffic counters. */
+int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double *ms_per_copy);
+
 /* Host-only helpers (no GPU needed). */
 
 /* Checks a CSR matrix against the conventions above; require_diag = 1 also

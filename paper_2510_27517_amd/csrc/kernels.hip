@@ -18,12 +18,17 @@
 // d and r alternate between two buffers by iteration parity, so no
 // workgroup overwrites a vector entry another one still gathers.
 //
-// Reductions are deterministic: each workgroup reduces its rows with wave
-// shuffles and LDS, writes one partial, and the last workgroup to arrive
-// (arrival counter) adds the partials in a fixed order and updates the
-// scalars in device memory. Workgroups are mapped so that each of the 8
-// XCDs processes one contiguous eighth of the rows, keeping the gathered
-// neighbourhoods inside that XCD's L2.
+// Reductions are deterministic and need no atomics: each workgroup reduces
+// its rows with wave shuffles and LDS and writes one partial per value; every
+// workgroup of the next kernel adds all partials in the same fixed order
+// (kernel boundaries make them visible), so all obtain the identical total.
+// One workgroup publishes the updated scalars into a state slot that the
+// kernel itself does not read.
+//
+// Work placement: each of the 8 XCDs (workgroup b runs on XCD b % 8) owns a
+// contiguous eighth of the row blocks, and its workgroups take those blocks
+// interleaved, so at any moment an XCD works on one window of consecutive
+// rows whose gathered neighbourhoods stay in that XCD's L2.
 //
 // Built with floating-point contraction off: every product and sum rounds
 // separately, in the order written (rows summed left to right from zero),
@@ -62,26 +67,43 @@ static Mat<TM> mat(const DevCSR &m) {
   return Mat<TM>{m.rp, m.ci, (const TM *)m.val, m.blk, m.nblk};
 }
 
-// One row block: stage products in LDS, sum each row in CSR order.
-template <typename TACC, typename TM, typename Gather, typename Epi>
-__device__ __forceinline__ void stream_block(int r0, int r1, const Mat<TM> &M, TACC *lds, Gather gather, Epi epi) {
+// Operands of one row loaded before the row's products are staged.
+template <typename TV>
+struct RowVals {
+  TV a, b, c;
+};
+
+// One row block: stage products in LDS, sum each row in CSR order. `pre(row)`
+// loads the row's own operands early (overlapping the gathers), `epi(row,
+// sum, pre_values)` consumes the row's sum.
+template <typename TACC, typename TM, typename Pre, typename Gather, typename Epi>
+__device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds, Pre pre, Gather gather, Epi epi) {
   constexpr int cap = kLdsBytes / (int)sizeof(TACC);
   const int tid = threadIdx.x;
-  const int k0 = M.rp[r0], k1 = M.rp[r1];
+  const int r0 = M.blk[2 * b], k0 = M.blk[2 * b + 1], r1 = M.blk[2 * b + 2], k1 = M.blk[2 * b + 3];
   if (k1 - k0 <= cap) {
+    const int row = r0 + tid;
+    const bool has = row < r1;
+    int a = 0, e = 0;
+    RowVals<TACC> pv{};
+    if (has) {
+      a = M.rp[row] - k0;
+      e = M.rp[row + 1] - k0;
+      pv = pre(row);
+    }
 #pragma unroll 4
     for (int k = k0 + tid; k < k1; k += kBlock) lds[k - k0] = (TACC)ldval(M.val, k) * gather(M.ci[k]);
     __syncthreads();
-    const int row = r0 + tid;
-    if (row < r1) {
-      const int a = M.rp[row] - k0, e = M.rp[row + 1] - k0;
+    if (has) {
       TACC sum = 0;
       for (int k = a; k < e; ++k) sum += lds[k];
-      epi(row, sum);
+      epi(row, sum, pv);
     }
     __syncthreads();
   } else {
     // a single row longer than the LDS window: chunks, summed in order by thread 0
+    RowVals<TACC> pv{};
+    if (tid == 0) pv = pre(r0);
     TACC sum = 0;
     for (int c0 = k0; c0 < k1; c0 += cap) {
       const int c1 = min(c0 + cap, k1);
@@ -91,16 +113,24 @@ __device__ __forceinline__ void stream_block(int r0, int r1, const Mat<TM> &M, T
         for (int k = 0; k < c1 - c0; ++k) sum += lds[k];
       __syncthreads();
     }
-    if (tid == 0) epi(r0, sum);
+    if (tid == 0) epi(r0, sum, pv);
   }
 }
 
-// Row blocks [bstart, bend) of logical workgroup L out of G.
-__device__ __forceinline__ void my_blocks(int nblk, int &bstart, int &bend) {
-  const int G = gridDim.x;
-  const int L = xcd_remap(blockIdx.x, G);
-  bstart = (int)((int64_t)L * nblk / G);
-  bend = (int)((int64_t)(L + 1) * nblk / G);
+// This workgroup's row blocks: first, first + stride, ... < end; L is its
+// logical index (the slot of its partial sums).
+struct Sched {
+  int first, end, stride, L;
+};
+
+__device__ __forceinline__ Sched sched(int nblk) {
+  const int G = gridDim.x, W = G >> 3, x = blockIdx.x & 7, l = blockIdx.x >> 3;
+  Sched sc;
+  sc.first = (int)((int64_t)x * nblk / 8) + l;
+  sc.end = (int)((int64_t)(x + 1) * nblk / 8);
+  sc.stride = W;
+  sc.L = x * W + l;
+  return sc;
 }
 
 template <int NV>
@@ -125,38 +155,33 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
   __syncthreads();
 }
 
-// Reduce v over the grid. Returns true in the last-arriving workgroup, where
-// thread 0 then holds the grid totals (added in a fixed order).
+// Write this workgroup's partial sums (value j at p[j * G + L]).
 template <int NV>
-__device__ __forceinline__ bool grid_sum(double (&v)[NV], double *partials, uint32_t *ctr, double *sh) {
-  __shared__ int is_last;
-  const int G = gridDim.x;
-  const int L = xcd_remap(blockIdx.x, G);
+__device__ __forceinline__ void put_partials(double (&v)[NV], double *p, int L, double *sh) {
   block_sum<NV>(v, sh);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int j = 0; j < NV; ++j) partials[(int64_t)j * G + L] = v[j];
-    __threadfence();
-    const uint32_t prev = atomicAdd(ctr, 1u);
-    is_last = (prev == (uint32_t)G - 1);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
+    for (int j = 0; j < NV; ++j) p[(int64_t)j * gridDim.x + L] = v[j];
+}
+
+// Sum the P partials of each value in a fixed order; every thread gets the totals.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ p, int P, double (&out)[NV], double *sh) {
   double acc[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-  for (int k = threadIdx.x; k < G; k += kBlock)
+#pragma unroll 8
+  for (int k = threadIdx.x; k < P; k += kBlock)
 #pragma unroll
-    for (int j = 0; j < NV; ++j)
-      acc[j] += __hip_atomic_load(&partials[(int64_t)j * G + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int j = 0; j < NV; ++j) acc[j] += p[(int64_t)j * P + k];
   block_sum<NV>(acc, sh);
-  if (threadIdx.x == 0) {
+  __shared__ double tot[NV];
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = acc[j];
-    *ctr = 0u;
-  }
-  return true;
+    for (int j = 0; j < NV; ++j) tot[j] = acc[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NV; ++j) out[j] = tot[j];
 }
 
 // ------------------------------------------------------------------ kernels
@@ -164,119 +189,141 @@ __device__ __forceinline__ bool grid_sum(double (&v)[NV], double *partials, uint
 template <typename TV, typename TA>
 __global__ __launch_bounds__(kBlock) void k_iter_A(Mat<TA> A, TV *__restrict__ x, const TV *__restrict__ s,
                                                    TV *__restrict__ d0, TV *__restrict__ d1, TV *__restrict__ q,
-                                                   State *__restrict__ st, double *__restrict__ partials) {
+                                                   const State *__restrict__ st, double *__restrict__ pg) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
-  if (st->done) return;
-  const int it = st->iter;
-  const TV beta = (TV)st->beta, ap = (TV)st->alpha;
+  const State &S = st[0];
+  if (S.done) return;
+  const int it = S.iter;
+  const TV beta = (TV)S.beta, ap = (TV)S.alpha;
   const TV *__restrict__ dold = (it & 1) ? d0 : d1;  // d_{i-1}
   TV *__restrict__ dnew = (it & 1) ? d1 : d0;        // d_i
   double part[1] = {0.0};
-  int b0, b1;
-  my_blocks(A.nblk, b0, b1);
-  for (int b = b0; b < b1; ++b)
+  const Sched sc = sched(A.nblk);
+  for (int b = sc.first; b < sc.end; b += sc.stride)
     stream_block<TV>(
-        A.blk[b], A.blk[b + 1], A, lds, [&](int j) -> TV { return s[j] + beta * dold[j]; },
-        [&](int row, TV sum) {
-          const TV dold_r = dold[row];
-          const TV di = s[row] + beta * dold_r;
+        A, b, lds, [&](int row) { return RowVals<TV>{s[row], dold[row], x[row]}; },
+        [&](int j) -> TV { return s[j] + beta * dold[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          const TV di = pv.a + beta * pv.b;
           dnew[row] = di;
           q[row] = sum;
-          x[row] = x[row] + ap * dold_r;
+          x[row] = pv.c + ap * pv.b;
           part[0] += (double)di * (double)sum;
         });
-  if (grid_sum<1>(part, partials, &st->ctr[0], sh) && threadIdx.x == 0) {
-    const double g = part[0];
-    st->gamma = g;
-    if (!(g > 0.0) || !isfinite(g)) {
-      st->status = ST_BREAK_GAMMA;
-      st->done = 1;
-      st->alpha = 0.0;  // x already holds x_i
-    } else {
-      st->alpha = st->delta / g;
-    }
-  }
+  put_partials<1>(part, pg, sc.L, sh);
 }
 
 template <typename TV, typename TG>
 __global__ __launch_bounds__(kBlock) void k_iter_GT(Mat<TG> GT, TV *__restrict__ r0, TV *__restrict__ r1,
                                                     const TV *__restrict__ q, TV *__restrict__ t,
-                                                    State *__restrict__ st, double *__restrict__ partials,
-                                                    int mode) {
+                                                    State *__restrict__ st, const double *__restrict__ pg, int P_a,
+                                                    double *__restrict__ prt, int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
-  if (st->done) return;
-  const int it = st->iter;
-  const TV al = (mode == 0) ? (TV)st->alpha : (TV)0;
+  const State &S = st[0];
+  if (S.done) return;
+  const int it = S.iter;
+  double alpha = S.alpha, gamma = S.gamma;
+  bool brk = false;
+  if (mode != 2) {
+    double g[1];
+    sum_partials<1>(pg, P_a, g, sh);
+    gamma = g[0];
+    brk = !(gamma > 0.0) || !isfinite(gamma);
+    alpha = brk ? 0.0 : S.delta / gamma;  // on breakdown x already holds x_i
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    State o = S;
+    o.gamma = gamma;
+    o.alpha = alpha;
+    if (brk) {
+      o.status = ST_BREAK_GAMMA;
+      o.done = 1;
+    }
+    st[1] = o;
+  }
+  if (brk) return;
+  const TV al = (mode == 0) ? (TV)alpha : (TV)0;
   const TV *__restrict__ src = (((mode == 1) ? it + 1 : it) & 1) ? r1 : r0;
   TV *__restrict__ dst = ((it + 1) & 1) ? r1 : r0;
   double part[2] = {0.0, 0.0};
-  int b0, b1;
-  my_blocks(GT.nblk, b0, b1);
+  const Sched sc = sched(GT.nblk);
   if (mode == 0) {
-    for (int b = b0; b < b1; ++b)
+    for (int b = sc.first; b < sc.end; b += sc.stride)
       stream_block<TV>(
-          GT.blk[b], GT.blk[b + 1], GT, lds, [&](int j) -> TV { return src[j] - al * q[j]; },
-          [&](int row, TV sum) {
-            const TV rn = src[row] - al * q[row];
+          GT, b, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
+          [&](int j) -> TV { return src[j] - al * q[j]; },
+          [&](int row, TV sum, const RowVals<TV> &pv) {
+            const TV rn = pv.a - al * pv.b;
             dst[row] = rn;
             t[row] = sum;
             part[0] += (double)rn * (double)rn;
             part[1] += (double)sum * (double)sum;
           });
   } else {
-    for (int b = b0; b < b1; ++b)
+    for (int b = sc.first; b < sc.end; b += sc.stride)
       stream_block<TV>(
-          GT.blk[b], GT.blk[b + 1], GT, lds, [&](int j) -> TV { return src[j]; },
-          [&](int row, TV sum) {
-            const TV rn = src[row];
+          GT, b, lds, [&](int row) { return RowVals<TV>{src[row], (TV)0, (TV)0}; },
+          [&](int j) -> TV { return src[j]; },
+          [&](int row, TV sum, const RowVals<TV> &pv) {
             t[row] = sum;
-            part[0] += (double)rn * (double)rn;
+            part[0] += (double)pv.a * (double)pv.a;
             part[1] += (double)sum * (double)sum;
           });
   }
-  if (grid_sum<2>(part, partials, &st->ctr[1], sh) && threadIdx.x == 0) {
-    const double rr = part[0], tt = part[1];
-    st->rr = rr;
-    st->tt = tt;
-    const double dn = tt + st->eps * rr;
-    const int i1 = (mode == 2) ? it : it + 1;
-    st->iter = i1;
-    if (mode != 2 && (!(dn >= 0.0) || !isfinite(dn))) {
-      st->status = ST_BREAK_DELTA;
-      st->done = 1;
-    } else {
-      st->beta = (mode == 2) ? 0.0 : dn / st->delta;
-      st->delta = dn;
-      if (sqrt(rr) <= st->tol_nb) {
-        st->status = ST_CONV_REC;
-        st->done = 1;
-      } else if (i1 >= st->maxit) {
-        st->status = ST_MAXIT;
-        st->done = 1;
-      }
-    }
-  }
+  put_partials<2>(part, prt, sc.L, sh);
 }
 
 template <typename TV, typename TG, bool HAS_EPS>
 __global__ __launch_bounds__(kBlock) void k_iter_G(Mat<TG> G, const TV *__restrict__ t, const TV *__restrict__ r0,
                                                    const TV *__restrict__ r1, TV *__restrict__ s,
-                                                   State *__restrict__ st) {
+                                                   State *__restrict__ st, const double *__restrict__ prt, int P_gt,
+                                                   int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
-  if (st->done) return;
-  const int it = st->iter;
-  const TV *__restrict__ rc = (it & 1) ? r1 : r0;
-  const TV eps = (TV)st->eps;
-  int b0, b1;
-  my_blocks(G.nblk, b0, b1);
-  for (int b = b0; b < b1; ++b)
+  __shared__ double sh[4 * (kBlock / 64)];
+  if (st[0].done) return;  // stopped before this iteration's G^T-kernel ran
+  const State &S = st[1];
+  if (S.done) {  // the G^T-kernel flagged a breakdown: publish it
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[0] = S;
+    return;
+  }
+  const int it = S.iter;
+  double v[2];
+  sum_partials<2>(prt, P_gt, v, sh);
+  const double rr = v[0], tt = v[1];
+  const double dn = tt + S.eps * rr;
+  State o = S;
+  o.rr = rr;
+  o.tt = tt;
+  const int i1 = (mode == 2) ? it : it + 1;
+  o.iter = i1;
+  if (mode != 2 && (!(dn >= 0.0) || !isfinite(dn))) {
+    o.status = ST_BREAK_DELTA;
+    o.done = 1;
+  } else {
+    o.beta = (mode == 2) ? 0.0 : dn / S.delta;
+    o.delta = dn;
+    if (sqrt(rr) <= S.tol_nb) {
+      o.status = ST_CONV_REC;
+      o.done = 1;
+    } else if (i1 >= S.maxit) {
+      o.status = ST_MAXIT;
+      o.done = 1;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[0] = o;
+  if (o.done) return;
+  const TV *__restrict__ rc = (i1 & 1) ? r1 : r0;
+  const TV eps = (TV)S.eps;
+  const Sched sc = sched(G.nblk);
+  for (int b = sc.first; b < sc.end; b += sc.stride)
     stream_block<TV>(
-        G.blk[b], G.blk[b + 1], G, lds, [&](int j) -> TV { return t[j]; },
-        [&](int row, TV sum) {
+        G, b, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, (TV)0, (TV)0}; },
+        [&](int j) -> TV { return t[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
           if (HAS_EPS)
-            s[row] = sum + eps * rc[row];
+            s[row] = sum + eps * pv.a;
           else
             s[row] = sum;
         });
@@ -285,82 +332,100 @@ __global__ __launch_bounds__(kBlock) void k_iter_G(Mat<TG> G, const TV *__restri
 template <typename TV, typename TA>
 __global__ __launch_bounds__(kBlock) void k_resid(Mat<TA> A, const TV *__restrict__ b, const TV *__restrict__ x,
                                                   const TV *__restrict__ d0, const TV *__restrict__ d1,
-                                                  TV *__restrict__ r0, TV *__restrict__ r1, State *__restrict__ st,
-                                                  double *__restrict__ partials, int slot_sel, int with_d,
-                                                  int reduce, int respect_done) {
+                                                  TV *__restrict__ r0, TV *__restrict__ r1,
+                                                  const State *__restrict__ st, const double *__restrict__ pg,
+                                                  int P_a, double *__restrict__ ptr, int slot_sel, int with_d,
+                                                  int respect_done) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
-  if (respect_done && st->done) return;
-  const int it = st->iter;
+  const State &S = st[0];
+  if (respect_done && S.done) return;
+  const int it = S.iter;
   TV *__restrict__ rout = ((it + slot_sel) & 1) ? r1 : r0;
   const TV *__restrict__ dc = (it & 1) ? d1 : d0;  // d_i
-  const TV al = (TV)st->alpha;
+  TV al = (TV)0;
+  if (with_d) {
+    double g[1];
+    sum_partials<1>(pg, P_a, g, sh);
+    if (!(g[0] > 0.0) || !isfinite(g[0])) return;  // the G^T-kernel reports the breakdown
+    al = (TV)(S.delta / g[0]);
+  }
   double part[1] = {0.0};
-  int b0, b1;
-  my_blocks(A.nblk, b0, b1);
-  auto epi = [&](int row, TV sum) {
-    const TV rv = b[row] - sum;
+  const Sched sc = sched(A.nblk);
+  auto pre = [&](int row) { return RowVals<TV>{b[row], (TV)0, (TV)0}; };
+  auto epi = [&](int row, TV sum, const RowVals<TV> &pv) {
+    const TV rv = pv.a - sum;
     rout[row] = rv;
     part[0] += (double)rv * (double)rv;
   };
   if (with_d) {
-    for (int k = b0; k < b1; ++k)
-      stream_block<TV>(A.blk[k], A.blk[k + 1], A, lds, [&](int j) -> TV { return x[j] + al * dc[j]; }, epi);
+    for (int k = sc.first; k < sc.end; k += sc.stride)
+      stream_block<TV>(A, k, lds, pre, [&](int j) -> TV { return x[j] + al * dc[j]; }, epi);
   } else {
-    for (int k = b0; k < b1; ++k)
-      stream_block<TV>(A.blk[k], A.blk[k + 1], A, lds, [&](int j) -> TV { return x[j]; }, epi);
+    for (int k = sc.first; k < sc.end; k += sc.stride)
+      stream_block<TV>(A, k, lds, pre, [&](int j) -> TV { return x[j]; }, epi);
   }
-  if (reduce && grid_sum<1>(part, partials, &st->ctr[3], sh) && threadIdx.x == 0) st->true_rr = part[0];
+  if (ptr) put_partials<1>(part, ptr, sc.L, sh);
 }
 
 template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_finalize(int32_t n, TV *__restrict__ x, const TV *__restrict__ d0,
                                                      const TV *__restrict__ d1, const State *__restrict__ st) {
-  const TV al = (TV)st->alpha;
+  const TV al = (TV)st[0].alpha;
   if (al == (TV)0) return;
-  const TV *__restrict__ dc = ((st->iter - 1) & 1) ? d1 : d0;
+  const TV *__restrict__ dc = ((st[0].iter - 1) & 1) ? d1 : d0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
     x[i] = x[i] + al * dc[i];
 }
 
-__global__ void k_state_clear_alpha(State *st) { st->alpha = 0.0; }
+__global__ void k_state_clear_alpha(State *st) { st[0].alpha = 0.0; }
 
 __global__ void k_state_restart(State *st) {
-  st->done = 0;
-  st->status = ST_RUNNING;
-  st->alpha = 0.0;
-  st->beta = 0.0;
+  st[0].done = 0;
+  st[0].status = ST_RUNNING;
+  st[0].alpha = 0.0;
+  st[0].beta = 0.0;
 }
 
 template <typename TV>
-__global__ __launch_bounds__(kBlock) void k_norm_b(int32_t n, const TV *__restrict__ b, State *__restrict__ st,
-                                                   double *__restrict__ partials) {
+__global__ __launch_bounds__(kBlock) void k_norm_b(int32_t n, const TV *__restrict__ b, double *__restrict__ pb) {
   __shared__ double sh[4 * (kBlock / 64)];
   double part[1] = {0.0};
   // logical id -> contiguous slice, so the sum order is fixed
-  const int G = gridDim.x, L = xcd_remap(blockIdx.x, G);
+  const int G = gridDim.x, L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   const int64_t i0 = (int64_t)L * n / G, i1 = (int64_t)(L + 1) * n / G;
+#pragma unroll 8
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) part[0] += (double)b[i] * (double)b[i];
-  if (grid_sum<1>(part, partials, &st->ctr[2], sh) && threadIdx.x == 0) {
-    const double bb = part[0];
-    st->bb = bb;
-    const double nb = sqrt(bb);
-    st->tol_nb = st->tol * nb;
-    if (bb == 0.0) {
-      st->status = ST_ZERO_B;
-      st->done = 1;
+  put_partials<1>(part, pb, L, sh);
+}
+
+// Single workgroup: ||b||^2 (what = 0, also tol * ||b|| and the b = 0 test)
+// or ||b - A x||^2 (what = 1) from P partials into st[0].
+__global__ __launch_bounds__(kBlock) void k_reduce_state(const double *__restrict__ p, int P, State *st, int what) {
+  __shared__ double sh[4 * (kBlock / 64)];
+  double v[1];
+  sum_partials<1>(p, P, v, sh);
+  if (threadIdx.x != 0) return;
+  if (what == 0) {
+    st[0].bb = v[0];
+    st[0].tol_nb = st[0].tol * sqrt(v[0]);
+    if (v[0] == 0.0) {
+      st[0].status = ST_ZERO_B;
+      st[0].done = 1;
     }
+  } else {
+    st[0].true_rr = v[0];
   }
 }
 
 template <typename TV, typename TM>
 __global__ __launch_bounds__(kBlock) void k_spmv(Mat<TM> M, const TV *__restrict__ x, TV *__restrict__ y) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
-  int b0, b1;
-  my_blocks(M.nblk, b0, b1);
-  for (int b = b0; b < b1; ++b)
-    stream_block<TV>(M.blk[b], M.blk[b + 1], M, lds, [&](int j) -> TV { return x[j]; },
-                     [&](int row, TV sum) { y[row] = sum; });
+  const Sched sc = sched(M.nblk);
+  for (int b = sc.first; b < sc.end; b += sc.stride)
+    stream_block<TV>(
+        M, b, lds, [&](int) { return RowVals<TV>{}; }, [&](int j) -> TV { return x[j]; },
+        [&](int row, TV sum, const RowVals<TV> &) { y[row] = sum; });
 }
 
 template <typename TV>
@@ -387,6 +452,13 @@ __global__ void k_refine_update(int32_t n, double *__restrict__ x64, const TC *_
     x64[i] = x64[i] + scale * (double)c[i];
 }
 
+// Plain streaming copy (16-byte accesses): the reference for the HBM ceiling
+// and for calibrating the memory-traffic counters.
+__global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock)
+    dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline int ew_grid(int64_t n) {
@@ -411,56 +483,64 @@ static inline int ew_grid(int64_t n) {
     default: return hipErrorInvalidValue;                     \
   }
 
-hipError_t launch_iter_A(const Types &ty, const DevCSR &A, const Vecs &v, State *st, double *partials,
+hipError_t launch_iter_A(const Types &ty, const DevCSR &A, const Vecs &v, State *st, const Partials &p,
                          hipStream_t s) {
   if (ty.vec == F64 && A.dtype == F64) {
     hipLaunchKernelGGL((k_iter_A<double, double>), dim3(A.grid), dim3(kBlock), 0, s, mat<double>(A), (double *)v.x,
-                       (const double *)v.s, (double *)v.d0, (double *)v.d1, (double *)v.q, st, partials);
+                       (const double *)v.s, (double *)v.d0, (double *)v.d1, (double *)v.q, st, p.g);
   } else if (ty.vec == F32 && A.dtype == F32) {
     hipLaunchKernelGGL((k_iter_A<float, float>), dim3(A.grid), dim3(kBlock), 0, s, mat<float>(A), (float *)v.x,
-                       (const float *)v.s, (float *)v.d0, (float *)v.d1, (float *)v.q, st, partials);
+                       (const float *)v.s, (float *)v.d0, (float *)v.d1, (float *)v.q, st, p.g);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_iter_GT(const Types &ty, const DevCSR &GT, const Vecs &v, State *st, double *partials, int mode,
-                          hipStream_t s) {
+hipError_t launch_iter_GT(const Types &ty, const DevCSR &GT, const Vecs &v, State *st, const Partials &p, int P_a,
+                          int mode, hipStream_t s) {
   PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(GT.dtype, TG, {
     hipLaunchKernelGGL((k_iter_GT<TV, TG>), dim3(GT.grid), dim3(kBlock), 0, s, mat<TG>(GT), (TV *)v.r0,
-                       (TV *)v.r1, (const TV *)v.q, (TV *)v.t, st, partials, mode);
+                       (TV *)v.r1, (const TV *)v.q, (TV *)v.t, st, p.g, P_a, p.rt, mode);
   }));
   return hipGetLastError();
 }
 
-hipError_t launch_iter_G(const Types &ty, const DevCSR &G, const Vecs &v, State *st, bool has_eps, hipStream_t s) {
+hipError_t launch_iter_G(const Types &ty, const DevCSR &G, const Vecs &v, State *st, const Partials &p, int P_gt,
+                         bool has_eps, int mode, hipStream_t s) {
   PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(G.dtype, TG, {
     if (has_eps)
       hipLaunchKernelGGL((k_iter_G<TV, TG, true>), dim3(G.grid), dim3(kBlock), 0, s, mat<TG>(G), (const TV *)v.t,
-                         (const TV *)v.r0, (const TV *)v.r1, (TV *)v.s, st);
+                         (const TV *)v.r0, (const TV *)v.r1, (TV *)v.s, st, p.rt, P_gt, mode);
     else
       hipLaunchKernelGGL((k_iter_G<TV, TG, false>), dim3(G.grid), dim3(kBlock), 0, s, mat<TG>(G), (const TV *)v.t,
-                         (const TV *)v.r0, (const TV *)v.r1, (TV *)v.s, st);
+                         (const TV *)v.r0, (const TV *)v.r1, (TV *)v.s, st, p.rt, P_gt, mode);
   }));
   return hipGetLastError();
 }
 
-hipError_t launch_resid(const Types &ty, const DevCSR &A, const Vecs &v, State *st, double *partials, int slot_sel,
+hipError_t launch_resid(const Types &ty, const DevCSR &A, const Vecs &v, State *st, const Partials &p, int slot_sel,
                         bool with_d, bool reduce, bool respect_done, hipStream_t s) {
+  double *ptr = reduce ? p.tr : nullptr;
   if (ty.vec == F64 && A.dtype == F64) {
     hipLaunchKernelGGL((k_resid<double, double>), dim3(A.grid), dim3(kBlock), 0, s, mat<double>(A),
                        (const double *)v.b, (const double *)v.x, (const double *)v.d0, (const double *)v.d1,
-                       (double *)v.r0, (double *)v.r1, st, partials, slot_sel, (int)with_d, (int)reduce,
+                       (double *)v.r0, (double *)v.r1, st, p.g, A.grid, ptr, slot_sel, (int)with_d,
                        (int)respect_done);
   } else if (ty.vec == F32 && A.dtype == F32) {
     hipLaunchKernelGGL((k_resid<float, float>), dim3(A.grid), dim3(kBlock), 0, s, mat<float>(A),
                        (const float *)v.b, (const float *)v.x, (const float *)v.d0, (const float *)v.d1,
-                       (float *)v.r0, (float *)v.r1, st, partials, slot_sel, (int)with_d, (int)reduce,
+                       (float *)v.r0, (float *)v.r1, st, p.g, A.grid, ptr, slot_sel, (int)with_d,
                        (int)respect_done);
   } else {
     return hipErrorInvalidValue;
   }
+  if (reduce) hipLaunchKernelGGL(k_reduce_state, dim3(1), dim3(kBlock), 0, s, (const double *)p.tr, A.grid, st, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_true(State *st, const Partials &p, int P, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_state, dim3(1), dim3(kBlock), 0, s, (const double *)p.tr, P, st, 1);
   return hipGetLastError();
 }
 
@@ -473,14 +553,15 @@ hipError_t launch_finalize(const Types &ty, int32_t n, const Vecs &v, State *st,
   return hipGetLastError();
 }
 
-hipError_t launch_norm_b(const Types &ty, int32_t n, const Vecs &v, State *st, double *partials, hipStream_t s) {
-  // the grid must stay within the partial buffer sized for the matrices' grids
+hipError_t launch_norm_b(const Types &ty, int32_t n, const Vecs &v, State *st, const Partials &p, hipStream_t s) {
+  // the grid must stay within the partial buffers (sized for at least 1024)
   int g = ew_grid(n);
   if (g > 1024) g = 1024;
   g = (g + 7) & ~7;
   PCG_DISPATCH_V(ty.vec, TV, {
-    hipLaunchKernelGGL((k_norm_b<TV>), dim3(g), dim3(kBlock), 0, s, n, (const TV *)v.b, st, partials);
+    hipLaunchKernelGGL((k_norm_b<TV>), dim3(g), dim3(kBlock), 0, s, n, (const TV *)v.b, p.b);
   });
+  hipLaunchKernelGGL(k_reduce_state, dim3(1), dim3(kBlock), 0, s, (const double *)p.b, g, st, 0);
   return hipGetLastError();
 }
 
@@ -524,6 +605,11 @@ hipError_t launch_refine_update(int32_t n, double *x64, const void *c, int c_dty
   PCG_DISPATCH_V(c_dtype, TC, {
     hipLaunchKernelGGL((k_refine_update<TC>), dim3(ew_grid(n)), dim3(kBlock), 0, s, n, x64, (const TC *)c, scale);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kBlock), 0, s, (const uint4 *)src, (uint4 *)dst, bytes / 16);
   return hipGetLastError();
 }
 

@@ -243,9 +243,11 @@ int build_g(int kind, int32_t n, const int32_t *rp, const int32_t *ci, const dou
 
 // Row-block partition for the CSR-stream kernels: consecutive rows, at most
 // kBlock rows and `cap` nonzeros per block; a longer row is a block alone.
+// Returned as (row start, nonzero start) pairs, nblk + 1 of them.
 std::vector<int32_t> row_blocks(int32_t n, const int32_t *rp, int cap) {
   std::vector<int32_t> blk;
   blk.push_back(0);
+  blk.push_back(rp[0]);
   int32_t start = 0;
   while (start < n) {
     int32_t end = start + 1;
@@ -253,6 +255,7 @@ std::vector<int32_t> row_blocks(int32_t n, const int32_t *rp, int cap) {
       while (end < n && end - start < pcgk::kBlock && rp[end + 1] - rp[start] <= cap) ++end;
     }
     blk.push_back(end);
+    blk.push_back(rp[end]);
     start = end;
   }
   return blk;
@@ -295,8 +298,9 @@ struct pcg_ctx {
   double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
   void *tmp_in = nullptr, *tmp_out = nullptr;  // matvec staging (vec dtype)
   double *stage64 = nullptr;                   // FP64 staging of boundary vectors
-  State *st = nullptr, *st64 = nullptr;
-  double *partials = nullptr;
+  State *st = nullptr, *st64 = nullptr;  // two slots each (see State)
+  pcgk::Partials parts{};
+  double *partials = nullptr;  // backing store of parts: 5 * partial_cap doubles
   int64_t partial_cap = 0;
   State *hst = nullptr;  // pinned: [0..1] status readback, [2] upload
   hipEvent_t ev[2] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
@@ -390,7 +394,7 @@ int upload_csr(pcg_ctx *ctx, int32_t n, const int32_t *rp, const int32_t *ci, co
   }
   const int vdt = ctx->cfg.vec_dtype;
   std::vector<int32_t> blk = row_blocks(n, rp, pcgk::lds_cap(vdt));
-  m.nblk = (int32_t)blk.size() - 1;
+  m.nblk = (int32_t)blk.size() / 2 - 1;
   if ((rc = dev_alloc(ctx, sizeof(int32_t) * blk.size(), (void **)&m.blk))) return rc;
   HIPCHK(hipMemcpy(m.blk, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice));
   m.grid = grid_for(ctx, m.nblk);
@@ -399,14 +403,18 @@ int upload_csr(pcg_ctx *ctx, int32_t n, const int32_t *rp, const int32_t *ci, co
 
 int ensure_partials(pcg_ctx *ctx) {
   int64_t need = 1024;
-  for (const DevCSR *m : {&ctx->A, &ctx->G, &ctx->GT})
+  for (const DevCSR *m : {&ctx->A, &ctx->G, &ctx->GT, &ctx->A64})
     if (m->grid > need) need = m->grid;
-  need *= 2;
   if (need <= ctx->partial_cap) return PCG_OK;
   dev_free(ctx, ctx->partials);
-  int rc = dev_alloc(ctx, sizeof(double) * need, (void **)&ctx->partials);
+  ctx->partial_cap = 0;
+  int rc = dev_alloc(ctx, sizeof(double) * 5 * need, (void **)&ctx->partials);
   if (rc) return rc;
   ctx->partial_cap = need;
+  ctx->parts.g = ctx->partials;
+  ctx->parts.rt = ctx->partials + need;
+  ctx->parts.b = ctx->partials + 3 * need;
+  ctx->parts.tr = ctx->partials + 4 * need;
   return PCG_OK;
 }
 
@@ -486,14 +494,20 @@ void enqueue_iteration(pcg_ctx *ctx, const Types &ty, bool replace, hipError_t &
   auto chain = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  chain(pcgk::launch_iter_A(ty, ctx->A, ctx->v, ctx->st, ctx->partials, ctx->stream));
-  if (replace) {
-    chain(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->partials, 1, true, false, true, ctx->stream));
-    chain(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, ctx->partials, 1, ctx->stream));
-  } else {
-    chain(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, ctx->partials, 0, ctx->stream));
-  }
-  chain(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, eps != 0.0, ctx->stream));
+  const pcgk::Partials &p = ctx->parts;
+  chain(pcgk::launch_iter_A(ty, ctx->A, ctx->v, ctx->st, p, ctx->stream));
+  if (replace) chain(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, p, 1, true, false, true, ctx->stream));
+  const int mode = replace ? 1 : 0;
+  chain(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, p, ctx->A.grid, mode, ctx->stream));
+  chain(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, p, ctx->GT.grid, eps != 0.0, mode, ctx->stream));
+}
+
+// Start (or restart) sequence: t = G^T r, s = G t, delta, beta = 0, tests.
+int enqueue_start(pcg_ctx *ctx, const Types &ty, double eps) {
+  const pcgk::Partials &p = ctx->parts;
+  HIPCHK(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, p, ctx->A.grid, 2, ctx->stream));
+  HIPCHK(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, p, ctx->GT.grid, eps != 0.0, 2, ctx->stream));
+  return PCG_OK;
 }
 
 int get_graph(pcg_ctx *ctx, const Types &ty, int iters, bool replace_first, hipGraphExec_t *out) {
@@ -534,15 +548,17 @@ int solve_core(pcg_ctx *ctx, const Types &ty, double tol, int maxit, CoreOut &ou
   init.tol = tol;
   init.eps = ctx->cfg.eps * ctx->g_scale * ctx->g_scale;
   init.rr_period = ctx->cfg.rr_period;
-  State *up = &ctx->hst[2];
-  *up = init;
-  HIPCHK(hipMemcpyAsync(ctx->st, up, sizeof(State), hipMemcpyHostToDevice, s));
+  ctx->hst[2] = init;
+  ctx->hst[3] = init;
+  HIPCHK(hipMemcpyAsync(ctx->st, &ctx->hst[2], 2 * sizeof(State), hipMemcpyHostToDevice, s));
   HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.d0, n, 0.0, s));
   HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.d1, n, 0.0, s));
-  HIPCHK(pcgk::launch_norm_b(ty, n, ctx->v, ctx->st, ctx->partials, s));
-  HIPCHK(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->partials, 0, false, false, true, s));
-  HIPCHK(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, ctx->partials, 2, s));
-  HIPCHK(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, init.eps != 0.0, s));
+  HIPCHK(pcgk::launch_norm_b(ty, n, ctx->v, ctx->st, ctx->parts, s));
+  HIPCHK(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->parts, 0, false, false, true, s));
+  {
+    int rc = enqueue_start(ctx, ty, init.eps);
+    if (rc) return rc;
+  }
 
   const int rr = ctx->cfg.rr_period;
   int K = ctx->cfg.graph_iters;
@@ -596,7 +612,7 @@ int solve_core(pcg_ctx *ctx, const Types &ty, double tol, int maxit, CoreOut &ou
       return PCG_OK;
     }
     HIPCHK(pcgk::launch_finalize(ty, n, ctx->v, ctx->st, s));
-    HIPCHK(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->partials, 0, false, true, false, s));
+    HIPCHK(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->parts, 0, false, true, false, s));
     State f;
     HIPCHK(hipMemcpyAsync(&ctx->hst[0], ctx->st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -614,8 +630,10 @@ int solve_core(pcg_ctx *ctx, const Types &ty, double tol, int maxit, CoreOut &ou
       // restart from the true residual (now in the current r slot)
       ++restarts;
       HIPCHK(pcgk::launch_state_restart(ctx->st, s));
-      HIPCHK(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, ctx->partials, 2, s));
-      HIPCHK(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, init.eps != 0.0, s));
+      {
+        int rc = enqueue_start(ctx, ty, init.eps);
+        if (rc) return rc;
+      }
       base = f.iter;
       continue;
     }
@@ -669,14 +687,15 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
   State init{};
   init.tol = tol;
   ctx->hst[2] = init;
-  HIPCHK(hipMemcpyAsync(ctx->st64, &ctx->hst[2], sizeof(State), hipMemcpyHostToDevice, s));
-  HIPCHK(pcgk::launch_norm_b(t64, n, v64, ctx->st64, ctx->partials, s));
+  ctx->hst[3] = init;
+  HIPCHK(hipMemcpyAsync(ctx->st64, &ctx->hst[2], 2 * sizeof(State), hipMemcpyHostToDevice, s));
+  HIPCHK(pcgk::launch_norm_b(t64, n, v64, ctx->st64, ctx->parts, s));
   int total_iters = 0, outer = 0, restarts = 0, status = PCG_NOT_CONVERGED;
   double prev = INFINITY, relres = NAN, last_rec = NAN;
   const double inner_tol = ctx->cfg.inner_tol > 0 ? ctx->cfg.inner_tol : 1e-4;
   const int max_outer = ctx->cfg.max_outer > 0 ? ctx->cfg.max_outer : 30;
   for (;;) {
-    HIPCHK(pcgk::launch_resid(t64, ctx->A64, v64, ctx->st64, ctx->partials, 0, false, true, false, s));
+    HIPCHK(pcgk::launch_resid(t64, ctx->A64, v64, ctx->st64, ctx->parts, 0, false, true, false, s));
     HIPCHK(hipMemcpyAsync(&ctx->hst[0], ctx->st64, sizeof(State), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const State h = ctx->hst[0];
@@ -777,14 +796,14 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
     ctx->cus = prop.multiProcessorCount;
   if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) return fail(PCG_EDEVICE);
   ctx->own_stream = true;
-  if (hipHostMalloc((void **)&ctx->hst, sizeof(State) * 3, hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void **)&ctx->hst, sizeof(State) * 4, hipHostMallocDefault) != hipSuccess)
     return fail(PCG_EDEVICE);
   for (auto &e : ctx->ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(PCG_EDEVICE);
   if (hipEventCreate(&ctx->t0) != hipSuccess || hipEventCreate(&ctx->t1) != hipSuccess) return fail(PCG_EDEVICE);
-  if (dev_alloc(ctx, sizeof(State), (void **)&ctx->st) || dev_alloc(ctx, sizeof(State), (void **)&ctx->st64))
+  if (dev_alloc(ctx, 2 * sizeof(State), (void **)&ctx->st) || dev_alloc(ctx, 2 * sizeof(State), (void **)&ctx->st64))
     return fail(PCG_ENOMEM);
-  if (hipMemset(ctx->st, 0, sizeof(State)) != hipSuccess || hipMemset(ctx->st64, 0, sizeof(State)) != hipSuccess)
+  if (hipMemset(ctx->st, 0, 2 * sizeof(State)) != hipSuccess || hipMemset(ctx->st64, 0, 2 * sizeof(State)) != hipSuccess)
     return fail(PCG_EDEVICE);
   *out = ctx;
   return PCG_OK;
@@ -853,7 +872,7 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
     HIPCHK(hipMemcpy(ctx->A64.val, ctx->a_val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
     // the FP64 kernels stage FP64 products: their row blocks differ
     std::vector<int32_t> blk = row_blocks(n, ctx->a_rp.data(), pcgk::lds_cap(pcgk::F64));
-    ctx->A64.nblk = (int32_t)blk.size() - 1;
+    ctx->A64.nblk = (int32_t)blk.size() / 2 - 1;
     ctx->A64.blk = nullptr;
     if ((rc = dev_alloc(ctx, sizeof(int32_t) * blk.size(), (void **)&ctx->A64.blk))) return rc;
     HIPCHK(hipMemcpy(ctx->A64.blk, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice));
@@ -861,12 +880,6 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
   }
   ctx->have_a = true;
   if ((rc = ensure_partials(ctx))) return rc;
-  if (ctx->A64.grid > ctx->partial_cap / 2) {
-    dev_free(ctx, ctx->partials);
-    ctx->partial_cap = 0;
-    if ((rc = dev_alloc(ctx, sizeof(double) * 2 * ctx->A64.grid, (void **)&ctx->partials))) return rc;
-    ctx->partial_cap = 2 * ctx->A64.grid;
-  }
   return ensure_vectors(ctx, n);
 }
 
@@ -1008,6 +1021,135 @@ int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device) 
       break;
   }
   return store_vec(ctx, ctx->tmp_out, vdt, y, on_device, n);
+}
+
+int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
+  if (!ctx) return PCG_EINVAL;
+  if (!ms || iters < 1 || iters > 100000) return PCG_EINVAL;
+  if (!ctx->have_a || !ctx->have_g) {
+    ctx->err = "pcg_time_kernels: matrix and preconditioner must be set";
+    return PCG_ESTATE;
+  }
+  const int32_t n = ctx->n;
+  const Types ty = ctx->ty;
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  // a fresh solve of the stored right-hand side from x0 = 0 that never stops
+  State init{};
+  init.maxit = INT32_MAX;
+  init.tol = -1.0;
+  init.eps = ctx->cfg.eps * ctx->g_scale * ctx->g_scale;
+  ctx->hst[2] = init;
+  ctx->hst[3] = init;
+  HIPCHK(hipMemcpyAsync(ctx->st, &ctx->hst[2], 2 * sizeof(State), hipMemcpyHostToDevice, s));
+  HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.x, n, 0.0, s));
+  HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.d0, n, 0.0, s));
+  HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.d1, n, 0.0, s));
+  HIPCHK(pcgk::launch_norm_b(ty, n, ctx->v, ctx->st, ctx->parts, s));
+  HIPCHK(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->parts, 0, false, false, true, s));
+  {
+    int rc0 = enqueue_start(ctx, ty, init.eps);
+    if (rc0) return rc0;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  State h;
+  HIPCHK(hipMemcpy(&h, ctx->st, sizeof(State), hipMemcpyDeviceToHost));
+  if (h.done) {
+    ctx->err = "pcg_time_kernels: solve a nonzero right-hand side first";
+    return PCG_ESTATE;
+  }
+  std::vector<hipEvent_t> ev(4 * (size_t)iters, nullptr);
+  int rc = PCG_OK;
+  for (auto &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) rc = PCG_EDEVICE;
+  double acc[4] = {0, 0, 0, 0};
+  if (rc == PCG_OK) {
+    hipError_t e = hipSuccess;
+    auto chain = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    for (int it = 0; it < iters; ++it) {
+      chain(hipEventRecord(ev[4 * it], s));
+      chain(pcgk::launch_iter_A(ty, ctx->A, ctx->v, ctx->st, ctx->parts, s));
+      chain(hipEventRecord(ev[4 * it + 1], s));
+      chain(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, ctx->parts, ctx->A.grid, 0, s));
+      chain(hipEventRecord(ev[4 * it + 2], s));
+      chain(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, ctx->parts, ctx->GT.grid, init.eps != 0.0, 0, s));
+      chain(hipEventRecord(ev[4 * it + 3], s));
+    }
+    chain(hipStreamSynchronize(s));
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+      float t;
+      for (int k = 0; k < 3; ++k) {
+        chain(hipEventElapsedTime(&t, ev[4 * it + k], ev[4 * it + k + 1]));
+        acc[k] += t;
+      }
+      chain(hipEventElapsedTime(&t, ev[4 * it], ev[4 * it + 3]));
+      acc[3] += t;
+    }
+    if (e != hipSuccess) {
+      ctx->err = std::string("pcg_time_kernels: ") + hipGetErrorString(e);
+      rc = PCG_EDEVICE;
+    }
+  }
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  HIPCHK(hipMemcpy(&h, ctx->st, sizeof(State), hipMemcpyDeviceToHost));
+  if (h.done) {
+    ctx->err = "pcg_time_kernels: the iteration stopped (breakdown) while timing";
+    return PCG_EBREAKDOWN;
+  }
+  for (int k = 0; k < 4; ++k) ms[k] = acc[k] / iters;
+  if (bytes) {
+    const double sa = (double)pcgk::dtype_size(ctx->cfg.a_dtype), sg = (double)pcgk::dtype_size(ctx->cfg.g_dtype),
+                 sv = (double)pcgk::dtype_size(ctx->cfg.vec_dtype);
+    const double rp = 4.0 * (n + 1.0);
+    bytes[0] = (double)ctx->A.nnz * (sa + 4) + rp + 6.0 * n * sv;
+    bytes[1] = (double)ctx->GT.nnz * (sg + 4) + rp + 4.0 * n * sv;
+    bytes[2] = (double)ctx->G.nnz * (sg + 4) + rp + (init.eps != 0.0 ? 3.0 : 2.0) * n * sv;
+    bytes[3] = bytes[0] + bytes[1] + bytes[2];
+  }
+  return PCG_OK;
+}
+
+int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double *ms_per_copy) {
+  if (bytes < 16 || reps < 1 || !gbps) return PCG_EINVAL;
+  bytes &= ~int64_t(15);
+  if (hipSetDevice(device) != hipSuccess) return PCG_EDEVICE;
+  void *src = nullptr, *dst = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = PCG_OK;
+  hipDeviceProp_t prop;
+  int cus = 256;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+  if (hipMalloc(&src, bytes) != hipSuccess || hipMalloc(&dst, bytes) != hipSuccess) rc = PCG_ENOMEM;
+  if (!rc && (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+              hipEventCreate(&e1) != hipSuccess))
+    rc = PCG_EDEVICE;
+  if (!rc && hipMemsetAsync(src, 0, bytes, s) != hipSuccess) rc = PCG_EDEVICE;
+  float ms = 0.0f;
+  if (!rc) {
+    const int grid = cus * 16;
+    hipError_t e = hipSuccess;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = pcgk::launch_copy(src, dst, bytes, grid, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = pcgk::launch_copy(src, dst, bytes, grid, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) rc = PCG_EDEVICE;
+  }
+  if (!rc) {
+    *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    if (ms_per_copy) *ms_per_copy = ms / reps;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  if (src) (void)hipFree(src);
+  if (dst) (void)hipFree(dst);
+  (void)hipGetLastError();
+  return rc;
 }
 
 int pcg_validate_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col, int require_diag) {

@@ -29,7 +29,7 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 EXPORTS = [
     "pcg_config_default", "pcg_create", "pcg_destroy", "pcg_set_matrix", "pcg_set_precond", "pcg_build_precond",
     "pcg_solve", "pcg_matvec", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
-    "pcg_last_error", "pcg_strerror",
+    "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth",
 ]
 
 
@@ -82,6 +82,8 @@ def load():
     lib.pcg_build_g_host.argtypes = [c_int, i32, P, P, P, P, P, P]
     lib.pcg_bytes_per_iter.argtypes = [i32, i64, i64, c_int, c_int, c_int]
     lib.pcg_bytes_per_iter.restype = dbl
+    lib.pcg_time_kernels.argtypes = [P, c_int, P, P]
+    lib.pcg_copy_bandwidth.argtypes = [c_int, i64, c_int, P, P]
     lib.pcg_last_error.argtypes = [P]
     lib.pcg_last_error.restype = ctypes.c_char_p
     lib.pcg_strerror.argtypes = [c_int]
@@ -146,6 +148,16 @@ def build_g_host(kind: int, A):
     if st != OK:
         raise PCGError(st, "pcg_build_g_host")
     return grp, gci, gv
+
+
+def copy_bandwidth(bytes_: int, reps: int = 20, device: int = 0):
+    """(GB/s, ms per copy) of the library's plain device copy kernel."""
+    g = np.zeros(1)
+    m = np.zeros(1)
+    st = load().pcg_copy_bandwidth(device, int(bytes_), int(reps), g.ctypes.data, m.ctypes.data)
+    if st != OK:
+        raise PCGError(st, "pcg_copy_bandwidth")
+    return float(g[0]), float(m[0])
 
 
 def bytes_per_iter(n, nnz_a, nnz_g, a_dtype=F64, g_dtype=F64, vec_dtype=F64) -> float:
@@ -245,6 +257,14 @@ class Solver:
         self._check(st, "pcg_solve", allow)
         return SolveOut(x, res.status, res.iters, res.outer_iters, res.restarts, res.relres_true, res.relres_rec,
                         res.t_solve_ms, res.bytes_per_iter)
+
+    def time_kernels(self, iters: int = 50):
+        """{'ms': [A, GT, G, iteration], 'bytes': [A, GT, G, iteration]} per launch."""
+        ms = np.zeros(4)
+        by = np.zeros(4)
+        self._check(self._lib.pcg_time_kernels(self._h, int(iters), ms.ctypes.data, by.ctypes.data),
+                    "pcg_time_kernels")
+        return {"ms": ms.tolist(), "bytes": by.tolist()}
 
     def matvec(self, op: int, x):
         if _is_torch(x):
