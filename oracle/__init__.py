@@ -66,6 +66,8 @@ def _load():
     lib.or_spmv.argtypes = [i32, P, P, P, P, P, ctypes.c_int]
     lib.or_spmv_t.argtypes = [i32, i32, P, P, P, P, P]
     lib.or_transpose.argtypes = [i32, i32, P, P, P, P, P, P]
+    lib.or_spmv_f32.argtypes = [i32, P, P, P, P, P]
+    lib.or_spmv_t_f32.argtypes = [i32, i32, P, P, P, P, P]
     lib.or_dot.restype = ctypes.c_double
     lib.or_dot.argtypes = [i32, P, P]
     lib.or_apply_precond.argtypes = [i32, P, P, P, ctypes.c_double, P, P]
@@ -125,6 +127,25 @@ def spmv_t(G, x, ncols: int | None = None) -> np.ndarray:
     x = _c(x, np.float64)
     y = np.empty(ncols, np.float64)
     _load().or_spmv_t(G.n, ncols, _p(G.rowptr), _p(G.col), _p(G.val), _p(x), _p(y))
+    return y
+
+
+def spmv_f32(rowptr, col, val32, x32) -> np.ndarray:
+    """y = A x with FP32 values, vector and sums (FP32 storage path)."""
+    rp, ci = _c(rowptr, np.int32), _c(col, np.int32)
+    v, x = _c(val32, np.float32), _c(x32, np.float32)
+    y = np.empty(rp.shape[0] - 1, np.float32)
+    _load().or_spmv_f32(rp.shape[0] - 1, _p(rp), _p(ci), _p(v), _p(x), _p(y))
+    return y
+
+
+def spmv_t_f32(rowptr, col, val32, x32) -> np.ndarray:
+    """y = G^T x with FP32 values, vector and sums, rows of G scattered in order."""
+    rp, ci = _c(rowptr, np.int32), _c(col, np.int32)
+    v, x = _c(val32, np.float32), _c(x32, np.float32)
+    n = rp.shape[0] - 1
+    y = np.empty(n, np.float32)
+    _load().or_spmv_t_f32(n, n, _p(rp), _p(ci), _p(v), _p(x), _p(y))
     return y
 
 

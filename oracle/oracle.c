@@ -54,6 +54,24 @@ void or_spmv_t(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t *c
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) y[ci[k]] += v[k] * x[i];
 }
 
+/* Single-precision products for the mixed-precision path (vectors and
+ * accumulation in FP32): the same definitions with float operands, each
+ * product and sum rounded to FP32 in the order written. */
+void or_spmv_f32(int32_t n, const int32_t *rp, const int32_t *ci, const float *v, const float *x, float *y) {
+  for (int32_t i = 0; i < n; ++i) {
+    float s = 0.0f;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * x[ci[k]];
+    y[i] = s;
+  }
+}
+
+void or_spmv_t_f32(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t *ci, const float *v,
+                   const float *x, float *y) {
+  for (int32_t j = 0; j < ncols; ++j) y[j] = 0.0f;
+  for (int32_t i = 0; i < nrows; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) y[ci[k]] += v[k] * x[i];
+}
+
 /* CSR of the transpose by counting: out arrays sized ncols+1 / nnz. */
 void or_transpose(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t *ci, const double *v,
                   int32_t *trp, int32_t *tci, double *tv) {

@@ -67,8 +67,16 @@ struct Types {
   int g;    // F64, F32, BF16 or F16
 };
 
-constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
-constexpr int kLdsBytes = 16384;   // LDS staging for row products per workgroup
+// Compile-time tuning of the CSR-stream kernels (defaults measured best on
+// MI355X for 5-7 nonzeros per row).
+#ifndef PCG_BLOCK_THREADS
+#define PCG_BLOCK_THREADS 256
+#endif
+#ifndef PCG_LDS_BYTES
+#define PCG_LDS_BYTES 16384
+#endif
+constexpr int kBlock = PCG_BLOCK_THREADS;  // threads per workgroup (waves of 64); also max rows per row block
+constexpr int kLdsBytes = PCG_LDS_BYTES;   // LDS staging for row products per workgroup
 
 inline int lds_cap(int vec_dtype) { return kLdsBytes / (int)dtype_size(vec_dtype); }
 

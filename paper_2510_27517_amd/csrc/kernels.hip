@@ -41,14 +41,33 @@
 
 namespace pcgk {
 
+// Matrix values and column indices are read exactly once per product:
+// nontemporal loads keep them from displacing the gathered vector entries in
+// L2 (PCG_NT_MATRIX = 0 uses ordinary loads).
+#ifndef PCG_NT_MATRIX
+#define PCG_NT_MATRIX 1
+#endif
+#ifndef PCG_UNROLL
+#define PCG_UNROLL 4
+#endif
+
 struct bf16_t { uint16_t bits; };
 
-__device__ __forceinline__ double ldval(const double *p, int64_t k) { return p[k]; }
-__device__ __forceinline__ float ldval(const float *p, int64_t k) { return p[k]; }
-__device__ __forceinline__ float ldval(const bf16_t *p, int64_t k) {
-  return __uint_as_float((uint32_t)p[k].bits << 16);
+template <typename T>
+__device__ __forceinline__ T ldstream(const T *p, int64_t k) {
+#if PCG_NT_MATRIX
+  return __builtin_nontemporal_load(p + k);
+#else
+  return p[k];
+#endif
 }
-__device__ __forceinline__ float ldval(const _Float16 *p, int64_t k) { return (float)p[k]; }
+
+__device__ __forceinline__ double ldval(const double *p, int64_t k) { return ldstream(p, k); }
+__device__ __forceinline__ float ldval(const float *p, int64_t k) { return ldstream(p, k); }
+__device__ __forceinline__ float ldval(const bf16_t *p, int64_t k) {
+  return __uint_as_float((uint32_t)ldstream((const uint16_t *)p, k) << 16);
+}
+__device__ __forceinline__ float ldval(const _Float16 *p, int64_t k) { return (float)ldstream(p, k); }
 
 // Workgroup b is dispatched to XCD b % 8; give XCD x the logical ids
 // [x*G/8, (x+1)*G/8) so its workgroups cover consecutive rows. G % 8 == 0.
@@ -91,8 +110,8 @@ __device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds,
       e = M.rp[row + 1] - k0;
       pv = pre(row);
     }
-#pragma unroll 4
-    for (int k = k0 + tid; k < k1; k += kBlock) lds[k - k0] = (TACC)ldval(M.val, k) * gather(M.ci[k]);
+#pragma unroll PCG_UNROLL
+    for (int k = k0 + tid; k < k1; k += kBlock) lds[k - k0] = (TACC)ldval(M.val, k) * gather(ldstream(M.ci, k));
     __syncthreads();
     if (has) {
       TACC sum = 0;
@@ -107,7 +126,7 @@ __device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds,
     TACC sum = 0;
     for (int c0 = k0; c0 < k1; c0 += cap) {
       const int c1 = min(c0 + cap, k1);
-      for (int k = c0 + tid; k < c1; k += kBlock) lds[k - c0] = (TACC)ldval(M.val, k) * gather(M.ci[k]);
+      for (int k = c0 + tid; k < c1; k += kBlock) lds[k - c0] = (TACC)ldval(M.val, k) * gather(ldstream(M.ci, k));
       __syncthreads();
       if (tid == 0)
         for (int k = 0; k < c1 - c0; ++k) sum += lds[k];

@@ -1,0 +1,152 @@
+"""Mixed-precision path on the GPU: FP32 vectors and A, G stored in FP32,
+BF16 or FP16, FP32 accumulation, FP64 dot products, FP64 iterative
+refinement. Operator products are compared bit for bit with the oracle's FP32
+products on identically rounded operands; solves are compared with the FP64
+oracle, each stating its error."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_27517_amd import inputs
+from paper_2510_27517_amd.inputs import CSR
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def round_sig(v, sig, emin):
+    """Round to nearest-even onto a binary format with `sig` significant bits
+    and minimum normal exponent emin (subnormals included)."""
+    v = np.asarray(v, np.float64)
+    out = np.zeros_like(v)
+    nz = v != 0
+    a = np.abs(v[nz])
+    _, e = np.frexp(a)
+    q = np.where(e - 1 < emin, emin - (sig - 1), e - sig)
+    out[nz] = np.copysign(np.ldexp(np.rint(np.ldexp(a, -q)), q), v[nz])
+    return out
+
+
+def stored_g(val, gdt):
+    """G's values as the library stores them (as float32) and the scale."""
+    if gdt == "f32":
+        return val.astype(np.float32), 1.0
+    if gdt == "bf16":
+        return round_sig(val, 8, -126).astype(np.float32), 1.0
+    _, e = np.frexp(np.abs(val).max())
+    scale = 2.0 ** (14 - int(e))
+    return round_sig(val * scale, 11, -14).astype(np.float32), scale
+
+
+def _random_spd(n, seed):
+    rng = np.random.default_rng(seed)
+    import scipy.sparse as sp
+
+    m = sp.random(n, n, density=6.0 / n, random_state=seed, data_rvs=lambda k: rng.uniform(-1, 1, k)).tocsr()
+    m = m + m.T
+    m.setdiag(0)
+    m.eliminate_zeros()
+    m = m + sp.diags(np.asarray(abs(m).sum(axis=1)).ravel() + 1.0)
+    return CSR.from_scipy(m)
+
+
+@pytest.mark.parametrize("gdt", ["f32", "bf16", "f16"])
+def test_fp32_operator_products_bitwise(gpu_lib, gdt):
+    pcg = gpu_lib
+    A = _random_spd(3001, 7)
+    rng = np.random.default_rng(8)
+    G = CSR(A.rowptr.copy(), A.col.copy(), rng.uniform(-2, 2, A.nnz) * 10.0 ** rng.integers(-3, 1, A.nnz))
+    x = rng.standard_normal(A.n)
+    eps = 0.25
+    say("fp32 products", gdt)
+    with pcg.Solver(pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype=gdt, eps=eps)) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        x32 = x.astype(np.float32)
+        A32 = A.val.astype(np.float32)
+        g32, sc = stored_g(G.val, gdt)
+        assert np.array_equal(s.matvec(pcg.OP_A, x), oracle.spmv_f32(A.rowptr, A.col, A32, x32).astype(np.float64))
+        inv = np.float32(1.0 / sc)
+        gt = oracle.spmv_t_f32(G.rowptr, G.col, g32, x32)
+        assert np.array_equal(s.matvec(pcg.OP_GT, x), (inv * gt + np.float32(0) * x32).astype(np.float64))
+        g = oracle.spmv_f32(G.rowptr, G.col, g32, x32)
+        assert np.array_equal(s.matvec(pcg.OP_G, x), (inv * g + np.float32(0) * x32).astype(np.float64))
+        o = oracle.spmv_f32(G.rowptr, G.col, g32, gt)
+        y = np.float32(1.0 / (sc * sc)) * o + np.float32(eps) * x32
+        assert np.array_equal(s.matvec(pcg.OP_MINV, x), y.astype(np.float64))
+
+
+def test_fp32_solve_against_fp64_oracle(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.poisson(3, 24, 1.0, 1)
+    b = inputs.rhs(A.n, 1)
+    say("fp32 solve 24^3 tol 1e-6")
+    with pcg.Solver(pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="f32")) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        got = s.solve(b, tol=1e-6, maxit=2000)
+    ref = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-6, maxit=2000, delta_form=1)
+    assert got.status == pcg.OK and got.relres_true <= 1e-6
+    assert abs(got.iters - ref.iters) <= 3, (got.iters, ref.iters)
+    r64 = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+    err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
+    say(f"fp32: iters {got.iters} (oracle {ref.iters}), fp64 relres {r64:.2e}, error vs oracle {err:.2e}")
+    assert r64 <= 2e-6 and err <= 1e-4
+
+
+@pytest.mark.parametrize("gdt", ["f32", "bf16", "f16"])
+def test_refinement_reaches_1e10(gpu_lib, gdt):
+    """FP32 inner PCG with G in gdt, FP64 outer residual: the true FP64
+    residual reaches 1e-10 and x matches the FP64 oracle solution."""
+    pcg = gpu_lib
+    A = inputs.poisson(3, 24, 1.0, 2)
+    b = inputs.rhs(A.n, 2)
+    say("refinement", gdt)
+    with pcg.Solver(pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype=gdt, refine=1)) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        got = s.solve(b, tol=1e-10, maxit=2000)
+    ref = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-13, maxit=5000, delta_form=1)
+    r64 = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+    err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
+    say(f"{gdt}: status {got.status} outer {got.outer_iters} inner total {got.iters} "
+        f"fp64 relres {r64:.2e} (reported {got.relres_true:.2e}) error vs oracle {err:.2e}")
+    assert got.status == pcg.OK and got.outer_iters >= 2
+    assert got.relres_true <= 1e-10 and r64 <= 1.0001e-10
+    assert err <= 1e-8
+
+
+def test_refinement_elasticity_bf16(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.elasticity(8, 1.0, 0.3, 0)
+    b = inputs.rhs(A.n, 5)
+    say("refinement elasticity 8^3 x3 bf16")
+    with pcg.Solver(pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        got = s.solve(b, tol=1e-10, maxit=5000)
+    ref = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-13, maxit=20000, delta_form=1)
+    r64 = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+    err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
+    say(f"elasticity bf16: outer {got.outer_iters} inner {got.iters} fp64 relres {r64:.2e} error {err:.2e}")
+    assert got.status == pcg.OK and r64 <= 1.0001e-10
+    assert err <= 1e-6
+
+
+def test_mixed_zero_rhs_and_bad_config(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.poisson(2, 8)
+    with pcg.Solver(pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        z = s.solve(np.zeros(A.n), np.ones(A.n))
+        assert z.status == pcg.OK and np.all(z.x == 0)
+    with pytest.raises(pcg.PCGError) as e:
+        pcg.Solver(pcg.default_config(vec_dtype="f64", a_dtype="f64", g_dtype="bf16"))
+    assert e.value.status == pcg.EINVAL
