@@ -80,7 +80,8 @@ typedef struct {
   int max_outer;     /* refinement steps at most (default 30) */
   int graph_iters;   /* iterations per captured HIP graph replay (default 10; 0 = plain launches) */
   int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */
-  int reserved[8];
+  int mem_budget_mb; /* device memory pool for batched / served systems, MiB (0: half the free memory at first use) */
+  int reserved[7];
 } pcg_config;
 
 typedef struct {
@@ -90,9 +91,29 @@ typedef struct {
   int restarts;        /* times the recurrence residual met tol but b - A x did not (restart from it) */
   double relres_true;  /* ||b - A x|| / ||b|| at exit, formed in the vector precision (FP64 under refinement) */
   double relres_rec;   /* recurrence ||r|| / ||b|| at exit */
-  double t_solve_ms;   /* wall time of the solve on the device stream */
+  double t_solve_ms;   /* single solve: device time; batched: admission to completion (host clock) */
   double bytes_per_iter; /* algorithmic HBM bytes of one iteration (A, G^T, G once; 12 vector streams) */
+  double t_latency_ms; /* batched: submission to completion (host clock) */
+  double t_queue_ms;   /* batched: submission to admission (host clock) */
 } pcg_result;
+
+/* One system of a batch (all pointers host memory, borrowed for the call). */
+typedef struct {
+  int32_t n;
+  int64_t nnz_a;
+  const int32_t *a_rowptr;
+  const int32_t *a_col;
+  const double *a_val;
+  int64_t nnz_g;             /* G given explicitly (g_rowptr non-NULL) ... */
+  const int32_t *g_rowptr;
+  const int32_t *g_col;
+  const double *g_val;
+  int g_kind;                /* ... or built on the host by this kind (PCG_G_FSAI, ...) */
+  const double *b;           /* right-hand side, n entries */
+  double *x;                 /* x0 on submission (NULL: zeros); the solution is written here on completion */
+  double tol;
+  int maxit;
+} pcg_system;
 
 /* Fills cfg with the defaults: device 0, own stream, all FP64, rr_period 50,
  * eps 0, no refinement, inner_tol 1e-4, max_outer 30, graph_iters 10,
@@ -146,6 +167,36 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes);
  * frees its own buffers. The measured HBM ceiling and the reference for
  * calibrating memory-traffic counters. */
 int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double *ms_per_copy);
+
+/* Batching and serving. Independent systems of any sizes are solved
+ * together: each CG kernel is one launch over all admitted systems (each
+ * system keeps its own row blocks, reductions and scalars, so its result is
+ * bit for bit the one it gets alone). The context owns a device memory pool
+ * (pcg_config.mem_budget_mb); a request is admitted when its storage fits and
+ * refused with PCG_ENOMEM only if it exceeds the whole pool. Vector and
+ * storage types are the context's; refinement is not available here.
+ *
+ * pcg_submit_batch copies every input and returns at once with one ticket per
+ * system (nothing is queued if any system is invalid). Host worker threads
+ * build G (when not given) and stage the data. pcg_progress runs one
+ * scheduler step on the calling thread: admit ready requests in arrival order
+ * while the pool has room, run `iters` CG iterations over all admitted systems
+ * (iteration-level continuous batching), and retire finished systems (x
+ * written to the caller's pointer, device storage freed). *active and *queued
+ * (may be NULL) report the systems admitted and waiting. pcg_poll returns
+ * PCG_PENDING until the ticket's request has finished, then its final status
+ * (and fills *res); a finished ticket is released by the poll that reports
+ * it. Submission may run concurrently with pcg_progress from another thread;
+ * the caller must keep each system's x buffer alive until its ticket is done.
+ * pcg_solve_batch submits `count` systems and progresses until all finish,
+ * `iters_per_step` iterations per step (0: 20). */
+int pcg_submit_batch(pcg_ctx *ctx, int count, const pcg_system *sys, uint64_t *tickets);
+int pcg_progress(pcg_ctx *ctx, int iters, int *active, int *queued);
+int pcg_poll(pcg_ctx *ctx, uint64_t ticket, pcg_result *res);
+int pcg_solve_batch(pcg_ctx *ctx, int count, const pcg_system *sys, pcg_result *results, int iters_per_step);
+
+/* Capacity and bytes in use of the batch pool (0 before first use). */
+int pcg_pool_info(pcg_ctx *ctx, size_t *capacity, size_t *in_use);
 
 /* Host-only helpers (no GPU needed). */
 

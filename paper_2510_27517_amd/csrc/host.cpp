@@ -1,0 +1,305 @@
+// Host-side building blocks (see host.h) and the host-only C ABI entry points.
+#include "host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+
+#include "kernels.h"
+#include "pcg.h"
+
+namespace pcgh {
+
+// ------------------------------------------------------------ host helpers
+
+int validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, int require_diag, std::string *why) {
+  auto fail = [&](const char *m, int64_t i) {
+    if (why) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "%s (at %lld)", m, (long long)i);
+      *why = buf;
+    }
+    return PCG_EINVAL;
+  };
+  if (n < 0 || nnz < 0 || nnz > INT32_MAX) return fail("bad n or nnz", nnz);
+  if (n > 0 && (!rp || (nnz > 0 && !ci))) return fail("null CSR array", 0);
+  if (n == 0) return nnz == 0 ? PCG_OK : fail("nnz > 0 with n = 0", nnz);
+  if (rp[0] != 0) return fail("rowptr[0] != 0", 0);
+  for (int32_t i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return fail("rowptr decreases", i);
+    bool diag = false;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      if (k >= nnz) return fail("rowptr exceeds nnz", i);
+      if (ci[k] < 0 || ci[k] >= n) return fail("column out of range", k);
+      if (k > rp[i] && ci[k] <= ci[k - 1]) return fail("columns not strictly ascending", k);
+      if (ci[k] == i) diag = true;
+    }
+    if (require_diag && !diag) return fail("missing diagonal entry", i);
+  }
+  if (rp[n] != nnz) return fail("rowptr[n] != nnz", n);
+  return PCG_OK;
+}
+
+void transpose_csr(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                   const std::vector<double> &v, std::vector<int32_t> &trp, std::vector<int32_t> &tci,
+                   std::vector<double> &tv) {
+  const int64_t nnz = rp[n];
+  trp.assign(n + 1, 0);
+  tci.resize(nnz);
+  tv.resize(nnz);
+  for (int64_t k = 0; k < nnz; ++k) trp[ci[k] + 1]++;
+  for (int32_t j = 0; j < n; ++j) trp[j + 1] += trp[j];
+  std::vector<int32_t> pos(trp.begin(), trp.end() - 1);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int32_t p = pos[ci[k]]++;
+      tci[p] = i;
+      tv[p] = v[k];
+    }
+}
+
+// Round to nearest, ties to even, onto a binary format with `sig` significant
+// bits, minimum normal exponent emin and largest finite value vmax.
+double round_to_format(double v, int sig, int emin, double vmax) {
+  if (v == 0.0 || !std::isfinite(v)) return v;
+  int e;
+  std::frexp(std::fabs(v), &e);  // |v| in [2^(e-1), 2^e)
+  int q = e - sig;
+  if (e - 1 < emin) q = emin - (sig - 1);  // subnormal quantum
+  double r = std::ldexp(std::nearbyint(std::ldexp(std::fabs(v), -q)), q);
+  if (r > vmax) r = INFINITY;
+  return std::copysign(r, v);
+}
+
+uint16_t to_bf16_bits(double v) {
+  const float f = (float)round_to_format(v, 8, -126, 3.3895313892515355e38);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return (uint16_t)(u >> 16);
+}
+
+uint16_t to_f16_bits(double v) {
+  const double r = round_to_format(v, 11, -14, 65504.0);
+  if (std::isinf(r)) return r > 0 ? 0x7C00 : 0xFC00;
+  if (std::isnan(r)) return 0x7E00;
+  uint16_t sign = std::signbit(r) ? 0x8000 : 0;
+  double a = std::fabs(r);
+  if (a == 0.0) return sign;
+  int e;
+  double m = std::frexp(a, &e);  // a = m 2^e, m in [0.5, 1)
+  if (e - 1 >= -14) {
+    const uint16_t exp = (uint16_t)(e - 1 + 15);
+    const uint16_t frac = (uint16_t)std::lround((m * 2.0 - 1.0) * 1024.0);
+    return sign | (uint16_t)(exp << 10) | frac;
+  }
+  return sign | (uint16_t)std::lround(a * 16777216.0);  // subnormal: multiples of 2^-24
+}
+
+// ---------------------------------------------- preconditioner builders (host)
+
+int64_t g_nnz(int kind, int32_t n, const int32_t *rp, const int32_t *ci) {
+  if (kind == PCG_G_JACOBI || kind == PCG_G_IDENTITY) return n;
+  if (kind != PCG_G_FSAI && kind != PCG_G_FIXED) return -1;
+  int64_t c = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] <= i);
+  return c;
+}
+
+// FSAI rows [r0, r1) of the lower factor G_L on tril(A): with A[J,J] = L L^T
+// (J = lower pattern of row i, i last), the FSAI row is L^-T e_last, i.e. the
+// last column of L^-T, found by one back substitution L^T g = e_last.
+int fsai_rows(int32_t r0, int32_t r1, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *lrp,
+              int32_t *lci, double *lv, int32_t n) {
+  std::vector<int32_t> where(n, -1);
+  std::vector<int32_t> J;
+  std::vector<double> S, g;
+  for (int32_t i = r0; i < r1; ++i) {
+    J.clear();
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] <= i) J.push_back(ci[k]);
+    const int m = (int)J.size();
+    if (m == 0 || J.back() != i) return PCG_EINVAL;
+    for (int a = 0; a < m; ++a) where[J[a]] = a;
+    S.assign((size_t)m * m, 0.0);
+    for (int a = 0; a < m; ++a) {
+      const int32_t row = J[a];
+      for (int32_t k = rp[row]; k < rp[row + 1]; ++k) {
+        const int32_t c = ci[k];
+        if (c > i) break;
+        const int b = where[c];
+        if (b >= 0) S[(size_t)a * m + b] = v[k];
+      }
+    }
+    for (int a = 0; a < m; ++a) where[J[a]] = -1;
+    // Cholesky (lower) in place
+    for (int c = 0; c < m; ++c) {
+      double dsum = S[(size_t)c * m + c];
+      for (int k = 0; k < c; ++k) dsum -= S[(size_t)c * m + k] * S[(size_t)c * m + k];
+      if (!(dsum > 0.0)) return PCG_EBREAKDOWN;
+      const double l = std::sqrt(dsum);
+      S[(size_t)c * m + c] = l;
+      for (int a = c + 1; a < m; ++a) {
+        double e = S[(size_t)a * m + c];
+        for (int k = 0; k < c; ++k) e -= S[(size_t)a * m + k] * S[(size_t)c * m + k];
+        S[(size_t)a * m + c] = e / l;
+      }
+    }
+    // back substitution L^T g = e_last
+    g.assign(m, 0.0);
+    for (int a = m - 1; a >= 0; --a) {
+      double e = (a == m - 1) ? 1.0 : 0.0;
+      for (int k = a + 1; k < m; ++k) e -= S[(size_t)k * m + a] * g[k];
+      g[a] = e / S[(size_t)a * m + a];
+    }
+    for (int a = 0; a < m; ++a) {
+      lci[lrp[i] + a] = J[a];
+      lv[lrp[i] + a] = g[a];
+    }
+  }
+  return PCG_OK;
+}
+
+// Builds G (CSR) for `kind`; for the lower kinds also returns G^T directly.
+int build_g(int kind, int32_t n, const int32_t *rp, const int32_t *ci, const double *v, std::vector<int32_t> &grp,
+            std::vector<int32_t> &gci, std::vector<double> &gv) {
+  if (kind == PCG_G_JACOBI || kind == PCG_G_IDENTITY) {
+    grp.resize(n + 1);
+    gci.resize(n);
+    gv.resize(n);
+    for (int32_t i = 0; i <= n; ++i) grp[i] = i;
+    for (int32_t i = 0; i < n; ++i) {
+      gci[i] = i;
+      if (kind == PCG_G_IDENTITY) {
+        gv[i] = 1.0;
+        continue;
+      }
+      double d = 0.0;
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) d = v[k];
+      if (!(d > 0.0)) return PCG_EINVAL;
+      gv[i] = 1.0 / std::sqrt(d);
+    }
+    return PCG_OK;
+  }
+  const int64_t m = g_nnz(kind, n, rp, ci);
+  if (m < 0) return PCG_EINVAL;
+  std::vector<int32_t> lrp(n + 1, 0), lci(m);
+  std::vector<double> lv(m);
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t c = 0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] <= i);
+    lrp[i + 1] = lrp[i] + c;
+  }
+  if (kind == PCG_G_FIXED) {
+    std::vector<double> dg(n, 0.0);
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) dg[i] = v[k];
+    for (int32_t i = 0; i < n; ++i) {
+      if (!(dg[i] > 0.0)) return PCG_EINVAL;
+      int32_t p = lrp[i];
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int32_t j = ci[k];
+        if (j > i) break;
+        lci[p] = j;
+        lv[p] = (j == i) ? 1.0 / std::sqrt(dg[i]) : -0.25 * v[k] / std::sqrt(dg[i] * dg[j]);
+        ++p;
+      }
+    }
+    grp.swap(lrp);
+    gci.swap(lci);
+    gv.swap(lv);
+    return PCG_OK;  // this G is lower-triangular itself
+  }
+  // FSAI: G_L rows in parallel, then G = G_L^T
+  unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (n < 20000) nt = 1;
+  std::vector<int> rcs(nt, PCG_OK);
+  std::vector<std::thread> th;
+  for (unsigned w = 0; w < nt; ++w) {
+    const int32_t a = (int32_t)((int64_t)n * w / nt), b = (int32_t)((int64_t)n * (w + 1) / nt);
+    th.emplace_back([&, a, b, w] { rcs[w] = fsai_rows(a, b, rp, ci, v, lrp.data(), lci.data(), lv.data(), n); });
+  }
+  for (auto &t : th) t.join();
+  for (int rc : rcs)
+    if (rc != PCG_OK) return rc;
+  transpose_csr(n, lrp, lci, lv, grp, gci, gv);
+  return PCG_OK;
+}
+
+// Row-block partition for the CSR-stream kernels: consecutive rows, at most
+// kBlock rows and `cap` nonzeros per block; a longer row is a block alone.
+// Returned as (row start, nonzero start) pairs, nblk + 1 of them.
+std::vector<int32_t> row_blocks(int32_t n, const int32_t *rp, int cap) {
+  std::vector<int32_t> blk;
+  blk.push_back(0);
+  blk.push_back(rp[0]);
+  int32_t start = 0;
+  while (start < n) {
+    int32_t end = start + 1;
+    if (rp[start + 1] - rp[start] <= cap) {
+      while (end < n && end - start < pcgk::kBlock && rp[end + 1] - rp[start] <= cap) ++end;
+    }
+    blk.push_back(end);
+    blk.push_back(rp[end]);
+    start = end;
+  }
+  return blk;
+}
+
+double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt) {
+  const double sa = (double)pcgk::dtype_size(adt), sg = (double)pcgk::dtype_size(gdt),
+               sv = (double)pcgk::dtype_size(vdt);
+  return (double)a * (sa + 4) + 2.0 * (double)g * (sg + 4) + 3.0 * 4.0 * (n + 1.0) + 12.0 * n * sv;
+}
+
+}  // namespace pcgh
+
+extern "C" {
+
+int pcg_validate_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col, int require_diag) {
+  return pcgh::validate_csr(n, nnz, rowptr, col, require_diag, nullptr);
+}
+
+int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col) {
+  if (n <= 0 || !rowptr || !col) return -1;
+  return pcgh::g_nnz(kind, n, rowptr, col);
+}
+
+int pcg_build_g_host(int kind, int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                     int32_t *g_rowptr, int32_t *g_col, double *g_val) {
+  if (n <= 0 || !rowptr || !col || !val || !g_rowptr || !g_col || !g_val) return PCG_EINVAL;
+  int rc = pcgh::validate_csr(n, rowptr[n], rowptr, col, 1, nullptr);
+  if (rc) return rc;
+  std::vector<int32_t> grp, gci;
+  std::vector<double> gv;
+  rc = pcgh::build_g(kind, n, rowptr, col, val, grp, gci, gv);
+  if (rc) return rc;
+  std::memcpy(g_rowptr, grp.data(), sizeof(int32_t) * grp.size());
+  std::memcpy(g_col, gci.data(), sizeof(int32_t) * gci.size());
+  std::memcpy(g_val, gv.data(), sizeof(double) * gv.size());
+  return PCG_OK;
+}
+
+double pcg_bytes_per_iter(int32_t n, int64_t nnz_a, int64_t nnz_g, int a_dtype, int g_dtype, int vec_dtype) {
+  return pcgh::bytes_per_iter(n, nnz_a, nnz_g, a_dtype, g_dtype, vec_dtype);
+}
+
+const char *pcg_strerror(int status) {
+  switch (status) {
+    case PCG_OK: return "ok";
+    case PCG_PENDING: return "pending";
+    case PCG_NOT_CONVERGED: return "not converged (maxit reached)";
+    case PCG_EINVAL: return "invalid argument";
+    case PCG_ESTATE: return "invalid state";
+    case PCG_ENOMEM: return "out of device memory";
+    case PCG_EBREAKDOWN: return "breakdown (matrix or preconditioner not SPD, or non-finite values)";
+    case PCG_EDEVICE: return "device error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,37 @@
+// Host-side building blocks of the library: CSR validation and transpose,
+// rounding to the half storage formats, preconditioner construction, and the
+// row-block partition used by the kernels. No GPU calls.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pcgh {
+
+// PCG_OK or PCG_EINVAL (with a reason in *why when given).
+int validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, int require_diag, std::string *why);
+
+// CSR of the transpose of an n x n matrix (stable: rows of the transpose list
+// the original rows in ascending order).
+void transpose_csr(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                   const std::vector<double> &v, std::vector<int32_t> &trp, std::vector<int32_t> &tci,
+                   std::vector<double> &tv);
+
+// Round to nearest, ties to even, onto the BF16 / FP16 grids (bit patterns).
+uint16_t to_bf16_bits(double v);
+uint16_t to_f16_bits(double v);
+
+// Nonzeros of G for a preconditioner kind on A's pattern (-1: unknown kind).
+int64_t g_nnz(int kind, int32_t n, const int32_t *rp, const int32_t *ci);
+
+// G (CSR) for a preconditioner kind built from A.
+int build_g(int kind, int32_t n, const int32_t *rp, const int32_t *ci, const double *v, std::vector<int32_t> &grp,
+            std::vector<int32_t> &gci, std::vector<double> &gv);
+
+// Row-block partition: (row start, nonzero start) pairs, nblk + 1 of them.
+std::vector<int32_t> row_blocks(int32_t n, const int32_t *rp, int cap);
+
+// Algorithmic bytes of one PCG iteration (12 vector streams).
+double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt);
+
+}  // namespace pcgh

@@ -1,5 +1,13 @@
 // Internal interface between the library driver (pcg.cpp) and the gfx950
 // kernels (kernels.hip). Not part of the public C ABI.
+//
+// Every kernel works on a set of independent systems at once. A system is
+// described by a SysDev record in a device-resident directory; a launch set
+// lists the systems of one launch and, for each kind of kernel, maps every
+// workgroup of the launch to (system, local workgroup). A system's share of a
+// launch (its workgroup count, row blocks and reduction order) depends only
+// on the system itself, so it computes bit for bit the same whether it is
+// solved alone or inside any batch. A single-system solve is a set of one.
 #pragma once
 #include <hip/hip_runtime_api.h>
 #include <cstdint>
@@ -11,11 +19,11 @@ enum Dtype : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 
 inline size_t dtype_size(int dt) { return dt == F64 ? 8 : dt == F32 ? 4 : 2; }
 
-// Device-resident solver scalars, kept in two slots: st[0] is written by the
-// G-kernel (and by the host and single-workgroup helper kernels), st[1] by
-// the G^T-kernel. A kernel never reads a slot it writes, so the workgroup that
-// publishes new scalars cannot race the others reading the old ones. No
-// host round trip is needed inside an iteration.
+// Device-resident solver scalars of one system, kept in two slots: st[0] is
+// written by the G-kernel (and by the host and one-thread helper kernels),
+// st[1] by the G^T-kernel. A kernel never reads a slot it writes, so the
+// workgroup that publishes new scalars cannot race the others reading the
+// old ones. No host round trip is needed inside an iteration.
 struct alignas(64) State {
   double delta;    // delta_i = r_i^T M^-1 r_i
   double alpha;    // alpha_i, pending in x until the next A-kernel applies it
@@ -46,27 +54,6 @@ enum Status : int32_t {
   ST_ZERO_B = 5,       // ||b|| = 0: x = 0
 };
 
-// A CSR matrix resident on the device, with its row-block partition: block k
-// covers rows [blk[2k], blk[2k+2]) and nonzeros [blk[2k+1], blk[2k+3]),
-// holding at most `lds_cap` nonzeros unless it is a single longer row.
-struct DevCSR {
-  int32_t n = 0;
-  int64_t nnz = 0;
-  int32_t *rp = nullptr, *ci = nullptr;
-  void *val = nullptr;
-  int dtype = F64;
-  int32_t *blk = nullptr;  // nblk + 1 (row start, nonzero start) pairs
-  int32_t nblk = 0;
-  int32_t grid = 0;        // workgroups per launch (multiple of 8)
-};
-
-// Vector-kind launch geometry: which storage types one solver instance uses.
-struct Types {
-  int vec;  // F64 or F32 (accumulation type equals this)
-  int a;    // F64 or F32
-  int g;    // F64, F32, BF16 or F16
-};
-
 // Compile-time tuning of the CSR-stream kernels (defaults measured best on
 // MI355X for 5-7 nonzeros per row).
 #ifndef PCG_BLOCK_THREADS
@@ -80,66 +67,97 @@ constexpr int kLdsBytes = PCG_LDS_BYTES;   // LDS staging for row products per w
 
 inline int lds_cap(int vec_dtype) { return kLdsBytes / (int)dtype_size(vec_dtype); }
 
+// A CSR matrix resident on the device, with its row-block partition: block k
+// covers rows [blk[2k], blk[2k+2]) and nonzeros [blk[2k+1], blk[2k+3]),
+// holding at most `lds_cap` nonzeros unless it is a single longer row.
+// `grid` is the system's workgroup count for products with this matrix (a
+// multiple of 8, a function of nblk only).
+struct DevCSR {
+  const int32_t *rp = nullptr, *ci = nullptr;
+  const void *val = nullptr;
+  const int32_t *blk = nullptr;
+  int32_t nblk = 0;
+  int32_t grid = 0;
+  int64_t nnz = 0;
+  int32_t n = 0;
+  int32_t dtype = F64;
+};
+
+// One system in the directory (device-resident, POD).
+struct SysDev {
+  DevCSR A, GT, G;
+  void *x, *r0, *r1, *d0, *d1, *q, *t, *s, *b;  // n entries of the vector type
+  State *st;                                    // two slots
+  double *pg;   // A.grid partials: d^T A d
+  double *prt;  // 2 * GT.grid partials: ||r||^2, ||t||^2
+  double *pb;   // gB partials: ||b||^2
+  double *ptr;  // A.grid partials: ||b - A x||^2
+  int32_t n;
+  int32_t gB;   // workgroups of the ||b|| kernel (multiple of 8)
+};
+
+// Storage types shared by all systems of a context.
+struct Types {
+  int vec;  // F64 or F32 (accumulation type equals this)
+  int a;    // F64 or F32
+  int g;    // F64, F32, BF16 or F16
+};
+
+// One launch over a set of systems. Workgroup w of an A-kind launch (A, resid,
+// elementwise) works for system mapA[w].x as its local workgroup mapA[w].y;
+// likewise mapGT, mapG, mapB. `set` lists the systems (for one-thread-per-
+// system helpers). All arrays are device-resident.
+struct LaunchSet {
+  const SysDev *dir = nullptr;
+  const int2 *mapA = nullptr, *mapGT = nullptr, *mapG = nullptr, *mapB = nullptr;
+  const int32_t *set = nullptr;
+  int32_t nA = 0, nGT = 0, nG = 0, nB = 0, nset = 0;  // workgroups of each kind, systems
+};
+
 // ---- launchers (all asynchronous on `s`) ----------------------------------
 
-// Iteration kernels. `v` holds the solver's vectors.
-struct Vecs {
-  void *x, *r0, *r1, *d0, *d1, *q, *t, *s, *b;
-};
-
-// Per-workgroup partial sums (one value per logical workgroup, value j of
-// workgroup L at p[j * P + L]). Every workgroup of the consuming kernel adds
-// them in the same fixed order, so each obtains the identical total without
-// atomics or inter-workgroup synchronisation.
-struct Partials {
-  double *g;   // d^T A d          (written by the A-kernel)
-  double *rt;  // ||r||^2, ||t||^2 (written by the G^T-kernel)
-  double *b;   // ||b||^2
-  double *tr;  // ||b - A x||^2
-};
-
-// r_slot = b - A (x [+ alpha d_i]);  slot = iter&1 (sel 0) or (iter+1)&1 (sel 1).
-// with_d: add the pending alpha d_i; reduce: store ||r||^2 in st->true_rr;
-// respect_done: return at once when st->done is set.
-// with_d needs the A-kernel's partials (grid A.grid) to form alpha_i.
-hipError_t launch_resid(const Types &ty, const DevCSR &A, const Vecs &v, State *st, const Partials &p,
-                        int slot_sel, bool with_d, bool reduce, bool respect_done, hipStream_t s);
+// r_slot = b - A (x [+ alpha_i d_i]), slot = iter&1 (sel 0) or (iter+1)&1
+// (sel 1); sel 2: only for systems at a replacement iteration (i > 0,
+// i % rr_period == 0), slot (iter+1)&1. with_d forms alpha_i from the A-kernel's partials; reduce writes
+// ||r||^2 into st[0].true_rr; respect_done skips stopped systems.
+hipError_t launch_resid(const Types &ty, const LaunchSet &L, int slot_sel, bool with_d, bool reduce,
+                        bool respect_done, hipStream_t s);
 
 // A-kernel of iteration i: d_i = s + beta d_{i-1}; x += alpha_{i-1} d_{i-1};
-// q = A d_i; gamma = d_i^T q; alpha_i = delta_i / gamma.
-hipError_t launch_iter_A(const Types &ty, const DevCSR &A, const Vecs &v, State *st, const Partials &p,
-                         hipStream_t s);
+// q = A d_i; partials of d_i^T q.
+hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s);
 
-// G^T-kernel: mode 0 (update r_{i+1} = r_i - alpha q), 1 (r_{i+1} already
-// replaced), 2 (start or restart: r_i given, no update, beta = 0).
-// Reduces the A-kernel's partials (P_a workgroups) to gamma, alpha_i, or flags
-// breakdown. t = G^T r; partials ||r||^2, ||t||^2. Publishes st[1].
-hipError_t launch_iter_GT(const Types &ty, const DevCSR &GT, const Vecs &v, State *st, const Partials &p, int P_a,
-                          int mode, hipStream_t s);
+// G^T-kernel: mode 0 (r_{i+1} = r_i - alpha_i q), 1 (r_{i+1} already
+// replaced), 2 (start or restart: r_i given, beta = 0), 3 (0 or 1 per system
+// from its iteration count and replacement period). Forms gamma and
+// alpha_i (or flags breakdown), t = G^T r, partials of ||r||^2 and ||t||^2;
+// publishes st[1].
+hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStream_t s);
 
-// G-kernel: reduces the G^T-kernel's partials (P_gt) to delta_{i+1},
-// beta_{i+1}, the convergence / maxit / breakdown tests and iter; publishes
-// st[0]; then s = G t + eps r unless stopped. `mode` as for the G^T-kernel.
-hipError_t launch_iter_G(const Types &ty, const DevCSR &G, const Vecs &v, State *st, const Partials &p, int P_gt,
-                         bool has_eps, int mode, hipStream_t s);
+// G-kernel: delta_{i+1}, beta_{i+1}, convergence / maxit / breakdown, iter;
+// publishes st[0]; then s = G t + eps r unless stopped.
+hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s);
 
 // x += alpha d_{iter-1} (the pending update), then alpha = 0.
-hipError_t launch_finalize(const Types &ty, int32_t n, const Vecs &v, State *st, hipStream_t s);
+hipError_t launch_finalize(const Types &ty, const LaunchSet &L, hipStream_t s);
 
-// ||b||^2, ||b||, tol*||b|| into st[0]; ZERO_B status when b = 0.
-hipError_t launch_norm_b(const Types &ty, int32_t n, const Vecs &v, State *st, const Partials &p, hipStream_t s);
+// ||b||^2, tol*||b|| into st[0]; ZERO_B status when b = 0.
+hipError_t launch_norm_b(const Types &ty, const LaunchSet &L, hipStream_t s);
 
-// st[0].true_rr = sum of the true-residual partials (P workgroups).
-hipError_t launch_reduce_true(State *st, const Partials &p, int P, hipStream_t s);
+// Fill d0, d1 (and x when zero_x) of every system with zeros.
+hipError_t launch_zero_dirs(const Types &ty, const LaunchSet &L, bool zero_x, hipStream_t s);
 
-// Small state edits, ordered on the stream.
-hipError_t launch_state_restart(State *st, hipStream_t s);  // done = 0, status = RUNNING, alpha = beta = 0
+// Refinement over FP64 views (see k_outer): what 0: x64 += rn x_inner;
+// what 1: b_inner = r64 / rn, with rn = sqrt(st[0].true_rr) of each view.
+hipError_t launch_outer(int vec_dtype, const LaunchSet &L64, int what, hipStream_t s);
 
-// y = op(x) for parity checks and the plain operator products: y = M x with M
-// any stored CSR matrix (vector types = ty.vec).
-hipError_t launch_spmv(const Types &ty, const DevCSR &M, int mdtype, const void *x, void *y, hipStream_t s);
+// done = 0, status = RUNNING, alpha = beta = 0 for every system of the set.
+hipError_t launch_state_restart(const LaunchSet &L, hipStream_t s);
 
-// y = a*y + b*x (elementwise, vector type ty.vec).
+// y = M x for one stored matrix (plain product, vector type ty.vec).
+hipError_t launch_spmv(const Types &ty, const DevCSR &M, const void *x, void *y, hipStream_t s);
+
+// y = a*y + b*x (elementwise, vector type).
 hipError_t launch_axpby(int vec_dtype, int32_t n, double a, void *y, double b, const void *x, hipStream_t s);
 
 // Conversions: dst[i] = (Tdst) (scale * src[i]).

@@ -82,7 +82,7 @@ struct Mat {
 };
 
 template <typename TM>
-static Mat<TM> mat(const DevCSR &m) {
+__device__ __forceinline__ Mat<TM> mat(const DevCSR &m) {
   return Mat<TM>{m.rp, m.ci, (const TM *)m.val, m.blk, m.nblk};
 }
 
@@ -137,18 +137,20 @@ __device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds,
 }
 
 // This workgroup's row blocks: first, first + stride, ... < end; L is its
-// logical index (the slot of its partial sums).
+// logical index (the slot of its partial sums). l is the workgroup's index
+// among its system's G workgroups (G and the system's first workgroup are
+// multiples of 8, so l % 8 is the XCD the workgroup runs on).
 struct Sched {
   int first, end, stride, L;
 };
 
-__device__ __forceinline__ Sched sched(int nblk) {
-  const int G = gridDim.x, W = G >> 3, x = blockIdx.x & 7, l = blockIdx.x >> 3;
+__device__ __forceinline__ Sched sched(int nblk, int l, int G) {
+  const int W = G >> 3, x = l & 7, w = l >> 3;
   Sched sc;
-  sc.first = (int)((int64_t)x * nblk / 8) + l;
+  sc.first = (int)((int64_t)x * nblk / 8) + w;
   sc.end = (int)((int64_t)(x + 1) * nblk / 8);
   sc.stride = W;
-  sc.L = x * W + l;
+  sc.L = x * W + w;
   return sc;
 }
 
@@ -176,11 +178,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
 
 // Write this workgroup's partial sums (value j at p[j * G + L]).
 template <int NV>
-__device__ __forceinline__ void put_partials(double (&v)[NV], double *p, int L, double *sh) {
+__device__ __forceinline__ void put_partials(double (&v)[NV], double *p, int L, int G, double *sh) {
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int j = 0; j < NV; ++j) p[(int64_t)j * gridDim.x + L] = v[j];
+    for (int j = 0; j < NV; ++j) p[(int64_t)j * G + L] = v[j];
 }
 
 // Sum the P partials of each value in a fixed order; every thread gets the totals.
@@ -206,19 +208,23 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ p, int P
 // ------------------------------------------------------------------ kernels
 
 template <typename TV, typename TA>
-__global__ __launch_bounds__(kBlock) void k_iter_A(Mat<TA> A, TV *__restrict__ x, const TV *__restrict__ s,
-                                                   TV *__restrict__ d0, TV *__restrict__ d1, TV *__restrict__ q,
-                                                   const State *__restrict__ st, double *__restrict__ pg) {
+__global__ __launch_bounds__(kBlock) void k_iter_A(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
-  const State &S = st[0];
+  const int2 m = map[blockIdx.x];
+  const SysDev &D = dir[m.x];
+  const State &S = D.st[0];
   if (S.done) return;
+  const Mat<TA> A = mat<TA>(D.A);
   const int it = S.iter;
   const TV beta = (TV)S.beta, ap = (TV)S.alpha;
-  const TV *__restrict__ dold = (it & 1) ? d0 : d1;  // d_{i-1}
-  TV *__restrict__ dnew = (it & 1) ? d1 : d0;        // d_i
+  TV *__restrict__ x = (TV *)D.x;
+  const TV *__restrict__ s = (const TV *)D.s;
+  TV *__restrict__ q = (TV *)D.q;
+  const TV *__restrict__ dold = (const TV *)((it & 1) ? D.d0 : D.d1);  // d_{i-1}
+  TV *__restrict__ dnew = (TV *)((it & 1) ? D.d1 : D.d0);              // d_i
   double part[1] = {0.0};
-  const Sched sc = sched(A.nblk);
+  const Sched sc = sched(A.nblk, m.y, D.A.grid);
   for (int b = sc.first; b < sc.end; b += sc.stride)
     stream_block<TV>(
         A, b, lds, [&](int row) { return RowVals<TV>{s[row], dold[row], x[row]}; },
@@ -230,29 +236,30 @@ __global__ __launch_bounds__(kBlock) void k_iter_A(Mat<TA> A, TV *__restrict__ x
           x[row] = pv.c + ap * pv.b;
           part[0] += (double)di * (double)sum;
         });
-  put_partials<1>(part, pg, sc.L, sh);
+  put_partials<1>(part, D.pg, sc.L, D.A.grid, sh);
 }
 
 template <typename TV, typename TG>
-__global__ __launch_bounds__(kBlock) void k_iter_GT(Mat<TG> GT, TV *__restrict__ r0, TV *__restrict__ r1,
-                                                    const TV *__restrict__ q, TV *__restrict__ t,
-                                                    State *__restrict__ st, const double *__restrict__ pg, int P_a,
-                                                    double *__restrict__ prt, int mode) {
+__global__ __launch_bounds__(kBlock) void k_iter_GT(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+                                                    int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
-  const State &S = st[0];
+  const int2 m = map[blockIdx.x];
+  const SysDev &D = dir[m.x];
+  const State &S = D.st[0];
   if (S.done) return;
   const int it = S.iter;
+  if (mode == 3) mode = (S.rr_period > 0 && it > 0 && it % S.rr_period == 0) ? 1 : 0;
   double alpha = S.alpha, gamma = S.gamma;
   bool brk = false;
   if (mode != 2) {
     double g[1];
-    sum_partials<1>(pg, P_a, g, sh);
+    sum_partials<1>(D.pg, D.A.grid, g, sh);
     gamma = g[0];
     brk = !(gamma > 0.0) || !isfinite(gamma);
     alpha = brk ? 0.0 : S.delta / gamma;  // on breakdown x already holds x_i
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (m.y == 0 && threadIdx.x == 0) {
     State o = S;
     o.gamma = gamma;
     o.alpha = alpha;
@@ -260,14 +267,17 @@ __global__ __launch_bounds__(kBlock) void k_iter_GT(Mat<TG> GT, TV *__restrict__
       o.status = ST_BREAK_GAMMA;
       o.done = 1;
     }
-    st[1] = o;
+    D.st[1] = o;
   }
   if (brk) return;
+  const Mat<TG> GT = mat<TG>(D.GT);
+  const TV *__restrict__ q = (const TV *)D.q;
+  TV *__restrict__ t = (TV *)D.t;
   const TV al = (mode == 0) ? (TV)alpha : (TV)0;
-  const TV *__restrict__ src = (((mode == 1) ? it + 1 : it) & 1) ? r1 : r0;
-  TV *__restrict__ dst = ((it + 1) & 1) ? r1 : r0;
+  const TV *__restrict__ src = (const TV *)((((mode == 1) ? it + 1 : it) & 1) ? D.r1 : D.r0);
+  TV *__restrict__ dst = (TV *)(((it + 1) & 1) ? D.r1 : D.r0);
   double part[2] = {0.0, 0.0};
-  const Sched sc = sched(GT.nblk);
+  const Sched sc = sched(GT.nblk, m.y, D.GT.grid);
   if (mode == 0) {
     for (int b = sc.first; b < sc.end; b += sc.stride)
       stream_block<TV>(
@@ -291,25 +301,25 @@ __global__ __launch_bounds__(kBlock) void k_iter_GT(Mat<TG> GT, TV *__restrict__
             part[1] += (double)sum * (double)sum;
           });
   }
-  put_partials<2>(part, prt, sc.L, sh);
+  put_partials<2>(part, D.prt, sc.L, D.GT.grid, sh);
 }
 
 template <typename TV, typename TG, bool HAS_EPS>
-__global__ __launch_bounds__(kBlock) void k_iter_G(Mat<TG> G, const TV *__restrict__ t, const TV *__restrict__ r0,
-                                                   const TV *__restrict__ r1, TV *__restrict__ s,
-                                                   State *__restrict__ st, const double *__restrict__ prt, int P_gt,
+__global__ __launch_bounds__(kBlock) void k_iter_G(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                    int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
-  if (st[0].done) return;  // stopped before this iteration's G^T-kernel ran
-  const State &S = st[1];
+  const int2 m = map[blockIdx.x];
+  const SysDev &D = dir[m.x];
+  if (D.st[0].done) return;  // stopped before this iteration's G^T-kernel ran
+  const State &S = D.st[1];
   if (S.done) {  // the G^T-kernel flagged a breakdown: publish it
-    if (blockIdx.x == 0 && threadIdx.x == 0) st[0] = S;
+    if (m.y == 0 && threadIdx.x == 0) D.st[0] = S;
     return;
   }
   const int it = S.iter;
   double v[2];
-  sum_partials<2>(prt, P_gt, v, sh);
+  sum_partials<2>(D.prt, D.GT.grid, v, sh);
   const double rr = v[0], tt = v[1];
   const double dn = tt + S.eps * rr;
   State o = S;
@@ -331,11 +341,14 @@ __global__ __launch_bounds__(kBlock) void k_iter_G(Mat<TG> G, const TV *__restri
       o.done = 1;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) st[0] = o;
+  if (m.y == 0 && threadIdx.x == 0) D.st[0] = o;
   if (o.done) return;
-  const TV *__restrict__ rc = (i1 & 1) ? r1 : r0;
+  const Mat<TG> G = mat<TG>(D.G);
+  const TV *__restrict__ t = (const TV *)D.t;
+  TV *__restrict__ s = (TV *)D.s;
+  const TV *__restrict__ rc = (const TV *)((i1 & 1) ? D.r1 : D.r0);
   const TV eps = (TV)S.eps;
-  const Sched sc = sched(G.nblk);
+  const Sched sc = sched(G.nblk, m.y, D.G.grid);
   for (int b = sc.first; b < sc.end; b += sc.stride)
     stream_block<TV>(
         G, b, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, (TV)0, (TV)0}; },
@@ -349,28 +362,33 @@ __global__ __launch_bounds__(kBlock) void k_iter_G(Mat<TG> G, const TV *__restri
 }
 
 template <typename TV, typename TA>
-__global__ __launch_bounds__(kBlock) void k_resid(Mat<TA> A, const TV *__restrict__ b, const TV *__restrict__ x,
-                                                  const TV *__restrict__ d0, const TV *__restrict__ d1,
-                                                  TV *__restrict__ r0, TV *__restrict__ r1,
-                                                  const State *__restrict__ st, const double *__restrict__ pg,
-                                                  int P_a, double *__restrict__ ptr, int slot_sel, int with_d,
-                                                  int respect_done) {
+__global__ __launch_bounds__(kBlock) void k_resid(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+                                                  int slot_sel, int with_d, int reduce, int respect_done) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
-  const State &S = st[0];
+  const int2 m = map[blockIdx.x];
+  const SysDev &D = dir[m.x];
+  const State &S = D.st[0];
   if (respect_done && S.done) return;
   const int it = S.iter;
-  TV *__restrict__ rout = ((it + slot_sel) & 1) ? r1 : r0;
-  const TV *__restrict__ dc = (it & 1) ? d1 : d0;  // d_i
+  if (slot_sel == 2) {  // replacement decided per system
+    if (!(S.rr_period > 0 && it > 0 && it % S.rr_period == 0)) return;
+    slot_sel = 1;
+  }
+  const Mat<TA> A = mat<TA>(D.A);
+  const TV *__restrict__ b = (const TV *)D.b;
+  const TV *__restrict__ x = (const TV *)D.x;
+  TV *__restrict__ rout = (TV *)(((it + slot_sel) & 1) ? D.r1 : D.r0);
+  const TV *__restrict__ dc = (const TV *)((it & 1) ? D.d1 : D.d0);  // d_i
   TV al = (TV)0;
   if (with_d) {
     double g[1];
-    sum_partials<1>(pg, P_a, g, sh);
+    sum_partials<1>(D.pg, D.A.grid, g, sh);
     if (!(g[0] > 0.0) || !isfinite(g[0])) return;  // the G^T-kernel reports the breakdown
     al = (TV)(S.delta / g[0]);
   }
   double part[1] = {0.0};
-  const Sched sc = sched(A.nblk);
+  const Sched sc = sched(A.nblk, m.y, D.A.grid);
   auto pre = [&](int row) { return RowVals<TV>{b[row], (TV)0, (TV)0}; };
   auto epi = [&](int row, TV sum, const RowVals<TV> &pv) {
     const TV rv = pv.a - sum;
@@ -384,63 +402,130 @@ __global__ __launch_bounds__(kBlock) void k_resid(Mat<TA> A, const TV *__restric
     for (int k = sc.first; k < sc.end; k += sc.stride)
       stream_block<TV>(A, k, lds, pre, [&](int j) -> TV { return x[j]; }, epi);
   }
-  if (ptr) put_partials<1>(part, ptr, sc.L, sh);
+  if (reduce) put_partials<1>(part, D.ptr, sc.L, D.A.grid, sh);
+}
+
+// Rows [l n / G, (l+1) n / G) of a system for elementwise work on A's map.
+__device__ __forceinline__ void ew_rows(int n, int l, int G, int64_t &i0, int64_t &i1) {
+  i0 = (int64_t)l * n / G;
+  i1 = (int64_t)(l + 1) * n / G;
 }
 
 template <typename TV>
-__global__ __launch_bounds__(kBlock) void k_finalize(int32_t n, TV *__restrict__ x, const TV *__restrict__ d0,
-                                                     const TV *__restrict__ d1, const State *__restrict__ st) {
-  const TV al = (TV)st[0].alpha;
+__global__ __launch_bounds__(kBlock) void k_finalize(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
+  const int2 m = map[blockIdx.x];
+  const SysDev &D = dir[m.x];
+  const TV al = (TV)D.st[0].alpha;
   if (al == (TV)0) return;
-  const TV *__restrict__ dc = ((st[0].iter - 1) & 1) ? d1 : d0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-    x[i] = x[i] + al * dc[i];
-}
-
-__global__ void k_state_clear_alpha(State *st) { st[0].alpha = 0.0; }
-
-__global__ void k_state_restart(State *st) {
-  st[0].done = 0;
-  st[0].status = ST_RUNNING;
-  st[0].alpha = 0.0;
-  st[0].beta = 0.0;
+  TV *__restrict__ x = (TV *)D.x;
+  const TV *__restrict__ dc = (const TV *)(((D.st[0].iter - 1) & 1) ? D.d1 : D.d0);
+  int64_t i0, i1;
+  ew_rows(D.n, m.y, D.A.grid, i0, i1);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) x[i] = x[i] + al * dc[i];
 }
 
 template <typename TV>
-__global__ __launch_bounds__(kBlock) void k_norm_b(int32_t n, const TV *__restrict__ b, double *__restrict__ pb) {
+__global__ __launch_bounds__(kBlock) void k_zero_dirs(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+                                                      int zero_x) {
+  const int2 m = map[blockIdx.x];
+  const SysDev &D = dir[m.x];
+  TV *__restrict__ d0 = (TV *)D.d0;
+  TV *__restrict__ d1 = (TV *)D.d1;
+  TV *__restrict__ x = (TV *)D.x;
+  int64_t i0, i1;
+  ew_rows(D.n, m.y, D.A.grid, i0, i1);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    d0[i] = (TV)0;
+    d1[i] = (TV)0;
+    if (zero_x) x[i] = (TV)0;
+  }
+}
+
+// Refinement steps over FP64 system views (A = FP64 copy, x = x64, b = b64,
+// r0 = r64; s points at the inner solve's x and t at its right-hand side, both
+// in the vector type), with rn = sqrt(st[0].true_rr) of each view:
+//   update: x64 += rn * x_inner;   rhs: b_inner = (1 / rn) * r64.
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_outer(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+                                                  int what) {
+  const int2 m = map[blockIdx.x];
+  const SysDev &D = dir[m.x];
+  const double rn = sqrt(D.st[0].true_rr);
+  int64_t i0, i1;
+  ew_rows(D.n, m.y, D.A.grid, i0, i1);
+  if (what == 0) {
+    double *__restrict__ x64 = (double *)D.x;
+    const TV *__restrict__ c = (const TV *)D.s;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) x64[i] = x64[i] + rn * (double)c[i];
+  } else {
+    const double sc = 1.0 / rn;
+    const double *__restrict__ r64 = (const double *)D.r0;
+    TV *__restrict__ bi = (TV *)D.t;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) bi[i] = (TV)(sc * r64[i]);
+  }
+}
+
+// One thread per system of the set.
+__global__ void k_state_clear_alpha(const SysDev *__restrict__ dir, const int32_t *__restrict__ set, int nset) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nset) dir[set[k]].st[0].alpha = 0.0;
+}
+
+__global__ void k_state_restart(const SysDev *__restrict__ dir, const int32_t *__restrict__ set, int nset) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nset) return;
+  State &S = dir[set[k]].st[0];
+  S.done = 0;
+  S.status = ST_RUNNING;
+  S.alpha = 0.0;
+  S.beta = 0.0;
+}
+
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_norm_b(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
   __shared__ double sh[4 * (kBlock / 64)];
+  const int2 m = map[blockIdx.x];
+  const SysDev &D = dir[m.x];
+  const TV *__restrict__ b = (const TV *)D.b;
   double part[1] = {0.0};
-  // logical id -> contiguous slice, so the sum order is fixed
-  const int G = gridDim.x, L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  const int64_t i0 = (int64_t)L * n / G, i1 = (int64_t)(L + 1) * n / G;
+  // local workgroup l adds the contiguous slice l of b; the order is fixed
+  const int G = D.gB, l = m.y;
+  const int64_t i0 = (int64_t)l * D.n / G, i1 = (int64_t)(l + 1) * D.n / G;
 #pragma unroll 8
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) part[0] += (double)b[i] * (double)b[i];
-  put_partials<1>(part, pb, L, sh);
+  put_partials<1>(part, D.pb, l, G, sh);
 }
 
-// Single workgroup: ||b||^2 (what = 0, also tol * ||b|| and the b = 0 test)
-// or ||b - A x||^2 (what = 1) from P partials into st[0].
-__global__ __launch_bounds__(kBlock) void k_reduce_state(const double *__restrict__ p, int P, State *st, int what) {
+// One workgroup per system of the set: ||b||^2 (what = 0, also tol * ||b||
+// and the b = 0 test) or ||b - A x||^2 (what = 1) from its partials into st[0].
+__global__ __launch_bounds__(kBlock) void k_reduce_state(const SysDev *__restrict__ dir,
+                                                         const int32_t *__restrict__ set, int what) {
   __shared__ double sh[4 * (kBlock / 64)];
+  const SysDev &D = dir[set[blockIdx.x]];
   double v[1];
-  sum_partials<1>(p, P, v, sh);
+  if (what == 0)
+    sum_partials<1>(D.pb, D.gB, v, sh);
+  else
+    sum_partials<1>(D.ptr, D.A.grid, v, sh);
   if (threadIdx.x != 0) return;
+  State &S = D.st[0];
   if (what == 0) {
-    st[0].bb = v[0];
-    st[0].tol_nb = st[0].tol * sqrt(v[0]);
+    S.bb = v[0];
+    S.tol_nb = S.tol * sqrt(v[0]);
     if (v[0] == 0.0) {
-      st[0].status = ST_ZERO_B;
-      st[0].done = 1;
+      S.status = ST_ZERO_B;
+      S.done = 1;
     }
   } else {
-    st[0].true_rr = v[0];
+    S.true_rr = v[0];
   }
 }
 
 template <typename TV, typename TM>
-__global__ __launch_bounds__(kBlock) void k_spmv(Mat<TM> M, const TV *__restrict__ x, TV *__restrict__ y) {
+__global__ __launch_bounds__(kBlock) void k_spmv(DevCSR Md, const TV *__restrict__ x, TV *__restrict__ y) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
-  const Sched sc = sched(M.nblk);
+  const Mat<TM> M = mat<TM>(Md);
+  const Sched sc = sched(M.nblk, blockIdx.x, gridDim.x);
   for (int b = sc.first; b < sc.end; b += sc.stride)
     stream_block<TV>(
         M, b, lds, [&](int) { return RowVals<TV>{}; }, [&](int j) -> TV { return x[j]; },
@@ -502,96 +587,96 @@ static inline int ew_grid(int64_t n) {
     default: return hipErrorInvalidValue;                     \
   }
 
-hipError_t launch_iter_A(const Types &ty, const DevCSR &A, const Vecs &v, State *st, const Partials &p,
-                         hipStream_t s) {
-  if (ty.vec == F64 && A.dtype == F64) {
-    hipLaunchKernelGGL((k_iter_A<double, double>), dim3(A.grid), dim3(kBlock), 0, s, mat<double>(A), (double *)v.x,
-                       (const double *)v.s, (double *)v.d0, (double *)v.d1, (double *)v.q, st, p.g);
-  } else if (ty.vec == F32 && A.dtype == F32) {
-    hipLaunchKernelGGL((k_iter_A<float, float>), dim3(A.grid), dim3(kBlock), 0, s, mat<float>(A), (float *)v.x,
-                       (const float *)v.s, (float *)v.d0, (float *)v.d1, (float *)v.q, st, p.g);
+hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s) {
+  if (L.nA == 0) return hipSuccess;
+  if (ty.vec == F64 && ty.a == F64) {
+    hipLaunchKernelGGL((k_iter_A<double, double>), dim3(L.nA), dim3(kBlock), 0, s, L.dir, L.mapA);
+  } else if (ty.vec == F32 && ty.a == F32) {
+    hipLaunchKernelGGL((k_iter_A<float, float>), dim3(L.nA), dim3(kBlock), 0, s, L.dir, L.mapA);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_iter_GT(const Types &ty, const DevCSR &GT, const Vecs &v, State *st, const Partials &p, int P_a,
-                          int mode, hipStream_t s) {
-  PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(GT.dtype, TG, {
-    hipLaunchKernelGGL((k_iter_GT<TV, TG>), dim3(GT.grid), dim3(kBlock), 0, s, mat<TG>(GT), (TV *)v.r0,
-                       (TV *)v.r1, (const TV *)v.q, (TV *)v.t, st, p.g, P_a, p.rt, mode);
+hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStream_t s) {
+  if (L.nGT == 0) return hipSuccess;
+  PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(ty.g, TG, {
+    hipLaunchKernelGGL((k_iter_GT<TV, TG>), dim3(L.nGT), dim3(kBlock), 0, s, L.dir, L.mapGT, mode);
   }));
   return hipGetLastError();
 }
 
-hipError_t launch_iter_G(const Types &ty, const DevCSR &G, const Vecs &v, State *st, const Partials &p, int P_gt,
-                         bool has_eps, int mode, hipStream_t s) {
-  PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(G.dtype, TG, {
+hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s) {
+  if (L.nG == 0) return hipSuccess;
+  PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(ty.g, TG, {
     if (has_eps)
-      hipLaunchKernelGGL((k_iter_G<TV, TG, true>), dim3(G.grid), dim3(kBlock), 0, s, mat<TG>(G), (const TV *)v.t,
-                         (const TV *)v.r0, (const TV *)v.r1, (TV *)v.s, st, p.rt, P_gt, mode);
+      hipLaunchKernelGGL((k_iter_G<TV, TG, true>), dim3(L.nG), dim3(kBlock), 0, s, L.dir, L.mapG, mode);
     else
-      hipLaunchKernelGGL((k_iter_G<TV, TG, false>), dim3(G.grid), dim3(kBlock), 0, s, mat<TG>(G), (const TV *)v.t,
-                         (const TV *)v.r0, (const TV *)v.r1, (TV *)v.s, st, p.rt, P_gt, mode);
+      hipLaunchKernelGGL((k_iter_G<TV, TG, false>), dim3(L.nG), dim3(kBlock), 0, s, L.dir, L.mapG, mode);
   }));
   return hipGetLastError();
 }
 
-hipError_t launch_resid(const Types &ty, const DevCSR &A, const Vecs &v, State *st, const Partials &p, int slot_sel,
-                        bool with_d, bool reduce, bool respect_done, hipStream_t s) {
-  double *ptr = reduce ? p.tr : nullptr;
-  if (ty.vec == F64 && A.dtype == F64) {
-    hipLaunchKernelGGL((k_resid<double, double>), dim3(A.grid), dim3(kBlock), 0, s, mat<double>(A),
-                       (const double *)v.b, (const double *)v.x, (const double *)v.d0, (const double *)v.d1,
-                       (double *)v.r0, (double *)v.r1, st, p.g, A.grid, ptr, slot_sel, (int)with_d,
-                       (int)respect_done);
-  } else if (ty.vec == F32 && A.dtype == F32) {
-    hipLaunchKernelGGL((k_resid<float, float>), dim3(A.grid), dim3(kBlock), 0, s, mat<float>(A),
-                       (const float *)v.b, (const float *)v.x, (const float *)v.d0, (const float *)v.d1,
-                       (float *)v.r0, (float *)v.r1, st, p.g, A.grid, ptr, slot_sel, (int)with_d,
-                       (int)respect_done);
+hipError_t launch_resid(const Types &ty, const LaunchSet &L, int slot_sel, bool with_d, bool reduce,
+                        bool respect_done, hipStream_t s) {
+  if (L.nA == 0) return hipSuccess;
+  if (ty.vec == F64 && ty.a == F64) {
+    hipLaunchKernelGGL((k_resid<double, double>), dim3(L.nA), dim3(kBlock), 0, s, L.dir, L.mapA, slot_sel,
+                       (int)with_d, (int)reduce, (int)respect_done);
+  } else if (ty.vec == F32 && ty.a == F32) {
+    hipLaunchKernelGGL((k_resid<float, float>), dim3(L.nA), dim3(kBlock), 0, s, L.dir, L.mapA, slot_sel,
+                       (int)with_d, (int)reduce, (int)respect_done);
   } else {
     return hipErrorInvalidValue;
   }
-  if (reduce) hipLaunchKernelGGL(k_reduce_state, dim3(1), dim3(kBlock), 0, s, (const double *)p.tr, A.grid, st, 1);
+  if (reduce) hipLaunchKernelGGL(k_reduce_state, dim3(L.nset), dim3(kBlock), 0, s, L.dir, L.set, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_true(State *st, const Partials &p, int P, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_state, dim3(1), dim3(kBlock), 0, s, (const double *)p.tr, P, st, 1);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize(const Types &ty, int32_t n, const Vecs &v, State *st, hipStream_t s) {
+hipError_t launch_finalize(const Types &ty, const LaunchSet &L, hipStream_t s) {
+  if (L.nA == 0) return hipSuccess;
   PCG_DISPATCH_V(ty.vec, TV, {
-    hipLaunchKernelGGL((k_finalize<TV>), dim3(ew_grid(n)), dim3(kBlock), 0, s, n, (TV *)v.x, (const TV *)v.d0,
-                       (const TV *)v.d1, st);
+    hipLaunchKernelGGL((k_finalize<TV>), dim3(L.nA), dim3(kBlock), 0, s, L.dir, L.mapA);
   });
-  hipLaunchKernelGGL(k_state_clear_alpha, dim3(1), dim3(1), 0, s, st);
+  hipLaunchKernelGGL(k_state_clear_alpha, dim3((L.nset + 255) / 256), dim3(256), 0, s, L.dir, L.set, L.nset);
   return hipGetLastError();
 }
 
-hipError_t launch_norm_b(const Types &ty, int32_t n, const Vecs &v, State *st, const Partials &p, hipStream_t s) {
-  // the grid must stay within the partial buffers (sized for at least 1024)
-  int g = ew_grid(n);
-  if (g > 1024) g = 1024;
-  g = (g + 7) & ~7;
+hipError_t launch_norm_b(const Types &ty, const LaunchSet &L, hipStream_t s) {
+  if (L.nB == 0) return hipSuccess;
   PCG_DISPATCH_V(ty.vec, TV, {
-    hipLaunchKernelGGL((k_norm_b<TV>), dim3(g), dim3(kBlock), 0, s, n, (const TV *)v.b, p.b);
+    hipLaunchKernelGGL((k_norm_b<TV>), dim3(L.nB), dim3(kBlock), 0, s, L.dir, L.mapB);
   });
-  hipLaunchKernelGGL(k_reduce_state, dim3(1), dim3(kBlock), 0, s, (const double *)p.b, g, st, 0);
+  hipLaunchKernelGGL(k_reduce_state, dim3(L.nset), dim3(kBlock), 0, s, L.dir, L.set, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_state_restart(State *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(1), 0, s, st);
+hipError_t launch_zero_dirs(const Types &ty, const LaunchSet &L, bool zero_x, hipStream_t s) {
+  if (L.nA == 0) return hipSuccess;
+  PCG_DISPATCH_V(ty.vec, TV, {
+    hipLaunchKernelGGL((k_zero_dirs<TV>), dim3(L.nA), dim3(kBlock), 0, s, L.dir, L.mapA, (int)zero_x);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_spmv(const Types &ty, const DevCSR &M, int mdtype, const void *x, void *y, hipStream_t s) {
-  PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(mdtype, TM, {
-    hipLaunchKernelGGL((k_spmv<TV, TM>), dim3(M.grid), dim3(kBlock), 0, s, mat<TM>(M), (const TV *)x, (TV *)y);
+hipError_t launch_outer(int vec_dtype, const LaunchSet &L64, int what, hipStream_t s) {
+  if (L64.nA == 0) return hipSuccess;
+  PCG_DISPATCH_V(vec_dtype, TV, {
+    hipLaunchKernelGGL((k_outer<TV>), dim3(L64.nA), dim3(kBlock), 0, s, L64.dir, L64.mapA, what);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_state_restart(const LaunchSet &L, hipStream_t s) {
+  if (L.nset == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_state_restart, dim3((L.nset + 255) / 256), dim3(256), 0, s, L.dir, L.set, L.nset);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv(const Types &ty, const DevCSR &M, const void *x, void *y, hipStream_t s) {
+  PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(M.dtype, TM, {
+    hipLaunchKernelGGL((k_spmv<TV, TM>), dim3(M.grid), dim3(kBlock), 0, s, M, (const TV *)x, (TV *)y);
   }));
   return hipGetLastError();
 }

@@ -1,311 +1,447 @@
-// Host side of the C ABI in include/pcg.h: context, validation, device
-// storage, preconditioner construction, and the solve driver that replays
-// captured HIP graphs of whole CG iterations with device-resident scalars.
+// Host side of the C ABI in include/pcg.h: contexts, per-system device
+// storage, launch sets, the single-system driver (captured HIP graphs of whole
+// iterations, device-resident scalars), FP64 iterative refinement, and the
+// batching / serving scheduler (device memory pool, host preparation worker,
+// iteration-level continuous batching).
 #include "pcg.h"
 
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
+#include <climits>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
+#include "host.h"
 #include "kernels.h"
 
 using pcgk::DevCSR;
+using pcgk::LaunchSet;
 using pcgk::State;
+using pcgk::SysDev;
 using pcgk::Types;
-using pcgk::Vecs;
 
 namespace {
 
-// ------------------------------------------------------------ host helpers
+constexpr size_t kAlign = 256;
+constexpr int kDirCap = 4096;  // systems per context (directory and state slots)
+constexpr int kSlotMain = 0, kSlot64 = 1, kFirstBatchSlot = 2;
 
-int validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, int require_diag, std::string *why) {
-  auto fail = [&](const char *m, int64_t i) {
-    if (why) {
-      char buf[160];
-      snprintf(buf, sizeof buf, "%s (at %lld)", m, (long long)i);
-      *why = buf;
-    }
-    return PCG_EINVAL;
-  };
-  if (n < 0 || nnz < 0 || nnz > INT32_MAX) return fail("bad n or nnz", nnz);
-  if (n > 0 && (!rp || (nnz > 0 && !ci))) return fail("null CSR array", 0);
-  if (n == 0) return nnz == 0 ? PCG_OK : fail("nnz > 0 with n = 0", nnz);
-  if (rp[0] != 0) return fail("rowptr[0] != 0", 0);
-  for (int32_t i = 0; i < n; ++i) {
-    if (rp[i + 1] < rp[i]) return fail("rowptr decreases", i);
-    bool diag = false;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-      if (k >= nnz) return fail("rowptr exceeds nnz", i);
-      if (ci[k] < 0 || ci[k] >= n) return fail("column out of range", k);
-      if (k > rp[i] && ci[k] <= ci[k - 1]) return fail("columns not strictly ascending", k);
-      if (ci[k] == i) diag = true;
-    }
-    if (require_diag && !diag) return fail("missing diagonal entry", i);
-  }
-  if (rp[n] != nnz) return fail("rowptr[n] != nnz", n);
-  return PCG_OK;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-void transpose_csr(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
-                   const std::vector<double> &v, std::vector<int32_t> &trp, std::vector<int32_t> &tci,
-                   std::vector<double> &tv) {
-  const int64_t nnz = rp[n];
-  trp.assign(n + 1, 0);
-  tci.resize(nnz);
-  tv.resize(nnz);
-  for (int64_t k = 0; k < nnz; ++k) trp[ci[k] + 1]++;
-  for (int32_t j = 0; j < n; ++j) trp[j + 1] += trp[j];
-  std::vector<int32_t> pos(trp.begin(), trp.end() - 1);
-  for (int32_t i = 0; i < n; ++i)
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-      const int32_t p = pos[ci[k]]++;
-      tci[p] = i;
-      tv[p] = v[k];
+// ---------------------------------------------------------------- device pool
+
+// First-fit sub-allocator over one device allocation (the admission budget
+// of the batch/serving scheduler). Free blocks coalesce with neighbours.
+class DevPool {
+ public:
+  ~DevPool() { reset(); }
+  int init(size_t cap) {
+    reset();
+    cap = align_up(cap);
+    if (hipMalloc(&base_, cap) != hipSuccess) {
+      (void)hipGetLastError();
+      base_ = nullptr;
+      return PCG_ENOMEM;
     }
-}
-
-// Round to nearest, ties to even, onto a binary format with `sig` significant
-// bits, minimum normal exponent emin and largest finite value vmax.
-double round_to_format(double v, int sig, int emin, double vmax) {
-  if (v == 0.0 || !std::isfinite(v)) return v;
-  int e;
-  std::frexp(std::fabs(v), &e);  // |v| in [2^(e-1), 2^e)
-  int q = e - sig;
-  if (e - 1 < emin) q = emin - (sig - 1);  // subnormal quantum
-  double r = std::ldexp(std::nearbyint(std::ldexp(std::fabs(v), -q)), q);
-  if (r > vmax) r = INFINITY;
-  return std::copysign(r, v);
-}
-
-uint16_t to_bf16_bits(double v) {
-  const float f = (float)round_to_format(v, 8, -126, 3.3895313892515355e38);
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  return (uint16_t)(u >> 16);
-}
-
-uint16_t to_f16_bits(double v) {
-  const double r = round_to_format(v, 11, -14, 65504.0);
-  if (std::isinf(r)) return r > 0 ? 0x7C00 : 0xFC00;
-  if (std::isnan(r)) return 0x7E00;
-  uint16_t sign = std::signbit(r) ? 0x8000 : 0;
-  double a = std::fabs(r);
-  if (a == 0.0) return sign;
-  int e;
-  double m = std::frexp(a, &e);  // a = m 2^e, m in [0.5, 1)
-  if (e - 1 >= -14) {
-    const uint16_t exp = (uint16_t)(e - 1 + 15);
-    const uint16_t frac = (uint16_t)std::lround((m * 2.0 - 1.0) * 1024.0);
-    return sign | (uint16_t)(exp << 10) | frac;
-  }
-  return sign | (uint16_t)std::lround(a * 16777216.0);  // subnormal: multiples of 2^-24
-}
-
-// ---------------------------------------------- preconditioner builders (host)
-
-int64_t g_nnz(int kind, int32_t n, const int32_t *rp, const int32_t *ci) {
-  if (kind == PCG_G_JACOBI || kind == PCG_G_IDENTITY) return n;
-  if (kind != PCG_G_FSAI && kind != PCG_G_FIXED) return -1;
-  int64_t c = 0;
-  for (int32_t i = 0; i < n; ++i)
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] <= i);
-  return c;
-}
-
-// FSAI rows [r0, r1) of the lower factor G_L on tril(A): with A[J,J] = L L^T
-// (J = lower pattern of row i, i last), the FSAI row is L^-T e_last, i.e. the
-// last column of L^-T, found by one back substitution L^T g = e_last.
-int fsai_rows(int32_t r0, int32_t r1, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *lrp,
-              int32_t *lci, double *lv, int32_t n) {
-  std::vector<int32_t> where(n, -1);
-  std::vector<int32_t> J;
-  std::vector<double> S, g;
-  for (int32_t i = r0; i < r1; ++i) {
-    J.clear();
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
-      if (ci[k] <= i) J.push_back(ci[k]);
-    const int m = (int)J.size();
-    if (m == 0 || J.back() != i) return PCG_EINVAL;
-    for (int a = 0; a < m; ++a) where[J[a]] = a;
-    S.assign((size_t)m * m, 0.0);
-    for (int a = 0; a < m; ++a) {
-      const int32_t row = J[a];
-      for (int32_t k = rp[row]; k < rp[row + 1]; ++k) {
-        const int32_t c = ci[k];
-        if (c > i) break;
-        const int b = where[c];
-        if (b >= 0) S[(size_t)a * m + b] = v[k];
-      }
-    }
-    for (int a = 0; a < m; ++a) where[J[a]] = -1;
-    // Cholesky (lower) in place
-    for (int c = 0; c < m; ++c) {
-      double dsum = S[(size_t)c * m + c];
-      for (int k = 0; k < c; ++k) dsum -= S[(size_t)c * m + k] * S[(size_t)c * m + k];
-      if (!(dsum > 0.0)) return PCG_EBREAKDOWN;
-      const double l = std::sqrt(dsum);
-      S[(size_t)c * m + c] = l;
-      for (int a = c + 1; a < m; ++a) {
-        double e = S[(size_t)a * m + c];
-        for (int k = 0; k < c; ++k) e -= S[(size_t)a * m + k] * S[(size_t)c * m + k];
-        S[(size_t)a * m + c] = e / l;
-      }
-    }
-    // back substitution L^T g = e_last
-    g.assign(m, 0.0);
-    for (int a = m - 1; a >= 0; --a) {
-      double e = (a == m - 1) ? 1.0 : 0.0;
-      for (int k = a + 1; k < m; ++k) e -= S[(size_t)k * m + a] * g[k];
-      g[a] = e / S[(size_t)a * m + a];
-    }
-    for (int a = 0; a < m; ++a) {
-      lci[lrp[i] + a] = J[a];
-      lv[lrp[i] + a] = g[a];
-    }
-  }
-  return PCG_OK;
-}
-
-// Builds G (CSR) for `kind`; for the lower kinds also returns G^T directly.
-int build_g(int kind, int32_t n, const int32_t *rp, const int32_t *ci, const double *v, std::vector<int32_t> &grp,
-            std::vector<int32_t> &gci, std::vector<double> &gv) {
-  if (kind == PCG_G_JACOBI || kind == PCG_G_IDENTITY) {
-    grp.resize(n + 1);
-    gci.resize(n);
-    gv.resize(n);
-    for (int32_t i = 0; i <= n; ++i) grp[i] = i;
-    for (int32_t i = 0; i < n; ++i) {
-      gci[i] = i;
-      if (kind == PCG_G_IDENTITY) {
-        gv[i] = 1.0;
-        continue;
-      }
-      double d = 0.0;
-      for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
-        if (ci[k] == i) d = v[k];
-      if (!(d > 0.0)) return PCG_EINVAL;
-      gv[i] = 1.0 / std::sqrt(d);
-    }
+    cap_ = cap;
+    free_[0] = cap;
     return PCG_OK;
   }
-  const int64_t m = g_nnz(kind, n, rp, ci);
-  if (m < 0) return PCG_EINVAL;
-  std::vector<int32_t> lrp(n + 1, 0), lci(m);
-  std::vector<double> lv(m);
-  for (int32_t i = 0; i < n; ++i) {
-    int32_t c = 0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] <= i);
-    lrp[i + 1] = lrp[i] + c;
+  void reset() {
+    if (base_) (void)hipFree(base_);
+    base_ = nullptr;
+    cap_ = used_bytes_ = 0;
+    free_.clear();
+    used_.clear();
   }
-  if (kind == PCG_G_FIXED) {
-    std::vector<double> dg(n, 0.0);
-    for (int32_t i = 0; i < n; ++i)
-      for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
-        if (ci[k] == i) dg[i] = v[k];
-    for (int32_t i = 0; i < n; ++i) {
-      if (!(dg[i] > 0.0)) return PCG_EINVAL;
-      int32_t p = lrp[i];
-      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int32_t j = ci[k];
-        if (j > i) break;
-        lci[p] = j;
-        lv[p] = (j == i) ? 1.0 / std::sqrt(dg[i]) : -0.25 * v[k] / std::sqrt(dg[i] * dg[j]);
-        ++p;
+  bool ready() const { return base_ != nullptr; }
+  void *alloc(size_t bytes) {
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, sz = it->second;
+      free_.erase(it);
+      if (sz > bytes) free_[off + bytes] = sz - bytes;
+      used_[off] = bytes;
+      used_bytes_ += bytes;
+      return (uint8_t *)base_ + off;
+    }
+    return nullptr;
+  }
+  void release(void *p) {
+    if (!p || !base_) return;
+    const size_t off = (size_t)((uint8_t *)p - (uint8_t *)base_);
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    size_t start = off, sz = u->second;
+    used_bytes_ -= sz;
+    used_.erase(u);
+    auto nx = free_.lower_bound(start);
+    if (nx != free_.end() && nx->first == start + sz) {
+      sz += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == start) {
+        start = pv->first;
+        sz += pv->second;
+        free_.erase(pv);
       }
     }
-    grp.swap(lrp);
-    gci.swap(lci);
-    gv.swap(lv);
-    return PCG_OK;  // this G is lower-triangular itself
+    free_[start] = sz;
   }
-  // FSAI: G_L rows in parallel, then G = G_L^T
-  unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-  if (n < 20000) nt = 1;
-  std::vector<int> rcs(nt, PCG_OK);
-  std::vector<std::thread> th;
-  for (unsigned w = 0; w < nt; ++w) {
-    const int32_t a = (int32_t)((int64_t)n * w / nt), b = (int32_t)((int64_t)n * (w + 1) / nt);
-    th.emplace_back([&, a, b, w] { rcs[w] = fsai_rows(a, b, rp, ci, v, lrp.data(), lci.data(), lv.data(), n); });
-  }
-  for (auto &t : th) t.join();
-  for (int rc : rcs)
-    if (rc != PCG_OK) return rc;
-  transpose_csr(n, lrp, lci, lv, grp, gci, gv);
-  return PCG_OK;
+  size_t capacity() const { return cap_; }
+  size_t in_use() const { return used_bytes_; }
+
+ private:
+  void *base_ = nullptr;
+  size_t cap_ = 0, used_bytes_ = 0;
+  std::map<size_t, size_t> free_, used_;
+};
+
+// ------------------------------------------------------- host staging of a system
+
+// Everything a system's A part needs on the device, prepared on the host.
+struct APart {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int adt = pcgk::F64, vdt = pcgk::F64;
+  bool refine = false, staging = false;
+  std::vector<int32_t> rp, ci, blk, blk64;
+  std::vector<uint8_t> val;       // A's values in the storage type
+  const double *val64 = nullptr;  // FP64 values for refinement (borrowed)
+  int32_t grid = 8, grid64 = 8, gB = 8;
+  size_t bytes = 0;
+};
+
+struct GPart {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int gdt = pcgk::F64, vdt = pcgk::F64;
+  std::vector<int32_t> rp, ci, blk, trp, tci, tblk;
+  std::vector<uint8_t> val, tval;
+  int32_t grid = 8, tgrid = 8;
+  double scale = 1.0;
+  size_t bytes = 0;
+};
+
+// Device storage of one system.
+struct Sys {
+  int32_t n = 0;
+  int64_t nnz_a = 0, nnz_g = 0;
+  double g_scale = 1.0;
+  SysDev dev{};    // directory entry
+  SysDev dev64{};  // FP64 view for refinement (single path)
+  void *blkA = nullptr, *blkG = nullptr;
+  bool pooled = false;
+  void *tmp_in = nullptr, *tmp_out = nullptr;
+  double *stage64 = nullptr;
+};
+
+int grid_for(int cus, int mult, int32_t nblk) {
+  if (mult <= 0) mult = 8;
+  int64_t g = std::min<int64_t>(nblk, (int64_t)cus * mult);
+  g = (g + 7) & ~int64_t(7);
+  return (int)std::max<int64_t>(g, 8);
 }
 
-// Row-block partition for the CSR-stream kernels: consecutive rows, at most
-// kBlock rows and `cap` nonzeros per block; a longer row is a block alone.
-// Returned as (row start, nonzero start) pairs, nblk + 1 of them.
-std::vector<int32_t> row_blocks(int32_t n, const int32_t *rp, int cap) {
-  std::vector<int32_t> blk;
-  blk.push_back(0);
-  blk.push_back(rp[0]);
-  int32_t start = 0;
-  while (start < n) {
-    int32_t end = start + 1;
-    if (rp[start + 1] - rp[start] <= cap) {
-      while (end < n && end - start < pcgk::kBlock && rp[end + 1] - rp[start] <= cap) ++end;
+int norm_grid(int32_t n) {
+  int64_t g = ((int64_t)n + pcgk::kBlock - 1) / pcgk::kBlock;
+  g = std::min<int64_t>(std::max<int64_t>(g, 1), 1024);
+  return (int)((g + 7) & ~int64_t(7));
+}
+
+void cast_values(const double *v, int64_t nnz, int dt, double scale, std::vector<uint8_t> &out) {
+  out.resize(pcgk::dtype_size(dt) * (size_t)std::max<int64_t>(nnz, 1));
+  for (int64_t k = 0; k < nnz; ++k) {
+    const double x = v[k] * scale;
+    switch (dt) {
+      case pcgk::F64: ((double *)out.data())[k] = x; break;
+      case pcgk::F32: ((float *)out.data())[k] = (float)x; break;
+      case pcgk::BF16: ((uint16_t *)out.data())[k] = pcgh::to_bf16_bits(x); break;
+      default: ((uint16_t *)out.data())[k] = pcgh::to_f16_bits(x); break;
     }
-    blk.push_back(end);
-    blk.push_back(rp[end]);
-    start = end;
   }
-  return blk;
 }
 
-double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt) {
-  const double sa = (double)pcgk::dtype_size(adt), sg = (double)pcgk::dtype_size(gdt),
-               sv = (double)pcgk::dtype_size(vdt);
-  return (double)a * (sa + 4) + 2.0 * (double)g * (sg + 4) + 3.0 * 4.0 * (n + 1.0) + 12.0 * n * sv;
+size_t csr_bytes(int32_t n, int64_t nnz, int dt, size_t nblk) {
+  return align_up(4 * (size_t)(n + 1)) + align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) +
+         align_up(pcgk::dtype_size(dt) * (size_t)std::max<int64_t>(nnz, 1)) + align_up(8 * (nblk + 1));
 }
+
+void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+            bool staging, APart &P) {
+  P.n = n;
+  P.nnz = rp[n];
+  P.adt = cfg.a_dtype;
+  P.vdt = cfg.vec_dtype;
+  P.refine = cfg.refine != 0;
+  P.staging = staging;
+  P.rp.assign(rp, rp + n + 1);
+  P.ci.assign(ci, ci + P.nnz);
+  cast_values(v, P.nnz, P.adt, 1.0, P.val);
+  P.blk = pcgh::row_blocks(n, rp, pcgk::lds_cap(P.vdt));
+  P.grid = grid_for(cus, cfg.grid_mult, (int32_t)(P.blk.size() / 2 - 1));
+  P.gB = norm_grid(n);
+  if (P.refine) {
+    P.val64 = v;
+    P.blk64 = pcgh::row_blocks(n, rp, pcgk::lds_cap(pcgk::F64));
+    P.grid64 = grid_for(cus, cfg.grid_mult, (int32_t)(P.blk64.size() / 2 - 1));
+  }
+  const size_t vb = align_up(pcgk::dtype_size(P.vdt) * (size_t)n), db = align_up(8 * (size_t)n);
+  size_t b = csr_bytes(n, P.nnz, P.adt, P.blk.size() / 2 - 1) + 9 * vb;
+  if (P.refine) b += align_up(8 * (size_t)std::max<int64_t>(P.nnz, 1)) + align_up(4 * P.blk64.size()) + 3 * db;
+  if (P.staging) b += 2 * vb + db;
+  const int gtr = std::max(P.grid, P.refine ? P.grid64 : 0);
+  b += align_up(8 * (size_t)P.grid) + align_up(8 * (size_t)gtr) + align_up(8 * (size_t)P.gB);
+  P.bytes = b;
+}
+
+void prep_g(const pcg_config &cfg, int cus, int32_t n, std::vector<int32_t> &grp, std::vector<int32_t> &gci,
+            std::vector<double> &gv, GPart &P) {
+  P.n = n;
+  P.nnz = (int64_t)gci.size();
+  P.gdt = cfg.g_dtype;
+  P.vdt = cfg.vec_dtype;
+  std::vector<double> tv;
+  pcgh::transpose_csr(n, grp, gci, gv, P.trp, P.tci, tv);
+  // F16 has a narrow exponent range: store G times a power of two (PCG is
+  // invariant to the scale of M^-1 when eps is scaled alike).
+  P.scale = 1.0;
+  if (P.gdt == pcgk::F16) {
+    double mx = 0.0;
+    for (double x : gv) mx = std::max(mx, std::fabs(x));
+    if (mx > 0) {
+      int e;
+      std::frexp(mx, &e);
+      P.scale = std::ldexp(1.0, 14 - e);  // max |G| scaled into [2^13, 2^14)
+    }
+  }
+  cast_values(gv.data(), P.nnz, P.gdt, P.scale, P.val);
+  cast_values(tv.data(), P.nnz, P.gdt, P.scale, P.tval);
+  P.rp.swap(grp);
+  P.ci.swap(gci);
+  P.blk = pcgh::row_blocks(n, P.rp.data(), pcgk::lds_cap(P.vdt));
+  P.tblk = pcgh::row_blocks(n, P.trp.data(), pcgk::lds_cap(P.vdt));
+  P.grid = grid_for(cus, cfg.grid_mult, (int32_t)(P.blk.size() / 2 - 1));
+  P.tgrid = grid_for(cus, cfg.grid_mult, (int32_t)(P.tblk.size() / 2 - 1));
+  P.bytes = csr_bytes(n, P.nnz, P.gdt, P.blk.size() / 2 - 1) + csr_bytes(n, P.nnz, P.gdt, P.tblk.size() / 2 - 1) +
+            align_up(16 * (size_t)P.tgrid);
+}
+
+struct Carver {
+  uint8_t *base;
+  size_t off = 0;
+  void *take(size_t bytes) {
+    void *p = base + off;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return p;
+  }
+};
+
+hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (!bytes) return hipSuccess;
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+}
+
+// Carve the A part into `block` and upload it (asynchronously: P must live
+// until the stream has passed the copies).
+hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
+  Carver c{(uint8_t *)block};
+  const int32_t n = P.n;
+  const size_t vb = pcgk::dtype_size(P.vdt) * (size_t)n;
+  DevCSR &A = S.dev.A;
+  int32_t *rp = (int32_t *)c.take(4 * (size_t)(n + 1));
+  int32_t *ci = (int32_t *)c.take(4 * (size_t)std::max<int64_t>(P.nnz, 1));
+  void *val = c.take(P.val.size());
+  int32_t *blk = (int32_t *)c.take(4 * P.blk.size());
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chain(h2d(rp, P.rp.data(), 4 * (size_t)(n + 1), s));
+  chain(h2d(ci, P.ci.data(), 4 * (size_t)P.nnz, s));
+  chain(h2d(val, P.val.data(), pcgk::dtype_size(P.adt) * (size_t)P.nnz, s));
+  chain(h2d(blk, P.blk.data(), 4 * P.blk.size(), s));
+  A.rp = rp;
+  A.ci = ci;
+  A.val = val;
+  A.blk = blk;
+  A.nblk = (int32_t)(P.blk.size() / 2 - 1);
+  A.grid = P.grid;
+  A.nnz = P.nnz;
+  A.n = n;
+  A.dtype = P.adt;
+  void **vecs[] = {&S.dev.x, &S.dev.r0, &S.dev.r1, &S.dev.d0, &S.dev.d1, &S.dev.q, &S.dev.t, &S.dev.s, &S.dev.b};
+  for (void **v : vecs) *v = c.take(vb);
+  S.dev.n = n;
+  S.dev.gB = P.gB;
+  S.n = n;
+  S.nnz_a = P.nnz;
+  S.dev.pg = (double *)c.take(8 * (size_t)P.grid);
+  S.dev.ptr = (double *)c.take(8 * (size_t)std::max(P.grid, P.refine ? P.grid64 : 0));
+  S.dev.pb = (double *)c.take(8 * (size_t)P.gB);
+  if (P.refine) {
+    void *v64 = c.take(8 * (size_t)std::max<int64_t>(P.nnz, 1));
+    int32_t *b64k = (int32_t *)c.take(4 * P.blk64.size());
+    chain(h2d(v64, P.val64, 8 * (size_t)P.nnz, s));
+    chain(h2d(b64k, P.blk64.data(), 4 * P.blk64.size(), s));
+    SysDev &D = S.dev64;
+    D = SysDev{};
+    D.A = A;
+    D.A.val = v64;
+    D.A.blk = b64k;
+    D.A.nblk = (int32_t)(P.blk64.size() / 2 - 1);
+    D.A.grid = P.grid64;
+    D.A.dtype = pcgk::F64;
+    D.x = c.take(8 * (size_t)n);
+    D.b = c.take(8 * (size_t)n);
+    D.r0 = D.r1 = D.d0 = D.d1 = c.take(8 * (size_t)n);
+    D.ptr = S.dev.ptr;
+    D.pb = S.dev.pb;
+    D.pg = S.dev.pg;
+    D.n = n;
+    D.gB = P.gB;
+  }
+  if (P.staging) {
+    S.tmp_in = c.take(vb);
+    S.tmp_out = c.take(vb);
+    S.stage64 = (double *)c.take(8 * (size_t)n);
+  }
+  return e;
+}
+
+hipError_t place_g(const GPart &P, void *block, Sys &S, hipStream_t s) {
+  Carver c{(uint8_t *)block};
+  const int32_t n = P.n;
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  auto put = [&](DevCSR &M, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                 const std::vector<uint8_t> &val, const std::vector<int32_t> &blk, int grid) {
+    int32_t *drp = (int32_t *)c.take(4 * (size_t)(n + 1));
+    int32_t *dci = (int32_t *)c.take(4 * (size_t)std::max<int64_t>(P.nnz, 1));
+    void *dval = c.take(val.size());
+    int32_t *dblk = (int32_t *)c.take(4 * blk.size());
+    chain(h2d(drp, rp.data(), 4 * (size_t)(n + 1), s));
+    chain(h2d(dci, ci.data(), 4 * (size_t)P.nnz, s));
+    chain(h2d(dval, val.data(), pcgk::dtype_size(P.gdt) * (size_t)P.nnz, s));
+    chain(h2d(dblk, blk.data(), 4 * blk.size(), s));
+    M.rp = drp;
+    M.ci = dci;
+    M.val = dval;
+    M.blk = dblk;
+    M.nblk = (int32_t)(blk.size() / 2 - 1);
+    M.grid = grid;
+    M.nnz = P.nnz;
+    M.n = n;
+    M.dtype = P.gdt;
+  };
+  put(S.dev.G, P.rp, P.ci, P.val, P.blk, P.grid);
+  put(S.dev.GT, P.trp, P.tci, P.tval, P.tblk, P.tgrid);
+  S.dev.prt = (double *)c.take(16 * (size_t)P.tgrid);
+  S.nnz_g = P.nnz;
+  S.g_scale = P.scale;
+  return e;
+}
+
+// ------------------------------------------------------------ launch sets
+
+struct HostSet {
+  std::vector<int> slots;
+  void *dev = nullptr;  // maps + set
+  LaunchSet L{};
+};
+
+// ----------------------------------------------------------------- requests
+
+enum ReqState { RQ_PREP, RQ_READY, RQ_ACTIVE, RQ_DONE };
+
+struct Req {
+  uint64_t ticket = 0;
+  int32_t n = 0;
+  std::vector<int32_t> a_rp, a_ci, g_rp, g_ci;
+  std::vector<double> a_val, g_val, b, x0;
+  int g_kind = PCG_G_FSAI;
+  bool g_given = false;
+  double tol = 1e-8;
+  int maxit = 1000;
+  double *x_out = nullptr;
+  APart ap;
+  GPart gp;
+  size_t bytes = 0;
+  int prep_rc = PCG_OK;
+  ReqState st = RQ_PREP;
+  Sys sys;
+  int slot = -1;
+  int slot64 = -1;  // FP64 view under refinement
+  int restarts = 0;
+  int outer = 0, inner_total = 0;
+  double prev_rn = INFINITY, relres64 = NAN, last_rec = NAN;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  pcg_result res{};
+};
 
 }  // namespace
 
 // ----------------------------------------------------------------- context
 
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-};
-
 struct pcg_ctx {
   pcg_config cfg{};
   hipStream_t stream = nullptr;
-  bool own_stream = false;
   int cus = 256;
   std::string err;
+  Types ty{};
 
-  // host copies used by pcg_build_precond / G^T construction
-  int32_t n = 0;
+  // directory of systems and their state slots (device), with a host mirror
+  SysDev *d_dir = nullptr;
+  State *d_states = nullptr;  // kDirCap * 2
+  State *h_states = nullptr;  // pinned mirror
+  State *h_init = nullptr;    // pinned upload staging (2 slots)
+  std::vector<SysDev> dir;    // host copy of the directory
+  std::vector<int> free_slots;
+
+  // single-system path
   std::vector<int32_t> a_rp, a_ci;
   std::vector<double> a_val;
   bool have_a = false, have_g = false;
-  int64_t g_nnz = 0;
-  double g_scale = 1.0;  // G is stored times this (power of two, half formats)
-
-  std::vector<DevBuf> bufs;  // everything allocated, freed at destroy
-  DevCSR A, A64, G, GT;      // A64 shares A's pattern (refinement residual)
-  Types ty{};
-  Vecs v{};                  // vectors in vec_dtype
-  double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
-  void *tmp_in = nullptr, *tmp_out = nullptr;  // matvec staging (vec dtype)
-  double *stage64 = nullptr;                   // FP64 staging of boundary vectors
-  State *st = nullptr, *st64 = nullptr;  // two slots each (see State)
-  pcgk::Partials parts{};
-  double *partials = nullptr;  // backing store of parts: 5 * partial_cap doubles
-  int64_t partial_cap = 0;
-  State *hst = nullptr;  // pinned: [0..1] status readback, [2] upload
-  hipEvent_t ev[2] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
+  Sys single;
+  HostSet set_main, set_64;
   std::map<int, hipGraphExec_t> graphs;  // key: iters*2 + replace_first
-  int32_t vec_n = 0;                     // size the vectors were allocated for
+  hipEvent_t ev[2] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
+
+  // batching / serving
+  DevPool pool;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::shared_ptr<Req>> prep_q;   // awaiting host preparation
+  std::deque<std::shared_ptr<Req>> ready_q;  // prepared, awaiting admission
+  std::vector<std::shared_ptr<Req>> active;  // admitted
+  std::unordered_map<uint64_t, std::shared_ptr<Req>> by_ticket;
+  uint64_t next_ticket = 1;
+  std::vector<std::thread> workers;
+  bool stop = false;
+  HostSet set_active;
+  bool active_dirty = true;
 };
 
 namespace {
@@ -319,198 +455,108 @@ namespace {
     }                                                                                \
   } while (0)
 
-int dev_alloc(pcg_ctx *ctx, size_t bytes, void **out) {
-  *out = nullptr;
-  if (bytes == 0) bytes = 64;
-  hipError_t e = hipMalloc(out, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    ctx->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
-    *out = nullptr;
-    return PCG_ENOMEM;
-  }
-  ctx->bufs.push_back(DevBuf{*out, bytes});
-  return PCG_OK;
-}
-
-void dev_free(pcg_ctx *ctx, void *p) {
-  if (!p) return;
-  for (size_t i = 0; i < ctx->bufs.size(); ++i)
-    if (ctx->bufs[i].p == p) {
-      (void)hipFree(p);
-      ctx->bufs.erase(ctx->bufs.begin() + i);
-      return;
-    }
-}
-
-void free_csr(pcg_ctx *ctx, DevCSR &m, bool pattern_too) {
-  if (pattern_too) {
-    dev_free(ctx, m.rp);
-    dev_free(ctx, m.ci);
-    dev_free(ctx, m.blk);
-  }
-  dev_free(ctx, m.val);
-  m = DevCSR{};
-}
-
 void drop_graphs(pcg_ctx *ctx) {
   for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
   ctx->graphs.clear();
 }
 
-int grid_for(pcg_ctx *ctx, int32_t nblk) {
-  const int mult = ctx->cfg.grid_mult > 0 ? ctx->cfg.grid_mult : 8;
-  int64_t g = std::min<int64_t>(nblk, (int64_t)ctx->cus * mult);
-  g = (g + 7) & ~int64_t(7);
-  return (int)std::max<int64_t>(g, 8);
+void free_set(HostSet &hs) {
+  if (hs.dev) (void)hipFree(hs.dev);
+  hs = HostSet{};
 }
 
-// Upload a host CSR with values cast to dtype (times `scale`).
-int upload_csr(pcg_ctx *ctx, int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int dtype,
-               double scale, DevCSR &m) {
-  m.n = n;
-  m.nnz = rp[n];
-  m.dtype = dtype;
-  int rc;
-  if ((rc = dev_alloc(ctx, sizeof(int32_t) * (n + 1), (void **)&m.rp))) return rc;
-  if ((rc = dev_alloc(ctx, sizeof(int32_t) * m.nnz, (void **)&m.ci))) return rc;
-  if ((rc = dev_alloc(ctx, pcgk::dtype_size(dtype) * m.nnz, &m.val))) return rc;
-  HIPCHK(hipMemcpy(m.rp, rp, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(m.ci, ci, sizeof(int32_t) * m.nnz, hipMemcpyHostToDevice));
-  if (dtype == pcgk::F64 && scale == 1.0) {
-    HIPCHK(hipMemcpy(m.val, v, sizeof(double) * m.nnz, hipMemcpyHostToDevice));
+// Maps for the systems in `slots` (directory indices).
+int build_set(pcg_ctx *ctx, HostSet &hs, const std::vector<int> &slots) {
+  free_set(hs);
+  hs.slots = slots;
+  std::vector<int2> mA, mGT, mG, mB;
+  for (int sl : slots) {
+    const SysDev &D = ctx->dir[sl];
+    for (int l = 0; l < D.A.grid; ++l) mA.push_back(make_int2(sl, l));
+    for (int l = 0; l < D.GT.grid; ++l) mGT.push_back(make_int2(sl, l));
+    for (int l = 0; l < D.G.grid; ++l) mG.push_back(make_int2(sl, l));
+    for (int l = 0; l < D.gB; ++l) mB.push_back(make_int2(sl, l));
+  }
+  const size_t bytes = 8 * (mA.size() + mGT.size() + mG.size() + mB.size()) + 4 * slots.size() + 64;
+  HIPCHK(hipMalloc(&hs.dev, bytes));
+  int2 *p = (int2 *)hs.dev;
+  LaunchSet &L = hs.L;
+  L.dir = ctx->d_dir;
+  auto put = [&](const std::vector<int2> &m, const int2 *&dst, int32_t &cnt) -> hipError_t {
+    dst = p;
+    cnt = (int32_t)m.size();
+    hipError_t e = m.empty() ? hipSuccess : hipMemcpy(p, m.data(), 8 * m.size(), hipMemcpyHostToDevice);
+    p += m.size();
+    return e;
+  };
+  HIPCHK(put(mA, L.mapA, L.nA));
+  HIPCHK(put(mGT, L.mapGT, L.nGT));
+  HIPCHK(put(mG, L.mapG, L.nG));
+  HIPCHK(put(mB, L.mapB, L.nB));
+  L.set = (const int32_t *)p;
+  L.nset = (int32_t)slots.size();
+  if (!slots.empty()) HIPCHK(hipMemcpy(p, slots.data(), 4 * slots.size(), hipMemcpyHostToDevice));
+  return PCG_OK;
+}
+
+int upload_dir_entry(pcg_ctx *ctx, int slot) {
+  HIPCHK(hipMemcpy(ctx->d_dir + slot, &ctx->dir[slot], sizeof(SysDev), hipMemcpyHostToDevice));
+  return PCG_OK;
+}
+
+void free_sys(pcg_ctx *ctx, Sys &S) {
+  if (S.pooled) {
+    ctx->pool.release(S.blkA);
+    ctx->pool.release(S.blkG);
   } else {
-    std::vector<uint8_t> h(pcgk::dtype_size(dtype) * m.nnz);
-    for (int64_t k = 0; k < m.nnz; ++k) {
-      const double x = v[k] * scale;
-      switch (dtype) {
-        case pcgk::F64: ((double *)h.data())[k] = x; break;
-        case pcgk::F32: ((float *)h.data())[k] = (float)x; break;
-        case pcgk::BF16: ((uint16_t *)h.data())[k] = to_bf16_bits(x); break;
-        default: ((uint16_t *)h.data())[k] = to_f16_bits(x); break;
-      }
-    }
-    HIPCHK(hipMemcpy(m.val, h.data(), h.size(), hipMemcpyHostToDevice));
+    if (S.blkA) (void)hipFree(S.blkA);
+    if (S.blkG) (void)hipFree(S.blkG);
   }
-  const int vdt = ctx->cfg.vec_dtype;
-  std::vector<int32_t> blk = row_blocks(n, rp, pcgk::lds_cap(vdt));
-  m.nblk = (int32_t)blk.size() / 2 - 1;
-  if ((rc = dev_alloc(ctx, sizeof(int32_t) * blk.size(), (void **)&m.blk))) return rc;
-  HIPCHK(hipMemcpy(m.blk, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice));
-  m.grid = grid_for(ctx, m.nblk);
-  return PCG_OK;
+  S = Sys{};
 }
 
-int ensure_partials(pcg_ctx *ctx) {
-  int64_t need = 1024;
-  for (const DevCSR *m : {&ctx->A, &ctx->G, &ctx->GT, &ctx->A64})
-    if (m->grid > need) need = m->grid;
-  if (need <= ctx->partial_cap) return PCG_OK;
-  dev_free(ctx, ctx->partials);
-  ctx->partial_cap = 0;
-  int rc = dev_alloc(ctx, sizeof(double) * 5 * need, (void **)&ctx->partials);
-  if (rc) return rc;
-  ctx->partial_cap = need;
-  ctx->parts.g = ctx->partials;
-  ctx->parts.rt = ctx->partials + need;
-  ctx->parts.b = ctx->partials + 3 * need;
-  ctx->parts.tr = ctx->partials + 4 * need;
-  return PCG_OK;
+// Initial scalars of a solve. The inner solves of refinement run without
+// residual replacement (inner = true): their recurrence residual must be free
+// to fall below the true-residual floor of an FP32 iterate, because the FP64
+// outer residual is what corrects x.
+State init_state(const pcg_ctx *ctx, double tol, int maxit, double g_scale, bool inner = false) {
+  State st{};
+  st.tol = tol;
+  st.maxit = maxit;
+  st.eps = ctx->cfg.eps * g_scale * g_scale;
+  st.rr_period = inner ? 0 : ctx->cfg.rr_period;
+  return st;
 }
 
-int ensure_vectors(pcg_ctx *ctx, int32_t n) {
-  if (ctx->vec_n == n && ctx->v.x) return PCG_OK;
+// --------------------------------------------------------- single-system path
+
+int single_sets(pcg_ctx *ctx) {
   drop_graphs(ctx);
-  for (void *p : {ctx->v.x, ctx->v.r0, ctx->v.r1, ctx->v.d0, ctx->v.d1, ctx->v.q, ctx->v.t, ctx->v.s, ctx->v.b,
-                  ctx->tmp_in, ctx->tmp_out, (void *)ctx->x64, (void *)ctx->b64, (void *)ctx->r64,
-                  (void *)ctx->stage64})
-    dev_free(ctx, p);
-  ctx->v = Vecs{};
-  ctx->x64 = ctx->b64 = ctx->r64 = ctx->stage64 = nullptr;
-  const size_t vb = pcgk::dtype_size(ctx->cfg.vec_dtype) * (size_t)std::max(n, 1);
-  int rc;
-  void **slots[] = {&ctx->v.x, &ctx->v.r0, &ctx->v.r1, &ctx->v.d0, &ctx->v.d1, &ctx->v.q,
-                    &ctx->v.t, &ctx->v.s,  &ctx->v.b,  &ctx->tmp_in, &ctx->tmp_out};
-  for (void **p : slots)
-    if ((rc = dev_alloc(ctx, vb, p))) return rc;
-  const size_t db = sizeof(double) * (size_t)std::max(n, 1);
-  if ((rc = dev_alloc(ctx, db, (void **)&ctx->stage64))) return rc;
+  ctx->single.dev.st = ctx->d_states + 2 * kSlotMain;
+  ctx->dir[kSlotMain] = ctx->single.dev;
+  int rc = upload_dir_entry(ctx, kSlotMain);
+  if (rc) return rc;
   if (ctx->cfg.refine) {
-    if ((rc = dev_alloc(ctx, db, (void **)&ctx->x64))) return rc;
-    if ((rc = dev_alloc(ctx, db, (void **)&ctx->b64))) return rc;
-    if ((rc = dev_alloc(ctx, db, (void **)&ctx->r64))) return rc;
+    ctx->single.dev64.st = ctx->d_states + 2 * kSlot64;
+    ctx->dir[kSlot64] = ctx->single.dev64;
+    if ((rc = upload_dir_entry(ctx, kSlot64))) return rc;
+    if ((rc = build_set(ctx, ctx->set_64, {kSlot64}))) return rc;
   }
-  ctx->vec_n = n;
-  return PCG_OK;
+  return build_set(ctx, ctx->set_main, {kSlotMain});
 }
 
-// Fetch a CSR given by device pointers to the host (setup only).
-int fetch_csr(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
-              std::vector<int32_t> &hrp, std::vector<int32_t> &hci, std::vector<double> &hv) {
-  hrp.resize(n + 1);
-  hci.resize(nnz);
-  hv.resize(nnz);
-  HIPCHK(hipMemcpy(hrp.data(), rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
-  if (nnz) {
-    HIPCHK(hipMemcpy(hci.data(), ci, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(hv.data(), v, sizeof(double) * nnz, hipMemcpyDeviceToHost));
-  }
-  return PCG_OK;
-}
-
-int set_g_host(pcg_ctx *ctx, std::vector<int32_t> &grp, std::vector<int32_t> &gci, std::vector<double> &gv) {
-  const int32_t n = ctx->n;
-  std::vector<int32_t> trp, tci;
-  std::vector<double> tv;
-  transpose_csr(n, grp, gci, gv, trp, tci, tv);
-  drop_graphs(ctx);
-  free_csr(ctx, ctx->G, true);
-  free_csr(ctx, ctx->GT, true);
-  // F16 has a narrow exponent range: store G times a power of two (PCG is
-  // invariant to the scale of M^-1 when eps is scaled alike).
-  ctx->g_scale = 1.0;
-  if (ctx->cfg.g_dtype == pcgk::F16) {
-    double mx = 0.0;
-    for (double x : gv) mx = std::max(mx, std::fabs(x));
-    if (mx > 0) {
-      int e;
-      std::frexp(mx, &e);
-      ctx->g_scale = std::ldexp(1.0, 14 - e);  // max |G| scaled into [2^13, 2^14)
-    }
-  }
-  int rc = upload_csr(ctx, n, grp.data(), gci.data(), gv.data(), ctx->cfg.g_dtype, ctx->g_scale, ctx->G);
-  if (rc) return rc;
-  rc = upload_csr(ctx, n, trp.data(), tci.data(), tv.data(), ctx->cfg.g_dtype, ctx->g_scale, ctx->GT);
-  if (rc) return rc;
-  ctx->g_nnz = (int64_t)gci.size();
-  ctx->have_g = true;
-  return ensure_partials(ctx);
-}
-
-// --------------------------------------------------------------- solve core
-
-void enqueue_iteration(pcg_ctx *ctx, const Types &ty, bool replace, hipError_t &e) {
-  const double eps = ctx->cfg.eps * ctx->g_scale * ctx->g_scale;
+void enqueue_iteration(pcg_ctx *ctx, const Types &ty, const LaunchSet &L, bool replace, double eps, hipError_t &e) {
   auto chain = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  const pcgk::Partials &p = ctx->parts;
-  chain(pcgk::launch_iter_A(ty, ctx->A, ctx->v, ctx->st, p, ctx->stream));
-  if (replace) chain(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, p, 1, true, false, true, ctx->stream));
+  chain(pcgk::launch_iter_A(ty, L, ctx->stream));
+  if (replace) chain(pcgk::launch_resid(ty, L, 1, true, false, true, ctx->stream));
   const int mode = replace ? 1 : 0;
-  chain(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, p, ctx->A.grid, mode, ctx->stream));
-  chain(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, p, ctx->GT.grid, eps != 0.0, mode, ctx->stream));
+  chain(pcgk::launch_iter_GT(ty, L, mode, ctx->stream));
+  chain(pcgk::launch_iter_G(ty, L, eps != 0.0, mode, ctx->stream));
 }
 
-// Start (or restart) sequence: t = G^T r, s = G t, delta, beta = 0, tests.
-int enqueue_start(pcg_ctx *ctx, const Types &ty, double eps) {
-  const pcgk::Partials &p = ctx->parts;
-  HIPCHK(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, p, ctx->A.grid, 2, ctx->stream));
-  HIPCHK(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, p, ctx->GT.grid, eps != 0.0, 2, ctx->stream));
-  return PCG_OK;
-}
-
-int get_graph(pcg_ctx *ctx, const Types &ty, int iters, bool replace_first, hipGraphExec_t *out) {
+int get_graph(pcg_ctx *ctx, const Types &ty, int iters, bool replace_first, double eps, hipGraphExec_t *out) {
   const int key = iters * 2 + (replace_first ? 1 : 0);
   auto it = ctx->graphs.find(key);
   if (it != ctx->graphs.end()) {
@@ -519,7 +565,7 @@ int get_graph(pcg_ctx *ctx, const Types &ty, int iters, bool replace_first, hipG
   }
   HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int k = 0; k < iters; ++k) enqueue_iteration(ctx, ty, replace_first && k == 0, e);
+  for (int k = 0; k < iters; ++k) enqueue_iteration(ctx, ty, ctx->set_main.L, replace_first && k == 0, eps, e);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
   HIPCHK(e);
@@ -539,38 +585,50 @@ struct CoreOut {
   double rr = 0, true_rr = 0, bb = 0;
 };
 
-// Runs PCG on the vectors in ctx->v (b and x0 loaded) with ctx->st.
-int solve_core(pcg_ctx *ctx, const Types &ty, double tol, int maxit, CoreOut &out) {
-  const int32_t n = ctx->n;
+// Start sequence for the systems of L: ||b||, r = b - A x, t = G^T r,
+// s = G t, delta (states already uploaded; x loaded).
+int enqueue_start(pcg_ctx *ctx, const Types &ty, const LaunchSet &L, bool has_eps) {
   hipStream_t s = ctx->stream;
-  State init{};
-  init.maxit = maxit;
-  init.tol = tol;
-  init.eps = ctx->cfg.eps * ctx->g_scale * ctx->g_scale;
-  init.rr_period = ctx->cfg.rr_period;
-  ctx->hst[2] = init;
-  ctx->hst[3] = init;
-  HIPCHK(hipMemcpyAsync(ctx->st, &ctx->hst[2], 2 * sizeof(State), hipMemcpyHostToDevice, s));
-  HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.d0, n, 0.0, s));
-  HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.d1, n, 0.0, s));
-  HIPCHK(pcgk::launch_norm_b(ty, n, ctx->v, ctx->st, ctx->parts, s));
-  HIPCHK(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->parts, 0, false, false, true, s));
+  HIPCHK(pcgk::launch_zero_dirs(ty, L, false, s));
+  HIPCHK(pcgk::launch_norm_b(ty, L, s));
+  HIPCHK(pcgk::launch_resid(ty, L, 0, false, false, true, s));
+  HIPCHK(pcgk::launch_iter_GT(ty, L, 2, s));
+  HIPCHK(pcgk::launch_iter_G(ty, L, has_eps, 2, s));
+  return PCG_OK;
+}
+
+// PCG on the single system (b and x0 loaded). confirm: when the recurrence
+// residual meets tol, check b - A x and restart from it if that fails (the
+// inner solves of refinement skip this: the FP64 outer residual is the check,
+// and an FP32 iterate's true residual has a floor near u32 ||A|| ||x||).
+int solve_core(pcg_ctx *ctx, double tol, int maxit, CoreOut &out, bool confirm = true) {
+  const Types &ty = ctx->ty;
+  const LaunchSet &L = ctx->set_main.L;
+  hipStream_t s = ctx->stream;
+  State init = init_state(ctx, tol, maxit, ctx->single.g_scale, !confirm);
+  const bool has_eps = init.eps != 0.0;
+  ctx->h_init[0] = init;
+  ctx->h_init[1] = init;
+  HIPCHK(hipMemcpyAsync(ctx->single.dev.st, ctx->h_init, 2 * sizeof(State), hipMemcpyHostToDevice, s));
   {
-    int rc = enqueue_start(ctx, ty, init.eps);
+    int rc = enqueue_start(ctx, ty, L, has_eps);
     if (rc) return rc;
   }
-
-  const int rr = ctx->cfg.rr_period;
+  const int rr = init.rr_period;
   int K = ctx->cfg.graph_iters;
   if (K > 0 && rr > 0) {
     int a = K, b = rr;
-    while (b) { int t = a % b; a = b; b = t; }
+    while (b) {
+      int t = a % b;
+      a = b;
+      b = t;
+    }
     K = a;  // K divides rr: replacement can only fall on a chunk's first iteration
   }
-  int base = 0;  // iterations enqueued so far (exact while not done)
+  State *hst = ctx->h_states + 2 * kSlotMain;  // two pinned readback buffers
+  int base = 0;
   int restarts = 0;
   for (;;) {
-    // chunks in flight: launch up to two ahead, read the status of the oldest
     int inflight = 0, slot_next = 0, slot_wait = 0;
     bool done = false;
     while (!done) {
@@ -579,61 +637,57 @@ int solve_core(pcg_ctx *ctx, const Types &ty, double tol, int maxit, CoreOut &ou
         int len;
         if (K <= 0) {
           hipError_t e = hipSuccess;
-          enqueue_iteration(ctx, ty, rep, e);
+          enqueue_iteration(ctx, ty, L, rep, init.eps, e);
           HIPCHK(e);
           len = 1;
         } else {
           len = (base % K == 0) ? K : 1;
           hipGraphExec_t g;
-          int rc = get_graph(ctx, ty, len, rep, &g);
+          int rc = get_graph(ctx, ty, len, rep, init.eps, &g);
           if (rc) return rc;
           HIPCHK(hipGraphLaunch(g, s));
         }
         base += len;
-        HIPCHK(hipMemcpyAsync(&ctx->hst[slot_next], ctx->st, sizeof(State), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hst[slot_next], ctx->single.dev.st, sizeof(State), hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ctx->ev[slot_next], s));
         slot_next ^= 1;
         ++inflight;
       }
       HIPCHK(hipEventSynchronize(ctx->ev[slot_wait]));
-      const State &h = ctx->hst[slot_wait];
+      const bool d = hst[slot_wait].done != 0;
       slot_wait ^= 1;
       --inflight;
-      if (h.done) done = true;
+      if (d) done = true;
     }
     HIPCHK(hipStreamSynchronize(s));
     State h;
-    HIPCHK(hipMemcpy(&h, ctx->st, sizeof(State), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&h, ctx->single.dev.st, sizeof(State), hipMemcpyDeviceToHost));
     if (h.status == pcgk::ST_ZERO_B) {
-      HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.x, n, 0.0, s));
+      HIPCHK(pcgk::launch_fill(ty.vec, ctx->single.dev.x, ctx->single.n, 0.0, s));
       HIPCHK(hipStreamSynchronize(s));
       out = CoreOut{};
-      out.status = PCG_OK;
       return PCG_OK;
     }
-    HIPCHK(pcgk::launch_finalize(ty, n, ctx->v, ctx->st, s));
-    HIPCHK(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->parts, 0, false, true, false, s));
-    State f;
-    HIPCHK(hipMemcpyAsync(&ctx->hst[0], ctx->st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIPCHK(pcgk::launch_finalize(ty, L, s));
+    HIPCHK(pcgk::launch_resid(ty, L, 0, false, true, false, s));
+    HIPCHK(hipMemcpyAsync(&hst[0], ctx->single.dev.st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    f = ctx->hst[0];
+    const State f = hst[0];
     out.iters = f.iter;
     out.rr = f.rr;
     out.true_rr = f.true_rr;
     out.bb = f.bb;
     out.restarts = restarts;
     if (f.status == pcgk::ST_CONV_REC) {
-      if (std::sqrt(f.true_rr) <= f.tol_nb) {
+      if (!confirm || std::sqrt(f.true_rr) <= f.tol_nb) {
         out.status = PCG_OK;
         return PCG_OK;
       }
       // restart from the true residual (now in the current r slot)
       ++restarts;
-      HIPCHK(pcgk::launch_state_restart(ctx->st, s));
-      {
-        int rc = enqueue_start(ctx, ty, init.eps);
-        if (rc) return rc;
-      }
+      HIPCHK(pcgk::launch_state_restart(L, s));
+      HIPCHK(pcgk::launch_iter_GT(ty, L, 2, s));
+      HIPCHK(pcgk::launch_iter_G(ty, L, has_eps, 2, s));
       base = f.iter;
       continue;
     }
@@ -650,8 +704,8 @@ int load_vec(pcg_ctx *ctx, const double *src, int on_device, void *dst, int dtyp
   }
   const double *dsrc = src;
   if (!on_device) {  // stage host FP64 through the device FP64 buffer
-    HIPCHK(hipMemcpyAsync(ctx->stage64, src, sizeof(double) * n, kind, ctx->stream));
-    dsrc = ctx->stage64;
+    HIPCHK(hipMemcpyAsync(ctx->single.stage64, src, sizeof(double) * n, kind, ctx->stream));
+    dsrc = ctx->single.stage64;
   }
   HIPCHK(pcgk::launch_convert(pcgk::F64, dsrc, dtype, dst, n, 1.0, ctx->stream));
   return PCG_OK;
@@ -664,43 +718,39 @@ int store_vec(pcg_ctx *ctx, const void *src, int dtype, double *dst, int on_devi
   } else if (on_device) {
     HIPCHK(pcgk::launch_convert(dtype, src, pcgk::F64, dst, n, 1.0, ctx->stream));
   } else {
-    HIPCHK(pcgk::launch_convert(dtype, src, pcgk::F64, ctx->stage64, n, 1.0, ctx->stream));
-    HIPCHK(hipMemcpyAsync(dst, ctx->stage64, sizeof(double) * n, kind, ctx->stream));
+    HIPCHK(pcgk::launch_convert(dtype, src, pcgk::F64, ctx->single.stage64, n, 1.0, ctx->stream));
+    HIPCHK(hipMemcpyAsync(dst, ctx->single.stage64, sizeof(double) * n, kind, ctx->stream));
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return PCG_OK;
 }
 
+// FP64 iterative refinement: r64 = b - A64 x64 in FP64; inner PCG on
+// A c = r64 / ||r64|| to inner_tol; x64 += ||r64|| c.
 int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
-  // FP64 iterative refinement: r64 = b - A64 x64 in FP64; inner FP32 PCG on
-  // A c = r64 / ||r64|| to inner_tol; x64 += ||r64|| c.
-  const int32_t n = ctx->n;
+  Sys &S = ctx->single;
+  const int32_t n = S.n;
   hipStream_t s = ctx->stream;
-  Types t64{pcgk::F64, pcgk::F64, pcgk::F64};
-  Vecs v64{};
-  v64.x = ctx->x64;
-  v64.b = ctx->b64;
-  v64.r0 = ctx->r64;
-  v64.r1 = ctx->r64;
-  v64.d0 = ctx->r64;
-  v64.d1 = ctx->r64;
+  const Types t64{pcgk::F64, pcgk::F64, pcgk::F64};
+  const LaunchSet &L64 = ctx->set_64.L;
   State init{};
   init.tol = tol;
-  ctx->hst[2] = init;
-  ctx->hst[3] = init;
-  HIPCHK(hipMemcpyAsync(ctx->st64, &ctx->hst[2], 2 * sizeof(State), hipMemcpyHostToDevice, s));
-  HIPCHK(pcgk::launch_norm_b(t64, n, v64, ctx->st64, ctx->parts, s));
+  ctx->h_init[0] = init;
+  ctx->h_init[1] = init;
+  HIPCHK(hipMemcpyAsync(S.dev64.st, ctx->h_init, 2 * sizeof(State), hipMemcpyHostToDevice, s));
+  HIPCHK(pcgk::launch_norm_b(t64, L64, s));
   int total_iters = 0, outer = 0, restarts = 0, status = PCG_NOT_CONVERGED;
   double prev = INFINITY, relres = NAN, last_rec = NAN;
   const double inner_tol = ctx->cfg.inner_tol > 0 ? ctx->cfg.inner_tol : 1e-4;
   const int max_outer = ctx->cfg.max_outer > 0 ? ctx->cfg.max_outer : 30;
+  State *hst = ctx->h_states + 2 * kSlot64;
   for (;;) {
-    HIPCHK(pcgk::launch_resid(t64, ctx->A64, v64, ctx->st64, ctx->parts, 0, false, true, false, s));
-    HIPCHK(hipMemcpyAsync(&ctx->hst[0], ctx->st64, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIPCHK(pcgk::launch_resid(t64, L64, 0, false, true, false, s));
+    HIPCHK(hipMemcpyAsync(hst, S.dev64.st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const State h = ctx->hst[0];
+    const State h = *hst;
     if (h.bb == 0.0) {
-      HIPCHK(pcgk::launch_fill(pcgk::F64, ctx->x64, n, 0.0, s));
+      HIPCHK(pcgk::launch_fill(pcgk::F64, S.dev64.x, n, 0.0, s));
       status = PCG_OK;
       relres = 0.0;
       break;
@@ -721,10 +771,10 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
     }
     prev = rn;
     // inner right-hand side: r64 / ||r64|| in the vector precision
-    HIPCHK(pcgk::launch_convert(pcgk::F64, ctx->r64, ctx->ty.vec, ctx->v.b, n, 1.0 / rn, s));
-    HIPCHK(pcgk::launch_fill(ctx->ty.vec, ctx->v.x, n, 0.0, s));
+    HIPCHK(pcgk::launch_convert(pcgk::F64, S.dev64.r0, ctx->ty.vec, S.dev.b, n, 1.0 / rn, s));
+    HIPCHK(pcgk::launch_fill(ctx->ty.vec, S.dev.x, n, 0.0, s));
     CoreOut co;
-    int rc = solve_core(ctx, ctx->ty, inner_tol, maxit, co);
+    int rc = solve_core(ctx, inner_tol, maxit, co, false);
     if (rc) return rc;
     total_iters += co.iters;
     restarts += co.restarts;
@@ -733,7 +783,7 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
       status = PCG_EBREAKDOWN;
       break;
     }
-    HIPCHK(pcgk::launch_refine_update(n, ctx->x64, ctx->v.x, ctx->ty.vec, rn, s));
+    HIPCHK(pcgk::launch_refine_update(n, (double *)S.dev64.x, S.dev.x, ctx->ty.vec, rn, s));
     ++outer;
   }
   if (res) {
@@ -745,6 +795,483 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
     res->relres_rec = last_rec;
   }
   return status;
+}
+
+// ------------------------------------------------------- batching / serving
+
+void prep_request(const pcg_config &cfg, int cus, Req &R) {
+  R.ap = APart{};
+  prep_a(cfg, cus, R.n, R.a_rp.data(), R.a_ci.data(), R.a_val.data(), false, R.ap);
+  std::vector<int32_t> grp, gci;
+  std::vector<double> gv;
+  if (R.g_given) {
+    grp.swap(R.g_rp);
+    gci.swap(R.g_ci);
+    gv.swap(R.g_val);
+  } else {
+    int rc = pcgh::build_g(R.g_kind, R.n, R.a_rp.data(), R.a_ci.data(), R.a_val.data(), grp, gci, gv);
+    if (rc) {
+      R.prep_rc = rc;
+      return;
+    }
+  }
+  R.gp = GPart{};
+  prep_g(cfg, cus, R.n, grp, gci, gv, R.gp);
+  R.bytes = R.ap.bytes + R.gp.bytes;
+  R.prep_rc = PCG_OK;
+}
+
+void worker_main(pcg_ctx *ctx) {
+  for (;;) {
+    std::shared_ptr<Req> R;
+    {
+      std::unique_lock<std::mutex> lk(ctx->mu);
+      ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->prep_q.empty(); });
+      if (ctx->stop) return;
+      R = ctx->prep_q.front();
+      ctx->prep_q.pop_front();
+    }
+    prep_request(ctx->cfg, ctx->cus, *R);
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      R->st = RQ_READY;
+      ctx->ready_q.push_back(R);
+    }
+    ctx->cv.notify_all();
+  }
+}
+
+int ensure_pool(pcg_ctx *ctx) {
+  if (ctx->pool.ready()) return PCG_OK;
+  size_t cap = ctx->cfg.mem_budget_mb > 0 ? (size_t)ctx->cfg.mem_budget_mb << 20 : 0;
+  if (!cap) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    cap = fr / 2;
+  }
+  int rc = ctx->pool.init(cap);
+  if (rc) ctx->err = "device pool allocation failed";
+  return rc;
+}
+
+void start_workers(pcg_ctx *ctx) {
+  if (!ctx->workers.empty()) return;
+  unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency() / 2));
+  for (unsigned i = 0; i < nt; ++i) ctx->workers.emplace_back(worker_main, ctx);
+}
+
+void finish_request(pcg_ctx *ctx, Req &R, int status, const State &f, int restarts) {
+  R.t_done = now_ms();
+  R.res.status = status;
+  R.res.iters = f.iter;
+  R.res.outer_iters = 0;
+  R.res.restarts = restarts;
+  R.res.relres_true = f.bb > 0 ? std::sqrt(f.true_rr / f.bb) : 0.0;
+  R.res.relres_rec = f.bb > 0 ? std::sqrt(f.rr / f.bb) : 0.0;
+  R.res.t_solve_ms = R.t_done - R.t_admit;
+  R.res.bytes_per_iter = pcgh::bytes_per_iter(R.n, R.sys.nnz_a, R.sys.nnz_g, ctx->cfg.a_dtype, ctx->cfg.g_dtype,
+                                              ctx->cfg.vec_dtype);
+  R.res.t_latency_ms = R.t_done - R.t_submit;
+  R.res.t_queue_ms = R.t_admit - R.t_submit;
+  R.st = RQ_DONE;
+}
+
+// Admit ready requests (FIFO) while the pool has room; start their solves.
+int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
+  std::vector<std::shared_ptr<Req>> cand;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    while (!ctx->ready_q.empty()) {
+      auto R = ctx->ready_q.front();
+      if (R->prep_rc != PCG_OK) {  // failed preparation completes at once
+        ctx->ready_q.pop_front();
+        State z{};
+        R->t_admit = now_ms();
+        finish_request(ctx, *R, R->prep_rc, z, 0);
+        continue;
+      }
+      const size_t need_slots = ctx->cfg.refine ? 2 : 1;
+      if (ctx->free_slots.size() < need_slots) break;
+      void *bA = ctx->pool.alloc(R->ap.bytes);
+      void *bG = bA ? ctx->pool.alloc(R->gp.bytes) : nullptr;
+      if (!bA || !bG) {
+        ctx->pool.release(bA);
+        if (ctx->active.empty() && cand.empty() && ctx->pool.in_use() == 0) {
+          ctx->ready_q.pop_front();  // larger than the whole pool: refuse
+          State z{};
+          R->t_admit = now_ms();
+          finish_request(ctx, *R, PCG_ENOMEM, z, 0);
+          continue;
+        }
+        break;
+      }
+      ctx->ready_q.pop_front();
+      R->sys.blkA = bA;
+      R->sys.blkG = bG;
+      R->sys.pooled = true;
+      R->slot = ctx->free_slots.back();
+      ctx->free_slots.pop_back();
+      if (ctx->cfg.refine) {
+        R->slot64 = ctx->free_slots.back();
+        ctx->free_slots.pop_back();
+      }
+      cand.push_back(R);
+    }
+  }
+  if (cand.empty()) return PCG_OK;
+  hipStream_t s = ctx->stream;
+  std::vector<State> inits(2 * cand.size());
+  std::vector<int> slots;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    Req &R = *cand[i];
+    HIPCHK(place_a(R.ap, R.sys.blkA, R.sys, s));
+    HIPCHK(place_g(R.gp, R.sys.blkG, R.sys, s));
+    R.sys.dev.st = ctx->d_states + 2 * R.slot;
+    ctx->dir[R.slot] = R.sys.dev;
+    inits[2 * i] = inits[2 * i + 1] = init_state(ctx, R.tol, R.maxit, R.sys.g_scale);
+    if (ctx->cfg.refine) {
+      // FP64 view: b64, x64 from the caller; s and t point at the inner x and b
+      SysDev &V = R.sys.dev64;
+      V.st = ctx->d_states + 2 * R.slot64;
+      V.s = R.sys.dev.x;
+      V.t = R.sys.dev.b;
+      ctx->dir[R.slot64] = V;
+      HIPCHK(h2d(V.b, R.b.data(), 8 * (size_t)R.n, s));
+      if (R.x0.empty())
+        HIPCHK(pcgk::launch_fill(pcgk::F64, V.x, R.n, 0.0, s));
+      else
+        HIPCHK(h2d(V.x, R.x0.data(), 8 * (size_t)R.n, s));
+      State o{};
+      o.tol = R.tol;
+      inits[2 * i] = inits[2 * i + 1] = o;
+      slots.push_back(R.slot64);
+      HIPCHK(h2d(ctx->d_dir + R.slot, &ctx->dir[R.slot], sizeof(SysDev), s));
+      HIPCHK(h2d(ctx->d_dir + R.slot64, &ctx->dir[R.slot64], sizeof(SysDev), s));
+      HIPCHK(h2d(ctx->d_states + 2 * R.slot64, &inits[2 * i], 2 * sizeof(State), s));
+      continue;
+    }
+    slots.push_back(R.slot);
+    // b and x0 (zeros when not given). FP64 vectors load directly; FP32
+    // vectors stage FP64 through r0 and r1, which are adjacent and together
+    // hold n doubles, then convert.
+    if (ctx->ty.vec == pcgk::F64) {
+      HIPCHK(h2d(R.sys.dev.b, R.b.data(), 8 * (size_t)R.n, s));
+      if (R.x0.empty())
+        HIPCHK(pcgk::launch_fill(pcgk::F64, R.sys.dev.x, R.n, 0.0, s));
+      else
+        HIPCHK(h2d(R.sys.dev.x, R.x0.data(), 8 * (size_t)R.n, s));
+    } else {
+      double *stage = (double *)R.sys.dev.r0;
+      HIPCHK(h2d(stage, R.b.data(), 8 * (size_t)R.n, s));
+      HIPCHK(pcgk::launch_convert(pcgk::F64, stage, ctx->ty.vec, R.sys.dev.b, R.n, 1.0, s));
+      if (R.x0.empty()) {
+        HIPCHK(pcgk::launch_fill(ctx->ty.vec, R.sys.dev.x, R.n, 0.0, s));
+      } else {
+        HIPCHK(h2d(stage, R.x0.data(), 8 * (size_t)R.n, s));
+        HIPCHK(pcgk::launch_convert(pcgk::F64, stage, ctx->ty.vec, R.sys.dev.x, R.n, 1.0, s));
+      }
+    }
+    HIPCHK(h2d(ctx->d_dir + R.slot, &ctx->dir[R.slot], sizeof(SysDev), s));
+    HIPCHK(h2d(ctx->d_states + 2 * R.slot, &inits[2 * i], 2 * sizeof(State), s));
+  }
+  HostSet hs;
+  int rc = build_set(ctx, hs, slots);
+  if (rc) return rc;
+  if (ctx->cfg.refine) {  // first FP64 residual of every new system
+    const Types t64{pcgk::F64, pcgk::F64, pcgk::F64};
+    HIPCHK(pcgk::launch_norm_b(t64, hs.L, s));
+    HIPCHK(pcgk::launch_resid(t64, hs.L, 0, false, true, false, s));
+  } else {
+    rc = enqueue_start(ctx, ctx->ty, hs.L, ctx->cfg.eps != 0.0);
+  }
+  HIPCHK(hipStreamSynchronize(s));  // copies done: host staging may go
+  free_set(hs);
+  if (rc) return rc;
+  const double t = now_ms();
+  for (auto &R : cand) {
+    R->t_admit = t;
+    R->st = RQ_ACTIVE;
+    R->ap = APart{};
+    R->gp = GPart{};
+    std::vector<int32_t>().swap(R->a_rp);
+    std::vector<int32_t>().swap(R->a_ci);
+    std::vector<double>().swap(R->a_val);
+    std::vector<double>().swap(R->b);
+    std::vector<double>().swap(R->x0);
+    admitted.push_back(R);
+  }
+  return PCG_OK;
+}
+
+// Copy x of a finished system to the caller (host FP64) and free its storage.
+int retire(pcg_ctx *ctx, Req &R) {
+  if (R.x_out && R.slot64 >= 0) {
+    HIPCHK(hipMemcpy(R.x_out, R.sys.dev64.x, 8 * (size_t)R.n, hipMemcpyDeviceToHost));
+  } else if (R.x_out) {
+    if (ctx->ty.vec == pcgk::F64) {
+      HIPCHK(hipMemcpy(R.x_out, R.sys.dev.x, 8 * (size_t)R.n, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmp(R.n);
+      HIPCHK(hipMemcpy(tmp.data(), R.sys.dev.x, 4 * (size_t)R.n, hipMemcpyDeviceToHost));
+      for (int32_t i = 0; i < R.n; ++i) R.x_out[i] = (double)tmp[i];
+    }
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  free_sys(ctx, R.sys);
+  ctx->dir[R.slot] = SysDev{};
+  ctx->free_slots.push_back(R.slot);
+  R.slot = -1;
+  if (R.slot64 >= 0) {
+    ctx->dir[R.slot64] = SysDev{};
+    ctx->free_slots.push_back(R.slot64);
+    R.slot64 = -1;
+  }
+  return PCG_OK;
+}
+
+void finish_refined(pcg_ctx *ctx, Req &R, int status) {
+  R.t_done = now_ms();
+  R.res.status = status;
+  R.res.iters = R.inner_total;
+  R.res.outer_iters = R.outer;
+  R.res.restarts = R.restarts;
+  R.res.relres_true = R.relres64;
+  R.res.relres_rec = R.last_rec;
+  R.res.t_solve_ms = R.t_done - R.t_admit;
+  R.res.bytes_per_iter = pcgh::bytes_per_iter(R.n, R.sys.nnz_a, R.sys.nnz_g, ctx->cfg.a_dtype, ctx->cfg.g_dtype,
+                                              ctx->cfg.vec_dtype);
+  R.res.t_latency_ms = R.t_done - R.t_submit;
+  R.res.t_queue_ms = R.t_admit - R.t_submit;
+  R.st = RQ_DONE;
+}
+
+// Refinement decision after the FP64 residual of each system in `list` (its
+// FP64 view's state already read back into h_states): finish, or start the
+// next inner solve on r64 / ||r64||. Continuing systems go to `cont`.
+int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vector<std::shared_ptr<Req>> &cont) {
+  hipStream_t s = ctx->stream;
+  const int max_outer = ctx->cfg.max_outer > 0 ? ctx->cfg.max_outer : 30;
+  const double inner_tol = ctx->cfg.inner_tol > 0 ? ctx->cfg.inner_tol : 1e-4;
+  std::vector<int> slots, slots64;
+  std::vector<std::shared_ptr<Req>> go;
+  for (auto &R : list) {
+    const State h = ctx->h_states[2 * R->slot64];
+    int status = 1;  // continue
+    if (h.bb == 0.0) {
+      HIPCHK(pcgk::launch_fill(pcgk::F64, R->sys.dev64.x, R->n, 0.0, s));
+      HIPCHK(hipStreamSynchronize(s));
+      R->relres64 = 0.0;
+      status = PCG_OK;
+    } else {
+      const double rn = std::sqrt(h.true_rr), nb = std::sqrt(h.bb);
+      R->relres64 = rn / nb;
+      if (rn <= R->tol * nb)
+        status = PCG_OK;
+      else if (!std::isfinite(rn))
+        status = PCG_EBREAKDOWN;
+      else if (R->outer >= max_outer || rn > 0.9 * R->prev_rn)
+        status = PCG_NOT_CONVERGED;
+      else
+        R->prev_rn = rn;
+    }
+    if (status != 1) {
+      int rc = retire(ctx, *R);
+      if (rc) return rc;
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      finish_refined(ctx, *R, status);
+      continue;
+    }
+    go.push_back(R);
+    slots.push_back(R->slot);
+    slots64.push_back(R->slot64);
+  }
+  if (go.empty()) return PCG_OK;
+  HostSet h64, hin;
+  int rc = build_set(ctx, h64, slots64);
+  if (!rc) rc = build_set(ctx, hin, slots);
+  if (rc) return rc;
+  std::vector<State> inits(2 * go.size());
+  HIPCHK(pcgk::launch_outer(ctx->ty.vec, h64.L, 1, s));  // inner b = r64 / ||r64||
+  HIPCHK(pcgk::launch_zero_dirs(ctx->ty, hin.L, true, s));
+  for (size_t i = 0; i < go.size(); ++i) {
+    inits[2 * i] = inits[2 * i + 1] = init_state(ctx, inner_tol, go[i]->maxit, go[i]->sys.g_scale, true);
+    HIPCHK(h2d(ctx->d_states + 2 * go[i]->slot, &inits[2 * i], 2 * sizeof(State), s));
+  }
+  rc = enqueue_start(ctx, ctx->ty, hin.L, ctx->cfg.eps != 0.0);
+  HIPCHK(hipStreamSynchronize(s));
+  free_set(h64);
+  free_set(hin);
+  if (rc) return rc;
+  for (auto &R : go) cont.push_back(R);
+  return PCG_OK;
+}
+
+// One scheduler step: admit, `iters` iterations over the active set, retire.
+int progress(pcg_ctx *ctx, int iters) {
+  int rc;
+  if ((rc = ensure_pool(ctx))) return rc;
+  std::vector<std::shared_ptr<Req>> admitted;
+  if ((rc = admit(ctx, admitted))) return rc;
+  if (!admitted.empty() && ctx->cfg.refine) {
+    int mx = 0;
+    for (auto &R : admitted) mx = std::max(mx, R->slot64);
+    HIPCHK(hipMemcpy(ctx->h_states, ctx->d_states, 2 * sizeof(State) * (size_t)(mx + 1), hipMemcpyDeviceToHost));
+    std::vector<std::shared_ptr<Req>> cont;
+    if ((rc = outer_decide(ctx, admitted, cont))) return rc;
+    admitted.swap(cont);
+  }
+  if (!admitted.empty()) {
+    for (auto &R : admitted) ctx->active.push_back(R);
+    ctx->active_dirty = true;
+  }
+  if (ctx->active.empty()) return PCG_OK;
+  hipStream_t s = ctx->stream;
+  if (ctx->active_dirty) {
+    std::vector<int> slots;
+    for (auto &R : ctx->active) slots.push_back(R->slot);
+    if ((rc = build_set(ctx, ctx->set_active, slots))) return rc;
+    ctx->active_dirty = false;
+  }
+  const LaunchSet &L = ctx->set_active.L;
+  const bool has_eps = ctx->cfg.eps != 0.0;
+  for (int k = 0; k < iters; ++k) {
+    HIPCHK(pcgk::launch_iter_A(ctx->ty, L, s));
+    HIPCHK(pcgk::launch_resid(ctx->ty, L, 2, true, false, true, s));
+    HIPCHK(pcgk::launch_iter_GT(ctx->ty, L, 3, s));
+    HIPCHK(pcgk::launch_iter_G(ctx->ty, L, has_eps, 3, s));
+  }
+  int maxslot = 0;
+  for (auto &R : ctx->active) maxslot = std::max(maxslot, R->slot);
+  const size_t sb = 2 * sizeof(State) * (size_t)(maxslot + 1);
+  HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, sb, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int> done_slots;
+  for (auto &R : ctx->active)
+    if (ctx->h_states[2 * R->slot].done) done_slots.push_back(R->slot);
+  if (done_slots.empty()) return PCG_OK;
+  // finish the stopped systems: pending x update, true residual
+  HostSet hs;
+  if ((rc = build_set(ctx, hs, done_slots))) return rc;
+  HIPCHK(pcgk::launch_finalize(ctx->ty, hs.L, s));
+  HIPCHK(pcgk::launch_resid(ctx->ty, hs.L, 0, false, true, false, s));
+  HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, sb, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  free_set(hs);
+  std::vector<int> restart_slots;
+  std::vector<std::shared_ptr<Req>> keep, outer_list;
+  for (auto &R : ctx->active) {
+    const State f = ctx->h_states[2 * R->slot];
+    if (!f.done) {
+      keep.push_back(R);
+      continue;
+    }
+    int status;
+    if (f.status == pcgk::ST_CONV_REC && R->slot64 < 0 && !(std::sqrt(f.true_rr) <= f.tol_nb)) {
+      R->restarts++;
+      restart_slots.push_back(R->slot);
+      keep.push_back(R);
+      continue;
+    }
+    if (R->slot64 >= 0) {  // an inner solve ended: refinement step next
+      R->inner_total += f.iter;
+      R->last_rec = f.bb > 0 ? std::sqrt(f.rr / f.bb) : 0.0;
+      if (f.status == pcgk::ST_BREAK_GAMMA || f.status == pcgk::ST_BREAK_DELTA) {
+        if ((rc = retire(ctx, *R))) return rc;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        finish_refined(ctx, *R, PCG_EBREAKDOWN);
+        continue;
+      }
+      outer_list.push_back(R);
+      continue;
+    }
+    if (f.status == pcgk::ST_CONV_REC) {
+      status = PCG_OK;
+    } else if (f.status == pcgk::ST_ZERO_B) {
+      HIPCHK(pcgk::launch_fill(ctx->ty.vec, R->sys.dev.x, R->n, 0.0, s));
+      HIPCHK(hipStreamSynchronize(s));
+      status = PCG_OK;
+    } else if (f.status == pcgk::ST_MAXIT) {
+      status = PCG_NOT_CONVERGED;
+    } else {
+      status = PCG_EBREAKDOWN;
+    }
+    if ((rc = retire(ctx, *R))) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    finish_request(ctx, *R, status, f, R->restarts);
+  }
+  if (!restart_slots.empty()) {
+    if ((rc = build_set(ctx, hs, restart_slots))) return rc;
+    HIPCHK(pcgk::launch_state_restart(hs.L, s));
+    HIPCHK(pcgk::launch_iter_GT(ctx->ty, hs.L, 2, s));
+    HIPCHK(pcgk::launch_iter_G(ctx->ty, hs.L, has_eps, 2, s));
+    HIPCHK(hipStreamSynchronize(s));
+    free_set(hs);
+  }
+  if (!outer_list.empty()) {  // x64 += ||r|| c, then the FP64 residual
+    const Types t64{pcgk::F64, pcgk::F64, pcgk::F64};
+    std::vector<int> s64;
+    int mx = 0;
+    for (auto &R : outer_list) {
+      s64.push_back(R->slot64);
+      mx = std::max(mx, R->slot64);
+    }
+    if ((rc = build_set(ctx, hs, s64))) return rc;
+    HIPCHK(pcgk::launch_outer(ctx->ty.vec, hs.L, 0, s));
+    HIPCHK(pcgk::launch_resid(t64, hs.L, 0, false, true, false, s));
+    HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, 2 * sizeof(State) * (size_t)(mx + 1), hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+    free_set(hs);
+    for (auto &R : outer_list) R->outer++;
+    std::vector<std::shared_ptr<Req>> cont;
+    if ((rc = outer_decide(ctx, outer_list, cont))) return rc;
+    for (auto &R : cont) keep.push_back(R);
+  }
+  if (keep.size() != ctx->active.size()) {
+    ctx->active.swap(keep);
+    ctx->active_dirty = true;
+  }
+  return PCG_OK;
+}
+
+int copy_request(pcg_ctx *ctx, const pcg_system &S, std::shared_ptr<Req> &out) {
+  if (S.n <= 0 || !S.a_rowptr || !S.a_col || !S.a_val || !S.b || !(S.tol >= 0.0) || S.maxit < 0) {
+    ctx->err = "pcg_submit_batch: bad system (n, arrays, tol or maxit)";
+    return PCG_EINVAL;
+  }
+  if (S.a_rowptr[S.n] != S.nnz_a) {
+    ctx->err = "pcg_submit_batch: a_rowptr[n] != nnz_a";
+    return PCG_EINVAL;
+  }
+  int rc = pcgh::validate_csr(S.n, S.nnz_a, S.a_rowptr, S.a_col, 1, &ctx->err);
+  if (rc) return rc;
+  auto R = std::make_shared<Req>();
+  R->n = S.n;
+  R->a_rp.assign(S.a_rowptr, S.a_rowptr + S.n + 1);
+  R->a_ci.assign(S.a_col, S.a_col + S.nnz_a);
+  R->a_val.assign(S.a_val, S.a_val + S.nnz_a);
+  R->b.assign(S.b, S.b + S.n);
+  if (S.x) R->x0.assign(S.x, S.x + S.n);
+  R->x_out = S.x;
+  R->tol = S.tol;
+  R->maxit = S.maxit;
+  if (S.g_rowptr) {
+    if (!S.g_col || !S.g_val || S.g_rowptr[S.n] != S.nnz_g) return PCG_EINVAL;
+    rc = pcgh::validate_csr(S.n, S.nnz_g, S.g_rowptr, S.g_col, 0, &ctx->err);
+    if (rc) return rc;
+    R->g_given = true;
+    R->g_rp.assign(S.g_rowptr, S.g_rowptr + S.n + 1);
+    R->g_ci.assign(S.g_col, S.g_col + S.nnz_g);
+    R->g_val.assign(S.g_val, S.g_val + S.nnz_g);
+  } else {
+    if (pcgh::g_nnz(S.g_kind, S.n, S.a_rowptr, S.a_col) < 0) {
+      ctx->err = "pcg_submit_batch: unknown preconditioner kind";
+      return PCG_EINVAL;
+    }
+    R->g_kind = S.g_kind;
+  }
+  out = R;
+  return PCG_OK;
 }
 
 }  // namespace
@@ -777,7 +1304,8 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
   const int v = cfg->vec_dtype, a = cfg->a_dtype, g = cfg->g_dtype;
   const bool ok = (v == PCG_F64 && a == PCG_F64 && g == PCG_F64 && !cfg->refine) ||
                   (v == PCG_F32 && a == PCG_F32 && (g == PCG_F32 || g == PCG_BF16 || g == PCG_F16));
-  if (!ok || cfg->rr_period < 0 || cfg->graph_iters < 0 || !(cfg->eps >= 0.0)) return PCG_EINVAL;
+  if (!ok || cfg->rr_period < 0 || cfg->graph_iters < 0 || !(cfg->eps >= 0.0) || cfg->mem_budget_mb < 0)
+    return PCG_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= cfg->device || cfg->device < 0) {
     (void)hipGetLastError();
@@ -795,32 +1323,51 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
   if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->cus = prop.multiProcessorCount;
   if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) return fail(PCG_EDEVICE);
-  ctx->own_stream = true;
-  if (hipHostMalloc((void **)&ctx->hst, sizeof(State) * 4, hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void **)&ctx->h_states, sizeof(State) * 2 * kDirCap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&ctx->h_init, sizeof(State) * 2, hipHostMallocDefault) != hipSuccess)
     return fail(PCG_EDEVICE);
   for (auto &e : ctx->ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(PCG_EDEVICE);
   if (hipEventCreate(&ctx->t0) != hipSuccess || hipEventCreate(&ctx->t1) != hipSuccess) return fail(PCG_EDEVICE);
-  if (dev_alloc(ctx, 2 * sizeof(State), (void **)&ctx->st) || dev_alloc(ctx, 2 * sizeof(State), (void **)&ctx->st64))
+  if (hipMalloc((void **)&ctx->d_dir, sizeof(SysDev) * kDirCap) != hipSuccess ||
+      hipMalloc((void **)&ctx->d_states, sizeof(State) * 2 * kDirCap) != hipSuccess)
     return fail(PCG_ENOMEM);
-  if (hipMemset(ctx->st, 0, 2 * sizeof(State)) != hipSuccess || hipMemset(ctx->st64, 0, 2 * sizeof(State)) != hipSuccess)
+  if (hipMemset(ctx->d_dir, 0, sizeof(SysDev) * kDirCap) != hipSuccess ||
+      hipMemset(ctx->d_states, 0, sizeof(State) * 2 * kDirCap) != hipSuccess)
     return fail(PCG_EDEVICE);
+  ctx->dir.assign(kDirCap, SysDev{});
+  for (int sl = kDirCap - 1; sl >= kFirstBatchSlot; --sl) ctx->free_slots.push_back(sl);
   *out = ctx;
   return PCG_OK;
 }
 
 void pcg_destroy(pcg_ctx *ctx) {
   if (!ctx) return;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stop = true;
+  }
+  ctx->cv.notify_all();
+  for (auto &t : ctx->workers) t.join();
+  ctx->workers.clear();
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   drop_graphs(ctx);
-  for (auto &b : ctx->bufs) (void)hipFree(b.p);
-  ctx->bufs.clear();
+  for (auto &R : ctx->active) free_sys(ctx, R->sys);
+  ctx->active.clear();
+  free_set(ctx->set_main);
+  free_set(ctx->set_64);
+  free_set(ctx->set_active);
+  free_sys(ctx, ctx->single);
+  ctx->pool.reset();
   for (auto &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->t0) (void)hipEventDestroy(ctx->t0);
   if (ctx->t1) (void)hipEventDestroy(ctx->t1);
-  if (ctx->hst) (void)hipHostFree(ctx->hst);
-  if (ctx->stream && ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  if (ctx->h_states) (void)hipHostFree(ctx->h_states);
+  if (ctx->h_init) (void)hipHostFree(ctx->h_init);
+  if (ctx->d_dir) (void)hipFree(ctx->d_dir);
+  if (ctx->d_states) (void)hipFree(ctx->d_states);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -831,11 +1378,21 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
     ctx->err = "pcg_set_matrix: n must be positive and arrays non-null";
     return PCG_EINVAL;
   }
-  std::vector<int32_t> hrp, hci;
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  std::vector<int32_t> hrp(n + 1), hci;
   std::vector<double> hv;
   if (on_device) {
-    int rc = fetch_csr(ctx, n, nnz, rowptr, col, val, hrp, hci, hv);
-    if (rc) return rc;
+    HIPCHK(hipMemcpy(hrp.data(), rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    if (hrp[n] != nnz || nnz < 0) {
+      ctx->err = "pcg_set_matrix: rowptr[n] != nnz";
+      return PCG_EINVAL;
+    }
+    hci.resize(nnz);
+    hv.resize(nnz);
+    if (nnz) {
+      HIPCHK(hipMemcpy(hci.data(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(hv.data(), val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    }
   } else {
     hrp.assign(rowptr, rowptr + n + 1);
     if (hrp[n] != nnz) {
@@ -845,42 +1402,54 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
     hci.assign(col, col + nnz);
     hv.assign(val, val + nnz);
   }
-  int rc = validate_csr(n, nnz, hrp.data(), hci.data(), 1, &ctx->err);
+  int rc = pcgh::validate_csr(n, nnz, hrp.data(), hci.data(), 1, &ctx->err);
   if (rc) return rc;
   drop_graphs(ctx);
-  dev_free(ctx, ctx->A64.val);  // A64 shares A's rp/ci but owns its values and row blocks
-  dev_free(ctx, ctx->A64.blk);
-  ctx->A64 = DevCSR{};
-  free_csr(ctx, ctx->A, true);
-  if (ctx->have_g && ctx->n != n) {
-    free_csr(ctx, ctx->G, true);
-    free_csr(ctx, ctx->GT, true);
-    ctx->have_g = false;
-  }
-  ctx->n = n;
+  free_set(ctx->set_main);
+  free_set(ctx->set_64);
+  free_sys(ctx, ctx->single);
+  ctx->have_a = ctx->have_g = false;
   ctx->a_rp.swap(hrp);
   ctx->a_ci.swap(hci);
   ctx->a_val.swap(hv);
-  rc = upload_csr(ctx, n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), ctx->cfg.a_dtype, 1.0, ctx->A);
-  if (rc) return rc;
-  if (ctx->cfg.refine) {
-    // FP64 values on A's pattern for the refinement residual
-    ctx->A64 = ctx->A;
-    ctx->A64.dtype = pcgk::F64;
-    ctx->A64.val = nullptr;
-    if ((rc = dev_alloc(ctx, sizeof(double) * std::max<int64_t>(nnz, 1), &ctx->A64.val))) return rc;
-    HIPCHK(hipMemcpy(ctx->A64.val, ctx->a_val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
-    // the FP64 kernels stage FP64 products: their row blocks differ
-    std::vector<int32_t> blk = row_blocks(n, ctx->a_rp.data(), pcgk::lds_cap(pcgk::F64));
-    ctx->A64.nblk = (int32_t)blk.size() / 2 - 1;
-    ctx->A64.blk = nullptr;
-    if ((rc = dev_alloc(ctx, sizeof(int32_t) * blk.size(), (void **)&ctx->A64.blk))) return rc;
-    HIPCHK(hipMemcpy(ctx->A64.blk, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice));
-    ctx->A64.grid = grid_for(ctx, ctx->A64.nblk);
+  APart P;
+  prep_a(ctx->cfg, ctx->cus, n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), true, P);
+  void *blk = nullptr;
+  if (hipMalloc(&blk, P.bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "pcg_set_matrix: device allocation failed";
+    return PCG_ENOMEM;
   }
+  ctx->single.blkA = blk;
+  HIPCHK(place_a(P, blk, ctx->single, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->have_a = true;
-  if ((rc = ensure_partials(ctx))) return rc;
-  return ensure_vectors(ctx, n);
+  return PCG_OK;
+}
+
+static int set_g_from_host(pcg_ctx *ctx, std::vector<int32_t> &grp, std::vector<int32_t> &gci,
+                           std::vector<double> &gv) {
+  drop_graphs(ctx);
+  if (ctx->single.blkG) {
+    (void)hipFree(ctx->single.blkG);
+    ctx->single.blkG = nullptr;
+  }
+  ctx->have_g = false;
+  GPart P;
+  prep_g(ctx->cfg, ctx->cus, ctx->single.n, grp, gci, gv, P);
+  void *blk = nullptr;
+  if (hipMalloc(&blk, P.bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "pcg_set_precond: device allocation failed";
+    return PCG_ENOMEM;
+  }
+  ctx->single.blkG = blk;
+  HIPCHK(place_g(P, blk, ctx->single, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  int rc = single_sets(ctx);
+  if (rc) return rc;
+  ctx->have_g = true;
+  return PCG_OK;
 }
 
 int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
@@ -890,16 +1459,23 @@ int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr,
     ctx->err = "pcg_set_precond: set the matrix first";
     return PCG_ESTATE;
   }
-  if (n != ctx->n) {
+  if (n != ctx->single.n) {
     ctx->err = "pcg_set_precond: size differs from A";
     return PCG_ESTATE;
   }
   if (!rowptr || !col || !val) return PCG_EINVAL;
-  std::vector<int32_t> hrp, hci;
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  std::vector<int32_t> hrp(n + 1), hci;
   std::vector<double> hv;
   if (on_device) {
-    int rc = fetch_csr(ctx, n, nnz, rowptr, col, val, hrp, hci, hv);
-    if (rc) return rc;
+    HIPCHK(hipMemcpy(hrp.data(), rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    if (hrp[n] != nnz || nnz < 0) return PCG_EINVAL;
+    hci.resize(nnz);
+    hv.resize(nnz);
+    if (nnz) {
+      HIPCHK(hipMemcpy(hci.data(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(hv.data(), val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    }
   } else {
     hrp.assign(rowptr, rowptr + n + 1);
     if (hrp[n] != nnz) {
@@ -909,9 +1485,9 @@ int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr,
     hci.assign(col, col + nnz);
     hv.assign(val, val + nnz);
   }
-  int rc = validate_csr(n, nnz, hrp.data(), hci.data(), 0, &ctx->err);
+  int rc = pcgh::validate_csr(n, nnz, hrp.data(), hci.data(), 0, &ctx->err);
   if (rc) return rc;
-  return set_g_host(ctx, hrp, hci, hv);
+  return set_g_from_host(ctx, hrp, hci, hv);
 }
 
 int pcg_build_precond(pcg_ctx *ctx, int kind) {
@@ -922,12 +1498,12 @@ int pcg_build_precond(pcg_ctx *ctx, int kind) {
   }
   std::vector<int32_t> grp, gci;
   std::vector<double> gv;
-  int rc = build_g(kind, ctx->n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), grp, gci, gv);
+  int rc = pcgh::build_g(kind, ctx->single.n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), grp, gci, gv);
   if (rc) {
     ctx->err = "pcg_build_precond: construction failed (kind or matrix not SPD)";
     return rc;
   }
-  return set_g_host(ctx, grp, gci, gv);
+  return set_g_from_host(ctx, grp, gci, gv);
 }
 
 int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, int on_device, pcg_result *res) {
@@ -941,37 +1517,39 @@ int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, i
     ctx->err = "pcg_solve: matrix and preconditioner must be set";
     return PCG_ESTATE;
   }
-  const int32_t n = ctx->n;
+  Sys &S = ctx->single;
+  const int32_t n = S.n;
   int rc;
   HIPCHK(hipSetDevice(ctx->cfg.device));
   if (on_device) HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipEventRecord(ctx->t0, ctx->stream));
+  const double bpi =
+      pcgh::bytes_per_iter(n, S.nnz_a, S.nnz_g, ctx->cfg.a_dtype, ctx->cfg.g_dtype, ctx->cfg.vec_dtype);
   if (ctx->cfg.refine) {
-    HIPCHK(hipMemcpyAsync(ctx->b64, b, sizeof(double) * n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                          ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->x64, x, sizeof(double) * n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                          ctx->stream));
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(S.dev64.b, b, sizeof(double) * n, kind, ctx->stream));
+    HIPCHK(hipMemcpyAsync(S.dev64.x, x, sizeof(double) * n, kind, ctx->stream));
     pcg_result r{};
     rc = refine_solve(ctx, tol, maxit, &r);
     if (rc < PCG_EBREAKDOWN) return rc;  // device or memory error
     HIPCHK(hipEventRecord(ctx->t1, ctx->stream));
-    HIPCHK(hipMemcpyAsync(x, ctx->x64, sizeof(double) * n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(x, S.dev64.x, sizeof(double) * n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
     r.t_solve_ms = ms;
-    r.bytes_per_iter = bytes_per_iter(n, ctx->A.nnz, ctx->g_nnz, ctx->cfg.a_dtype, ctx->cfg.g_dtype, ctx->cfg.vec_dtype);
+    r.bytes_per_iter = bpi;
     if (res) *res = r;
     if (r.status == PCG_EBREAKDOWN) ctx->err = "breakdown: A or M not SPD, or non-finite values";
     return r.status;
   }
-  if ((rc = load_vec(ctx, b, on_device, ctx->v.b, ctx->ty.vec, n))) return rc;
-  if ((rc = load_vec(ctx, x, on_device, ctx->v.x, ctx->ty.vec, n))) return rc;
+  if ((rc = load_vec(ctx, b, on_device, S.dev.b, ctx->ty.vec, n))) return rc;
+  if ((rc = load_vec(ctx, x, on_device, S.dev.x, ctx->ty.vec, n))) return rc;
   CoreOut co;
-  if ((rc = solve_core(ctx, ctx->ty, tol, maxit, co))) return rc;
+  if ((rc = solve_core(ctx, tol, maxit, co))) return rc;
   HIPCHK(hipEventRecord(ctx->t1, ctx->stream));
-  if ((rc = store_vec(ctx, ctx->v.x, ctx->ty.vec, x, on_device, n))) return rc;
+  if ((rc = store_vec(ctx, S.dev.x, ctx->ty.vec, x, on_device, n))) return rc;
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
   if (res) {
@@ -982,8 +1560,7 @@ int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, i
     res->relres_true = co.bb > 0 ? std::sqrt(co.true_rr / co.bb) : 0.0;
     res->relres_rec = co.bb > 0 ? std::sqrt(co.rr / co.bb) : 0.0;
     res->t_solve_ms = ms;
-    res->bytes_per_iter =
-        bytes_per_iter(n, ctx->A.nnz, ctx->g_nnz, ctx->cfg.a_dtype, ctx->cfg.g_dtype, ctx->cfg.vec_dtype);
+    res->bytes_per_iter = bpi;
   }
   if (co.status == PCG_EBREAKDOWN) ctx->err = "breakdown: A or M not SPD, or non-finite values";
   return co.status;
@@ -996,31 +1573,32 @@ int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device) 
     ctx->err = "pcg_matvec: operator not set";
     return PCG_ESTATE;
   }
-  const int32_t n = ctx->n;
+  Sys &S = ctx->single;
+  const int32_t n = S.n;
   const int vdt = ctx->ty.vec;
   int rc;
   HIPCHK(hipSetDevice(ctx->cfg.device));
   if (on_device) HIPCHK(hipDeviceSynchronize());
-  if ((rc = load_vec(ctx, x, on_device, ctx->tmp_in, vdt, n))) return rc;
+  if ((rc = load_vec(ctx, x, on_device, S.tmp_in, vdt, n))) return rc;
   hipStream_t s = ctx->stream;
-  const double inv_scale2 = 1.0 / (ctx->g_scale * ctx->g_scale);
+  const double inv_scale2 = 1.0 / (S.g_scale * S.g_scale);
   switch (op) {
-    case PCG_OP_A: HIPCHK(pcgk::launch_spmv(ctx->ty, ctx->A, ctx->A.dtype, ctx->tmp_in, ctx->tmp_out, s)); break;
+    case PCG_OP_A: HIPCHK(pcgk::launch_spmv(ctx->ty, S.dev.A, S.tmp_in, S.tmp_out, s)); break;
     case PCG_OP_GT:
-      HIPCHK(pcgk::launch_spmv(ctx->ty, ctx->GT, ctx->GT.dtype, ctx->tmp_in, ctx->tmp_out, s));
-      if (ctx->g_scale != 1.0) HIPCHK(pcgk::launch_axpby(vdt, n, 1.0 / ctx->g_scale, ctx->tmp_out, 0.0, ctx->tmp_in, s));
+      HIPCHK(pcgk::launch_spmv(ctx->ty, S.dev.GT, S.tmp_in, S.tmp_out, s));
+      if (S.g_scale != 1.0) HIPCHK(pcgk::launch_axpby(vdt, n, 1.0 / S.g_scale, S.tmp_out, 0.0, S.tmp_in, s));
       break;
     case PCG_OP_G:
-      HIPCHK(pcgk::launch_spmv(ctx->ty, ctx->G, ctx->G.dtype, ctx->tmp_in, ctx->tmp_out, s));
-      if (ctx->g_scale != 1.0) HIPCHK(pcgk::launch_axpby(vdt, n, 1.0 / ctx->g_scale, ctx->tmp_out, 0.0, ctx->tmp_in, s));
+      HIPCHK(pcgk::launch_spmv(ctx->ty, S.dev.G, S.tmp_in, S.tmp_out, s));
+      if (S.g_scale != 1.0) HIPCHK(pcgk::launch_axpby(vdt, n, 1.0 / S.g_scale, S.tmp_out, 0.0, S.tmp_in, s));
       break;
     default:
-      HIPCHK(pcgk::launch_spmv(ctx->ty, ctx->GT, ctx->GT.dtype, ctx->tmp_in, ctx->v.t, s));
-      HIPCHK(pcgk::launch_spmv(ctx->ty, ctx->G, ctx->G.dtype, ctx->v.t, ctx->tmp_out, s));
-      HIPCHK(pcgk::launch_axpby(vdt, n, inv_scale2, ctx->tmp_out, ctx->cfg.eps, ctx->tmp_in, s));
+      HIPCHK(pcgk::launch_spmv(ctx->ty, S.dev.GT, S.tmp_in, S.dev.t, s));
+      HIPCHK(pcgk::launch_spmv(ctx->ty, S.dev.G, S.dev.t, S.tmp_out, s));
+      HIPCHK(pcgk::launch_axpby(vdt, n, inv_scale2, S.tmp_out, ctx->cfg.eps, S.tmp_in, s));
       break;
   }
-  return store_vec(ctx, ctx->tmp_out, vdt, y, on_device, n);
+  return store_vec(ctx, S.tmp_out, vdt, y, on_device, n);
 }
 
 int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
@@ -1030,30 +1608,27 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
     ctx->err = "pcg_time_kernels: matrix and preconditioner must be set";
     return PCG_ESTATE;
   }
-  const int32_t n = ctx->n;
+  Sys &S = ctx->single;
+  const int32_t n = S.n;
   const Types ty = ctx->ty;
+  const LaunchSet &L = ctx->set_main.L;
   hipStream_t s = ctx->stream;
   HIPCHK(hipSetDevice(ctx->cfg.device));
   // a fresh solve of the stored right-hand side from x0 = 0 that never stops
-  State init{};
-  init.maxit = INT32_MAX;
-  init.tol = -1.0;
-  init.eps = ctx->cfg.eps * ctx->g_scale * ctx->g_scale;
-  ctx->hst[2] = init;
-  ctx->hst[3] = init;
-  HIPCHK(hipMemcpyAsync(ctx->st, &ctx->hst[2], 2 * sizeof(State), hipMemcpyHostToDevice, s));
-  HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.x, n, 0.0, s));
-  HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.d0, n, 0.0, s));
-  HIPCHK(pcgk::launch_fill(ty.vec, ctx->v.d1, n, 0.0, s));
-  HIPCHK(pcgk::launch_norm_b(ty, n, ctx->v, ctx->st, ctx->parts, s));
-  HIPCHK(pcgk::launch_resid(ty, ctx->A, ctx->v, ctx->st, ctx->parts, 0, false, false, true, s));
+  State init = init_state(ctx, -1.0, INT32_MAX, S.g_scale);
+  init.rr_period = 0;
+  const bool has_eps = init.eps != 0.0;
+  ctx->h_init[0] = init;
+  ctx->h_init[1] = init;
+  HIPCHK(hipMemcpyAsync(S.dev.st, ctx->h_init, 2 * sizeof(State), hipMemcpyHostToDevice, s));
+  HIPCHK(pcgk::launch_fill(ty.vec, S.dev.x, n, 0.0, s));
   {
-    int rc0 = enqueue_start(ctx, ty, init.eps);
+    int rc0 = enqueue_start(ctx, ty, L, has_eps);
     if (rc0) return rc0;
   }
   HIPCHK(hipStreamSynchronize(s));
   State h;
-  HIPCHK(hipMemcpy(&h, ctx->st, sizeof(State), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&h, S.dev.st, sizeof(State), hipMemcpyDeviceToHost));
   if (h.done) {
     ctx->err = "pcg_time_kernels: solve a nonzero right-hand side first";
     return PCG_ESTATE;
@@ -1065,14 +1640,16 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
   double acc[4] = {0, 0, 0, 0};
   if (rc == PCG_OK) {
     hipError_t e = hipSuccess;
-    auto chain = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    auto chain = [&](hipError_t x) {
+      if (e == hipSuccess) e = x;
+    };
     for (int it = 0; it < iters; ++it) {
       chain(hipEventRecord(ev[4 * it], s));
-      chain(pcgk::launch_iter_A(ty, ctx->A, ctx->v, ctx->st, ctx->parts, s));
+      chain(pcgk::launch_iter_A(ty, L, s));
       chain(hipEventRecord(ev[4 * it + 1], s));
-      chain(pcgk::launch_iter_GT(ty, ctx->GT, ctx->v, ctx->st, ctx->parts, ctx->A.grid, 0, s));
+      chain(pcgk::launch_iter_GT(ty, L, 0, s));
       chain(hipEventRecord(ev[4 * it + 2], s));
-      chain(pcgk::launch_iter_G(ty, ctx->G, ctx->v, ctx->st, ctx->parts, ctx->GT.grid, init.eps != 0.0, 0, s));
+      chain(pcgk::launch_iter_G(ty, L, has_eps, 0, s));
       chain(hipEventRecord(ev[4 * it + 3], s));
     }
     chain(hipStreamSynchronize(s));
@@ -1093,7 +1670,7 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
   for (auto &e : ev)
     if (e) (void)hipEventDestroy(e);
   if (rc) return rc;
-  HIPCHK(hipMemcpy(&h, ctx->st, sizeof(State), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&h, S.dev.st, sizeof(State), hipMemcpyDeviceToHost));
   if (h.done) {
     ctx->err = "pcg_time_kernels: the iteration stopped (breakdown) while timing";
     return PCG_EBREAKDOWN;
@@ -1103,9 +1680,9 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
     const double sa = (double)pcgk::dtype_size(ctx->cfg.a_dtype), sg = (double)pcgk::dtype_size(ctx->cfg.g_dtype),
                  sv = (double)pcgk::dtype_size(ctx->cfg.vec_dtype);
     const double rp = 4.0 * (n + 1.0);
-    bytes[0] = (double)ctx->A.nnz * (sa + 4) + rp + 6.0 * n * sv;
-    bytes[1] = (double)ctx->GT.nnz * (sg + 4) + rp + 4.0 * n * sv;
-    bytes[2] = (double)ctx->G.nnz * (sg + 4) + rp + (init.eps != 0.0 ? 3.0 : 2.0) * n * sv;
+    bytes[0] = (double)S.nnz_a * (sa + 4) + rp + 6.0 * n * sv;
+    bytes[1] = (double)S.nnz_g * (sg + 4) + rp + 4.0 * n * sv;
+    bytes[2] = (double)S.nnz_g * (sg + 4) + rp + (has_eps ? 3.0 : 2.0) * n * sv;
     bytes[3] = bytes[0] + bytes[1] + bytes[2];
   }
   return PCG_OK;
@@ -1152,48 +1729,91 @@ int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double
   return rc;
 }
 
-int pcg_validate_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col, int require_diag) {
-  return validate_csr(n, nnz, rowptr, col, require_diag, nullptr);
-}
+// ------------------------------------------------------------ batching / serving
 
-int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col) {
-  if (n <= 0 || !rowptr || !col) return -1;
-  return g_nnz(kind, n, rowptr, col);
-}
-
-int pcg_build_g_host(int kind, int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
-                     int32_t *g_rowptr, int32_t *g_col, double *g_val) {
-  if (n <= 0 || !rowptr || !col || !val || !g_rowptr || !g_col || !g_val) return PCG_EINVAL;
-  int rc = validate_csr(n, rowptr[n], rowptr, col, 1, nullptr);
-  if (rc) return rc;
-  std::vector<int32_t> grp, gci;
-  std::vector<double> gv;
-  rc = build_g(kind, n, rowptr, col, val, grp, gci, gv);
-  if (rc) return rc;
-  std::memcpy(g_rowptr, grp.data(), sizeof(int32_t) * grp.size());
-  std::memcpy(g_col, gci.data(), sizeof(int32_t) * gci.size());
-  std::memcpy(g_val, gv.data(), sizeof(double) * gv.size());
+int pcg_submit_batch(pcg_ctx *ctx, int count, const pcg_system *sys, uint64_t *tickets) {
+  if (!ctx) return PCG_EINVAL;
+  if (count < 0 || (count > 0 && (!sys || !tickets))) return PCG_EINVAL;
+  std::vector<std::shared_ptr<Req>> reqs(count);
+  for (int i = 0; i < count; ++i) {
+    int rc = copy_request(ctx, sys[i], reqs[i]);
+    if (rc) return rc;  // nothing queued on error
+  }
+  const double t = now_ms();
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (int i = 0; i < count; ++i) {
+      reqs[i]->ticket = ctx->next_ticket++;
+      reqs[i]->t_submit = t;
+      tickets[i] = reqs[i]->ticket;
+      ctx->by_ticket[reqs[i]->ticket] = reqs[i];
+      ctx->prep_q.push_back(reqs[i]);
+    }
+    start_workers(ctx);
+  }
+  ctx->cv.notify_all();
   return PCG_OK;
 }
 
-double pcg_bytes_per_iter(int32_t n, int64_t nnz_a, int64_t nnz_g, int a_dtype, int g_dtype, int vec_dtype) {
-  return bytes_per_iter(n, nnz_a, nnz_g, a_dtype, g_dtype, vec_dtype);
+int pcg_progress(pcg_ctx *ctx, int iters, int *active, int *queued) {
+  if (!ctx) return PCG_EINVAL;
+  if (iters < 0) return PCG_EINVAL;
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  int rc = progress(ctx, iters);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (active) *active = (int)ctx->active.size();
+  if (queued) *queued = (int)(ctx->prep_q.size() + ctx->ready_q.size());
+  return rc;
+}
+
+int pcg_poll(pcg_ctx *ctx, uint64_t ticket, pcg_result *res) {
+  if (!ctx) return PCG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->by_ticket.find(ticket);
+  if (it == ctx->by_ticket.end()) return PCG_EINVAL;
+  if (it->second->st != RQ_DONE) return PCG_PENDING;
+  if (res) *res = it->second->res;
+  const int st = it->second->res.status;
+  ctx->by_ticket.erase(it);
+  return st;
+}
+
+int pcg_solve_batch(pcg_ctx *ctx, int count, const pcg_system *sys, pcg_result *results, int iters_per_step) {
+  if (!ctx || count < 0 || (count > 0 && (!sys || !results))) return PCG_EINVAL;
+  std::vector<uint64_t> t(count);
+  int rc = pcg_submit_batch(ctx, count, sys, t.data());
+  if (rc) return rc;
+  const int step = iters_per_step > 0 ? iters_per_step : 20;
+  for (;;) {
+    int act = 0, q = 0;
+    rc = pcg_progress(ctx, step, &act, &q);
+    if (rc) return rc;
+    bool all = true;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      for (uint64_t tk : t) {
+        auto it = ctx->by_ticket.find(tk);
+        if (it != ctx->by_ticket.end() && it->second->st != RQ_DONE) {
+          all = false;
+          break;
+        }
+      }
+    }
+    if (all) break;
+    if (act == 0) std::this_thread::sleep_for(std::chrono::microseconds(200));
+  }
+  for (int i = 0; i < count; ++i) (void)pcg_poll(ctx, t[i], &results[i]);
+  return PCG_OK;
+}
+
+int pcg_pool_info(pcg_ctx *ctx, size_t *capacity, size_t *in_use) {
+  if (!ctx) return PCG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (capacity) *capacity = ctx->pool.capacity();
+  if (in_use) *in_use = ctx->pool.in_use();
+  return PCG_OK;
 }
 
 const char *pcg_last_error(const pcg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
-
-const char *pcg_strerror(int status) {
-  switch (status) {
-    case PCG_OK: return "ok";
-    case PCG_PENDING: return "pending";
-    case PCG_NOT_CONVERGED: return "not converged (maxit reached)";
-    case PCG_EINVAL: return "invalid argument";
-    case PCG_ESTATE: return "invalid state";
-    case PCG_ENOMEM: return "out of device memory";
-    case PCG_EBREAKDOWN: return "breakdown (matrix or preconditioner not SPD, or non-finite values)";
-    case PCG_EDEVICE: return "device error";
-    default: return "unknown status";
-  }
-}
 
 }  // extern "C"

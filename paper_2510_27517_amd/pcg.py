@@ -29,7 +29,8 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 EXPORTS = [
     "pcg_config_default", "pcg_create", "pcg_destroy", "pcg_set_matrix", "pcg_set_precond", "pcg_build_precond",
     "pcg_solve", "pcg_matvec", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
-    "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth",
+    "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth", "pcg_submit_batch",
+    "pcg_progress", "pcg_poll", "pcg_solve_batch", "pcg_pool_info",
 ]
 
 
@@ -39,7 +40,7 @@ class Config(ctypes.Structure):
         ("a_dtype", ctypes.c_int), ("g_dtype", ctypes.c_int), ("rr_period", ctypes.c_int),
         ("eps", ctypes.c_double), ("refine", ctypes.c_int), ("inner_tol", ctypes.c_double),
         ("max_outer", ctypes.c_int), ("graph_iters", ctypes.c_int), ("grid_mult", ctypes.c_int),
-        ("reserved", ctypes.c_int * 8),
+        ("mem_budget_mb", ctypes.c_int), ("reserved", ctypes.c_int * 7),
     ]
 
 
@@ -48,10 +49,21 @@ class Result(ctypes.Structure):
         ("status", ctypes.c_int), ("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
         ("restarts", ctypes.c_int), ("relres_true", ctypes.c_double), ("relres_rec", ctypes.c_double),
         ("t_solve_ms", ctypes.c_double), ("bytes_per_iter", ctypes.c_double),
+        ("t_latency_ms", ctypes.c_double), ("t_queue_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class System(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("nnz_a", ctypes.c_int64), ("a_rowptr", ctypes.c_void_p),
+        ("a_col", ctypes.c_void_p), ("a_val", ctypes.c_void_p), ("nnz_g", ctypes.c_int64),
+        ("g_rowptr", ctypes.c_void_p), ("g_col", ctypes.c_void_p), ("g_val", ctypes.c_void_p),
+        ("g_kind", ctypes.c_int), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("tol", ctypes.c_double),
+        ("maxit", ctypes.c_int),
+    ]
 
 
 _lib = None
@@ -84,6 +96,11 @@ def load():
     lib.pcg_bytes_per_iter.restype = dbl
     lib.pcg_time_kernels.argtypes = [P, c_int, P, P]
     lib.pcg_copy_bandwidth.argtypes = [c_int, i64, c_int, P, P]
+    lib.pcg_submit_batch.argtypes = [P, c_int, ctypes.POINTER(System), ctypes.POINTER(ctypes.c_uint64)]
+    lib.pcg_progress.argtypes = [P, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    lib.pcg_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+    lib.pcg_solve_batch.argtypes = [P, c_int, ctypes.POINTER(System), ctypes.POINTER(Result), c_int]
+    lib.pcg_pool_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.pcg_last_error.argtypes = [P]
     lib.pcg_last_error.restype = ctypes.c_char_p
     lib.pcg_strerror.argtypes = [c_int]
@@ -265,6 +282,73 @@ class Solver:
         self._check(self._lib.pcg_time_kernels(self._h, int(iters), ms.ctypes.data, by.ctypes.data),
                     "pcg_time_kernels")
         return {"ms": ms.tolist(), "bytes": by.tolist()}
+
+    # ------------------------------------------------------- batch / serving
+
+    def _system(self, A, b, x0=None, G=None, g_kind=G_FSAI, tol=1e-8, maxit=2000):
+        keep = [_host(A.rowptr, np.int32), _host(A.col, np.int32), _host(A.val, np.float64),
+                _host(b, np.float64)]
+        x = np.zeros(keep[0].shape[0] - 1) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        keep.append(x)
+        sysd = System()
+        sysd.n = keep[0].shape[0] - 1
+        sysd.nnz_a = keep[1].shape[0]
+        sysd.a_rowptr, sysd.a_col, sysd.a_val = keep[0].ctypes.data, keep[1].ctypes.data, keep[2].ctypes.data
+        if G is not None:
+            g = [_host(G.rowptr, np.int32), _host(G.col, np.int32), _host(G.val, np.float64)]
+            keep += g
+            sysd.nnz_g = g[1].shape[0]
+            sysd.g_rowptr, sysd.g_col, sysd.g_val = g[0].ctypes.data, g[1].ctypes.data, g[2].ctypes.data
+        sysd.g_kind = g_kind
+        sysd.b = keep[3].ctypes.data
+        sysd.x = x.ctypes.data
+        sysd.tol = float(tol)
+        sysd.maxit = int(maxit)
+        return sysd, keep, x
+
+    def submit(self, systems):
+        """Queue systems (dicts with A, b and optional x0, G, g_kind, tol,
+        maxit); returns their tickets. Inputs are copied by the library; the
+        solution arrays stay owned here until the ticket finishes."""
+        if not hasattr(self, "_pending"):
+            self._pending = {}
+        built = [self._system(**sd) for sd in systems]
+        arr = (System * len(built))(*[b[0] for b in built])
+        tk = (ctypes.c_uint64 * len(built))()
+        self._check(self._lib.pcg_submit_batch(self._h, len(built), arr, tk), "pcg_submit_batch")
+        for i, b in enumerate(built):
+            self._pending[int(tk[i])] = (b[1], b[2])
+        return [int(t) for t in tk]
+
+    def progress(self, iters=20):
+        """One scheduler step; returns (active, queued)."""
+        a, q = ctypes.c_int(), ctypes.c_int()
+        self._check(self._lib.pcg_progress(self._h, int(iters), ctypes.byref(a), ctypes.byref(q)), "pcg_progress")
+        return a.value, q.value
+
+    def poll(self, ticket):
+        """None while pending, else (x, result dict)."""
+        res = Result()
+        st = self._lib.pcg_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(res))
+        if st == PENDING:
+            return None
+        if st == EINVAL and ticket not in self._pending:
+            raise PCGError(st, "pcg_poll: unknown ticket")
+        _keep, x = self._pending.pop(ticket)
+        return x, res.as_dict()
+
+    def solve_batch(self, systems, iters_per_step=20):
+        """Solve all systems as one batch; returns [(x, result dict)]."""
+        built = [self._system(**sd) for sd in systems]
+        arr = (System * len(built))(*[b[0] for b in built])
+        res = (Result * len(built))()
+        self._check(self._lib.pcg_solve_batch(self._h, len(built), arr, res, int(iters_per_step)), "pcg_solve_batch")
+        return [(b[2], res[i].as_dict()) for i, b in enumerate(built)]
+
+    def pool_info(self):
+        cap, used = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self._lib.pcg_pool_info(self._h, ctypes.byref(cap), ctypes.byref(used)), "pcg_pool_info")
+        return cap.value, used.value
 
     def matvec(self, op: int, x):
         if _is_torch(x):

@@ -1,0 +1,181 @@
+"""Batched and served solves on the GPU: many systems of different sizes in
+one launch per CG kernel. Each system's share of a launch depends only on the
+system, so its result must be bit for bit its single-system result, alone or
+in any mix; and each must match the FP64 oracle to the single-solve bar."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_27517_amd import inputs
+from paper_2510_27517_amd.inputs import CSR
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _mix(seed, count, tol=1e-8):
+    """Systems of mixed kinds and sizes (2D/3D lognormal Poisson, RGG)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        kind = k % 3
+        if kind == 0:
+            A = inputs.poisson(2, int(rng.integers(4, 60)), 0.5, seed * 100 + k)
+        elif kind == 1:
+            A = inputs.poisson(3, int(rng.integers(3, 20)), 0.5, seed * 100 + k)
+        else:
+            A = inputs.rgg_laplacian(int(rng.integers(50, 5000)), seed * 100 + k)
+        out.append(dict(A=A, b=inputs.rhs(A.n, seed * 100 + k), tol=tol, maxit=3000))
+    return out
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batch_equals_single_bitwise(gpu_lib, dt):
+    pcg = gpu_lib
+    systems = _mix(1, 12, tol=1e-8 if dt == "f64" else 1e-6)  # FP32 cannot certify 1e-8
+    kw = dict(vec_dtype=dt, a_dtype=dt, g_dtype=dt)
+    say("batch vs single", dt, [s["A"].n for s in systems])
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        batch = s.solve_batch(systems, iters_per_step=7)
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        for sd, (xb, rb) in zip(systems, batch):
+            s.set_matrix(sd["A"])
+            s.build_precond(pcg.G_FSAI)
+            single = s.solve(sd["b"], tol=sd["tol"], maxit=sd["maxit"])
+            # plain FP32 x cannot always certify the tolerance (the attainable
+            # residual is about u32 ||A|| ||x||): equality is what is required
+            assert rb["status"] == single.status
+            if dt == "f64":
+                assert rb["status"] == pcg.OK
+            assert rb["iters"] == single.iters
+            assert np.array_equal(xb, single.x)
+
+
+@pytest.mark.parametrize("gdt", ["bf16", "f32"])
+def test_refined_batch_equals_single_and_oracle(gpu_lib, gdt):
+    """FP32 vectors and A, G in gdt, FP64 refinement to 1e-8 for every system
+    of the batch: bit-identical to the single refined solve, and within the
+    single-solve bar of the FP64 oracle."""
+    pcg = gpu_lib
+    systems = _mix(5, 9, tol=1e-8)
+    kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype=gdt, refine=1)
+    say("refined batch", gdt, [s["A"].n for s in systems])
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        batch = s.solve_batch(systems, iters_per_step=6)
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        for sd, (xb, rb) in zip(systems, batch):
+            s.set_matrix(sd["A"])
+            s.build_precond(pcg.G_FSAI)
+            single = s.solve(sd["b"], tol=1e-8, maxit=3000)
+            assert rb["status"] == single.status == pcg.OK
+            assert rb["iters"] == single.iters and rb["outer_iters"] == single.outer_iters
+            assert np.array_equal(xb, single.x)
+            r64 = np.linalg.norm(sd["b"] - oracle.spmv(sd["A"], xb)) / np.linalg.norm(sd["b"])
+            assert r64 <= 1.0001e-8 and rb["relres_true"] <= 1e-8
+            ref = oracle.pcg(sd["A"], oracle.fsai_g(sd["A"]), sd["b"], tol=1e-12, maxit=20000, delta_form=1)
+            kappa_bound = 1e-8 * np.linalg.cond(sd["A"].to_dense()) if sd["A"].n <= 1500 else None
+            err = np.linalg.norm(xb - ref.x) / np.linalg.norm(ref.x)
+            say(f"  n={sd['A'].n} outer={rb['outer_iters']} inner={rb['iters']} relres64={r64:.2e} err={err:.2e}")
+            if kappa_bound is not None:
+                assert err <= kappa_bound
+
+
+def test_batch_matches_oracle(gpu_lib):
+    pcg = gpu_lib
+    systems = _mix(2, 9)
+    with pcg.Solver(pcg.default_config()) as s:
+        batch = s.solve_batch(systems)
+    for sd, (x, r) in zip(systems, batch):
+        ref = oracle.pcg(sd["A"], oracle.fsai_g(sd["A"]), sd["b"], tol=1e-8, maxit=3000, delta_form=1)
+        assert r["status"] == pcg.OK and abs(r["iters"] - ref.iters) <= 1
+        assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_served_alone_equals_mixed(gpu_lib):
+    """Continuous batching: requests arrive while others run (admitted between
+    steps). A request's result is bit-identical to the same request alone."""
+    pcg = gpu_lib
+    systems = _mix(3, 15, tol=1e-8)
+    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    alone = []
+    with pcg.Solver(cfg) as s:
+        for sd in systems:
+            alone.append(s.solve_batch([sd])[0])
+    say("served mix")
+    with pcg.Solver(cfg) as s:
+        tickets = []
+        waves = [systems[0:5], systems[5:9], systems[9:15]]
+        got = {}
+        for w in waves:
+            tickets += s.submit(w)
+            for _ in range(3):
+                s.progress(5)
+                for t in tickets:
+                    if t not in got:
+                        r = s.poll(t)
+                        if r is not None:
+                            got[t] = r
+        while len(got) < len(tickets):
+            s.progress(10)
+            for t in tickets:
+                if t not in got:
+                    r = s.poll(t)
+                    if r is not None:
+                        got[t] = r
+        assert s.pool_info()[1] == 0  # everything retired and freed
+    for sd, t, (xa, ra) in zip(systems, tickets, alone):
+        xm, rm = got[t]
+        say(f"  n={sd['A'].n} alone {ra['status']} {ra['iters']}/{ra['outer_iters']} {ra['relres_true']:.2e} "
+            f"mixed {rm['status']} {rm['iters']}/{rm['outer_iters']} {rm['relres_true']:.2e} "
+            f"latency {rm['t_latency_ms']:.1f} ms queue {rm['t_queue_ms']:.1f} ms")
+    for t, (xa, ra) in zip(tickets, alone):
+        xm, rm = got[t]
+        assert rm["status"] == ra["status"] == pcg.OK and rm["relres_true"] <= 1e-8
+        assert rm["iters"] == ra["iters"] and np.array_equal(xm, xa)
+        assert rm["t_latency_ms"] >= rm["t_queue_ms"] >= 0
+
+
+def test_batch_mixed_outcomes(gpu_lib):
+    """Zero right-hand side, iteration limit and breakdown in one batch with a
+    normal system: each system gets its own status, the normal one is
+    unaffected."""
+    pcg = gpu_lib
+    A = inputs.poisson(2, 20, 0.5, 4)
+    b = inputs.rhs(A.n, 4)
+    neg = CSR(A.rowptr, A.col, -A.val)
+    systems = [dict(A=A, b=b, tol=1e-8, maxit=3000), dict(A=A, b=np.zeros(A.n), x0=np.ones(A.n)),
+               dict(A=A, b=b, tol=1e-8, maxit=5),
+               dict(A=neg, b=b, G=oracle.identity(A.n), tol=1e-8, maxit=100)]
+    with pcg.Solver(pcg.default_config()) as s:
+        res = s.solve_batch(systems, iters_per_step=4)
+    (x0, r0), (x1, r1), (x2, r2), (x3, r3) = res
+    ref = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-8, maxit=3000, delta_form=1)
+    assert r0["status"] == pcg.OK and np.linalg.norm(x0 - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    assert r1["status"] == pcg.OK and r1["iters"] == 0 and np.all(x1 == 0)
+    assert r2["status"] == pcg.NOT_CONVERGED and r2["iters"] == 5
+    ref5 = oracle.pcg(A, oracle.fsai_g(A), b, maxit=5, delta_form=1)
+    assert np.linalg.norm(x2 - ref5.x) <= 1e-12 * np.linalg.norm(ref5.x)
+    assert r3["status"] == pcg.EBREAKDOWN
+
+
+def test_admission_by_memory_budget(gpu_lib):
+    """A 4 MiB pool: a system larger than the pool is refused with ENOMEM;
+    the others are admitted as room frees up and all complete."""
+    pcg = gpu_lib
+    small = [dict(A=inputs.poisson(2, 30, 0.5, k), b=inputs.rhs(900, k), tol=1e-8, maxit=2000) for k in range(6)]
+    big = inputs.poisson(3, 60, 0.5, 9)
+    systems = small[:3] + [dict(A=big, b=inputs.rhs(big.n, 9), tol=1e-8, maxit=100)] + small[3:]
+    with pcg.Solver(pcg.default_config(mem_budget_mb=4)) as s:
+        res = s.solve_batch(systems, iters_per_step=10)
+        cap, used = s.pool_info()
+    assert cap == 4 << 20 and used == 0
+    assert res[3][1]["status"] == pcg.ENOMEM
+    for k, (x, r) in enumerate(res):
+        if k != 3:
+            assert r["status"] == pcg.OK and r["relres_true"] <= 1e-8
