@@ -1,23 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of FSAI-preconditioned CG (M^-1 = G G^T) on one MI355X.
 
-Workload: 3D variable-coefficient Poisson, 7-point stencil on a 128^3 grid
-(n = 2,097,152, nnz = 14,581,760), lognormal face coefficients (sigma = 1),
-b ~ N(0, 1) (seed 0), G = FSAI on tril(A), solved in FP64 from x0 = 0 to
-||b - A x|| <= 1e-8 ||b||. One step = one complete solve with A, G, b resident
-in HBM (the preconditioner is built once, outside the timed region, as the
-paper's T_construct).
+Headline workload (the JSON line's `value`): 3D variable-coefficient Poisson,
+7-point stencil on a 128^3 grid (n = 2,097,152, nnz = 14,581,760), lognormal
+face coefficients (sigma = 1), b ~ N(0, 1) (seed 0), G = FSAI on tril(A),
+solved in FP64 from x0 = 0 to ||b - A x|| <= 1e-8 ||b||. One step = one
+complete solve with A, G, b resident in HBM (the preconditioner is built
+once, outside the timed region, as the paper's T_construct).
 
-Prints one JSON line: solves/s (value), time to tolerance, HBM GB/s per
-iteration, the roofline of the dominant kernel (the A-kernel) from live
-HIP-event timing, the measured copy ceiling, and the FP64 CPU oracle timed on
-the host cores on a bounded sample of the same solve.
+Further sections, each under its own key of the same JSON line:
+  mixed      the same system in FP32 (A, vectors) with BF16 G and FP64
+             iterative refinement to 1e-8, against the FP64 time to tolerance;
+  batched    512 2D/3D lognormal Poisson systems of uneven size solved as one
+             batch (FP32, FP64 refinement, tol 1e-6): solves/s, latency;
+  serving    random-geometric-graph Laplacian requests arriving as a Poisson
+             stream at 0.8x the measured closed-loop rate: p50/p99 latency;
+  elasticity Q1 elasticity, 64^3 free nodes x 3 dof (n = 786,432, 61.7M
+             nonzeros): BF16/FP16 G with FP64 refinement to 1e-10 against the
+             plain FP64 solve.
+The FP64 CPU oracle is timed on the host cores on the headline solve and also
+states each GPU solution's error against its own solution.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -35,6 +44,7 @@ TOL = 1e-8
 MAXIT = 5000
 KERNEL_SOURCES = ["paper_2510_27517_amd/csrc/kernels.hip", "paper_2510_27517_amd/csrc/kernels.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iter_A_poisson3d_128_f64_traffic.md")
+SECTIONS = ["mixed", "batched", "serving", "elasticity"]
 
 
 def log(*a):
@@ -62,28 +72,204 @@ def stored_traffic():
     return float(m_b.group(1))
 
 
-def cpu_baseline(A, b, gpu_iters, budget_s):
-    """The FP64 oracle (as it stands) on the host cores: a bounded number of
-    iterations of the same solve, scaled to the GPU's iteration count."""
+def pct(v, q):
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def cpu_baseline(A, b, gpu_iters, budget_s, gpu_solutions):
+    """The FP64 oracle (as it stands) on the host cores: the same solve, cut
+    to a bounded number of iterations when a full solve would exceed the
+    budget, scaled to the GPU's iteration count. When it runs to the
+    tolerance its solution also gives the GPU solutions' errors."""
     import oracle
 
     threads = len(os.sched_getaffinity(0))
     G = oracle.fsai_g(A)
     t0 = time.perf_counter()
     oracle.pcg(A, G, b, tol=TOL, maxit=3, delta_form=1, threads=threads)
-    t3 = time.perf_counter() - t0
-    per = t3 / 3
-    m = int(max(5, min(400, budget_s / max(per, 1e-6))))
+    per = (time.perf_counter() - t0) / 3
+    m = int(max(5, min(MAXIT, budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
     r = oracle.pcg(A, G, b, tol=TOL, maxit=m, delta_form=1, threads=threads)
     el = time.perf_counter() - t0
     per_it = el / max(r.iters, 1)
-    t_solve = per_it * gpu_iters
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{r.iters} FP64 oracle PCG iterations of the same 128^3 FSAI solve on {threads} host threads "
-                      f"({el:.1f} s, {per_it * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations",
-            "ms_per_iteration": per_it * 1e3}
+    out = {"value": 1.0 / (per_it * gpu_iters), "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"{r.iters} FP64 oracle PCG iterations of the same 128^3 FSAI solve on {threads} host threads "
+                     f"({el:.1f} s, {per_it * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations",
+           "ms_per_iteration": per_it * 1e3, "oracle_iters": r.iters, "oracle_status": r.status}
+    if r.status == oracle.OK:
+        nx = float(np.linalg.norm(r.x))
+        out["gpu_error_vs_oracle"] = {k: float(np.linalg.norm(x - r.x) / nx) for k, x in gpu_solutions.items()}
+    return out
 
+
+# ---------------------------------------------------------------- sections
+
+def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
+    """128^3 in FP32 (A, vectors) with BF16 G and FP64 refinement to 1e-8."""
+    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    with pcg.Solver(cfg) as s:
+        s.set_matrix(A)
+        s.set_precond(rowptr=G[0], col=G[1], val=G[2])
+        s.solve(b_dev, tol=TOL, maxit=MAXIT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = s.solve(b_dev, tol=TOL, maxit=MAXIT)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"workload": "poisson3d_128^3_sigma1_fsai, A/vectors f32, G bf16, FP64 refinement to 1e-8",
+            "time_to_tol_ms": round(ms, 3), "speedup_vs_fp64": round(t_fp64_ms / ms, 3), "status": r.status,
+            "inner_iters": r.iters, "outer_iters": r.outer_iters, "relres_true_fp64": r.relres_true,
+            "alg_bytes_per_inner_iter": r.bytes_per_iter}, r.x.cpu().numpy()
+
+
+def batch_systems(inputs, count):
+    """2D (side U{16..256}) or 3D (side U{8..64}) lognormal (sigma 0.5) Poisson
+    with probability 1/2 each, b ~ N(0,1); system i uses seed i."""
+    kind = inputs.u01(0, inputs.STREAM_KIND, count)
+    size = inputs.u01(0, inputs.STREAM_SIZES, count)
+    out = []
+    for i in range(count):
+        if kind[i] < 0.5:
+            N = 16 + min(240, int(size[i] * 241))
+            A = inputs.poisson(2, N, 0.5, i)
+        else:
+            N = 8 + min(56, int(size[i] * 57))
+            A = inputs.poisson(3, N, 0.5, i)
+        out.append(dict(A=A, b=inputs.rhs(A.n, i), tol=1e-6, maxit=10000))
+    return out
+
+
+def section_batched(pcg, inputs, count):
+    log(f"batched: generating {count} systems")
+    systems = batch_systems(inputs, count)
+    n_tot = sum(s["A"].n for s in systems)
+    nnz_tot = sum(s["A"].nnz for s in systems)
+    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="f32", refine=1)
+    log(f"batched: solving {count} systems, {n_tot} rows")
+    with pcg.Solver(cfg) as s:
+        t0 = time.perf_counter()
+        res = s.solve_batch(systems, iters_per_step=10)
+        wall = time.perf_counter() - t0
+    st = [r["status"] for _, r in res]
+    lat = [r["t_latency_ms"] for _, r in res]
+    solve = [r["t_solve_ms"] for _, r in res]
+    return {"workload": f"{count} systems: 2D side U[16,256] / 3D side U[8,64] lognormal sigma 0.5 Poisson, "
+                        "FSAI G built on the host, A/vectors/G f32, FP64 refinement, tol 1e-6",
+            "systems": count, "rows_total": n_tot, "nnz_total": nnz_tot,
+            "solves_per_s": round(count / wall, 2), "wall_s": round(wall, 3),
+            "ok": st.count(pcg.OK), "statuses": sorted(set(st)),
+            "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99),
+            "solve_ms_p50": pct(solve, 50), "solve_ms_p99": pct(solve, 99),
+            "max_relres_true_fp64": max(r["relres_true"] for _, r in res),
+            "inner_iters_max": max(r["iters"] for _, r in res),
+            "note": "wall time from submission to the last completion, including host FSAI construction and "
+                    "uploads"}
+
+
+def serving_requests(inputs, count):
+    """RGG Laplacian + 1e-3 I, n log-uniform in [1e3, 1e6]."""
+    u = inputs.u01(7, inputs.STREAM_SIZES, count)
+    out = []
+    for i in range(count):
+        n = int(round(10 ** (3 + 3 * u[i])))
+        A = inputs.rgg_laplacian(n, 10_000 + i)
+        out.append(dict(A=A, b=inputs.rhs(A.n, 10_000 + i), tol=1e-6, maxit=20000))
+    return out
+
+
+def _drain(s, tickets, got):
+    for t in tickets:
+        if t not in got:
+            r = s.poll(t)
+            if r is not None:
+                got[t] = r
+
+
+def section_serving(pcg, inputs, count, iters_per_step):
+    log(f"serving: generating {count} requests")
+    reqs = serving_requests(inputs, count)
+    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    # closed loop: everything at once, the sustainable rate mu
+    with pcg.Solver(cfg) as s:
+        t0 = time.perf_counter()
+        res = s.solve_batch(reqs, iters_per_step=iters_per_step)
+        wall = time.perf_counter() - t0
+    mu = count / wall
+    lam = 0.8 * mu
+    # open loop: Poisson arrivals at lambda; each request submitted at its
+    # arrival time (to the loop's step granularity)
+    gaps = -np.log(inputs.u01(7, inputs.STREAM_ARRIVALS, count)) / lam
+    arrive = np.cumsum(gaps)
+    got, tickets, sub_lag = {}, [], {}
+    log(f"serving: open loop at {lam:.1f} requests/s")
+    with pcg.Solver(cfg) as s:
+        t0 = time.perf_counter()
+        nxt = 0
+        active = queued = 0
+        while len(got) < count:
+            now = time.perf_counter() - t0
+            batch = []
+            while nxt < count and arrive[nxt] <= now:
+                batch.append(nxt)
+                nxt += 1
+            if batch:
+                tk = s.submit([reqs[i] for i in batch])
+                for i, t in zip(batch, tk):
+                    tickets.append(t)
+                    sub_lag[t] = (now - arrive[i]) * 1e3
+            if active or queued or batch:
+                active, queued = s.progress(iters_per_step)
+            elif nxt < count:
+                time.sleep(max(0.0, min(0.01, arrive[nxt] - now)))
+            _drain(s, tickets, got)
+        span = time.perf_counter() - t0
+    lat = [got[t][1]["t_latency_ms"] + sub_lag[t] for t in tickets]
+    st = [got[t][1]["status"] for t in tickets]
+    ns = [r["A"].n for r in reqs]
+    return {"workload": f"{count} RGG Laplacian + 1e-3 I requests, n log-uniform [1e3,1e6] (mean {np.mean(ns):.0f}), "
+                        "mean degree ~8, weights U[0.1,10]; f32 A/vectors, bf16 FSAI G, FP64 refinement, tol 1e-6; "
+                        "Poisson arrivals at 0.8x the closed-loop rate",
+            "requests": count, "closed_loop_solves_per_s": round(mu, 2), "arrival_rate": round(lam, 2),
+            "open_loop_solves_per_s": round(count / span, 2), "latency_ms_p50": pct(lat, 50),
+            "latency_ms_p99": pct(lat, 99), "ok": st.count(pcg.OK),
+            "max_relres_true_fp64": max(got[t][1]["relres_true"] for t in tickets),
+            "closed_loop_latency_ms_p99": pct([r["t_latency_ms"] for _, r in res], 99)}
+
+
+def section_elasticity(pcg, inputs, N):
+    log(f"elasticity: generating {N}^3 x 3")
+    A = inputs.elasticity(N, 1.0, 0.3, 0)
+    b = inputs.rhs(A.n, 0)
+    t0 = time.perf_counter()
+    G = pcg.build_g_host(pcg.G_FSAI, A)
+    t_fsai = time.perf_counter() - t0
+    out = {"workload": f"Q1 elasticity {N}^3 free nodes x 3 dof, E lognormal sigma 1, nu 0.3, FSAI G, tol 1e-10",
+           "n": A.n, "nnz": A.nnz, "t_construct_fsai_s": round(t_fsai, 2)}
+    x64 = None
+    for name, kw in [("fp64", dict()), ("f32_bf16_refined", dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16",
+                                                                   refine=1)),
+                     ("f32_f16_refined", dict(vec_dtype="f32", a_dtype="f32", g_dtype="f16", refine=1))]:
+        log(f"elasticity: {name}")
+        with pcg.Solver(pcg.default_config(**kw)) as s:
+            s.set_matrix(A)
+            s.set_precond(rowptr=G[0], col=G[1], val=G[2])
+            t0 = time.perf_counter()
+            r = s.solve(b, tol=1e-10, maxit=20000)
+            ms = (time.perf_counter() - t0) * 1e3
+        d = {"time_to_tol_ms": round(ms, 2), "status": r.status, "iters": r.iters, "outer_iters": r.outer_iters,
+             "relres_true_fp64": r.relres_true}
+        if x64 is None:
+            x64 = r.x
+            out["ms_per_iter_fp64"] = round(ms / max(r.iters, 1), 4)
+        else:
+            d["error_vs_fp64_gpu"] = float(np.linalg.norm(r.x - x64) / np.linalg.norm(x64))
+        out[name] = d
+    return out
+
+
+# ---------------------------------------------------------------- main
 
 def main():
     ap = argparse.ArgumentParser()
@@ -91,14 +277,20 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kernel-iters", type=int, default=60)
-    ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--sections", default=",".join(SECTIONS), help="comma list of " + ",".join(SECTIONS) + " or none")
+    ap.add_argument("--batch-systems", type=int, default=512)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-step", type=int, default=10)
+    ap.add_argument("--elasticity-n", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs single-GPU solves only (independent systems would "
               "shard by request across GPUs, a single system by row slabs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    sections = [x for x in args.sections.split(",") if x in SECTIONS]
 
     import torch
 
@@ -111,17 +303,18 @@ def main():
     log("generating 128^3 system")
     A = inputs.poisson(3, N_SIDE, 1.0, 0)
     b = inputs.rhs(A.n, 0)
+    t0 = time.perf_counter()
+    G = pcg.build_g_host(pcg.G_FSAI, A)
+    t_construct = time.perf_counter() - t0
     solver = pcg.Solver(pcg.default_config(device=0))
     solver.set_matrix(A)
-    t0 = time.perf_counter()
-    solver.build_precond(pcg.G_FSAI)
-    t_construct = time.perf_counter() - t0
+    solver.set_precond(rowptr=G[0], col=G[1], val=G[2])
     b_dev = torch.from_numpy(b).to(dev)
     torch.cuda.synchronize()
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
-        out = solver.solve(b_dev, tol=TOL, maxit=MAXIT)
+        solver.solve(b_dev, tol=TOL, maxit=MAXIT)
     torch.cuda.synchronize()
     log(f"timing {args.steps} solves")
     results = []
@@ -136,6 +329,7 @@ def main():
     iters = last.iters
     bpi = last.bytes_per_iter
     gbps_iter = bpi / (ms_per_step * 1e-3 / iters) / 1e9
+    x_fp64 = last.x.cpu().numpy()
 
     log("kernel timing")
     kt = solver.time_kernels(args.kernel_iters)
@@ -154,26 +348,39 @@ def main():
         log("copy probe")
         gb, ms = pcg.copy_bandwidth(4 << 30, reps=10)
         copy = {"gbps": round(gb, 1), "bytes": 4 << 30, "ms_per_copy": ms}
-
     relres = last.relres_true  # ||b - A x|| / ||b|| from the library's FP64 residual kernel
     solver.close()
+
+    extra, sols = {}, {"fp64": x_fp64}
+    if "mixed" in sections:
+        log("mixed precision")
+        extra["mixed"], sols["mixed_f32_bf16_refined"] = section_mixed(pcg, torch, A, G, b_dev, max(3, args.steps // 2),
+                                                                       ms_per_step)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(A, b, iters, args.cpu_budget_s)
+        cpu = cpu_baseline(A, b, iters, args.cpu_budget_s, sols)
+    del b_dev
+    if "batched" in sections and args.batch_systems > 0:
+        extra["batched"] = section_batched(pcg, inputs, args.batch_systems)
+    if "serving" in sections and args.serve_requests > 0:
+        extra["serving"] = section_serving(pcg, inputs, args.serve_requests, args.serve_step)
+    if "elasticity" in sections and args.elasticity_n > 0:
+        extra["elasticity"] = section_elasticity(pcg, inputs, args.elasticity_n)
 
     line = {
         "metric": METRIC, "value": round(1e3 / ms_per_step, 3), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "poisson3d_7pt_128^3_lognormal_sigma1_fsai_f64_tol1e-8", "n": A.n, "nnz_a": A.nnz,
-                   "nnz_g": (A.nnz + A.n) // 2, "tol": TOL, "x0": "zeros", "rr_period": 50},
+                   "nnz_g": int(G[1].shape[0]), "tol": TOL, "x0": "zeros", "rr_period": 50},
         "time_to_tol_ms": round(ms_per_step, 3), "iters": iters, "ms_per_iter": round(ms_per_step / iters, 5),
         "hbm_gbps_per_iter": round(gbps_iter, 1), "alg_bytes_per_iter": bpi,
         "relres_true_fp64": relres, "t_construct_s": round(t_construct, 3),
         "roofline": roofline, "kernels": kernels, "copy_probe": copy, "cpu_baseline": cpu,
         "kernel_sources_sha": kernel_sha(),
     }
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 
