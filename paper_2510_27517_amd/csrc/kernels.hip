@@ -53,8 +53,19 @@ namespace pcgk {
 
 struct bf16_t { uint16_t bits; };
 
+// Pointers that come out of the device directory are not known to the
+// compiler to address global memory, and accesses through them compile to
+// flat instructions, which also count on the LDS wait counter and so stall
+// every LDS wait of the staging loop behind outstanding gathers. Kernels
+// therefore take every directory pointer into the global address space.
+#define GLOBAL __attribute__((address_space(1)))
 template <typename T>
-__device__ __forceinline__ T ldstream(const T *p, int64_t k) {
+__device__ __forceinline__ GLOBAL T *gl(T *p) {
+  return (GLOBAL T *)p;
+}
+
+template <typename T>
+__device__ __forceinline__ T ldstream(GLOBAL const T *p, int64_t k) {
 #if PCG_NT_MATRIX
   return __builtin_nontemporal_load(p + k);
 #else
@@ -62,28 +73,49 @@ __device__ __forceinline__ T ldstream(const T *p, int64_t k) {
 #endif
 }
 
-__device__ __forceinline__ double ldval(const double *p, int64_t k) { return ldstream(p, k); }
-__device__ __forceinline__ float ldval(const float *p, int64_t k) { return ldstream(p, k); }
-__device__ __forceinline__ float ldval(const bf16_t *p, int64_t k) {
-  return __uint_as_float((uint32_t)ldstream((const uint16_t *)p, k) << 16);
+__device__ __forceinline__ double ldval(GLOBAL const double *p, int64_t k) { return ldstream(p, k); }
+__device__ __forceinline__ float ldval(GLOBAL const float *p, int64_t k) { return ldstream(p, k); }
+__device__ __forceinline__ float ldval(GLOBAL const bf16_t *p, int64_t k) {
+  return __uint_as_float((uint32_t)ldstream((GLOBAL const uint16_t *)p, k) << 16);
 }
-__device__ __forceinline__ float ldval(const _Float16 *p, int64_t k) { return (float)ldstream(p, k); }
+__device__ __forceinline__ float ldval(GLOBAL const _Float16 *p, int64_t k) { return (float)ldstream(p, k); }
 
-// Workgroup b is dispatched to XCD b % 8; give XCD x the logical ids
-// [x*G/8, (x+1)*G/8) so its workgroups cover consecutive rows. G % 8 == 0.
-__device__ __forceinline__ int xcd_remap(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
+// Whole-record copies of a State (one thread publishes a slot), in 16-byte
+// words of a builtin vector type (usable in any address space).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ State ld_state(GLOBAL const State *p) {
+  constexpr int W = (int)(sizeof(State) / 16);
+  u32x4 w[W];
+  GLOBAL const u32x4 *q = (GLOBAL const u32x4 *)p;
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = q[i];
+  State o;
+  __builtin_memcpy(&o, w, sizeof(State));
+  return o;
+}
+
+__device__ __forceinline__ void st_state(GLOBAL State *p, const State &o) {
+  constexpr int W = (int)(sizeof(State) / 16);
+  u32x4 w[W];
+  __builtin_memcpy(w, &o, sizeof(State));
+  GLOBAL u32x4 *q = (GLOBAL u32x4 *)p;
+#pragma unroll
+  for (int i = 0; i < W; ++i) q[i] = w[i];
+}
 
 template <typename TM>
 struct Mat {
-  const int32_t *rp, *ci;
-  const TM *val;
-  const int32_t *blk;
+  GLOBAL const int32_t *rp;
+  GLOBAL const int32_t *ci;
+  GLOBAL const TM *val;
+  GLOBAL const int32_t *blk;
   int32_t nblk;
 };
 
 template <typename TM>
 __device__ __forceinline__ Mat<TM> mat(const DevCSR &m) {
-  return Mat<TM>{m.rp, m.ci, (const TM *)m.val, m.blk, m.nblk};
+  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk};
 }
 
 // Operands of one row loaded before the row's products are staged.
@@ -178,7 +210,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
 
 // Write this workgroup's partial sums (value j at p[j * G + L]).
 template <int NV>
-__device__ __forceinline__ void put_partials(double (&v)[NV], double *p, int L, int G, double *sh) {
+__device__ __forceinline__ void put_partials(double (&v)[NV], GLOBAL double *p, int L, int G, double *sh) {
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0)
 #pragma unroll
@@ -187,7 +219,8 @@ __device__ __forceinline__ void put_partials(double (&v)[NV], double *p, int L, 
 
 // Sum the P partials of each value in a fixed order; every thread gets the totals.
 template <int NV>
-__device__ __forceinline__ void sum_partials(const double *__restrict__ p, int P, double (&out)[NV], double *sh) {
+__device__ __forceinline__ void sum_partials(GLOBAL const double *__restrict__ p, int P, double (&out)[NV],
+                                             double *sh) {
   double acc[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
@@ -213,16 +246,16 @@ __global__ __launch_bounds__(kBlock) void k_iter_A(const SysDev *__restrict__ di
   __shared__ double sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
-  const State &S = D.st[0];
+  GLOBAL const State &S = gl(D.st)[0];
   if (S.done) return;
   const Mat<TA> A = mat<TA>(D.A);
   const int it = S.iter;
   const TV beta = (TV)S.beta, ap = (TV)S.alpha;
-  TV *__restrict__ x = (TV *)D.x;
-  const TV *__restrict__ s = (const TV *)D.s;
-  TV *__restrict__ q = (TV *)D.q;
-  const TV *__restrict__ dold = (const TV *)((it & 1) ? D.d0 : D.d1);  // d_{i-1}
-  TV *__restrict__ dnew = (TV *)((it & 1) ? D.d1 : D.d0);              // d_i
+  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
+  GLOBAL const TV *__restrict__ s = gl((const TV *)D.s);
+  GLOBAL TV *__restrict__ q = gl((TV *)D.q);
+  GLOBAL const TV *__restrict__ dold = gl((const TV *)((it & 1) ? D.d0 : D.d1));  // d_{i-1}
+  GLOBAL TV *__restrict__ dnew = gl((TV *)((it & 1) ? D.d1 : D.d0));              // d_i
   double part[1] = {0.0};
   const Sched sc = sched(A.nblk, m.y, D.A.grid);
   for (int b = sc.first; b < sc.end; b += sc.stride)
@@ -236,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_A(const SysDev *__restrict__ di
           x[row] = pv.c + ap * pv.b;
           part[0] += (double)di * (double)sum;
         });
-  put_partials<1>(part, D.pg, sc.L, D.A.grid, sh);
+  put_partials<1>(part, gl(D.pg), sc.L, D.A.grid, sh);
 }
 
 template <typename TV, typename TG>
@@ -246,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void k_iter_GT(const SysDev *__restrict__ d
   __shared__ double sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
-  const State &S = D.st[0];
+  GLOBAL State *st = gl(D.st);
+  GLOBAL const State &S = st[0];
   if (S.done) return;
   const int it = S.iter;
   if (mode == 3) mode = (S.rr_period > 0 && it > 0 && it % S.rr_period == 0) ? 1 : 0;
@@ -254,28 +288,28 @@ __global__ __launch_bounds__(kBlock) void k_iter_GT(const SysDev *__restrict__ d
   bool brk = false;
   if (mode != 2) {
     double g[1];
-    sum_partials<1>(D.pg, D.A.grid, g, sh);
+    sum_partials<1>(gl(D.pg), D.A.grid, g, sh);
     gamma = g[0];
     brk = !(gamma > 0.0) || !isfinite(gamma);
     alpha = brk ? 0.0 : S.delta / gamma;  // on breakdown x already holds x_i
   }
   if (m.y == 0 && threadIdx.x == 0) {
-    State o = S;
+    State o = ld_state(&S);
     o.gamma = gamma;
     o.alpha = alpha;
     if (brk) {
       o.status = ST_BREAK_GAMMA;
       o.done = 1;
     }
-    D.st[1] = o;
+    st_state(st + 1, o);
   }
   if (brk) return;
   const Mat<TG> GT = mat<TG>(D.GT);
-  const TV *__restrict__ q = (const TV *)D.q;
-  TV *__restrict__ t = (TV *)D.t;
+  GLOBAL const TV *__restrict__ q = gl((const TV *)D.q);
+  GLOBAL TV *__restrict__ t = gl((TV *)D.t);
   const TV al = (mode == 0) ? (TV)alpha : (TV)0;
-  const TV *__restrict__ src = (const TV *)((((mode == 1) ? it + 1 : it) & 1) ? D.r1 : D.r0);
-  TV *__restrict__ dst = (TV *)(((it + 1) & 1) ? D.r1 : D.r0);
+  GLOBAL const TV *__restrict__ src = gl((const TV *)((((mode == 1) ? it + 1 : it) & 1) ? D.r1 : D.r0));
+  GLOBAL TV *__restrict__ dst = gl((TV *)(((it + 1) & 1) ? D.r1 : D.r0));
   double part[2] = {0.0, 0.0};
   const Sched sc = sched(GT.nblk, m.y, D.GT.grid);
   if (mode == 0) {
@@ -301,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_GT(const SysDev *__restrict__ d
             part[1] += (double)sum * (double)sum;
           });
   }
-  put_partials<2>(part, D.prt, sc.L, D.GT.grid, sh);
+  put_partials<2>(part, gl(D.prt), sc.L, D.GT.grid, sh);
 }
 
 template <typename TV, typename TG, bool HAS_EPS>
@@ -311,42 +345,46 @@ __global__ __launch_bounds__(kBlock) void k_iter_G(const SysDev *__restrict__ di
   __shared__ double sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
-  if (D.st[0].done) return;  // stopped before this iteration's G^T-kernel ran
-  const State &S = D.st[1];
+  GLOBAL State *st = gl(D.st);
+  if (st[0].done) return;  // stopped before this iteration's G^T-kernel ran
+  GLOBAL const State &S = st[1];
   if (S.done) {  // the G^T-kernel flagged a breakdown: publish it
-    if (m.y == 0 && threadIdx.x == 0) D.st[0] = S;
+    if (m.y == 0 && threadIdx.x == 0) st_state(st, ld_state(&S));
     return;
   }
   const int it = S.iter;
   double v[2];
-  sum_partials<2>(D.prt, D.GT.grid, v, sh);
+  sum_partials<2>(gl(D.prt), D.GT.grid, v, sh);
   const double rr = v[0], tt = v[1];
   const double dn = tt + S.eps * rr;
-  State o = S;
-  o.rr = rr;
-  o.tt = tt;
   const int i1 = (mode == 2) ? it : it + 1;
-  o.iter = i1;
-  if (mode != 2 && (!(dn >= 0.0) || !isfinite(dn))) {
-    o.status = ST_BREAK_DELTA;
-    o.done = 1;
-  } else {
-    o.beta = (mode == 2) ? 0.0 : dn / S.delta;
-    o.delta = dn;
-    if (sqrt(rr) <= S.tol_nb) {
-      o.status = ST_CONV_REC;
-      o.done = 1;
-    } else if (i1 >= S.maxit) {
-      o.status = ST_MAXIT;
+  int status = ST_RUNNING;
+  if (mode != 2 && (!(dn >= 0.0) || !isfinite(dn)))
+    status = ST_BREAK_DELTA;
+  else if (sqrt(rr) <= S.tol_nb)
+    status = ST_CONV_REC;
+  else if (i1 >= S.maxit)
+    status = ST_MAXIT;
+  if (m.y == 0 && threadIdx.x == 0) {
+    State o = ld_state(&S);
+    o.rr = rr;
+    o.tt = tt;
+    o.iter = i1;
+    if (status != ST_BREAK_DELTA) {
+      o.beta = (mode == 2) ? 0.0 : dn / S.delta;
+      o.delta = dn;
+    }
+    if (status != ST_RUNNING) {
+      o.status = status;
       o.done = 1;
     }
+    st_state(st, o);
   }
-  if (m.y == 0 && threadIdx.x == 0) D.st[0] = o;
-  if (o.done) return;
+  if (status != ST_RUNNING) return;
   const Mat<TG> G = mat<TG>(D.G);
-  const TV *__restrict__ t = (const TV *)D.t;
-  TV *__restrict__ s = (TV *)D.s;
-  const TV *__restrict__ rc = (const TV *)((i1 & 1) ? D.r1 : D.r0);
+  GLOBAL const TV *__restrict__ t = gl((const TV *)D.t);
+  GLOBAL TV *__restrict__ s = gl((TV *)D.s);
+  GLOBAL const TV *__restrict__ rc = gl((const TV *)((i1 & 1) ? D.r1 : D.r0));
   const TV eps = (TV)S.eps;
   const Sched sc = sched(G.nblk, m.y, D.G.grid);
   for (int b = sc.first; b < sc.end; b += sc.stride)
@@ -368,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(const SysDev *__restrict__ dir
   __shared__ double sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
-  const State &S = D.st[0];
+  GLOBAL const State &S = gl(D.st)[0];
   if (respect_done && S.done) return;
   const int it = S.iter;
   if (slot_sel == 2) {  // replacement decided per system
@@ -376,14 +414,14 @@ __global__ __launch_bounds__(kBlock) void k_resid(const SysDev *__restrict__ dir
     slot_sel = 1;
   }
   const Mat<TA> A = mat<TA>(D.A);
-  const TV *__restrict__ b = (const TV *)D.b;
-  const TV *__restrict__ x = (const TV *)D.x;
-  TV *__restrict__ rout = (TV *)(((it + slot_sel) & 1) ? D.r1 : D.r0);
-  const TV *__restrict__ dc = (const TV *)((it & 1) ? D.d1 : D.d0);  // d_i
+  GLOBAL const TV *__restrict__ b = gl((const TV *)D.b);
+  GLOBAL const TV *__restrict__ x = gl((const TV *)D.x);
+  GLOBAL TV *__restrict__ rout = gl((TV *)(((it + slot_sel) & 1) ? D.r1 : D.r0));
+  GLOBAL const TV *__restrict__ dc = gl((const TV *)((it & 1) ? D.d1 : D.d0));  // d_i
   TV al = (TV)0;
   if (with_d) {
     double g[1];
-    sum_partials<1>(D.pg, D.A.grid, g, sh);
+    sum_partials<1>(gl(D.pg), D.A.grid, g, sh);
     if (!(g[0] > 0.0) || !isfinite(g[0])) return;  // the G^T-kernel reports the breakdown
     al = (TV)(S.delta / g[0]);
   }
@@ -402,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(const SysDev *__restrict__ dir
     for (int k = sc.first; k < sc.end; k += sc.stride)
       stream_block<TV>(A, k, lds, pre, [&](int j) -> TV { return x[j]; }, epi);
   }
-  if (reduce) put_partials<1>(part, D.ptr, sc.L, D.A.grid, sh);
+  if (reduce) put_partials<1>(part, gl(D.ptr), sc.L, D.A.grid, sh);
 }
 
 // Rows [l n / G, (l+1) n / G) of a system for elementwise work on A's map.
@@ -415,10 +453,11 @@ template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_finalize(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
-  const TV al = (TV)D.st[0].alpha;
+  GLOBAL const State &S = gl(D.st)[0];
+  const TV al = (TV)S.alpha;
   if (al == (TV)0) return;
-  TV *__restrict__ x = (TV *)D.x;
-  const TV *__restrict__ dc = (const TV *)(((D.st[0].iter - 1) & 1) ? D.d1 : D.d0);
+  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
+  GLOBAL const TV *__restrict__ dc = gl((const TV *)(((S.iter - 1) & 1) ? D.d1 : D.d0));
   int64_t i0, i1;
   ew_rows(D.n, m.y, D.A.grid, i0, i1);
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) x[i] = x[i] + al * dc[i];
@@ -429,9 +468,9 @@ __global__ __launch_bounds__(kBlock) void k_zero_dirs(const SysDev *__restrict__
                                                       int zero_x) {
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
-  TV *__restrict__ d0 = (TV *)D.d0;
-  TV *__restrict__ d1 = (TV *)D.d1;
-  TV *__restrict__ x = (TV *)D.x;
+  GLOBAL TV *__restrict__ d0 = gl((TV *)D.d0);
+  GLOBAL TV *__restrict__ d1 = gl((TV *)D.d1);
+  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
   int64_t i0, i1;
   ew_rows(D.n, m.y, D.A.grid, i0, i1);
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
@@ -450,17 +489,17 @@ __global__ __launch_bounds__(kBlock) void k_outer(const SysDev *__restrict__ dir
                                                   int what) {
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
-  const double rn = sqrt(D.st[0].true_rr);
+  const double rn = sqrt(gl(D.st)[0].true_rr);
   int64_t i0, i1;
   ew_rows(D.n, m.y, D.A.grid, i0, i1);
   if (what == 0) {
-    double *__restrict__ x64 = (double *)D.x;
-    const TV *__restrict__ c = (const TV *)D.s;
+    GLOBAL double *__restrict__ x64 = gl((double *)D.x);
+    GLOBAL const TV *__restrict__ c = gl((const TV *)D.s);
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) x64[i] = x64[i] + rn * (double)c[i];
   } else {
     const double sc = 1.0 / rn;
-    const double *__restrict__ r64 = (const double *)D.r0;
-    TV *__restrict__ bi = (TV *)D.t;
+    GLOBAL const double *__restrict__ r64 = gl((const double *)D.r0);
+    GLOBAL TV *__restrict__ bi = gl((TV *)D.t);
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) bi[i] = (TV)(sc * r64[i]);
   }
 }
@@ -468,13 +507,13 @@ __global__ __launch_bounds__(kBlock) void k_outer(const SysDev *__restrict__ dir
 // One thread per system of the set.
 __global__ void k_state_clear_alpha(const SysDev *__restrict__ dir, const int32_t *__restrict__ set, int nset) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nset) dir[set[k]].st[0].alpha = 0.0;
+  if (k < nset) gl(dir[set[k]].st)[0].alpha = 0.0;
 }
 
 __global__ void k_state_restart(const SysDev *__restrict__ dir, const int32_t *__restrict__ set, int nset) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nset) return;
-  State &S = dir[set[k]].st[0];
+  GLOBAL State &S = gl(dir[set[k]].st)[0];
   S.done = 0;
   S.status = ST_RUNNING;
   S.alpha = 0.0;
@@ -486,14 +525,14 @@ __global__ __launch_bounds__(kBlock) void k_norm_b(const SysDev *__restrict__ di
   __shared__ double sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
-  const TV *__restrict__ b = (const TV *)D.b;
+  GLOBAL const TV *__restrict__ b = gl((const TV *)D.b);
   double part[1] = {0.0};
   // local workgroup l adds the contiguous slice l of b; the order is fixed
   const int G = D.gB, l = m.y;
   const int64_t i0 = (int64_t)l * D.n / G, i1 = (int64_t)(l + 1) * D.n / G;
 #pragma unroll 8
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) part[0] += (double)b[i] * (double)b[i];
-  put_partials<1>(part, D.pb, l, G, sh);
+  put_partials<1>(part, gl(D.pb), l, G, sh);
 }
 
 // One workgroup per system of the set: ||b||^2 (what = 0, also tol * ||b||
@@ -504,11 +543,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce_state(const SysDev *__restric
   const SysDev &D = dir[set[blockIdx.x]];
   double v[1];
   if (what == 0)
-    sum_partials<1>(D.pb, D.gB, v, sh);
+    sum_partials<1>(gl(D.pb), D.gB, v, sh);
   else
-    sum_partials<1>(D.ptr, D.A.grid, v, sh);
+    sum_partials<1>(gl(D.ptr), D.A.grid, v, sh);
   if (threadIdx.x != 0) return;
-  State &S = D.st[0];
+  GLOBAL State &S = gl(D.st)[0];
   if (what == 0) {
     S.bb = v[0];
     S.tol_nb = S.tol * sqrt(v[0]);

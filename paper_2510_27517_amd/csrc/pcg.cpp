@@ -725,8 +725,17 @@ int store_vec(pcg_ctx *ctx, const void *src, int dtype, double *dst, int on_devi
   return PCG_OK;
 }
 
+// Relative tolerance of the next inner solve: the configured one, but no
+// tighter than what brings ||r64|| from rn to a quarter of the target tol*nb
+// (the margin covers the gap between the inner solve's recurrence residual
+// and the FP64 residual), and never looser than 1/2.
+double inner_tolerance(double cfg_inner_tol, double tol, double nb, double rn) {
+  const double base = cfg_inner_tol > 0 ? cfg_inner_tol : 1e-4;
+  return std::min(0.5, std::max(base, 0.25 * tol * nb / rn));
+}
+
 // FP64 iterative refinement: r64 = b - A64 x64 in FP64; inner PCG on
-// A c = r64 / ||r64|| to inner_tol; x64 += ||r64|| c.
+// A c = r64 / ||r64|| to the inner tolerance; x64 += ||r64|| c.
 int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
   Sys &S = ctx->single;
   const int32_t n = S.n;
@@ -741,7 +750,6 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
   HIPCHK(pcgk::launch_norm_b(t64, L64, s));
   int total_iters = 0, outer = 0, restarts = 0, status = PCG_NOT_CONVERGED;
   double prev = INFINITY, relres = NAN, last_rec = NAN;
-  const double inner_tol = ctx->cfg.inner_tol > 0 ? ctx->cfg.inner_tol : 1e-4;
   const int max_outer = ctx->cfg.max_outer > 0 ? ctx->cfg.max_outer : 30;
   State *hst = ctx->h_states + 2 * kSlot64;
   for (;;) {
@@ -774,7 +782,7 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
     HIPCHK(pcgk::launch_convert(pcgk::F64, S.dev64.r0, ctx->ty.vec, S.dev.b, n, 1.0 / rn, s));
     HIPCHK(pcgk::launch_fill(ctx->ty.vec, S.dev.x, n, 0.0, s));
     CoreOut co;
-    int rc = solve_core(ctx, inner_tol, maxit, co, false);
+    int rc = solve_core(ctx, inner_tolerance(ctx->cfg.inner_tol, tol, nb, rn), maxit, co, false);
     if (rc) return rc;
     total_iters += co.iters;
     restarts += co.restarts;
@@ -1051,12 +1059,13 @@ void finish_refined(pcg_ctx *ctx, Req &R, int status) {
 int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vector<std::shared_ptr<Req>> &cont) {
   hipStream_t s = ctx->stream;
   const int max_outer = ctx->cfg.max_outer > 0 ? ctx->cfg.max_outer : 30;
-  const double inner_tol = ctx->cfg.inner_tol > 0 ? ctx->cfg.inner_tol : 1e-4;
   std::vector<int> slots, slots64;
   std::vector<std::shared_ptr<Req>> go;
+  std::vector<double> itol;
   for (auto &R : list) {
     const State h = ctx->h_states[2 * R->slot64];
     int status = 1;  // continue
+    double next_tol = 0.0;
     if (h.bb == 0.0) {
       HIPCHK(pcgk::launch_fill(pcgk::F64, R->sys.dev64.x, R->n, 0.0, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -1073,6 +1082,7 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
         status = PCG_NOT_CONVERGED;
       else
         R->prev_rn = rn;
+      next_tol = inner_tolerance(ctx->cfg.inner_tol, R->tol, nb, rn);
     }
     if (status != 1) {
       int rc = retire(ctx, *R);
@@ -1082,6 +1092,7 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
       continue;
     }
     go.push_back(R);
+    itol.push_back(next_tol);
     slots.push_back(R->slot);
     slots64.push_back(R->slot64);
   }
@@ -1094,7 +1105,7 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
   HIPCHK(pcgk::launch_outer(ctx->ty.vec, h64.L, 1, s));  // inner b = r64 / ||r64||
   HIPCHK(pcgk::launch_zero_dirs(ctx->ty, hin.L, true, s));
   for (size_t i = 0; i < go.size(); ++i) {
-    inits[2 * i] = inits[2 * i + 1] = init_state(ctx, inner_tol, go[i]->maxit, go[i]->sys.g_scale, true);
+    inits[2 * i] = inits[2 * i + 1] = init_state(ctx, itol[i], go[i]->maxit, go[i]->sys.g_scale, true);
     HIPCHK(h2d(ctx->d_states + 2 * go[i]->slot, &inits[2 * i], 2 * sizeof(State), s));
   }
   rc = enqueue_start(ctx, ctx->ty, hin.L, ctx->cfg.eps != 0.0);
