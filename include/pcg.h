@@ -57,6 +57,14 @@ extern "C" {
 #define PCG_G_FIXED 2    /* lower G on tril(A): G_ii = 1/sqrt(A_ii), G_ij = -0.25 A_ij / sqrt(A_ii A_jj) */
 #define PCG_G_JACOBI 3   /* G = D^-1/2, so M^-1 = D^-1 */
 #define PCG_G_IDENTITY 4 /* G = I: plain CG */
+/* Seeded G on A's full pattern, standing in for a learned G of that shape
+ * (Sec. 3.2.2): G_ii = 1/sqrt(A_ii) and, for j != i,
+ * G_ij = 0.25 u_ij |A_ij| / sqrt(A_ii A_jj) with u_ij = 2 U - 1, U the draw at
+ * index i*n + j of stream 3 of the SplitMix64 counter generator keyed by the
+ * seed (Steele, Lea and Flood 2014: key = mix(mix(seed + GAMMA) + 4 GAMMA),
+ * draw k = mix(key + (k + 1) GAMMA), U = ((draw >> 11) + 1) 2^-53). G G^T is
+ * not guaranteed SPD for every A: use it with eps > 0, e.g. 1e-4 / mean|A_ij|. */
+#define PCG_G_SEEDED 5
 
 /* operators for pcg_matvec */
 #define PCG_OP_A 0    /* y = A x */
@@ -111,6 +119,7 @@ typedef struct {
   const int32_t *g_col;
   const double *g_val;
   int g_kind;                /* ... or built on the host by this kind (PCG_G_FSAI, ...) */
+  uint64_t g_seed;           /* seed of PCG_G_SEEDED */
   const double *b;           /* right-hand side, n entries */
   double *x;                 /* x0 on submission (NULL: zeros); the solution is written here on completion */
   double tol;
@@ -139,9 +148,10 @@ int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr,
                     const double *val, int on_device);
 
 /* Builds G from the current A on the host (PCG_G_FSAI, PCG_G_FIXED,
- * PCG_G_JACOBI, PCG_G_IDENTITY) and sets it. A must have been set from host
- * memory or will be downloaded once. */
-int pcg_build_precond(pcg_ctx *ctx, int kind);
+ * PCG_G_JACOBI, PCG_G_IDENTITY, PCG_G_SEEDED with `seed`; the seed is ignored
+ * by the other kinds) and sets it. A must have been set from host memory or
+ * will be downloaded once. */
+int pcg_build_precond(pcg_ctx *ctx, int kind, uint64_t seed);
 
 /* Solves A x = b by PCG (Algorithm 1) to ||b - A x|| <= tol ||b||, at most
  * maxit iterations (per refinement step under refinement). x holds x0 on
@@ -209,9 +219,10 @@ int pcg_validate_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int32_
 /* Number of nonzeros of G for kind on A's pattern (-1 on error). */
 int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col);
 
-/* Builds G of kind from A into caller arrays sized n+1 / pcg_g_nnz. */
-int pcg_build_g_host(int kind, int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
-                     int32_t *g_rowptr, int32_t *g_col, double *g_val);
+/* Builds G of kind (seed: PCG_G_SEEDED only) from A into caller arrays sized
+ * n+1 / pcg_g_nnz. */
+int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, const int32_t *col,
+                     const double *val, int32_t *g_rowptr, int32_t *g_col, double *g_val);
 
 /* Algorithmic device bytes of one PCG iteration: A, G^T and G read once,
  * their row pointers, and 12 vector streams of n entries (vec bytes each). */

@@ -241,6 +241,36 @@ def g_cfg1(A) -> Mat:
     return Mat(grp, gci, gv)
 
 
+def seeded_g(A, seed: int) -> Mat:
+    """Seeded G on A's full pattern, a stand-in for a learned G of that shape
+    (Sec. 3.2.2: the learned G keeps A's sparsity): G_ii = 1/sqrt(A_ii); for
+    j != i, G_ij = 0.25 u_ij |A_ij| / sqrt(A_ii A_jj), u_ij = 2U - 1 with U the
+    draw at index i*n + j of the preconditioner stream (taken from the shared
+    input generator, which holds none of the method's arithmetic)."""
+    from paper_2510_27517_amd import inputs
+
+    A = _mat(A)
+    n = A.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.rowptr))
+    cols = A.col.astype(np.int64)
+    diag = np.zeros(n)
+    on = rows == cols
+    diag[rows[on]] = A.val[on]
+    if not np.all(diag > 0):
+        raise ValueError("seeded_g needs a positive stored diagonal")
+    u = 2.0 * inputs.u01_at(seed, inputs.STREAM_G, rows * n + cols) - 1.0
+    val = 0.25 * u * np.abs(A.val) / np.sqrt(diag[rows] * diag[cols])
+    val[on] = 1.0 / np.sqrt(diag[rows[on]])
+    return Mat(A.rowptr.copy(), A.col.copy(), val)
+
+
+def eps_shift(A, rel: float = 1e-4) -> float:
+    """Absolute shift of M^-1 = G G^T + eps I for a G normalised to A's scale:
+    the paper's relative shift (1e-4, Sec. 3.2.1) over the mean |A_ij|."""
+    A = _mat(A)
+    return rel / float(np.mean(np.abs(A.val)))
+
+
 def identity(n: int) -> Mat:
     return Mat(np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
 

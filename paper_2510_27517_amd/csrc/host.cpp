@@ -101,6 +101,7 @@ uint16_t to_f16_bits(double v) {
 
 int64_t g_nnz(int kind, int32_t n, const int32_t *rp, const int32_t *ci) {
   if (kind == PCG_G_JACOBI || kind == PCG_G_IDENTITY) return n;
+  if (kind == PCG_G_SEEDED) return rp[n];
   if (kind != PCG_G_FSAI && kind != PCG_G_FIXED) return -1;
   int64_t c = 0;
   for (int32_t i = 0; i < n; ++i)
@@ -162,9 +163,52 @@ int fsai_rows(int32_t r0, int32_t r1, const int32_t *rp, const int32_t *ci, cons
   return PCG_OK;
 }
 
+// SplitMix64 (Steele, Lea and Flood 2014) used as a counter generator: draw
+// k of stream `stream` under `seed` is mix(key + (k + 1) GAMMA) with
+// key = mix(mix(seed + GAMMA) + (stream + 1) GAMMA); U(0,1] from its top 53 bits.
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ULL;
+constexpr uint64_t kStreamG = 3;  // stream of the seeded preconditioner's draws
+
+inline uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+inline double sm_u01(uint64_t key, uint64_t k) {
+  return (double)((sm_mix(key + (k + 1) * kGamma) >> 11) + 1) * 0x1.0p-53;
+}
+
+// Seeded G on A's full pattern (stand-in for a learned G of that shape).
+int build_seeded(uint64_t seed, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                 std::vector<int32_t> &grp, std::vector<int32_t> &gci, std::vector<double> &gv) {
+  std::vector<double> dg(n, 0.0);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) dg[i] = v[k];
+  for (int32_t i = 0; i < n; ++i)
+    if (!(dg[i] > 0.0)) return PCG_EINVAL;
+  const uint64_t key = sm_mix(sm_mix(seed + kGamma) + (kStreamG + 1) * kGamma);
+  grp.assign(rp, rp + n + 1);
+  gci.assign(ci, ci + rp[n]);
+  gv.resize(rp[n]);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int32_t j = ci[k];
+      if (j == i) {
+        gv[k] = 1.0 / std::sqrt(dg[i]);
+      } else {
+        const double u = 2.0 * sm_u01(key, (uint64_t)i * (uint64_t)n + (uint64_t)j) - 1.0;
+        gv[k] = 0.25 * u * std::fabs(v[k]) / std::sqrt(dg[i] * dg[j]);
+      }
+    }
+  return PCG_OK;
+}
+
 // Builds G (CSR) for `kind`; for the lower kinds also returns G^T directly.
-int build_g(int kind, int32_t n, const int32_t *rp, const int32_t *ci, const double *v, std::vector<int32_t> &grp,
-            std::vector<int32_t> &gci, std::vector<double> &gv) {
+int build_g(int kind, uint64_t seed, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+            std::vector<int32_t> &grp, std::vector<int32_t> &gci, std::vector<double> &gv) {
+  if (kind == PCG_G_SEEDED) return build_seeded(seed, n, rp, ci, v, grp, gci, gv);
   if (kind == PCG_G_JACOBI || kind == PCG_G_IDENTITY) {
     grp.resize(n + 1);
     gci.resize(n);
@@ -269,14 +313,14 @@ int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col
   return pcgh::g_nnz(kind, n, rowptr, col);
 }
 
-int pcg_build_g_host(int kind, int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
-                     int32_t *g_rowptr, int32_t *g_col, double *g_val) {
+int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, const int32_t *col,
+                     const double *val, int32_t *g_rowptr, int32_t *g_col, double *g_val) {
   if (n <= 0 || !rowptr || !col || !val || !g_rowptr || !g_col || !g_val) return PCG_EINVAL;
   int rc = pcgh::validate_csr(n, rowptr[n], rowptr, col, 1, nullptr);
   if (rc) return rc;
   std::vector<int32_t> grp, gci;
   std::vector<double> gv;
-  rc = pcgh::build_g(kind, n, rowptr, col, val, grp, gci, gv);
+  rc = pcgh::build_g(kind, seed, n, rowptr, col, val, grp, gci, gv);
   if (rc) return rc;
   std::memcpy(g_rowptr, grp.data(), sizeof(int32_t) * grp.size());
   std::memcpy(g_col, gci.data(), sizeof(int32_t) * gci.size());

@@ -24,8 +24,8 @@ uint16_t to_f16_bits(double v);
 // Nonzeros of G for a preconditioner kind on A's pattern (-1: unknown kind).
 int64_t g_nnz(int kind, int32_t n, const int32_t *rp, const int32_t *ci);
 
-// G (CSR) for a preconditioner kind built from A.
-int build_g(int kind, int32_t n, const int32_t *rp, const int32_t *ci, const double *v, std::vector<int32_t> &grp,
+// G (CSR) for a preconditioner kind built from A (seed: PCG_G_SEEDED).
+int build_g(int kind, uint64_t seed, int32_t n, const int32_t *rp, const int32_t *ci, const double *v, std::vector<int32_t> &grp,
             std::vector<int32_t> &gci, std::vector<double> &gv);
 
 // Row-block partition: (row start, nonzero start) pairs, nblk + 1 of them.

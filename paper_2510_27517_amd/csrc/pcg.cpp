@@ -382,6 +382,7 @@ struct Req {
   std::vector<int32_t> a_rp, a_ci, g_rp, g_ci;
   std::vector<double> a_val, g_val, b, x0;
   int g_kind = PCG_G_FSAI;
+  uint64_t g_seed = 0;
   bool g_given = false;
   double tol = 1e-8;
   int maxit = 1000;
@@ -817,7 +818,7 @@ void prep_request(const pcg_config &cfg, int cus, Req &R) {
     gci.swap(R.g_ci);
     gv.swap(R.g_val);
   } else {
-    int rc = pcgh::build_g(R.g_kind, R.n, R.a_rp.data(), R.a_ci.data(), R.a_val.data(), grp, gci, gv);
+    int rc = pcgh::build_g(R.g_kind, R.g_seed, R.n, R.a_rp.data(), R.a_ci.data(), R.a_val.data(), grp, gci, gv);
     if (rc) {
       R.prep_rc = rc;
       return;
@@ -1280,6 +1281,7 @@ int copy_request(pcg_ctx *ctx, const pcg_system &S, std::shared_ptr<Req> &out) {
       return PCG_EINVAL;
     }
     R->g_kind = S.g_kind;
+    R->g_seed = S.g_seed;
   }
   out = R;
   return PCG_OK;
@@ -1501,7 +1503,7 @@ int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr,
   return set_g_from_host(ctx, hrp, hci, hv);
 }
 
-int pcg_build_precond(pcg_ctx *ctx, int kind) {
+int pcg_build_precond(pcg_ctx *ctx, int kind, uint64_t seed) {
   if (!ctx) return PCG_EINVAL;
   if (!ctx->have_a) {
     ctx->err = "pcg_build_precond: set the matrix first";
@@ -1509,7 +1511,7 @@ int pcg_build_precond(pcg_ctx *ctx, int kind) {
   }
   std::vector<int32_t> grp, gci;
   std::vector<double> gv;
-  int rc = pcgh::build_g(kind, ctx->single.n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), grp, gci, gv);
+  int rc = pcgh::build_g(kind, seed, ctx->single.n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), grp, gci, gv);
   if (rc) {
     ctx->err = "pcg_build_precond: construction failed (kind or matrix not SPD)";
     return rc;

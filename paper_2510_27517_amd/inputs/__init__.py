@@ -72,6 +72,7 @@ def _load():
     lib.gen_normal.restype = dbl
     lib.gen_normal.argtypes = [u64, u64, u64]
     lib.gen_u01_vec.argtypes = [u64, u64, i64, P]
+    lib.gen_u01_at.argtypes = [u64, u64, i64, P, P]
     lib.gen_normal_vec.argtypes = [u64, u64, i64, P]
     lib.gen_poisson_nnz.restype = i64
     lib.gen_poisson_nnz.argtypes = [i32, i64]
@@ -147,6 +148,14 @@ def bits(seed: int, stream: int, i: int) -> int:
 def u01(seed: int, stream: int, n: int) -> np.ndarray:
     out = np.empty(n, np.float64)
     _load().gen_u01_vec(seed, stream, n, _ptr(out))
+    return out
+
+
+def u01_at(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
+    """u01 draws at the given (non-negative) indices of a stream."""
+    ix = np.ascontiguousarray(idx, dtype=np.uint64)
+    out = np.empty(ix.shape[0], np.float64)
+    _load().gen_u01_at(seed, stream, ix.shape[0], _ptr(ix), _ptr(out))
     return out
 
 

@@ -59,6 +59,12 @@ void gen_u01_vec(uint64_t seed, uint64_t stream, int64_t n, double *out) {
   for (int64_t i = 0; i < n; ++i) out[i] = u01_k(key, (uint64_t)i);
 }
 
+/* Draws at arbitrary indices: out[k] = u01(seed, stream, idx[k]). */
+void gen_u01_at(uint64_t seed, uint64_t stream, int64_t n, const uint64_t *idx, double *out) {
+  uint64_t key = gen_key(seed, stream);
+  for (int64_t k = 0; k < n; ++k) out[k] = u01_k(key, idx[k]);
+}
+
 void gen_normal_vec(uint64_t seed, uint64_t stream, int64_t n, double *out) {
   uint64_t key = gen_key(seed, stream);
   for (int64_t i = 0; i < n; ++i) out[i] = normal_k(key, (uint64_t)i);

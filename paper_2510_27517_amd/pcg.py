@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libpcg.so")
 OK, PENDING, NOT_CONVERGED = 0, 1, 2
 EINVAL, ESTATE, ENOMEM, EBREAKDOWN, EDEVICE = -1, -2, -3, -4, -5
 F64, F32, BF16, F16 = 0, 1, 2, 3
-G_FSAI, G_FIXED, G_JACOBI, G_IDENTITY = 1, 2, 3, 4
+G_FSAI, G_FIXED, G_JACOBI, G_IDENTITY, G_SEEDED = 1, 2, 3, 4, 5
 OP_A, OP_GT, OP_G, OP_MINV = 0, 1, 2, 3
 
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
@@ -61,7 +61,7 @@ class System(ctypes.Structure):
         ("n", ctypes.c_int32), ("nnz_a", ctypes.c_int64), ("a_rowptr", ctypes.c_void_p),
         ("a_col", ctypes.c_void_p), ("a_val", ctypes.c_void_p), ("nnz_g", ctypes.c_int64),
         ("g_rowptr", ctypes.c_void_p), ("g_col", ctypes.c_void_p), ("g_val", ctypes.c_void_p),
-        ("g_kind", ctypes.c_int), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("tol", ctypes.c_double),
+        ("g_kind", ctypes.c_int), ("g_seed", ctypes.c_uint64), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("tol", ctypes.c_double),
         ("maxit", ctypes.c_int),
     ]
 
@@ -85,13 +85,13 @@ def load():
     lib.pcg_destroy.restype = None
     lib.pcg_set_matrix.argtypes = [P, i32, i64, P, P, P, c_int]
     lib.pcg_set_precond.argtypes = [P, i32, i64, P, P, P, c_int]
-    lib.pcg_build_precond.argtypes = [P, c_int]
+    lib.pcg_build_precond.argtypes = [P, c_int, ctypes.c_uint64]
     lib.pcg_solve.argtypes = [P, P, P, dbl, c_int, c_int, ctypes.POINTER(Result)]
     lib.pcg_matvec.argtypes = [P, c_int, P, P, c_int]
     lib.pcg_validate_csr.argtypes = [i32, i64, P, P, c_int]
     lib.pcg_g_nnz.argtypes = [c_int, i32, P, P]
     lib.pcg_g_nnz.restype = i64
-    lib.pcg_build_g_host.argtypes = [c_int, i32, P, P, P, P, P, P]
+    lib.pcg_build_g_host.argtypes = [c_int, ctypes.c_uint64, i32, P, P, P, P, P, P]
     lib.pcg_bytes_per_iter.argtypes = [i32, i64, i64, c_int, c_int, c_int]
     lib.pcg_bytes_per_iter.restype = dbl
     lib.pcg_time_kernels.argtypes = [P, c_int, P, P]
@@ -149,7 +149,7 @@ def validate_csr(rowptr, col, n=None, require_diag=True) -> int:
     return int(load().pcg_validate_csr(n, ci.shape[0], rp.ctypes.data, ci.ctypes.data, int(require_diag)))
 
 
-def build_g_host(kind: int, A):
+def build_g_host(kind: int, A, seed: int = 0):
     """G of `kind` from A, built by the library's host code: (rowptr, col, val)."""
     lib = load()
     rp, ci, v = _host(A.rowptr, np.int32), _host(A.col, np.int32), _host(A.val, np.float64)
@@ -160,7 +160,7 @@ def build_g_host(kind: int, A):
     grp = np.empty(n + 1, np.int32)
     gci = np.empty(m, np.int32)
     gv = np.empty(m, np.float64)
-    st = lib.pcg_build_g_host(kind, n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, grp.ctypes.data,
+    st = lib.pcg_build_g_host(kind, int(seed), n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, grp.ctypes.data,
                               gci.ctypes.data, gv.ctypes.data)
     if st != OK:
         raise PCGError(st, "pcg_build_g_host")
@@ -253,8 +253,8 @@ class Solver:
         n, nnz, prp, pci, pv, dev, _keep = self._csr_args(rowptr, col, val)
         self._check(self._lib.pcg_set_precond(self._h, n, nnz, prp, pci, pv, dev), "pcg_set_precond")
 
-    def build_precond(self, kind: int = G_FSAI):
-        self._check(self._lib.pcg_build_precond(self._h, kind), "pcg_build_precond")
+    def build_precond(self, kind: int = G_FSAI, seed: int = 0):
+        self._check(self._lib.pcg_build_precond(self._h, kind, int(seed)), "pcg_build_precond")
 
     def solve(self, b, x0=None, *, tol=1e-8, maxit=2000, allow_failure=False) -> SolveOut:
         """Solve A x = b; returns the solution (same kind of array as b)."""
@@ -285,7 +285,7 @@ class Solver:
 
     # ------------------------------------------------------- batch / serving
 
-    def _system(self, A, b, x0=None, G=None, g_kind=G_FSAI, tol=1e-8, maxit=2000):
+    def _system(self, A, b, x0=None, G=None, g_kind=G_FSAI, g_seed=0, tol=1e-8, maxit=2000):
         keep = [_host(A.rowptr, np.int32), _host(A.col, np.int32), _host(A.val, np.float64),
                 _host(b, np.float64)]
         x = np.zeros(keep[0].shape[0] - 1) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -300,6 +300,7 @@ class Solver:
             sysd.nnz_g = g[1].shape[0]
             sysd.g_rowptr, sysd.g_col, sysd.g_val = g[0].ctypes.data, g[1].ctypes.data, g[2].ctypes.data
         sysd.g_kind = g_kind
+        sysd.g_seed = int(g_seed)
         sysd.b = keep[3].ctypes.data
         sysd.x = x.ctypes.data
         sysd.tol = float(tol)
@@ -307,7 +308,7 @@ class Solver:
         return sysd, keep, x
 
     def submit(self, systems):
-        """Queue systems (dicts with A, b and optional x0, G, g_kind, tol,
+        """Queue systems (dicts with A, b and optional x0, G, g_kind, g_seed, tol,
         maxit); returns their tickets. Inputs are copied by the library; the
         solution arrays stay owned here until the ticket finishes."""
         if not hasattr(self, "_pending"):

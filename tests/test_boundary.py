@@ -84,6 +84,16 @@ def test_library_fixed_g_matches_oracle_exactly():
     assert np.array_equal(grp, G.rowptr) and np.array_equal(gci, G.col) and np.array_equal(gv, G.val)
 
 
+@pytest.mark.parametrize("case", ["poisson3d", "rgg", "elasticity"])
+def test_library_seeded_g_matches_oracle_exactly(case):
+    A = {"poisson3d": lambda: inputs.poisson(3, 9, 1.0, 3), "rgg": lambda: inputs.rgg_laplacian(3000, 2),
+         "elasticity": lambda: inputs.elasticity(4, 1.0)}[case]()
+    for seed in (0, 2**40 + 9):
+        grp, gci, gv = pcg.build_g_host(pcg.G_SEEDED, A, seed)
+        G = oracle.seeded_g(A, seed)
+        assert np.array_equal(grp, G.rowptr) and np.array_equal(gci, G.col) and np.array_equal(gv, G.val)
+
+
 def test_library_jacobi_identity():
     A = inputs.poisson(3, 4, 1.0, 1)
     grp, gci, gv = pcg.build_g_host(pcg.G_JACOBI, A)

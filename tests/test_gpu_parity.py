@@ -81,13 +81,14 @@ def test_operator_products_bitwise(gpu_lib, case):
         assert np.array_equal(s.matvec(pcg.OP_MINV, x), oracle.apply_precond(G, x, eps))
 
 
-def _parity(pcg, A, kind, b, *, tol=1e-8, maxit=2000, eps=0.0, rr=50, graph=10, x0=None):
+def _parity(pcg, A, kind, b, *, tol=1e-8, maxit=2000, eps=0.0, rr=50, graph=10, x0=None, seed=0):
     with _solver(pcg, eps=eps, rr_period=rr, graph_iters=graph) as s:
         s.set_matrix(A)
-        s.build_precond(kind)
+        s.build_precond(kind, seed)
         got = s.solve(b, x0, tol=tol, maxit=maxit)
     G = {pcg.G_FSAI: oracle.fsai_g, pcg.G_FIXED: oracle.g_cfg1, pcg.G_JACOBI: oracle.diag_inv_sqrt,
-         pcg.G_IDENTITY: lambda A: oracle.identity(A.n)}[kind](A)
+         pcg.G_IDENTITY: lambda A: oracle.identity(A.n),
+         pcg.G_SEEDED: lambda A: oracle.seeded_g(A, seed)}[kind](A)
     ref = oracle.pcg(A, G, b, x0, eps=eps, tol=tol, maxit=maxit, rr_period=rr, delta_form=1)
     return got, ref
 
@@ -130,6 +131,20 @@ def test_pcg_fsai_rgg(gpu_lib):
     say("pcg fsai rgg 20000")
     got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=1e-8, maxit=5000)
     _check(got, ref)
+
+
+@pytest.mark.parametrize("case", ["poisson3d", "rgg"])
+def test_pcg_seeded_full_pattern_g_with_shift(gpu_lib, case):
+    """G on A's full pattern (the learned preconditioner's shape) with the
+    shift eps = 1e-4 / mean|A_ij|: both products run over the full pattern."""
+    pcg = gpu_lib
+    A = inputs.poisson(3, 20, 1.0, 6) if case == "poisson3d" else inputs.rgg_laplacian(15000, 6)
+    b = inputs.rhs(A.n, 6)
+    eps = oracle.eps_shift(A)
+    say("pcg seeded G", case, A.n, "eps", eps)
+    got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=1e-8, maxit=5000)
+    _check(got, ref)
+    assert got.status == pcg.OK
 
 
 def test_pcg_random_spd_long_rows(gpu_lib):

@@ -31,6 +31,17 @@ def test_counter_generator_matches_definition(seed, stream):
         assert u[i] == ((v >> 11) + 1) * 2.0 ** -53
 
 
+def test_indexed_draws_match_definition():
+    seed, stream = 11, 3
+    key = _mix((_mix((seed + GAMMA) & MASK) + (stream + 1) * GAMMA) & MASK)
+    idx = np.array([0, 5, 2**33 + 7, 123456789012, 3], np.uint64)
+    got = inputs.u01_at(seed, stream, idx)
+    for k, i in enumerate(idx.tolist()):
+        v = _mix((key + (i + 1) * GAMMA) & MASK)
+        assert got[k] == ((v >> 11) + 1) * 2.0 ** -53
+    assert np.array_equal(inputs.u01_at(seed, stream, np.arange(50)), inputs.u01(seed, stream, 50))
+
+
 def test_normal_moments_and_determinism():
     z = inputs.normal(0, inputs.STREAM_B, 200_000)
     assert abs(z.mean()) < 4 / np.sqrt(z.size)

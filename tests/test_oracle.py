@@ -384,3 +384,67 @@ def test_residual_replacement_schedule(period):
     assert replaced >= 2
     if period > 1:
         assert updated >= 3
+
+
+# ------------------------------------------------------- seeded full-pattern G
+
+def _u_from_definition(seed, i, j, n):
+    """2U - 1 for draw index i*n + j of the preconditioner stream, computed
+    here from the SplitMix64 definition (not through the input module)."""
+    MASK, GAMMA = (1 << 64) - 1, 0x9E3779B97F4A7C15
+
+    def mix(z):
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
+        return z ^ (z >> 31)
+
+    key = mix((mix((seed + GAMMA) & MASK) + 4 * GAMMA) & MASK)  # stream 3
+    v = mix((key + (int(i) * int(n) + int(j) + 1) * GAMMA) & MASK)
+    return 2.0 * (((v >> 11) + 1) * 2.0 ** -53) - 1.0
+
+
+def test_seeded_g_definition():
+    """Full pattern of A; G_ii = 1/sqrt(A_ii) exactly; G_ij equals
+    0.25 u_ij |A_ij| / sqrt(A_ii A_jj) with u_ij from the generator's
+    definition at index i*n + j; a different seed changes every off-diagonal
+    entry; the draws are spread over (-1, 1]."""
+    assert inputs.STREAM_G == 3
+    A = inputs.poisson(2, 12, 1.0, 5)
+    G = oracle.seeded_g(A, 42)
+    assert np.array_equal(G.rowptr, A.rowptr) and np.array_equal(G.col, A.col)
+    d = A.to_dense().diagonal()
+    us = []
+    for i in range(A.n):
+        for k in range(A.rowptr[i], A.rowptr[i + 1]):
+            j = A.col[k]
+            if j == i:
+                assert G.val[k] == 1.0 / np.sqrt(d[i])
+            else:
+                u = _u_from_definition(42, i, j, A.n)
+                assert -1.0 < u <= 1.0
+                assert G.val[k] == pytest.approx(0.25 * u * abs(A.val[k]) / np.sqrt(d[i] * d[j]), rel=1e-15)
+                us.append(u)
+    us = np.array(us)
+    assert abs(us.mean()) < 0.1 and abs(us.var() - 1 / 3) < 0.05
+    G2 = oracle.seeded_g(A, 43)
+    off = A.col != np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    assert np.all(G2.val[off] != G.val[off]) and np.array_equal(G2.val[~off], G.val[~off])
+
+
+def test_seeded_g_with_shift_solves_to_dense_solution():
+    """With the shift eps = 1e-4 / mean|A_ij|, M^-1 = G G^T + eps I is SPD and
+    PCG reaches the dense solution; the shift helper is that ratio."""
+    A = inputs.rgg_laplacian(400, 8)
+    b = inputs.rhs(A.n, 8)
+    eps = oracle.eps_shift(A)
+    assert eps == 1e-4 / np.mean(np.abs(A.val))
+    G = oracle.seeded_g(A, 1)
+    Gd = np.zeros((A.n, A.n))
+    for i in range(A.n):
+        Gd[i, G.col[G.rowptr[i]:G.rowptr[i + 1]]] = G.val[G.rowptr[i]:G.rowptr[i + 1]]
+    Minv = Gd @ Gd.T + eps * np.eye(A.n)
+    assert np.linalg.eigvalsh(Minv).min() > 0
+    res = oracle.pcg(A, G, b, eps=eps, tol=1e-12, maxit=5000)
+    xs = np.linalg.solve(A.to_dense(), b)
+    assert res.status == oracle.OK
+    assert np.linalg.norm(res.x - xs) <= 1e-9 * np.linalg.norm(xs)
