@@ -14,7 +14,8 @@ Further sections, each under its own key of the same JSON line:
   batched    512 2D/3D lognormal Poisson systems of uneven size solved as one
              batch (FP32, FP64 refinement, tol 1e-6): solves/s, latency;
   serving    random-geometric-graph Laplacian requests arriving as a Poisson
-             stream at 0.8x the measured closed-loop rate: p50/p99 latency;
+             stream at 0.5, 0.8 and 0.95 of the measured closed-loop rate:
+             p50/p99 latency, queue depth and admitted bytes;
   elasticity Q1 elasticity, 64^3 free nodes x 3 dof (n = 786,432, 61.7M
              nonzeros): BF16/FP16 G with FP64 refinement to 1e-10 against the
              plain FP64 solve.
@@ -187,23 +188,13 @@ def _drain(s, tickets, got):
                 got[t] = r
 
 
-def section_serving(pcg, inputs, count, iters_per_step):
-    log(f"serving: generating {count} requests")
-    reqs = serving_requests(inputs, count)
-    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
-    # closed loop: everything at once, the sustainable rate mu
-    with pcg.Solver(cfg) as s:
-        t0 = time.perf_counter()
-        res = s.solve_batch(reqs, iters_per_step=iters_per_step)
-        wall = time.perf_counter() - t0
-    mu = count / wall
-    lam = 0.8 * mu
-    # open loop: Poisson arrivals at lambda; each request submitted at its
-    # arrival time (to the loop's step granularity)
-    gaps = -np.log(inputs.u01(7, inputs.STREAM_ARRIVALS, count)) / lam
-    arrive = np.cumsum(gaps)
+def _open_loop(pcg, cfg, reqs, arrive, iters_per_step):
+    """Submit each request at its arrival time (to the step granularity) and
+    drive the scheduler; returns latencies (arrival to completion), statuses,
+    the span, and the queue depth and admitted bytes seen after each step."""
+    count = len(reqs)
     got, tickets, sub_lag = {}, [], {}
-    log(f"serving: open loop at {lam:.1f} requests/s")
+    depth, used = [], []
     with pcg.Solver(cfg) as s:
         t0 = time.perf_counter()
         nxt = 0
@@ -221,21 +212,50 @@ def section_serving(pcg, inputs, count, iters_per_step):
                     sub_lag[t] = (now - arrive[i]) * 1e3
             if active or queued or batch:
                 active, queued = s.progress(iters_per_step)
+                depth.append(active + queued)
+                used.append(s.pool_info()[1])
             elif nxt < count:
                 time.sleep(max(0.0, min(0.01, arrive[nxt] - now)))
             _drain(s, tickets, got)
         span = time.perf_counter() - t0
     lat = [got[t][1]["t_latency_ms"] + sub_lag[t] for t in tickets]
     st = [got[t][1]["status"] for t in tickets]
+    rel = max(got[t][1]["relres_true"] for t in tickets)
+    return lat, st, span, depth, used, rel
+
+
+def section_serving(pcg, inputs, count, iters_per_step):
+    log(f"serving: generating {count} requests")
+    reqs = serving_requests(inputs, count)
+    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    # closed loop: everything at once gives the sustainable rate mu
+    with pcg.Solver(cfg) as s:
+        t0 = time.perf_counter()
+        res = s.solve_batch(reqs, iters_per_step=iters_per_step)
+        wall = time.perf_counter() - t0
+    mu = count / wall
     ns = [r["A"].n for r in reqs]
-    return {"workload": f"{count} RGG Laplacian + 1e-3 I requests, n log-uniform [1e3,1e6] (mean {np.mean(ns):.0f}), "
-                        "mean degree ~8, weights U[0.1,10]; f32 A/vectors, bf16 FSAI G, FP64 refinement, tol 1e-6; "
-                        "Poisson arrivals at 0.8x the closed-loop rate",
-            "requests": count, "closed_loop_solves_per_s": round(mu, 2), "arrival_rate": round(lam, 2),
-            "open_loop_solves_per_s": round(count / span, 2), "latency_ms_p50": pct(lat, 50),
-            "latency_ms_p99": pct(lat, 99), "ok": st.count(pcg.OK),
-            "max_relres_true_fp64": max(got[t][1]["relres_true"] for t in tickets),
-            "closed_loop_latency_ms_p99": pct([r["t_latency_ms"] for _, r in res], 99)}
+    out = {"workload": f"{count} RGG Laplacian + 1e-3 I requests, n log-uniform [1e3,1e6] (mean {np.mean(ns):.0f}), "
+                       "mean degree ~8, weights U[0.1,10]; f32 A/vectors, bf16 FSAI G, FP64 refinement, tol 1e-6; "
+                       "Poisson arrivals at 0.5/0.8/0.95 of the closed-loop rate",
+           "requests": count, "closed_loop_solves_per_s": round(mu, 2),
+           "closed_loop_latency_ms_p99": pct([r["t_latency_ms"] for _, r in res], 99), "loads": {}}
+    # open loop: Poisson arrivals (exponential gaps from the arrivals stream)
+    gaps01 = -np.log(inputs.u01(7, inputs.STREAM_ARRIVALS, count))
+    for f in (0.5, 0.8, 0.95):
+        lam = f * mu
+        log(f"serving: open loop at {lam:.1f} requests/s ({f} mu)")
+        lat, st, span, depth, used, rel = _open_loop(pcg, cfg, reqs, np.cumsum(gaps01 / lam), iters_per_step)
+        out["loads"][str(f)] = {
+            "arrival_rate": round(lam, 2), "solves_per_s": round(count / span, 2),
+            "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99), "ok": st.count(pcg.OK),
+            "max_relres_true_fp64": rel, "queue_depth_mean": float(np.mean(depth)) if depth else 0.0,
+            "queue_depth_max": int(max(depth)) if depth else 0,
+            "admitted_mb_mean": float(np.mean(used)) / 2**20 if used else 0.0,
+            "admitted_mb_max": float(max(used)) / 2**20 if used else 0.0}
+    main = out["loads"]["0.8"]
+    out["latency_ms_p50"], out["latency_ms_p99"] = main["latency_ms_p50"], main["latency_ms_p99"]
+    return out
 
 
 def section_elasticity(pcg, inputs, N):

@@ -142,7 +142,13 @@ def test_pcg_seeded_full_pattern_g_with_shift(gpu_lib, case):
     b = inputs.rhs(A.n, 6)
     eps = oracle.eps_shift(A)
     say("pcg seeded G", case, A.n, "eps", eps)
-    got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=1e-8, maxit=5000)
+    # a random (unlearned) G converges slowly, so at 1e-8 the two iterates can
+    # differ by more than 1e-10 from the order of the dot products alone:
+    # compare at a fixed iteration count, and near the exact solution
+    got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=0.0, maxit=25)
+    _check(got, ref)
+    assert got.status == pcg.NOT_CONVERGED and got.iters == 25
+    got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=1e-11, maxit=5000)
     _check(got, ref)
     assert got.status == pcg.OK
 
