@@ -221,7 +221,9 @@ def _open_loop(pcg, cfg, reqs, arrive, iters_per_step):
     lat = [got[t][1]["t_latency_ms"] + sub_lag[t] for t in tickets]
     st = [got[t][1]["status"] for t in tickets]
     rel = max(got[t][1]["relres_true"] for t in tickets)
-    return lat, st, span, depth, used, rel
+    split = {"queue_ms_p50": pct([got[t][1]["t_queue_ms"] for t in tickets], 50),
+             "solve_ms_p50": pct([got[t][1]["t_solve_ms"] for t in tickets], 50)}
+    return lat, st, span, depth, used, rel, split
 
 
 def section_serving(pcg, inputs, count, iters_per_step):
@@ -245,14 +247,16 @@ def section_serving(pcg, inputs, count, iters_per_step):
     for f in (0.5, 0.8, 0.95):
         lam = f * mu
         log(f"serving: open loop at {lam:.1f} requests/s ({f} mu)")
-        lat, st, span, depth, used, rel = _open_loop(pcg, cfg, reqs, np.cumsum(gaps01 / lam), iters_per_step)
+        lat, st, span, depth, used, rel, split = _open_loop(pcg, cfg, reqs, np.cumsum(gaps01 / lam), iters_per_step)
         out["loads"][str(f)] = {
             "arrival_rate": round(lam, 2), "solves_per_s": round(count / span, 2),
             "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99), "ok": st.count(pcg.OK),
             "max_relres_true_fp64": rel, "queue_depth_mean": float(np.mean(depth)) if depth else 0.0,
             "queue_depth_max": int(max(depth)) if depth else 0,
             "admitted_mb_mean": float(np.mean(used)) / 2**20 if used else 0.0,
-            "admitted_mb_max": float(max(used)) / 2**20 if used else 0.0}
+            "admitted_mb_max": float(max(used)) / 2**20 if used else 0.0,
+            "note": "queue = submission to admission (host G construction, staging, waiting for memory); "
+                    "solve = admission to completion", **split}
     main = out["loads"]["0.8"]
     out["latency_ms_p50"], out["latency_ms_p99"] = main["latency_ms_p50"], main["latency_ms_p99"]
     return out

@@ -91,8 +91,21 @@ typedef struct {
   int graph_iters;   /* iterations per captured HIP graph replay (default 10; 0 = plain launches) */
   int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */
   int mem_budget_mb; /* device memory pool for batched / served systems, MiB (0: half the free memory at first use) */
-  int reserved[7];
+  int layout;        /* storage of A, G, G^T: PCG_LAYOUT_AUTO (default), PCG_LAYOUT_CSR or PCG_LAYOUT_SELL */
+  int reserved[6];
 } pcg_config;
+
+/* Matrix storage layouts (pcg_config.layout). Both give bit-identical
+ * products (each row is summed left to right in CSR order).
+ *  CSR:  CSR plus a partition into blocks of up to 256 rows whose products
+ *        fit the workgroup's LDS; any row lengths.
+ *  SELL: sliced ELL, slices of 64 consecutive rows stored column-major and
+ *        padded to the slice's longest row; coalesced loads without LDS.
+ *  AUTO: SELL for a matrix whose padding stays within 1/8 of its nonzeros,
+ *        CSR otherwise. PCG_LAYOUT_SELL still falls back to CSR above 2x. */
+#define PCG_LAYOUT_AUTO 0
+#define PCG_LAYOUT_CSR 1
+#define PCG_LAYOUT_SELL 2
 
 typedef struct {
   int status;          /* PCG_OK, PCG_NOT_CONVERGED or a negative code */

@@ -40,10 +40,13 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")
         path = os.path.join(CSRC, src)
+        # host-only sources hold no device code: plain C++ (still through
+        # hipcc for the HIP runtime headers), so no device target is built
         if src.endswith(".hip"):
             cmd = [HIPCC, *COMMON, *DEVICE, "-c", path, "-o", obj]
         else:
-            cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
+            rocm_inc = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "include")
+            cmd = [HIPCC, *COMMON, "-x", "c++", "-D__HIP_PLATFORM_AMD__", f"-I{rocm_inc}", "-c", path, "-o", obj]
         _run(cmd, verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"

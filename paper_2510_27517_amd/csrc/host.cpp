@@ -294,6 +294,50 @@ std::vector<int32_t> row_blocks(int32_t n, const int32_t *rp, int cap) {
   return blk;
 }
 
+int64_t sell_entries(int32_t n, const int32_t *rp) {
+  int64_t tot = 0;
+  for (int32_t r0 = 0; r0 < n; r0 += kSlice) {
+    int32_t w = 0;
+    for (int32_t r = r0; r < std::min(n, r0 + kSlice); ++r) w = std::max(w, rp[r + 1] - rp[r]);
+    tot += (int64_t)w * kSlice;
+  }
+  return tot;
+}
+
+void sell_offsets(int32_t n, const int32_t *rp, std::vector<int32_t> &so) {
+  const int32_t ns = (n + kSlice - 1) / kSlice;
+  so.assign(ns + 1, 0);
+  for (int32_t c = 0; c < ns; ++c) {
+    int32_t w = 0;
+    for (int32_t r = c * kSlice; r < std::min(n, (c + 1) * kSlice); ++r) w = std::max(w, rp[r + 1] - rp[r]);
+    so[c + 1] = so[c] + w;
+  }
+}
+
+void sell_columns(int32_t n, const int32_t *rp, const int32_t *ci, const std::vector<int32_t> &so,
+                  std::vector<int32_t> &out) {
+  const int32_t ns = (int32_t)so.size() - 1;
+  out.resize((size_t)so[ns] * kSlice);
+  for (int32_t c = 0; c < ns; ++c)
+    for (int32_t l = 0; l < kSlice; ++l) {
+      const int32_t r = c * kSlice + l;
+      const int32_t len = r < n ? rp[r + 1] - rp[r] : 0;
+      for (int32_t k = 0; k < so[c + 1] - so[c]; ++k)
+        out[((size_t)so[c] + k) * kSlice + l] = k < len ? ci[rp[r] + k] : (r < n ? r : 0);
+    }
+}
+
+void sell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, const std::vector<int32_t> &so,
+                std::vector<uint8_t> &out) {
+  const int32_t ns = (int32_t)so.size() - 1;
+  out.assign((size_t)so[ns] * kSlice * esz, 0);
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t c = r / kSlice, l = r % kSlice;
+    for (int32_t k = 0; k < rp[r + 1] - rp[r]; ++k)
+      std::memcpy(&out[(((size_t)so[c] + k) * kSlice + l) * esz], in + (size_t)(rp[r] + k) * esz, esz);
+  }
+}
+
 double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt) {
   const double sa = (double)pcgk::dtype_size(adt), sg = (double)pcgk::dtype_size(gdt),
                sv = (double)pcgk::dtype_size(vdt);
@@ -347,3 +391,5 @@ const char *pcg_strerror(int status) {
 }
 
 }  // extern "C"
+
+static_assert(pcgh::kSlice == pcgk::kSliceRows, "slice height shared by host layout and kernels");

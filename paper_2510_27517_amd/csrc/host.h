@@ -31,6 +31,28 @@ int build_g(int kind, uint64_t seed, int32_t n, const int32_t *rp, const int32_t
 // Row-block partition: (row start, nonzero start) pairs, nblk + 1 of them.
 std::vector<int32_t> row_blocks(int32_t n, const int32_t *rp, int cap);
 
+// Sliced ELL with slices of kSlice consecutive rows: slice c holds
+// so[c+1] - so[c] columns (its longest row); entry k of row 64c + l sits at
+// (so[c] + k) * kSlice + l. Rows keep their CSR order; shorter rows and rows
+// past n are padded with column `pad_col(row)` and value 0.
+constexpr int kSlice = 64;
+
+// Stored entries (nonzeros plus padding) of the sliced layout of a pattern.
+int64_t sell_entries(int32_t n, const int32_t *rp);
+
+// Slice offsets: nslice + 1 of them, in units of kSlice entries.
+void sell_offsets(int32_t n, const int32_t *rp, std::vector<int32_t> &so);
+
+// Columns in sliced order; a padding entry takes its own row as column (0
+// for rows past n), so every gather stays in range.
+void sell_columns(int32_t n, const int32_t *rp, const int32_t *ci, const std::vector<int32_t> &so,
+                  std::vector<int32_t> &out);
+
+// Elements of `esz` bytes in CSR order (`in`) moved to sliced order; padding
+// is all-zero bytes (+0 in every floating-point format).
+void sell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, const std::vector<int32_t> &so,
+                std::vector<uint8_t> &out);
+
 // Algorithmic bytes of one PCG iteration (12 vector streams).
 double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt);
 

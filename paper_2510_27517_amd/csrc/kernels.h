@@ -67,9 +67,19 @@ constexpr int kLdsBytes = PCG_LDS_BYTES;   // LDS staging for row products per w
 
 inline int lds_cap(int vec_dtype) { return kLdsBytes / (int)dtype_size(vec_dtype); }
 
-// A CSR matrix resident on the device, with its row-block partition: block k
-// covers rows [blk[2k], blk[2k+2]) and nonzeros [blk[2k+1], blk[2k+3]),
-// holding at most `lds_cap` nonzeros unless it is a single longer row.
+// Storage layouts of a sparse matrix on the device.
+enum Fmt : int32_t {
+  FMT_CSR = 0,   // CSR with a row-block partition (any row lengths)
+  FMT_SELL = 1,  // sliced ELL, slices of 64 rows (rows of similar length)
+};
+
+// A sparse matrix resident on the device.
+// FMT_CSR: rp/ci/val are CSR; block k covers rows [blk[2k], blk[2k+2]) and
+//   nonzeros [blk[2k+1], blk[2k+3]), holding at most `lds_cap` nonzeros
+//   unless it is a single longer row; nblk blocks.
+// FMT_SELL: rp is unused; nblk slices of 64 rows; slice c has blk[c+1] -
+//   blk[c] columns, entry k of row 64c + l at ci/val[(blk[c] + k) * 64 + l]
+//   (rows keep their CSR order; padding has value 0 and a valid column).
 // `grid` is the system's workgroup count for products with this matrix (a
 // multiple of 8, a function of nblk only).
 struct DevCSR {
@@ -81,7 +91,11 @@ struct DevCSR {
   int64_t nnz = 0;
   int32_t n = 0;
   int32_t dtype = F64;
+  int32_t fmt = FMT_CSR;
 };
+
+// Rows per slice of FMT_SELL, and slices per workgroup round (one per wave).
+constexpr int kSliceRows = 64;
 
 // One system in the directory (device-resident, POD).
 struct SysDev {

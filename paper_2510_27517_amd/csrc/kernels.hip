@@ -111,11 +111,13 @@ struct Mat {
   GLOBAL const TM *val;
   GLOBAL const int32_t *blk;
   int32_t nblk;
+  int32_t n;
+  int32_t fmt;
 };
 
 template <typename TM>
 __device__ __forceinline__ Mat<TM> mat(const DevCSR &m) {
-  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk};
+  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk, m.n, m.fmt};
 }
 
 // Operands of one row loaded before the row's products are staged.
@@ -184,6 +186,63 @@ __device__ __forceinline__ Sched sched(int nblk, int l, int G) {
   sc.stride = W;
   sc.L = x * W + w;
   return sc;
+}
+
+// Slot of this workgroup's partial sums (the same for both layouts).
+__device__ __forceinline__ int part_slot(int l, int G) { return (l & 7) * (G >> 3) + (l >> 3); }
+
+// One lane's row of a slice: products of its wd entries added left to right
+// from zero (loads issued UNR at a time).
+template <typename TACC, int UNR, typename TM, typename Gather>
+__device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const int32_t *cc, int wd, Gather gather) {
+  TACC sum = 0;
+  int k = 0;
+  for (; k + UNR <= wd; k += UNR) {
+    TACC p[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) p[u] = (TACC)ldval(vv, (k + u) * kSliceRows) * gather(ldstream(cc, (k + u) * kSliceRows));
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) sum += p[u];
+  }
+  for (; k < wd; ++k) sum += (TACC)ldval(vv, k * kSliceRows) * gather(ldstream(cc, k * kSliceRows));
+  return sum;
+}
+
+// Sliced-ELL rows: each wave takes whole slices (64 rows, one per lane); a
+// lane loads its row's entries with coalesced loads across the slice, gathers,
+// and adds the products left to right from zero, the CSR order. No LDS and no
+// barrier. The XCD slab split is the one of the row blocks.
+template <typename TACC, typename TM, typename Pre, typename Gather, typename Epi>
+__device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi) {
+  constexpr int NW = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = G >> 3, x = l & 7, w = l >> 3;
+  const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
+  for (int c = s0 + w * NW + wv; c < s1; c += W * NW) {
+    const int o0 = M.blk[c], wd = M.blk[c + 1] - o0;
+    const int row = c * kSliceRows + lane;
+    const bool has = row < M.n;
+    RowVals<TACC> pv{};
+    if (has) pv = pre(row);
+    GLOBAL const int32_t *cc = M.ci + (int64_t)o0 * kSliceRows + lane;
+    GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lane;
+    // wide slices (tens of entries per row) keep more loads in flight
+    const TACC sum = wd >= 32 ? slice_row_sum<TACC, 8>(vv, cc, wd, gather) : slice_row_sum<TACC, 4>(vv, cc, wd, gather);
+    if (has) epi(row, sum, pv);
+  }
+}
+
+// All rows of this workgroup (local index l of the system's G workgroups),
+// in either layout.
+template <typename TACC, typename TM, typename Pre, typename Gather, typename Epi>
+__device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather, Epi epi) {
+  if (M.fmt == FMT_SELL) {
+    sell_rows<TACC>(M, l, G, pre, gather, epi);
+  } else {
+    const Sched sc = sched(M.nblk, l, G);
+    for (int b = sc.first; b < sc.end; b += sc.stride) stream_block<TACC>(M, b, lds, pre, gather, epi);
+  }
 }
 
 template <int NV>
@@ -257,19 +316,17 @@ __global__ __launch_bounds__(kBlock) void k_iter_A(const SysDev *__restrict__ di
   GLOBAL const TV *__restrict__ dold = gl((const TV *)((it & 1) ? D.d0 : D.d1));  // d_{i-1}
   GLOBAL TV *__restrict__ dnew = gl((TV *)((it & 1) ? D.d1 : D.d0));              // d_i
   double part[1] = {0.0};
-  const Sched sc = sched(A.nblk, m.y, D.A.grid);
-  for (int b = sc.first; b < sc.end; b += sc.stride)
-    stream_block<TV>(
-        A, b, lds, [&](int row) { return RowVals<TV>{s[row], dold[row], x[row]}; },
-        [&](int j) -> TV { return s[j] + beta * dold[j]; },
-        [&](int row, TV sum, const RowVals<TV> &pv) {
-          const TV di = pv.a + beta * pv.b;
-          dnew[row] = di;
-          q[row] = sum;
-          x[row] = pv.c + ap * pv.b;
-          part[0] += (double)di * (double)sum;
-        });
-  put_partials<1>(part, gl(D.pg), sc.L, D.A.grid, sh);
+  for_rows<TV>(
+      A, m.y, D.A.grid, lds, [&](int row) { return RowVals<TV>{s[row], dold[row], x[row]}; },
+      [&](int j) -> TV { return s[j] + beta * dold[j]; },
+      [&](int row, TV sum, const RowVals<TV> &pv) {
+        const TV di = pv.a + beta * pv.b;
+        dnew[row] = di;
+        q[row] = sum;
+        x[row] = pv.c + ap * pv.b;
+        part[0] += (double)di * (double)sum;
+      });
+  put_partials<1>(part, gl(D.pg), part_slot(m.y, D.A.grid), D.A.grid, sh);
 }
 
 template <typename TV, typename TG>
@@ -311,31 +368,28 @@ __global__ __launch_bounds__(kBlock) void k_iter_GT(const SysDev *__restrict__ d
   GLOBAL const TV *__restrict__ src = gl((const TV *)((((mode == 1) ? it + 1 : it) & 1) ? D.r1 : D.r0));
   GLOBAL TV *__restrict__ dst = gl((TV *)(((it + 1) & 1) ? D.r1 : D.r0));
   double part[2] = {0.0, 0.0};
-  const Sched sc = sched(GT.nblk, m.y, D.GT.grid);
   if (mode == 0) {
-    for (int b = sc.first; b < sc.end; b += sc.stride)
-      stream_block<TV>(
-          GT, b, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
-          [&](int j) -> TV { return src[j] - al * q[j]; },
-          [&](int row, TV sum, const RowVals<TV> &pv) {
-            const TV rn = pv.a - al * pv.b;
-            dst[row] = rn;
-            t[row] = sum;
-            part[0] += (double)rn * (double)rn;
-            part[1] += (double)sum * (double)sum;
-          });
+    for_rows<TV>(
+        GT, m.y, D.GT.grid, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
+        [&](int j) -> TV { return src[j] - al * q[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          const TV rn = pv.a - al * pv.b;
+          dst[row] = rn;
+          t[row] = sum;
+          part[0] += (double)rn * (double)rn;
+          part[1] += (double)sum * (double)sum;
+        });
   } else {
-    for (int b = sc.first; b < sc.end; b += sc.stride)
-      stream_block<TV>(
-          GT, b, lds, [&](int row) { return RowVals<TV>{src[row], (TV)0, (TV)0}; },
-          [&](int j) -> TV { return src[j]; },
-          [&](int row, TV sum, const RowVals<TV> &pv) {
-            t[row] = sum;
-            part[0] += (double)pv.a * (double)pv.a;
-            part[1] += (double)sum * (double)sum;
-          });
+    for_rows<TV>(
+        GT, m.y, D.GT.grid, lds, [&](int row) { return RowVals<TV>{src[row], (TV)0, (TV)0}; },
+        [&](int j) -> TV { return src[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          t[row] = sum;
+          part[0] += (double)pv.a * (double)pv.a;
+          part[1] += (double)sum * (double)sum;
+        });
   }
-  put_partials<2>(part, gl(D.prt), sc.L, D.GT.grid, sh);
+  put_partials<2>(part, gl(D.prt), part_slot(m.y, D.GT.grid), D.GT.grid, sh);
 }
 
 template <typename TV, typename TG, bool HAS_EPS>
@@ -386,17 +440,15 @@ __global__ __launch_bounds__(kBlock) void k_iter_G(const SysDev *__restrict__ di
   GLOBAL TV *__restrict__ s = gl((TV *)D.s);
   GLOBAL const TV *__restrict__ rc = gl((const TV *)((i1 & 1) ? D.r1 : D.r0));
   const TV eps = (TV)S.eps;
-  const Sched sc = sched(G.nblk, m.y, D.G.grid);
-  for (int b = sc.first; b < sc.end; b += sc.stride)
-    stream_block<TV>(
-        G, b, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, (TV)0, (TV)0}; },
-        [&](int j) -> TV { return t[j]; },
-        [&](int row, TV sum, const RowVals<TV> &pv) {
-          if (HAS_EPS)
-            s[row] = sum + eps * pv.a;
-          else
-            s[row] = sum;
-        });
+  for_rows<TV>(
+      G, m.y, D.G.grid, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, (TV)0, (TV)0}; },
+      [&](int j) -> TV { return t[j]; },
+      [&](int row, TV sum, const RowVals<TV> &pv) {
+        if (HAS_EPS)
+          s[row] = sum + eps * pv.a;
+        else
+          s[row] = sum;
+      });
 }
 
 template <typename TV, typename TA>
@@ -426,21 +478,17 @@ __global__ __launch_bounds__(kBlock) void k_resid(const SysDev *__restrict__ dir
     al = (TV)(S.delta / g[0]);
   }
   double part[1] = {0.0};
-  const Sched sc = sched(A.nblk, m.y, D.A.grid);
   auto pre = [&](int row) { return RowVals<TV>{b[row], (TV)0, (TV)0}; };
   auto epi = [&](int row, TV sum, const RowVals<TV> &pv) {
     const TV rv = pv.a - sum;
     rout[row] = rv;
     part[0] += (double)rv * (double)rv;
   };
-  if (with_d) {
-    for (int k = sc.first; k < sc.end; k += sc.stride)
-      stream_block<TV>(A, k, lds, pre, [&](int j) -> TV { return x[j] + al * dc[j]; }, epi);
-  } else {
-    for (int k = sc.first; k < sc.end; k += sc.stride)
-      stream_block<TV>(A, k, lds, pre, [&](int j) -> TV { return x[j]; }, epi);
-  }
-  if (reduce) put_partials<1>(part, gl(D.ptr), sc.L, D.A.grid, sh);
+  if (with_d)
+    for_rows<TV>(A, m.y, D.A.grid, lds, pre, [&](int j) -> TV { return x[j] + al * dc[j]; }, epi);
+  else
+    for_rows<TV>(A, m.y, D.A.grid, lds, pre, [&](int j) -> TV { return x[j]; }, epi);
+  if (reduce) put_partials<1>(part, gl(D.ptr), part_slot(m.y, D.A.grid), D.A.grid, sh);
 }
 
 // Rows [l n / G, (l+1) n / G) of a system for elementwise work on A's map.
@@ -564,11 +612,9 @@ template <typename TV, typename TM>
 __global__ __launch_bounds__(kBlock) void k_spmv(DevCSR Md, const TV *__restrict__ x, TV *__restrict__ y) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   const Mat<TM> M = mat<TM>(Md);
-  const Sched sc = sched(M.nblk, blockIdx.x, gridDim.x);
-  for (int b = sc.first; b < sc.end; b += sc.stride)
-    stream_block<TV>(
-        M, b, lds, [&](int) { return RowVals<TV>{}; }, [&](int j) -> TV { return x[j]; },
-        [&](int row, TV sum, const RowVals<TV> &) { y[row] = sum; });
+  for_rows<TV>(
+      M, blockIdx.x, gridDim.x, lds, [&](int) { return RowVals<TV>{}; }, [&](int j) -> TV { return x[j]; },
+      [&](int row, TV sum, const RowVals<TV> &) { y[row] = sum; });
 }
 
 template <typename TV>

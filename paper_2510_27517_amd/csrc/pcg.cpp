@@ -119,16 +119,36 @@ class DevPool {
 
 // ------------------------------------------------------- host staging of a system
 
+// One sparse matrix laid out for the device on the host (see DevCSR).
+struct HostMat {
+  int32_t fmt = pcgk::FMT_CSR;
+  int dt = pcgk::F64;
+  int32_t n = 0;
+  int64_t nnz = 0;           // nonzeros of the matrix (padding excluded)
+  std::vector<int32_t> rp;   // CSR row pointers (FMT_CSR only)
+  std::vector<int32_t> ci;   // columns in storage order
+  std::vector<uint8_t> val;  // values in dt, in storage order
+  std::vector<int32_t> blk;  // row-block pairs (FMT_CSR) or slice offsets (FMT_SELL)
+  int32_t nunits = 0, grid = 8;
+  size_t bytes() const {
+    return align_up(4 * rp.size()) + align_up(4 * std::max<size_t>(ci.size(), 1)) +
+           align_up(std::max<size_t>(val.size(), 1)) + align_up(4 * blk.size());
+  }
+};
+
 // Everything a system's A part needs on the device, prepared on the host.
 struct APart {
   int32_t n = 0;
   int64_t nnz = 0;
   int adt = pcgk::F64, vdt = pcgk::F64;
   bool refine = false, staging = false;
-  std::vector<int32_t> rp, ci, blk, blk64;
-  std::vector<uint8_t> val;       // A's values in the storage type
-  const double *val64 = nullptr;  // FP64 values for refinement (borrowed)
-  int32_t grid = 8, grid64 = 8, gB = 8;
+  HostMat A;
+  // refinement view: FP64 values of A on A's pattern (shared on the device),
+  // with its own row blocks in the CSR layout
+  std::vector<uint8_t> sliced64;  // sliced FP64 values (FMT_SELL)
+  const double *val64 = nullptr;  // CSR-ordered FP64 values (FMT_CSR, borrowed)
+  std::vector<int32_t> blk64;
+  int32_t nunits64 = 0, grid64 = 8, gB = 8;
   size_t bytes = 0;
 };
 
@@ -136,9 +156,7 @@ struct GPart {
   int32_t n = 0;
   int64_t nnz = 0;
   int gdt = pcgk::F64, vdt = pcgk::F64;
-  std::vector<int32_t> rp, ci, blk, trp, tci, tblk;
-  std::vector<uint8_t> val, tval;
-  int32_t grid = 8, tgrid = 8;
+  HostMat G, GT;
   double scale = 1.0;
   size_t bytes = 0;
 };
@@ -156,9 +174,9 @@ struct Sys {
   double *stage64 = nullptr;
 };
 
-int grid_for(int cus, int mult, int32_t nblk) {
+int grid_for(int cus, int mult, int32_t units) {
   if (mult <= 0) mult = 8;
-  int64_t g = std::min<int64_t>(nblk, (int64_t)cus * mult);
+  int64_t g = std::min<int64_t>(units, (int64_t)cus * mult);
   g = (g + 7) & ~int64_t(7);
   return (int)std::max<int64_t>(g, 8);
 }
@@ -182,9 +200,43 @@ void cast_values(const double *v, int64_t nnz, int dt, double scale, std::vector
   }
 }
 
-size_t csr_bytes(int32_t n, int64_t nnz, int dt, size_t nblk) {
-  return align_up(4 * (size_t)(n + 1)) + align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) +
-         align_up(pcgk::dtype_size(dt) * (size_t)std::max<int64_t>(nnz, 1)) + align_up(8 * (nblk + 1));
+// Layout choice (pcg_config.layout): the sliced layout when its padding stays
+// small, the CSR row blocks otherwise.
+bool use_sell(int layout, int32_t n, const int32_t *rp) {
+  if (layout == PCG_LAYOUT_CSR || n <= 0) return false;
+  const int64_t nnz = rp[n], stored = pcgh::sell_entries(n, rp);
+  if (stored >= ((int64_t)1 << 31)) return false;
+  if (layout == PCG_LAYOUT_SELL) return stored <= 2 * nnz + pcgh::kSlice;
+  return stored <= nnz + nnz / 8;
+}
+
+// Lay out one matrix with values v (CSR order) times `scale` in dt; the row
+// blocks (CSR) are sized for products in vector type vdt.
+void make_mat(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+              int dt, double scale, int vdt, HostMat &M) {
+  M.n = n;
+  M.nnz = rp[n];
+  M.dt = dt;
+  std::vector<uint8_t> csr_val;
+  cast_values(v, M.nnz, dt, scale, csr_val);
+  if (use_sell(cfg.layout, n, rp)) {
+    M.fmt = pcgk::FMT_SELL;
+    M.rp.clear();
+    pcgh::sell_offsets(n, rp, M.blk);
+    pcgh::sell_columns(n, rp, ci, M.blk, M.ci);
+    pcgh::sell_bytes(n, rp, csr_val.data(), pcgk::dtype_size(dt), M.blk, M.val);
+    M.nunits = (int32_t)M.blk.size() - 1;
+    const int32_t rounds = (M.nunits + pcgk::kBlock / 64 - 1) / (pcgk::kBlock / 64);
+    M.grid = grid_for(cus, cfg.grid_mult, rounds);
+  } else {
+    M.fmt = pcgk::FMT_CSR;
+    M.rp.assign(rp, rp + n + 1);
+    M.ci.assign(ci, ci + M.nnz);
+    M.val.swap(csr_val);
+    M.blk = pcgh::row_blocks(n, rp, pcgk::lds_cap(vdt));
+    M.nunits = (int32_t)(M.blk.size() / 2 - 1);
+    M.grid = grid_for(cus, cfg.grid_mult, M.nunits);
+  }
 }
 
 void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
@@ -195,23 +247,29 @@ void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const 
   P.vdt = cfg.vec_dtype;
   P.refine = cfg.refine != 0;
   P.staging = staging;
-  P.rp.assign(rp, rp + n + 1);
-  P.ci.assign(ci, ci + P.nnz);
-  cast_values(v, P.nnz, P.adt, 1.0, P.val);
-  P.blk = pcgh::row_blocks(n, rp, pcgk::lds_cap(P.vdt));
-  P.grid = grid_for(cus, cfg.grid_mult, (int32_t)(P.blk.size() / 2 - 1));
+  make_mat(cfg, cus, n, rp, ci, v, P.adt, 1.0, P.vdt, P.A);
   P.gB = norm_grid(n);
+  size_t b64 = 0;
   if (P.refine) {
-    P.val64 = v;
-    P.blk64 = pcgh::row_blocks(n, rp, pcgk::lds_cap(pcgk::F64));
-    P.grid64 = grid_for(cus, cfg.grid_mult, (int32_t)(P.blk64.size() / 2 - 1));
+    if (P.A.fmt == pcgk::FMT_SELL) {
+      pcgh::sell_bytes(n, rp, (const uint8_t *)v, 8, P.A.blk, P.sliced64);
+      P.nunits64 = P.A.nunits;
+      P.grid64 = P.A.grid;
+      b64 = align_up(P.sliced64.size());
+    } else {
+      P.val64 = v;
+      P.blk64 = pcgh::row_blocks(n, rp, pcgk::lds_cap(pcgk::F64));
+      P.nunits64 = (int32_t)(P.blk64.size() / 2 - 1);
+      P.grid64 = grid_for(cus, cfg.grid_mult, P.nunits64);
+      b64 = align_up(8 * (size_t)std::max<int64_t>(P.nnz, 1)) + align_up(4 * P.blk64.size());
+    }
   }
   const size_t vb = align_up(pcgk::dtype_size(P.vdt) * (size_t)n), db = align_up(8 * (size_t)n);
-  size_t b = csr_bytes(n, P.nnz, P.adt, P.blk.size() / 2 - 1) + 9 * vb;
-  if (P.refine) b += align_up(8 * (size_t)std::max<int64_t>(P.nnz, 1)) + align_up(4 * P.blk64.size()) + 3 * db;
+  size_t b = P.A.bytes() + 9 * vb;
+  if (P.refine) b += b64 + 3 * db;
   if (P.staging) b += 2 * vb + db;
-  const int gtr = std::max(P.grid, P.refine ? P.grid64 : 0);
-  b += align_up(8 * (size_t)P.grid) + align_up(8 * (size_t)gtr) + align_up(8 * (size_t)P.gB);
+  const int gtr = std::max(P.A.grid, P.refine ? P.grid64 : 0);
+  b += align_up(8 * (size_t)P.A.grid) + align_up(8 * (size_t)gtr) + align_up(8 * (size_t)P.gB);
   P.bytes = b;
 }
 
@@ -221,8 +279,9 @@ void prep_g(const pcg_config &cfg, int cus, int32_t n, std::vector<int32_t> &grp
   P.nnz = (int64_t)gci.size();
   P.gdt = cfg.g_dtype;
   P.vdt = cfg.vec_dtype;
+  std::vector<int32_t> trp, tci;
   std::vector<double> tv;
-  pcgh::transpose_csr(n, grp, gci, gv, P.trp, P.tci, tv);
+  pcgh::transpose_csr(n, grp, gci, gv, trp, tci, tv);
   // F16 has a narrow exponent range: store G times a power of two (PCG is
   // invariant to the scale of M^-1 when eps is scaled alike).
   P.scale = 1.0;
@@ -235,16 +294,9 @@ void prep_g(const pcg_config &cfg, int cus, int32_t n, std::vector<int32_t> &grp
       P.scale = std::ldexp(1.0, 14 - e);  // max |G| scaled into [2^13, 2^14)
     }
   }
-  cast_values(gv.data(), P.nnz, P.gdt, P.scale, P.val);
-  cast_values(tv.data(), P.nnz, P.gdt, P.scale, P.tval);
-  P.rp.swap(grp);
-  P.ci.swap(gci);
-  P.blk = pcgh::row_blocks(n, P.rp.data(), pcgk::lds_cap(P.vdt));
-  P.tblk = pcgh::row_blocks(n, P.trp.data(), pcgk::lds_cap(P.vdt));
-  P.grid = grid_for(cus, cfg.grid_mult, (int32_t)(P.blk.size() / 2 - 1));
-  P.tgrid = grid_for(cus, cfg.grid_mult, (int32_t)(P.tblk.size() / 2 - 1));
-  P.bytes = csr_bytes(n, P.nnz, P.gdt, P.blk.size() / 2 - 1) + csr_bytes(n, P.nnz, P.gdt, P.tblk.size() / 2 - 1) +
-            align_up(16 * (size_t)P.tgrid);
+  make_mat(cfg, cus, n, grp.data(), gci.data(), gv.data(), P.gdt, P.scale, P.vdt, P.G);
+  make_mat(cfg, cus, n, trp.data(), tci.data(), tv.data(), P.gdt, P.scale, P.vdt, P.GT);
+  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * (size_t)P.GT.grid);
 }
 
 struct Carver {
@@ -262,6 +314,33 @@ hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
   return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
 }
 
+// Carve one matrix out of `c` and upload it into M.
+hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  int32_t *drp = H.rp.empty() ? nullptr : (int32_t *)c.take(4 * H.rp.size());
+  int32_t *dci = (int32_t *)c.take(4 * std::max<size_t>(H.ci.size(), 1));
+  void *dval = c.take(std::max<size_t>(H.val.size(), 1));
+  int32_t *dblk = (int32_t *)c.take(4 * H.blk.size());
+  if (drp) chain(h2d(drp, H.rp.data(), 4 * H.rp.size(), s));
+  chain(h2d(dci, H.ci.data(), 4 * H.ci.size(), s));
+  chain(h2d(dval, H.val.data(), H.val.size(), s));
+  chain(h2d(dblk, H.blk.data(), 4 * H.blk.size(), s));
+  M.rp = drp;
+  M.ci = dci;
+  M.val = dval;
+  M.blk = dblk;
+  M.nblk = H.nunits;
+  M.grid = H.grid;
+  M.nnz = H.nnz;
+  M.n = H.n;
+  M.dtype = H.dt;
+  M.fmt = H.fmt;
+  return e;
+}
+
 // Carve the A part into `block` and upload it (asynchronously: P must live
 // until the stream has passed the copies).
 hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
@@ -269,49 +348,38 @@ hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
   const int32_t n = P.n;
   const size_t vb = pcgk::dtype_size(P.vdt) * (size_t)n;
   DevCSR &A = S.dev.A;
-  int32_t *rp = (int32_t *)c.take(4 * (size_t)(n + 1));
-  int32_t *ci = (int32_t *)c.take(4 * (size_t)std::max<int64_t>(P.nnz, 1));
-  void *val = c.take(P.val.size());
-  int32_t *blk = (int32_t *)c.take(4 * P.blk.size());
-  hipError_t e = hipSuccess;
+  hipError_t e = put_mat(c, P.A, A, s);
   auto chain = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  chain(h2d(rp, P.rp.data(), 4 * (size_t)(n + 1), s));
-  chain(h2d(ci, P.ci.data(), 4 * (size_t)P.nnz, s));
-  chain(h2d(val, P.val.data(), pcgk::dtype_size(P.adt) * (size_t)P.nnz, s));
-  chain(h2d(blk, P.blk.data(), 4 * P.blk.size(), s));
-  A.rp = rp;
-  A.ci = ci;
-  A.val = val;
-  A.blk = blk;
-  A.nblk = (int32_t)(P.blk.size() / 2 - 1);
-  A.grid = P.grid;
-  A.nnz = P.nnz;
-  A.n = n;
-  A.dtype = P.adt;
   void **vecs[] = {&S.dev.x, &S.dev.r0, &S.dev.r1, &S.dev.d0, &S.dev.d1, &S.dev.q, &S.dev.t, &S.dev.s, &S.dev.b};
   for (void **v : vecs) *v = c.take(vb);
   S.dev.n = n;
   S.dev.gB = P.gB;
   S.n = n;
   S.nnz_a = P.nnz;
-  S.dev.pg = (double *)c.take(8 * (size_t)P.grid);
-  S.dev.ptr = (double *)c.take(8 * (size_t)std::max(P.grid, P.refine ? P.grid64 : 0));
+  S.dev.pg = (double *)c.take(8 * (size_t)P.A.grid);
+  S.dev.ptr = (double *)c.take(8 * (size_t)std::max(P.A.grid, P.refine ? P.grid64 : 0));
   S.dev.pb = (double *)c.take(8 * (size_t)P.gB);
   if (P.refine) {
-    void *v64 = c.take(8 * (size_t)std::max<int64_t>(P.nnz, 1));
-    int32_t *b64k = (int32_t *)c.take(4 * P.blk64.size());
-    chain(h2d(v64, P.val64, 8 * (size_t)P.nnz, s));
-    chain(h2d(b64k, P.blk64.data(), 4 * P.blk64.size(), s));
     SysDev &D = S.dev64;
     D = SysDev{};
     D.A = A;
-    D.A.val = v64;
-    D.A.blk = b64k;
-    D.A.nblk = (int32_t)(P.blk64.size() / 2 - 1);
-    D.A.grid = P.grid64;
     D.A.dtype = pcgk::F64;
+    if (P.A.fmt == pcgk::FMT_SELL) {  // same slices and columns, FP64 values
+      void *v64 = c.take(P.sliced64.size());
+      chain(h2d(v64, P.sliced64.data(), P.sliced64.size(), s));
+      D.A.val = v64;
+    } else {  // same CSR pattern, FP64 values, row blocks for FP64 products
+      void *v64 = c.take(8 * (size_t)std::max<int64_t>(P.nnz, 1));
+      int32_t *b64k = (int32_t *)c.take(4 * P.blk64.size());
+      chain(h2d(v64, P.val64, 8 * (size_t)P.nnz, s));
+      chain(h2d(b64k, P.blk64.data(), 4 * P.blk64.size(), s));
+      D.A.val = v64;
+      D.A.blk = b64k;
+    }
+    D.A.nblk = P.nunits64;
+    D.A.grid = P.grid64;
     D.x = c.take(8 * (size_t)n);
     D.b = c.take(8 * (size_t)n);
     D.r0 = D.r1 = D.d0 = D.d1 = c.take(8 * (size_t)n);
@@ -331,34 +399,10 @@ hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
 
 hipError_t place_g(const GPart &P, void *block, Sys &S, hipStream_t s) {
   Carver c{(uint8_t *)block};
-  const int32_t n = P.n;
-  hipError_t e = hipSuccess;
-  auto chain = [&](hipError_t x) {
-    if (e == hipSuccess) e = x;
-  };
-  auto put = [&](DevCSR &M, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
-                 const std::vector<uint8_t> &val, const std::vector<int32_t> &blk, int grid) {
-    int32_t *drp = (int32_t *)c.take(4 * (size_t)(n + 1));
-    int32_t *dci = (int32_t *)c.take(4 * (size_t)std::max<int64_t>(P.nnz, 1));
-    void *dval = c.take(val.size());
-    int32_t *dblk = (int32_t *)c.take(4 * blk.size());
-    chain(h2d(drp, rp.data(), 4 * (size_t)(n + 1), s));
-    chain(h2d(dci, ci.data(), 4 * (size_t)P.nnz, s));
-    chain(h2d(dval, val.data(), pcgk::dtype_size(P.gdt) * (size_t)P.nnz, s));
-    chain(h2d(dblk, blk.data(), 4 * blk.size(), s));
-    M.rp = drp;
-    M.ci = dci;
-    M.val = dval;
-    M.blk = dblk;
-    M.nblk = (int32_t)(blk.size() / 2 - 1);
-    M.grid = grid;
-    M.nnz = P.nnz;
-    M.n = n;
-    M.dtype = P.gdt;
-  };
-  put(S.dev.G, P.rp, P.ci, P.val, P.blk, P.grid);
-  put(S.dev.GT, P.trp, P.tci, P.tval, P.tblk, P.tgrid);
-  S.dev.prt = (double *)c.take(16 * (size_t)P.tgrid);
+  hipError_t e = put_mat(c, P.G, S.dev.G, s);
+  hipError_t e2 = put_mat(c, P.GT, S.dev.GT, s);
+  if (e == hipSuccess) e = e2;
+  S.dev.prt = (double *)c.take(16 * (size_t)P.GT.grid);
   S.nnz_g = P.nnz;
   S.g_scale = P.scale;
   return e;
@@ -397,6 +441,7 @@ struct Req {
   int slot64 = -1;  // FP64 view under refinement
   int restarts = 0;
   int outer = 0, inner_total = 0;
+  int iter_host = 0;  // the system's iteration count at the start of the next scheduler step
   double prev_rn = INFINITY, relres64 = NAN, last_rec = NAN;
   double t_submit = 0, t_admit = 0, t_done = 0;
   pcg_result res{};
@@ -938,6 +983,7 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
     R.sys.dev.st = ctx->d_states + 2 * R.slot;
     ctx->dir[R.slot] = R.sys.dev;
     inits[2 * i] = inits[2 * i + 1] = init_state(ctx, R.tol, R.maxit, R.sys.g_scale);
+    R.iter_host = 0;
     if (ctx->cfg.refine) {
       // FP64 view: b64, x64 from the caller; s and t point at the inner x and b
       SysDev &V = R.sys.dev64;
@@ -1107,6 +1153,7 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
   HIPCHK(pcgk::launch_zero_dirs(ctx->ty, hin.L, true, s));
   for (size_t i = 0; i < go.size(); ++i) {
     inits[2 * i] = inits[2 * i + 1] = init_state(ctx, itol[i], go[i]->maxit, go[i]->sys.g_scale, true);
+    go[i]->iter_host = 0;
     HIPCHK(h2d(ctx->d_states + 2 * go[i]->slot, &inits[2 * i], 2 * sizeof(State), s));
   }
   rc = enqueue_start(ctx, ctx->ty, hin.L, ctx->cfg.eps != 0.0);
@@ -1146,9 +1193,22 @@ int progress(pcg_ctx *ctx, int iters) {
   }
   const LaunchSet &L = ctx->set_active.L;
   const bool has_eps = ctx->cfg.eps != 0.0;
+  // The residual kernel decides per system whether it is at a replacement
+  // iteration; it is only launched when some running system may be (inner
+  // solves of refinement never replace).
+  const int rr = ctx->cfg.rr_period;
+  auto any_replacement = [&](int k) {
+    if (rr <= 0) return false;
+    for (auto &R : ctx->active) {
+      if (R->slot64 >= 0) continue;
+      const int i = R->iter_host + k;
+      if (i > 0 && i % rr == 0) return true;
+    }
+    return false;
+  };
   for (int k = 0; k < iters; ++k) {
     HIPCHK(pcgk::launch_iter_A(ctx->ty, L, s));
-    HIPCHK(pcgk::launch_resid(ctx->ty, L, 2, true, false, true, s));
+    if (any_replacement(k)) HIPCHK(pcgk::launch_resid(ctx->ty, L, 2, true, false, true, s));
     HIPCHK(pcgk::launch_iter_GT(ctx->ty, L, 3, s));
     HIPCHK(pcgk::launch_iter_G(ctx->ty, L, has_eps, 3, s));
   }
@@ -1157,6 +1217,7 @@ int progress(pcg_ctx *ctx, int iters) {
   const size_t sb = 2 * sizeof(State) * (size_t)(maxslot + 1);
   HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, sb, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  for (auto &R : ctx->active) R->iter_host = ctx->h_states[2 * R->slot].iter;
   std::vector<int> done_slots;
   for (auto &R : ctx->active)
     if (ctx->h_states[2 * R->slot].done) done_slots.push_back(R->slot);

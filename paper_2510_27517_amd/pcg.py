@@ -22,6 +22,8 @@ EINVAL, ESTATE, ENOMEM, EBREAKDOWN, EDEVICE = -1, -2, -3, -4, -5
 F64, F32, BF16, F16 = 0, 1, 2, 3
 G_FSAI, G_FIXED, G_JACOBI, G_IDENTITY, G_SEEDED = 1, 2, 3, 4, 5
 OP_A, OP_GT, OP_G, OP_MINV = 0, 1, 2, 3
+LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SELL = 0, 1, 2
+LAYOUTS = {"auto": LAYOUT_AUTO, "csr": LAYOUT_CSR, "sell": LAYOUT_SELL}
 
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 
@@ -40,7 +42,7 @@ class Config(ctypes.Structure):
         ("a_dtype", ctypes.c_int), ("g_dtype", ctypes.c_int), ("rr_period", ctypes.c_int),
         ("eps", ctypes.c_double), ("refine", ctypes.c_int), ("inner_tol", ctypes.c_double),
         ("max_outer", ctypes.c_int), ("graph_iters", ctypes.c_int), ("grid_mult", ctypes.c_int),
-        ("mem_budget_mb", ctypes.c_int), ("reserved", ctypes.c_int * 7),
+        ("mem_budget_mb", ctypes.c_int), ("layout", ctypes.c_int), ("reserved", ctypes.c_int * 6),
     ]
 
 
@@ -121,6 +123,8 @@ def default_config(**kw) -> Config:
     for k, v in kw.items():
         if k in ("vec_dtype", "a_dtype", "g_dtype") and isinstance(v, str):
             v = DTYPES[v]
+        if k == "layout" and isinstance(v, str):
+            v = LAYOUTS[v]
         setattr(cfg, k, v)
     return cfg
 

@@ -59,20 +59,26 @@ def _random_g(A, seed):
     return CSR(A.rowptr.copy(), A.col.copy(), rng.uniform(-1, 1, A.nnz))
 
 
-@pytest.mark.parametrize("case", ["ragged", "longrows", "poisson3d"])
-def test_operator_products_bitwise(gpu_lib, case):
+@pytest.mark.parametrize("layout", ["auto", "csr", "sell"])
+@pytest.mark.parametrize("case", ["ragged", "longrows", "poisson3d", "elasticity"])
+def test_operator_products_bitwise(gpu_lib, case, layout):
+    """Both storage layouts give the oracle's products bit for bit (the sliced
+    layout is forced onto ragged rows, so padding is exercised; the long rows
+    fall back to CSR)."""
     pcg = gpu_lib
     if case == "ragged":
         A = _random_spd_pattern(1537, 1)
     elif case == "longrows":
         A = _random_spd_pattern(5000, 2, long_rows=(0, 17, 4999))
+    elif case == "elasticity":
+        A = inputs.elasticity(6, 1.0, 0.3, 2)
     else:
         A = inputs.poisson(3, 40, 1.0, 2)
     G = _random_g(A, 3)
     x = np.random.default_rng(4).standard_normal(A.n)
     eps = 0.37
-    say("operator products", case, A.n, A.nnz)
-    with _solver(pcg, eps=eps) as s:
+    say("operator products", case, layout, A.n, A.nnz)
+    with _solver(pcg, eps=eps, layout=layout) as s:
         s.set_matrix(A)
         s.set_precond(G)
         assert np.array_equal(s.matvec(pcg.OP_A, x), oracle.spmv(A, x))
@@ -81,8 +87,8 @@ def test_operator_products_bitwise(gpu_lib, case):
         assert np.array_equal(s.matvec(pcg.OP_MINV, x), oracle.apply_precond(G, x, eps))
 
 
-def _parity(pcg, A, kind, b, *, tol=1e-8, maxit=2000, eps=0.0, rr=50, graph=10, x0=None, seed=0):
-    with _solver(pcg, eps=eps, rr_period=rr, graph_iters=graph) as s:
+def _parity(pcg, A, kind, b, *, tol=1e-8, maxit=2000, eps=0.0, rr=50, graph=10, x0=None, seed=0, layout="auto"):
+    with _solver(pcg, eps=eps, rr_period=rr, graph_iters=graph, layout=layout) as s:
         s.set_matrix(A)
         s.build_precond(kind, seed)
         got = s.solve(b, x0, tol=tol, maxit=maxit)
@@ -113,13 +119,14 @@ def test_pcg_fixed_g_poisson2d_64(gpu_lib):
     say("iters", got.iters, ref.iters, "xerr", err)
 
 
+@pytest.mark.parametrize("layout", ["csr", "sell"])
 @pytest.mark.parametrize("N", [16, 24])
-def test_pcg_fsai_poisson3d_lognormal(gpu_lib, N):
+def test_pcg_fsai_poisson3d_lognormal(gpu_lib, N, layout):
     pcg = gpu_lib
     A = inputs.poisson(3, N, 1.0, 0)
     b = inputs.rhs(A.n, 0)
-    say("pcg fsai 3D", N)
-    got, ref = _parity(pcg, A, pcg.G_FSAI, b)
+    say("pcg fsai 3D", N, layout)
+    got, ref = _parity(pcg, A, pcg.G_FSAI, b, layout=layout)
     _check(got, ref)
     assert got.status == pcg.OK
 
@@ -142,15 +149,27 @@ def test_pcg_seeded_full_pattern_g_with_shift(gpu_lib, case):
     b = inputs.rhs(A.n, 6)
     eps = oracle.eps_shift(A)
     say("pcg seeded G", case, A.n, "eps", eps)
-    # a random (unlearned) G converges slowly, so at 1e-8 the two iterates can
-    # differ by more than 1e-10 from the order of the dot products alone:
-    # compare at a fixed iteration count, and near the exact solution
+    # A random (unlearned) G converges slowly: over hundreds to thousands of
+    # iterations the order of the dot products alone moves the stopping point.
+    # Parity is binding at a fixed iteration count; the converged solves are
+    # held to what the residual bound allows, ||x - x*|| <= kappa(A) ||r||/||b||
+    # ||x*|| for each, with kappa bounded by Gershgorin over lambda_min.
     got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=0.0, maxit=25)
     _check(got, ref)
     assert got.status == pcg.NOT_CONVERGED and got.iters == 25
-    got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=1e-11, maxit=5000)
-    _check(got, ref)
-    assert got.status == pcg.OK
+    tol = 1e-11
+    got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=tol, maxit=5000)
+    assert got.status == ref.status == pcg.OK
+    assert abs(got.iters - ref.iters) <= 1, (got.iters, ref.iters)
+    r = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+    assert r <= 1.0001 * tol
+    lam_max = max(np.abs(A.val[A.rowptr[i]:A.rowptr[i + 1]]).sum() for i in range(A.n))
+    import scipy.sparse.linalg as spla
+
+    lam_min = float(spla.eigsh(A.to_scipy(), k=1, sigma=0, which="LM", return_eigenvectors=False)[0])
+    err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
+    say(f"  iters {got.iters}/{ref.iters} relres {r:.2e} xdiff {err:.2e} bound {2 * lam_max / lam_min * tol:.2e}")
+    assert err <= 2 * lam_max / lam_min * tol
 
 
 def test_pcg_random_spd_long_rows(gpu_lib):
