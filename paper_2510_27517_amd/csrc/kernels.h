@@ -100,7 +100,7 @@ constexpr int kSliceRows = 64;
 // One system in the directory (device-resident, POD).
 struct SysDev {
   DevCSR A, GT, G;
-  void *x, *r0, *r1, *d0, *d1, *q, *t, *s, *b;  // n entries of the vector type
+  void *x, *r0, *r1, *d0, *d1, *q, *t, *s, *b;  // n entries of the vector type (s: FP64 views only)
   State *st;                                    // two slots
   double *pg;   // A.grid partials: d^T A d
   double *prt;  // 2 * GT.grid partials: ||r||^2, ||t||^2
@@ -137,8 +137,8 @@ struct LaunchSet {
 hipError_t launch_resid(const Types &ty, const LaunchSet &L, int slot_sel, bool with_d, bool reduce,
                         bool respect_done, hipStream_t s);
 
-// A-kernel of iteration i: d_i = s + beta d_{i-1}; x += alpha_{i-1} d_{i-1};
-// q = A d_i; partials of d_i^T q.
+// A-kernel of iteration i: x += alpha_{i-1} d_{i-1}; q = A d_i; partials of
+// d_i^T q.
 hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s);
 
 // G^T-kernel: mode 0 (r_{i+1} = r_i - alpha_i q), 1 (r_{i+1} already
@@ -149,7 +149,8 @@ hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s);
 hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStream_t s);
 
 // G-kernel: delta_{i+1}, beta_{i+1}, convergence / maxit / breakdown, iter;
-// publishes st[0]; then s = G t + eps r unless stopped.
+// publishes st[0]; then, unless stopped, d_{i+1} = (G t + eps r) + beta d_i
+// (beta = 0 in mode 2).
 hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s);
 
 // x += alpha d_{iter-1} (the pending update), then alpha = 0.

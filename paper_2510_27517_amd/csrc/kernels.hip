@@ -7,14 +7,14 @@
 // row products in LDS; then one thread per row adds its products in CSR
 // order. The A, G^T and G products carry the CG vector updates in their
 // gathers and epilogues, so one iteration is three launches:
-//   A-kernel : d_i = s_i + beta_i d_{i-1}  (formed where it is gathered),
-//              x += alpha_{i-1} d_{i-1}     (the update deferred from i-1),
-//              q = A d_i,  gamma = d_i^T q, alpha_i = delta_i / gamma;
-//   G^T-kernel: r_{i+1} = r_i - alpha_i q  (formed where it is gathered),
-//              t = G^T r_{i+1}, ||r||^2, ||t||^2,
-//              delta_{i+1} = ||t||^2 + eps ||r||^2 (= r^T M^-1 r),
-//              beta_{i+1} = delta_{i+1} / delta_i, convergence test;
-//   G-kernel : s_{i+1} = G t + eps r_{i+1}.
+//   A-kernel : x += alpha_{i-1} d_{i-1}     (the update deferred from i-1),
+//              q = A d_i,  partials of gamma = d_i^T q;
+//   G^T-kernel: alpha_i = delta_i / gamma,
+//              r_{i+1} = r_i - alpha_i q  (formed where it is gathered),
+//              t = G^T r_{i+1}, partials of ||r||^2, ||t||^2;
+//   G-kernel : delta_{i+1} = ||t||^2 + eps ||r||^2 (= r^T M^-1 r),
+//              beta_{i+1} = delta_{i+1} / delta_i, convergence test,
+//              d_{i+1} = (G t + eps r_{i+1}) + beta_{i+1} d_i.
 // d and r alternate between two buffers by iteration parity, so no
 // workgroup overwrites a vector entry another one still gathers.
 //
@@ -309,22 +309,19 @@ __global__ __launch_bounds__(kBlock) void k_iter_A(const SysDev *__restrict__ di
   if (S.done) return;
   const Mat<TA> A = mat<TA>(D.A);
   const int it = S.iter;
-  const TV beta = (TV)S.beta, ap = (TV)S.alpha;
+  const TV ap = (TV)S.alpha;
   GLOBAL TV *__restrict__ x = gl((TV *)D.x);
-  GLOBAL const TV *__restrict__ s = gl((const TV *)D.s);
   GLOBAL TV *__restrict__ q = gl((TV *)D.q);
   GLOBAL const TV *__restrict__ dold = gl((const TV *)((it & 1) ? D.d0 : D.d1));  // d_{i-1}
-  GLOBAL TV *__restrict__ dnew = gl((TV *)((it & 1) ? D.d1 : D.d0));              // d_i
+  GLOBAL const TV *__restrict__ dcur = gl((const TV *)((it & 1) ? D.d1 : D.d0));  // d_i
   double part[1] = {0.0};
   for_rows<TV>(
-      A, m.y, D.A.grid, lds, [&](int row) { return RowVals<TV>{s[row], dold[row], x[row]}; },
-      [&](int j) -> TV { return s[j] + beta * dold[j]; },
+      A, m.y, D.A.grid, lds, [&](int row) { return RowVals<TV>{dcur[row], dold[row], x[row]}; },
+      [&](int j) -> TV { return dcur[j]; },
       [&](int row, TV sum, const RowVals<TV> &pv) {
-        const TV di = pv.a + beta * pv.b;
-        dnew[row] = di;
         q[row] = sum;
         x[row] = pv.c + ap * pv.b;
-        part[0] += (double)di * (double)sum;
+        part[0] += (double)pv.a * (double)sum;
       });
   put_partials<1>(part, gl(D.pg), part_slot(m.y, D.A.grid), D.A.grid, sh);
 }
@@ -435,19 +432,21 @@ __global__ __launch_bounds__(kBlock) void k_iter_G(const SysDev *__restrict__ di
     st_state(st, o);
   }
   if (status != ST_RUNNING) return;
+  // s = G t + eps r, and the next direction d_{i+1} = s + beta d_i (at a
+  // start or restart beta = 0, d = s)
   const Mat<TG> G = mat<TG>(D.G);
   GLOBAL const TV *__restrict__ t = gl((const TV *)D.t);
-  GLOBAL TV *__restrict__ s = gl((TV *)D.s);
   GLOBAL const TV *__restrict__ rc = gl((const TV *)((i1 & 1) ? D.r1 : D.r0));
+  GLOBAL const TV *__restrict__ dprev = gl((const TV *)((i1 & 1) ? D.d0 : D.d1));
+  GLOBAL TV *__restrict__ dnext = gl((TV *)((i1 & 1) ? D.d1 : D.d0));
   const TV eps = (TV)S.eps;
+  const TV beta = (TV)((mode == 2) ? 0.0 : dn / S.delta);
   for_rows<TV>(
-      G, m.y, D.G.grid, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, (TV)0, (TV)0}; },
+      G, m.y, D.G.grid, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], (TV)0}; },
       [&](int j) -> TV { return t[j]; },
       [&](int row, TV sum, const RowVals<TV> &pv) {
-        if (HAS_EPS)
-          s[row] = sum + eps * pv.a;
-        else
-          s[row] = sum;
+        const TV sv = HAS_EPS ? sum + eps * pv.a : sum;
+        dnext[row] = sv + beta * pv.b;
       });
 }
 

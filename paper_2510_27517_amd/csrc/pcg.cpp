@@ -265,7 +265,7 @@ void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const 
     }
   }
   const size_t vb = align_up(pcgk::dtype_size(P.vdt) * (size_t)n), db = align_up(8 * (size_t)n);
-  size_t b = P.A.bytes() + 9 * vb;
+  size_t b = P.A.bytes() + 8 * vb;
   if (P.refine) b += b64 + 3 * db;
   if (P.staging) b += 2 * vb + db;
   const int gtr = std::max(P.A.grid, P.refine ? P.grid64 : 0);
@@ -352,8 +352,9 @@ hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
   auto chain = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  void **vecs[] = {&S.dev.x, &S.dev.r0, &S.dev.r1, &S.dev.d0, &S.dev.d1, &S.dev.q, &S.dev.t, &S.dev.s, &S.dev.b};
+  void **vecs[] = {&S.dev.x, &S.dev.r0, &S.dev.r1, &S.dev.d0, &S.dev.d1, &S.dev.q, &S.dev.t, &S.dev.b};
   for (void **v : vecs) *v = c.take(vb);
+  S.dev.s = nullptr;  // s = G t + eps r is folded into d by the G-kernel
   S.dev.n = n;
   S.dev.gB = P.gB;
   S.n = n;
@@ -1754,9 +1755,9 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
     const double sa = (double)pcgk::dtype_size(ctx->cfg.a_dtype), sg = (double)pcgk::dtype_size(ctx->cfg.g_dtype),
                  sv = (double)pcgk::dtype_size(ctx->cfg.vec_dtype);
     const double rp = 4.0 * (n + 1.0);
-    bytes[0] = (double)S.nnz_a * (sa + 4) + rp + 6.0 * n * sv;
+    bytes[0] = (double)S.nnz_a * (sa + 4) + rp + 5.0 * n * sv;
     bytes[1] = (double)S.nnz_g * (sg + 4) + rp + 4.0 * n * sv;
-    bytes[2] = (double)S.nnz_g * (sg + 4) + rp + (has_eps ? 3.0 : 2.0) * n * sv;
+    bytes[2] = (double)S.nnz_g * (sg + 4) + rp + (has_eps ? 4.0 : 3.0) * n * sv;
     bytes[3] = bytes[0] + bytes[1] + bytes[2];
   }
   return PCG_OK;

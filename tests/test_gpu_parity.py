@@ -149,18 +149,25 @@ def test_pcg_seeded_full_pattern_g_with_shift(gpu_lib, case):
     b = inputs.rhs(A.n, 6)
     eps = oracle.eps_shift(A)
     say("pcg seeded G", case, A.n, "eps", eps)
-    # A random (unlearned) G converges slowly: over hundreds to thousands of
-    # iterations the order of the dot products alone moves the stopping point.
-    # Parity is binding at a fixed iteration count; the converged solves are
-    # held to what the residual bound allows, ||x - x*|| <= kappa(A) ||r||/||b||
-    # ||x*|| for each, with kappa bounded by Gershgorin over lambda_min.
-    got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=0.0, maxit=25)
+    # A random (unlearned) G makes the iteration sensitive to rounding order:
+    # on the RGG system the oracle's two algebraically equal delta formulas
+    # already differ by 2e-12 in x after 20 iterations and 3.4e-10 after 25
+    # (3.4e-15 after 10). Parity is binding at a fixed count of 10; the
+    # converged solves are held to what the residual bound allows,
+    # ||x - x*|| <= kappa(A) ||r||/||b|| ||x*|| for each, with kappa bounded by
+    # Gershgorin over lambda_min.
+    got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=0.0, maxit=10)
     _check(got, ref)
-    assert got.status == pcg.NOT_CONVERGED and got.iters == 25
+    assert got.status == pcg.NOT_CONVERGED and got.iters == 10
     tol = 1e-11
     got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=tol, maxit=5000)
     assert got.status == ref.status == pcg.OK
-    assert abs(got.iters - ref.iters) <= 1, (got.iters, ref.iters)
+    # the iteration count is as sensitive: the oracle's own count moves under
+    # its other delta formula and under a 1e-16 relative change of b
+    alt = [oracle.pcg(A, oracle.seeded_g(A, 77), bb, eps=eps, tol=tol, maxit=5000, delta_form=df).iters
+           for bb, df in ((b, 0), (b * (1 + 1e-16 * np.sign(np.sin(np.arange(A.n)))), 1))]
+    spread = max(abs(k - ref.iters) for k in alt)
+    assert abs(got.iters - ref.iters) <= max(1, spread + 1), (got.iters, ref.iters, alt)
     r = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
     assert r <= 1.0001 * tol
     lam_max = max(np.abs(A.val[A.rowptr[i]:A.rowptr[i + 1]]).sum() for i in range(A.n))
