@@ -179,11 +179,12 @@ int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device);
 /* Measurement. Runs `iters` CG iterations of the stored system (a fresh
  * solve of the last right-hand side from x0 = 0 that never stops; the
  * context's vectors are overwritten) as plain launches on the context's
- * stream, with HIP events around each kernel. ms[0..2]: average duration of
- * the A-, G^T- and G-kernel launches; ms[3]: average iteration. bytes[0..3]
- * (may be NULL): their algorithmic device bytes per launch (A: A's values,
- * columns and row pointers plus 6 vector streams; G^T: G^T plus 4; G: G plus
- * 2, 3 with eps). Needs one prior pcg_solve with b != 0. */
+ * stream, each with start/stop events attached to its dispatch (the
+ * kernel's own execution interval). ms[0..2]: average duration of the A-,
+ * G^T- and G-kernel launches; ms[3]: average iteration (A start to G end).
+ * bytes[0..3] (may be NULL): their algorithmic device bytes per launch
+ * (A: A's values, columns and row pointers plus 5 vector streams; G^T: G^T
+ * plus 4; G: G plus 3, 4 with eps). Needs one prior pcg_solve with b != 0. */
 int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes);
 
 /* Device-to-device copy of `bytes` (rounded down to 16) repeated `reps`

@@ -139,19 +139,24 @@ hipError_t launch_resid(const Types &ty, const LaunchSet &L, int slot_sel, bool 
 
 // A-kernel of iteration i: x += alpha_{i-1} d_{i-1}; q = A d_i; partials of
 // d_i^T q.
-hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s);
+// Optional events e0/e1 are attached to the dispatch itself (start and end
+// of the kernel's execution), for timing.
+hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 
 // G^T-kernel: mode 0 (r_{i+1} = r_i - alpha_i q), 1 (r_{i+1} already
 // replaced), 2 (start or restart: r_i given, beta = 0), 3 (0 or 1 per system
 // from its iteration count and replacement period). Forms gamma and
 // alpha_i (or flags breakdown), t = G^T r, partials of ||r||^2 and ||t||^2;
 // publishes st[1].
-hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStream_t s);
+hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStream_t s, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
 
 // G-kernel: delta_{i+1}, beta_{i+1}, convergence / maxit / breakdown, iter;
 // publishes st[0]; then, unless stopped, d_{i+1} = (G t + eps r) + beta d_i
 // (beta = 0 in mode 2).
-hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s);
+hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // x += alpha d_{iter-1} (the pending update), then alpha = 0.
 hipError_t launch_finalize(const Types &ty, const LaunchSet &L, hipStream_t s);

@@ -33,6 +33,7 @@
 // Built with floating-point contraction off: every product and sum rounds
 // separately, in the order written (rows summed left to right from zero),
 // which is also the order of the plain CSR definition.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdint>
@@ -671,33 +672,44 @@ static inline int ew_grid(int64_t n) {
     default: return hipErrorInvalidValue;                     \
   }
 
-hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s) {
+// Plain launch, or with events on the dispatch when timing.
+#define PCG_LAUNCH(kern, grid, s, e0, e1, ...)                                                  \
+  do {                                                                                          \
+    if ((e0) || (e1))                                                                           \
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, __VA_ARGS__);     \
+    else                                                                                        \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                   \
+  } while (0)
+
+hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (L.nA == 0) return hipSuccess;
   if (ty.vec == F64 && ty.a == F64) {
-    hipLaunchKernelGGL((k_iter_A<double, double>), dim3(L.nA), dim3(kBlock), 0, s, L.dir, L.mapA);
+    PCG_LAUNCH((k_iter_A<double, double>), L.nA, s, e0, e1, L.dir, L.mapA);
   } else if (ty.vec == F32 && ty.a == F32) {
-    hipLaunchKernelGGL((k_iter_A<float, float>), dim3(L.nA), dim3(kBlock), 0, s, L.dir, L.mapA);
+    PCG_LAUNCH((k_iter_A<float, float>), L.nA, s, e0, e1, L.dir, L.mapA);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStream_t s) {
+hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1) {
   if (L.nGT == 0) return hipSuccess;
   PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(ty.g, TG, {
-    hipLaunchKernelGGL((k_iter_GT<TV, TG>), dim3(L.nGT), dim3(kBlock), 0, s, L.dir, L.mapGT, mode);
+    PCG_LAUNCH((k_iter_GT<TV, TG>), L.nGT, s, e0, e1, L.dir, L.mapGT, mode);
   }));
   return hipGetLastError();
 }
 
-hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s) {
+hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
   if (L.nG == 0) return hipSuccess;
   PCG_DISPATCH_V(ty.vec, TV, PCG_DISPATCH_G(ty.g, TG, {
     if (has_eps)
-      hipLaunchKernelGGL((k_iter_G<TV, TG, true>), dim3(L.nG), dim3(kBlock), 0, s, L.dir, L.mapG, mode);
+      PCG_LAUNCH((k_iter_G<TV, TG, true>), L.nG, s, e0, e1, L.dir, L.mapG, mode);
     else
-      hipLaunchKernelGGL((k_iter_G<TV, TG, false>), dim3(L.nG), dim3(kBlock), 0, s, L.dir, L.mapG, mode);
+      PCG_LAUNCH((k_iter_G<TV, TG, false>), L.nG, s, e0, e1, L.dir, L.mapG, mode);
   }));
   return hipGetLastError();
 }

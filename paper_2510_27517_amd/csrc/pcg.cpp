@@ -1708,7 +1708,8 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
     ctx->err = "pcg_time_kernels: solve a nonzero right-hand side first";
     return PCG_ESTATE;
   }
-  std::vector<hipEvent_t> ev(4 * (size_t)iters, nullptr);
+  // events attached to each dispatch: the kernels' own execution intervals
+  std::vector<hipEvent_t> ev(6 * (size_t)iters, nullptr);
   int rc = PCG_OK;
   for (auto &e : ev)
     if (hipEventCreate(&e) != hipSuccess) rc = PCG_EDEVICE;
@@ -1719,22 +1720,20 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
       if (e == hipSuccess) e = x;
     };
     for (int it = 0; it < iters; ++it) {
-      chain(hipEventRecord(ev[4 * it], s));
-      chain(pcgk::launch_iter_A(ty, L, s));
-      chain(hipEventRecord(ev[4 * it + 1], s));
-      chain(pcgk::launch_iter_GT(ty, L, 0, s));
-      chain(hipEventRecord(ev[4 * it + 2], s));
-      chain(pcgk::launch_iter_G(ty, L, has_eps, 0, s));
-      chain(hipEventRecord(ev[4 * it + 3], s));
+      hipEvent_t *E = &ev[6 * (size_t)it];
+      chain(pcgk::launch_iter_A(ty, L, s, E[0], E[1]));
+      chain(pcgk::launch_iter_GT(ty, L, 0, s, E[2], E[3]));
+      chain(pcgk::launch_iter_G(ty, L, has_eps, 0, s, E[4], E[5]));
     }
     chain(hipStreamSynchronize(s));
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
+      const hipEvent_t *E = &ev[6 * (size_t)it];
       float t;
       for (int k = 0; k < 3; ++k) {
-        chain(hipEventElapsedTime(&t, ev[4 * it + k], ev[4 * it + k + 1]));
+        chain(hipEventElapsedTime(&t, E[2 * k], E[2 * k + 1]));
         acc[k] += t;
       }
-      chain(hipEventElapsedTime(&t, ev[4 * it], ev[4 * it + 3]));
+      chain(hipEventElapsedTime(&t, E[0], E[5]));
       acc[3] += t;
     }
     if (e != hipSuccess) {
