@@ -362,7 +362,7 @@ def main():
     traffic = stored_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "k_iter_A (q = A d fused with the d and x updates and d^T q)",
+                "kernel": "k_iter_A (q = A d with the partial sums of d^T q)",
                 "bytes_per_launch": bytes_a, "avg_launch_ms": ms_a}
     kernels = {name: {"avg_ms": kt["ms"][k], "alg_bytes": kt["bytes"][k],
                       "gbps": kt["bytes"][k] / (kt["ms"][k] * 1e-3) / 1e9}

@@ -115,7 +115,7 @@ typedef struct {
   double relres_true;  /* ||b - A x|| / ||b|| at exit, formed in the vector precision (FP64 under refinement) */
   double relres_rec;   /* recurrence ||r|| / ||b|| at exit */
   double t_solve_ms;   /* single solve: device time; batched: admission to completion (host clock) */
-  double bytes_per_iter; /* algorithmic HBM bytes of one iteration (A, G^T, G once; 12 vector streams) */
+  double bytes_per_iter; /* algorithmic HBM bytes of one iteration (A, G^T, G once; 11 vector streams) */
   double t_latency_ms; /* batched: submission to completion (host clock) */
   double t_queue_ms;   /* batched: submission to admission (host clock) */
 } pcg_result;
@@ -183,8 +183,8 @@ int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device);
  * kernel's own execution interval). ms[0..2]: average duration of the A-,
  * G^T- and G-kernel launches; ms[3]: average iteration (A start to G end).
  * bytes[0..3] (may be NULL): their algorithmic device bytes per launch
- * (A: A's values, columns and row pointers plus 5 vector streams; G^T: G^T
- * plus 4; G: G plus 3, 4 with eps). Needs one prior pcg_solve with b != 0. */
+ * (A: A's values, columns and row pointers plus 2 vector streams; G^T: G^T
+ * plus 4; G: G plus 5, 6 with eps). Needs one prior pcg_solve with b != 0. */
 int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes);
 
 /* Device-to-device copy of `bytes` (rounded down to 16) repeated `reps`
@@ -239,7 +239,7 @@ int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, 
                      const double *val, int32_t *g_rowptr, int32_t *g_col, double *g_val);
 
 /* Algorithmic device bytes of one PCG iteration: A, G^T and G read once,
- * their row pointers, and 12 vector streams of n entries (vec bytes each). */
+ * their row pointers, and 11 vector streams of n entries (vec bytes each). */
 double pcg_bytes_per_iter(int32_t n, int64_t nnz_a, int64_t nnz_g, int a_dtype, int g_dtype, int vec_dtype);
 
 const char *pcg_last_error(const pcg_ctx *ctx);

@@ -341,7 +341,7 @@ void sell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, con
 double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt) {
   const double sa = (double)pcgk::dtype_size(adt), sg = (double)pcgk::dtype_size(gdt),
                sv = (double)pcgk::dtype_size(vdt);
-  return (double)a * (sa + 4) + 2.0 * (double)g * (sg + 4) + 3.0 * 4.0 * (n + 1.0) + 12.0 * n * sv;
+  return (double)a * (sa + 4) + 2.0 * (double)g * (sg + 4) + 3.0 * 4.0 * (n + 1.0) + 11.0 * n * sv;
 }
 
 }  // namespace pcgh

@@ -53,7 +53,7 @@ void sell_columns(int32_t n, const int32_t *rp, const int32_t *ci, const std::ve
 void sell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, const std::vector<int32_t> &so,
                 std::vector<uint8_t> &out);
 
-// Algorithmic bytes of one PCG iteration (12 vector streams).
+// Algorithmic bytes of one PCG iteration (11 vector streams).
 double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt);
 
 }  // namespace pcgh

@@ -137,8 +137,7 @@ struct LaunchSet {
 hipError_t launch_resid(const Types &ty, const LaunchSet &L, int slot_sel, bool with_d, bool reduce,
                         bool respect_done, hipStream_t s);
 
-// A-kernel of iteration i: x += alpha_{i-1} d_{i-1}; q = A d_i; partials of
-// d_i^T q.
+// A-kernel of iteration i: q = A d_i; partials of d_i^T q.
 // Optional events e0/e1 are attached to the dispatch itself (start and end
 // of the kernel's execution), for timing.
 hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s, hipEvent_t e0 = nullptr,
@@ -148,17 +147,20 @@ hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s, hip
 // replaced), 2 (start or restart: r_i given, beta = 0), 3 (0 or 1 per system
 // from its iteration count and replacement period). Forms gamma and
 // alpha_i (or flags breakdown), t = G^T r, partials of ||r||^2 and ||t||^2;
-// publishes st[1].
+// publishes st[1] (a copy of st[0] for a system that had already stopped).
 hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStream_t s, hipEvent_t e0 = nullptr,
                           hipEvent_t e1 = nullptr);
 
 // G-kernel: delta_{i+1}, beta_{i+1}, convergence / maxit / breakdown, iter;
 // publishes st[0]; then, unless stopped, d_{i+1} = (G t + eps r) + beta d_i
-// (beta = 0 in mode 2).
+// (beta = 0 in mode 2), and x += alpha_i d_i (not in mode 2; also when the
+// system stops at this iteration). Reads st[1] only.
 hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
-// x += alpha d_{iter-1} (the pending update), then alpha = 0.
+// x += alpha d_{iter-1} if an update is still pending (alpha != 0), then
+// alpha = 0. The G-kernel applies every update itself and leaves alpha = 0, so
+// this only matters for states written by the host.
 hipError_t launch_finalize(const Types &ty, const LaunchSet &L, hipStream_t s);
 
 // ||b||^2, tol*||b|| into st[0]; ZERO_B status when b = 0.

@@ -7,14 +7,16 @@
 // row products in LDS; then one thread per row adds its products in CSR
 // order. The A, G^T and G products carry the CG vector updates in their
 // gathers and epilogues, so one iteration is three launches:
-//   A-kernel : x += alpha_{i-1} d_{i-1}     (the update deferred from i-1),
-//              q = A d_i,  partials of gamma = d_i^T q;
+//   A-kernel : q = A d_i,  partials of gamma = d_i^T q;
 //   G^T-kernel: alpha_i = delta_i / gamma,
 //              r_{i+1} = r_i - alpha_i q  (formed where it is gathered),
 //              t = G^T r_{i+1}, partials of ||r||^2, ||t||^2;
 //   G-kernel : delta_{i+1} = ||t||^2 + eps ||r||^2 (= r^T M^-1 r),
 //              beta_{i+1} = delta_{i+1} / delta_i, convergence test,
+//              x_{i+1} = x_i + alpha_i d_i (also on the last iteration),
 //              d_{i+1} = (G t + eps r_{i+1}) + beta_{i+1} d_i.
+// That is 11 vector streams of n entries per iteration: A reads d, writes
+// q; G^T reads r and q, writes r and t; G reads t, d and x, writes x and d.
 // d and r alternate between two buffers by iteration parity, so no
 // workgroup overwrites a vector entry another one still gathers.
 //
@@ -41,6 +43,14 @@
 #include "kernels.h"
 
 namespace pcgk {
+
+// The SpMV kernels are memory-latency bound: they are compiled for 8 waves
+// per SIMD (at most 64 VGPRs, checked free of scratch spills), which keeps
+// twice the loads in flight of the 4-6 waves the compiler otherwise picks.
+#ifndef PCG_WAVES_PER_EU
+#define PCG_WAVES_PER_EU 8
+#endif
+#define PCG_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PCG_WAVES_PER_EU)))
 
 // Matrix values and column indices are read exactly once per product:
 // nontemporal loads keep them from displacing the gathered vector entries in
@@ -213,7 +223,10 @@ __device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const 
 // lane loads its row's entries with coalesced loads across the slice, gathers,
 // and adds the products left to right from zero, the CSR order. No LDS and no
 // barrier. The XCD slab split is the one of the row blocks.
-template <typename TACC, typename TM, typename Pre, typename Gather, typename Epi>
+// UW: loads in flight per lane for rows of 32 entries or more (8 pays where a
+// row product gathers one vector and the epilogue holds few operands; under
+// the 64-register budget kernels with two gathers per entry do better with 4).
+template <typename TACC, int UW, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi) {
   constexpr int NW = kBlock / 64;
   const int lane = threadIdx.x & 63;
@@ -228,18 +241,18 @@ __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pr
     if (has) pv = pre(row);
     GLOBAL const int32_t *cc = M.ci + (int64_t)o0 * kSliceRows + lane;
     GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lane;
-    // wide slices (tens of entries per row) keep more loads in flight
-    const TACC sum = wd >= 32 ? slice_row_sum<TACC, 8>(vv, cc, wd, gather) : slice_row_sum<TACC, 4>(vv, cc, wd, gather);
+    const TACC sum = (UW > 4 && wd >= 32) ? slice_row_sum<TACC, UW>(vv, cc, wd, gather)
+                                          : slice_row_sum<TACC, 4>(vv, cc, wd, gather);
     if (has) epi(row, sum, pv);
   }
 }
 
 // All rows of this workgroup (local index l of the system's G workgroups),
 // in either layout.
-template <typename TACC, typename TM, typename Pre, typename Gather, typename Epi>
+template <typename TACC, int UW = 4, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather, Epi epi) {
   if (M.fmt == FMT_SELL) {
-    sell_rows<TACC>(M, l, G, pre, gather, epi);
+    sell_rows<TACC, UW>(M, l, G, pre, gather, epi);
   } else {
     const Sched sc = sched(M.nblk, l, G);
     for (int b = sc.first; b < sc.end; b += sc.stride) stream_block<TACC>(M, b, lds, pre, gather, epi);
@@ -300,8 +313,15 @@ __device__ __forceinline__ void sum_partials(GLOBAL const double *__restrict__ p
 
 // ------------------------------------------------------------------ kernels
 
+// Rows [l n / G, (l+1) n / G) of a system: local workgroup l's share of
+// elementwise work over G workgroups.
+__device__ __forceinline__ void ew_rows(int n, int l, int G, int64_t &i0, int64_t &i1) {
+  i0 = (int64_t)l * n / G;
+  i1 = (int64_t)(l + 1) * n / G;
+}
+
 template <typename TV, typename TA>
-__global__ __launch_bounds__(kBlock) void k_iter_A(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
+__global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_A(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
@@ -310,25 +330,21 @@ __global__ __launch_bounds__(kBlock) void k_iter_A(const SysDev *__restrict__ di
   if (S.done) return;
   const Mat<TA> A = mat<TA>(D.A);
   const int it = S.iter;
-  const TV ap = (TV)S.alpha;
-  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
   GLOBAL TV *__restrict__ q = gl((TV *)D.q);
-  GLOBAL const TV *__restrict__ dold = gl((const TV *)((it & 1) ? D.d0 : D.d1));  // d_{i-1}
   GLOBAL const TV *__restrict__ dcur = gl((const TV *)((it & 1) ? D.d1 : D.d0));  // d_i
   double part[1] = {0.0};
-  for_rows<TV>(
-      A, m.y, D.A.grid, lds, [&](int row) { return RowVals<TV>{dcur[row], dold[row], x[row]}; },
+  for_rows<TV, 8>(
+      A, m.y, D.A.grid, lds, [&](int row) { return RowVals<TV>{dcur[row], (TV)0, (TV)0}; },
       [&](int j) -> TV { return dcur[j]; },
       [&](int row, TV sum, const RowVals<TV> &pv) {
         q[row] = sum;
-        x[row] = pv.c + ap * pv.b;
         part[0] += (double)pv.a * (double)sum;
       });
   put_partials<1>(part, gl(D.pg), part_slot(m.y, D.A.grid), D.A.grid, sh);
 }
 
 template <typename TV, typename TG>
-__global__ __launch_bounds__(kBlock) void k_iter_GT(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+__global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                     int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
@@ -336,7 +352,10 @@ __global__ __launch_bounds__(kBlock) void k_iter_GT(const SysDev *__restrict__ d
   const SysDev &D = dir[m.x];
   GLOBAL State *st = gl(D.st);
   GLOBAL const State &S = st[0];
-  if (S.done) return;
+  if (S.done) {  // stopped earlier: st[1] mirrors st[0], so the G-kernel need not read st[0]
+    if (m.y == 0 && threadIdx.x == 0) st_state(st + 1, ld_state(&S));
+    return;
+  }
   const int it = S.iter;
   if (mode == 3) mode = (S.rr_period > 0 && it > 0 && it % S.rr_period == 0) ? 1 : 0;
   double alpha = S.alpha, gamma = S.gamma;
@@ -391,16 +410,17 @@ __global__ __launch_bounds__(kBlock) void k_iter_GT(const SysDev *__restrict__ d
 }
 
 template <typename TV, typename TG, bool HAS_EPS>
-__global__ __launch_bounds__(kBlock) void k_iter_G(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+__global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_G(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                    int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
   GLOBAL State *st = gl(D.st);
-  if (st[0].done) return;  // stopped before this iteration's G^T-kernel ran
+  // st[1] is the G^T-kernel's publication for this iteration; st[0] is written
+  // below by workgroup 0 and must not be read by the others
   GLOBAL const State &S = st[1];
-  if (S.done) {  // the G^T-kernel flagged a breakdown: publish it
+  if (S.done) {  // stopped earlier, or the G^T-kernel flagged a breakdown
     if (m.y == 0 && threadIdx.x == 0) st_state(st, ld_state(&S));
     return;
   }
@@ -422,6 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_G(const SysDev *__restrict__ di
     o.rr = rr;
     o.tt = tt;
     o.iter = i1;
+    o.alpha = 0.0;  // x += alpha_i d_i is applied below, whatever the status
     if (status != ST_BREAK_DELTA) {
       o.beta = (mode == 2) ? 0.0 : dn / S.delta;
       o.delta = dn;
@@ -432,27 +453,49 @@ __global__ __launch_bounds__(kBlock) void k_iter_G(const SysDev *__restrict__ di
     }
     st_state(st, o);
   }
-  if (status != ST_RUNNING) return;
+  // x_{i+1} = x_i + alpha_i d_i (not at a start or restart, mode 2)
+  const bool upd = mode != 2;
+  const TV ap = (TV)S.alpha;
+  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
+  GLOBAL const TV *__restrict__ dprev = gl((const TV *)((i1 & 1) ? D.d0 : D.d1));  // d_i
+  if (status != ST_RUNNING) {
+    if (upd) {
+      int64_t i0, i1r;
+      ew_rows(D.n, m.y, D.G.grid, i0, i1r);
+      for (int64_t i = i0 + threadIdx.x; i < i1r; i += kBlock) x[i] = x[i] + ap * dprev[i];
+    }
+    return;
+  }
   // s = G t + eps r, and the next direction d_{i+1} = s + beta d_i (at a
   // start or restart beta = 0, d = s)
   const Mat<TG> G = mat<TG>(D.G);
   GLOBAL const TV *__restrict__ t = gl((const TV *)D.t);
   GLOBAL const TV *__restrict__ rc = gl((const TV *)((i1 & 1) ? D.r1 : D.r0));
-  GLOBAL const TV *__restrict__ dprev = gl((const TV *)((i1 & 1) ? D.d0 : D.d1));
   GLOBAL TV *__restrict__ dnext = gl((TV *)((i1 & 1) ? D.d1 : D.d0));
   const TV eps = (TV)S.eps;
   const TV beta = (TV)((mode == 2) ? 0.0 : dn / S.delta);
-  for_rows<TV>(
-      G, m.y, D.G.grid, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], (TV)0}; },
-      [&](int j) -> TV { return t[j]; },
-      [&](int row, TV sum, const RowVals<TV> &pv) {
-        const TV sv = HAS_EPS ? sum + eps * pv.a : sum;
-        dnext[row] = sv + beta * pv.b;
-      });
+  if (upd)
+    for_rows<TV>(
+        G, m.y, D.G.grid, lds,
+        [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], x[row]}; },
+        [&](int j) -> TV { return t[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          const TV sv = HAS_EPS ? sum + eps * pv.a : sum;
+          dnext[row] = sv + beta * pv.b;
+          x[row] = pv.c + ap * pv.b;
+        });
+  else
+    for_rows<TV>(
+        G, m.y, D.G.grid, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], (TV)0}; },
+        [&](int j) -> TV { return t[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          const TV sv = HAS_EPS ? sum + eps * pv.a : sum;
+          dnext[row] = sv + beta * pv.b;
+        });
 }
 
 template <typename TV, typename TA>
-__global__ __launch_bounds__(kBlock) void k_resid(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+__global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_resid(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                   int slot_sel, int with_d, int reduce, int respect_done) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ double sh[4 * (kBlock / 64)];
@@ -491,11 +534,6 @@ __global__ __launch_bounds__(kBlock) void k_resid(const SysDev *__restrict__ dir
   if (reduce) put_partials<1>(part, gl(D.ptr), part_slot(m.y, D.A.grid), D.A.grid, sh);
 }
 
-// Rows [l n / G, (l+1) n / G) of a system for elementwise work on A's map.
-__device__ __forceinline__ void ew_rows(int n, int l, int G, int64_t &i0, int64_t &i1) {
-  i0 = (int64_t)l * n / G;
-  i1 = (int64_t)(l + 1) * n / G;
-}
 
 template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_finalize(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
@@ -609,10 +647,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_state(const SysDev *__restric
 }
 
 template <typename TV, typename TM>
-__global__ __launch_bounds__(kBlock) void k_spmv(DevCSR Md, const TV *__restrict__ x, TV *__restrict__ y) {
+__global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmv(DevCSR Md, const TV *__restrict__ x, TV *__restrict__ y) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   const Mat<TM> M = mat<TM>(Md);
-  for_rows<TV>(
+  for_rows<TV, 8>(
       M, blockIdx.x, gridDim.x, lds, [&](int) { return RowVals<TV>{}; }, [&](int j) -> TV { return x[j]; },
       [&](int row, TV sum, const RowVals<TV> &) { y[row] = sum; });
 }

@@ -1754,9 +1754,9 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
     const double sa = (double)pcgk::dtype_size(ctx->cfg.a_dtype), sg = (double)pcgk::dtype_size(ctx->cfg.g_dtype),
                  sv = (double)pcgk::dtype_size(ctx->cfg.vec_dtype);
     const double rp = 4.0 * (n + 1.0);
-    bytes[0] = (double)S.nnz_a * (sa + 4) + rp + 5.0 * n * sv;
+    bytes[0] = (double)S.nnz_a * (sa + 4) + rp + 2.0 * n * sv;
     bytes[1] = (double)S.nnz_g * (sg + 4) + rp + 4.0 * n * sv;
-    bytes[2] = (double)S.nnz_g * (sg + 4) + rp + (has_eps ? 4.0 : 3.0) * n * sv;
+    bytes[2] = (double)S.nnz_g * (sg + 4) + rp + (has_eps ? 6.0 : 5.0) * n * sv;
     bytes[3] = bytes[0] + bytes[1] + bytes[2];
   }
   return PCG_OK;

@@ -106,9 +106,9 @@ def test_library_jacobi_identity():
 def test_bytes_per_iter_formula():
     n, a, g = 2_097_152, 14_581_760, 8_339_456
     got = pcg.bytes_per_iter(n, a, g, pcg.F64, pcg.F64, pcg.F64)
-    assert got == a * 12 + 2 * g * 12 + 12 * (n + 1) + 12 * n * 8
+    assert got == a * 12 + 2 * g * 12 + 12 * (n + 1) + 11 * n * 8
     got32 = pcg.bytes_per_iter(n, a, g, pcg.F32, pcg.BF16, pcg.F32)
-    assert got32 == a * 8 + 2 * g * 6 + 12 * (n + 1) + 12 * n * 4
+    assert got32 == a * 8 + 2 * g * 6 + 12 * (n + 1) + 11 * n * 4
 
 
 def test_create_without_gpu_fails_cleanly():
