@@ -92,7 +92,10 @@ typedef struct {
   int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */
   int mem_budget_mb; /* device memory pool for batched / served systems, MiB (0: half the free memory at first use) */
   int layout;        /* storage of A, G, G^T: PCG_LAYOUT_AUTO (default), PCG_LAYOUT_CSR or PCG_LAYOUT_SELL */
-  int reserved[6];
+  int g_device;      /* 1: pcg_build_precond(PCG_G_FSAI) factors on the device (one wave per row; same
+                        arithmetic as the host builder); falls back to the host for tril rows longer
+                        than 80 or a structurally unsymmetric A. 0 (default): on the host */
+  int reserved[5];
 } pcg_config;
 
 /* Matrix storage layouts (pcg_config.layout). Both give bit-identical

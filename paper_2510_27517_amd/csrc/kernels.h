@@ -191,6 +191,31 @@ hipError_t launch_fill(int dtype, void *p, int64_t n, double value, hipStream_t 
 // x64 += scale * (double) c  (iterative refinement update)
 hipError_t launch_refine_update(int32_t n, double *x64, const void *c, int c_dtype, double scale, hipStream_t s);
 
+// ---- FSAI construction on the device (classic FSAI on tril(A), G = G_L^T)
+//
+// A in CSR with FP64 values; dpos[i] = position of row i's diagonal; lrp =
+// row pointers of tril(A), the pattern of G_L. One wave per row i gathers
+// A[J,J] (J = tril pattern of row i) into LDS, factors it A[J,J] = L L^T and
+// writes row i of G_L = L^-T e_last into lv[lrp[i]..], with the arithmetic
+// of the host builder in the same order. err[0] = 1 on a non-positive pivot.
+// mmax (the longest tril row) sizes the LDS: at most kFsaiMaxRow.
+constexpr int kFsaiMaxRow = 80;
+hipError_t launch_fsai_rows(const int32_t *rp, const int32_t *ci, const double *v, const int32_t *dpos,
+                            const int32_t *lrp, int32_t n, int32_t mmax, double *lv, int32_t *err, int grid,
+                            hipStream_t s);
+
+// part[b] = max |x[k]| over workgroup b's share (grid = 1024 workgroups).
+hipError_t launch_absmax(const double *x, int64_t m, double *part, hipStream_t s);
+constexpr int kAbsmaxGrid = 1024;
+
+// Writes G_L (times scale, rounded to the storage type) into GT's storage and
+// G_L^T into G's storage, each in its layout. G's row j holds the entries of
+// A's row j from its diagonal on (A structurally symmetric); err[0] = 2 when
+// an entry has no counterpart there.
+hipError_t launch_fsai_place(const int32_t *rp, const int32_t *ci, const int32_t *dpos, const int32_t *lrp,
+                             const double *lv, int32_t n, double scale, const DevCSR &GT, const DevCSR &G,
+                             int32_t *err, hipStream_t s);
+
 // dst = src, `bytes` a multiple of 16.
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int grid, hipStream_t s);
 

@@ -686,6 +686,176 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, 
     dst[i] = src[i];
 }
 
+// ------------------------------------------------ FSAI construction on the device
+
+// One wave (the whole workgroup) per row; LDS holds S = A[J,J] (m x m,
+// row-major), g (m) and J (m).
+__global__ __launch_bounds__(64) void k_fsai_rows(const int32_t *__restrict__ rp_, const int32_t *__restrict__ ci_,
+                                                  const double *__restrict__ v_, const int32_t *__restrict__ dpos_,
+                                                  const int32_t *__restrict__ lrp_, int32_t n, int32_t mmax,
+                                                  double *__restrict__ lv_, int32_t *__restrict__ err_) {
+  extern __shared__ double smem[];
+  GLOBAL const int32_t *rp = gl(rp_), *ci = gl(ci_), *dpos = gl(dpos_), *lrp = gl(lrp_);
+  GLOBAL const double *v = gl(v_);
+  GLOBAL double *lv = gl(lv_);
+  GLOBAL int32_t *err = gl(err_);
+  double *S = smem;
+  double *g = smem + (size_t)mmax * mmax;
+  int32_t *J = (int32_t *)(g + mmax);
+  const int lane = threadIdx.x;
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int32_t r0 = rp[i];
+    const int m = dpos[i] - r0 + 1;
+    for (int a = lane; a < m; a += 64) J[a] = ci[r0 + a];
+    __syncthreads();
+    // lower part of S: S[a][b] = A[J[a], J[b]] (b <= a), merging row J[a]'s
+    // columns up to its diagonal with J
+    for (int a = lane; a < m; a += 64) {
+      const int32_t row = J[a];
+      int32_t k = rp[row];
+      const int32_t kend = dpos[row];
+      double *Sa = S + (size_t)a * m;
+      int b = 0;
+      while (b <= a) {
+        if (k > kend) {
+          Sa[b++] = 0.0;
+          continue;
+        }
+        const int32_t c = ci[k], jb = J[b];
+        if (c == jb) {
+          Sa[b++] = v[k++];
+        } else if (c < jb) {
+          ++k;
+        } else {
+          Sa[b++] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    // Cholesky, column by column: the pivot by lane 0, the column below it by
+    // one lane per entry, each sum left to right
+    for (int c = 0; c < m; ++c) {
+      if (lane == 0) {
+        double dsum = S[(size_t)c * m + c];
+        for (int k = 0; k < c; ++k) dsum -= S[(size_t)c * m + k] * S[(size_t)c * m + k];
+        if (!(dsum > 0.0)) {
+          err[0] = 1;
+          dsum = 1.0;
+        }
+        S[(size_t)c * m + c] = sqrt(dsum);
+      }
+      __syncthreads();
+      const double l = S[(size_t)c * m + c];
+      for (int a = c + 1 + lane; a < m; a += 64) {
+        double e = S[(size_t)a * m + c];
+        for (int k = 0; k < c; ++k) e -= S[(size_t)a * m + k] * S[(size_t)c * m + k];
+        S[(size_t)a * m + c] = e / l;
+      }
+      __syncthreads();
+    }
+    // back substitution L^T g = e_last
+    if (lane == 0) {
+      const int32_t base = lrp[i];
+      for (int a = m - 1; a >= 0; --a) {
+        double e = (a == m - 1) ? 1.0 : 0.0;
+        for (int k = a + 1; k < m; ++k) e -= S[(size_t)k * m + a] * g[k];
+        g[a] = e / S[(size_t)a * m + a];
+        lv[base + a] = g[a];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_absmax(const double *__restrict__ x, int64_t m, double *__restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  double a = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock)
+    a = fmax(a, fabs(x[k]));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) a = fmax(a, __shfl_xor(a, off));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) a = fmax(a, sh[w]);
+    part[blockIdx.x] = a;
+  }
+}
+
+// Rounding to nearest even onto a format with `sig` significant bits, least
+// normal exponent emin and largest finite value vmax (subnormals included,
+// beyond vmax: infinity); every step is exact.
+__device__ double round_sig(double v, int sig, int emin, double vmax) {
+  if (v == 0.0 || !isfinite(v)) return v;
+  int e;
+  frexp(fabs(v), &e);
+  int q = e - sig;
+  if (e - 1 < emin) q = emin - (sig - 1);
+  double r = ldexp(rint(ldexp(fabs(v), -q)), q);
+  if (r > vmax) r = INFINITY;
+  return copysign(r, v);
+}
+
+__device__ uint16_t bf16_bits(double v) {
+  return (uint16_t)(__float_as_uint((float)round_sig(v, 8, -126, 3.3895313892515355e38)) >> 16);
+}
+
+__device__ uint16_t f16_bits(double v) {
+  const double r = round_sig(v, 11, -14, 65504.0);
+  if (isinf(r)) return r > 0 ? 0x7C00 : 0xFC00;
+  if (isnan(r)) return 0x7E00;
+  const uint16_t sign = signbit(r) ? 0x8000 : 0;
+  const double a = fabs(r);
+  if (a == 0.0) return sign;
+  int e;
+  const double mnt = frexp(a, &e);  // a = mnt 2^e, mnt in [0.5, 1)
+  if (e - 1 >= -14) return sign | (uint16_t)((e - 1 + 15) << 10) | (uint16_t)rint((mnt * 2.0 - 1.0) * 1024.0);
+  return sign | (uint16_t)rint(a * 16777216.0);  // subnormal: multiples of 2^-24
+}
+
+__device__ __forceinline__ void store_val(const DevCSR &M, int32_t row, int32_t idx, double x) {
+  const int64_t p = (M.fmt == FMT_SELL)
+                        ? ((int64_t)gl(M.blk)[row / kSliceRows] + idx) * kSliceRows + row % kSliceRows
+                        : (int64_t)gl(M.rp)[row] + idx;
+  switch (M.dtype) {
+    case F64: gl((double *)M.val)[p] = x; break;
+    case F32: gl((float *)M.val)[p] = (float)x; break;
+    case BF16: gl((uint16_t *)M.val)[p] = bf16_bits(x); break;
+    default: gl((uint16_t *)M.val)[p] = f16_bits(x); break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fsai_place(const int32_t *__restrict__ rp_, const int32_t *__restrict__ ci_,
+                                                       const int32_t *__restrict__ dpos_,
+                                                       const int32_t *__restrict__ lrp_, const double *__restrict__ lv_,
+                                                       int32_t n, double scale, DevCSR GT, DevCSR G,
+                                                       int32_t *__restrict__ err_) {
+  GLOBAL const int32_t *rp = gl(rp_), *ci = gl(ci_), *dpos = gl(dpos_), *lrp = gl(lrp_);
+  GLOBAL const double *lv = gl(lv_);
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const int32_t r0 = rp[i], m = dpos[i] - r0 + 1, base = lrp[i];
+    for (int32_t k = 0; k < m; ++k) {
+      const int32_t j = ci[r0 + k];
+      const double x = lv[base + k] * scale;
+      store_val(GT, i, k, x);
+      // entry (j, i) of G = G_L^T: its rank in the upper part of A's row j
+      int32_t lo = dpos[j], hi = rp[j + 1] - 1;
+      while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (ci[mid] < i)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo > rp[j + 1] - 1 || ci[lo] != i) {
+        gl(err_)[0] = 2;
+        continue;
+      }
+      store_val(G, j, lo - dpos[j], x);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline int ew_grid(int64_t n) {
@@ -843,6 +1013,29 @@ hipError_t launch_refine_update(int32_t n, double *x64, const void *c, int c_dty
   PCG_DISPATCH_V(c_dtype, TC, {
     hipLaunchKernelGGL((k_refine_update<TC>), dim3(ew_grid(n)), dim3(kBlock), 0, s, n, x64, (const TC *)c, scale);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_fsai_rows(const int32_t *rp, const int32_t *ci, const double *v, const int32_t *dpos,
+                            const int32_t *lrp, int32_t n, int32_t mmax, double *lv, int32_t *err, int grid,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (mmax < 1 || mmax > kFsaiMaxRow) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * ((size_t)mmax * mmax + mmax) + sizeof(int32_t) * mmax;
+  hipLaunchKernelGGL(k_fsai_rows, dim3(grid), dim3(64), lds, s, rp, ci, v, dpos, lrp, n, mmax, lv, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const double *x, int64_t m, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_absmax, dim3(kAbsmaxGrid), dim3(kBlock), 0, s, x, m, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_fsai_place(const int32_t *rp, const int32_t *ci, const int32_t *dpos, const int32_t *lrp,
+                             const double *lv, int32_t n, double scale, const DevCSR &GT, const DevCSR &G,
+                             int32_t *err, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fsai_place, dim3(ew_grid(n)), dim3(kBlock), 0, s, rp, ci, dpos, lrp, lv, n, scale, GT, G, err);
   return hipGetLastError();
 }
 

@@ -127,12 +127,13 @@ struct HostMat {
   int64_t nnz = 0;           // nonzeros of the matrix (padding excluded)
   std::vector<int32_t> rp;   // CSR row pointers (FMT_CSR only)
   std::vector<int32_t> ci;   // columns in storage order
-  std::vector<uint8_t> val;  // values in dt, in storage order
+  std::vector<uint8_t> val;  // values in dt, in storage order (empty: written on the device)
   std::vector<int32_t> blk;  // row-block pairs (FMT_CSR) or slice offsets (FMT_SELL)
   int32_t nunits = 0, grid = 8;
+  size_t val_bytes() const { return pcgk::dtype_size(dt) * std::max<size_t>(ci.size(), 1); }
   size_t bytes() const {
-    return align_up(4 * rp.size()) + align_up(4 * std::max<size_t>(ci.size(), 1)) +
-           align_up(std::max<size_t>(val.size(), 1)) + align_up(4 * blk.size());
+    return align_up(4 * rp.size()) + align_up(4 * std::max<size_t>(ci.size(), 1)) + align_up(val_bytes()) +
+           align_up(4 * blk.size());
   }
 };
 
@@ -210,21 +211,19 @@ bool use_sell(int layout, int32_t n, const int32_t *rp) {
   return stored <= nnz + nnz / 8;
 }
 
-// Lay out one matrix with values v (CSR order) times `scale` in dt; the row
-// blocks (CSR) are sized for products in vector type vdt.
-void make_mat(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
-              int dt, double scale, int vdt, HostMat &M) {
+// Lay out one matrix's pattern (no values); the row blocks (CSR) are sized for
+// products in vector type vdt.
+void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, int dt, int vdt,
+                  HostMat &M) {
   M.n = n;
   M.nnz = rp[n];
   M.dt = dt;
-  std::vector<uint8_t> csr_val;
-  cast_values(v, M.nnz, dt, scale, csr_val);
+  M.val.clear();
   if (use_sell(cfg.layout, n, rp)) {
     M.fmt = pcgk::FMT_SELL;
     M.rp.clear();
     pcgh::sell_offsets(n, rp, M.blk);
     pcgh::sell_columns(n, rp, ci, M.blk, M.ci);
-    pcgh::sell_bytes(n, rp, csr_val.data(), pcgk::dtype_size(dt), M.blk, M.val);
     M.nunits = (int32_t)M.blk.size() - 1;
     const int32_t rounds = (M.nunits + pcgk::kBlock / 64 - 1) / (pcgk::kBlock / 64);
     M.grid = grid_for(cus, cfg.grid_mult, rounds);
@@ -232,11 +231,22 @@ void make_mat(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, cons
     M.fmt = pcgk::FMT_CSR;
     M.rp.assign(rp, rp + n + 1);
     M.ci.assign(ci, ci + M.nnz);
-    M.val.swap(csr_val);
     M.blk = pcgh::row_blocks(n, rp, pcgk::lds_cap(vdt));
     M.nunits = (int32_t)(M.blk.size() / 2 - 1);
     M.grid = grid_for(cus, cfg.grid_mult, M.nunits);
   }
+}
+
+// Lay out one matrix with values v (CSR order) times `scale` in dt.
+void make_mat(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+              int dt, double scale, int vdt, HostMat &M) {
+  make_pattern(cfg, cus, n, rp, ci, dt, vdt, M);
+  std::vector<uint8_t> csr_val;
+  cast_values(v, M.nnz, dt, scale, csr_val);
+  if (M.fmt == pcgk::FMT_SELL)
+    pcgh::sell_bytes(n, rp, csr_val.data(), pcgk::dtype_size(dt), M.blk, M.val);
+  else
+    M.val.swap(csr_val);
 }
 
 void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
@@ -322,11 +332,11 @@ hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, hipStream_t s) {
   };
   int32_t *drp = H.rp.empty() ? nullptr : (int32_t *)c.take(4 * H.rp.size());
   int32_t *dci = (int32_t *)c.take(4 * std::max<size_t>(H.ci.size(), 1));
-  void *dval = c.take(std::max<size_t>(H.val.size(), 1));
+  void *dval = c.take(H.val_bytes());
   int32_t *dblk = (int32_t *)c.take(4 * H.blk.size());
   if (drp) chain(h2d(drp, H.rp.data(), 4 * H.rp.size(), s));
   chain(h2d(dci, H.ci.data(), 4 * H.ci.size(), s));
-  chain(h2d(dval, H.val.data(), H.val.size(), s));
+  if (!H.val.empty()) chain(h2d(dval, H.val.data(), H.val.size(), s));
   chain(h2d(dblk, H.blk.data(), 4 * H.blk.size(), s));
   M.rp = drp;
   M.ci = dci;
@@ -1565,11 +1575,140 @@ int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr,
   return set_g_from_host(ctx, hrp, hci, hv);
 }
 
+// FSAI factored on the device: the host lays out the patterns of G = triu(A)
+// and G^T = tril(A) (O(nnz) integer work), the device computes G_L's values
+// row by row and writes them, cast, into both layouts. Returns 1 (nothing
+// changed) when the host builder must be used instead.
+static int build_fsai_device(pcg_ctx *ctx) {
+  Sys &S = ctx->single;
+  const int32_t n = S.n;
+  const int32_t *rp = ctx->a_rp.data(), *ci = ctx->a_ci.data();
+  const double *v = ctx->a_val.data();
+  std::vector<int32_t> dpos(n), lrp(n + 1, 0), lci, grp(n + 1, 0), gci;
+  int32_t mmax = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t d = -1;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) d = k;
+    if (d < 0) {
+      ctx->err = "pcg_build_precond: FSAI needs a stored diagonal in every row";
+      return PCG_EINVAL;
+    }
+    dpos[i] = d;
+    mmax = std::max(mmax, d - rp[i] + 1);
+    lrp[i + 1] = lrp[i] + (d - rp[i] + 1);
+    grp[i + 1] = grp[i] + (rp[i + 1] - d);
+  }
+  if (mmax > pcgk::kFsaiMaxRow || lrp[n] != grp[n]) return 1;  // long rows or unsymmetric counts
+  lci.resize(lrp[n]);
+  gci.resize(grp[n]);
+  for (int32_t i = 0; i < n; ++i) {
+    std::copy(ci + rp[i], ci + dpos[i] + 1, lci.begin() + lrp[i]);
+    std::copy(ci + dpos[i], ci + rp[i + 1], gci.begin() + grp[i]);
+  }
+  drop_graphs(ctx);
+  if (S.blkG) {
+    (void)hipFree(S.blkG);
+    S.blkG = nullptr;
+  }
+  ctx->have_g = false;
+  GPart P;
+  P.n = n;
+  P.nnz = lrp[n];
+  P.gdt = ctx->cfg.g_dtype;
+  P.vdt = ctx->cfg.vec_dtype;
+  make_pattern(ctx->cfg, ctx->cus, n, grp.data(), gci.data(), P.gdt, P.vdt, P.G);
+  make_pattern(ctx->cfg, ctx->cus, n, lrp.data(), lci.data(), P.gdt, P.vdt, P.GT);
+  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * (size_t)P.GT.grid);
+  // temporaries: A (CSR, FP64), dpos, lrp, G_L's values, flags, partial maxima
+  const int64_t nnz = rp[n], nl = lrp[n];
+  const size_t tb = align_up(4 * (size_t)(n + 1)) + align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) +
+                    align_up(8 * (size_t)std::max<int64_t>(nnz, 1)) + align_up(4 * (size_t)n) +
+                    align_up(4 * (size_t)(n + 1)) + align_up(8 * (size_t)std::max<int64_t>(nl, 1)) + align_up(8) +
+                    align_up(8 * (size_t)pcgk::kAbsmaxGrid);
+  void *blk = nullptr, *tmp = nullptr;
+  if (hipMalloc(&blk, P.bytes) != hipSuccess || hipMalloc(&tmp, tb) != hipSuccess) {
+    (void)hipGetLastError();
+    if (blk) (void)hipFree(blk);
+    ctx->err = "pcg_build_precond: device allocation failed";
+    return PCG_ENOMEM;
+  }
+  S.blkG = blk;
+  hipStream_t s = ctx->stream;
+  Carver c{(uint8_t *)tmp};
+  int32_t *d_rp = (int32_t *)c.take(4 * (size_t)(n + 1));
+  int32_t *d_ci = (int32_t *)c.take(4 * (size_t)std::max<int64_t>(nnz, 1));
+  double *d_v = (double *)c.take(8 * (size_t)std::max<int64_t>(nnz, 1));
+  int32_t *d_dpos = (int32_t *)c.take(4 * (size_t)n);
+  int32_t *d_lrp = (int32_t *)c.take(4 * (size_t)(n + 1));
+  double *d_lv = (double *)c.take(8 * (size_t)std::max<int64_t>(nl, 1));
+  int32_t *d_err = (int32_t *)c.take(8);
+  double *d_part = (double *)c.take(8 * (size_t)pcgk::kAbsmaxGrid);
+  int rc = PCG_OK;
+  int32_t herr[2] = {0, 0};
+  auto run = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    auto chain = [&](hipError_t x) {
+      if (e == hipSuccess) e = x;
+    };
+    chain(place_g(P, blk, S, s));  // patterns (no values yet)
+    // the sliced layout's padding must hold zeros (outside any graph capture)
+    chain(hipMemsetAsync((void *)S.dev.G.val, 0, P.G.val_bytes(), s));
+    chain(hipMemsetAsync((void *)S.dev.GT.val, 0, P.GT.val_bytes(), s));
+    chain(h2d(d_rp, rp, 4 * (size_t)(n + 1), s));
+    chain(h2d(d_ci, ci, 4 * (size_t)nnz, s));
+    chain(h2d(d_v, v, 8 * (size_t)nnz, s));
+    chain(h2d(d_dpos, dpos.data(), 4 * (size_t)n, s));
+    chain(h2d(d_lrp, lrp.data(), 4 * (size_t)(n + 1), s));
+    chain(h2d(d_err, herr, 8, s));
+    const int grid = (int)std::min<int64_t>(n, (int64_t)ctx->cus * 16);
+    chain(pcgk::launch_fsai_rows(d_rp, d_ci, d_v, d_dpos, d_lrp, n, mmax, d_lv, d_err, grid, s));
+    double scale = 1.0;
+    if (P.gdt == pcgk::F16) {  // same power-of-two scale as the host path
+      std::vector<double> part(pcgk::kAbsmaxGrid);
+      chain(pcgk::launch_absmax(d_lv, nl, d_part, s));
+      chain(hipMemcpyAsync(part.data(), d_part, 8 * part.size(), hipMemcpyDeviceToHost, s));
+      chain(hipStreamSynchronize(s));
+      double mx = 0.0;
+      for (double x : part) mx = std::max(mx, x);
+      if (mx > 0) {
+        int ex;
+        std::frexp(mx, &ex);
+        scale = std::ldexp(1.0, 14 - ex);
+      }
+    }
+    chain(pcgk::launch_fsai_place(d_rp, d_ci, d_dpos, d_lrp, d_lv, n, scale, S.dev.GT, S.dev.G, d_err, s));
+    chain(hipMemcpyAsync(herr, d_err, 8, hipMemcpyDeviceToHost, s));
+    chain(hipStreamSynchronize(s));
+    S.g_scale = scale;
+    return e;
+  };
+  const hipError_t e = run();
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    ctx->err = std::string("pcg_build_precond: ") + hipGetErrorString(e);
+    return PCG_EDEVICE;
+  }
+  if (herr[0] == 2) return 1;  // pattern not symmetric: the host builder handles it
+  if (herr[0] == 1) {
+    ctx->err = "pcg_build_precond: FSAI pivot not positive (A not SPD)";
+    return PCG_EBREAKDOWN;
+  }
+  if ((rc = single_sets(ctx))) return rc;
+  ctx->have_g = true;
+  return PCG_OK;
+}
+
 int pcg_build_precond(pcg_ctx *ctx, int kind, uint64_t seed) {
   if (!ctx) return PCG_EINVAL;
   if (!ctx->have_a) {
     ctx->err = "pcg_build_precond: set the matrix first";
     return PCG_ESTATE;
+  }
+  if (kind == PCG_G_FSAI && ctx->cfg.g_device) {
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    const int rd = build_fsai_device(ctx);
+    if (rd != 1) return rd;  // 1: use the host builder
   }
   std::vector<int32_t> grp, gci;
   std::vector<double> gv;
