@@ -17,6 +17,8 @@ Further sections, each under its own key of the same JSON line:
   serving    random-geometric-graph Laplacian requests arriving as a Poisson
              stream at 0.5, 0.8 and 0.95 of the measured closed-loop rate:
              p50/p99 latency, queue depth and admitted bytes;
+  sai_loss   the SAI/L2/cosine preconditioner losses (Sec. 3.3) over 32
+             Gaussian probes on the 128^3 system;
   elasticity Q1 elasticity, 64^3 free nodes x 3 dof (n = 786,432, 61.7M
              nonzeros): BF16/FP16 G with FP64 refinement to 1e-10 against the
              plain FP64 solve.
@@ -46,7 +48,7 @@ TOL = 1e-8
 MAXIT = 5000
 KERNEL_SOURCES = ["paper_2510_27517_amd/csrc/kernels.hip", "paper_2510_27517_amd/csrc/kernels.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iter_A_poisson3d_128_f64_traffic.md")
-SECTIONS = ["mixed", "batched", "serving", "elasticity"]
+SECTIONS = ["mixed", "sai_loss", "batched", "serving", "elasticity"]
 
 
 def log(*a):
@@ -124,6 +126,31 @@ def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
             "time_to_tol_ms": round(ms, 3), "speedup_vs_fp64": round(t_fp64_ms / ms, 3), "status": r.status,
             "inner_iters": r.iters, "outer_iters": r.outer_iters, "relres_true_fp64": r.relres_true,
             "alg_bytes_per_inner_iter": r.bytes_per_iter}, r.x.cpu().numpy()
+
+
+def section_sai_loss(pcg, inputs, A, G, k, reps=3):
+    """The SAI/L2/cosine losses of Sec. 3.3 for k Gaussian probes on the 128^3
+    system with its FSAI G (three multi-probe products and the sums)."""
+    import torch
+
+    W = torch.from_numpy(inputs.normal(0, inputs.STREAM_PROBE, A.n * k).reshape(A.n, k)).to("cuda:0")
+    with pcg.Solver(pcg.default_config()) as s:
+        s.set_matrix(A)
+        s.set_precond(rowptr=G[0], col=G[1], val=G[2])
+        out = s.sai_loss(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = s.sai_loss(W)
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+    # each product streams its matrix once and two n x k probe blocks
+    mat = A.nnz * 12 + 2 * int(G[1].shape[0]) * 12 + 3 * 4 * (A.n + 1)
+    vec = (2 + 2 + 3 + 2) * A.n * k * 8
+    return {"workload": f"SAI, L2 and cosine losses, 128^3 FSAI, {k} N(0,1) probes (FP64)", "probes": k,
+            "ms_per_call": round(ms, 3), "probes_per_s": round(k / (ms * 1e-3), 1),
+            "alg_gbps": round((mat + vec) / (ms * 1e-3) / 1e9, 1), "sai_mean": float(np.mean(out["sai"])),
+            "l2_mean": float(np.mean(out["l2"])), "cs_mean": float(np.mean(out["cs"])),
+            "note": "probes resident on the device; scratch kept by the context after the first call"}
 
 
 def batch_systems(inputs, count):
@@ -311,6 +338,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--sections", default=",".join(SECTIONS), help="comma list of " + ",".join(SECTIONS) + " or none")
+    ap.add_argument("--probes", type=int, default=32)
     ap.add_argument("--batch-systems", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-step", type=int, default=10)
@@ -397,6 +425,9 @@ def main():
         log("mixed precision")
         extra["mixed"], sols["mixed_f32_bf16_refined"] = section_mixed(pcg, torch, A, G, b_dev, max(3, args.steps // 2),
                                                                        ms_per_step)
+    if "sai_loss" in sections:
+        log("sai loss")
+        extra["sai_loss"] = section_sai_loss(pcg, inputs, A, G, args.probes)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -179,6 +179,25 @@ int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, i
  * context's vector precision (values at the boundary are float64). */
 int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device);
 
+/* Preconditioner-quality losses over k probe vectors (Sec. 3.3, the loss
+ * function: the Hutchinson estimate of a Frobenius norm by products with
+ * i.i.d. N(0,1) probes, Eq. "loss-initial"; the scale-invariant SAI loss of
+ * Eq. "our-loss" with ||A|| = mean |A_ij| over the nonzeros; the L2 and
+ * cosine-similarity losses of the loss ablation). With y = A M^-1 w and
+ * M^-1 = G G^T + eps I for the context's stored A, G and eps, for each probe
+ * p (column p of W):
+ *   sai[p] = || y / ||A|| - w ||^2,   l2[p] = || y - w ||^2,
+ *   cs[p]  = w^T y / (||w|| ||y||).
+ * Their means over the probes estimate ||A M^-1 / ||A|| - I||_F^2 and
+ * ||A M^-1 - I||_F^2. W: n x k, row-major (probe p of row i at W[i*k + p]),
+ * FP64, host or device memory (on_device), borrowed for the call; sai, l2,
+ * cs: host arrays of k doubles, each may be NULL. Products run in FP64 on the
+ * stored values (rounded to their storage types); each row is summed in CSR
+ * order. Uses 3 n k doubles of device scratch, allocated at the first call
+ * that needs more and kept by the context until pcg_destroy.
+ * PCG_EINVAL (k < 1, null W), PCG_ESTATE (A or G unset), PCG_ENOMEM. */
+int pcg_sai_loss(pcg_ctx *ctx, int32_t k, const double *W, int on_device, double *sai, double *l2, double *cs);
+
 /* Measurement. Runs `iters` CG iterations of the stored system (a fresh
  * solve of the last right-hand side from x0 = 0 that never stops; the
  * context's vectors are overwritten) as plain launches on the context's

@@ -264,11 +264,37 @@ def seeded_g(A, seed: int) -> Mat:
     return Mat(A.rowptr.copy(), A.col.copy(), val)
 
 
+def mean_norm(A) -> float:
+    """||A|| of the SAI loss (Sec. 3.3): the mean of |A_ij| over the nonzero
+    entries."""
+    A = _mat(A)
+    v = np.abs(A.val[A.val != 0.0])
+    return float(np.mean(v)) if v.size else 1.0
+
+
 def eps_shift(A, rel: float = 1e-4) -> float:
     """Absolute shift of M^-1 = G G^T + eps I for a G normalised to A's scale:
     the paper's relative shift (1e-4, Sec. 3.2.1) over the mean |A_ij|."""
-    A = _mat(A)
-    return rel / float(np.mean(np.abs(A.val)))
+    return rel / mean_norm(A)
+
+
+def sai_losses(A, G, W, eps: float = 0.0):
+    """Per-probe losses of Sec. 3.3 and its loss ablation, probe by probe:
+    y = A M^-1 w with M^-1 = G G^T + eps I (Eq. "major"),
+      sai = ||y / ||A|| - w||^2  (Eq. "our-loss"),  l2 = ||y - w||^2,
+      cs  = w^T y / (||w|| ||y||).
+    W is n x k (one probe per column). Their means over i.i.d. N(0,1) probes
+    estimate the squared Frobenius norms of Eq. "loss-initial"."""
+    W = np.asarray(W, dtype=np.float64)
+    na = mean_norm(A)
+    out = {"sai": np.zeros(W.shape[1]), "l2": np.zeros(W.shape[1]), "cs": np.zeros(W.shape[1])}
+    for p in range(W.shape[1]):
+        w = np.ascontiguousarray(W[:, p])
+        y = spmv(A, apply_precond(G, w, eps))
+        out["sai"][p] = float(np.sum((y / na - w) ** 2))
+        out["l2"][p] = float(np.sum((y - w) ** 2))
+        out["cs"][p] = float(np.dot(w, y) / (np.linalg.norm(w) * np.linalg.norm(y)))
+    return out
 
 
 def identity(n: int) -> Mat:

@@ -216,6 +216,21 @@ hipError_t launch_fsai_place(const int32_t *rp, const int32_t *ci, const int32_t
                              const double *lv, int32_t n, double scale, const DevCSR &GT, const DevCSR &G,
                              int32_t *err, hipStream_t s);
 
+// ---- multi-probe products for the SAI loss (FP64 probes, n x k row-major)
+//
+// Y = c * (M X) + d * Z for a stored matrix M (either layout, any storage
+// type; Z may be null): one wave per row, lane p for probes p, p+64, ...;
+// each row summed left to right in CSR order.
+hipError_t launch_spmm(const DevCSR &M, int32_t k, const double *X, double c, const double *Z, double d, double *Y,
+                       hipStream_t s);
+
+// Per-probe partial sums over rows for the losses: part[(b*5 + q)*k + p] for
+// workgroup b < kLossGrid and q = 0..4: sum (y/na - w)^2, sum (y - w)^2,
+// sum w y, sum y^2, sum w^2 (probe p's columns of Y and W).
+constexpr int kLossGrid = 512;
+hipError_t launch_loss_partials(int32_t n, int32_t k, const double *W, const double *Y, double na, double *part,
+                                hipStream_t s);
+
 // dst = src, `bytes` a multiple of 16.
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int grid, hipStream_t s);
 

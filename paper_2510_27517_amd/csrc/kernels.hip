@@ -856,6 +856,124 @@ __global__ __launch_bounds__(kBlock) void k_fsai_place(const int32_t *__restrict
   }
 }
 
+// ------------------------------------------------ multi-probe products (SAI loss)
+
+template <typename TM>
+__device__ __forceinline__ double ld64(GLOBAL const TM *p, int64_t k) {
+  return (double)ldval(p, k);
+}
+__device__ __forceinline__ double ld64(GLOBAL const double *p, int64_t k) { return p[k]; }
+
+// LPR lanes per row (a power of two >= the probe count, up to 64): a wave
+// works on 64 / LPR rows at once, lane p of a group on probes p, p + LPR, ...
+// Each group loads four entries' columns and values ahead of their gathers;
+// the products are still added left to right.
+template <typename TM, int LPR>
+__global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmm(DevCSR Md, int32_t k, const double *__restrict__ X_,
+                                                              double c, const double *__restrict__ Z_, double d,
+                                                              double *__restrict__ Y_) {
+  const Mat<TM> M = mat<TM>(Md);
+  GLOBAL const double *X = gl(X_);
+  GLOBAL const double *Z = Z_ ? gl(Z_) : nullptr;
+  GLOBAL double *Y = gl(Y_);
+  constexpr int RPW = 64 / LPR;  // rows per wave
+  constexpr int NW = kBlock / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int grp = lane / LPR, pl = lane % LPR;
+  const int64_t rows_per_block = (int64_t)NW * RPW;
+  for (int64_t base = (int64_t)blockIdx.x * rows_per_block; base < M.n; base += (int64_t)gridDim.x * rows_per_block) {
+    const int64_t r = base + (int64_t)wv * RPW + grp;
+    const bool has = r < M.n;
+    const int32_t row = has ? (int32_t)r : 0;
+    int64_t e0 = 0, stride = 1;
+    int32_t len = 0;
+    if (has) {
+      if (M.fmt == FMT_SELL) {  // padded entries add +0 (value 0, valid column)
+        const int32_t sl = row / kSliceRows;
+        e0 = (int64_t)M.blk[sl] * kSliceRows + row % kSliceRows;
+        stride = kSliceRows;
+        len = M.blk[sl + 1] - M.blk[sl];
+      } else {
+        e0 = M.rp[row];
+        len = M.rp[row + 1] - M.rp[row];
+      }
+    }
+    for (int32_t p0 = 0; p0 < k; p0 += LPR) {
+      const int32_t p = p0 + pl;
+      const bool act = has && p < k;
+      double sum = 0.0;
+      int32_t e = 0;
+      for (; e + 4 <= len; e += 4) {
+        int32_t col[4];
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t q = e0 + (int64_t)(e + u) * stride;
+          col[u] = M.ci[q];
+          a[u] = ld64(M.val, q);
+        }
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = act ? X[(int64_t)col[u] * k + p] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sum += a[u] * x[u];
+      }
+      for (; e < len; ++e) {
+        const int64_t q = e0 + (int64_t)e * stride;
+        const int32_t col = M.ci[q];
+        const double a = ld64(M.val, q);
+        sum += a * (act ? X[(int64_t)col * k + p] : 0.0);
+      }
+      if (act) {
+        double y = c * sum;
+        if (Z) y = y + d * Z[(int64_t)row * k + p];
+        Y[(int64_t)row * k + p] = y;
+      }
+    }
+  }
+}
+
+// Partial sums per workgroup (rows split in contiguous ranges), one lane per
+// probe, each sum in row order.
+__global__ __launch_bounds__(kBlock) void k_loss_partials(int32_t n, int32_t k, const double *__restrict__ W_,
+                                                          const double *__restrict__ Y_, double na,
+                                                          double *__restrict__ part_) {
+  __shared__ double sh[5 * kBlock];
+  GLOBAL const double *W = gl(W_), *Y = gl(Y_);
+  GLOBAL double *part = gl(part_);
+  const int64_t r0 = (int64_t)blockIdx.x * n / gridDim.x, r1 = (int64_t)(blockIdx.x + 1) * n / gridDim.x;
+  const int t = threadIdx.x;
+  const int lanes = kBlock;
+  for (int32_t p0 = 0; p0 < k; p0 += lanes) {
+    // thread t of group g = t / k2 handles probe p0 + t % k2 over rows r0 + g, r0 + g + ng, ...
+    const int32_t kk = min(lanes, k - p0);
+    const int ng = lanes / kk;
+    const int g = t / kk, p = p0 + t % kk;
+    double acc[5] = {0, 0, 0, 0, 0};
+    if (g < ng)
+      for (int64_t r = r0 + g; r < r1; r += ng) {
+        const double w = W[r * k + p], y = Y[r * k + p];
+        const double e = y / na - w, f = y - w;
+        acc[0] += e * e;
+        acc[1] += f * f;
+        acc[2] += w * y;
+        acc[3] += y * y;
+        acc[4] += w * w;
+      }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sh[q * kBlock + t] = (g < ng) ? acc[q] : 0.0;
+    __syncthreads();
+    if (t < kk) {  // fixed order over the groups
+      for (int q = 0; q < 5; ++q) {
+        double a = 0.0;
+        for (int gg = 0; gg < ng; ++gg) a += sh[q * kBlock + gg * kk + t];
+        part[((int64_t)blockIdx.x * 5 + q) * k + p0 + t] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline int ew_grid(int64_t n) {
@@ -1036,6 +1154,33 @@ hipError_t launch_fsai_place(const int32_t *rp, const int32_t *ci, const int32_t
                              int32_t *err, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fsai_place, dim3(ew_grid(n)), dim3(kBlock), 0, s, rp, ci, dpos, lrp, lv, n, scale, GT, G, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm(const DevCSR &M, int32_t k, const double *X, double c, const double *Z, double d, double *Y,
+                       hipStream_t s) {
+  if (M.n <= 0 || k <= 0) return hipSuccess;
+  const int lpr = k >= 64 ? 64 : k > 16 ? 32 : k > 8 ? 16 : 8;
+  const int64_t rows_per_block = (int64_t)(kBlock / 64) * (64 / lpr);
+  const int grid = (int)std::min<int64_t>(((int64_t)M.n + rows_per_block - 1) / rows_per_block, 65536);
+#define PCG_SPMM(L)                                                                                          \
+  PCG_DISPATCH_G(M.dtype, TM, {                                                                              \
+    hipLaunchKernelGGL((k_spmm<TM, L>), dim3(grid), dim3(kBlock), 0, s, M, k, X, c, Z, d, Y);                \
+  })
+  switch (lpr) {
+    case 64: PCG_SPMM(64); break;
+    case 32: PCG_SPMM(32); break;
+    case 16: PCG_SPMM(16); break;
+    default: PCG_SPMM(8); break;
+  }
+#undef PCG_SPMM
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_partials(int32_t n, int32_t k, const double *W, const double *Y, double na, double *part,
+                                hipStream_t s) {
+  if (n <= 0 || k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loss_partials, dim3(kLossGrid), dim3(kBlock), 0, s, n, k, W, Y, na, part);
   return hipGetLastError();
 }
 

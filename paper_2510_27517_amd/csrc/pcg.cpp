@@ -471,6 +471,8 @@ struct pcg_ctx {
 
   // directory of systems and their state slots (device), with a host mirror
   SysDev *d_dir = nullptr;
+  void *loss_buf = nullptr;  // scratch of pcg_sai_loss, kept between calls
+  size_t loss_bytes = 0;
   State *d_states = nullptr;  // kDirCap * 2
   State *h_states = nullptr;  // pinned mirror
   State *h_init = nullptr;    // pinned upload staging (2 slots)
@@ -480,6 +482,7 @@ struct pcg_ctx {
   // single-system path
   std::vector<int32_t> a_rp, a_ci;
   std::vector<double> a_val;
+  double a_mean_abs = 1.0;  // mean |A_ij| over the nonzeros (the SAI loss's ||A||)
   bool have_a = false, have_g = false;
   Sys single;
   HostSet set_main, set_64;
@@ -1451,6 +1454,7 @@ void pcg_destroy(pcg_ctx *ctx) {
   if (ctx->h_states) (void)hipHostFree(ctx->h_states);
   if (ctx->h_init) (void)hipHostFree(ctx->h_init);
   if (ctx->d_dir) (void)hipFree(ctx->d_dir);
+  if (ctx->loss_buf) (void)hipFree(ctx->loss_buf);
   if (ctx->d_states) (void)hipFree(ctx->d_states);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -1497,6 +1501,16 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
   ctx->a_rp.swap(hrp);
   ctx->a_ci.swap(hci);
   ctx->a_val.swap(hv);
+  {
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (double x : ctx->a_val)
+      if (x != 0.0) {
+        sum += std::fabs(x);
+        ++cnt;
+      }
+    ctx->a_mean_abs = cnt ? sum / (double)cnt : 1.0;
+  }
   APart P;
   prep_a(ctx->cfg, ctx->cus, n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), true, P);
   void *blk = nullptr;
@@ -1813,6 +1827,68 @@ int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device) 
       break;
   }
   return store_vec(ctx, S.tmp_out, vdt, y, on_device, n);
+}
+
+int pcg_sai_loss(pcg_ctx *ctx, int32_t k, const double *W, int on_device, double *sai, double *l2, double *cs) {
+  if (!ctx) return PCG_EINVAL;
+  if (k < 1 || !W) {
+    ctx->err = "pcg_sai_loss: need k >= 1 probes and W";
+    return PCG_EINVAL;
+  }
+  if (!ctx->have_a || !ctx->have_g) {
+    ctx->err = "pcg_sai_loss: matrix and preconditioner must be set";
+    return PCG_ESTATE;
+  }
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  Sys &S = ctx->single;
+  const int32_t n = S.n;
+  const double na = ctx->a_mean_abs;  // ||A|| = mean |A_ij| over the nonzeros
+  const size_t nk = (size_t)n * (size_t)k;
+  const size_t pb = sizeof(double) * (size_t)pcgk::kLossGrid * 5 * (size_t)k;
+  const size_t need = 3 * align_up(8 * nk) + align_up(pb);
+  if (need > ctx->loss_bytes) {
+    if (ctx->loss_buf) (void)hipFree(ctx->loss_buf);
+    ctx->loss_buf = nullptr;
+    ctx->loss_bytes = 0;
+    if (hipMalloc(&ctx->loss_buf, need) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->loss_buf = nullptr;
+      ctx->err = "pcg_sai_loss: device allocation failed";
+      return PCG_ENOMEM;
+    }
+    ctx->loss_bytes = need;
+  }
+  Carver c{(uint8_t *)ctx->loss_buf};
+  double *Wd = (double *)c.take(8 * nk), *T = (double *)c.take(8 * nk), *U = (double *)c.take(8 * nk);
+  double *part = (double *)c.take(pb);
+  std::vector<double> hp((size_t)pcgk::kLossGrid * 5 * (size_t)k);
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  if (on_device) chain(hipDeviceSynchronize());
+  chain(hipMemcpyAsync(Wd, W, 8 * nk, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  const double eps = ctx->cfg.eps;
+  chain(pcgk::launch_spmm(S.dev.GT, k, Wd, 1.0, nullptr, 0.0, T, s));  // T = G^T W
+  chain(pcgk::launch_spmm(S.dev.G, k, T, 1.0 / (S.g_scale * S.g_scale), eps != 0.0 ? Wd : nullptr, eps, U, s));
+  chain(pcgk::launch_spmm(S.dev.A, k, U, 1.0, nullptr, 0.0, T, s));  // Y = A M^-1 W
+  chain(pcgk::launch_loss_partials(n, k, Wd, T, na, part, s));
+  chain(hipMemcpyAsync(hp.data(), part, pb, hipMemcpyDeviceToHost, s));
+  chain(hipStreamSynchronize(s));
+  if (e != hipSuccess) {
+    ctx->err = std::string("pcg_sai_loss: ") + hipGetErrorString(e);
+    return PCG_EDEVICE;
+  }
+  for (int32_t p = 0; p < k; ++p) {
+    double q[5] = {0, 0, 0, 0, 0};
+    for (int b = 0; b < pcgk::kLossGrid; ++b)
+      for (int j = 0; j < 5; ++j) q[j] += hp[((size_t)b * 5 + j) * k + p];
+    if (sai) sai[p] = q[0];
+    if (l2) l2[p] = q[1];
+    if (cs) cs[p] = q[2] / (std::sqrt(q[4]) * std::sqrt(q[3]));
+  }
+  return PCG_OK;
 }
 
 int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {

@@ -36,6 +36,7 @@ STREAM_ARRIVALS = 7
 STREAM_KIND = 8
 STREAM_E = 9
 STREAM_REQ = 10
+STREAM_PROBE = 11  # probe vectors of the loss estimators
 
 _lib = None
 

@@ -30,7 +30,7 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 # every symbol include/pcg.h declares
 EXPORTS = [
     "pcg_config_default", "pcg_create", "pcg_destroy", "pcg_set_matrix", "pcg_set_precond", "pcg_build_precond",
-    "pcg_solve", "pcg_matvec", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
+    "pcg_solve", "pcg_matvec", "pcg_sai_loss", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
     "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth", "pcg_submit_batch",
     "pcg_progress", "pcg_poll", "pcg_solve_batch", "pcg_pool_info",
 ]
@@ -89,6 +89,7 @@ def load():
     lib.pcg_set_matrix.argtypes = [P, i32, i64, P, P, P, c_int]
     lib.pcg_set_precond.argtypes = [P, i32, i64, P, P, P, c_int]
     lib.pcg_build_precond.argtypes = [P, c_int, ctypes.c_uint64]
+    lib.pcg_sai_loss.argtypes = [P, i32, P, c_int, P, P, P]
     lib.pcg_solve.argtypes = [P, P, P, dbl, c_int, c_int, ctypes.POINTER(Result)]
     lib.pcg_matvec.argtypes = [P, c_int, P, P, c_int]
     lib.pcg_validate_csr.argtypes = [i32, i64, P, P, c_int]
@@ -279,6 +280,22 @@ class Solver:
         self._check(st, "pcg_solve", allow)
         return SolveOut(x, res.status, res.iters, res.outer_iters, res.restarts, res.relres_true, res.relres_rec,
                         res.t_solve_ms, res.bytes_per_iter)
+
+    def sai_loss(self, W):
+        """Per-probe SAI, L2 and cosine-similarity losses of the stored A and
+        M^-1 = G G^T + eps I for probes W (n x k; numpy or torch, FP64)."""
+        if _is_torch(W):
+            Wc = W.to(dtype=__import__("torch").float64).contiguous()
+        else:
+            Wc = np.ascontiguousarray(W, dtype=np.float64)
+        if Wc.ndim != 2:
+            raise PCGError(EINVAL, "sai_loss: W must be n x k")
+        k = int(Wc.shape[1])
+        pw, dev = _ptr(Wc)
+        out = {name: np.zeros(k) for name in ("sai", "l2", "cs")}
+        self._check(self._lib.pcg_sai_loss(self._h, k, pw, dev, out["sai"].ctypes.data, out["l2"].ctypes.data,
+                                           out["cs"].ctypes.data), "pcg_sai_loss")
+        return out
 
     def time_kernels(self, iters: int = 50):
         """{'ms': [A, GT, G, iteration], 'bytes': [A, GT, G, iteration]} per launch."""

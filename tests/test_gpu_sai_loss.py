@@ -1,0 +1,94 @@
+"""The preconditioner-quality losses of Sec. 3.3 on the GPU (multi-probe
+products over the stored A and G) against the oracle, probe by probe. The
+products are summed in CSR order on both sides; only the sums over rows
+differ in order, so values agree to 1e-12 relative."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_27517_amd import inputs
+from paper_2510_27517_amd.inputs import CSR
+from test_gpu_mixed import stored_g
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _check(got, ref):
+    for key in ("sai", "l2"):
+        assert np.allclose(got[key], ref[key], rtol=1e-12, atol=0), key
+    assert np.allclose(got["cs"], ref["cs"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("case,k,layout", [("poisson3d", 1, "auto"), ("poisson3d", 7, "sell"), ("poisson3d", 64, "csr"),
+                                           ("rgg", 100, "auto"), ("elasticity", 33, "auto"),
+                                           ("poisson2d", 300, "auto")])
+def test_sai_loss_matches_oracle_fp64(gpu_lib, case, k, layout):
+    pcg = gpu_lib
+    A = {"poisson3d": lambda: inputs.poisson(3, 18, 1.0, 4), "rgg": lambda: inputs.rgg_laplacian(6000, 4),
+         "elasticity": lambda: inputs.elasticity(6, 1.0, 0.3, 4), "poisson2d": lambda: inputs.poisson(2, 40, 1.0, 4)}[case]()
+    W = inputs.normal(4, inputs.STREAM_PROBE, A.n * k).reshape(A.n, k)
+    say("sai loss", case, k, layout, A.n)
+    with pcg.Solver(pcg.default_config(layout=layout)) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        got = s.sai_loss(W)
+    _check(got, oracle.sai_losses(A, oracle.fsai_g(A), W))
+
+
+def test_sai_loss_seeded_full_pattern_with_shift(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.poisson(3, 14, 1.0, 8)
+    eps = oracle.eps_shift(A)
+    W = inputs.normal(8, inputs.STREAM_PROBE, A.n * 16).reshape(A.n, 16)
+    with pcg.Solver(pcg.default_config(eps=eps)) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_SEEDED, 5)
+        got = s.sai_loss(W)
+    _check(got, oracle.sai_losses(A, oracle.seeded_g(A, 5), W, eps))
+
+
+@pytest.mark.parametrize("gdt", ["f32", "bf16", "f16"])
+def test_sai_loss_low_precision_storage(gpu_lib, gdt):
+    """FP32 A and FP32/BF16/FP16 G: the losses of the stored (rounded)
+    operators, which the oracle forms from the same rounded values."""
+    pcg = gpu_lib
+    A = inputs.poisson(3, 16, 1.0, 9)
+    G = oracle.fsai_g(A)
+    W = inputs.normal(9, inputs.STREAM_PROBE, A.n * 8).reshape(A.n, 8)
+    with pcg.Solver(pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype=gdt)) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        got = s.sai_loss(W)
+    gv, scale = stored_g(G.val, gdt)
+    A32 = CSR(A.rowptr, A.col, A.val.astype(np.float32).astype(np.float64))
+    Gs = CSR(G.rowptr, G.col, gv.astype(np.float64) / scale)
+    na = oracle.mean_norm(A)  # ||A|| from the FP64 values the caller gave
+    ref = {"sai": np.zeros(8), "l2": np.zeros(8), "cs": np.zeros(8)}
+    for p in range(8):
+        w = W[:, p]
+        y = oracle.spmv(A32, oracle.apply_precond(Gs, w))
+        ref["sai"][p] = np.sum((y / na - w) ** 2)
+        ref["l2"][p] = np.sum((y - w) ** 2)
+        ref["cs"][p] = np.dot(w, y) / (np.linalg.norm(w) * np.linalg.norm(y))
+    _check(got, ref)
+
+
+def test_sai_loss_errors(gpu_lib):
+    pcg = gpu_lib
+    A = inputs.poisson(2, 8)
+    with pcg.Solver() as s:
+        s.set_matrix(A)
+        with pytest.raises(pcg.PCGError) as e:
+            s.sai_loss(np.ones((A.n, 2)))
+        assert e.value.status == pcg.ESTATE
+        s.build_precond(pcg.G_FSAI)
+        with pytest.raises(pcg.PCGError) as e:
+            s.sai_loss(np.ones((A.n, 0)))
+        assert e.value.status == pcg.EINVAL

@@ -448,3 +448,74 @@ def test_seeded_g_with_shift_solves_to_dense_solution():
     xs = np.linalg.solve(A.to_dense(), b)
     assert res.status == oracle.OK
     assert np.linalg.norm(res.x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+# ------------------------------------------------------------ SAI loss (Sec. 3.3)
+
+def _dense_g(G, n):
+    D = np.zeros((n, n))
+    for i in range(n):
+        D[i, G.col[G.rowptr[i]:G.rowptr[i + 1]]] = G.val[G.rowptr[i]:G.rowptr[i + 1]]
+    return D
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.02])
+def test_sai_loss_unit_probes_give_the_frobenius_norm(eps):
+    """With the n unit vectors as probes the sums are exact:
+    sum_p sai = ||A M^-1 / ||A|| - I||_F^2 and sum_p l2 = ||A M^-1 - I||_F^2,
+    formed here with dense matrices."""
+    A = inputs.poisson(2, 5, 1.0, 3)
+    G = oracle.fsai_g(A)
+    n = A.n
+    Ad = A.to_dense()
+    Minv = _dense_g(G, n) @ _dense_g(G, n).T + eps * np.eye(n)
+    na = np.mean(np.abs(A.val))
+    out = oracle.sai_losses(A, G, np.eye(n), eps)
+    E = Ad @ Minv / na - np.eye(n)
+    F = Ad @ Minv - np.eye(n)
+    assert out["sai"].sum() == pytest.approx(np.sum(E * E), rel=1e-12)
+    assert out["l2"].sum() == pytest.approx(np.sum(F * F), rel=1e-12)
+    for p in range(n):
+        col = (Ad @ Minv)[:, p]
+        assert out["cs"][p] == pytest.approx(col[p] / np.linalg.norm(col), rel=1e-12)
+
+
+def test_sai_loss_exact_inverse_closed_form():
+    """G = L^-T (A = L L^T) makes M^-1 = A^-1: y = w, so sai = (1/||A|| - 1)^2
+    ||w||^2, l2 = 0 and cs = 1."""
+    Ad = _dense_spd(12, 4)
+    A = CSR.from_dense(Ad)
+    L = np.linalg.cholesky(Ad)
+    G = CSR.from_dense(np.linalg.inv(L).T)
+    W = inputs.normal(1, inputs.STREAM_PROBE, 12 * 3).reshape(12, 3)
+    out = oracle.sai_losses(A, G, W)
+    na = np.mean(np.abs(A.val))
+    for p in range(3):
+        w = W[:, p]
+        assert out["sai"][p] == pytest.approx((1 / na - 1) ** 2 * np.dot(w, w), rel=1e-10)
+        assert out["l2"][p] <= 1e-20 * np.dot(w, w)
+        assert out["cs"][p] == pytest.approx(1.0, abs=1e-12)
+
+
+def test_sai_loss_scale_invariant_bitwise():
+    """||A|| scales with A, so for a power-of-two factor the SAI loss is the
+    same bit for bit (Sec. 3.3); the L2 loss is not scale invariant."""
+    A = inputs.poisson(3, 6, 1.0, 2)
+    G = oracle.fsai_g(A)
+    W = inputs.normal(2, inputs.STREAM_PROBE, A.n * 4).reshape(A.n, 4)
+    a = oracle.sai_losses(A, G, W)
+    b = oracle.sai_losses(CSR(A.rowptr, A.col, A.val * 8.0), G, W)
+    assert np.array_equal(a["sai"], b["sai"]) and np.array_equal(a["cs"], b["cs"])
+    assert not np.allclose(a["l2"], b["l2"])
+
+
+def test_hutchinson_mean_approaches_the_frobenius_norm():
+    """E_w ||B w||^2 = ||B||_F^2 for w ~ N(0, I) (Eq. "loss-initial"): the mean
+    over 4000 probes is within 10% (its relative spread is below 3%)."""
+    A = inputs.poisson(2, 4, 1.0, 5)
+    G = oracle.diag_inv_sqrt(A)
+    n = A.n
+    W = inputs.normal(3, inputs.STREAM_PROBE, n * 4000).reshape(n, 4000)
+    out = oracle.sai_losses(A, G, W)
+    exact = oracle.sai_losses(A, G, np.eye(n))["sai"].sum()
+    assert abs(out["sai"].mean() - exact) <= 0.1 * exact
