@@ -19,6 +19,8 @@ Further sections, each under its own key of the same JSON line:
              p50/p99 latency, queue depth and admitted bytes;
   sai_loss   the SAI/L2/cosine preconditioner losses (Sec. 3.3) over 32
              Gaussian probes on the 128^3 system;
+  synthetic  the paper's synthetic P P^T + 1e-4 I systems (n 18000 and 72000,
+             and a batch of 64 with n in [12000, 24000]);
   elasticity Q1 elasticity, 64^3 free nodes x 3 dof (n = 786,432, 61.7M
              nonzeros): BF16/FP16 G with FP64 refinement to 1e-10 against the
              plain FP64 solve.
@@ -48,7 +50,7 @@ TOL = 1e-8
 MAXIT = 5000
 KERNEL_SOURCES = ["paper_2510_27517_amd/csrc/kernels.hip", "paper_2510_27517_amd/csrc/kernels.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iter_A_poisson3d_128_f64_traffic.md")
-SECTIONS = ["mixed", "sai_loss", "batched", "serving", "elasticity"]
+SECTIONS = ["mixed", "sai_loss", "batched", "serving", "elasticity", "synthetic"]
 
 
 def log(*a):
@@ -151,6 +153,41 @@ def section_sai_loss(pcg, inputs, A, G, k, reps=3):
             "alg_gbps": round((mat + vec) / (ms * 1e-3) / 1e9, 1), "sai_mean": float(np.mean(out["sai"])),
             "l2_mean": float(np.mean(out["l2"])), "cs_mean": float(np.mean(out["cs"])),
             "note": "probes resident on the device; scratch kept by the context after the first call"}
+
+
+def section_synthetic(pcg, inputs, count):
+    """The paper's synthetic set (Sec. 4.1, App. C): A = P P^T + 1e-4 I, P of
+    density 3e-4, n uniform in [12000, 24000] (and one Synthetic-Large system,
+    n = 72000), FSAI, FP64, tol 1e-8: the small, latency-bound regime."""
+    out = {"workload": "synthetic P P^T + 1e-4 I (P density 3e-4), FSAI G, FP64, tol 1e-8"}
+    for tag, n in (("n18000", 18000), ("large_n72000", 72000)):
+        A = inputs.synthetic_ppt(n, 7)
+        b = inputs.rhs(A.n, 7)
+        with pcg.Solver(pcg.default_config()) as s:
+            s.set_matrix(A)
+            s.build_precond(pcg.G_FSAI)
+            s.solve(b, tol=1e-8, maxit=20000)
+            t0 = time.perf_counter()
+            r = s.solve(b, tol=1e-8, maxit=20000)
+            ms = (time.perf_counter() - t0) * 1e3
+        out[tag] = {"n": A.n, "nnz": A.nnz, "time_to_tol_ms": round(ms, 2), "iters": r.iters, "status": r.status,
+                    "us_per_iter": round(ms * 1e3 / max(r.iters, 1), 2), "relres_true_fp64": r.relres_true}
+    log(f"synthetic: batch of {count}")
+    u = inputs.u01(11, inputs.STREAM_SIZES, count)
+    systems = []
+    for i in range(count):
+        A = inputs.synthetic_ppt(12000 + min(12000, int(u[i] * 12001)), 100 + i)
+        systems.append(dict(A=A, b=inputs.rhs(A.n, 100 + i), tol=1e-8, maxit=20000))
+    with pcg.Solver(pcg.default_config()) as s:
+        t0 = time.perf_counter()
+        res = s.solve_batch(systems, iters_per_step=50)
+        wall = time.perf_counter() - t0
+    st = [r["status"] for _, r in res]
+    out["batch"] = {"systems": count, "solves_per_s": round(count / wall, 2), "wall_s": round(wall, 3),
+                    "ok": st.count(pcg.OK), "iters_max": max(r["iters"] for _, r in res),
+                    "iters_median": float(np.median([r["iters"] for _, r in res])),
+                    "note": "n uniform in [12000, 24000]; wall time includes host FSAI and uploads"}
+    return out
 
 
 def batch_systems(inputs, count):
@@ -343,6 +380,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-step", type=int, default=10)
     ap.add_argument("--elasticity-n", type=int, default=64)
+    ap.add_argument("--synthetic-batch", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs single-GPU solves only (independent systems would "
@@ -439,6 +477,8 @@ def main():
         extra["serving"] = section_serving(pcg, inputs, args.serve_requests, args.serve_step)
     if "elasticity" in sections and args.elasticity_n > 0:
         extra["elasticity"] = section_elasticity(pcg, inputs, args.elasticity_n)
+    if "synthetic" in sections and args.synthetic_batch > 0:
+        extra["synthetic"] = section_synthetic(pcg, inputs, args.synthetic_batch)
 
     line = {
         "metric": METRIC, "value": round(1e3 / ms_per_step, 3), "unit": "solves/s", "n_gpus": 1,

@@ -137,6 +137,23 @@ struct RowVals {
   TV a, b, c;
 };
 
+// Sum of lds[a..e) added left to right onto s0; eight reads are issued ahead
+// of their adds, so long rows are not one LDS round trip per entry.
+template <typename TACC>
+__device__ __forceinline__ TACC lds_row_sum(const TACC *lds, int a, int e, TACC s0 = 0) {
+  TACC sum = s0;
+  int k = a;
+  for (; k + 8 <= e; k += 8) {
+    TACC v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = lds[k + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += v[u];
+  }
+  for (; k < e; ++k) sum += lds[k];
+  return sum;
+}
+
 // One row block: stage products in LDS, sum each row in CSR order. `pre(row)`
 // loads the row's own operands early (overlapping the gathers), `epi(row,
 // sum, pre_values)` consumes the row's sum.
@@ -158,11 +175,7 @@ __device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds,
 #pragma unroll PCG_UNROLL
     for (int k = k0 + tid; k < k1; k += kBlock) lds[k - k0] = (TACC)ldval(M.val, k) * gather(ldstream(M.ci, k));
     __syncthreads();
-    if (has) {
-      TACC sum = 0;
-      for (int k = a; k < e; ++k) sum += lds[k];
-      epi(row, sum, pv);
-    }
+    if (has) epi(row, lds_row_sum(lds, a, e), pv);
     __syncthreads();
   } else {
     // a single row longer than the LDS window: chunks, summed in order by thread 0
@@ -173,8 +186,7 @@ __device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds,
       const int c1 = min(c0 + cap, k1);
       for (int k = c0 + tid; k < c1; k += kBlock) lds[k - c0] = (TACC)ldval(M.val, k) * gather(ldstream(M.ci, k));
       __syncthreads();
-      if (tid == 0)
-        for (int k = 0; k < c1 - c0; ++k) sum += lds[k];
+      if (tid == 0) sum = lds_row_sum(lds, 0, c1 - c0, sum);
       __syncthreads();
     }
     if (tid == 0) epi(r0, sum, pv);

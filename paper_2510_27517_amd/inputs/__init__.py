@@ -37,6 +37,8 @@ STREAM_KIND = 8
 STREAM_E = 9
 STREAM_REQ = 10
 STREAM_PROBE = 11  # probe vectors of the loss estimators
+STREAM_SYN_POS = 12  # positions of P's entries (synthetic P P^T systems)
+STREAM_SYN_VAL = 13  # values of P's entries
 
 _lib = None
 
@@ -200,6 +202,26 @@ def rgg_laplacian(n: int, seed: int = 0, shift: float = 1e-3) -> CSR:
         lib.gen_free(pcol)
         lib.gen_free(pval)
     return CSR(rp, col, val)
+
+
+def synthetic_ppt(n: int, seed: int = 0, density: float = 3e-4, shift: float = 1e-4) -> CSR:
+    """The paper's synthetic SPD system (Sec. 4.1, App. C): A = P P^T + shift I
+    with P an n x n random sparse matrix of the given density. P has
+    round(density n^2) entries at uniform positions (row, column from two
+    draws of the position stream; coinciding positions add up) with N(0,1)
+    values; A's density comes out near 1.2e-3 for n in [12000, 24000]."""
+    import scipy.sparse as sp
+
+    m = int(round(density * n * n))
+    u = u01(seed, STREAM_SYN_POS, 2 * m)
+    rows = np.minimum((u[0::2] * n).astype(np.int64), n - 1)
+    cols = np.minimum((u[1::2] * n).astype(np.int64), n - 1)
+    vals = normal(seed, STREAM_SYN_VAL, m)
+    P = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    A = (P @ P.T + shift * sp.identity(n, format="csr")).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return CSR.from_scipy(A)
 
 
 def elasticity(N: int, sigma: float = 1.0, nu: float = 0.3, seed: int = 0) -> CSR:

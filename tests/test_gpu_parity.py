@@ -314,3 +314,27 @@ def test_full_size_poisson3d_128(gpu_lib):
     r = b - oracle.spmv(A, full.x, threads=8)
     assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(b)
     say("iters", full.iters, "ms", full.t_solve_ms)
+
+
+def test_pcg_synthetic_ppt(gpu_lib):
+    """The paper's synthetic system A = P P^T + 1e-4 I (n = 12000, P density
+    3e-4) with FSAI. Its trajectory is very sensitive to rounding order (the
+    oracle's own two delta formulas differ by 2.8e-13 in x after 25
+    iterations, 5e-9 after 50, 3e-5 after 100, and 3.1e-11 at convergence
+    after 1459/1460 iterations): parity binds at 25 iterations; the converged
+    solve must meet the tolerance by the oracle's own residual and stay within
+    the oracle's iteration spread plus one."""
+    pcg = gpu_lib
+    A = inputs.synthetic_ppt(12000, 1)
+    b = inputs.rhs(A.n, 1)
+    say("synthetic P P^T", A.n, A.nnz)
+    got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=0.0, maxit=25)
+    _check(got, ref)
+    got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=1e-8, maxit=20000)
+    alt = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-8, maxit=20000, delta_form=0).iters
+    assert got.status == ref.status == pcg.OK
+    assert abs(got.iters - ref.iters) <= abs(alt - ref.iters) + 1, (got.iters, ref.iters, alt)
+    r = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+    say(f"  iters {got.iters}/{ref.iters}/{alt} relres {r:.2e} xdiff "
+        f"{np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x):.2e}")
+    assert r <= 1.0001e-8
