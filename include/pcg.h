@@ -91,7 +91,7 @@ typedef struct {
   int graph_iters;   /* iterations per captured HIP graph replay (default 10; 0 = plain launches) */
   int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */
   int mem_budget_mb; /* device memory pool for batched / served systems, MiB (0: half the free memory at first use) */
-  int layout;        /* storage of A, G, G^T: PCG_LAYOUT_AUTO (default), PCG_LAYOUT_CSR or PCG_LAYOUT_SELL */
+  int layout;        /* storage of A, G, G^T: PCG_LAYOUT_AUTO (default), _CSR, _SELL or _BSR3 */
   int g_device;      /* 1: pcg_build_precond(PCG_G_FSAI) factors on the device (one wave per row; same
                         arithmetic as the host builder); falls back to the host for tril rows longer
                         than 80 or a structurally unsymmetric A. 0 (default): on the host */
@@ -104,11 +104,17 @@ typedef struct {
  *        fit the workgroup's LDS; any row lengths.
  *  SELL: sliced ELL, slices of 64 consecutive rows stored column-major and
  *        padded to the slice's longest row; coalesced loads without LDS.
- *  AUTO: SELL for a matrix whose padding stays within 1/8 of its nonzeros,
- *        CSR otherwise. PCG_LAYOUT_SELL still falls back to CSR above 2x. */
+ *  BSR3: for A only, when it is exactly 3x3-blocked (n % 3 == 0, each block
+ *        row's three rows store the same complete column triples, as in
+ *        node-major 3-dof systems): slices of 21 block rows, one column index
+ *        per 3x3 block; products are still summed in CSR order.
+ *  AUTO: BSR3 for such an A whose block padding stays within 1/8; otherwise
+ *        SELL for a matrix whose padding stays within 1/8 of its nonzeros,
+ *        CSR otherwise. PCG_LAYOUT_SELL (BSR3) still falls back above 2x. */
 #define PCG_LAYOUT_AUTO 0
 #define PCG_LAYOUT_CSR 1
 #define PCG_LAYOUT_SELL 2
+#define PCG_LAYOUT_BSR3 3
 
 typedef struct {
   int status;          /* PCG_OK, PCG_NOT_CONVERGED or a negative code */

@@ -338,6 +338,72 @@ void sell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, con
   }
 }
 
+bool is_block3(int32_t n, const int32_t *rp, const int32_t *ci, int64_t *blocks) {
+  if (n <= 0 || n % 3) return false;
+  int64_t nb = 0;
+  for (int32_t R = 0; R < n / 3; ++R) {
+    const int32_t r = 3 * R, len = rp[r + 1] - rp[r];
+    if (len % 3 || rp[r + 2] - rp[r + 1] != len || rp[r + 3] - rp[r + 2] != len) return false;
+    for (int32_t k = 0; k < len; k += 3) {
+      const int32_t c = ci[rp[r] + k];
+      if (c % 3) return false;
+      for (int s = 0; s < 3; ++s)
+        for (int j = 0; j < 3; ++j)
+          if (ci[rp[r + s] + k + j] != c + j) return false;
+    }
+    nb += len / 3;
+  }
+  if (blocks) *blocks = nb;
+  return true;
+}
+
+int64_t bsell_blocks(int32_t n, const int32_t *rp) {
+  const int32_t nbr = n / 3;
+  int64_t tot = 0;
+  for (int32_t R0 = 0; R0 < nbr; R0 += kBSlice) {
+    int32_t w = 0;
+    for (int32_t R = R0; R < std::min(nbr, R0 + kBSlice); ++R) w = std::max(w, (rp[3 * R + 1] - rp[3 * R]) / 3);
+    tot += (int64_t)w * kBSlice;
+  }
+  return tot;
+}
+
+void bsell_pattern(int32_t n, const int32_t *rp, const int32_t *ci, std::vector<int32_t> &bo,
+                   std::vector<int32_t> &bcol) {
+  const int32_t nbr = n / 3, ns = (nbr + kBSlice - 1) / kBSlice;
+  bo.assign(ns + 1, 0);
+  for (int32_t c = 0; c < ns; ++c) {
+    int32_t w = 0;
+    for (int32_t R = c * kBSlice; R < std::min(nbr, (c + 1) * kBSlice); ++R)
+      w = std::max(w, (rp[3 * R + 1] - rp[3 * R]) / 3);
+    bo[c + 1] = bo[c] + w;
+  }
+  bcol.resize((size_t)bo[ns] * kBSlice);
+  for (int32_t c = 0; c < ns; ++c)
+    for (int32_t r = 0; r < kBSlice; ++r) {
+      const int32_t R = c * kBSlice + r;
+      const int32_t nbk = R < nbr ? (rp[3 * R + 1] - rp[3 * R]) / 3 : 0;
+      for (int32_t k = 0; k < bo[c + 1] - bo[c]; ++k)
+        bcol[((size_t)bo[c] + k) * kBSlice + r] = k < nbk ? ci[rp[3 * R] + 3 * k] / 3 : (R < nbr ? R : 0);
+    }
+}
+
+void bsell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, const std::vector<int32_t> &bo,
+                 std::vector<uint8_t> &out) {
+  const int32_t nbr = n / 3, ns = (int32_t)bo.size() - 1;
+  out.assign((size_t)bo[ns] * kBSlice * 9 * esz, 0);
+  for (int32_t R = 0; R < nbr; ++R) {
+    const int32_t c = R / kBSlice, r = R % kBSlice, nbk = (rp[3 * R + 1] - rp[3 * R]) / 3;
+    for (int32_t k = 0; k < nbk; ++k)
+      for (int s = 0; s < 3; ++s)
+        for (int j = 0; j < 3; ++j) {
+          const size_t pos = esz == 8 ? (((size_t)bo[c] + k) * 3 + j) * 3 * kBSlice + (size_t)s * kBSlice + r
+                                      : (((size_t)bo[c] + k) * kBSlice + r) * 9 + 3 * s + j;
+          std::memcpy(&out[pos * esz], in + (size_t)(rp[3 * R + s] + 3 * k + j) * esz, esz);
+        }
+  }
+}
+
 double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt) {
   const double sa = (double)pcgk::dtype_size(adt), sg = (double)pcgk::dtype_size(gdt),
                sv = (double)pcgk::dtype_size(vdt);

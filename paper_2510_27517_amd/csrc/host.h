@@ -53,6 +53,34 @@ void sell_columns(int32_t n, const int32_t *rp, const int32_t *ci, const std::ve
 void sell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, const std::vector<int32_t> &so,
                 std::vector<uint8_t> &out);
 
+// Sliced 3x3-block layout: the matrix is exactly 3x3-blocked when n % 3 == 0
+// and rows 3R, 3R+1, 3R+2 store the same columns, all in complete groups
+// {3C, 3C+1, 3C+2}. Slices of kBSlice block rows (3 kBSlice rows, one lane
+// each); slice c holds bo[c+1] - bo[c] blocks per block row (its longest
+// block row); block k of block row kBSlice c + r has column index
+// bcol[(bo[c] + k) kBSlice + r]. Its row s, column j value sits, for 8-byte
+// values, at ((bo[c] + k) 3 + j) 3 kBSlice + s kBSlice + r (for each block
+// and column the slice's rows are contiguous: one coalesced load per column),
+// and for narrower values at 9 ((bo[c] + k) kBSlice + r) + 3 s + j (each row's
+// three values contiguous, rows adjacent: one wide load per lane). Padding
+// blocks take their own block row as column and zero values.
+constexpr int kBSlice = 21;
+
+// True when the pattern is exactly 3x3-blocked; *blocks = number of blocks.
+bool is_block3(int32_t n, const int32_t *rp, const int32_t *ci, int64_t *blocks);
+
+// Stored blocks (with padding) of the sliced block layout.
+int64_t bsell_blocks(int32_t n, const int32_t *rp);
+
+// Block offsets (nslice + 1) and block columns in sliced order.
+void bsell_pattern(int32_t n, const int32_t *rp, const int32_t *ci, std::vector<int32_t> &bo,
+                   std::vector<int32_t> &bcol);
+
+// Elements of `esz` bytes in CSR order moved to the sliced block order
+// (padding all-zero bytes).
+void bsell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, const std::vector<int32_t> &bo,
+                 std::vector<uint8_t> &out);
+
 // Algorithmic bytes of one PCG iteration (11 vector streams).
 double bytes_per_iter(int32_t n, int64_t a, int64_t g, int adt, int gdt, int vdt);
 

@@ -71,6 +71,7 @@ inline int lds_cap(int vec_dtype) { return kLdsBytes / (int)dtype_size(vec_dtype
 enum Fmt : int32_t {
   FMT_CSR = 0,   // CSR with a row-block partition (any row lengths)
   FMT_SELL = 1,  // sliced ELL, slices of 64 rows (rows of similar length)
+  FMT_BSR3 = 2,  // sliced 3x3 blocks, slices of 21 block rows (exactly 3x3-blocked matrices)
 };
 
 // A sparse matrix resident on the device.
@@ -80,6 +81,12 @@ enum Fmt : int32_t {
 // FMT_SELL: rp is unused; nblk slices of 64 rows; slice c has blk[c+1] -
 //   blk[c] columns, entry k of row 64c + l at ci/val[(blk[c] + k) * 64 + l]
 //   (rows keep their CSR order; padding has value 0 and a valid column).
+// FMT_BSR3: rp is unused; nblk slices of 21 block rows (63 rows); slice c has
+//   blk[c+1] - blk[c] blocks per block row; block k of block row 21c + r has
+//   block column ci[(blk[c] + k) * 21 + r] and its row s, column j value at
+//   val[((blk[c] + k) * 3 + j) * 63 + 21 s + r] for 8-byte values, at
+//   val[9 ((blk[c] + k) * 21 + r) + 3 s + j] for 4-byte values (padding: own
+//   block row, zeros).
 // `grid` is the system's workgroup count for products with this matrix (a
 // multiple of 8, a function of nblk only).
 struct DevCSR {
@@ -94,8 +101,9 @@ struct DevCSR {
   int32_t fmt = FMT_CSR;
 };
 
-// Rows per slice of FMT_SELL, and slices per workgroup round (one per wave).
+// Rows per slice of FMT_SELL; block rows per slice of FMT_BSR3.
 constexpr int kSliceRows = 64;
+constexpr int kBSliceRows = 21;
 
 // One system in the directory (device-resident, POD).
 struct SysDev {

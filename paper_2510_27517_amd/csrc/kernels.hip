@@ -259,12 +259,72 @@ __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pr
   }
 }
 
+// Sliced 3x3-block rows: each wave takes whole slices of 21 block rows, one
+// lane per row (lane 63 idle); the three lanes of a block row read the same
+// block column. 8-byte values are stored column-major within the slice (lane
+// 21 s + r for row s of block row r), so each column's values are one
+// coalesced load; 4-byte values keep each row's three values contiguous
+// (lane 3 r + s), one 12-byte load per lane. Each lane adds its row's three
+// products block by block: the CSR order.
+template <typename TM>
+struct BsrLanes {
+  static constexpr bool kColMajor = sizeof(TM) == 8;
+  __device__ static int sub(int lane) { return kColMajor ? lane / kBSliceRows : lane % 3; }
+  __device__ static int blockrow(int lane) { return kColMajor ? lane % kBSliceRows : lane / 3; }
+  // offset of block k's column-j value for this lane, relative to the slice's first block
+  __device__ static int64_t at(int lane, int k, int j) {
+    return kColMajor ? ((int64_t)k * 3 + j) * (3 * kBSliceRows) + lane
+                     : ((int64_t)k * kBSliceRows + lane / 3) * 9 + 3 * (lane % 3) + j;
+  }
+};
+
+template <typename TACC, typename TM, typename Pre, typename Gather, typename Epi>
+__device__ __forceinline__ void bsr_rows(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi) {
+  constexpr int NW = kBlock / 64;
+  constexpr int SR = 3 * kBSliceRows;  // rows per slice
+  using BL = BsrLanes<TM>;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = G >> 3, x = l & 7, w = l >> 3;
+  const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
+  const int sub = BL::sub(lane), r = BL::blockrow(lane);
+  for (int c = s0 + w * NW + wv; c < s1; c += W * NW) {
+    const int o0 = M.blk[c], wd = M.blk[c + 1] - o0;
+    const int row = (c * kBSliceRows + r) * 3 + sub;
+    const bool has = lane < SR && row < M.n;
+    if (!has) continue;
+    const RowVals<TACC> pv = pre(row);
+    GLOBAL const int32_t *bc = M.ci + (int64_t)o0 * kBSliceRows + r;
+    GLOBAL const TM *bv = M.val + (int64_t)o0 * 9 * kBSliceRows;
+    TACC sum = 0;
+    int k = 0;
+    for (; k + 2 <= wd; k += 2) {
+      const int32_t c0 = 3 * ldstream(bc, (int64_t)k * kBSliceRows), c1 = 3 * ldstream(bc, (int64_t)(k + 1) * kBSliceRows);
+      TACC p[6];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) p[j] = (TACC)ldval(bv, BL::at(lane, k, j)) * gather(c0 + j);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) p[3 + j] = (TACC)ldval(bv, BL::at(lane, k + 1, j)) * gather(c1 + j);
+#pragma unroll
+      for (int u = 0; u < 6; ++u) sum += p[u];
+    }
+    if (k < wd) {
+      const int32_t c0 = 3 * ldstream(bc, (int64_t)k * kBSliceRows);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) sum += (TACC)ldval(bv, BL::at(lane, k, j)) * gather(c0 + j);
+    }
+    epi(row, sum, pv);
+  }
+}
+
 // All rows of this workgroup (local index l of the system's G workgroups),
-// in either layout.
+// in any layout.
 template <typename TACC, int UW = 4, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather, Epi epi) {
   if (M.fmt == FMT_SELL) {
     sell_rows<TACC, UW>(M, l, G, pre, gather, epi);
+  } else if (M.fmt == FMT_BSR3) {
+    bsr_rows<TACC>(M, l, G, pre, gather, epi);
   } else {
     const Sched sc = sched(M.nblk, l, G);
     for (int b = sc.first; b < sc.end; b += sc.stride) stream_block<TACC>(M, b, lds, pre, gather, epi);
@@ -899,6 +959,31 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmm(DevCSR Md, int32_
     const int32_t row = has ? (int32_t)r : 0;
     int64_t e0 = 0, stride = 1;
     int32_t len = 0;
+    if (has && M.fmt == FMT_BSR3) {  // whole blocks: three entries of the row per block
+      const int32_t R = row / 3, sub = row % 3, sl = R / kBSliceRows, rr = R % kBSliceRows;
+      const int32_t o0 = M.blk[sl], wd = M.blk[sl + 1] - o0;
+      for (int32_t p0 = 0; p0 < k; p0 += LPR) {
+        const int32_t p = p0 + pl;
+        double sum = 0.0;
+        for (int32_t b = 0; b < wd; ++b) {
+          const int64_t blk = ((int64_t)o0 + b) * kBSliceRows + rr;
+          const int32_t c0 = 3 * M.ci[blk];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const int64_t vi = sizeof(TM) == 8 ? (((int64_t)o0 + b) * 3 + j) * (3 * kBSliceRows) + sub * kBSliceRows + rr
+                                               : (((int64_t)o0 + b) * kBSliceRows + rr) * 9 + 3 * sub + j;
+            const double a = ld64(M.val, vi);
+            sum += a * (p < k ? X[(int64_t)(c0 + j) * k + p] : 0.0);
+          }
+        }
+        if (p < k) {
+          double y = c * sum;
+          if (Z) y = y + d * Z[(int64_t)row * k + p];
+          Y[(int64_t)row * k + p] = y;
+        }
+      }
+      continue;
+    }
     if (has) {
       if (M.fmt == FMT_SELL) {  // padded entries add +0 (value 0, valid column)
         const int32_t sl = row / kSliceRows;

@@ -130,7 +130,8 @@ struct HostMat {
   std::vector<uint8_t> val;  // values in dt, in storage order (empty: written on the device)
   std::vector<int32_t> blk;  // row-block pairs (FMT_CSR) or slice offsets (FMT_SELL)
   int32_t nunits = 0, grid = 8;
-  size_t val_bytes() const { return pcgk::dtype_size(dt) * std::max<size_t>(ci.size(), 1); }
+  int vpi = 1;  // values per stored index (9 for 3x3 blocks)
+  size_t val_bytes() const { return pcgk::dtype_size(dt) * (size_t)vpi * std::max<size_t>(ci.size(), 1); }
   size_t bytes() const {
     return align_up(4 * rp.size()) + align_up(4 * std::max<size_t>(ci.size(), 1)) + align_up(val_bytes()) +
            align_up(4 * blk.size());
@@ -205,21 +206,42 @@ void cast_values(const double *v, int64_t nnz, int dt, double scale, std::vector
 // small, the CSR row blocks otherwise.
 bool use_sell(int layout, int32_t n, const int32_t *rp) {
   if (layout == PCG_LAYOUT_CSR || n <= 0) return false;
+  if (layout == PCG_LAYOUT_BSR3) layout = PCG_LAYOUT_AUTO;  // a matrix without 3x3 blocks
   const int64_t nnz = rp[n], stored = pcgh::sell_entries(n, rp);
   if (stored >= ((int64_t)1 << 31)) return false;
   if (layout == PCG_LAYOUT_SELL) return stored <= 2 * nnz + pcgh::kSlice;
   return stored <= nnz + nnz / 8;
 }
 
+// The sliced 3x3-block layout for an exactly 3x3-blocked matrix whose block
+// padding stays within 1/8 (at most 2x when asked for explicitly).
+bool use_bsr3(int layout, int32_t n, const int32_t *rp, const int32_t *ci) {
+  if (layout != PCG_LAYOUT_AUTO && layout != PCG_LAYOUT_BSR3) return false;
+  int64_t nb = 0;
+  if (!pcgh::is_block3(n, rp, ci, &nb) || nb == 0) return false;
+  const int64_t stored = pcgh::bsell_blocks(n, rp);
+  if (stored * 9 >= ((int64_t)1 << 31)) return false;
+  return layout == PCG_LAYOUT_BSR3 ? stored <= 2 * nb : stored <= nb + nb / 8;
+}
+
 // Lay out one matrix's pattern (no values); the row blocks (CSR) are sized for
-// products in vector type vdt.
+// products in vector type vdt. `blocks`: the 3x3-block layout may be used.
 void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, int dt, int vdt,
-                  HostMat &M) {
+                  HostMat &M, bool blocks = false) {
   M.n = n;
   M.nnz = rp[n];
   M.dt = dt;
+  M.vpi = 1;
   M.val.clear();
-  if (use_sell(cfg.layout, n, rp)) {
+  if (blocks && use_bsr3(cfg.layout, n, rp, ci)) {
+    M.fmt = pcgk::FMT_BSR3;
+    M.rp.clear();
+    pcgh::bsell_pattern(n, rp, ci, M.blk, M.ci);
+    M.vpi = 9;
+    M.nunits = (int32_t)M.blk.size() - 1;
+    const int32_t rounds = (M.nunits + pcgk::kBlock / 64 - 1) / (pcgk::kBlock / 64);
+    M.grid = grid_for(cus, cfg.grid_mult, rounds);
+  } else if (use_sell(cfg.layout, n, rp)) {
     M.fmt = pcgk::FMT_SELL;
     M.rp.clear();
     pcgh::sell_offsets(n, rp, M.blk);
@@ -239,11 +261,13 @@ void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, 
 
 // Lay out one matrix with values v (CSR order) times `scale` in dt.
 void make_mat(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
-              int dt, double scale, int vdt, HostMat &M) {
-  make_pattern(cfg, cus, n, rp, ci, dt, vdt, M);
+              int dt, double scale, int vdt, HostMat &M, bool blocks = false) {
+  make_pattern(cfg, cus, n, rp, ci, dt, vdt, M, blocks);
   std::vector<uint8_t> csr_val;
   cast_values(v, M.nnz, dt, scale, csr_val);
-  if (M.fmt == pcgk::FMT_SELL)
+  if (M.fmt == pcgk::FMT_BSR3)
+    pcgh::bsell_bytes(n, rp, csr_val.data(), pcgk::dtype_size(dt), M.blk, M.val);
+  else if (M.fmt == pcgk::FMT_SELL)
     pcgh::sell_bytes(n, rp, csr_val.data(), pcgk::dtype_size(dt), M.blk, M.val);
   else
     M.val.swap(csr_val);
@@ -257,12 +281,15 @@ void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const 
   P.vdt = cfg.vec_dtype;
   P.refine = cfg.refine != 0;
   P.staging = staging;
-  make_mat(cfg, cus, n, rp, ci, v, P.adt, 1.0, P.vdt, P.A);
+  make_mat(cfg, cus, n, rp, ci, v, P.adt, 1.0, P.vdt, P.A, true);
   P.gB = norm_grid(n);
   size_t b64 = 0;
   if (P.refine) {
-    if (P.A.fmt == pcgk::FMT_SELL) {
-      pcgh::sell_bytes(n, rp, (const uint8_t *)v, 8, P.A.blk, P.sliced64);
+    if (P.A.fmt != pcgk::FMT_CSR) {
+      if (P.A.fmt == pcgk::FMT_BSR3)
+        pcgh::bsell_bytes(n, rp, (const uint8_t *)v, 8, P.A.blk, P.sliced64);
+      else
+        pcgh::sell_bytes(n, rp, (const uint8_t *)v, 8, P.A.blk, P.sliced64);
       P.nunits64 = P.A.nunits;
       P.grid64 = P.A.grid;
       b64 = align_up(P.sliced64.size());
@@ -377,7 +404,7 @@ hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
     D = SysDev{};
     D.A = A;
     D.A.dtype = pcgk::F64;
-    if (P.A.fmt == pcgk::FMT_SELL) {  // same slices and columns, FP64 values
+    if (P.A.fmt != pcgk::FMT_CSR) {  // same slices and columns, FP64 values
       void *v64 = c.take(P.sliced64.size());
       chain(h2d(v64, P.sliced64.data(), P.sliced64.size(), s));
       D.A.val = v64;

@@ -22,8 +22,8 @@ EINVAL, ESTATE, ENOMEM, EBREAKDOWN, EDEVICE = -1, -2, -3, -4, -5
 F64, F32, BF16, F16 = 0, 1, 2, 3
 G_FSAI, G_FIXED, G_JACOBI, G_IDENTITY, G_SEEDED = 1, 2, 3, 4, 5
 OP_A, OP_GT, OP_G, OP_MINV = 0, 1, 2, 3
-LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SELL = 0, 1, 2
-LAYOUTS = {"auto": LAYOUT_AUTO, "csr": LAYOUT_CSR, "sell": LAYOUT_SELL}
+LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SELL, LAYOUT_BSR3 = 0, 1, 2, 3
+LAYOUTS = {"auto": LAYOUT_AUTO, "csr": LAYOUT_CSR, "sell": LAYOUT_SELL, "bsr3": LAYOUT_BSR3}
 
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 

@@ -59,12 +59,13 @@ def _random_g(A, seed):
     return CSR(A.rowptr.copy(), A.col.copy(), rng.uniform(-1, 1, A.nnz))
 
 
-@pytest.mark.parametrize("layout", ["auto", "csr", "sell"])
+@pytest.mark.parametrize("layout", ["auto", "csr", "sell", "bsr3"])
 @pytest.mark.parametrize("case", ["ragged", "longrows", "poisson3d", "elasticity"])
 def test_operator_products_bitwise(gpu_lib, case, layout):
-    """Both storage layouts give the oracle's products bit for bit (the sliced
+    """Every storage layout gives the oracle's products bit for bit (the sliced
     layout is forced onto ragged rows, so padding is exercised; the long rows
-    fall back to CSR)."""
+    fall back to CSR; the 3x3-block layout applies to the elasticity A, whose
+    boundary block rows are shorter, and falls back elsewhere)."""
     pcg = gpu_lib
     if case == "ragged":
         A = _random_spd_pattern(1537, 1)
@@ -177,6 +178,19 @@ def test_pcg_seeded_full_pattern_g_with_shift(gpu_lib, case):
     err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
     say(f"  iters {got.iters}/{ref.iters} relres {r:.2e} xdiff {err:.2e} bound {2 * lam_max / lam_min * tol:.2e}")
     assert err <= 2 * lam_max / lam_min * tol
+
+
+@pytest.mark.parametrize("layout", ["bsr3", "sell"])
+def test_pcg_fsai_elasticity(gpu_lib, layout):
+    """Q1 elasticity (3 dof per node) with FSAI, A in the 3x3-block layout
+    (or sliced ELL), against the oracle."""
+    pcg = gpu_lib
+    A = inputs.elasticity(9, 1.0, 0.3, 3)
+    b = inputs.rhs(A.n, 3)
+    say("pcg fsai elasticity", layout, A.n)
+    got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=1e-10, maxit=3000, layout=layout)
+    _check(got, ref)
+    assert got.status == pcg.OK
 
 
 def test_pcg_random_spd_long_rows(gpu_lib):
