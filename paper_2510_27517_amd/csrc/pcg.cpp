@@ -529,6 +529,10 @@ struct pcg_ctx {
   bool stop = false;
   HostSet set_active;
   bool active_dirty = true;
+  // the scheduler step (K iterations over the active set) as a HIP graph,
+  // valid until the active set changes
+  hipGraphExec_t step_graph = nullptr;
+  int step_graph_iters = 0;
 };
 
 namespace {
@@ -1206,6 +1210,12 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
   return PCG_OK;
 }
 
+void drop_step_graph(pcg_ctx *ctx) {
+  if (ctx->step_graph) (void)hipGraphExecDestroy(ctx->step_graph);
+  ctx->step_graph = nullptr;
+  ctx->step_graph_iters = 0;
+}
+
 // One scheduler step: admit, `iters` iterations over the active set, retire.
 int progress(pcg_ctx *ctx, int iters) {
   int rc;
@@ -1227,6 +1237,7 @@ int progress(pcg_ctx *ctx, int iters) {
   if (ctx->active.empty()) return PCG_OK;
   hipStream_t s = ctx->stream;
   if (ctx->active_dirty) {
+    drop_step_graph(ctx);
     std::vector<int> slots;
     for (auto &R : ctx->active) slots.push_back(R->slot);
     if ((rc = build_set(ctx, ctx->set_active, slots))) return rc;
@@ -1247,11 +1258,41 @@ int progress(pcg_ctx *ctx, int iters) {
     }
     return false;
   };
-  for (int k = 0; k < iters; ++k) {
-    HIPCHK(pcgk::launch_iter_A(ctx->ty, L, s));
-    if (any_replacement(k)) HIPCHK(pcgk::launch_resid(ctx->ty, L, 2, true, false, true, s));
-    HIPCHK(pcgk::launch_iter_GT(ctx->ty, L, 3, s));
-    HIPCHK(pcgk::launch_iter_G(ctx->ty, L, has_eps, 3, s));
+  if (ctx->cfg.graph_iters > 0) {
+    // one graph per active set: the residual kernel runs every iteration and
+    // decides per system, when some system replaces at all
+    bool replaces = false;
+    for (auto &R : ctx->active) replaces = replaces || (rr > 0 && R->slot64 < 0);
+    if (!ctx->step_graph || ctx->step_graph_iters != iters) {
+      drop_step_graph(ctx);
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      auto chain = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+      };
+      for (int k = 0; k < iters; ++k) {
+        chain(pcgk::launch_iter_A(ctx->ty, L, s));
+        if (replaces) chain(pcgk::launch_resid(ctx->ty, L, 2, true, false, true, s));
+        chain(pcgk::launch_iter_GT(ctx->ty, L, 3, s));
+        chain(pcgk::launch_iter_G(ctx->ty, L, has_eps, 3, s));
+      }
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(s, &g);
+      HIPCHK(e);
+      HIPCHK(e2);
+      const hipError_t e3 = hipGraphInstantiate(&ctx->step_graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(e3);
+      ctx->step_graph_iters = iters;
+    }
+    HIPCHK(hipGraphLaunch(ctx->step_graph, s));
+  } else {
+    for (int k = 0; k < iters; ++k) {
+      HIPCHK(pcgk::launch_iter_A(ctx->ty, L, s));
+      if (any_replacement(k)) HIPCHK(pcgk::launch_resid(ctx->ty, L, 2, true, false, true, s));
+      HIPCHK(pcgk::launch_iter_GT(ctx->ty, L, 3, s));
+      HIPCHK(pcgk::launch_iter_G(ctx->ty, L, has_eps, 3, s));
+    }
   }
   int maxslot = 0;
   for (auto &R : ctx->active) maxslot = std::max(maxslot, R->slot);
@@ -1467,6 +1508,7 @@ void pcg_destroy(pcg_ctx *ctx) {
   ctx->workers.clear();
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   drop_graphs(ctx);
+  drop_step_graph(ctx);
   for (auto &R : ctx->active) free_sys(ctx, R->sys);
   ctx->active.clear();
   free_set(ctx->set_main);
