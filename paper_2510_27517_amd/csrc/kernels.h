@@ -26,7 +26,7 @@ inline size_t dtype_size(int dt) { return dt == F64 ? 8 : dt == F32 ? 4 : 2; }
 // old ones. No host round trip is needed inside an iteration.
 struct alignas(64) State {
   double delta;    // delta_i = r_i^T M^-1 r_i
-  double alpha;    // alpha_i, pending in x until the next A-kernel applies it
+  double alpha;    // alpha_i (st[1], from the G^T-kernel); 0 in st[0] once the G-kernel applied it
   double beta;     // beta_{i+1}, used by the next A-kernel to form d
   double gamma;    // d_i^T A d_i
   double rr;       // ||r||^2 of the current residual

@@ -677,7 +677,7 @@ struct CoreOut {
 };
 
 // Start sequence for the systems of L: ||b||, r = b - A x, t = G^T r,
-// s = G t, delta (states already uploaded; x loaded).
+// d = G t (+ eps r), delta (states already uploaded; x loaded).
 int enqueue_start(pcg_ctx *ctx, const Types &ty, const LaunchSet &L, bool has_eps) {
   hipStream_t s = ctx->stream;
   HIPCHK(pcgk::launch_zero_dirs(ty, L, false, s));
@@ -1304,7 +1304,7 @@ int progress(pcg_ctx *ctx, int iters) {
   for (auto &R : ctx->active)
     if (ctx->h_states[2 * R->slot].done) done_slots.push_back(R->slot);
   if (done_slots.empty()) return PCG_OK;
-  // finish the stopped systems: pending x update, true residual
+  // finish the stopped systems: any pending x update, true residual
   HostSet hs;
   if ((rc = build_set(ctx, hs, done_slots))) return rc;
   HIPCHK(pcgk::launch_finalize(ctx->ty, hs.L, s));

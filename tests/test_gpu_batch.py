@@ -179,3 +179,29 @@ def test_admission_by_memory_budget(gpu_lib):
     for k, (x, r) in enumerate(res):
         if k != 3:
             assert r["status"] == pcg.OK and r["relres_true"] <= 1e-8
+
+
+@pytest.mark.parametrize("refine", [0, 1])
+def test_batch_with_blocked_systems_equals_single(gpu_lib, refine):
+    """Elasticity systems (A in the 3x3-block layout) batched with Poisson and
+    RGG systems (sliced ELL, CSR): each equals its single solve bit for bit,
+    plain FP64 and FP32 with FP64 refinement (whose FP64 view of A keeps the
+    block layout)."""
+    pcg = gpu_lib
+    systems = []
+    for k, A in enumerate([inputs.elasticity(5, 1.0, 0.3, 1), inputs.poisson(3, 12, 0.5, 2),
+                           inputs.elasticity(7, 1.0, 0.3, 3), inputs.rgg_laplacian(3000, 4)]):
+        systems.append(dict(A=A, b=inputs.rhs(A.n, k), tol=1e-9, maxit=4000))
+    kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1) if refine else {}
+    say("blocked batch", refine, [s["A"].n for s in systems])
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        batch = s.solve_batch(systems, iters_per_step=9)
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        for sd, (xb, rb) in zip(systems, batch):
+            s.set_matrix(sd["A"])
+            s.build_precond(pcg.G_FSAI)
+            single = s.solve(sd["b"], tol=sd["tol"], maxit=sd["maxit"])
+            assert rb["status"] == single.status == pcg.OK
+            assert rb["iters"] == single.iters and np.array_equal(xb, single.x)
+            r64 = np.linalg.norm(sd["b"] - oracle.spmv(sd["A"], xb)) / np.linalg.norm(sd["b"])
+            assert r64 <= 1.0001e-9
