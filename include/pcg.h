@@ -243,10 +243,17 @@ int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double
  * it. Submission may run concurrently with pcg_progress from another thread;
  * the caller must keep each system's x buffer alive until its ticket is done.
  * pcg_solve_batch submits `count` systems and progresses until all finish,
- * `iters_per_step` iterations per step (0: 20). */
+ * `iters_per_step` iterations per step (0: 20). pcg_wait drives pcg_progress
+ * (graph_iters iterations per step, 0: 20) until every one of `count`
+ * tickets has finished, then collects them as pcg_poll does (results may be
+ * NULL); timeout_s < 0 waits without limit. It returns PCG_PENDING, with no
+ * ticket collected, when the time runs out first, and PCG_EINVAL for an
+ * unknown or already collected ticket. The per-system status is in
+ * results[i].status. */
 int pcg_submit_batch(pcg_ctx *ctx, int count, const pcg_system *sys, uint64_t *tickets);
 int pcg_progress(pcg_ctx *ctx, int iters, int *active, int *queued);
 int pcg_poll(pcg_ctx *ctx, uint64_t ticket, pcg_result *res);
+int pcg_wait(pcg_ctx *ctx, int count, const uint64_t *tickets, pcg_result *results, double timeout_s);
 int pcg_solve_batch(pcg_ctx *ctx, int count, const pcg_system *sys, pcg_result *results, int iters_per_step);
 
 /* Capacity and bytes in use of the batch pool (0 before first use). */
@@ -265,6 +272,15 @@ int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col
  * n+1 / pcg_g_nnz. */
 int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, const int32_t *col,
                      const double *val, int32_t *g_rowptr, int32_t *g_col, double *g_val);
+
+/* Upper estimate of the device memory one system (n unknowns, nnz_a entries
+ * of A, nnz_g of G) takes from the serving pool of a context configured by
+ * cfg: A, G and G^T as the automatic layout stores them (sliced layouts are
+ * chosen only while their padding stays within 1/8; a forced sliced layout
+ * may pad more), the vectors, staging, partial sums, and the FP64 view of A
+ * under refinement. For admission planning; host only, no GPU needed.
+ * Returns PCG_EINVAL for a NULL pointer, n <= 0 or negative counts. */
+int pcg_estimate_bytes(const pcg_config *cfg, int32_t n, int64_t nnz_a, int64_t nnz_g, size_t *bytes);
 
 /* Algorithmic device bytes of one PCG iteration: A, G^T and G read once,
  * their row pointers, and 11 vector streams of n entries (vec bytes each). */

@@ -438,6 +438,22 @@ int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, 
   return PCG_OK;
 }
 
+int pcg_estimate_bytes(const pcg_config *cfg, int32_t n, int64_t nnz_a, int64_t nnz_g, size_t *bytes) {
+  if (!cfg || !bytes || n <= 0 || nnz_a < 0 || nnz_g < 0) return PCG_EINVAL;
+  const double sa = (double)pcgk::dtype_size(cfg->a_dtype), sg = (double)pcgk::dtype_size(cfg->g_dtype),
+               sv = (double)pcgk::dtype_size(cfg->vec_dtype);
+  const double pad = 1.125;  // sliced layouts keep padding within 1/8
+  const double blocks = 8.0 * ((double)n / 32.0 + 2.0);  // row blocks or slice offsets
+  double b = pad * (double)nnz_a * (sa + 4.0) + 4.0 * (n + 1.0) + blocks;        // A
+  b += 2.0 * (pad * (double)nnz_g * (sg + 4.0) + 4.0 * (n + 1.0) + blocks);      // G, G^T
+  b += (8.0 + 2.0) * (double)n * sv + 8.0 * (double)n;                           // vectors, staging
+  b += 8.0 * 6.0 * 256.0 * std::max(cfg->grid_mult, 8);                         // partial sums
+  if (cfg->refine) b += pad * 8.0 * (double)nnz_a + blocks + 3.0 * 8.0 * (double)n;  // FP64 view of A
+  b += 256.0 * 32.0;                                                             // alignment of the carved arrays
+  *bytes = (size_t)b;
+  return PCG_OK;
+}
+
 double pcg_bytes_per_iter(int32_t n, int64_t nnz_a, int64_t nnz_g, int a_dtype, int g_dtype, int vec_dtype) {
   return pcgh::bytes_per_iter(n, nnz_a, nnz_g, a_dtype, g_dtype, vec_dtype);
 }

@@ -2136,32 +2136,47 @@ int pcg_poll(pcg_ctx *ctx, uint64_t ticket, pcg_result *res) {
   return st;
 }
 
+// Drives the scheduler until every ticket is done (or the time limit).
+static int wait_tickets(pcg_ctx *ctx, int count, const uint64_t *tickets, pcg_result *results, double timeout_s,
+                        int iters_per_step) {
+  const int step = iters_per_step > 0 ? iters_per_step : 20;
+  const double t_end = now_ms() + (timeout_s < 0 ? 1e300 : timeout_s * 1e3);
+  for (;;) {
+    bool all = true;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      for (int i = 0; i < count && all; ++i) {
+        auto it = ctx->by_ticket.find(tickets[i]);
+        if (it == ctx->by_ticket.end()) {
+          ctx->err = "pcg_wait: unknown or already collected ticket";
+          return PCG_EINVAL;
+        }
+        all = it->second->st == RQ_DONE;
+      }
+    }
+    if (all) break;
+    if (now_ms() >= t_end) return PCG_PENDING;
+    int act = 0, q = 0;
+    const int rc = pcg_progress(ctx, step, &act, &q);
+    if (rc) return rc;
+    if (act == 0) std::this_thread::sleep_for(std::chrono::microseconds(200));
+  }
+  for (int i = 0; i < count; ++i) (void)pcg_poll(ctx, tickets[i], results ? &results[i] : nullptr);
+  return PCG_OK;
+}
+
+int pcg_wait(pcg_ctx *ctx, int count, const uint64_t *tickets, pcg_result *results, double timeout_s) {
+  if (!ctx || count < 0 || (count > 0 && !tickets)) return PCG_EINVAL;
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  return wait_tickets(ctx, count, tickets, results, timeout_s, ctx->cfg.graph_iters);
+}
+
 int pcg_solve_batch(pcg_ctx *ctx, int count, const pcg_system *sys, pcg_result *results, int iters_per_step) {
   if (!ctx || count < 0 || (count > 0 && (!sys || !results))) return PCG_EINVAL;
   std::vector<uint64_t> t(count);
   int rc = pcg_submit_batch(ctx, count, sys, t.data());
   if (rc) return rc;
-  const int step = iters_per_step > 0 ? iters_per_step : 20;
-  for (;;) {
-    int act = 0, q = 0;
-    rc = pcg_progress(ctx, step, &act, &q);
-    if (rc) return rc;
-    bool all = true;
-    {
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      for (uint64_t tk : t) {
-        auto it = ctx->by_ticket.find(tk);
-        if (it != ctx->by_ticket.end() && it->second->st != RQ_DONE) {
-          all = false;
-          break;
-        }
-      }
-    }
-    if (all) break;
-    if (act == 0) std::this_thread::sleep_for(std::chrono::microseconds(200));
-  }
-  for (int i = 0; i < count; ++i) (void)pcg_poll(ctx, t[i], &results[i]);
-  return PCG_OK;
+  return wait_tickets(ctx, count, t.data(), results, -1.0, iters_per_step);
 }
 
 int pcg_pool_info(pcg_ctx *ctx, size_t *capacity, size_t *in_use) {

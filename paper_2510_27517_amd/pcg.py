@@ -32,7 +32,7 @@ EXPORTS = [
     "pcg_config_default", "pcg_create", "pcg_destroy", "pcg_set_matrix", "pcg_set_precond", "pcg_build_precond",
     "pcg_solve", "pcg_matvec", "pcg_sai_loss", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
     "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth", "pcg_submit_batch",
-    "pcg_progress", "pcg_poll", "pcg_solve_batch", "pcg_pool_info",
+    "pcg_progress", "pcg_poll", "pcg_wait", "pcg_solve_batch", "pcg_pool_info", "pcg_estimate_bytes",
 ]
 
 
@@ -103,6 +103,8 @@ def load():
     lib.pcg_submit_batch.argtypes = [P, c_int, ctypes.POINTER(System), ctypes.POINTER(ctypes.c_uint64)]
     lib.pcg_progress.argtypes = [P, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     lib.pcg_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+    lib.pcg_wait.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(Result), dbl]
+    lib.pcg_estimate_bytes.argtypes = [ctypes.POINTER(Config), i32, i64, i64, ctypes.POINTER(ctypes.c_size_t)]
     lib.pcg_solve_batch.argtypes = [P, c_int, ctypes.POINTER(System), ctypes.POINTER(Result), c_int]
     lib.pcg_pool_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.pcg_last_error.argtypes = [P]
@@ -181,6 +183,15 @@ def copy_bandwidth(bytes_: int, reps: int = 20, device: int = 0):
     if st != OK:
         raise PCGError(st, "pcg_copy_bandwidth")
     return float(g[0]), float(m[0])
+
+
+def estimate_bytes(cfg: Config, n: int, nnz_a: int, nnz_g: int) -> int:
+    """Upper estimate of the device bytes one system takes under cfg."""
+    out = ctypes.c_size_t()
+    st = load().pcg_estimate_bytes(ctypes.byref(cfg), int(n), int(nnz_a), int(nnz_g), ctypes.byref(out))
+    if st != OK:
+        raise PCGError(st, "pcg_estimate_bytes")
+    return int(out.value)
 
 
 def bytes_per_iter(n, nnz_a, nnz_g, a_dtype=F64, g_dtype=F64, vec_dtype=F64) -> float:
@@ -359,6 +370,21 @@ class Solver:
             raise PCGError(st, "pcg_poll: unknown ticket")
         _keep, x = self._pending.pop(ticket)
         return x, res.as_dict()
+
+    def wait(self, tickets, timeout_s=-1.0):
+        """Block until all tickets finish: [(x, result dict)] in ticket order,
+        or None when timeout_s (seconds, < 0: no limit) runs out first."""
+        tickets = [int(t) for t in tickets]
+        for t in tickets:
+            if t not in getattr(self, "_pending", {}):
+                raise PCGError(EINVAL, "wait: unknown ticket")
+        tk = (ctypes.c_uint64 * len(tickets))(*tickets)
+        res = (Result * len(tickets))()
+        st = self._lib.pcg_wait(self._h, len(tickets), tk, res, float(timeout_s))
+        if st == PENDING:
+            return None
+        self._check(st, "pcg_wait")
+        return [(self._pending.pop(t)[1], res[i].as_dict()) for i, t in enumerate(tickets)]
 
     def solve_batch(self, systems, iters_per_step=20):
         """Solve all systems as one batch; returns [(x, result dict)]."""

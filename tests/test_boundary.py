@@ -111,6 +111,23 @@ def test_bytes_per_iter_formula():
     assert got32 == a * 8 + 2 * g * 6 + 12 * (n + 1) + 11 * n * 4
 
 
+def test_estimate_bytes_bounds():
+    """Host-only admission estimate: at least the stored matrices and vectors,
+    growing with the precision, with refinement, and with the sizes."""
+    n, a, g = 262_144, 1_810_432, 1_036_288
+    e64 = pcg.estimate_bytes(pcg.default_config(), n, a, g)
+    assert e64 >= a * 12 + 2 * g * 12 + 8 * n * 8
+    assert e64 <= 1.25 * (a * 12 + 2 * g * 12) + 16 * n * 8 + (1 << 20)
+    mixed = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16")
+    e32 = pcg.estimate_bytes(mixed, n, a, g)
+    assert a * 8 + 2 * g * 6 + 8 * n * 4 <= e32 < e64
+    mixed.refine = 1
+    assert pcg.estimate_bytes(mixed, n, a, g) >= e32 + a * 8
+    assert pcg.estimate_bytes(pcg.default_config(), 2 * n, 2 * a, 2 * g) > e64
+    with pytest.raises(pcg.PCGError):
+        pcg.estimate_bytes(pcg.default_config(), 0, a, g)
+
+
 def test_create_without_gpu_fails_cleanly():
     import torch
 

@@ -3,6 +3,7 @@ one launch per CG kernel. Each system's share of a launch depends only on the
 system, so its result must be bit for bit its single-system result, alone or
 in any mix; and each must match the FP64 oracle to the single-solve bar."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -205,3 +206,47 @@ def test_batch_with_blocked_systems_equals_single(gpu_lib, refine):
             assert rb["iters"] == single.iters and np.array_equal(xb, single.x)
             r64 = np.linalg.norm(sd["b"] - oracle.spmv(sd["A"], xb)) / np.linalg.norm(sd["b"])
             assert r64 <= 1.0001e-9
+
+
+def test_wait_and_timeout(gpu_lib):
+    """pcg_wait: a zero time limit returns pending with nothing collected;
+    without a limit it drives the scheduler until every ticket is done and
+    the results equal those of a batch solve; a collected ticket is refused."""
+    pcg = gpu_lib
+    systems = _mix(6, 5)
+    with pcg.Solver(pcg.default_config()) as s:
+        ref = s.solve_batch(systems)
+    with pcg.Solver(pcg.default_config()) as s:
+        tickets = s.submit(systems)
+        assert s.wait(tickets, timeout_s=0.0) is None
+        got = s.wait(tickets)
+        assert s.pool_info()[1] == 0
+        st = s._lib.pcg_wait(s._h, 1, (pcg.ctypes.c_uint64 * 1)(tickets[0]), None, -1.0)
+        assert st == pcg.EINVAL
+    for (xr, rr), (xw, rw) in zip(ref, got):
+        assert rw["status"] == rr["status"] == pcg.OK and rw["iters"] == rr["iters"]
+        assert np.array_equal(xw, xr)
+
+
+@pytest.mark.parametrize("refine", [0, 1])
+def test_estimate_bytes_covers_admitted_storage(gpu_lib, refine):
+    """The host-only estimate is an upper bound of what admission takes from
+    the pool, for A in CSR, sliced ELL and 3x3 blocks."""
+    pcg = gpu_lib
+    kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1) if refine else {}
+    cfg = pcg.default_config(**kw)
+    for A in [inputs.poisson(3, 24, 0.5, 1), inputs.elasticity(8, 1.0, 0.3, 2), inputs.rgg_laplacian(6000, 3)]:
+        nnz_g = (A.nnz + A.n) // 2
+        est = pcg.estimate_bytes(cfg, A.n, A.nnz, nnz_g)
+        with pcg.Solver(cfg) as s:
+            t = s.submit([dict(A=A, b=inputs.rhs(A.n, 1), tol=1e-10, maxit=5000)])
+            used = 0
+            for _ in range(2000):
+                act, _q = s.progress(1)
+                if act:
+                    used = s.pool_info()[1]
+                    break
+                time.sleep(0.002)
+            s.wait(t)
+        say(f"estimate n={A.n} nnz={A.nnz} refine={refine}: used {used} estimate {est}")
+        assert 0 < used <= est <= 1.4 * used + (512 << 10)
