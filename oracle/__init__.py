@@ -8,7 +8,8 @@ arrays and shares no code with the HIP path.
 
 Every function names the passage it follows; see ``oracle.c`` for the
 readings of Algorithm 1 (replacement branch, stopping rule, restart on a
-failed true-residual check).
+failed true-residual check). ``pcg_ir`` emulates the mixed-precision solve
+(FP64 iterative refinement around a PCG on rounded operands) in FP64.
 """
 from __future__ import annotations
 
@@ -295,6 +296,119 @@ def sai_losses(A, G, W, eps: float = 0.0):
         out["l2"][p] = float(np.sum((y - w) ** 2))
         out["cs"][p] = float(np.dot(w, y) / (np.linalg.norm(w) * np.linalg.norm(y)))
     return out
+
+
+# ------------------------------------------- mixed precision (FP64 emulation)
+
+# (significand bits p, exponent of the smallest normal, largest finite value)
+# of the storage formats: IEEE binary32, bfloat16 and IEEE binary16
+_FORMATS = {
+    "f32": (24, -126, (2.0 - 2.0 ** -23) * 2.0 ** 127),
+    "bf16": (8, -126, (2.0 - 2.0 ** -7) * 2.0 ** 127),
+    "f16": (11, -14, 65504.0),
+}
+
+
+def round_storage(x, fmt: str) -> np.ndarray:
+    """x rounded once, to nearest with ties to even, onto the storage format
+    fmt ("f64" keeps x). A value in [2^(e-1), 2^e) has the quantum 2^(e-p);
+    below the smallest normal 2^emin the quantum stays 2^(emin-p+1)
+    (subnormals); a result above the largest finite value is infinite."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    if fmt == "f64":
+        return x
+    p, emin, vmax = _FORMATS[fmt]
+    _, e = np.frexp(x)
+    q = np.maximum(e - p, emin - p + 1)
+    y = np.ldexp(np.rint(np.ldexp(x, -q)), q)
+    return np.where(np.abs(y) > vmax, np.copysign(np.inf, x), y)
+
+
+def g_storage_scale(G, fmt: str) -> float:
+    """Power-of-two scale under which G is stored (reading of the mixed-
+    precision setup): 1, except for binary16, whose narrow exponent range
+    takes G times 2^(14-e), max |G| = m 2^e with m in [1/2, 1), so that the
+    largest stored entry lies in [2^13, 2^14). PCG is invariant to the scale
+    of M^-1 when eps is scaled alike (Algorithm 1: alpha and x are unchanged,
+    delta and beta scale together)."""
+    if fmt != "f16":
+        return 1.0
+    m = float(np.abs(_mat(G).val).max())
+    if m == 0.0:
+        return 1.0
+    _, e = np.frexp(m)
+    return float(2.0 ** (14 - int(e)))
+
+
+def inner_tolerance(inner_tol: float, tol: float, nb: float, rn: float) -> float:
+    """Relative tolerance of an inner solve: inner_tol, but no tighter than
+    what brings ||r64|| from rn to a quarter of the target tol ||b||, and never
+    looser than 1/2."""
+    return min(0.5, max(inner_tol, 0.25 * tol * nb / rn))
+
+
+@dataclass
+class IRResult:
+    x: np.ndarray
+    status: int
+    outer: int
+    iters: int          # inner iterations over all outer steps
+    relres_true: float  # ||b - A x|| / ||b|| in FP64 at exit
+    rhist: np.ndarray   # ||r64|| / ||b|| before each outer step and at exit
+
+
+def pcg_ir(A, G, b, *, tol: float = 1e-10, a_dtype: str = "f32", g_dtype: str = "bf16", vec_dtype: str = "f32",
+           eps: float = 0.0, inner_tol: float = 1e-4, max_outer: int = 30, maxit: int = 2000) -> IRResult:
+    """FP64 iterative refinement around a PCG on stored operands (the mixed-
+    precision setting of Sec. 4: G in a 16-bit format, A and vectors in FP32,
+    FP64 dot products), as an FP64 emulation. Storage is emulated by rounding
+    (round_storage) A's values, G's values (times g_storage_scale) and the
+    vectors the inner solve receives and returns; the inner PCG itself runs
+    in FP64 on those rounded operands. The outer loop:
+      r = b - A x in FP64 on the unrounded A; stop with OK once
+      ||r|| <= tol ||b||; stop with NOT_CONVERGED after max_outer steps or
+      when ||r|| fails to fall below 0.9 times its previous value;
+      inner PCG (Algorithm 1 with M^-1 = G G^T + eps I, no residual
+      replacement, stopping on its recurrence residual) on A_s c = r / ||r||
+      from c = 0 to inner_tolerance(...); x += ||r|| c.
+    b = 0 returns x = 0 after no outer step; an inner breakdown ends the
+    solve with EBREAKDOWN."""
+    A = _mat(A)
+    G = _mat(G)
+    b = np.asarray(b, np.float64)
+    n = A.n
+    sc = g_storage_scale(G, g_dtype)
+    As = Mat(A.rowptr, A.col, round_storage(A.val, a_dtype))
+    Gs = Mat(G.rowptr, G.col, round_storage(G.val * sc, g_dtype))
+    x = np.zeros(n)
+    nb = float(np.sqrt(dot(b, b)))
+    if nb == 0.0:
+        return IRResult(x, OK, 0, 0, 0.0, np.zeros(1))
+    outer, iters, prev, status = 0, 0, np.inf, NOT_CONVERGED
+    hist = []
+    while True:
+        r = b - spmv(A, x)
+        rn = float(np.sqrt(dot(r, r)))
+        hist.append(rn / nb)
+        if rn <= tol * nb:
+            status = OK
+            break
+        if not np.isfinite(rn):
+            status = EBREAKDOWN
+            break
+        if outer >= max_outer or rn > 0.9 * prev:
+            break
+        prev = rn
+        rhs = round_storage(r / rn, vec_dtype)
+        inner = pcg(As, Gs, rhs, eps=eps * sc * sc, tol=inner_tolerance(inner_tol, tol, nb, rn), maxit=maxit,
+                    rr_period=0, delta_form=1, stop_rule=2)
+        iters += inner.iters
+        if inner.status == EBREAKDOWN:
+            status = EBREAKDOWN
+            break
+        x = x + rn * round_storage(inner.x, vec_dtype)
+        outer += 1
+    return IRResult(x, status, outer, iters, hist[-1], np.array(hist))
 
 
 def identity(n: int) -> Mat:

@@ -137,7 +137,10 @@ typedef struct {
   int32_t rr_period; /* residual replacement period of Algorithm 1 (50); 0 = never */
   int32_t delta_form; /* 0: delta = r^T s;  1: delta = ||G^T r||^2 + eps ||r||^2 (same value) */
   int32_t stop_rule;  /* 0: ||r|| <= tol ||b||, confirmed on the true residual;
-                         1: Algorithm 1's delta_new <= tol^2 delta_0 */
+                         1: Algorithm 1's delta_new <= tol^2 delta_0;
+                         2: ||r|| <= tol ||b|| on the recurrence alone (the inner
+                            solves of iterative refinement, whose FP64 outer
+                            residual is the check) */
   int32_t threads;
 } or_opts;
 
@@ -216,8 +219,10 @@ int or_pcg(int32_t n, const int32_t *arp, const int32_t *aci, const double *av, 
         memcpy(d, s, bytes);
         res->restarts++;
       }
-    } else {
+    } else if (o->stop_rule == 1) {
       if (!(delta > o->tol * o->tol * delta0)) { status = OR_OK; break; }
+    } else {
+      if (rnorm <= o->tol * nb) { status = OR_OK; break; }
     }
     if (i >= o->maxit) break;
 

@@ -20,28 +20,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def round_sig(v, sig, emin):
-    """Round to nearest-even onto a binary format with `sig` significant bits
-    and minimum normal exponent emin (subnormals included)."""
-    v = np.asarray(v, np.float64)
-    out = np.zeros_like(v)
-    nz = v != 0
-    a = np.abs(v[nz])
-    _, e = np.frexp(a)
-    q = np.where(e - 1 < emin, emin - (sig - 1), e - sig)
-    out[nz] = np.copysign(np.ldexp(np.rint(np.ldexp(a, -q)), q), v[nz])
-    return out
-
-
 def stored_g(val, gdt):
-    """G's values as the library stores them (as float32) and the scale."""
-    if gdt == "f32":
-        return val.astype(np.float32), 1.0
-    if gdt == "bf16":
-        return round_sig(val, 8, -126).astype(np.float32), 1.0
-    _, e = np.frexp(np.abs(val).max())
-    scale = 2.0 ** (14 - int(e))
-    return round_sig(val * scale, 11, -14).astype(np.float32), scale
+    """G's values as the library stores them (as float32) and the scale:
+    once-rounded RNE onto gdt, binary16 under its power-of-two scale."""
+    G = CSR(np.array([0, val.shape[0]], np.int32), np.zeros(val.shape[0], np.int32), val)
+    sc = oracle.g_storage_scale(G, gdt)
+    return oracle.round_storage(val * sc, gdt).astype(np.float32), sc
 
 
 def _random_spd(n, seed):
@@ -150,3 +134,46 @@ def test_mixed_zero_rhs_and_bad_config(gpu_lib):
     with pytest.raises(pcg.PCGError) as e:
         pcg.Solver(pcg.default_config(vec_dtype="f64", a_dtype="f64", g_dtype="bf16"))
     assert e.value.status == pcg.EINVAL
+
+
+@pytest.mark.parametrize("case,gdt", [("poisson3d", "bf16"), ("poisson3d", "f16"), ("poisson3d", "f32"),
+                                      ("elasticity", "bf16")])
+def test_refinement_follows_the_emulated_outer_loop(gpu_lib, case, gdt):
+    """The library's refinement against the oracle's FP64 emulation of the
+    same outer loop (operands rounded as stored, inner solve in FP64). Only
+    the inner solve's arithmetic differs (FP32 vectors and sums, FP64 dots),
+    which moves each inner residual by a relative O(kappa u32): same status
+    and outer steps, inner iterations within 2 % plus one per outer step, and
+    both solutions within the 1e-10 residual bound of each other. Cut to two
+    outer steps, both stop unconverged with FP64 residuals within a factor 2."""
+    pcg = gpu_lib
+    if case == "poisson3d":
+        A = inputs.poisson(3, 24, 1.0, 3)
+    else:
+        A = inputs.elasticity(8, 1.0, 0.3, 3)
+    b = inputs.rhs(A.n, 3)
+    G = oracle.fsai_g(A)
+    say("refinement vs emulation", case, gdt)
+    kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype=gdt, refine=1)
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        got = s.solve(b, tol=1e-10, maxit=5000)
+    emu = oracle.pcg_ir(A, G, b, tol=1e-10, a_dtype="f32", g_dtype=gdt, maxit=5000)
+    say(f"  gpu: status {got.status} outer {got.outer_iters} inner {got.iters} relres {got.relres_true:.2e}; "
+        f"emulation: status {emu.status} outer {emu.outer} inner {emu.iters} relres {emu.relres_true:.2e}")
+    assert got.status == emu.status == pcg.OK
+    assert got.outer_iters == emu.outer
+    assert abs(got.iters - emu.iters) <= 0.02 * emu.iters + emu.outer
+    nx = np.linalg.norm(emu.x)
+    assert np.linalg.norm(got.x - emu.x) <= 1e-6 * nx
+    with pcg.Solver(pcg.default_config(max_outer=2, **kw)) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        cut = s.solve(b, tol=1e-14, maxit=5000)
+    ecut = oracle.pcg_ir(A, G, b, tol=1e-14, a_dtype="f32", g_dtype=gdt, maxit=5000, max_outer=2)
+    r64 = np.linalg.norm(b - oracle.spmv(A, cut.x)) / np.linalg.norm(b)
+    say(f"  two outer steps: gpu relres {r64:.2e} (reported {cut.relres_true:.2e}), emulation {ecut.relres_true:.2e}")
+    assert cut.status == ecut.status == pcg.NOT_CONVERGED and cut.outer_iters == ecut.outer == 2
+    assert 0.5 <= r64 / ecut.relres_true <= 2.0
+    assert abs(cut.relres_true - r64) <= 1e-3 * r64

@@ -519,3 +519,124 @@ def test_hutchinson_mean_approaches_the_frobenius_norm():
     out = oracle.sai_losses(A, G, W)
     exact = oracle.sai_losses(A, G, np.eye(n))["sai"].sum()
     assert abs(out["sai"].mean() - exact) <= 0.1 * exact
+
+
+# ---------------------------------------------- mixed precision (emulation)
+
+def test_round_storage_matches_numpy_binary32_and_binary16():
+    """Once-rounded RNE onto binary32 and binary16 equals numpy's direct
+    double-to-float conversions, normals, subnormals, ties and overflow."""
+    rng = np.random.default_rng(40)
+    x = rng.standard_normal(20000) * 10.0 ** rng.integers(-46, 40, 20000)
+    x = np.concatenate([x, [0.0, -0.0, 3.4e38, 3.5e38, -1e39, 1e-45, 7e-46, 65504.0, 65519.9, 65520.0, 6e-8,
+                            2.0 ** -25, 3 * 2.0 ** -26, 1.0 + 2.0 ** -24, 1.0 + 3 * 2.0 ** -24]])
+    with np.errstate(over="ignore"):
+        assert np.array_equal(oracle.round_storage(x, "f32"), x.astype(np.float32).astype(np.float64))
+        assert np.array_equal(oracle.round_storage(x, "f16"), x.astype(np.float16).astype(np.float64))
+    assert np.array_equal(oracle.round_storage(x, "f64"), x)
+
+
+def test_round_storage_bfloat16_brute_force():
+    """bfloat16: nearest of all finite values (the binary32 patterns with the
+    low 16 bits clear), ties to the even pattern, including exact midpoints."""
+    k = np.arange(0, 0x7F80, dtype=np.uint32)
+    vals = (k << 16).view(np.float32).astype(np.float64)  # all finite non-negative bf16, ascending
+    rng = np.random.default_rng(41)
+    x = np.abs(rng.standard_normal(5000)) * 10.0 ** rng.integers(-40, 38, 5000)
+    mids = (vals[1:] + vals[:-1]) / 2  # exact in FP64 (9 significant bits)
+    x = np.concatenate([x, mids[rng.integers(0, mids.shape[0], 2000)], [0.0, vals[-1]]])
+    i = np.clip(np.searchsorted(vals, x), 1, vals.shape[0] - 1)
+    lo, hi = vals[i - 1], vals[i]
+    pick_hi = (x - lo > hi - x) | ((x - lo == hi - x) & (k[i] % 2 == 0))
+    want = np.where(x >= vals[-1], vals[-1], np.where(pick_hi, hi, lo))
+    want = np.where(x == 0, 0.0, want)
+    got = oracle.round_storage(x, "bf16")
+    assert np.array_equal(got, want)
+    assert np.array_equal(oracle.round_storage(-x, "bf16"), -want)
+
+
+def test_g_storage_scale_places_max_in_binade():
+    G = CSR(np.array([0, 1, 3], np.int32), np.array([0, 0, 1], np.int32), np.array([3e-7, -1.5e-9, 2.4e-7]))
+    sc = oracle.g_storage_scale(G, "f16")
+    assert 2.0 ** 13 <= np.abs(G.val).max() * sc < 2.0 ** 14 and np.log2(sc) == int(np.log2(sc))
+    assert oracle.g_storage_scale(G, "bf16") == 1.0
+
+
+def test_recurrence_only_stop_equals_confirmed_stop_without_drift():
+    """stop_rule 2 (no true-residual confirmation) takes the same iterates as
+    stop_rule 0 when the confirmation never fails."""
+    A = inputs.poisson(2, 20, 0.5, 3)
+    b = inputs.rhs(A.n, 3)
+    G = oracle.fsai_g(A)
+    r0 = oracle.pcg(A, G, b, tol=1e-6, rr_period=0, delta_form=1, stop_rule=0)
+    r2 = oracle.pcg(A, G, b, tol=1e-6, rr_period=0, delta_form=1, stop_rule=2)
+    assert r0.restarts == 0 and r0.status == r2.status == oracle.OK
+    assert r0.iters == r2.iters and np.array_equal(r0.x, r2.x)
+    assert r2.relres_rec <= 1e-6
+
+
+def test_ir_exact_storage_one_step():
+    """Unrounded storage and a tight inner tolerance: one outer step reaches
+    tol and x is the dense solution to the residual bound."""
+    A = inputs.poisson(2, 16, 0.5, 4)
+    b = inputs.rhs(A.n, 4)
+    res = oracle.pcg_ir(A, oracle.fsai_g(A), b, tol=1e-8, a_dtype="f64", g_dtype="f64", vec_dtype="f64",
+                        inner_tol=1e-12)
+    Ad = A.to_dense()
+    xs = np.linalg.solve(Ad, b)
+    assert res.status == oracle.OK and res.outer == 1 and res.relres_true <= 1e-8
+    assert np.linalg.norm(res.x - xs) <= np.linalg.cond(Ad) * 1e-8 * np.linalg.norm(xs)
+
+
+def test_ir_each_step_contracts_by_the_inner_tolerance():
+    """Exact storage: the inner solve is CG on A c = r/||r|| itself, so the
+    FP64 residual after x += ||r|| c is ||r|| times the inner relative
+    residual, at most the inner tolerance of that step."""
+    A = inputs.poisson(3, 8, 0.5, 5)
+    b = inputs.rhs(A.n, 5)
+    res = oracle.pcg_ir(A, oracle.fsai_g(A), b, tol=1e-13, a_dtype="f64", g_dtype="f64", vec_dtype="f64",
+                        inner_tol=1e-3)
+    h = res.rhist
+    assert res.status == oracle.OK and res.outer == h.shape[0] - 1 >= 3
+    for k in range(res.outer):
+        eta = oracle.inner_tolerance(1e-3, 1e-13, 1.0, h[k])
+        assert h[k + 1] <= eta * h[k] * (1 + 1e-6) + 1e-15, (k, h)
+
+
+@pytest.mark.parametrize("gdt", ["bf16", "f16", "f32"])
+def test_ir_rounded_storage_reaches_tolerance(gdt):
+    """A in FP32, G in gdt, vectors rounded to FP32: the FP64 outer residual
+    still reaches 1e-10 (the inner operator differs from A by about
+    2^-24 |A|, far inside the contraction), decreasing at every step."""
+    A = inputs.poisson(3, 10, 1.0, 6)
+    b = inputs.rhs(A.n, 6)
+    res = oracle.pcg_ir(A, oracle.fsai_g(A), b, tol=1e-10, a_dtype="f32", g_dtype=gdt)
+    assert res.status == oracle.OK and res.relres_true <= 1e-10 and 2 <= res.outer <= 5
+    assert np.all(np.diff(res.rhist) < 0)
+    r = b - oracle.spmv(A, res.x)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_ir_edge_cases():
+    A = inputs.poisson(2, 12, 0.5, 7)
+    b = inputs.rhs(A.n, 7)
+    G = oracle.fsai_g(A)
+    z = oracle.pcg_ir(A, G, np.zeros(A.n))
+    assert z.status == oracle.OK and z.outer == 0 and np.all(z.x == 0)
+    one = oracle.pcg_ir(A, G, b, tol=1e-14, max_outer=1)
+    assert one.status == oracle.NOT_CONVERGED and one.outer == 1 and one.relres_true <= 1e-3
+    neg = CSR(A.rowptr, A.col, -A.val)
+    bd = oracle.pcg_ir(neg, oracle.identity(A.n), b)
+    assert bd.status == oracle.EBREAKDOWN and bd.outer == 0
+    # one plain CG step per inner solve gains less and less: the loop stops
+    # at the first outer step that fails to gain 10 %
+    L = inputs.poisson(2, 30, 0.5, 8)
+    st = oracle.pcg_ir(L, oracle.identity(L.n), inputs.rhs(L.n, 8), tol=1e-12, a_dtype="f64", g_dtype="f64",
+                       vec_dtype="f64", maxit=1, max_outer=50)
+    assert st.status == oracle.NOT_CONVERGED and 1 < st.outer < 50
+    assert st.rhist[-1] > 0.9 * st.rhist[-2] and np.all(st.rhist[1:-1] <= 0.9 * st.rhist[:-2])
+    # high-contrast coefficients stored in bfloat16 lose definiteness: the
+    # inner solve breaks down instead of returning a wrong answer
+    H = inputs.poisson(2, 40, 2.0, 8)
+    hb = oracle.pcg_ir(H, oracle.fsai_g(H), inputs.rhs(H.n, 8), tol=1e-12, a_dtype="bf16")
+    assert hb.status == oracle.EBREAKDOWN and np.all(hb.x == 0)
