@@ -111,9 +111,7 @@ def cpu_baseline(A, b, gpu_iters, budget_s, gpu_solutions):
 
 # ---------------------------------------------------------------- sections
 
-def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
-    """128^3 in FP32 (A, vectors) with BF16 G and FP64 refinement to 1e-8."""
-    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+def _timed_solves(pcg, torch, cfg, A, G, b_dev, steps):
     with pcg.Solver(cfg) as s:
         s.set_matrix(A)
         s.set_precond(rowptr=G[0], col=G[1], val=G[2])
@@ -123,11 +121,24 @@ def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
         for _ in range(steps):
             r = s.solve(b_dev, tol=TOL, maxit=MAXIT)
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
+        return (time.perf_counter() - t0) * 1e3 / steps, r
+
+
+def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
+    """128^3 in FP32 (A, vectors) with BF16 G and FP64 refinement to 1e-8; and
+    FP64 vectors and A with the BF16 G (FP64 PCG, 16-bit preconditioner)."""
+    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    ms, r = _timed_solves(pcg, torch, cfg, A, G, b_dev, steps)
+    ms64, r64 = _timed_solves(pcg, torch, pcg.default_config(g_dtype="bf16"), A, G, b_dev, steps)
     return {"workload": "poisson3d_128^3_sigma1_fsai, A/vectors f32, G bf16, FP64 refinement to 1e-8",
             "time_to_tol_ms": round(ms, 3), "speedup_vs_fp64": round(t_fp64_ms / ms, 3), "status": r.status,
             "inner_iters": r.iters, "outer_iters": r.outer_iters, "relres_true_fp64": r.relres_true,
-            "alg_bytes_per_inner_iter": r.bytes_per_iter}, r.x.cpu().numpy()
+            "alg_bytes_per_inner_iter": r.bytes_per_iter,
+            "fp64_bf16_g": {"workload": "same system, A/vectors f64, G bf16 (no refinement), tol 1e-8",
+                            "time_to_tol_ms": round(ms64, 3), "speedup_vs_fp64": round(t_fp64_ms / ms64, 3),
+                            "status": r64.status, "iters": r64.iters, "relres_true_fp64": r64.relres_true,
+                            "ms_per_iter": round(ms64 / max(r64.iters, 1), 5),
+                            "alg_bytes_per_iter": r64.bytes_per_iter}}, r.x.cpu().numpy()
 
 
 def section_sai_loss(pcg, inputs, A, G, k, reps=3):

@@ -79,8 +79,10 @@ typedef struct {
   void *stream;      /* hipStream_t to run on; NULL: the library creates its own */
   int vec_dtype;     /* PCG_F64 or PCG_F32: Krylov vectors and SpMV accumulation */
   int a_dtype;       /* PCG_F64 or PCG_F32: stored values of A (must equal vec_dtype) */
-  int g_dtype;       /* PCG_F64, PCG_F32, PCG_BF16 or PCG_F16: stored values of G and G^T
-                        (F64 only with F64 vectors; half types with F32 vectors) */
+  int g_dtype;       /* PCG_F64, PCG_F32, PCG_BF16 or PCG_F16: stored values of G and G^T.
+                        With F64 vectors any of them (G only preconditions: a rounded G is another
+                        SPD M, and the FP64 iteration still reaches the FP64 tolerance); with F32
+                        vectors F32, BF16 or F16. F16 values are stored times a power of two. */
   int rr_period;     /* recompute r = b - A x every rr_period iterations (Algorithm 1 uses 50); 0 = never */
   double eps;        /* shift of M^-1 = G G^T + eps I, absolute units (default 0) */
   int refine;        /* 1: FP64 iterative refinement around a vec_dtype = F32 inner PCG */
@@ -95,7 +97,10 @@ typedef struct {
   int g_device;      /* 1: pcg_build_precond(PCG_G_FSAI) factors on the device (one wave per row; same
                         arithmetic as the host builder); falls back to the host for tril rows longer
                         than 80 or a structurally unsymmetric A. 0 (default): on the host */
-  int reserved[5];
+  int wide_index;    /* 0 (default): a sliced matrix whose every stored column lies within 32767 of its
+                        row keeps 16-bit column - row differences (half the index bytes); 1: always
+                        32-bit column indices */
+  int reserved[4];
 } pcg_config;
 
 /* Matrix storage layouts (pcg_config.layout). Both give bit-identical

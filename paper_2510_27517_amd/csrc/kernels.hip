@@ -124,11 +124,19 @@ struct Mat {
   int32_t nblk;
   int32_t n;
   int32_t fmt;
+  int32_t idx16;
 };
 
 template <typename TM>
 __device__ __forceinline__ Mat<TM> mat(const DevCSR &m) {
-  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk, m.n, m.fmt};
+  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk, m.n, m.fmt, m.idx16};
+}
+
+// Column of stored entry q of `row` (sliced layouts with 16-bit indices keep
+// the column minus the row).
+template <typename TM>
+__device__ __forceinline__ int32_t col_at(const Mat<TM> &M, int64_t q, int32_t row) {
+  return M.idx16 ? row + (int32_t)((GLOBAL const int16_t *)M.ci)[q] : M.ci[q];
 }
 
 // Operands of one row loaded before the row's products are staged.
@@ -214,21 +222,37 @@ __device__ __forceinline__ Sched sched(int nblk, int l, int G) {
 // Slot of this workgroup's partial sums (the same for both layouts).
 __device__ __forceinline__ int part_slot(int l, int G) { return (l & 7) * (G >> 3) + (l >> 3); }
 
+// Column of a slice entry: an absolute int32 index, or an int16 difference
+// from the lane's row.
+__device__ __forceinline__ int32_t slice_col(GLOBAL const int32_t *cc, int64_t k, int32_t) { return ldstream(cc, k); }
+__device__ __forceinline__ int32_t slice_col(GLOBAL const int16_t *cc, int64_t k, int32_t row) {
+  return row + (int32_t)ldstream(cc, k);
+}
+
 // One lane's row of a slice: products of its wd entries added left to right
 // from zero (loads issued UNR at a time).
-template <typename TACC, int UNR, typename TM, typename Gather>
-__device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const int32_t *cc, int wd, Gather gather) {
+template <typename TACC, int UNR, typename TM, typename TI, typename Gather>
+__device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const TI *cc, int32_t row, int wd,
+                                              Gather gather) {
   TACC sum = 0;
   int k = 0;
   for (; k + UNR <= wd; k += UNR) {
     TACC p[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) p[u] = (TACC)ldval(vv, (k + u) * kSliceRows) * gather(ldstream(cc, (k + u) * kSliceRows));
+    for (int u = 0; u < UNR; ++u)
+      p[u] = (TACC)ldval(vv, (k + u) * kSliceRows) * gather(slice_col(cc, (k + u) * kSliceRows, row));
 #pragma unroll
     for (int u = 0; u < UNR; ++u) sum += p[u];
   }
-  for (; k < wd; ++k) sum += (TACC)ldval(vv, k * kSliceRows) * gather(ldstream(cc, k * kSliceRows));
+  for (; k < wd; ++k) sum += (TACC)ldval(vv, k * kSliceRows) * gather(slice_col(cc, k * kSliceRows, row));
   return sum;
+}
+
+template <typename TACC, int UW, typename TM, typename TI, typename Gather>
+__device__ __forceinline__ TACC slice_row(GLOBAL const TM *vv, GLOBAL const TI *cc, int32_t row, int wd,
+                                          Gather gather) {
+  return (UW > 4 && wd >= 32) ? slice_row_sum<TACC, UW>(vv, cc, row, wd, gather)
+                              : slice_row_sum<TACC, 4>(vv, cc, row, wd, gather);
 }
 
 // Sliced-ELL rows: each wave takes whole slices (64 rows, one per lane); a
@@ -251,10 +275,10 @@ __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pr
     const bool has = row < M.n;
     RowVals<TACC> pv{};
     if (has) pv = pre(row);
-    GLOBAL const int32_t *cc = M.ci + (int64_t)o0 * kSliceRows + lane;
-    GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lane;
-    const TACC sum = (UW > 4 && wd >= 32) ? slice_row_sum<TACC, UW>(vv, cc, wd, gather)
-                                          : slice_row_sum<TACC, 4>(vv, cc, wd, gather);
+    const int64_t o = (int64_t)o0 * kSliceRows + lane;
+    GLOBAL const TM *vv = M.val + o;
+    const TACC sum = M.idx16 ? slice_row<TACC, UW>(vv, (GLOBAL const int16_t *)M.ci + o, row, wd, gather)
+                             : slice_row<TACC, UW>(vv, M.ci + o, row, wd, gather);
     if (has) epi(row, sum, pv);
   }
 }
@@ -1006,7 +1030,7 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmm(DevCSR Md, int32_
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int64_t q = e0 + (int64_t)(e + u) * stride;
-          col[u] = M.ci[q];
+          col[u] = col_at(M, q, row);
           a[u] = ld64(M.val, q);
         }
         double x[4];
@@ -1017,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmm(DevCSR Md, int32_
       }
       for (; e < len; ++e) {
         const int64_t q = e0 + (int64_t)e * stride;
-        const int32_t col = M.ci[q];
+        const int32_t col = col_at(M, q, row);
         const double a = ld64(M.val, q);
         sum += a * (act ? X[(int64_t)col * k + p] : 0.0);
       }

@@ -129,14 +129,35 @@ struct HostMat {
   std::vector<int32_t> ci;   // columns in storage order
   std::vector<uint8_t> val;  // values in dt, in storage order (empty: written on the device)
   std::vector<int32_t> blk;  // row-block pairs (FMT_CSR) or slice offsets (FMT_SELL)
+  std::vector<int16_t> ci16; // FMT_SELL with idx16: column - row of each stored entry (ci then empty)
+  int64_t stored = 0;        // stored indices (padding included)
+  int32_t idx16 = 0;
   int32_t nunits = 0, grid = 8;
   int vpi = 1;  // values per stored index (9 for 3x3 blocks)
-  size_t val_bytes() const { return pcgk::dtype_size(dt) * (size_t)vpi * std::max<size_t>(ci.size(), 1); }
+  size_t val_bytes() const { return pcgk::dtype_size(dt) * (size_t)vpi * (size_t)std::max<int64_t>(stored, 1); }
+  size_t idx_bytes() const { return (idx16 ? 2 : 4) * (size_t)std::max<int64_t>(stored, 1); }
   size_t bytes() const {
-    return align_up(4 * rp.size()) + align_up(4 * std::max<size_t>(ci.size(), 1)) + align_up(val_bytes()) +
-           align_up(4 * blk.size());
+    return align_up(4 * rp.size()) + align_up(idx_bytes()) + align_up(val_bytes()) + align_up(4 * blk.size());
   }
 };
+
+// Sliced columns as 16-bit differences from their rows, when every stored
+// entry's difference fits (entry p of a slice belongs to row 64 c + p % 64).
+bool narrow_columns(HostMat &M) {
+  const int64_t m = (int64_t)M.ci.size();
+  for (int32_t c = 0; c < M.nunits; ++c)
+    for (int64_t p = (int64_t)M.blk[c] * pcgk::kSliceRows; p < (int64_t)M.blk[c + 1] * pcgk::kSliceRows; ++p) {
+      const int64_t d = (int64_t)M.ci[p] - ((int64_t)c * pcgk::kSliceRows + p % pcgk::kSliceRows);
+      if (d < INT16_MIN || d > INT16_MAX) return false;
+    }
+  M.ci16.resize(m);
+  for (int32_t c = 0; c < M.nunits; ++c)
+    for (int64_t p = (int64_t)M.blk[c] * pcgk::kSliceRows; p < (int64_t)M.blk[c + 1] * pcgk::kSliceRows; ++p)
+      M.ci16[p] = (int16_t)(M.ci[p] - (c * pcgk::kSliceRows + (int32_t)(p % pcgk::kSliceRows)));
+  std::vector<int32_t>().swap(M.ci);
+  M.idx16 = 1;
+  return true;
+}
 
 // Everything a system's A part needs on the device, prepared on the host.
 struct APart {
@@ -232,6 +253,8 @@ void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, 
   M.nnz = rp[n];
   M.dt = dt;
   M.vpi = 1;
+  M.idx16 = 0;
+  M.ci16.clear();
   M.val.clear();
   if (blocks && use_bsr3(cfg.layout, n, rp, ci)) {
     M.fmt = pcgk::FMT_BSR3;
@@ -249,6 +272,9 @@ void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, 
     M.nunits = (int32_t)M.blk.size() - 1;
     const int32_t rounds = (M.nunits + pcgk::kBlock / 64 - 1) / (pcgk::kBlock / 64);
     M.grid = grid_for(cus, cfg.grid_mult, rounds);
+    M.stored = (int64_t)M.ci.size();
+    if (!cfg.wide_index) (void)narrow_columns(M);
+    return;
   } else {
     M.fmt = pcgk::FMT_CSR;
     M.rp.assign(rp, rp + n + 1);
@@ -257,6 +283,7 @@ void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, 
     M.nunits = (int32_t)(M.blk.size() / 2 - 1);
     M.grid = grid_for(cus, cfg.grid_mult, M.nunits);
   }
+  M.stored = (int64_t)M.ci.size();
 }
 
 // Lay out one matrix with values v (CSR order) times `scale` in dt.
@@ -358,11 +385,14 @@ hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, hipStream_t s) {
     if (e == hipSuccess) e = x;
   };
   int32_t *drp = H.rp.empty() ? nullptr : (int32_t *)c.take(4 * H.rp.size());
-  int32_t *dci = (int32_t *)c.take(4 * std::max<size_t>(H.ci.size(), 1));
+  int32_t *dci = (int32_t *)c.take(H.idx_bytes());
   void *dval = c.take(H.val_bytes());
   int32_t *dblk = (int32_t *)c.take(4 * H.blk.size());
   if (drp) chain(h2d(drp, H.rp.data(), 4 * H.rp.size(), s));
-  chain(h2d(dci, H.ci.data(), 4 * H.ci.size(), s));
+  if (H.idx16)
+    chain(h2d(dci, H.ci16.data(), 2 * H.ci16.size(), s));
+  else
+    chain(h2d(dci, H.ci.data(), 4 * H.ci.size(), s));
   if (!H.val.empty()) chain(h2d(dval, H.val.data(), H.val.size(), s));
   chain(h2d(dblk, H.blk.data(), 4 * H.blk.size(), s));
   M.rp = drp;
@@ -375,6 +405,7 @@ hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, hipStream_t s) {
   M.n = H.n;
   M.dtype = H.dt;
   M.fmt = H.fmt;
+  M.idx16 = H.idx16;
   return e;
 }
 
@@ -959,6 +990,18 @@ void start_workers(pcg_ctx *ctx) {
   for (unsigned i = 0; i < nt; ++i) ctx->workers.emplace_back(worker_main, ctx);
 }
 
+// Bytes one iteration moves in the layouts in use: each matrix's values and
+// column indices at their stored widths (3x3 blocks: one index per nine
+// values; 16-bit column differences: two bytes), its row pointers, and the
+// 11 vector streams.
+double layout_bytes_per_iter(const SysDev &D, int64_t nnz_a, int64_t nnz_g, const pcg_config &cfg) {
+  auto ib = [](const pcgk::DevCSR &M) { return M.fmt == pcgk::FMT_BSR3 ? 4.0 / 9.0 : M.idx16 ? 2.0 : 4.0; };
+  const double sa = (double)pcgk::dtype_size(cfg.a_dtype), sg = (double)pcgk::dtype_size(cfg.g_dtype),
+               sv = (double)pcgk::dtype_size(cfg.vec_dtype), rp = 4.0 * (D.n + 1.0);
+  return (double)nnz_a * (sa + ib(D.A)) + (double)nnz_g * (2.0 * sg + ib(D.G) + ib(D.GT)) + 3.0 * rp +
+         11.0 * D.n * sv;
+}
+
 void finish_request(pcg_ctx *ctx, Req &R, int status, const State &f, int restarts) {
   R.t_done = now_ms();
   R.res.status = status;
@@ -968,8 +1011,6 @@ void finish_request(pcg_ctx *ctx, Req &R, int status, const State &f, int restar
   R.res.relres_true = f.bb > 0 ? std::sqrt(f.true_rr / f.bb) : 0.0;
   R.res.relres_rec = f.bb > 0 ? std::sqrt(f.rr / f.bb) : 0.0;
   R.res.t_solve_ms = R.t_done - R.t_admit;
-  R.res.bytes_per_iter = pcgh::bytes_per_iter(R.n, R.sys.nnz_a, R.sys.nnz_g, ctx->cfg.a_dtype, ctx->cfg.g_dtype,
-                                              ctx->cfg.vec_dtype);
   R.res.t_latency_ms = R.t_done - R.t_submit;
   R.res.t_queue_ms = R.t_admit - R.t_submit;
   R.st = RQ_DONE;
@@ -1027,6 +1068,7 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
     HIPCHK(place_g(R.gp, R.sys.blkG, R.sys, s));
     R.sys.dev.st = ctx->d_states + 2 * R.slot;
     ctx->dir[R.slot] = R.sys.dev;
+    R.res.bytes_per_iter = layout_bytes_per_iter(R.sys.dev, R.sys.nnz_a, R.sys.nnz_g, ctx->cfg);
     inits[2 * i] = inits[2 * i + 1] = init_state(ctx, R.tol, R.maxit, R.sys.g_scale);
     R.iter_host = 0;
     if (ctx->cfg.refine) {
@@ -1138,8 +1180,6 @@ void finish_refined(pcg_ctx *ctx, Req &R, int status) {
   R.res.relres_true = R.relres64;
   R.res.relres_rec = R.last_rec;
   R.res.t_solve_ms = R.t_done - R.t_admit;
-  R.res.bytes_per_iter = pcgh::bytes_per_iter(R.n, R.sys.nnz_a, R.sys.nnz_g, ctx->cfg.a_dtype, ctx->cfg.g_dtype,
-                                              ctx->cfg.vec_dtype);
   R.res.t_latency_ms = R.t_done - R.t_submit;
   R.res.t_queue_ms = R.t_admit - R.t_submit;
   R.st = RQ_DONE;
@@ -1458,8 +1498,9 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
   *out = nullptr;
   if (!cfg) return PCG_EINVAL;
   const int v = cfg->vec_dtype, a = cfg->a_dtype, g = cfg->g_dtype;
-  const bool ok = (v == PCG_F64 && a == PCG_F64 && g == PCG_F64 && !cfg->refine) ||
-                  (v == PCG_F32 && a == PCG_F32 && (g == PCG_F32 || g == PCG_BF16 || g == PCG_F16));
+  const bool g_ok = g == PCG_F64 || g == PCG_F32 || g == PCG_BF16 || g == PCG_F16;
+  const bool ok = (v == PCG_F64 && a == PCG_F64 && g_ok && !cfg->refine) ||
+                  (v == PCG_F32 && a == PCG_F32 && g_ok && g != PCG_F64);
   if (!ok || cfg->rr_period < 0 || cfg->graph_iters < 0 || !(cfg->eps >= 0.0) || cfg->mem_budget_mb < 0)
     return PCG_EINVAL;
   int ndev = 0;
@@ -1820,8 +1861,7 @@ int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, i
   HIPCHK(hipSetDevice(ctx->cfg.device));
   if (on_device) HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipEventRecord(ctx->t0, ctx->stream));
-  const double bpi =
-      pcgh::bytes_per_iter(n, S.nnz_a, S.nnz_g, ctx->cfg.a_dtype, ctx->cfg.g_dtype, ctx->cfg.vec_dtype);
+  const double bpi = layout_bytes_per_iter(S.dev, S.nnz_a, S.nnz_g, ctx->cfg);
   if (ctx->cfg.refine) {
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpyAsync(S.dev64.b, b, sizeof(double) * n, kind, ctx->stream));
@@ -2038,9 +2078,10 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
     const double sa = (double)pcgk::dtype_size(ctx->cfg.a_dtype), sg = (double)pcgk::dtype_size(ctx->cfg.g_dtype),
                  sv = (double)pcgk::dtype_size(ctx->cfg.vec_dtype);
     const double rp = 4.0 * (n + 1.0);
-    bytes[0] = (double)S.nnz_a * (sa + 4) + rp + 2.0 * n * sv;
-    bytes[1] = (double)S.nnz_g * (sg + 4) + rp + 4.0 * n * sv;
-    bytes[2] = (double)S.nnz_g * (sg + 4) + rp + (has_eps ? 6.0 : 5.0) * n * sv;
+    auto ib = [](const pcgk::DevCSR &M) { return M.fmt == pcgk::FMT_BSR3 ? 4.0 / 9.0 : M.idx16 ? 2.0 : 4.0; };
+    bytes[0] = (double)S.nnz_a * (sa + ib(S.dev.A)) + rp + 2.0 * n * sv;
+    bytes[1] = (double)S.nnz_g * (sg + ib(S.dev.GT)) + rp + 4.0 * n * sv;
+    bytes[2] = (double)S.nnz_g * (sg + ib(S.dev.G)) + rp + (has_eps ? 6.0 : 5.0) * n * sv;
     bytes[3] = bytes[0] + bytes[1] + bytes[2];
   }
   return PCG_OK;

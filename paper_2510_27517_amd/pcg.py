@@ -43,7 +43,7 @@ class Config(ctypes.Structure):
         ("eps", ctypes.c_double), ("refine", ctypes.c_int), ("inner_tol", ctypes.c_double),
         ("max_outer", ctypes.c_int), ("graph_iters", ctypes.c_int), ("grid_mult", ctypes.c_int),
         ("mem_budget_mb", ctypes.c_int), ("layout", ctypes.c_int), ("g_device", ctypes.c_int),
-        ("reserved", ctypes.c_int * 5),
+        ("wide_index", ctypes.c_int), ("reserved", ctypes.c_int * 4),
     ]
 
 

@@ -131,9 +131,42 @@ def test_mixed_zero_rhs_and_bad_config(gpu_lib):
         s.build_precond(pcg.G_FSAI)
         z = s.solve(np.zeros(A.n), np.ones(A.n))
         assert z.status == pcg.OK and np.all(z.x == 0)
-    with pytest.raises(pcg.PCGError) as e:
-        pcg.Solver(pcg.default_config(vec_dtype="f64", a_dtype="f64", g_dtype="bf16"))
-    assert e.value.status == pcg.EINVAL
+    for bad in [dict(vec_dtype="f32", a_dtype="f32", g_dtype="f64"), dict(vec_dtype="f64", a_dtype="f32"),
+                dict(refine=1), dict(vec_dtype="f32", a_dtype="f64")]:
+        with pytest.raises(pcg.PCGError) as e:
+            pcg.Solver(pcg.default_config(**bad))
+        assert e.value.status == pcg.EINVAL
+
+
+@pytest.mark.parametrize("gdt", ["f32", "bf16", "f16"])
+def test_fp64_solve_with_rounded_g(gpu_lib, gdt):
+    """FP64 vectors and A with G stored in gdt: the library runs FP64 PCG
+    with the rounded G, i.e. the oracle's FP64 PCG with G's values rounded
+    once (binary16 under its power-of-two scale, divided out exactly).
+    Products are bit-identical to the oracle's on the rounded G; the solve
+    holds FP64 trajectory parity and reaches the FP64 tolerance."""
+    pcg = gpu_lib
+    A = inputs.poisson(3, 24, 1.0, 4)
+    b = inputs.rhs(A.n, 4)
+    G = oracle.fsai_g(A)
+    sc = oracle.g_storage_scale(G, gdt)
+    Gr = CSR(G.rowptr, G.col, oracle.round_storage(G.val * sc, gdt) / sc)
+    x = np.random.default_rng(5).standard_normal(A.n)
+    say("fp64 with rounded G", gdt)
+    with pcg.Solver(pcg.default_config(g_dtype=gdt)) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        assert np.array_equal(s.matvec(pcg.OP_GT, x), oracle.spmv_t(Gr, x))
+        assert np.array_equal(s.matvec(pcg.OP_G, x), oracle.spmv(Gr, x))
+        got = s.solve(b, tol=1e-10, maxit=3000)
+    ref = oracle.pcg(A, Gr, b, tol=1e-10, maxit=3000, delta_form=1)
+    full = oracle.pcg(A, G, b, tol=1e-10, maxit=3000, delta_form=1)
+    err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
+    r64 = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+    say(f"  {gdt}: iters {got.iters} (oracle rounded G {ref.iters}, FP64 G {full.iters}), error {err:.2e}, "
+        f"fp64 relres {r64:.2e}")
+    assert got.status == ref.status == pcg.OK and abs(got.iters - ref.iters) <= 1
+    assert err <= 1e-10 and r64 <= 1.0001e-10
 
 
 @pytest.mark.parametrize("case,gdt", [("poisson3d", "bf16"), ("poisson3d", "f16"), ("poisson3d", "f32"),

@@ -59,13 +59,16 @@ def _random_g(A, seed):
     return CSR(A.rowptr.copy(), A.col.copy(), rng.uniform(-1, 1, A.nnz))
 
 
-@pytest.mark.parametrize("layout", ["auto", "csr", "sell", "bsr3"])
-@pytest.mark.parametrize("case", ["ragged", "longrows", "poisson3d", "elasticity"])
+@pytest.mark.parametrize("layout", ["auto", "csr", "sell", "sell32", "bsr3"])
+@pytest.mark.parametrize("case", ["ragged", "longrows", "poisson3d", "elasticity", "far"])
 def test_operator_products_bitwise(gpu_lib, case, layout):
     """Every storage layout gives the oracle's products bit for bit (the sliced
     layout is forced onto ragged rows, so padding is exercised; the long rows
     fall back to CSR; the 3x3-block layout applies to the elasticity A, whose
-    boundary block rows are shorter, and falls back elsewhere)."""
+    boundary block rows are shorter, and falls back elsewhere). Sliced
+    matrices keep 16-bit column differences where every one fits ("sell32"
+    forces 32-bit columns); the "far" matrix has columns more than 32767 away
+    from their rows, so it keeps 32-bit columns in every layout."""
     pcg = gpu_lib
     if case == "ragged":
         A = _random_spd_pattern(1537, 1)
@@ -73,13 +76,16 @@ def test_operator_products_bitwise(gpu_lib, case, layout):
         A = _random_spd_pattern(5000, 2, long_rows=(0, 17, 4999))
     elif case == "elasticity":
         A = inputs.elasticity(6, 1.0, 0.3, 2)
+    elif case == "far":
+        A = _random_spd_pattern(70001, 5)
     else:
         A = inputs.poisson(3, 40, 1.0, 2)
     G = _random_g(A, 3)
     x = np.random.default_rng(4).standard_normal(A.n)
     eps = 0.37
     say("operator products", case, layout, A.n, A.nnz)
-    with _solver(pcg, eps=eps, layout=layout) as s:
+    kw = dict(layout="sell", wide_index=1) if layout == "sell32" else dict(layout=layout)
+    with _solver(pcg, eps=eps, **kw) as s:
         s.set_matrix(A)
         s.set_precond(G)
         assert np.array_equal(s.matvec(pcg.OP_A, x), oracle.spmv(A, x))
@@ -352,3 +358,28 @@ def test_pcg_synthetic_ppt(gpu_lib):
     say(f"  iters {got.iters}/{ref.iters}/{alt} relres {r:.2e} xdiff "
         f"{np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x):.2e}")
     assert r <= 1.0001e-8
+
+
+def test_index_width_in_bytes_and_results(gpu_lib):
+    """3D Poisson in the sliced layout: with 16-bit column differences the
+    reported bytes per iteration count two bytes per stored index of A, G and
+    G^T, with 32-bit columns four; the two solves are bit-identical and hold
+    parity with the oracle."""
+    pcg = gpu_lib
+    A = inputs.poisson(3, 30, 1.0, 3)
+    b = inputs.rhs(A.n, 3)
+    g = oracle.tril_nnz(A)
+    ref = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-8, maxit=2000, delta_form=1)
+    xs = []
+    for wide in (0, 1):
+        with _solver(pcg, wide_index=wide) as s:
+            s.set_matrix(A)
+            s.build_precond(pcg.G_FSAI)
+            got = s.solve(b, tol=1e-8, maxit=2000)
+        ib = 4 if wide else 2
+        want = A.nnz * (8 + ib) + g * (16 + 2 * ib) + 12 * (A.n + 1) + 11 * A.n * 8
+        say(f"index width {ib}: bytes/iter {got.bytes_per_iter:.0f} (want {want}), iters {got.iters}")
+        assert got.bytes_per_iter == want
+        _check(got, ref)
+        xs.append(got.x)
+    assert np.array_equal(xs[0], xs[1])
