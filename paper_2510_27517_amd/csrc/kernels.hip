@@ -230,7 +230,10 @@ __device__ __forceinline__ int32_t slice_col(GLOBAL const int16_t *cc, int64_t k
 }
 
 // One lane's row of a slice: products of its wd entries added left to right
-// from zero (loads issued UNR at a time).
+// from zero, loads issued UNR at a time. The last wd % UNR entries form one
+// more batch whose surplus loads repeat entry wd - 1 (in bounds) and whose
+// surplus products are not added, so every load of a batch is in flight at
+// once (wd is the same for the whole wave).
 template <typename TACC, int UNR, typename TM, typename TI, typename Gather>
 __device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const TI *cc, int32_t row, int wd,
                                               Gather gather) {
@@ -244,15 +247,26 @@ __device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const 
 #pragma unroll
     for (int u = 0; u < UNR; ++u) sum += p[u];
   }
-  for (; k < wd; ++k) sum += (TACC)ldval(vv, k * kSliceRows) * gather(slice_col(cc, k * kSliceRows, row));
+  const int rem = wd - k;
+  if (rem > 0) {
+    TACC p[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = k + min(u, rem - 1);
+      p[u] = (TACC)ldval(vv, e * kSliceRows) * gather(slice_col(cc, e * kSliceRows, row));
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      if (u < rem) sum += p[u];
+  }
   return sum;
 }
 
 template <typename TACC, int UW, typename TM, typename TI, typename Gather>
 __device__ __forceinline__ TACC slice_row(GLOBAL const TM *vv, GLOBAL const TI *cc, int32_t row, int wd,
                                           Gather gather) {
-  return (UW > 4 && wd >= 32) ? slice_row_sum<TACC, UW>(vv, cc, row, wd, gather)
-                              : slice_row_sum<TACC, 4>(vv, cc, row, wd, gather);
+  return (UW > 4 && wd > 4) ? slice_row_sum<TACC, UW>(vv, cc, row, wd, gather)
+                            : slice_row_sum<TACC, 4>(vv, cc, row, wd, gather);
 }
 
 // Sliced-ELL rows: each wave takes whole slices (64 rows, one per lane); a
@@ -386,17 +400,21 @@ __device__ __forceinline__ void put_partials(double (&v)[NV], GLOBAL double *p, 
     for (int j = 0; j < NV; ++j) p[(int64_t)j * G + L] = v[j];
 }
 
-// Sum the P partials of each value in a fixed order; every thread gets the totals.
+// Sum the P partials of each value in a fixed order; every thread gets the
+// totals. load_partials adds this thread's share (no barrier, so a kernel can
+// issue it before it reads its state); reduce_partials finishes the sums.
 template <int NV>
-__device__ __forceinline__ void sum_partials(GLOBAL const double *__restrict__ p, int P, double (&out)[NV],
-                                             double *sh) {
-  double acc[NV];
+__device__ __forceinline__ void load_partials(GLOBAL const double *__restrict__ p, int P, double (&acc)[NV]) {
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
 #pragma unroll 8
   for (int k = threadIdx.x; k < P; k += kBlock)
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] += p[(int64_t)j * P + k];
+}
+
+template <int NV>
+__device__ __forceinline__ void reduce_partials(double (&acc)[NV], double (&out)[NV], double *sh) {
   block_sum<NV>(acc, sh);
   __shared__ double tot[NV];
   if (threadIdx.x == 0)
@@ -405,6 +423,14 @@ __device__ __forceinline__ void sum_partials(GLOBAL const double *__restrict__ p
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < NV; ++j) out[j] = tot[j];
+}
+
+template <int NV>
+__device__ __forceinline__ void sum_partials(GLOBAL const double *__restrict__ p, int P, double (&out)[NV],
+                                             double *sh) {
+  double acc[NV];
+  load_partials<NV>(p, P, acc);
+  reduce_partials<NV>(acc, out, sh);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -448,6 +474,8 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
   const SysDev &D = dir[m.x];
   GLOBAL State *st = gl(D.st);
   GLOBAL const State &S = st[0];
+  double g[1];
+  load_partials<1>(gl(D.pg), D.A.grid, g);  // in flight while the state is read
   if (S.done) {  // stopped earlier: st[1] mirrors st[0], so the G-kernel need not read st[0]
     if (m.y == 0 && threadIdx.x == 0) st_state(st + 1, ld_state(&S));
     return;
@@ -457,8 +485,7 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
   double alpha = S.alpha, gamma = S.gamma;
   bool brk = false;
   if (mode != 2) {
-    double g[1];
-    sum_partials<1>(gl(D.pg), D.A.grid, g, sh);
+    reduce_partials<1>(g, g, sh);
     gamma = g[0];
     brk = !(gamma > 0.0) || !isfinite(gamma);
     alpha = brk ? 0.0 : S.delta / gamma;  // on breakdown x already holds x_i
@@ -516,13 +543,14 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_G(const SysDev *_
   // st[1] is the G^T-kernel's publication for this iteration; st[0] is written
   // below by workgroup 0 and must not be read by the others
   GLOBAL const State &S = st[1];
+  double v[2];
+  load_partials<2>(gl(D.prt), D.GT.grid, v);  // in flight while the state is read
   if (S.done) {  // stopped earlier, or the G^T-kernel flagged a breakdown
     if (m.y == 0 && threadIdx.x == 0) st_state(st, ld_state(&S));
     return;
   }
   const int it = S.iter;
-  double v[2];
-  sum_partials<2>(gl(D.prt), D.GT.grid, v, sh);
+  reduce_partials<2>(v, v, sh);
   const double rr = v[0], tt = v[1];
   const double dn = tt + S.eps * rr;
   const int i1 = (mode == 2) ? it : it + 1;
