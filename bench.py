@@ -50,7 +50,7 @@ TOL = 1e-8
 MAXIT = 5000
 KERNEL_SOURCES = ["paper_2510_27517_amd/csrc/kernels.hip", "paper_2510_27517_amd/csrc/kernels.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iter_A_poisson3d_128_f64_traffic.md")
-SECTIONS = ["mixed", "sai_loss", "batched", "serving", "elasticity", "synthetic"]
+SECTIONS = ["mixed", "sai_loss", "autotune", "batched", "serving", "elasticity", "synthetic"]
 
 
 def log(*a):
@@ -139,6 +139,30 @@ def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
                             "status": r64.status, "iters": r64.iters, "relres_true_fp64": r64.relres_true,
                             "ms_per_iter": round(ms64 / max(r64.iters, 1), 5),
                             "alg_bytes_per_iter": r64.bytes_per_iter}}, r.x.cpu().numpy()
+
+
+def section_autotune(pcg, torch, A, G, b_dev, steps, t_auto_ms):
+    """The autotuner on the 128^3 FP64 system: layouts and grid it keeps, the
+    time it took, and timed solves with its choice."""
+    with pcg.Solver(pcg.default_config()) as s:
+        s.set_matrix(A)
+        s.set_precond(rowptr=G[0], col=G[1], val=G[2])
+        t0 = time.perf_counter()
+        t = s.autotune(20)
+        t_tune = time.perf_counter() - t0
+        s.solve(b_dev, tol=TOL, maxit=MAXIT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = s.solve(b_dev, tol=TOL, maxit=MAXIT)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+    names = {v: k for k, v in pcg.LAYOUTS.items()}
+    return {"workload": "poisson3d_128^3_sigma1_fsai, FP64, tol 1e-8", "tune_s": round(t_tune, 2),
+            "candidates": t["candidates"], "layout_a": names.get(t["layout_a"]), "layout_g": names.get(t["layout_g"]),
+            "grid_mult": t["grid_mult"], "ms_per_iter_tuned": round(t["ms_per_iter"], 5),
+            "ms_per_iter_auto": round(t["ms_per_iter_auto"], 5), "time_to_tol_ms": round(ms, 3),
+            "time_to_tol_ms_auto": round(t_auto_ms, 3), "iters": r.iters, "status": r.status}
 
 
 def section_sai_loss(pcg, inputs, A, G, k, reps=3):
@@ -477,6 +501,9 @@ def main():
     if "sai_loss" in sections:
         log("sai loss")
         extra["sai_loss"] = section_sai_loss(pcg, inputs, A, G, args.probes)
+    if "autotune" in sections:
+        log("autotune")
+        extra["autotune"] = section_autotune(pcg, torch, A, G, b_dev, max(3, args.steps // 2), ms_per_step)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -100,7 +100,8 @@ typedef struct {
   int wide_index;    /* 0 (default): a sliced matrix whose every stored column lies within 32767 of its
                         row keeps 16-bit column - row differences (half the index bytes); 1: always
                         32-bit column indices */
-  int reserved[4];
+  int autotune;      /* 1: pcg_set_precond and pcg_build_precond end with pcg_autotune(ctx, 20, NULL) */
+  int reserved[3];
 } pcg_config;
 
 /* Matrix storage layouts (pcg_config.layout). Both give bit-identical
@@ -277,6 +278,32 @@ int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col
  * n+1 / pcg_g_nnz. */
 int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, const int32_t *col,
                      const double *val, int32_t *g_rowptr, int32_t *g_col, double *g_val);
+
+/* Autotuner: times one CG iteration of the single system (its three kernels,
+ * `iters` iterations on b = 1 after three warm-up iterations) for each
+ * candidate storage of A (CSR row blocks, sliced ELL, 3x3 blocks: each
+ * distinct format the matrix admits) and of G and G^T (CSR, sliced ELL), at
+ * the configured grid, then for the best layouts at half and twice the
+ * grid, and keeps the fastest (a candidate must beat the current best by 3%).
+ * The matrices are laid out again with the same values, so products stay
+ * bit-identical; the grid changes the partial-sum order of the dot products.
+ * A layout forced in the configuration is kept; only the grid is tuned then.
+ * The choice is cached per matrix signature (sizes, row-length structure, 3x3
+ * blocking, storage types, options, compute units) for the process, and in
+ * the file named by the environment variable PCG_TUNE_CACHE when set; a
+ * cached signature is applied without search (candidates = 0). A new
+ * pcg_set_matrix returns to the automatic layouts. Needs A and G set;
+ * overwrites the stored right-hand side. iters <= 0: 20. */
+typedef struct {
+  int layout_a, layout_g; /* chosen PCG_LAYOUT_* (PCG_LAYOUT_AUTO: the automatic choice won) */
+  int grid_mult;          /* chosen workgroups per compute unit */
+  int candidates;         /* configurations timed (0: taken from the cache) */
+  int fmt_a, fmt_g, fmt_gt; /* resulting storage: 0 CSR row blocks, 1 sliced ELL, 2 sliced 3x3 blocks */
+  int idx16;              /* bit 0/1/2: A / G / G^T keep 16-bit column differences */
+  double ms_per_iter;      /* chosen configuration, one iteration */
+  double ms_per_iter_auto; /* the automatic choice (NaN when taken from the cache) */
+} pcg_tune_result;
+int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res);
 
 /* Upper estimate of the device memory one system (n unknowns, nnz_a entries
  * of A, nnz_g of G) takes from the serving pool of a context configured by

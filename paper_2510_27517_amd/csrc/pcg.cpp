@@ -542,6 +542,15 @@ struct pcg_ctx {
   std::vector<double> a_val;
   double a_mean_abs = 1.0;  // mean |A_ij| over the nonzeros (the SAI loss's ||A||)
   bool have_a = false, have_g = false;
+  // G as last set from the host (kept for re-layouts), or built on the device
+  std::vector<int32_t> g_rp, g_ci;
+  std::vector<double> g_val;
+  bool g_from_device = false;
+  // layouts and grid the autotuner chose for the current A and G
+  struct Tune {
+    bool on = false;
+    int la = PCG_LAYOUT_AUTO, lg = PCG_LAYOUT_AUTO, gm = 8;
+  } tune;
   Sys single;
   HostSet set_main, set_64;
   std::map<int, hipGraphExec_t> graphs;  // key: iters*2 + replace_first
@@ -651,6 +660,17 @@ State init_state(const pcg_ctx *ctx, double tol, int maxit, double g_scale, bool
 }
 
 // --------------------------------------------------------- single-system path
+
+// The configuration one matrix of the single system is laid out with: the
+// context's, with the tuned layout and grid when the autotuner has chosen.
+pcg_config eff_cfg(const pcg_ctx *ctx, bool for_g) {
+  pcg_config c = ctx->cfg;
+  if (ctx->tune.on) {
+    c.layout = for_g ? ctx->tune.lg : ctx->tune.la;
+    c.grid_mult = ctx->tune.gm;
+  }
+  return c;
+}
 
 int single_sets(pcg_ctx *ctx) {
   drop_graphs(ctx);
@@ -1570,6 +1590,24 @@ void pcg_destroy(pcg_ctx *ctx) {
   delete ctx;
 }
 
+// Lay out and upload A (host copy in the context) for the single system.
+static int place_single_a(pcg_ctx *ctx) {
+  const int32_t n = (int32_t)ctx->a_rp.size() - 1;
+  APart P;
+  prep_a(eff_cfg(ctx, false), ctx->cus, n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), true, P);
+  void *blk = nullptr;
+  if (hipMalloc(&blk, P.bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "pcg_set_matrix: device allocation failed";
+    return PCG_ENOMEM;
+  }
+  ctx->single.blkA = blk;
+  HIPCHK(place_a(P, blk, ctx->single, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->have_a = true;
+  return PCG_OK;
+}
+
 int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
                    const double *val, int on_device) {
   if (!ctx) return PCG_EINVAL;
@@ -1608,6 +1646,7 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
   free_set(ctx->set_64);
   free_sys(ctx, ctx->single);
   ctx->have_a = ctx->have_g = false;
+  ctx->tune.on = false;  // a new matrix: automatic layouts until tuned again
   ctx->a_rp.swap(hrp);
   ctx->a_ci.swap(hci);
   ctx->a_val.swap(hv);
@@ -1621,19 +1660,7 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
       }
     ctx->a_mean_abs = cnt ? sum / (double)cnt : 1.0;
   }
-  APart P;
-  prep_a(ctx->cfg, ctx->cus, n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), true, P);
-  void *blk = nullptr;
-  if (hipMalloc(&blk, P.bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    ctx->err = "pcg_set_matrix: device allocation failed";
-    return PCG_ENOMEM;
-  }
-  ctx->single.blkA = blk;
-  HIPCHK(place_a(P, blk, ctx->single, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  ctx->have_a = true;
-  return PCG_OK;
+  return place_single_a(ctx);
 }
 
 static int set_g_from_host(pcg_ctx *ctx, std::vector<int32_t> &grp, std::vector<int32_t> &gci,
@@ -1644,8 +1671,12 @@ static int set_g_from_host(pcg_ctx *ctx, std::vector<int32_t> &grp, std::vector<
     ctx->single.blkG = nullptr;
   }
   ctx->have_g = false;
+  ctx->g_rp = grp;
+  ctx->g_ci = gci;
+  ctx->g_val = gv;
+  ctx->g_from_device = false;
   GPart P;
-  prep_g(ctx->cfg, ctx->cus, ctx->single.n, grp, gci, gv, P);
+  prep_g(eff_cfg(ctx, true), ctx->cus, ctx->single.n, grp, gci, gv, P);
   void *blk = nullptr;
   if (hipMalloc(&blk, P.bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -1696,7 +1727,9 @@ int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr,
   }
   int rc = pcgh::validate_csr(n, nnz, hrp.data(), hci.data(), 0, &ctx->err);
   if (rc) return rc;
-  return set_g_from_host(ctx, hrp, hci, hv);
+  rc = set_g_from_host(ctx, hrp, hci, hv);
+  if (!rc && ctx->cfg.autotune) rc = pcg_autotune(ctx, 20, nullptr);
+  return rc;
 }
 
 // FSAI factored on the device: the host lays out the patterns of G = triu(A)
@@ -1741,8 +1774,9 @@ static int build_fsai_device(pcg_ctx *ctx) {
   P.nnz = lrp[n];
   P.gdt = ctx->cfg.g_dtype;
   P.vdt = ctx->cfg.vec_dtype;
-  make_pattern(ctx->cfg, ctx->cus, n, grp.data(), gci.data(), P.gdt, P.vdt, P.G);
-  make_pattern(ctx->cfg, ctx->cus, n, lrp.data(), lci.data(), P.gdt, P.vdt, P.GT);
+  const pcg_config gcfg = eff_cfg(ctx, true);
+  make_pattern(gcfg, ctx->cus, n, grp.data(), gci.data(), P.gdt, P.vdt, P.G);
+  make_pattern(gcfg, ctx->cus, n, lrp.data(), lci.data(), P.gdt, P.vdt, P.GT);
   P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * (size_t)P.GT.grid);
   // temporaries: A (CSR, FP64), dpos, lrp, G_L's values, flags, partial maxima
   const int64_t nnz = rp[n], nl = lrp[n];
@@ -1819,6 +1853,10 @@ static int build_fsai_device(pcg_ctx *ctx) {
     return PCG_EBREAKDOWN;
   }
   if ((rc = single_sets(ctx))) return rc;
+  std::vector<int32_t>().swap(ctx->g_rp);
+  std::vector<int32_t>().swap(ctx->g_ci);
+  std::vector<double>().swap(ctx->g_val);
+  ctx->g_from_device = true;
   ctx->have_g = true;
   return PCG_OK;
 }
@@ -1829,19 +1867,239 @@ int pcg_build_precond(pcg_ctx *ctx, int kind, uint64_t seed) {
     ctx->err = "pcg_build_precond: set the matrix first";
     return PCG_ESTATE;
   }
+  int rc = 1;
   if (kind == PCG_G_FSAI && ctx->cfg.g_device) {
     HIPCHK(hipSetDevice(ctx->cfg.device));
-    const int rd = build_fsai_device(ctx);
-    if (rd != 1) return rd;  // 1: use the host builder
+    rc = build_fsai_device(ctx);  // 1: use the host builder
   }
-  std::vector<int32_t> grp, gci;
-  std::vector<double> gv;
-  int rc = pcgh::build_g(kind, seed, ctx->single.n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), grp, gci, gv);
-  if (rc) {
-    ctx->err = "pcg_build_precond: construction failed (kind or matrix not SPD)";
+  if (rc == 1) {
+    std::vector<int32_t> grp, gci;
+    std::vector<double> gv;
+    rc = pcgh::build_g(kind, seed, ctx->single.n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), grp, gci,
+                       gv);
+    if (rc) {
+      ctx->err = "pcg_build_precond: construction failed (kind or matrix not SPD)";
+      return rc;
+    }
+    rc = set_g_from_host(ctx, grp, gci, gv);
+  }
+  if (!rc && ctx->cfg.autotune) rc = pcg_autotune(ctx, 20, nullptr);
+  return rc;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+// Choices per matrix signature, shared by the contexts of the process and,
+// when the environment names a file in PCG_TUNE_CACHE, kept there as lines
+// "signature layout_a layout_g grid_mult".
+static std::mutex g_tune_mu;
+static std::map<std::string, pcg_ctx::Tune> g_tune_cache;
+static bool g_tune_loaded = false;
+
+static void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = std::getenv("PCG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char key[512];
+  int la, lg, gm;
+  while (std::fscanf(f, "%511s %d %d %d", key, &la, &lg, &gm) == 4) {
+    pcg_ctx::Tune t;
+    t.on = true;
+    t.la = la;
+    t.lg = lg;
+    t.gm = gm;
+    g_tune_cache[key] = t;
+  }
+  std::fclose(f);
+}
+
+static void tune_cache_store(const std::string &key, const pcg_ctx::Tune &t) {
+  g_tune_cache[key] = t;
+  const char *path = std::getenv("PCG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d\n", key.c_str(), t.la, t.lg, t.gm);
+  std::fclose(f);
+}
+
+// What the layouts depend on: sizes, row-length structure, 3x3 blocking,
+// storage types, the compute-unit count and the layout options.
+static std::string tune_key(const pcg_ctx *ctx) {
+  const int32_t n = (int32_t)ctx->a_rp.size() - 1;
+  const int32_t *rp = ctx->a_rp.data();
+  int32_t maxrow = 0;
+  for (int32_t i = 0; i < n; ++i) maxrow = std::max(maxrow, rp[i + 1] - rp[i]);
+  int64_t nb = 0;
+  const bool b3 = pcgh::is_block3(n, rp, ctx->a_ci.data(), &nb);
+  const pcg_config &c = ctx->cfg;
+  char buf[384];
+  std::snprintf(buf, sizeof buf, "n%d_a%lld_g%lld_r%d_s%lld_b%d_t%d.%d.%d_f%d.%d.%d.%d_cu%d", n,
+                (long long)rp[n], (long long)ctx->single.nnz_g, maxrow, (long long)pcgh::sell_entries(n, rp),
+                (int)b3, c.vec_dtype, c.a_dtype, c.g_dtype, c.refine, c.layout, c.wide_index, c.grid_mult, ctx->cus);
+  return buf;
+}
+
+// Lay A and G out again under ctx->tune (same values): G from the kept host
+// copy, or factored on the device again.
+static int relayout(pcg_ctx *ctx) {
+  std::vector<int32_t> grp = ctx->g_rp, gci = ctx->g_ci;
+  std::vector<double> gv = ctx->g_val;
+  const bool dev_g = ctx->g_from_device;
+  drop_graphs(ctx);
+  free_set(ctx->set_main);
+  free_set(ctx->set_64);
+  free_sys(ctx, ctx->single);
+  ctx->have_a = ctx->have_g = false;
+  int rc = place_single_a(ctx);
+  if (rc) return rc;
+  if (dev_g) {
+    rc = build_fsai_device(ctx);
+    if (rc == 1) {  // cannot happen for a G the device built before; rebuild on the host
+      rc = pcgh::build_g(PCG_G_FSAI, 0, ctx->single.n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), grp,
+                         gci, gv);
+      if (!rc) rc = set_g_from_host(ctx, grp, gci, gv);
+    }
     return rc;
   }
   return set_g_from_host(ctx, grp, gci, gv);
+}
+
+// One CG iteration's time (three kernels) on the stored right-hand side b = 1:
+// the smaller of two timings of `iters` iterations after as many for warm-up.
+static int time_iteration(pcg_ctx *ctx, int iters, double *ms) {
+  HIPCHK(pcgk::launch_fill(ctx->ty.vec, ctx->single.dev.b, ctx->single.n, 1.0, ctx->stream));
+  double m[4];
+  int rc = pcg_time_kernels(ctx, iters, m, nullptr);
+  double best = INFINITY;
+  for (int k = 0; k < 2 && !rc; ++k) {
+    rc = pcg_time_kernels(ctx, iters, m, nullptr);
+    best = std::min(best, m[3]);
+  }
+  if (!rc) *ms = best;
+  return rc;
+}
+
+static int apply_tune(pcg_ctx *ctx, const pcg_ctx::Tune &t) {
+  const bool same = ctx->tune.on == t.on && (!t.on || (ctx->tune.la == t.la && ctx->tune.lg == t.lg &&
+                                                       ctx->tune.gm == t.gm));
+  ctx->tune = t;
+  return same ? PCG_OK : relayout(ctx);
+}
+
+int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
+  if (!ctx) return PCG_EINVAL;
+  if (res) std::memset(res, 0, sizeof(*res));
+  if (iters <= 0) iters = 20;
+  if (iters > 1000) return PCG_EINVAL;
+  if (!ctx->have_a || !ctx->have_g) {
+    ctx->err = "pcg_autotune: matrix and preconditioner must be set";
+    return PCG_ESTATE;
+  }
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  const std::string key = tune_key(ctx);
+  pcg_ctx::Tune best;
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      best = it->second;
+      cached = true;
+    }
+  }
+  int rc;
+  double t_best = 0.0, t_auto = 0.0;
+  int ncand = 0;
+  if (cached) {
+    if ((rc = apply_tune(ctx, best))) return rc;
+    if ((rc = time_iteration(ctx, iters, &t_best))) return rc;
+    t_auto = NAN;
+  } else {
+    // the automatic choice first (the default to beat)
+    pcg_ctx::Tune a;
+    if ((rc = apply_tune(ctx, a))) return rc;
+    if ((rc = time_iteration(ctx, iters, &t_auto))) return rc;
+    ++ncand;
+    const int32_t n = ctx->single.n;
+    const int32_t *rp = ctx->a_rp.data(), *ci = ctx->a_ci.data();
+    const int gm0 = ctx->cfg.grid_mult > 0 ? ctx->cfg.grid_mult : 8;
+    // layouts of A (distinct by the format they give) and of G
+    std::vector<int> las, lgs;
+    if (ctx->cfg.layout == PCG_LAYOUT_AUTO) {
+      std::vector<int> fa;
+      for (int l : {PCG_LAYOUT_CSR, PCG_LAYOUT_SELL, PCG_LAYOUT_BSR3}) {
+        const int f = use_bsr3(l, n, rp, ci) ? pcgk::FMT_BSR3 : use_sell(l, n, rp) ? pcgk::FMT_SELL : pcgk::FMT_CSR;
+        if (std::find(fa.begin(), fa.end(), f) == fa.end()) {
+          fa.push_back(f);
+          las.push_back(l);
+        }
+      }
+      lgs.push_back(PCG_LAYOUT_CSR);
+      if (ctx->g_from_device || ctx->g_rp.empty() || use_sell(PCG_LAYOUT_SELL, n, ctx->g_rp.data()))
+        lgs.push_back(PCG_LAYOUT_SELL);
+    } else {
+      las.push_back(ctx->cfg.layout);
+      lgs.push_back(ctx->cfg.layout);
+    }
+    best = a;
+    best.gm = gm0;
+    t_best = t_auto;
+    auto consider = [&](const pcg_ctx::Tune &t) -> int {
+      int r = apply_tune(ctx, t);
+      if (r) return r;
+      double ms = 0.0;
+      if ((r = time_iteration(ctx, iters, &ms))) return r;
+      ++ncand;
+      if (ms < 0.97 * t_best) {  // a change must gain 3% (timing noise)
+        best = t;
+        t_best = ms;
+      }
+      return PCG_OK;
+    };
+    for (int la : las)
+      for (int lg : lgs) {
+        pcg_ctx::Tune t;
+        t.on = true;
+        t.la = la;
+        t.lg = lg;
+        t.gm = gm0;
+        if ((rc = consider(t))) return rc;
+      }
+    pcg_ctx::Tune base = best;
+    if (!base.on) {  // grids around the automatic layouts: pin them as the formats they gave
+      base.on = true;
+      base.la = ctx->cfg.layout;
+      base.lg = ctx->cfg.layout;
+    }
+    for (int gm : {gm0 / 2, gm0 * 2}) {
+      if (gm < 1) continue;
+      pcg_ctx::Tune t = base;
+      t.gm = gm;
+      if ((rc = consider(t))) return rc;
+    }
+    if ((rc = apply_tune(ctx, best))) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_store(key, best);
+  }
+  if (res) {
+    res->layout_a = best.on ? best.la : ctx->cfg.layout;
+    res->layout_g = best.on ? best.lg : ctx->cfg.layout;
+    res->grid_mult = best.on ? best.gm : (ctx->cfg.grid_mult > 0 ? ctx->cfg.grid_mult : 8);
+    res->candidates = ncand;
+    res->ms_per_iter = t_best;
+    res->ms_per_iter_auto = t_auto;
+    res->fmt_a = ctx->single.dev.A.fmt;
+    res->fmt_g = ctx->single.dev.G.fmt;
+    res->fmt_gt = ctx->single.dev.GT.fmt;
+    res->idx16 = (ctx->single.dev.A.idx16 ? 1 : 0) | (ctx->single.dev.G.idx16 ? 2 : 0) |
+                 (ctx->single.dev.GT.idx16 ? 4 : 0);
+  }
+  return PCG_OK;
 }
 
 int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, int on_device, pcg_result *res) {

@@ -33,6 +33,7 @@ EXPORTS = [
     "pcg_solve", "pcg_matvec", "pcg_sai_loss", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
     "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth", "pcg_submit_batch",
     "pcg_progress", "pcg_poll", "pcg_wait", "pcg_solve_batch", "pcg_pool_info", "pcg_estimate_bytes",
+    "pcg_autotune",
 ]
 
 
@@ -43,8 +44,19 @@ class Config(ctypes.Structure):
         ("eps", ctypes.c_double), ("refine", ctypes.c_int), ("inner_tol", ctypes.c_double),
         ("max_outer", ctypes.c_int), ("graph_iters", ctypes.c_int), ("grid_mult", ctypes.c_int),
         ("mem_budget_mb", ctypes.c_int), ("layout", ctypes.c_int), ("g_device", ctypes.c_int),
-        ("wide_index", ctypes.c_int), ("reserved", ctypes.c_int * 4),
+        ("wide_index", ctypes.c_int), ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 3),
     ]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("layout_a", ctypes.c_int), ("layout_g", ctypes.c_int), ("grid_mult", ctypes.c_int),
+        ("candidates", ctypes.c_int), ("fmt_a", ctypes.c_int), ("fmt_g", ctypes.c_int), ("fmt_gt", ctypes.c_int),
+        ("idx16", ctypes.c_int), ("ms_per_iter", ctypes.c_double), ("ms_per_iter_auto", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Result(ctypes.Structure):
@@ -105,6 +117,7 @@ def load():
     lib.pcg_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
     lib.pcg_wait.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(Result), dbl]
     lib.pcg_estimate_bytes.argtypes = [ctypes.POINTER(Config), i32, i64, i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pcg_autotune.argtypes = [P, c_int, ctypes.POINTER(TuneResult)]
     lib.pcg_solve_batch.argtypes = [P, c_int, ctypes.POINTER(System), ctypes.POINTER(Result), c_int]
     lib.pcg_pool_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.pcg_last_error.argtypes = [P]
@@ -307,6 +320,13 @@ class Solver:
         self._check(self._lib.pcg_sai_loss(self._h, k, pw, dev, out["sai"].ctypes.data, out["l2"].ctypes.data,
                                            out["cs"].ctypes.data), "pcg_sai_loss")
         return out
+
+    def autotune(self, iters: int = 20):
+        """Time the candidate layouts and grids of the set A and G and keep the
+        fastest (see pcg_autotune); returns the choice as a dict."""
+        out = TuneResult()
+        self._check(self._lib.pcg_autotune(self._h, int(iters), ctypes.byref(out)), "pcg_autotune")
+        return out.as_dict()
 
     def time_kernels(self, iters: int = 50):
         """{'ms': [A, GT, G, iteration], 'bytes': [A, GT, G, iteration]} per launch."""
