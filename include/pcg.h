@@ -76,7 +76,9 @@ typedef struct pcg_ctx pcg_ctx;
 
 typedef struct {
   int device;        /* HIP device ordinal */
-  void *stream;      /* hipStream_t to run on; NULL: the library creates its own */
+  void *stream;      /* hipStream_t to run on (kept alive by the caller until pcg_destroy; no other
+                        thread may enqueue on it during a library call, which may capture HIP
+                        graphs on it); NULL: the library creates its own */
   int vec_dtype;     /* PCG_F64 or PCG_F32: Krylov vectors and SpMV accumulation */
   int a_dtype;       /* PCG_F64 or PCG_F32: stored values of A (must equal vec_dtype) */
   int g_dtype;       /* PCG_F64, PCG_F32, PCG_BF16 or PCG_F16: stored values of G and G^T.
@@ -102,6 +104,16 @@ typedef struct {
                         32-bit column indices */
   int autotune;      /* 1: pcg_set_precond and pcg_build_precond end with pcg_autotune(ctx, 20, NULL) */
   int reserved[3];
+  /* Optional device allocator (for example a framework's caching allocator),
+   * used for every device allocation of the context (matrices, vectors,
+   * directory, serving pool, scratch): alloc returns at least `bytes` bytes of
+   * device memory on cfg.device, 16-byte aligned (256 preferred), or NULL
+   * (reported as PCG_ENOMEM); free releases a pointer alloc returned, after
+   * the context's stream has been drained. Both or neither must be set (else
+   * pcg_create returns PCG_EINVAL). NULL: hipMalloc / hipFree. */
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *alloc_user; /* passed to alloc and free */
 } pcg_config;
 
 /* Matrix storage layouts (pcg_config.layout). Both give bit-identical

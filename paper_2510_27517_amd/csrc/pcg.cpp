@@ -45,17 +45,44 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// ------------------------------------------------------ device allocations
+
+// Device memory of a context: hipMalloc/hipFree, or the caller's allocator
+// (pcg_config.alloc / free). Before memory goes back to the caller's
+// allocator the context's stream is drained, so no queued kernel still uses it.
+struct DevAlloc {
+  void *(*alloc)(size_t, void *) = nullptr;
+  void (*release)(void *, void *) = nullptr;
+  void *user = nullptr;
+  hipStream_t stream = nullptr;
+  hipError_t get(void **p, size_t bytes) const {
+    if (!alloc) return hipMalloc(p, bytes);
+    *p = alloc(bytes, user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  void put(void *p) const {
+    if (!p) return;
+    if (!release) {
+      (void)hipFree(p);
+      return;
+    }
+    if (stream) (void)hipStreamSynchronize(stream);
+    release(p, user);
+  }
+};
+
 // ---------------------------------------------------------------- device pool
 
 // First-fit sub-allocator over one device allocation (the admission budget
 // of the batch/serving scheduler). Free blocks coalesce with neighbours.
 class DevPool {
  public:
+  DevAlloc da;
   ~DevPool() { reset(); }
   int init(size_t cap) {
     reset();
     cap = align_up(cap);
-    if (hipMalloc(&base_, cap) != hipSuccess) {
+    if (da.get(&base_, cap) != hipSuccess) {
       (void)hipGetLastError();
       base_ = nullptr;
       return PCG_ENOMEM;
@@ -65,7 +92,7 @@ class DevPool {
     return PCG_OK;
   }
   void reset() {
-    if (base_) (void)hipFree(base_);
+    if (base_) da.put(base_);
     base_ = nullptr;
     cap_ = used_bytes_ = 0;
     free_.clear();
@@ -523,6 +550,8 @@ struct Req {
 struct pcg_ctx {
   pcg_config cfg{};
   hipStream_t stream = nullptr;
+  bool own_stream = true;  // created here (destroyed with the context)
+  DevAlloc da;
   int cus = 256;
   std::string err;
   Types ty{};
@@ -591,14 +620,14 @@ void drop_graphs(pcg_ctx *ctx) {
   ctx->graphs.clear();
 }
 
-void free_set(HostSet &hs) {
-  if (hs.dev) (void)hipFree(hs.dev);
+void free_set(pcg_ctx *ctx, HostSet &hs) {
+  if (hs.dev) ctx->da.put(hs.dev);
   hs = HostSet{};
 }
 
 // Maps for the systems in `slots` (directory indices).
 int build_set(pcg_ctx *ctx, HostSet &hs, const std::vector<int> &slots) {
-  free_set(hs);
+  free_set(ctx, hs);
   hs.slots = slots;
   std::vector<int2> mA, mGT, mG, mB;
   for (int sl : slots) {
@@ -609,7 +638,7 @@ int build_set(pcg_ctx *ctx, HostSet &hs, const std::vector<int> &slots) {
     for (int l = 0; l < D.gB; ++l) mB.push_back(make_int2(sl, l));
   }
   const size_t bytes = 8 * (mA.size() + mGT.size() + mG.size() + mB.size()) + 4 * slots.size() + 64;
-  HIPCHK(hipMalloc(&hs.dev, bytes));
+  HIPCHK(ctx->da.get(&hs.dev, bytes));
   int2 *p = (int2 *)hs.dev;
   LaunchSet &L = hs.L;
   L.dir = ctx->d_dir;
@@ -640,8 +669,8 @@ void free_sys(pcg_ctx *ctx, Sys &S) {
     ctx->pool.release(S.blkA);
     ctx->pool.release(S.blkG);
   } else {
-    if (S.blkA) (void)hipFree(S.blkA);
-    if (S.blkG) (void)hipFree(S.blkG);
+    ctx->da.put(S.blkA);
+    ctx->da.put(S.blkG);
   }
   S = Sys{};
 }
@@ -1147,7 +1176,7 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
     rc = enqueue_start(ctx, ctx->ty, hs.L, ctx->cfg.eps != 0.0);
   }
   HIPCHK(hipStreamSynchronize(s));  // copies done: host staging may go
-  free_set(hs);
+  free_set(ctx, hs);
   if (rc) return rc;
   const double t = now_ms();
   for (auto &R : cand) {
@@ -1263,8 +1292,8 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
   }
   rc = enqueue_start(ctx, ctx->ty, hin.L, ctx->cfg.eps != 0.0);
   HIPCHK(hipStreamSynchronize(s));
-  free_set(h64);
-  free_set(hin);
+  free_set(ctx, h64);
+  free_set(ctx, hin);
   if (rc) return rc;
   for (auto &R : go) cont.push_back(R);
   return PCG_OK;
@@ -1371,7 +1400,7 @@ int progress(pcg_ctx *ctx, int iters) {
   HIPCHK(pcgk::launch_resid(ctx->ty, hs.L, 0, false, true, false, s));
   HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, sb, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  free_set(hs);
+  free_set(ctx, hs);
   std::vector<int> restart_slots;
   std::vector<std::shared_ptr<Req>> keep, outer_list;
   for (auto &R : ctx->active) {
@@ -1420,7 +1449,7 @@ int progress(pcg_ctx *ctx, int iters) {
     HIPCHK(pcgk::launch_iter_GT(ctx->ty, hs.L, 2, s));
     HIPCHK(pcgk::launch_iter_G(ctx->ty, hs.L, has_eps, 2, s));
     HIPCHK(hipStreamSynchronize(s));
-    free_set(hs);
+    free_set(ctx, hs);
   }
   if (!outer_list.empty()) {  // x64 += ||r|| c, then the FP64 residual
     const Types t64{pcgk::F64, pcgk::F64, pcgk::F64};
@@ -1436,7 +1465,7 @@ int progress(pcg_ctx *ctx, int iters) {
     HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, 2 * sizeof(State) * (size_t)(mx + 1), hipMemcpyDeviceToHost,
                           s));
     HIPCHK(hipStreamSynchronize(s));
-    free_set(hs);
+    free_set(ctx, hs);
     for (auto &R : outer_list) R->outer++;
     std::vector<std::shared_ptr<Req>> cont;
     if ((rc = outer_decide(ctx, outer_list, cont))) return rc;
@@ -1521,7 +1550,8 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
   const bool g_ok = g == PCG_F64 || g == PCG_F32 || g == PCG_BF16 || g == PCG_F16;
   const bool ok = (v == PCG_F64 && a == PCG_F64 && g_ok && !cfg->refine) ||
                   (v == PCG_F32 && a == PCG_F32 && g_ok && g != PCG_F64);
-  if (!ok || cfg->rr_period < 0 || cfg->graph_iters < 0 || !(cfg->eps >= 0.0) || cfg->mem_budget_mb < 0)
+  if (!ok || cfg->rr_period < 0 || cfg->graph_iters < 0 || !(cfg->eps >= 0.0) || cfg->mem_budget_mb < 0 ||
+      (cfg->alloc == nullptr) != (cfg->free == nullptr))
     return PCG_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= cfg->device || cfg->device < 0) {
@@ -1539,15 +1569,25 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->cus = prop.multiProcessorCount;
-  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) return fail(PCG_EDEVICE);
+  if (cfg->stream) {
+    ctx->stream = (hipStream_t)cfg->stream;
+    ctx->own_stream = false;
+  } else if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+    return fail(PCG_EDEVICE);
+  }
+  ctx->da.alloc = cfg->alloc;
+  ctx->da.release = cfg->free;
+  ctx->da.user = cfg->alloc_user;
+  ctx->da.stream = ctx->stream;
+  ctx->pool.da = ctx->da;
   if (hipHostMalloc((void **)&ctx->h_states, sizeof(State) * 2 * kDirCap, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&ctx->h_init, sizeof(State) * 2, hipHostMallocDefault) != hipSuccess)
     return fail(PCG_EDEVICE);
   for (auto &e : ctx->ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(PCG_EDEVICE);
   if (hipEventCreate(&ctx->t0) != hipSuccess || hipEventCreate(&ctx->t1) != hipSuccess) return fail(PCG_EDEVICE);
-  if (hipMalloc((void **)&ctx->d_dir, sizeof(SysDev) * kDirCap) != hipSuccess ||
-      hipMalloc((void **)&ctx->d_states, sizeof(State) * 2 * kDirCap) != hipSuccess)
+  if (ctx->da.get((void **)&ctx->d_dir, sizeof(SysDev) * kDirCap) != hipSuccess ||
+      ctx->da.get((void **)&ctx->d_states, sizeof(State) * 2 * kDirCap) != hipSuccess)
     return fail(PCG_ENOMEM);
   if (hipMemset(ctx->d_dir, 0, sizeof(SysDev) * kDirCap) != hipSuccess ||
       hipMemset(ctx->d_states, 0, sizeof(State) * 2 * kDirCap) != hipSuccess)
@@ -1572,9 +1612,9 @@ void pcg_destroy(pcg_ctx *ctx) {
   drop_step_graph(ctx);
   for (auto &R : ctx->active) free_sys(ctx, R->sys);
   ctx->active.clear();
-  free_set(ctx->set_main);
-  free_set(ctx->set_64);
-  free_set(ctx->set_active);
+  free_set(ctx, ctx->set_main);
+  free_set(ctx, ctx->set_64);
+  free_set(ctx, ctx->set_active);
   free_sys(ctx, ctx->single);
   ctx->pool.reset();
   for (auto &e : ctx->ev)
@@ -1583,10 +1623,10 @@ void pcg_destroy(pcg_ctx *ctx) {
   if (ctx->t1) (void)hipEventDestroy(ctx->t1);
   if (ctx->h_states) (void)hipHostFree(ctx->h_states);
   if (ctx->h_init) (void)hipHostFree(ctx->h_init);
-  if (ctx->d_dir) (void)hipFree(ctx->d_dir);
-  if (ctx->loss_buf) (void)hipFree(ctx->loss_buf);
-  if (ctx->d_states) (void)hipFree(ctx->d_states);
-  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  ctx->da.put(ctx->d_dir);
+  ctx->da.put(ctx->loss_buf);
+  ctx->da.put(ctx->d_states);
+  if (ctx->stream && ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -1596,7 +1636,7 @@ static int place_single_a(pcg_ctx *ctx) {
   APart P;
   prep_a(eff_cfg(ctx, false), ctx->cus, n, ctx->a_rp.data(), ctx->a_ci.data(), ctx->a_val.data(), true, P);
   void *blk = nullptr;
-  if (hipMalloc(&blk, P.bytes) != hipSuccess) {
+  if (ctx->da.get(&blk, P.bytes) != hipSuccess) {
     (void)hipGetLastError();
     ctx->err = "pcg_set_matrix: device allocation failed";
     return PCG_ENOMEM;
@@ -1642,8 +1682,8 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
   int rc = pcgh::validate_csr(n, nnz, hrp.data(), hci.data(), 1, &ctx->err);
   if (rc) return rc;
   drop_graphs(ctx);
-  free_set(ctx->set_main);
-  free_set(ctx->set_64);
+  free_set(ctx, ctx->set_main);
+  free_set(ctx, ctx->set_64);
   free_sys(ctx, ctx->single);
   ctx->have_a = ctx->have_g = false;
   ctx->tune.on = false;  // a new matrix: automatic layouts until tuned again
@@ -1667,7 +1707,7 @@ static int set_g_from_host(pcg_ctx *ctx, std::vector<int32_t> &grp, std::vector<
                            std::vector<double> &gv) {
   drop_graphs(ctx);
   if (ctx->single.blkG) {
-    (void)hipFree(ctx->single.blkG);
+    ctx->da.put(ctx->single.blkG);
     ctx->single.blkG = nullptr;
   }
   ctx->have_g = false;
@@ -1678,7 +1718,7 @@ static int set_g_from_host(pcg_ctx *ctx, std::vector<int32_t> &grp, std::vector<
   GPart P;
   prep_g(eff_cfg(ctx, true), ctx->cus, ctx->single.n, grp, gci, gv, P);
   void *blk = nullptr;
-  if (hipMalloc(&blk, P.bytes) != hipSuccess) {
+  if (ctx->da.get(&blk, P.bytes) != hipSuccess) {
     (void)hipGetLastError();
     ctx->err = "pcg_set_precond: device allocation failed";
     return PCG_ENOMEM;
@@ -1765,7 +1805,7 @@ static int build_fsai_device(pcg_ctx *ctx) {
   }
   drop_graphs(ctx);
   if (S.blkG) {
-    (void)hipFree(S.blkG);
+    ctx->da.put(S.blkG);
     S.blkG = nullptr;
   }
   ctx->have_g = false;
@@ -1785,9 +1825,9 @@ static int build_fsai_device(pcg_ctx *ctx) {
                     align_up(4 * (size_t)(n + 1)) + align_up(8 * (size_t)std::max<int64_t>(nl, 1)) + align_up(8) +
                     align_up(8 * (size_t)pcgk::kAbsmaxGrid);
   void *blk = nullptr, *tmp = nullptr;
-  if (hipMalloc(&blk, P.bytes) != hipSuccess || hipMalloc(&tmp, tb) != hipSuccess) {
+  if (ctx->da.get(&blk, P.bytes) != hipSuccess || ctx->da.get(&tmp, tb) != hipSuccess) {
     (void)hipGetLastError();
-    if (blk) (void)hipFree(blk);
+    ctx->da.put(blk);
     ctx->err = "pcg_build_precond: device allocation failed";
     return PCG_ENOMEM;
   }
@@ -1842,7 +1882,7 @@ static int build_fsai_device(pcg_ctx *ctx) {
     return e;
   };
   const hipError_t e = run();
-  (void)hipFree(tmp);
+  ctx->da.put(tmp);
   if (e != hipSuccess) {
     ctx->err = std::string("pcg_build_precond: ") + hipGetErrorString(e);
     return PCG_EDEVICE;
@@ -1950,8 +1990,8 @@ static int relayout(pcg_ctx *ctx) {
   std::vector<double> gv = ctx->g_val;
   const bool dev_g = ctx->g_from_device;
   drop_graphs(ctx);
-  free_set(ctx->set_main);
-  free_set(ctx->set_64);
+  free_set(ctx, ctx->set_main);
+  free_set(ctx, ctx->set_64);
   free_sys(ctx, ctx->single);
   ctx->have_a = ctx->have_g = false;
   int rc = place_single_a(ctx);
@@ -2214,10 +2254,10 @@ int pcg_sai_loss(pcg_ctx *ctx, int32_t k, const double *W, int on_device, double
   const size_t pb = sizeof(double) * (size_t)pcgk::kLossGrid * 5 * (size_t)k;
   const size_t need = 3 * align_up(8 * nk) + align_up(pb);
   if (need > ctx->loss_bytes) {
-    if (ctx->loss_buf) (void)hipFree(ctx->loss_buf);
+    ctx->da.put(ctx->loss_buf);
     ctx->loss_buf = nullptr;
     ctx->loss_bytes = 0;
-    if (hipMalloc(&ctx->loss_buf, need) != hipSuccess) {
+    if (ctx->da.get(&ctx->loss_buf, need) != hipSuccess) {
       (void)hipGetLastError();
       ctx->loss_buf = nullptr;
       ctx->err = "pcg_sai_loss: device allocation failed";

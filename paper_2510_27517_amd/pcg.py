@@ -45,7 +45,43 @@ class Config(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("graph_iters", ctypes.c_int), ("grid_mult", ctypes.c_int),
         ("mem_budget_mb", ctypes.c_int), ("layout", ctypes.c_int), ("g_device", ctypes.c_int),
         ("wide_index", ctypes.c_int), ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 3),
+        ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("alloc_user", ctypes.c_void_p),
     ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Device allocator callbacks backed by PyTorch's caching allocator, for
+    pcg_config.alloc / free (keeps the callback objects alive)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        self.device = device
+        self.live = {}
+
+        def _alloc(nbytes, _user):
+            try:
+                p = int(torch.cuda.caching_allocator_alloc(int(nbytes), device))
+            except Exception:
+                return None
+            self.live[p] = int(nbytes)
+            return p
+
+        def _free(ptr, _user):
+            self.live.pop(int(ptr), None)
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc_fn = ALLOC_FN(_alloc)
+        self.free_fn = FREE_FN(_free)
+
+    def install(self, cfg):
+        cfg.alloc = ctypes.cast(self.alloc_fn, ctypes.c_void_p)
+        cfg.free = ctypes.cast(self.free_fn, ctypes.c_void_p)
+        return cfg
 
 
 class TuneResult(ctypes.Structure):
@@ -229,9 +265,16 @@ class SolveOut:
 class Solver:
     """One library context (one device, one stream)."""
 
-    def __init__(self, config: Config | None = None, **kw):
+    def __init__(self, config: Config | None = None, *, allocator=None, **kw):
+        """allocator: None (hipMalloc), "torch" (PyTorch's caching allocator) or
+        an object with install(cfg) such as TorchAllocator."""
         self._lib = load()
         self.cfg = config if config is not None else default_config(**kw)
+        if allocator == "torch":
+            allocator = TorchAllocator(self.cfg.device)
+        self.allocator = allocator
+        if allocator is not None:
+            allocator.install(self.cfg)
         h = ctypes.c_void_p()
         st = self._lib.pcg_create(ctypes.byref(self.cfg), ctypes.byref(h))
         if st != OK:

@@ -128,6 +128,16 @@ def test_estimate_bytes_bounds():
         pcg.estimate_bytes(pcg.default_config(), 0, a, g)
 
 
+def test_allocator_callbacks_come_in_pairs():
+    """alloc without free (or the reverse) is refused before any device work."""
+    cfg = pcg.default_config()
+    keep = pcg.ALLOC_FN(lambda n, u: None)
+    cfg.alloc = pcg.ctypes.cast(keep, pcg.ctypes.c_void_p)
+    with pytest.raises(pcg.PCGError) as e:
+        pcg.Solver(cfg)
+    assert e.value.status == pcg.EINVAL
+
+
 def test_create_without_gpu_fails_cleanly():
     import torch
 
