@@ -103,7 +103,12 @@ typedef struct {
                         row keeps 16-bit column - row differences (half the index bytes); 1: always
                         32-bit column indices */
   int autotune;      /* 1: pcg_set_precond and pcg_build_precond end with pcg_autotune(ctx, 20, NULL) */
-  int reserved[3];
+  int cache_mb;      /* memory-side cache the single system's residency plan assumes, MiB (0: 256). The
+                        matrices and iteration vectors all fit in 90% of it: all three matrices are read
+                        with ordinary loads and stay cached across iterations; else A alone if it fits
+                        in 75%; else none (nontemporal loads). Negative: always nontemporal. Batched
+                        and served systems always stream. */
+  int reserved[2];
   /* Optional device allocator (for example a framework's caching allocator),
    * used for every device allocation of the context (matrices, vectors,
    * directory, serving pool, scratch): alloc returns at least `bytes` bytes of
@@ -296,7 +301,10 @@ int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, 
  * candidate storage of A (CSR row blocks, sliced ELL, 3x3 blocks: each
  * distinct format the matrix admits) and of G and G^T (CSR, sliced ELL), at
  * the configured grid, then for the best layouts at half and twice the
- * grid, and keeps the fastest (a candidate must beat the current best by 3%).
+ * grid, then the load policy (no matrix, A alone, or all three read with
+ * ordinary loads and kept in the memory-side cache, besides the residency
+ * plan's choice), and keeps the fastest (a candidate must beat the current
+ * best by 3%).
  * The matrices are laid out again with the same values, so products stay
  * bit-identical; the grid changes the partial-sum order of the dot products.
  * A layout forced in the configuration is kept; only the grid is tuned then.
@@ -312,6 +320,7 @@ typedef struct {
   int candidates;         /* configurations timed (0: taken from the cache) */
   int fmt_a, fmt_g, fmt_gt; /* resulting storage: 0 CSR row blocks, 1 sliced ELL, 2 sliced 3x3 blocks */
   int idx16;              /* bit 0/1/2: A / G / G^T keep 16-bit column differences */
+  int temporal;           /* bit 0/1/2: A / G / G^T read with ordinary loads (cache-resident) */
   double ms_per_iter;      /* chosen configuration, one iteration */
   double ms_per_iter_auto; /* the automatic choice (NaN when taken from the cache) */
 } pcg_tune_result;

@@ -99,8 +99,8 @@ struct DevCSR {
   int32_t n = 0;
   int32_t dtype = F64;
   int32_t fmt = FMT_CSR;
-  int32_t idx16 = 0;  // FMT_SELL only: ci holds int16 column - row differences
-  int32_t pad_ = 0;
+  int32_t idx16 = 0;     // FMT_SELL only: ci holds int16 column - row differences
+  int32_t temporal = 0;  // 1: ordinary loads (kept in the memory-side cache); 0: nontemporal
 };
 
 // Rows per slice of FMT_SELL; block rows per slice of FMT_BSR3.

@@ -52,12 +52,6 @@ namespace pcgk {
 #endif
 #define PCG_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PCG_WAVES_PER_EU)))
 
-// Matrix values and column indices are read exactly once per product:
-// nontemporal loads keep them from displacing the gathered vector entries in
-// L2 (PCG_NT_MATRIX = 0 uses ordinary loads).
-#ifndef PCG_NT_MATRIX
-#define PCG_NT_MATRIX 1
-#endif
 #ifndef PCG_UNROLL
 #define PCG_UNROLL 4
 #endif
@@ -75,21 +69,35 @@ __device__ __forceinline__ GLOBAL T *gl(T *p) {
   return (GLOBAL T *)p;
 }
 
-template <typename T>
+// Matrix values and column indices are read once per product. NT = true:
+// nontemporal loads, which stream past the caches (they neither displace the
+// gathered vector entries in L2 nor stay in the memory-side cache); NT =
+// false: ordinary loads, for a matrix meant to stay resident in the 256 MB
+// memory-side cache from one iteration to the next (DevCSR::temporal).
+template <bool NT = true, typename T>
 __device__ __forceinline__ T ldstream(GLOBAL const T *p, int64_t k) {
-#if PCG_NT_MATRIX
-  return __builtin_nontemporal_load(p + k);
-#else
-  return p[k];
-#endif
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p + k);
+  else
+    return p[k];
 }
 
-__device__ __forceinline__ double ldval(GLOBAL const double *p, int64_t k) { return ldstream(p, k); }
-__device__ __forceinline__ float ldval(GLOBAL const float *p, int64_t k) { return ldstream(p, k); }
-__device__ __forceinline__ float ldval(GLOBAL const bf16_t *p, int64_t k) {
-  return __uint_as_float((uint32_t)ldstream((GLOBAL const uint16_t *)p, k) << 16);
+template <bool NT = true>
+__device__ __forceinline__ double ldval(GLOBAL const double *p, int64_t k) {
+  return ldstream<NT>(p, k);
 }
-__device__ __forceinline__ float ldval(GLOBAL const _Float16 *p, int64_t k) { return (float)ldstream(p, k); }
+template <bool NT = true>
+__device__ __forceinline__ float ldval(GLOBAL const float *p, int64_t k) {
+  return ldstream<NT>(p, k);
+}
+template <bool NT = true>
+__device__ __forceinline__ float ldval(GLOBAL const bf16_t *p, int64_t k) {
+  return __uint_as_float((uint32_t)ldstream<NT>((GLOBAL const uint16_t *)p, k) << 16);
+}
+template <bool NT = true>
+__device__ __forceinline__ float ldval(GLOBAL const _Float16 *p, int64_t k) {
+  return (float)ldstream<NT>(p, k);
+}
 
 // Whole-record copies of a State (one thread publishes a slot), in 16-byte
 // words of a builtin vector type (usable in any address space).
@@ -125,11 +133,12 @@ struct Mat {
   int32_t n;
   int32_t fmt;
   int32_t idx16;
+  int32_t temporal;
 };
 
 template <typename TM>
 __device__ __forceinline__ Mat<TM> mat(const DevCSR &m) {
-  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk, m.n, m.fmt, m.idx16};
+  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk, m.n, m.fmt, m.idx16, m.temporal};
 }
 
 // Column of stored entry q of `row` (sliced layouts with 16-bit indices keep
@@ -165,7 +174,7 @@ __device__ __forceinline__ TACC lds_row_sum(const TACC *lds, int a, int e, TACC 
 // One row block: stage products in LDS, sum each row in CSR order. `pre(row)`
 // loads the row's own operands early (overlapping the gathers), `epi(row,
 // sum, pre_values)` consumes the row's sum.
-template <typename TACC, typename TM, typename Pre, typename Gather, typename Epi>
+template <typename TACC, bool NT, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds, Pre pre, Gather gather, Epi epi) {
   constexpr int cap = kLdsBytes / (int)sizeof(TACC);
   const int tid = threadIdx.x;
@@ -181,7 +190,8 @@ __device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds,
       pv = pre(row);
     }
 #pragma unroll PCG_UNROLL
-    for (int k = k0 + tid; k < k1; k += kBlock) lds[k - k0] = (TACC)ldval(M.val, k) * gather(ldstream(M.ci, k));
+    for (int k = k0 + tid; k < k1; k += kBlock)
+      lds[k - k0] = (TACC)ldval<NT>(M.val, k) * gather(ldstream<NT>(M.ci, k));
     __syncthreads();
     if (has) epi(row, lds_row_sum(lds, a, e), pv);
     __syncthreads();
@@ -192,7 +202,8 @@ __device__ __forceinline__ void stream_block(const Mat<TM> &M, int b, TACC *lds,
     TACC sum = 0;
     for (int c0 = k0; c0 < k1; c0 += cap) {
       const int c1 = min(c0 + cap, k1);
-      for (int k = c0 + tid; k < c1; k += kBlock) lds[k - c0] = (TACC)ldval(M.val, k) * gather(ldstream(M.ci, k));
+      for (int k = c0 + tid; k < c1; k += kBlock)
+        lds[k - c0] = (TACC)ldval<NT>(M.val, k) * gather(ldstream<NT>(M.ci, k));
       __syncthreads();
       if (tid == 0) sum = lds_row_sum(lds, 0, c1 - c0, sum);
       __syncthreads();
@@ -224,9 +235,13 @@ __device__ __forceinline__ int part_slot(int l, int G) { return (l & 7) * (G >> 
 
 // Column of a slice entry: an absolute int32 index, or an int16 difference
 // from the lane's row.
-__device__ __forceinline__ int32_t slice_col(GLOBAL const int32_t *cc, int64_t k, int32_t) { return ldstream(cc, k); }
+template <bool NT>
+__device__ __forceinline__ int32_t slice_col(GLOBAL const int32_t *cc, int64_t k, int32_t) {
+  return ldstream<NT>(cc, k);
+}
+template <bool NT>
 __device__ __forceinline__ int32_t slice_col(GLOBAL const int16_t *cc, int64_t k, int32_t row) {
-  return row + (int32_t)ldstream(cc, k);
+  return row + (int32_t)ldstream<NT>(cc, k);
 }
 
 // One lane's row of a slice: products of its wd entries added left to right
@@ -234,7 +249,7 @@ __device__ __forceinline__ int32_t slice_col(GLOBAL const int16_t *cc, int64_t k
 // more batch whose surplus loads repeat entry wd - 1 (in bounds) and whose
 // surplus products are not added, so every load of a batch is in flight at
 // once (wd is the same for the whole wave).
-template <typename TACC, int UNR, typename TM, typename TI, typename Gather>
+template <typename TACC, int UNR, bool NT, typename TM, typename TI, typename Gather>
 __device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const TI *cc, int32_t row, int wd,
                                               Gather gather) {
   TACC sum = 0;
@@ -243,7 +258,7 @@ __device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const 
     TACC p[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
-      p[u] = (TACC)ldval(vv, (k + u) * kSliceRows) * gather(slice_col(cc, (k + u) * kSliceRows, row));
+      p[u] = (TACC)ldval<NT>(vv, (k + u) * kSliceRows) * gather(slice_col<NT>(cc, (k + u) * kSliceRows, row));
 #pragma unroll
     for (int u = 0; u < UNR; ++u) sum += p[u];
   }
@@ -253,7 +268,7 @@ __device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const 
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int e = k + min(u, rem - 1);
-      p[u] = (TACC)ldval(vv, e * kSliceRows) * gather(slice_col(cc, e * kSliceRows, row));
+      p[u] = (TACC)ldval<NT>(vv, e * kSliceRows) * gather(slice_col<NT>(cc, e * kSliceRows, row));
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
@@ -262,11 +277,11 @@ __device__ __forceinline__ TACC slice_row_sum(GLOBAL const TM *vv, GLOBAL const 
   return sum;
 }
 
-template <typename TACC, int UW, typename TM, typename TI, typename Gather>
+template <typename TACC, int UW, bool NT, typename TM, typename TI, typename Gather>
 __device__ __forceinline__ TACC slice_row(GLOBAL const TM *vv, GLOBAL const TI *cc, int32_t row, int wd,
                                           Gather gather) {
-  return (UW > 4 && wd > 4) ? slice_row_sum<TACC, UW>(vv, cc, row, wd, gather)
-                            : slice_row_sum<TACC, 4>(vv, cc, row, wd, gather);
+  return (UW > 4 && wd > 4) ? slice_row_sum<TACC, UW, NT>(vv, cc, row, wd, gather)
+                            : slice_row_sum<TACC, 4, NT>(vv, cc, row, wd, gather);
 }
 
 // Sliced-ELL rows: each wave takes whole slices (64 rows, one per lane); a
@@ -276,7 +291,7 @@ __device__ __forceinline__ TACC slice_row(GLOBAL const TM *vv, GLOBAL const TI *
 // UW: loads in flight per lane for rows of 32 entries or more (8 pays where a
 // row product gathers one vector and the epilogue holds few operands; under
 // the 64-register budget kernels with two gathers per entry do better with 4).
-template <typename TACC, int UW, typename TM, typename Pre, typename Gather, typename Epi>
+template <typename TACC, int UW, bool NT, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi) {
   constexpr int NW = kBlock / 64;
   const int lane = threadIdx.x & 63;
@@ -291,8 +306,8 @@ __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pr
     if (has) pv = pre(row);
     const int64_t o = (int64_t)o0 * kSliceRows + lane;
     GLOBAL const TM *vv = M.val + o;
-    const TACC sum = M.idx16 ? slice_row<TACC, UW>(vv, (GLOBAL const int16_t *)M.ci + o, row, wd, gather)
-                             : slice_row<TACC, UW>(vv, M.ci + o, row, wd, gather);
+    const TACC sum = M.idx16 ? slice_row<TACC, UW, NT>(vv, (GLOBAL const int16_t *)M.ci + o, row, wd, gather)
+                             : slice_row<TACC, UW, NT>(vv, M.ci + o, row, wd, gather);
     if (has) epi(row, sum, pv);
   }
 }
@@ -316,7 +331,7 @@ struct BsrLanes {
   }
 };
 
-template <typename TACC, typename TM, typename Pre, typename Gather, typename Epi>
+template <typename TACC, bool NT, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void bsr_rows(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi) {
   constexpr int NW = kBlock / 64;
   constexpr int SR = 3 * kBSliceRows;  // rows per slice
@@ -337,36 +352,46 @@ __device__ __forceinline__ void bsr_rows(const Mat<TM> &M, int l, int G, Pre pre
     TACC sum = 0;
     int k = 0;
     for (; k + 2 <= wd; k += 2) {
-      const int32_t c0 = 3 * ldstream(bc, (int64_t)k * kBSliceRows), c1 = 3 * ldstream(bc, (int64_t)(k + 1) * kBSliceRows);
+      const int32_t c0 = 3 * ldstream<NT>(bc, (int64_t)k * kBSliceRows);
+      const int32_t c1 = 3 * ldstream<NT>(bc, (int64_t)(k + 1) * kBSliceRows);
       TACC p[6];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) p[j] = (TACC)ldval(bv, BL::at(lane, k, j)) * gather(c0 + j);
+      for (int j = 0; j < 3; ++j) p[j] = (TACC)ldval<NT>(bv, BL::at(lane, k, j)) * gather(c0 + j);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) p[3 + j] = (TACC)ldval(bv, BL::at(lane, k + 1, j)) * gather(c1 + j);
+      for (int j = 0; j < 3; ++j) p[3 + j] = (TACC)ldval<NT>(bv, BL::at(lane, k + 1, j)) * gather(c1 + j);
 #pragma unroll
       for (int u = 0; u < 6; ++u) sum += p[u];
     }
     if (k < wd) {
-      const int32_t c0 = 3 * ldstream(bc, (int64_t)k * kBSliceRows);
+      const int32_t c0 = 3 * ldstream<NT>(bc, (int64_t)k * kBSliceRows);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) sum += (TACC)ldval(bv, BL::at(lane, k, j)) * gather(c0 + j);
+      for (int j = 0; j < 3; ++j) sum += (TACC)ldval<NT>(bv, BL::at(lane, k, j)) * gather(c0 + j);
     }
     epi(row, sum, pv);
   }
 }
 
 // All rows of this workgroup (local index l of the system's G workgroups),
-// in any layout.
-template <typename TACC, int UW = 4, typename TM, typename Pre, typename Gather, typename Epi>
-__device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather, Epi epi) {
+// in any layout, with the matrix's load policy.
+template <typename TACC, int UW, bool NT, typename TM, typename Pre, typename Gather, typename Epi>
+__device__ __forceinline__ void for_rows_as(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather,
+                                            Epi epi) {
   if (M.fmt == FMT_SELL) {
-    sell_rows<TACC, UW>(M, l, G, pre, gather, epi);
+    sell_rows<TACC, UW, NT>(M, l, G, pre, gather, epi);
   } else if (M.fmt == FMT_BSR3) {
-    bsr_rows<TACC>(M, l, G, pre, gather, epi);
+    bsr_rows<TACC, NT>(M, l, G, pre, gather, epi);
   } else {
     const Sched sc = sched(M.nblk, l, G);
-    for (int b = sc.first; b < sc.end; b += sc.stride) stream_block<TACC>(M, b, lds, pre, gather, epi);
+    for (int b = sc.first; b < sc.end; b += sc.stride) stream_block<TACC, NT>(M, b, lds, pre, gather, epi);
   }
+}
+
+template <typename TACC, int UW = 4, typename TM, typename Pre, typename Gather, typename Epi>
+__device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather, Epi epi) {
+  if (M.temporal)
+    for_rows_as<TACC, UW, false>(M, l, G, lds, pre, gather, epi);
+  else
+    for_rows_as<TACC, UW, true>(M, l, G, lds, pre, gather, epi);
 }
 
 template <int NV>

@@ -579,6 +579,7 @@ struct pcg_ctx {
   struct Tune {
     bool on = false;
     int la = PCG_LAYOUT_AUTO, lg = PCG_LAYOUT_AUTO, gm = 8;
+    int res = -1;  // matrices read with ordinary loads (bit 0 A, 1 G, 2 G^T); -1: the residency plan
   } tune;
   Sys single;
   HostSet set_main, set_64;
@@ -701,8 +702,40 @@ pcg_config eff_cfg(const pcg_ctx *ctx, bool for_g) {
   return c;
 }
 
+// Bytes of one placed matrix (values and indices at their stored widths, row
+// pointers; sliced padding not counted).
+double placed_bytes(const pcgk::DevCSR &M) {
+  const double ib = M.fmt == pcgk::FMT_BSR3 ? 4.0 / 9.0 : M.idx16 ? 2.0 : 4.0;
+  return (double)M.nnz * ((double)pcgk::dtype_size(M.dtype) + ib) + 4.0 * (M.n + 1.0);
+}
+
+// Residency plan of the single system: which matrices are read with ordinary
+// loads, so that they stay in the memory-side cache (cfg.cache_mb, default
+// 256 MB) from one iteration to the next, and which stream past it. All three
+// when the matrices and the 8 iteration vectors fit in 90% of the cache;
+// else A alone when it fits in 75% (the vectors and G, G^T stream around
+// it); else none. The FP64 view of A under refinement always streams.
+int residency_plan(const pcg_ctx *ctx) {
+  if (ctx->tune.on && ctx->tune.res >= 0) return ctx->tune.res;
+  if (ctx->cfg.cache_mb < 0) return 0;
+  const double cap = (ctx->cfg.cache_mb > 0 ? ctx->cfg.cache_mb : 256) * 1048576.0;
+  const pcgk::SysDev &D = ctx->single.dev;
+  const double a = placed_bytes(D.A), g = placed_bytes(D.G) + placed_bytes(D.GT);
+  const double v = 8.0 * D.n * (double)pcgk::dtype_size(ctx->ty.vec);
+  if (a + g + v <= 0.9 * cap) return 7;
+  if (a <= 0.75 * cap) return 1;
+  return 0;
+}
+
 int single_sets(pcg_ctx *ctx) {
   drop_graphs(ctx);
+  {
+    const int r = residency_plan(ctx);
+    ctx->single.dev.A.temporal = r & 1;
+    ctx->single.dev.G.temporal = (r >> 1) & 1;
+    ctx->single.dev.GT.temporal = (r >> 2) & 1;
+    ctx->single.dev64.A.temporal = 0;
+  }
   ctx->single.dev.st = ctx->d_states + 2 * kSlotMain;
   ctx->dir[kSlotMain] = ctx->single.dev;
   int rc = upload_dir_entry(ctx, kSlotMain);
@@ -1931,7 +1964,7 @@ int pcg_build_precond(pcg_ctx *ctx, int kind, uint64_t seed) {
 
 // Choices per matrix signature, shared by the contexts of the process and,
 // when the environment names a file in PCG_TUNE_CACHE, kept there as lines
-// "signature layout_a layout_g grid_mult".
+// "signature layout_a layout_g grid_mult load_policy".
 static std::mutex g_tune_mu;
 static std::map<std::string, pcg_ctx::Tune> g_tune_cache;
 static bool g_tune_loaded = false;
@@ -1944,13 +1977,14 @@ static void tune_cache_load() {
   FILE *f = std::fopen(path, "r");
   if (!f) return;
   char key[512];
-  int la, lg, gm;
-  while (std::fscanf(f, "%511s %d %d %d", key, &la, &lg, &gm) == 4) {
+  int la, lg, gm, res;
+  while (std::fscanf(f, "%511s %d %d %d %d", key, &la, &lg, &gm, &res) == 5) {
     pcg_ctx::Tune t;
     t.on = true;
     t.la = la;
     t.lg = lg;
     t.gm = gm;
+    t.res = res;
     g_tune_cache[key] = t;
   }
   std::fclose(f);
@@ -1962,7 +1996,7 @@ static void tune_cache_store(const std::string &key, const pcg_ctx::Tune &t) {
   if (!path || !*path) return;
   FILE *f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d\n", key.c_str(), t.la, t.lg, t.gm);
+  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), t.la, t.lg, t.gm, t.res);
   std::fclose(f);
 }
 
@@ -1977,9 +2011,10 @@ static std::string tune_key(const pcg_ctx *ctx) {
   const bool b3 = pcgh::is_block3(n, rp, ctx->a_ci.data(), &nb);
   const pcg_config &c = ctx->cfg;
   char buf[384];
-  std::snprintf(buf, sizeof buf, "n%d_a%lld_g%lld_r%d_s%lld_b%d_t%d.%d.%d_f%d.%d.%d.%d_cu%d", n,
+  std::snprintf(buf, sizeof buf, "n%d_a%lld_g%lld_r%d_s%lld_b%d_t%d.%d.%d_f%d.%d.%d.%d.%d_cu%d", n,
                 (long long)rp[n], (long long)ctx->single.nnz_g, maxrow, (long long)pcgh::sell_entries(n, rp),
-                (int)b3, c.vec_dtype, c.a_dtype, c.g_dtype, c.refine, c.layout, c.wide_index, c.grid_mult, ctx->cus);
+                (int)b3, c.vec_dtype, c.a_dtype, c.g_dtype, c.refine, c.layout, c.wide_index, c.grid_mult,
+                c.cache_mb, ctx->cus);
   return buf;
 }
 
@@ -2026,8 +2061,10 @@ static int time_iteration(pcg_ctx *ctx, int iters, double *ms) {
 static int apply_tune(pcg_ctx *ctx, const pcg_ctx::Tune &t) {
   const bool same = ctx->tune.on == t.on && (!t.on || (ctx->tune.la == t.la && ctx->tune.lg == t.lg &&
                                                        ctx->tune.gm == t.gm));
+  const bool same_res = same && (!t.on || ctx->tune.res == t.res);
   ctx->tune = t;
-  return same ? PCG_OK : relayout(ctx);
+  if (!same) return relayout(ctx);
+  return same_res ? PCG_OK : single_sets(ctx);  // load policy only: new directory entries
 }
 
 int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
@@ -2122,6 +2159,22 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
       t.gm = gm;
       if ((rc = consider(t))) return rc;
     }
+    // load policy for the best layouts and grid: none, A, all read with
+    // ordinary loads (the residency plan's choice was timed above)
+    base = best;
+    if (!base.on) {
+      base.on = true;
+      base.la = ctx->cfg.layout;
+      base.lg = ctx->cfg.layout;
+      base.gm = gm0;
+    }
+    const int planned = residency_plan(ctx);
+    for (int r : {0, 1, 7}) {
+      if (r == planned) continue;
+      pcg_ctx::Tune t = base;
+      t.res = r;
+      if ((rc = consider(t))) return rc;
+    }
     if ((rc = apply_tune(ctx, best))) return rc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_store(key, best);
@@ -2138,6 +2191,8 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
     res->fmt_gt = ctx->single.dev.GT.fmt;
     res->idx16 = (ctx->single.dev.A.idx16 ? 1 : 0) | (ctx->single.dev.G.idx16 ? 2 : 0) |
                  (ctx->single.dev.GT.idx16 ? 4 : 0);
+    res->temporal = ctx->single.dev.A.temporal | (ctx->single.dev.G.temporal << 1) |
+                    (ctx->single.dev.GT.temporal << 2);
   }
   return PCG_OK;
 }
