@@ -301,10 +301,10 @@ int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, 
  * candidate storage of A (CSR row blocks, sliced ELL, 3x3 blocks: each
  * distinct format the matrix admits) and of G and G^T (CSR, sliced ELL), at
  * the configured grid, then for the best layouts at half and twice the
- * grid, then the load policy (no matrix, A alone, or all three read with
- * ordinary loads and kept in the memory-side cache, besides the residency
- * plan's choice), and keeps the fastest (a candidate must beat the current
- * best by 3%).
+ * grid, then the load policy (each subset of A, G, G^T read with ordinary
+ * loads and kept in the memory-side cache, besides the residency plan's
+ * choice), and keeps the fastest (a candidate must beat the current best by
+ * 3%).
  * The matrices are laid out again with the same values, so products stay
  * bit-identical; the grid changes the partial-sum order of the dot products.
  * A layout forced in the configuration is kept; only the grid is tuned then.

@@ -2159,8 +2159,8 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
       t.gm = gm;
       if ((rc = consider(t))) return rc;
     }
-    // load policy for the best layouts and grid: none, A, all read with
-    // ordinary loads (the residency plan's choice was timed above)
+    // load policy for the best layouts and grid: every subset of {A, G, G^T}
+    // read with ordinary loads (the residency plan's choice was timed above)
     base = best;
     if (!base.on) {
       base.on = true;
@@ -2169,7 +2169,7 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
       base.gm = gm0;
     }
     const int planned = residency_plan(ctx);
-    for (int r : {0, 1, 7}) {
+    for (int r = 0; r < 8; ++r) {
       if (r == planned) continue;
       pcg_ctx::Tune t = base;
       t.res = r;

@@ -103,6 +103,6 @@ def test_autotune_keeps_forced_layout(gpu_lib):
         s.set_matrix(A)
         s.build_precond(pcg.G_FSAI)
         t = s.autotune(10)
-        assert t["fmt_a"] == 0 and t["fmt_g"] == 0 and t["fmt_gt"] == 0 and t["candidates"] == 6
+        assert t["fmt_a"] == 0 and t["fmt_g"] == 0 and t["fmt_gt"] == 0 and t["candidates"] == 11
         got = s.solve(b, tol=1e-8, maxit=5000)
         _parity(s, got, A, b, 1e-8)
