@@ -141,11 +141,14 @@ __device__ __forceinline__ Mat<TM> mat(const DevCSR &m) {
   return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk, m.n, m.fmt, m.idx16, m.temporal};
 }
 
-// Column of stored entry q of `row` (sliced layouts with 16-bit indices keep
-// the column minus the row).
-template <typename TM>
-__device__ __forceinline__ int32_t col_at(const Mat<TM> &M, int64_t q, int32_t row) {
-  return M.idx16 ? row + (int32_t)((GLOBAL const int16_t *)M.ci)[q] : M.ci[q];
+// Column of stored entry q of `row`: an absolute int32 index, or (sliced
+// layouts with 16-bit indices) an int16 difference from the row.
+template <typename TI>
+__device__ __forceinline__ int32_t col_at(GLOBAL const int32_t *ci, int64_t q, int32_t row) {
+  if constexpr (sizeof(TI) == 2)
+    return row + (int32_t)((GLOBAL const int16_t *)ci)[q];
+  else
+    return ci[q];
 }
 
 // Operands of one row loaded before the row's products are staged.
@@ -1017,7 +1020,7 @@ __device__ __forceinline__ double ld64(GLOBAL const double *p, int64_t k) { retu
 // works on 64 / LPR rows at once, lane p of a group on probes p, p + LPR, ...
 // Each group loads four entries' columns and values ahead of their gathers;
 // the products are still added left to right.
-template <typename TM, int LPR>
+template <typename TM, int LPR, typename TI>
 __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmm(DevCSR Md, int32_t k, const double *__restrict__ X_,
                                                               double c, const double *__restrict__ Z_, double d,
                                                               double *__restrict__ Y_) {
@@ -1083,7 +1086,7 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmm(DevCSR Md, int32_
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int64_t q = e0 + (int64_t)(e + u) * stride;
-          col[u] = col_at(M, q, row);
+          col[u] = col_at<TI>(M.ci, q, row);
           a[u] = ld64(M.val, q);
         }
         double x[4];
@@ -1094,7 +1097,7 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmm(DevCSR Md, int32_
       }
       for (; e < len; ++e) {
         const int64_t q = e0 + (int64_t)e * stride;
-        const int32_t col = col_at(M, q, row);
+        const int32_t col = col_at<TI>(M.ci, q, row);
         const double a = ld64(M.val, q);
         sum += a * (act ? X[(int64_t)col * k + p] : 0.0);
       }
@@ -1339,7 +1342,10 @@ hipError_t launch_spmm(const DevCSR &M, int32_t k, const double *X, double c, co
   const int grid = (int)std::min<int64_t>(((int64_t)M.n + rows_per_block - 1) / rows_per_block, 65536);
 #define PCG_SPMM(L)                                                                                          \
   PCG_DISPATCH_G(M.dtype, TM, {                                                                              \
-    hipLaunchKernelGGL((k_spmm<TM, L>), dim3(grid), dim3(kBlock), 0, s, M, k, X, c, Z, d, Y);                \
+    if (M.idx16)                                                                                             \
+      hipLaunchKernelGGL((k_spmm<TM, L, int16_t>), dim3(grid), dim3(kBlock), 0, s, M, k, X, c, Z, d, Y);     \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_spmm<TM, L, int32_t>), dim3(grid), dim3(kBlock), 0, s, M, k, X, c, Z, d, Y);     \
   })
   switch (lpr) {
     case 64: PCG_SPMM(64); break;
