@@ -1338,6 +1338,33 @@ void drop_step_graph(pcg_ctx *ctx) {
   ctx->step_graph_iters = 0;
 }
 
+// Residency of the active set: when the matrices and iteration vectors of all
+// active systems fit in 90% of the memory-side cache, their matrices are read
+// with ordinary loads and stay cached from step to step; else they stream
+// with nontemporal loads. Changed directory records are uploaded in stream
+// order (the kernels read the flags from the directory at run time).
+int batch_residency(pcg_ctx *ctx, hipStream_t s) {
+  bool keep = false;
+  if (ctx->cfg.cache_mb >= 0) {
+    const double cap = (ctx->cfg.cache_mb > 0 ? ctx->cfg.cache_mb : 256) * 1048576.0;
+    const double sv = (double)pcgk::dtype_size(ctx->ty.vec);
+    double total = 0.0;
+    for (auto &R : ctx->active) {
+      const SysDev &D = ctx->dir[R->slot];
+      total += placed_bytes(D.A) + placed_bytes(D.G) + placed_bytes(D.GT) + 8.0 * D.n * sv;
+    }
+    keep = total <= 0.9 * cap;
+  }
+  const int32_t t = keep ? 1 : 0;
+  for (auto &R : ctx->active) {
+    SysDev &D = ctx->dir[R->slot];
+    if (D.A.temporal == t && D.G.temporal == t && D.GT.temporal == t) continue;
+    D.A.temporal = D.G.temporal = D.GT.temporal = t;
+    HIPCHK(h2d(ctx->d_dir + R->slot, &ctx->dir[R->slot], sizeof(SysDev), s));
+  }
+  return PCG_OK;
+}
+
 // One scheduler step: admit, `iters` iterations over the active set, retire.
 int progress(pcg_ctx *ctx, int iters) {
   int rc;
@@ -1360,6 +1387,7 @@ int progress(pcg_ctx *ctx, int iters) {
   hipStream_t s = ctx->stream;
   if (ctx->active_dirty) {
     drop_step_graph(ctx);
+    if ((rc = batch_residency(ctx, s))) return rc;
     std::vector<int> slots;
     for (auto &R : ctx->active) slots.push_back(R->slot);
     if ((rc = build_set(ctx, ctx->set_active, slots))) return rc;
