@@ -88,9 +88,9 @@ typedef struct {
   int rr_period;     /* recompute r = b - A x every rr_period iterations (Algorithm 1 uses 50); 0 = never */
   double eps;        /* shift of M^-1 = G G^T + eps I, absolute units (default 0) */
   int refine;        /* 1: FP64 iterative refinement around a vec_dtype = F32 inner PCG */
-  double inner_tol;  /* relative tolerance of each inner solve under refinement (default 1e-4); an
-                        inner solve that needs less to reach the target runs to
-                        min(1/2, tol*||b|| / (4 ||r64||)) instead */
+  double inner_tol;  /* relative tolerance of each inner solve under refinement (default 1e-6). A
+                        step that can finish, i.e. whose target tol*||b|| / (4 ||r64||) is at least
+                        inner_tol / 10, runs to min(1/2, that target) instead */
   int max_outer;     /* refinement steps at most (default 30) */
   int graph_iters;   /* iterations per captured HIP graph replay (default 10; 0 = plain launches) */
   int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */

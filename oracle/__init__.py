@@ -341,10 +341,12 @@ def g_storage_scale(G, fmt: str) -> float:
 
 
 def inner_tolerance(inner_tol: float, tol: float, nb: float, rn: float) -> float:
-    """Relative tolerance of an inner solve: inner_tol, but no tighter than
-    what brings ||r64|| from rn to a quarter of the target tol ||b||, and never
-    looser than 1/2."""
-    return min(0.5, max(inner_tol, 0.25 * tol * nb / rn))
+    """Relative tolerance of an inner solve (reading of the mixed-precision
+    setup): the step that can finish runs to what brings ||r64|| from rn to a
+    quarter of the target tol ||b|| (never looser than 1/2, and used when it
+    is at least inner_tol / 10); other steps run to inner_tol."""
+    target = 0.25 * tol * nb / rn
+    return min(0.5, target) if target >= 0.1 * inner_tol else inner_tol
 
 
 @dataclass
@@ -358,7 +360,7 @@ class IRResult:
 
 
 def pcg_ir(A, G, b, *, tol: float = 1e-10, a_dtype: str = "f32", g_dtype: str = "bf16", vec_dtype: str = "f32",
-           eps: float = 0.0, inner_tol: float = 1e-4, max_outer: int = 30, maxit: int = 2000) -> IRResult:
+           eps: float = 0.0, inner_tol: float = 1e-6, max_outer: int = 30, maxit: int = 2000) -> IRResult:
     """FP64 iterative refinement around a PCG on stored operands (the mixed-
     precision setting of Sec. 4: G in a 16-bit format, A and vectors in FP32,
     FP64 dot products), as an FP64 emulation. Storage is emulated by rounding

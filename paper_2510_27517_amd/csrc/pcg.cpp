@@ -929,13 +929,17 @@ int store_vec(pcg_ctx *ctx, const void *src, int dtype, double *dst, int on_devi
   return PCG_OK;
 }
 
-// Relative tolerance of the next inner solve: the configured one, but no
-// tighter than what brings ||r64|| from rn to a quarter of the target tol*nb
-// (the margin covers the gap between the inner solve's recurrence residual
-// and the FP64 residual), and never looser than 1/2.
+// Relative tolerance of the next inner solve. The step that can finish runs
+// to what brings ||r64|| from rn to a quarter of the target tol*nb (the
+// margin covers the gap between the inner solve's recurrence residual and the
+// FP64 residual), never looser than 1/2, and up to ten times tighter than the
+// configured tolerance (one longer inner solve instead of one more outer step,
+// which would restart the Krylov space); other steps run to the configured
+// tolerance.
 double inner_tolerance(double cfg_inner_tol, double tol, double nb, double rn) {
-  const double base = cfg_inner_tol > 0 ? cfg_inner_tol : 1e-4;
-  return std::min(0.5, std::max(base, 0.25 * tol * nb / rn));
+  const double base = cfg_inner_tol > 0 ? cfg_inner_tol : 1e-6;
+  const double target = 0.25 * tol * nb / rn;
+  return target >= 0.1 * base ? std::min(0.5, target) : base;
 }
 
 // FP64 iterative refinement: r64 = b - A64 x64 in FP64; inner PCG on
@@ -1597,7 +1601,7 @@ void pcg_config_default(pcg_config *cfg) {
   cfg->rr_period = 50;
   cfg->eps = 0.0;
   cfg->refine = 0;
-  cfg->inner_tol = 1e-4;
+  cfg->inner_tol = 1e-6;
   cfg->max_outer = 30;
   cfg->graph_iters = 10;
   cfg->grid_mult = 8;

@@ -178,7 +178,8 @@ def test_refinement_follows_the_emulated_outer_loop(gpu_lib, case, gdt):
     which moves each inner residual by a relative O(kappa u32): same status
     and outer steps, inner iterations within 2 % plus one per outer step, and
     both solutions within the 1e-10 residual bound of each other. Cut to two
-    outer steps, both stop unconverged with FP64 residuals within a factor 2."""
+    outer steps of inner tolerance 1e-4, both stop unconverged with FP64
+    residuals within a factor 2."""
     pcg = gpu_lib
     if case == "poisson3d":
         A = inputs.poisson(3, 24, 1.0, 3)
@@ -200,11 +201,11 @@ def test_refinement_follows_the_emulated_outer_loop(gpu_lib, case, gdt):
     assert abs(got.iters - emu.iters) <= 0.02 * emu.iters + emu.outer
     nx = np.linalg.norm(emu.x)
     assert np.linalg.norm(got.x - emu.x) <= 1e-6 * nx
-    with pcg.Solver(pcg.default_config(max_outer=2, **kw)) as s:
+    with pcg.Solver(pcg.default_config(max_outer=2, inner_tol=1e-4, **kw)) as s:
         s.set_matrix(A)
         s.set_precond(G)
         cut = s.solve(b, tol=1e-14, maxit=5000)
-    ecut = oracle.pcg_ir(A, G, b, tol=1e-14, a_dtype="f32", g_dtype=gdt, maxit=5000, max_outer=2)
+    ecut = oracle.pcg_ir(A, G, b, tol=1e-14, a_dtype="f32", g_dtype=gdt, maxit=5000, max_outer=2, inner_tol=1e-4)
     r64 = np.linalg.norm(b - oracle.spmv(A, cut.x)) / np.linalg.norm(b)
     say(f"  two outer steps: gpu relres {r64:.2e} (reported {cut.relres_true:.2e}), emulation {ecut.relres_true:.2e}")
     assert cut.status == ecut.status == pcg.NOT_CONVERGED and cut.outer_iters == ecut.outer == 2

@@ -588,6 +588,18 @@ def test_ir_exact_storage_one_step():
     assert np.linalg.norm(res.x - xs) <= np.linalg.cond(Ad) * 1e-8 * np.linalg.norm(xs)
 
 
+def test_inner_tolerance_schedule():
+    """The finishing step runs to a quarter of the remaining reduction (at most
+    ten times tighter than inner_tol, never looser than 1/2); other steps run
+    to inner_tol."""
+    it = oracle.inner_tolerance
+    assert it(1e-6, 1e-8, 1.0, 1.0) == 1e-6           # 2.5e-9 needed: not the last step
+    assert it(1e-6, 1e-8, 1.0, 1e-4) == 0.25 * 1e-8 / 1e-4  # 2.5e-5: finish now
+    assert it(1e-6, 1e-8, 1.0, 2e-2) == 0.25 * 1e-8 / 2e-2  # 1.25e-7 >= inner_tol / 10: finish
+    assert it(1e-6, 1e-8, 1.0, 2.6e-2) == 1e-6        # 9.6e-8 < inner_tol / 10
+    assert it(1e-4, 1e-8, 1.0, 2e-9) == 0.5           # capped
+
+
 def test_ir_each_step_contracts_by_the_inner_tolerance():
     """Exact storage: the inner solve is CG on A c = r/||r|| itself, so the
     FP64 residual after x += ||r|| c is ||r|| times the inner relative
