@@ -207,6 +207,20 @@ def section_synthetic(pcg, inputs, count):
             ms = (time.perf_counter() - t0) * 1e3
         out[tag] = {"n": A.n, "nnz": A.nnz, "time_to_tol_ms": round(ms, 2), "iters": r.iters, "status": r.status,
                     "us_per_iter": round(ms * 1e3 / max(r.iters, 1), 2), "relres_true_fp64": r.relres_true}
+        with pcg.Solver(pcg.default_config()) as s:  # the same solve with the autotuner's choice
+            s.set_matrix(A)
+            s.build_precond(pcg.G_FSAI)
+            t = s.autotune(20)
+            s.solve(b, tol=1e-8, maxit=20000)
+            t0 = time.perf_counter()
+            r = s.solve(b, tol=1e-8, maxit=20000)
+            ms = (time.perf_counter() - t0) * 1e3
+        names = {v: k for k, v in pcg.LAYOUTS.items()}
+        out[tag]["autotuned"] = {"time_to_tol_ms": round(ms, 2), "iters": r.iters, "status": r.status,
+                                 "layout_a": names.get(t["layout_a"]), "layout_g": names.get(t["layout_g"]),
+                                 "grid_mult": t["grid_mult"], "temporal": t["temporal"],
+                                 "ms_per_iter_tuned": round(t["ms_per_iter"], 5),
+                                 "ms_per_iter_auto": round(t["ms_per_iter_auto"], 5)}
     log(f"synthetic: batch of {count}")
     u = inputs.u01(11, inputs.STREAM_SIZES, count)
     systems = []
