@@ -340,13 +340,16 @@ def g_storage_scale(G, fmt: str) -> float:
     return float(2.0 ** (14 - int(e)))
 
 
-def inner_tolerance(inner_tol: float, tol: float, nb: float, rn: float) -> float:
-    """Relative tolerance of an inner solve (reading of the mixed-precision
-    setup): the step that can finish runs to what brings ||r64|| from rn to a
-    quarter of the target tol ||b|| (never looser than 1/2, and used when it
-    is at least inner_tol / 10); other steps run to inner_tol."""
+def inner_tolerance(inner_tol: float, tol: float, nb: float, rn: float, step: int = 1) -> float:
+    """Relative tolerance of inner solve number `step` (0 first; reading of the
+    mixed-precision setup): inner_tol, or what brings ||r64|| from rn to a
+    quarter of the target tol ||b|| when that is looser (never looser than
+    1/2); after the first step, also that target when it is down to
+    inner_tol / 10 (the step that can finish)."""
     target = 0.25 * tol * nb / rn
-    return min(0.5, target) if target >= 0.1 * inner_tol else inner_tol
+    if target >= inner_tol or (step > 0 and target >= 0.1 * inner_tol):
+        return min(0.5, target)
+    return inner_tol
 
 
 @dataclass
@@ -402,7 +405,7 @@ def pcg_ir(A, G, b, *, tol: float = 1e-10, a_dtype: str = "f32", g_dtype: str = 
             break
         prev = rn
         rhs = round_storage(r / rn, vec_dtype)
-        inner = pcg(As, Gs, rhs, eps=eps * sc * sc, tol=inner_tolerance(inner_tol, tol, nb, rn), maxit=maxit,
+        inner = pcg(As, Gs, rhs, eps=eps * sc * sc, tol=inner_tolerance(inner_tol, tol, nb, rn, outer), maxit=maxit,
                     rr_period=0, delta_form=1, stop_rule=2)
         iters += inner.iters
         if inner.status == EBREAKDOWN:

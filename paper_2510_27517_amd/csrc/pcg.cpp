@@ -929,17 +929,19 @@ int store_vec(pcg_ctx *ctx, const void *src, int dtype, double *dst, int on_devi
   return PCG_OK;
 }
 
-// Relative tolerance of the next inner solve. The step that can finish runs
-// to what brings ||r64|| from rn to a quarter of the target tol*nb (the
-// margin covers the gap between the inner solve's recurrence residual and the
-// FP64 residual), never looser than 1/2, and up to ten times tighter than the
-// configured tolerance (one longer inner solve instead of one more outer step,
-// which would restart the Krylov space); other steps run to the configured
-// tolerance.
-double inner_tolerance(double cfg_inner_tol, double tol, double nb, double rn) {
+// Relative tolerance of inner solve number `step` (0 first). A solve runs to
+// the configured tolerance, or to what brings ||r64|| from rn to a quarter of
+// the target tol*nb when that is looser (the margin covers the gap between the
+// inner solve's recurrence residual and the FP64 residual), never looser than
+// 1/2. After the first step, whose result shows how deep the inner solve gets
+// in its precision, the step that can finish also runs to that target when it
+// is up to ten times tighter than the configured tolerance: one longer inner
+// solve instead of one more outer step, which would restart the Krylov space.
+double inner_tolerance(double cfg_inner_tol, double tol, double nb, double rn, int step) {
   const double base = cfg_inner_tol > 0 ? cfg_inner_tol : 1e-6;
   const double target = 0.25 * tol * nb / rn;
-  return target >= 0.1 * base ? std::min(0.5, target) : base;
+  if (target >= base || (step > 0 && target >= 0.1 * base)) return std::min(0.5, target);
+  return base;
 }
 
 // FP64 iterative refinement: r64 = b - A64 x64 in FP64; inner PCG on
@@ -990,7 +992,7 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
     HIPCHK(pcgk::launch_convert(pcgk::F64, S.dev64.r0, ctx->ty.vec, S.dev.b, n, 1.0 / rn, s));
     HIPCHK(pcgk::launch_fill(ctx->ty.vec, S.dev.x, n, 0.0, s));
     CoreOut co;
-    int rc = solve_core(ctx, inner_tolerance(ctx->cfg.inner_tol, tol, nb, rn), maxit, co, false);
+    int rc = solve_core(ctx, inner_tolerance(ctx->cfg.inner_tol, tol, nb, rn, outer), maxit, co, false);
     if (rc) return rc;
     total_iters += co.iters;
     restarts += co.restarts;
@@ -1300,7 +1302,7 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
         status = PCG_NOT_CONVERGED;
       else
         R->prev_rn = rn;
-      next_tol = inner_tolerance(ctx->cfg.inner_tol, R->tol, nb, rn);
+      next_tol = inner_tolerance(ctx->cfg.inner_tol, R->tol, nb, rn, R->outer);
     }
     if (status != 1) {
       int rc = retire(ctx, *R);

@@ -589,15 +589,18 @@ def test_ir_exact_storage_one_step():
 
 
 def test_inner_tolerance_schedule():
-    """The finishing step runs to a quarter of the remaining reduction (at most
-    ten times tighter than inner_tol, never looser than 1/2); other steps run
-    to inner_tol."""
+    """Steps run to inner_tol, or to a quarter of the remaining reduction when
+    that is looser (never looser than 1/2); after the first step also when it
+    is down to inner_tol / 10 (the finishing step)."""
     it = oracle.inner_tolerance
-    assert it(1e-6, 1e-8, 1.0, 1.0) == 1e-6           # 2.5e-9 needed: not the last step
-    assert it(1e-6, 1e-8, 1.0, 1e-4) == 0.25 * 1e-8 / 1e-4  # 2.5e-5: finish now
-    assert it(1e-6, 1e-8, 1.0, 2e-2) == 0.25 * 1e-8 / 2e-2  # 1.25e-7 >= inner_tol / 10: finish
-    assert it(1e-6, 1e-8, 1.0, 2.6e-2) == 1e-6        # 9.6e-8 < inner_tol / 10
-    assert it(1e-4, 1e-8, 1.0, 2e-9) == 0.5           # capped
+    assert it(1e-6, 1e-8, 1.0, 1.0, 0) == 1e-6           # 2.5e-9 needed: not the last step
+    assert it(1e-6, 1e-8, 1.0, 1e-4, 1) == 0.25 * 1e-8 / 1e-4  # 2.5e-5: finish now
+    assert it(1e-6, 1e-8, 1.0, 2e-2, 1) == 0.25 * 1e-8 / 2e-2  # 1.25e-7 >= inner_tol / 10: finish
+    assert it(1e-6, 1e-8, 1.0, 2e-2, 0) == 1e-6          # the first step stays at inner_tol
+    assert it(1e-6, 1e-6, 1.0, 1.0, 0) == 1e-6           # 2.5e-7: first step, not looser
+    assert it(1e-6, 1e-8, 1.0, 2.6e-2, 1) == 1e-6        # 9.6e-8 < inner_tol / 10
+    assert it(1e-6, 1e-4, 1.0, 1.0, 0) == 0.25 * 1e-4    # looser than inner_tol: any step
+    assert it(1e-4, 1e-8, 1.0, 2e-9, 3) == 0.5           # capped
 
 
 def test_ir_each_step_contracts_by_the_inner_tolerance():
@@ -611,7 +614,7 @@ def test_ir_each_step_contracts_by_the_inner_tolerance():
     h = res.rhist
     assert res.status == oracle.OK and res.outer == h.shape[0] - 1 >= 3
     for k in range(res.outer):
-        eta = oracle.inner_tolerance(1e-3, 1e-13, 1.0, h[k])
+        eta = oracle.inner_tolerance(1e-3, 1e-13, 1.0, h[k], k)
         assert h[k + 1] <= eta * h[k] * (1 + 1e-6) + 1e-15, (k, h)
 
 
