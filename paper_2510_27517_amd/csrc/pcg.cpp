@@ -509,6 +509,7 @@ hipError_t place_g(const GPart &P, void *block, Sys &S, hipStream_t s) {
 struct HostSet {
   std::vector<int> slots;
   void *dev = nullptr;  // maps + set
+  size_t cap = 0;       // bytes allocated at dev (reused by the next build)
   LaunchSet L{};
 };
 
@@ -597,7 +598,7 @@ struct pcg_ctx {
   uint64_t next_ticket = 1;
   std::vector<std::thread> workers;
   bool stop = false;
-  HostSet set_active;
+  HostSet set_active, set_done, set_tmp, set_tmp64;  // device buffers reused from step to step
   bool active_dirty = true;
   // the scheduler step (K iterations over the active set) as a HIP graph,
   // valid until the active set changes
@@ -627,36 +628,58 @@ void free_set(pcg_ctx *ctx, HostSet &hs) {
 }
 
 // Maps for the systems in `slots` (directory indices).
+// The maps (system, local workgroup) of the four launch shapes and the slot
+// list, staged on the host and uploaded in one copy. The set's device buffer
+// is reused when large enough (no graph may still reference the old maps:
+// callers drop their graphs first, and no kernel of the set is in flight).
 int build_set(pcg_ctx *ctx, HostSet &hs, const std::vector<int> &slots) {
-  free_set(ctx, hs);
+  void *keep = hs.dev;
+  const size_t kcap = hs.cap;
+  hs = HostSet{};
   hs.slots = slots;
-  std::vector<int2> mA, mGT, mG, mB;
+  size_t nA = 0, nGT = 0, nG = 0, nB = 0;
   for (int sl : slots) {
     const SysDev &D = ctx->dir[sl];
-    for (int l = 0; l < D.A.grid; ++l) mA.push_back(make_int2(sl, l));
-    for (int l = 0; l < D.GT.grid; ++l) mGT.push_back(make_int2(sl, l));
-    for (int l = 0; l < D.G.grid; ++l) mG.push_back(make_int2(sl, l));
-    for (int l = 0; l < D.gB; ++l) mB.push_back(make_int2(sl, l));
+    nA += D.A.grid;
+    nGT += D.GT.grid;
+    nG += D.G.grid;
+    nB += D.gB;
   }
-  const size_t bytes = 8 * (mA.size() + mGT.size() + mG.size() + mB.size()) + 4 * slots.size() + 64;
-  HIPCHK(ctx->da.get(&hs.dev, bytes));
-  int2 *p = (int2 *)hs.dev;
+  const size_t nmap = nA + nGT + nG + nB;
+  std::vector<int2> h(nmap + (slots.size() + 1) / 2);
+  size_t o = 0;
+  for (int sl : slots)
+    for (int l = 0; l < ctx->dir[sl].A.grid; ++l) h[o++] = make_int2(sl, l);
+  for (int sl : slots)
+    for (int l = 0; l < ctx->dir[sl].GT.grid; ++l) h[o++] = make_int2(sl, l);
+  for (int sl : slots)
+    for (int l = 0; l < ctx->dir[sl].G.grid; ++l) h[o++] = make_int2(sl, l);
+  for (int sl : slots)
+    for (int l = 0; l < ctx->dir[sl].gB; ++l) h[o++] = make_int2(sl, l);
+  if (!slots.empty()) std::memcpy(h.data() + nmap, slots.data(), 4 * slots.size());
+  const size_t used = 8 * h.size(), bytes = used + 64;
+  if (keep && kcap >= bytes) {
+    hs.dev = keep;
+    hs.cap = kcap;
+  } else {
+    ctx->da.put(keep);
+    HIPCHK(ctx->da.get(&hs.dev, bytes));
+    hs.cap = bytes;
+  }
+  if (used) HIPCHK(hipMemcpy(hs.dev, h.data(), used, hipMemcpyHostToDevice));
+  const int2 *p = (const int2 *)hs.dev;
   LaunchSet &L = hs.L;
   L.dir = ctx->d_dir;
-  auto put = [&](const std::vector<int2> &m, const int2 *&dst, int32_t &cnt) -> hipError_t {
-    dst = p;
-    cnt = (int32_t)m.size();
-    hipError_t e = m.empty() ? hipSuccess : hipMemcpy(p, m.data(), 8 * m.size(), hipMemcpyHostToDevice);
-    p += m.size();
-    return e;
-  };
-  HIPCHK(put(mA, L.mapA, L.nA));
-  HIPCHK(put(mGT, L.mapGT, L.nGT));
-  HIPCHK(put(mG, L.mapG, L.nG));
-  HIPCHK(put(mB, L.mapB, L.nB));
-  L.set = (const int32_t *)p;
+  L.mapA = p;
+  L.nA = (int32_t)nA;
+  L.mapGT = p + nA;
+  L.nGT = (int32_t)nGT;
+  L.mapG = p + nA + nGT;
+  L.nG = (int32_t)nG;
+  L.mapB = p + nA + nGT + nG;
+  L.nB = (int32_t)nB;
+  L.set = (const int32_t *)(p + nmap);
   L.nset = (int32_t)slots.size();
-  if (!slots.empty()) HIPCHK(hipMemcpy(p, slots.data(), 4 * slots.size(), hipMemcpyHostToDevice));
   return PCG_OK;
 }
 
@@ -1204,7 +1227,7 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
     HIPCHK(h2d(ctx->d_dir + R.slot, &ctx->dir[R.slot], sizeof(SysDev), s));
     HIPCHK(h2d(ctx->d_states + 2 * R.slot, &inits[2 * i], 2 * sizeof(State), s));
   }
-  HostSet hs;
+  HostSet &hs = ctx->set_tmp;
   int rc = build_set(ctx, hs, slots);
   if (rc) return rc;
   if (ctx->cfg.refine) {  // first FP64 residual of every new system
@@ -1215,7 +1238,6 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
     rc = enqueue_start(ctx, ctx->ty, hs.L, ctx->cfg.eps != 0.0);
   }
   HIPCHK(hipStreamSynchronize(s));  // copies done: host staging may go
-  free_set(ctx, hs);
   if (rc) return rc;
   const double t = now_ms();
   for (auto &R : cand) {
@@ -1317,7 +1339,7 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
     slots64.push_back(R->slot64);
   }
   if (go.empty()) return PCG_OK;
-  HostSet h64, hin;
+  HostSet &h64 = ctx->set_tmp64, &hin = ctx->set_tmp;
   int rc = build_set(ctx, h64, slots64);
   if (!rc) rc = build_set(ctx, hin, slots);
   if (rc) return rc;
@@ -1331,8 +1353,6 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
   }
   rc = enqueue_start(ctx, ctx->ty, hin.L, ctx->cfg.eps != 0.0);
   HIPCHK(hipStreamSynchronize(s));
-  free_set(ctx, h64);
-  free_set(ctx, hin);
   if (rc) return rc;
   for (auto &R : go) cont.push_back(R);
   return PCG_OK;
@@ -1391,6 +1411,7 @@ int progress(pcg_ctx *ctx, int iters) {
   }
   if (ctx->active.empty()) return PCG_OK;
   hipStream_t s = ctx->stream;
+  const bool changed = ctx->active_dirty;
   if (ctx->active_dirty) {
     drop_step_graph(ctx);
     if ((rc = batch_residency(ctx, s))) return rc;
@@ -1414,9 +1435,11 @@ int progress(pcg_ctx *ctx, int iters) {
     }
     return false;
   };
-  if (ctx->cfg.graph_iters > 0) {
-    // one graph per active set: the residual kernel runs every iteration and
-    // decides per system, when some system replaces at all
+  if (ctx->cfg.graph_iters > 0 && !changed) {
+    // one graph per active set, captured once the set has stayed the same
+    // for a step (a set that changes every step is cheaper to launch plainly
+    // than to capture): the residual kernel runs every iteration and decides
+    // per system, when some system replaces at all
     bool replaces = false;
     for (auto &R : ctx->active) replaces = replaces || (rr > 0 && R->slot64 < 0);
     if (!ctx->step_graph || ctx->step_graph_iters != iters) {
@@ -1461,13 +1484,12 @@ int progress(pcg_ctx *ctx, int iters) {
     if (ctx->h_states[2 * R->slot].done) done_slots.push_back(R->slot);
   if (done_slots.empty()) return PCG_OK;
   // finish the stopped systems: any pending x update, true residual
-  HostSet hs;
+  HostSet &hs = ctx->set_done;
   if ((rc = build_set(ctx, hs, done_slots))) return rc;
   HIPCHK(pcgk::launch_finalize(ctx->ty, hs.L, s));
   HIPCHK(pcgk::launch_resid(ctx->ty, hs.L, 0, false, true, false, s));
   HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, sb, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  free_set(ctx, hs);
   std::vector<int> restart_slots;
   std::vector<std::shared_ptr<Req>> keep, outer_list;
   for (auto &R : ctx->active) {
@@ -1516,7 +1538,6 @@ int progress(pcg_ctx *ctx, int iters) {
     HIPCHK(pcgk::launch_iter_GT(ctx->ty, hs.L, 2, s));
     HIPCHK(pcgk::launch_iter_G(ctx->ty, hs.L, has_eps, 2, s));
     HIPCHK(hipStreamSynchronize(s));
-    free_set(ctx, hs);
   }
   if (!outer_list.empty()) {  // x64 += ||r|| c, then the FP64 residual
     const Types t64{pcgk::F64, pcgk::F64, pcgk::F64};
@@ -1532,7 +1553,6 @@ int progress(pcg_ctx *ctx, int iters) {
     HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, 2 * sizeof(State) * (size_t)(mx + 1), hipMemcpyDeviceToHost,
                           s));
     HIPCHK(hipStreamSynchronize(s));
-    free_set(ctx, hs);
     for (auto &R : outer_list) R->outer++;
     std::vector<std::shared_ptr<Req>> cont;
     if ((rc = outer_decide(ctx, outer_list, cont))) return rc;
@@ -1682,6 +1702,9 @@ void pcg_destroy(pcg_ctx *ctx) {
   free_set(ctx, ctx->set_main);
   free_set(ctx, ctx->set_64);
   free_set(ctx, ctx->set_active);
+  free_set(ctx, ctx->set_done);
+  free_set(ctx, ctx->set_tmp);
+  free_set(ctx, ctx->set_tmp64);
   free_sys(ctx, ctx->single);
   ctx->pool.reset();
   for (auto &e : ctx->ev)
