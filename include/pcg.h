@@ -147,7 +147,9 @@ typedef struct {
   double relres_true;  /* ||b - A x|| / ||b|| at exit, formed in the vector precision (FP64 under refinement) */
   double relres_rec;   /* recurrence ||r|| / ||b|| at exit */
   double t_solve_ms;   /* single solve: device time; batched: admission to completion (host clock) */
-  double bytes_per_iter; /* algorithmic HBM bytes of one iteration (A, G^T, G once; 11 vector streams) */
+  double bytes_per_iter; /* device bytes of one iteration in the layouts in use: A, G^T and G once
+                            (values, and column indices at their stored width: 4, 2 for 16-bit
+                            differences, 4/9 per value in 3x3 blocks), row pointers, 11 vector streams */
   double t_latency_ms; /* batched: submission to completion (host clock) */
   double t_queue_ms;   /* batched: submission to admission (host clock) */
 } pcg_result;
@@ -233,9 +235,10 @@ int pcg_sai_loss(pcg_ctx *ctx, int32_t k, const double *W, int on_device, double
  * stream, each with start/stop events attached to its dispatch (the
  * kernel's own execution interval). ms[0..2]: average duration of the A-,
  * G^T- and G-kernel launches; ms[3]: average iteration (A start to G end).
- * bytes[0..3] (may be NULL): their algorithmic device bytes per launch
- * (A: A's values, columns and row pointers plus 2 vector streams; G^T: G^T
- * plus 4; G: G plus 5, 6 with eps). Needs one prior pcg_solve with b != 0. */
+ * bytes[0..3] (may be NULL): their device bytes per launch in the stored
+ * layouts (A: A's values, column indices at their stored width and row
+ * pointers, plus 2 vector streams; G^T: G^T plus 4; G: G plus 5, 6 with
+ * eps). Needs one prior pcg_solve with b != 0 (or a nonzero stored b). */
 int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes);
 
 /* Device-to-device copy of `bytes` (rounded down to 16) repeated `reps`
@@ -335,8 +338,11 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res);
  * Returns PCG_EINVAL for a NULL pointer, n <= 0 or negative counts. */
 int pcg_estimate_bytes(const pcg_config *cfg, int32_t n, int64_t nnz_a, int64_t nnz_g, size_t *bytes);
 
-/* Algorithmic device bytes of one PCG iteration: A, G^T and G read once,
- * their row pointers, and 11 vector streams of n entries (vec bytes each). */
+/* Algorithmic device bytes of one PCG iteration over int32 CSR: A, G^T and G
+ * read once (values and 4-byte column indices), their row pointers, and 11
+ * vector streams of n entries (vec bytes each). Results report the bytes of
+ * the layouts actually used (pcg_result.bytes_per_iter), which store 16-bit
+ * column differences or one index per 3x3 block where they can. */
 double pcg_bytes_per_iter(int32_t n, int64_t nnz_a, int64_t nnz_g, int a_dtype, int g_dtype, int vec_dtype);
 
 const char *pcg_last_error(const pcg_ctx *ctx);
