@@ -87,7 +87,9 @@ typedef struct {
                         vectors F32, BF16 or F16. F16 values are stored times a power of two. */
   int rr_period;     /* recompute r = b - A x every rr_period iterations (Algorithm 1 uses 50); 0 = never */
   double eps;        /* shift of M^-1 = G G^T + eps I, absolute units (default 0) */
-  int refine;        /* 1: FP64 iterative refinement around a vec_dtype = F32 inner PCG */
+  int refine;        /* 1: FP64 iterative refinement around a vec_dtype = F32 inner PCG. A single
+                        solve whose outer step gains less than 2x, or whose FP32 inner solve breaks
+                        down, continues with FP64 inner solves (pcg_result.escalated) */
   double inner_tol;  /* relative tolerance of each inner solve under refinement (default 1e-6). A
                         step that can finish, i.e. whose target tol*||b|| / (4 ||r64||) is at least
                         inner_tol / 10, runs to min(1/2, that target) instead */
@@ -152,6 +154,8 @@ typedef struct {
                             differences, 4/9 per value in 3x3 blocks), row pointers, 11 vector streams */
   double t_latency_ms; /* batched: submission to completion (host clock) */
   double t_queue_ms;   /* batched: submission to admission (host clock) */
+  int escalated;       /* single solve under refinement: 1 when the inner solves switched to FP64 */
+  int reserved_;
 } pcg_result;
 
 /* One system of a batch (all pointers host memory, borrowed for the call). */

@@ -36,7 +36,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDirCap = 4096;  // systems per context (directory and state slots)
-constexpr int kSlotMain = 0, kSlot64 = 1, kFirstBatchSlot = 2;
+constexpr int kSlotMain = 0, kSlot64 = 1, kSlotX = 2, kFirstBatchSlot = 3;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -218,7 +218,8 @@ struct Sys {
   double g_scale = 1.0;
   SysDev dev{};    // directory entry
   SysDev dev64{};  // FP64 view for refinement (single path)
-  void *blkA = nullptr, *blkG = nullptr;
+  SysDev devx{};   // FP64 inner solves after an escalation (single path; FP64 view of A, G as stored)
+  void *blkA = nullptr, *blkG = nullptr, *blkX = nullptr;
   bool pooled = false;
   void *tmp_in = nullptr, *tmp_out = nullptr;
   double *stage64 = nullptr;
@@ -584,7 +585,9 @@ struct pcg_ctx {
   } tune;
   Sys single;
   HostSet set_main, set_64;
-  std::map<int, hipGraphExec_t> graphs;  // key: iters*2 + replace_first
+  std::map<int, hipGraphExec_t> graphs;    // key: iters*2 + replace_first
+  std::map<int, hipGraphExec_t> graphs_x;  // the same for the escalated FP64 inner solves
+  HostSet set_x;
   hipEvent_t ev[2] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
 
   // batching / serving
@@ -620,6 +623,8 @@ namespace {
 void drop_graphs(pcg_ctx *ctx) {
   for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
   ctx->graphs.clear();
+  for (auto &kv : ctx->graphs_x) (void)hipGraphExecDestroy(kv.second);
+  ctx->graphs_x.clear();
 }
 
 void free_set(pcg_ctx *ctx, HostSet &hs) {
@@ -696,6 +701,7 @@ void free_sys(pcg_ctx *ctx, Sys &S) {
     ctx->da.put(S.blkA);
     ctx->da.put(S.blkG);
   }
+  ctx->da.put(S.blkX);
   S = Sys{};
 }
 
@@ -752,6 +758,10 @@ int residency_plan(const pcg_ctx *ctx) {
 
 int single_sets(pcg_ctx *ctx) {
   drop_graphs(ctx);
+  // the FP64 record of escalated inner solves refers to the placed G: rebuilt
+  // at the next escalation
+  ctx->da.put(ctx->single.blkX);
+  ctx->single.blkX = nullptr;
   {
     const int r = residency_plan(ctx);
     ctx->single.dev.A.temporal = r & 1;
@@ -783,16 +793,28 @@ void enqueue_iteration(pcg_ctx *ctx, const Types &ty, const LaunchSet &L, bool r
   chain(pcgk::launch_iter_G(ty, L, eps != 0.0, mode, ctx->stream));
 }
 
-int get_graph(pcg_ctx *ctx, const Types &ty, int iters, bool replace_first, double eps, hipGraphExec_t *out) {
+// What a single-system PCG runs on: the kernels' types, the launch set, the
+// directory record (state slot, vectors) and the graph cache.
+struct Core {
+  Types ty;
+  const LaunchSet *L;
+  SysDev *dev;
+  int slot;
+  std::map<int, hipGraphExec_t> *graphs;
+};
+
+Core main_core(pcg_ctx *ctx) { return Core{ctx->ty, &ctx->set_main.L, &ctx->single.dev, kSlotMain, &ctx->graphs}; }
+
+int get_graph(pcg_ctx *ctx, const Core &c, int iters, bool replace_first, double eps, hipGraphExec_t *out) {
   const int key = iters * 2 + (replace_first ? 1 : 0);
-  auto it = ctx->graphs.find(key);
-  if (it != ctx->graphs.end()) {
+  auto it = c.graphs->find(key);
+  if (it != c.graphs->end()) {
     *out = it->second;
     return PCG_OK;
   }
   HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int k = 0; k < iters; ++k) enqueue_iteration(ctx, ty, ctx->set_main.L, replace_first && k == 0, eps, e);
+  for (int k = 0; k < iters; ++k) enqueue_iteration(ctx, c.ty, *c.L, replace_first && k == 0, eps, e);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
   HIPCHK(e);
@@ -801,7 +823,7 @@ int get_graph(pcg_ctx *ctx, const Types &ty, int iters, bool replace_first, doub
   hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   HIPCHK(e3);
-  ctx->graphs[key] = ex;
+  (*c.graphs)[key] = ex;
   *out = ex;
   return PCG_OK;
 }
@@ -828,15 +850,16 @@ int enqueue_start(pcg_ctx *ctx, const Types &ty, const LaunchSet &L, bool has_ep
 // residual meets tol, check b - A x and restart from it if that fails (the
 // inner solves of refinement skip this: the FP64 outer residual is the check,
 // and an FP32 iterate's true residual has a floor near u32 ||A|| ||x||).
-int solve_core(pcg_ctx *ctx, double tol, int maxit, CoreOut &out, bool confirm = true) {
-  const Types &ty = ctx->ty;
-  const LaunchSet &L = ctx->set_main.L;
+int solve_core(pcg_ctx *ctx, const Core &c, double tol, int maxit, CoreOut &out, bool confirm = true) {
+  const Types &ty = c.ty;
+  const LaunchSet &L = *c.L;
+  SysDev &D = *c.dev;
   hipStream_t s = ctx->stream;
   State init = init_state(ctx, tol, maxit, ctx->single.g_scale, !confirm);
   const bool has_eps = init.eps != 0.0;
   ctx->h_init[0] = init;
   ctx->h_init[1] = init;
-  HIPCHK(hipMemcpyAsync(ctx->single.dev.st, ctx->h_init, 2 * sizeof(State), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(D.st, ctx->h_init, 2 * sizeof(State), hipMemcpyHostToDevice, s));
   {
     int rc = enqueue_start(ctx, ty, L, has_eps);
     if (rc) return rc;
@@ -852,7 +875,7 @@ int solve_core(pcg_ctx *ctx, double tol, int maxit, CoreOut &out, bool confirm =
     }
     K = a;  // K divides rr: replacement can only fall on a chunk's first iteration
   }
-  State *hst = ctx->h_states + 2 * kSlotMain;  // two pinned readback buffers
+  State *hst = ctx->h_states + 2 * c.slot;  // two pinned readback buffers
   int base = 0;
   int restarts = 0;
   for (;;) {
@@ -870,12 +893,12 @@ int solve_core(pcg_ctx *ctx, double tol, int maxit, CoreOut &out, bool confirm =
         } else {
           len = (base % K == 0) ? K : 1;
           hipGraphExec_t g;
-          int rc = get_graph(ctx, ty, len, rep, init.eps, &g);
+          int rc = get_graph(ctx, c, len, rep, init.eps, &g);
           if (rc) return rc;
           HIPCHK(hipGraphLaunch(g, s));
         }
         base += len;
-        HIPCHK(hipMemcpyAsync(&hst[slot_next], ctx->single.dev.st, sizeof(State), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hst[slot_next], D.st, sizeof(State), hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ctx->ev[slot_next], s));
         slot_next ^= 1;
         ++inflight;
@@ -888,16 +911,16 @@ int solve_core(pcg_ctx *ctx, double tol, int maxit, CoreOut &out, bool confirm =
     }
     HIPCHK(hipStreamSynchronize(s));
     State h;
-    HIPCHK(hipMemcpy(&h, ctx->single.dev.st, sizeof(State), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&h, D.st, sizeof(State), hipMemcpyDeviceToHost));
     if (h.status == pcgk::ST_ZERO_B) {
-      HIPCHK(pcgk::launch_fill(ty.vec, ctx->single.dev.x, ctx->single.n, 0.0, s));
+      HIPCHK(pcgk::launch_fill(ty.vec, D.x, ctx->single.n, 0.0, s));
       HIPCHK(hipStreamSynchronize(s));
       out = CoreOut{};
       return PCG_OK;
     }
     HIPCHK(pcgk::launch_finalize(ty, L, s));
     HIPCHK(pcgk::launch_resid(ty, L, 0, false, true, false, s));
-    HIPCHK(hipMemcpyAsync(&hst[0], ctx->single.dev.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hst[0], D.st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const State f = hst[0];
     out.iters = f.iter;
@@ -969,6 +992,51 @@ double inner_tolerance(double cfg_inner_tol, double tol, double nb, double rn, i
 
 // FP64 iterative refinement: r64 = b - A64 x64 in FP64; inner PCG on
 // A c = r64 / ||r64|| to the inner tolerance; x64 += ||r64|| c.
+// The FP64 record of escalated inner solves: A's FP64 view, G and G^T as
+// stored, FP64 vectors and partial sums of its own (allocated at the first
+// escalation, kept until the system's storage is freed).
+int prepare_escalation(pcg_ctx *ctx) {
+  Sys &S = ctx->single;
+  if (S.blkX) return PCG_OK;
+  const int32_t n = S.n;
+  const int ga = S.dev64.A.grid, gt = S.dev.GT.grid, gb = S.dev.gB;
+  const size_t vb = align_up(8 * (size_t)n);
+  const size_t bytes = 8 * vb + align_up(8 * (size_t)ga) * 2 + align_up(16 * (size_t)gt) + align_up(8 * (size_t)gb);
+  void *blk = nullptr;
+  if (ctx->da.get(&blk, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "refinement: allocation for the FP64 inner solve failed";
+    return PCG_ENOMEM;
+  }
+  S.blkX = blk;
+  Carver c{(uint8_t *)blk};
+  SysDev &D = S.devx;
+  D = SysDev{};
+  D.A = S.dev64.A;
+  D.G = S.dev.G;
+  D.GT = S.dev.GT;
+  void **vecs[] = {&D.x, &D.r0, &D.r1, &D.d0, &D.d1, &D.q, &D.t, &D.b};
+  for (void **v : vecs) *v = c.take(8 * (size_t)n);
+  D.s = nullptr;
+  D.pg = (double *)c.take(8 * (size_t)ga);
+  D.ptr = (double *)c.take(8 * (size_t)ga);
+  D.prt = (double *)c.take(16 * (size_t)gt);
+  D.pb = (double *)c.take(8 * (size_t)gb);
+  D.n = n;
+  D.gB = gb;
+  D.st = ctx->d_states + 2 * kSlotX;
+  ctx->dir[kSlotX] = D;
+  int rc = upload_dir_entry(ctx, kSlotX);
+  if (!rc) rc = build_set(ctx, ctx->set_x, {kSlotX});
+  return rc;
+}
+
+// FP64 iterative refinement: r64 = b - A64 x64 in FP64; inner PCG on
+// A c = r64 / ||r64|| to the inner tolerance; x64 += ||r64|| c. An outer step
+// that gains less than 2x (or an inner breakdown, the stored operator not
+// being SPD in its precision) escalates: from then on the inner solves run in
+// FP64 (FP64 view of A, FP64 vectors, G as stored); escalated steps that gain
+// less than 10% end the solve (PCG_NOT_CONVERGED).
 int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
   Sys &S = ctx->single;
   const int32_t n = S.n;
@@ -982,49 +1050,74 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
   HIPCHK(hipMemcpyAsync(S.dev64.st, ctx->h_init, 2 * sizeof(State), hipMemcpyHostToDevice, s));
   HIPCHK(pcgk::launch_norm_b(t64, L64, s));
   int total_iters = 0, outer = 0, restarts = 0, status = PCG_NOT_CONVERGED;
+  bool escalated = false;
   double prev = INFINITY, relres = NAN, last_rec = NAN;
   const int max_outer = ctx->cfg.max_outer > 0 ? ctx->cfg.max_outer : 30;
   State *hst = ctx->h_states + 2 * kSlot64;
+  bool redo = false;  // repeat the step escalated (its FP32 inner solve broke down)
+  double rn = 0.0, nb = 0.0;
   for (;;) {
-    HIPCHK(pcgk::launch_resid(t64, L64, 0, false, true, false, s));
-    HIPCHK(hipMemcpyAsync(hst, S.dev64.st, sizeof(State), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const State h = *hst;
-    if (h.bb == 0.0) {
-      HIPCHK(pcgk::launch_fill(pcgk::F64, S.dev64.x, n, 0.0, s));
-      status = PCG_OK;
-      relres = 0.0;
-      break;
+    if (!redo) {
+      HIPCHK(pcgk::launch_resid(t64, L64, 0, false, true, false, s));
+      HIPCHK(hipMemcpyAsync(hst, S.dev64.st, sizeof(State), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const State h = *hst;
+      if (h.bb == 0.0) {
+        HIPCHK(pcgk::launch_fill(pcgk::F64, S.dev64.x, n, 0.0, s));
+        status = PCG_OK;
+        relres = 0.0;
+        break;
+      }
+      rn = std::sqrt(h.true_rr);
+      nb = std::sqrt(h.bb);
+      relres = rn / nb;
+      if (rn <= tol * nb) {
+        status = PCG_OK;
+        break;
+      }
+      if (!std::isfinite(rn)) {
+        status = PCG_EBREAKDOWN;
+        break;
+      }
+      if (outer >= max_outer || (escalated && rn > 0.9 * prev)) {
+        status = PCG_NOT_CONVERGED;
+        break;
+      }
+      if (!escalated && rn > 0.5 * prev) escalated = true;
+      prev = rn;
     }
-    const double rn = std::sqrt(h.true_rr), nb = std::sqrt(h.bb);
-    relres = rn / nb;
-    if (rn <= tol * nb) {
-      status = PCG_OK;
-      break;
-    }
-    if (!std::isfinite(rn)) {
-      status = PCG_EBREAKDOWN;
-      break;
-    }
-    if (outer >= max_outer || rn > 0.9 * prev) {
-      status = PCG_NOT_CONVERGED;
-      break;
-    }
-    prev = rn;
-    // inner right-hand side: r64 / ||r64|| in the vector precision
-    HIPCHK(pcgk::launch_convert(pcgk::F64, S.dev64.r0, ctx->ty.vec, S.dev.b, n, 1.0 / rn, s));
-    HIPCHK(pcgk::launch_fill(ctx->ty.vec, S.dev.x, n, 0.0, s));
+    redo = false;
+    const double eta = inner_tolerance(ctx->cfg.inner_tol, tol, nb, rn, outer);
     CoreOut co;
-    int rc = solve_core(ctx, inner_tolerance(ctx->cfg.inner_tol, tol, nb, rn, outer), maxit, co, false);
+    int rc;
+    if (escalated) {
+      if ((rc = prepare_escalation(ctx))) return rc;
+      const Core cx{Types{pcgk::F64, pcgk::F64, ctx->ty.g}, &ctx->set_x.L, &S.devx, kSlotX, &ctx->graphs_x};
+      HIPCHK(pcgk::launch_convert(pcgk::F64, S.dev64.r0, pcgk::F64, S.devx.b, n, 1.0 / rn, s));
+      HIPCHK(pcgk::launch_fill(pcgk::F64, S.devx.x, n, 0.0, s));
+      rc = solve_core(ctx, cx, eta, maxit, co, false);
+    } else {
+      // inner right-hand side: r64 / ||r64|| in the vector precision
+      HIPCHK(pcgk::launch_convert(pcgk::F64, S.dev64.r0, ctx->ty.vec, S.dev.b, n, 1.0 / rn, s));
+      HIPCHK(pcgk::launch_fill(ctx->ty.vec, S.dev.x, n, 0.0, s));
+      rc = solve_core(ctx, main_core(ctx), eta, maxit, co, false);
+    }
     if (rc) return rc;
     total_iters += co.iters;
     restarts += co.restarts;
     last_rec = co.bb > 0 ? std::sqrt(co.rr / co.bb) : 0.0;
     if (co.status == PCG_EBREAKDOWN) {
+      if (!escalated) {
+        escalated = redo = true;
+        continue;
+      }
       status = PCG_EBREAKDOWN;
       break;
     }
-    HIPCHK(pcgk::launch_refine_update(n, (double *)S.dev64.x, S.dev.x, ctx->ty.vec, rn, s));
+    if (escalated)
+      HIPCHK(pcgk::launch_refine_update(n, (double *)S.dev64.x, S.devx.x, pcgk::F64, rn, s));
+    else
+      HIPCHK(pcgk::launch_refine_update(n, (double *)S.dev64.x, S.dev.x, ctx->ty.vec, rn, s));
     ++outer;
   }
   if (res) {
@@ -1034,6 +1127,7 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
     res->restarts = restarts;
     res->relres_true = relres;
     res->relres_rec = last_rec;
+    res->escalated = escalated ? 1 : 0;
   }
   return status;
 }
@@ -1701,6 +1795,7 @@ void pcg_destroy(pcg_ctx *ctx) {
   ctx->active.clear();
   free_set(ctx, ctx->set_main);
   free_set(ctx, ctx->set_64);
+  free_set(ctx, ctx->set_x);
   free_set(ctx, ctx->set_active);
   free_set(ctx, ctx->set_done);
   free_set(ctx, ctx->set_tmp);
@@ -1774,6 +1869,7 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
   drop_graphs(ctx);
   free_set(ctx, ctx->set_main);
   free_set(ctx, ctx->set_64);
+  free_set(ctx, ctx->set_x);
   free_sys(ctx, ctx->single);
   ctx->have_a = ctx->have_g = false;
   ctx->tune.on = false;  // a new matrix: automatic layouts until tuned again
@@ -2084,6 +2180,7 @@ static int relayout(pcg_ctx *ctx) {
   drop_graphs(ctx);
   free_set(ctx, ctx->set_main);
   free_set(ctx, ctx->set_64);
+  free_set(ctx, ctx->set_x);
   free_sys(ctx, ctx->single);
   ctx->have_a = ctx->have_g = false;
   int rc = place_single_a(ctx);
@@ -2294,7 +2391,7 @@ int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, i
   if ((rc = load_vec(ctx, b, on_device, S.dev.b, ctx->ty.vec, n))) return rc;
   if ((rc = load_vec(ctx, x, on_device, S.dev.x, ctx->ty.vec, n))) return rc;
   CoreOut co;
-  if ((rc = solve_core(ctx, tol, maxit, co))) return rc;
+  if ((rc = solve_core(ctx, main_core(ctx), tol, maxit, co))) return rc;
   HIPCHK(hipEventRecord(ctx->t1, ctx->stream));
   if ((rc = store_vec(ctx, S.dev.x, ctx->ty.vec, x, on_device, n))) return rc;
   float ms = 0;

@@ -103,6 +103,7 @@ class Result(ctypes.Structure):
         ("restarts", ctypes.c_int), ("relres_true", ctypes.c_double), ("relres_rec", ctypes.c_double),
         ("t_solve_ms", ctypes.c_double), ("bytes_per_iter", ctypes.c_double),
         ("t_latency_ms", ctypes.c_double), ("t_queue_ms", ctypes.c_double),
+        ("escalated", ctypes.c_int), ("reserved_", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -262,6 +263,7 @@ class SolveOut:
     relres_rec: float
     t_solve_ms: float
     bytes_per_iter: float
+    escalated: int = 0
 
 
 class Solver:
@@ -348,7 +350,7 @@ class Solver:
         allow = (OK, NOT_CONVERGED, EBREAKDOWN) if allow_failure else (OK, NOT_CONVERGED)
         self._check(st, "pcg_solve", allow)
         return SolveOut(x, res.status, res.iters, res.outer_iters, res.restarts, res.relres_true, res.relres_rec,
-                        res.t_solve_ms, res.bytes_per_iter)
+                        res.t_solve_ms, res.bytes_per_iter, res.escalated)
 
     def sai_loss(self, W):
         """Per-probe SAI, L2 and cosine-similarity losses of the stored A and

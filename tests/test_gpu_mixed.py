@@ -211,3 +211,36 @@ def test_refinement_follows_the_emulated_outer_loop(gpu_lib, case, gdt):
     assert cut.status == ecut.status == pcg.NOT_CONVERGED and cut.outer_iters == ecut.outer == 2
     assert 0.5 <= r64 / ecut.relres_true <= 2.0
     assert abs(cut.relres_true - r64) <= 1e-3 * r64
+
+
+def test_refinement_escalates_to_fp64_inner_solves(gpu_lib):
+    """Two systems where FP32 inner solves fail (a near-singular RGG Laplacian,
+    shift 1e-6, whose FP32 refinement stalls near 1e-2 in the oracle's
+    emulation while FP64 PCG converges to 1e-8 in about 300 iterations; and
+    one with shift 1e-7 whose FP32 operator is not SPD, so the FP32 inner
+    solve breaks down): the single solve switches its inner solves to FP64
+    and reaches the tolerance, reporting the escalation, while a
+    well-conditioned system never escalates."""
+    pcg = gpu_lib
+    kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    cases = [(inputs.rgg_laplacian(5000, 3, 1e-6), 1e-8), (inputs.rgg_laplacian(8000, 3, 1e-7), 1e-6)]
+    A0 = cases[0][0]
+    emu = oracle.pcg_ir(A0, oracle.fsai_g(A0), inputs.rhs(A0.n, 3), tol=1e-8, a_dtype="f32", g_dtype="bf16",
+                        maxit=20000)
+    assert emu.status == oracle.NOT_CONVERGED  # FP32 inner solves alone stall
+    for A, tol in cases:
+        b = inputs.rhs(A.n, 3)
+        with pcg.Solver(pcg.default_config(**kw)) as s:
+            s.set_matrix(A)
+            s.build_precond(pcg.G_FSAI)
+            got = s.solve(b, tol=tol, maxit=20000)
+        r64 = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+        say(f"escalation n={A.n} tol {tol}: status {got.status} escalated {got.escalated} outer {got.outer_iters} "
+            f"inner {got.iters} fp64 relres {r64:.2e}")
+        assert got.status == pcg.OK and got.escalated == 1 and r64 <= 1.0001 * tol
+    A = inputs.poisson(3, 16, 1.0, 4)
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        got = s.solve(inputs.rhs(A.n, 4), tol=1e-10, maxit=3000)
+    assert got.status == pcg.OK and got.escalated == 0
