@@ -373,6 +373,19 @@ def section_serving(pcg, inputs, count, iters_per_step):
                     "solve = admission to completion", **split}
     main = out["loads"]["0.8"]
     out["latency_ms_p50"], out["latency_ms_p99"] = main["latency_ms_p50"], main["latency_ms_p99"]
+    # the same requests with each FSAI factored on the device at admission
+    # (g_device = 1): closed loop only
+    log("serving: closed loop, FSAI on the device at admission")
+    cfg_d = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1, g_device=1)
+    with pcg.Solver(cfg_d) as s:
+        t0 = time.perf_counter()
+        res_d = s.solve_batch(reqs, iters_per_step=iters_per_step)
+        wall_d = time.perf_counter() - t0
+    out["device_fsai_at_admission"] = {
+        "closed_loop_solves_per_s": round(count / wall_d, 2),
+        "ok": sum(1 for _, r in res_d if r["status"] == pcg.OK),
+        "note": "the scheduler thread uploads A in FP64 CSR and factors each G at admission, serially; the "
+                "host builder runs on worker threads alongside the GPU"}
     return out
 
 

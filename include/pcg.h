@@ -98,8 +98,10 @@ typedef struct {
   int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */
   int mem_budget_mb; /* device memory pool for batched / served systems, MiB (0: half the free memory at first use) */
   int layout;        /* storage of A, G, G^T: PCG_LAYOUT_AUTO (default), _CSR, _SELL or _BSR3 */
-  int g_device;      /* 1: pcg_build_precond(PCG_G_FSAI) factors on the device (one wave per row; same
-                        arithmetic as the host builder); falls back to the host for tril rows longer
+  int g_device;      /* 1: FSAI factored on the device (one wave per row; same arithmetic as the host
+                        builder, bit-identical G): in pcg_build_precond(PCG_G_FSAI), and for batched
+                        systems with FSAI at admission (the host lays out only the patterns; F16 G
+                        is built on the host). Falls back to the host builder for tril rows longer
                         than 80 or a structurally unsymmetric A. 0 (default): on the host */
   int wide_index;    /* 0 (default): a sliced matrix whose every stored column lies within 32767 of its
                         row keeps 16-bit column - row differences (half the index bytes); 1: always

@@ -531,6 +531,11 @@ struct Req {
   double *x_out = nullptr;
   APart ap;
   GPart gp;
+  // FSAI factored on the device at admission: A's diagonal positions and
+  // G_L's row pointers (the patterns of G and G^T are laid out in gp)
+  bool dev_fsai = false;
+  std::vector<int32_t> fs_dpos, fs_lrp;
+  int32_t fs_mmax = 0;
   size_t bytes = 0;
   int prep_rc = PCG_OK;
   ReqState st = RQ_PREP;
@@ -1134,9 +1139,62 @@ int refine_solve(pcg_ctx *ctx, double tol, int maxit, pcg_result *res) {
 
 // ------------------------------------------------------- batching / serving
 
+// Host part of a device FSAI for a batched system (integer work only): the
+// diagonal positions, the patterns of G_L (tril) and G = G_L^T (triu), laid
+// out for the device. False when the device builder does not apply (a row of
+// tril(A) longer than it handles, a missing diagonal, or an unsymmetric
+// pattern): the host builder is used then.
+bool prep_fsai_pattern(const pcg_config &cfg, int cus, Req &R) {
+  const int32_t n = R.n;
+  const int32_t *rp = R.a_rp.data(), *ci = R.a_ci.data();
+  std::vector<int32_t> dpos(n), lrp(n + 1, 0), grp(n + 1, 0);
+  int32_t mmax = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t d = -1;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) d = k;
+    if (d < 0) return false;
+    dpos[i] = d;
+    mmax = std::max(mmax, d - rp[i] + 1);
+    lrp[i + 1] = lrp[i] + (d - rp[i] + 1);
+    grp[i + 1] = grp[i] + (rp[i + 1] - d);
+  }
+  if (mmax > pcgk::kFsaiMaxRow || lrp[n] != grp[n]) return false;
+  for (int32_t i = 0; i < n; ++i)  // structural symmetry: (j, i) stored for every (i, j), j < i
+    for (int32_t k = rp[i]; k < dpos[i]; ++k) {
+      const int32_t j = ci[k];
+      if (!std::binary_search(ci + dpos[j], ci + rp[j + 1], i)) return false;
+    }
+  std::vector<int32_t> lci(lrp[n]), gci(grp[n]);
+  for (int32_t i = 0; i < n; ++i) {
+    std::copy(ci + rp[i], ci + dpos[i] + 1, lci.begin() + lrp[i]);
+    std::copy(ci + dpos[i], ci + rp[i + 1], gci.begin() + grp[i]);
+  }
+  GPart &P = R.gp;
+  P = GPart{};
+  P.n = n;
+  P.nnz = lrp[n];
+  P.gdt = cfg.g_dtype;
+  P.vdt = cfg.vec_dtype;
+  make_pattern(cfg, cus, n, grp.data(), gci.data(), P.gdt, P.vdt, P.G);
+  make_pattern(cfg, cus, n, lrp.data(), lci.data(), P.gdt, P.vdt, P.GT);
+  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * (size_t)P.GT.grid);
+  R.fs_dpos.swap(dpos);
+  R.fs_lrp.swap(lrp);
+  R.fs_mmax = mmax;
+  R.dev_fsai = true;
+  return true;
+}
+
 void prep_request(const pcg_config &cfg, int cus, Req &R) {
   R.ap = APart{};
   prep_a(cfg, cus, R.n, R.a_rp.data(), R.a_ci.data(), R.a_val.data(), false, R.ap);
+  if (!R.g_given && R.g_kind == PCG_G_FSAI && cfg.g_device && cfg.g_dtype != PCG_F16 &&
+      prep_fsai_pattern(cfg, cus, R)) {
+    R.bytes = R.ap.bytes + R.gp.bytes;
+    R.prep_rc = PCG_OK;
+    return;
+  }
   std::vector<int32_t> grp, gci;
   std::vector<double> gv;
   if (R.g_given) {
@@ -1267,10 +1325,53 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
   hipStream_t s = ctx->stream;
   std::vector<State> inits(2 * cand.size());
   std::vector<int> slots;
+  std::vector<void *> temps;  // device FSAI scratch, freed once the stream has passed it
+  auto fail_temps = [&](hipError_t e) {
+    (void)hipStreamSynchronize(s);
+    for (void *t : temps) ctx->da.put(t);
+    ctx->err = std::string("admission: ") + hipGetErrorString(e);
+    return PCG_EDEVICE;
+  };
   for (size_t i = 0; i < cand.size(); ++i) {
     Req &R = *cand[i];
     HIPCHK(place_a(R.ap, R.sys.blkA, R.sys, s));
     HIPCHK(place_g(R.gp, R.sys.blkG, R.sys, s));
+    if (R.dev_fsai) {  // G_L's rows on the device, written into both layouts
+      const int32_t n = R.n;
+      const int64_t nnz = (int64_t)R.a_ci.size(), nl = R.fs_lrp[n];
+      const size_t tb = align_up(4 * (size_t)(n + 1)) + align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) +
+                        align_up(8 * (size_t)std::max<int64_t>(nnz, 1)) + align_up(4 * (size_t)n) +
+                        align_up(4 * (size_t)(n + 1)) + align_up(8 * (size_t)std::max<int64_t>(nl, 1)) + align_up(8);
+      void *tmp = nullptr;
+      hipError_t e = ctx->da.get(&tmp, tb);
+      if (e != hipSuccess) return fail_temps(e);
+      temps.push_back(tmp);
+      Carver c{(uint8_t *)tmp};
+      int32_t *d_rp = (int32_t *)c.take(4 * (size_t)(n + 1));
+      int32_t *d_ci = (int32_t *)c.take(4 * (size_t)std::max<int64_t>(nnz, 1));
+      double *d_v = (double *)c.take(8 * (size_t)std::max<int64_t>(nnz, 1));
+      int32_t *d_dpos = (int32_t *)c.take(4 * (size_t)n);
+      int32_t *d_lrp = (int32_t *)c.take(4 * (size_t)(n + 1));
+      double *d_lv = (double *)c.take(8 * (size_t)std::max<int64_t>(nl, 1));
+      int32_t *d_err = (int32_t *)c.take(8);
+      auto chain = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+      };
+      chain(hipMemsetAsync((void *)R.sys.dev.G.val, 0, R.gp.G.val_bytes(), s));
+      chain(hipMemsetAsync((void *)R.sys.dev.GT.val, 0, R.gp.GT.val_bytes(), s));
+      chain(hipMemsetAsync(d_lv, 0, 8 * (size_t)std::max<int64_t>(nl, 1), s));
+      chain(hipMemsetAsync(d_err, 0, 8, s));
+      chain(h2d(d_rp, R.a_rp.data(), 4 * (size_t)(n + 1), s));
+      chain(h2d(d_ci, R.a_ci.data(), 4 * (size_t)nnz, s));
+      chain(h2d(d_v, R.a_val.data(), 8 * (size_t)nnz, s));
+      chain(h2d(d_dpos, R.fs_dpos.data(), 4 * (size_t)n, s));
+      chain(h2d(d_lrp, R.fs_lrp.data(), 4 * (size_t)(n + 1), s));
+      const int grid = (int)std::min<int64_t>(n, (int64_t)ctx->cus * 16);
+      chain(pcgk::launch_fsai_rows(d_rp, d_ci, d_v, d_dpos, d_lrp, n, R.fs_mmax, d_lv, d_err, grid, s));
+      chain(pcgk::launch_fsai_place(d_rp, d_ci, d_dpos, d_lrp, d_lv, n, 1.0, R.sys.dev.GT, R.sys.dev.G, d_err, s));
+      if (e != hipSuccess) return fail_temps(e);
+      R.sys.g_scale = 1.0;
+    }
     R.sys.dev.st = ctx->d_states + 2 * R.slot;
     ctx->dir[R.slot] = R.sys.dev;
     R.res.bytes_per_iter = layout_bytes_per_iter(R.sys.dev, R.sys.nnz_a, R.sys.nnz_g, ctx->cfg);
@@ -1332,6 +1433,7 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
     rc = enqueue_start(ctx, ctx->ty, hs.L, ctx->cfg.eps != 0.0);
   }
   HIPCHK(hipStreamSynchronize(s));  // copies done: host staging may go
+  for (void *t : temps) ctx->da.put(t);
   if (rc) return rc;
   const double t = now_ms();
   for (auto &R : cand) {
@@ -1339,6 +1441,8 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
     R->st = RQ_ACTIVE;
     R->ap = APart{};
     R->gp = GPart{};
+    std::vector<int32_t>().swap(R->fs_dpos);
+    std::vector<int32_t>().swap(R->fs_lrp);
     std::vector<int32_t>().swap(R->a_rp);
     std::vector<int32_t>().swap(R->a_ci);
     std::vector<double>().swap(R->a_val);

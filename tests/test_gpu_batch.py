@@ -250,3 +250,40 @@ def test_estimate_bytes_covers_admitted_storage(gpu_lib, refine):
             s.wait(t)
         say(f"estimate n={A.n} nnz={A.nnz} refine={refine}: used {used} estimate {est}")
         assert 0 < used <= est <= 1.4 * used + (512 << 10)
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_device_fsai_at_admission_equals_host_fsai(gpu_lib, mixed):
+    """g_device = 1 in a batch: the FSAI of each admitted system is factored
+    on the device (the host lays out only the patterns); its values equal the
+    host builder's bit for bit, so every result equals the host-FSAI batch.
+    A system whose tril rows exceed the device builder's limit falls back to
+    the host builder in the same batch."""
+    pcg = gpu_lib
+    systems = _mix(8, 7, tol=1e-8)
+    big = _random_spd_long(900, 3)
+    systems.append(dict(A=big, b=inputs.rhs(big.n, 3), tol=1e-8, maxit=3000))
+    kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1) if mixed else {}
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        ref = s.solve_batch(systems, iters_per_step=8)
+    with pcg.Solver(pcg.default_config(g_device=1, **kw)) as s:
+        got = s.solve_batch(systems, iters_per_step=8)
+    for sd, (xr, rr), (xg, rg) in zip(systems, ref, got):
+        assert rg["status"] == rr["status"] == pcg.OK, (sd["A"].n, rg["status"])
+        assert rg["iters"] == rr["iters"] and np.array_equal(xg, xr)
+
+
+def _random_spd_long(n, seed):
+    """Diagonally dominant SPD matrix with one row of n - 1 entries (its tril
+    row exceeds the device FSAI's 80-entry limit)."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    m = sp.random(n, n, density=4.0 / n, random_state=seed, data_rvs=lambda k: rng.uniform(-1, 1, k)).tolil()
+    m[n - 1, : n - 1] = rng.uniform(-1, 1, n - 1) / n
+    m = m.tocsr()
+    m = m + m.T
+    m.setdiag(0)
+    m.eliminate_zeros()
+    m = m + sp.diags(np.asarray(abs(m).sum(axis=1)).ravel() + 1.0)
+    return CSR.from_scipy(m)
