@@ -106,3 +106,24 @@ def test_autotune_keeps_forced_layout(gpu_lib):
         assert t["fmt_a"] == 0 and t["fmt_g"] == 0 and t["fmt_gt"] == 0 and t["candidates"] == 11
         got = s.solve(b, tol=1e-8, maxit=5000)
         _parity(s, got, A, b, 1e-8)
+
+
+def test_autotune_mixed_precision_with_refinement(gpu_lib):
+    """FP32 vectors and A, BF16 G, FP64 refinement: the tuner times the FP32
+    inner iteration; the refined solve still reaches 1e-10 in FP64 and
+    equals the untuned solve bit for bit when the automatic choice wins."""
+    pcg = gpu_lib
+    A = inputs.poisson(3, 32, 1.0, 15)
+    b = inputs.rhs(A.n, 15)
+    kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    with pcg.Solver(pcg.default_config(**kw)) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        pre = s.solve(b, tol=1e-10, maxit=3000)
+        t = s.autotune(10)
+        got = s.solve(b, tol=1e-10, maxit=3000)
+    say("mixed tuned:", t)
+    r64 = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+    assert got.status == pcg.OK and r64 <= 1.0001e-10 and t["candidates"] >= 5
+    if (t["layout_a"], t["layout_g"], t["grid_mult"]) == (pcg.LAYOUT_AUTO, pcg.LAYOUT_AUTO, 8):
+        assert np.array_equal(got.x, pre.x)
