@@ -445,7 +445,7 @@ def main():
     ap.add_argument("--synthetic-batch", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs single-GPU solves only (independent systems would "
+        print("bench.py measures one GPU: the library runs each solve on one GPU (independent systems would "
               "shard by request across GPUs, a single system by row slabs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     sections = [x for x in args.sections.split(",") if x in SECTIONS]
