@@ -20,6 +20,10 @@
 #include <mutex>
 #include <string>
 #include <thread>
+
+#include <sys/resource.h>
+#include <sys/syscall.h>
+#include <unistd.h>
 #include <unordered_map>
 #include <vector>
 
@@ -1215,6 +1219,9 @@ void prep_request(const pcg_config &cfg, int cus, Req &R) {
 }
 
 void worker_main(pcg_ctx *ctx) {
+  // below the scheduler thread: host preparation must not starve the thread
+  // that keeps the GPU fed (lowering one's own priority needs no privilege)
+  (void)setpriority(PRIO_PROCESS, (id_t)syscall(SYS_gettid), 10);
   for (;;) {
     std::shared_ptr<Req> R;
     {
