@@ -111,15 +111,15 @@ def cpu_baseline(A, b, gpu_iters, budget_s, gpu_solutions):
 
 # ---------------------------------------------------------------- sections
 
-def _timed_solves(pcg, torch, cfg, A, G, b_dev, steps):
+def _timed_solves(pcg, torch, cfg, A, G, b_dev, steps, tol=TOL):
     with pcg.Solver(cfg) as s:
         s.set_matrix(A)
         s.set_precond(rowptr=G[0], col=G[1], val=G[2])
-        s.solve(b_dev, tol=TOL, maxit=MAXIT)
+        s.solve(b_dev, tol=tol, maxit=MAXIT)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            r = s.solve(b_dev, tol=TOL, maxit=MAXIT)
+            r = s.solve(b_dev, tol=tol, maxit=MAXIT)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps, r
 
@@ -130,6 +130,8 @@ def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
     cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
     ms, r = _timed_solves(pcg, torch, cfg, A, G, b_dev, steps)
     ms64, r64 = _timed_solves(pcg, torch, pcg.default_config(g_dtype="bf16"), A, G, b_dev, steps)
+    cfg32 = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="f32")
+    ms32, r32 = _timed_solves(pcg, torch, cfg32, A, G, b_dev, steps, tol=1e-6)
     return {"workload": "poisson3d_128^3_sigma1_fsai, A/vectors f32, G bf16, FP64 refinement to 1e-8",
             "time_to_tol_ms": round(ms, 3), "speedup_vs_fp64": round(t_fp64_ms / ms, 3), "status": r.status,
             "inner_iters": r.iters, "outer_iters": r.outer_iters, "relres_true_fp64": r.relres_true,
@@ -138,7 +140,12 @@ def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
                             "time_to_tol_ms": round(ms64, 3), "speedup_vs_fp64": round(t_fp64_ms / ms64, 3),
                             "status": r64.status, "iters": r64.iters, "relres_true_fp64": r64.relres_true,
                             "ms_per_iter": round(ms64 / max(r64.iters, 1), 5),
-                            "alg_bytes_per_iter": r64.bytes_per_iter}}, r.x.cpu().numpy()
+                            "alg_bytes_per_iter": r64.bytes_per_iter},
+            "fp32_plain": {"workload": "same system, A/vectors/G f32, no refinement, tol 1e-6 (plain FP32 cannot "
+                                       "certify 1e-8)",
+                           "time_to_tol_ms": round(ms32, 3), "status": r32.status, "iters": r32.iters,
+                           "relres_true_fp32": r32.relres_true, "ms_per_iter": round(ms32 / max(r32.iters, 1), 5),
+                           "alg_bytes_per_iter": r32.bytes_per_iter}}, r.x.cpu().numpy()
 
 
 def section_autotune(pcg, torch, A, G, b_dev, steps, t_auto_ms):
