@@ -318,10 +318,76 @@ void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, 
   M.stored = (int64_t)M.ci.size();
 }
 
-// Lay out one matrix with values v (CSR order) times `scale` in dt.
+// The 3x3-block cover of a scalar pattern (n a multiple of 3, rows sorted):
+// each row lists the three columns of every block that any row of its block
+// row touches, in column order; src[k] is the original position of entry k,
+// or -1 for an explicit zero (which adds +0 to its row's sum; the order of the
+// original products is unchanged).
+int64_t block_cover_size(int32_t n, const int32_t *rp, const int32_t *ci) {
+  int64_t x = 0;
+  std::vector<int32_t> bc;
+  for (int32_t R = 0; R < n / 3; ++R) {
+    bc.clear();
+    for (int s = 0; s < 3; ++s)
+      for (int32_t k = rp[3 * R + s]; k < rp[3 * R + s + 1]; ++k) bc.push_back(ci[k] / 3);
+    std::sort(bc.begin(), bc.end());
+    x += 9 * (int64_t)(std::unique(bc.begin(), bc.end()) - bc.begin());
+  }
+  return x;
+}
+
+void block_cover(int32_t n, const int32_t *rp, const int32_t *ci, std::vector<int32_t> &xrp,
+                 std::vector<int32_t> &xci, std::vector<int64_t> &src) {
+  xrp.assign((size_t)n + 1, 0);
+  xci.clear();
+  src.clear();
+  std::vector<int32_t> bc;
+  for (int32_t R = 0; R < n / 3; ++R) {
+    bc.clear();
+    for (int s = 0; s < 3; ++s)
+      for (int32_t k = rp[3 * R + s]; k < rp[3 * R + s + 1]; ++k) bc.push_back(ci[k] / 3);
+    std::sort(bc.begin(), bc.end());
+    bc.erase(std::unique(bc.begin(), bc.end()), bc.end());
+    for (int s = 0; s < 3; ++s) {
+      const int32_t r = 3 * R + s;
+      int32_t k = rp[r];
+      for (int32_t B : bc)
+        for (int j = 0; j < 3; ++j) {
+          const int32_t c = 3 * B + j;
+          while (k < rp[r + 1] && ci[k] < c) ++k;
+          const bool hit = k < rp[r + 1] && ci[k] == c;
+          xci.push_back(c);
+          src.push_back(hit ? k : -1);
+        }
+      xrp[r + 1] = (int32_t)xci.size();
+    }
+  }
+}
+
+// Lay out one matrix with values v (CSR order) times `scale` in dt. blocks:
+// 0 scalar layouts only; 1 also exact 3x3 blocks; 2 also the 3x3-block cover
+// of a pattern that is not exactly blocked (explicit zeros pad it), when the
+// cover adds at most 1/8 of the nonzeros (2x with the block layout forced).
 void make_mat(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
-              int dt, double scale, int vdt, HostMat &M, bool blocks = false) {
-  make_pattern(cfg, cus, n, rp, ci, dt, vdt, M, blocks);
+              int dt, double scale, int vdt, HostMat &M, int blocks = 0) {
+  if (blocks == 2 && n > 0 && n % 3 == 0 && (cfg.layout == PCG_LAYOUT_AUTO || cfg.layout == PCG_LAYOUT_BSR3) &&
+      !pcgh::is_block3(n, rp, ci, nullptr)) {
+    const int64_t nnz = rp[n], x = block_cover_size(n, rp, ci);
+    const bool ok = x < ((int64_t)1 << 31) / 9 && (cfg.layout == PCG_LAYOUT_BSR3 ? x <= 2 * nnz : x <= nnz + nnz / 8);
+    if (ok) {
+      std::vector<int32_t> xrp, xci;
+      std::vector<int64_t> src;
+      block_cover(n, rp, ci, xrp, xci, src);
+      std::vector<double> xv(x);
+      for (int64_t k = 0; k < x; ++k) xv[k] = src[k] >= 0 ? v[src[k]] : 0.0;
+      make_mat(cfg, cus, n, xrp.data(), xci.data(), xv.data(), dt, scale, vdt, M, 1);
+      if (M.fmt == pcgk::FMT_BSR3) {
+        M.nnz = nnz;  // the matrix's own nonzeros (explicit zeros are padding)
+        return;
+      }
+    }
+  }
+  make_pattern(cfg, cus, n, rp, ci, dt, vdt, M, blocks != 0);
   std::vector<uint8_t> csr_val;
   cast_values(v, M.nnz, dt, scale, csr_val);
   if (M.fmt == pcgk::FMT_BSR3)
@@ -340,7 +406,7 @@ void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const 
   P.vdt = cfg.vec_dtype;
   P.refine = cfg.refine != 0;
   P.staging = staging;
-  make_mat(cfg, cus, n, rp, ci, v, P.adt, 1.0, P.vdt, P.A, true);
+  make_mat(cfg, cus, n, rp, ci, v, P.adt, 1.0, P.vdt, P.A, 1);
   P.gB = norm_grid(n);
   size_t b64 = 0;
   if (P.refine) {
@@ -390,8 +456,8 @@ void prep_g(const pcg_config &cfg, int cus, int32_t n, std::vector<int32_t> &grp
       P.scale = std::ldexp(1.0, 14 - e);  // max |G| scaled into [2^13, 2^14)
     }
   }
-  make_mat(cfg, cus, n, grp.data(), gci.data(), gv.data(), P.gdt, P.scale, P.vdt, P.G);
-  make_mat(cfg, cus, n, trp.data(), tci.data(), tv.data(), P.gdt, P.scale, P.vdt, P.GT);
+  make_mat(cfg, cus, n, grp.data(), gci.data(), gv.data(), P.gdt, P.scale, P.vdt, P.G, 2);
+  make_mat(cfg, cus, n, trp.data(), tci.data(), tv.data(), P.gdt, P.scale, P.vdt, P.GT, 2);
   P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * (size_t)P.GT.grid);
 }
 
@@ -2384,6 +2450,7 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
       lgs.push_back(PCG_LAYOUT_CSR);
       if (ctx->g_from_device || ctx->g_rp.empty() || use_sell(PCG_LAYOUT_SELL, n, ctx->g_rp.data()))
         lgs.push_back(PCG_LAYOUT_SELL);
+      if (!ctx->g_from_device && n % 3 == 0) lgs.push_back(PCG_LAYOUT_BSR3);  // the 3x3-block cover of G
     } else {
       las.push_back(ctx->cfg.layout);
       lgs.push_back(ctx->cfg.layout);

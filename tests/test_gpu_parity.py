@@ -383,3 +383,34 @@ def test_index_width_in_bytes_and_results(gpu_lib):
         _check(got, ref)
         xs.append(got.x)
     assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("layout,N", [("bsr3", 6), ("sell", 6), ("auto", 20)])
+def test_fsai_g_in_padded_blocks(gpu_lib, layout, N):
+    """The FSAI G of an elasticity system is not exactly 3x3-blocked (its
+    diagonal blocks are triangular); the automatic and the forced block
+    layouts store its 3x3-block cover with explicit zeros. Products equal the
+    oracle's (the zeros add +0 to each row's sum, in the same order), the
+    kernels count one 4-byte index per block, and the solve holds parity.
+    The automatic choice takes the cover where its slices pad little (the
+    20^3-node system; the 6^3 one is mostly boundary)."""
+    pcg = gpu_lib
+    A = inputs.elasticity(N, 1.0, 0.3, 5)
+    G = oracle.fsai_g(A)
+    x = np.random.default_rng(6).standard_normal(A.n)
+    b = inputs.rhs(A.n, 6)
+    say("padded-block G", layout, A.n, G.nnz)
+    with _solver(pcg, layout=layout) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        assert np.array_equal(s.matvec(pcg.OP_G, x), oracle.spmv(G, x))
+        assert np.array_equal(s.matvec(pcg.OP_GT, x), oracle.spmv_t(G, x))
+        assert np.array_equal(s.matvec(pcg.OP_MINV, x), oracle.apply_precond(G, x, 0.0))
+        got = s.solve(b, tol=1e-10, maxit=3000)
+        kt = s.time_kernels(3)
+    ib = 4.0 / 9.0 if layout != "sell" else 2.0
+    want = G.nnz * (8 + ib) + 4 * (A.n + 1) + 5 * A.n * 8
+    say(f"  G-kernel bytes {kt['bytes'][2]:.0f} (want {want:.0f})")
+    assert abs(kt["bytes"][2] - want) <= 1e-9 * want
+    ref = oracle.pcg(A, G, b, tol=1e-10, maxit=3000, delta_form=1)
+    _check(got, ref)
