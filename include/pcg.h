@@ -109,9 +109,10 @@ typedef struct {
   int autotune;      /* 1: pcg_set_precond and pcg_build_precond end with pcg_autotune(ctx, 20, NULL) */
   int cache_mb;      /* memory-side cache the single system's residency plan assumes, MiB (0: 256). The
                         matrices and iteration vectors all fit in 90% of it: all three matrices are read
-                        with ordinary loads and stay cached across iterations; else A alone if it fits
-                        in 75%; else none (nontemporal loads). Negative: always nontemporal. Batched
-                        and served systems always stream. */
+                        with ordinary loads and stay cached across iterations; else the first of A, G
+                        with G^T, G that fits in 75%; else none (nontemporal loads). Negative: always
+                        nontemporal. Batched and served systems keep theirs while the whole active
+                        set fits in 90% */
   int reserved[2];
   /* Optional device allocator (for example a framework's caching allocator),
    * used for every device allocation of the context (matrices, vectors,

@@ -817,8 +817,9 @@ double placed_bytes(const pcgk::DevCSR &M) {
 // loads, so that they stay in the memory-side cache (cfg.cache_mb, default
 // 256 MB) from one iteration to the next, and which stream past it. All three
 // when the matrices and the 8 iteration vectors fit in 90% of the cache;
-// else A alone when it fits in 75% (the vectors and G, G^T stream around
-// it); else none. The FP64 view of A under refinement always streams.
+// else the first of A alone, G and G^T together, G alone that fits in 75%
+// (the vectors and the other matrices stream around it); else none. The FP64
+// view of A under refinement always streams.
 int residency_plan(const pcg_ctx *ctx) {
   if (ctx->tune.on && ctx->tune.res >= 0) return ctx->tune.res;
   if (ctx->cfg.cache_mb < 0) return 0;
@@ -828,6 +829,8 @@ int residency_plan(const pcg_ctx *ctx) {
   const double v = 8.0 * D.n * (double)pcgk::dtype_size(ctx->ty.vec);
   if (a + g + v <= 0.9 * cap) return 7;
   if (a <= 0.75 * cap) return 1;
+  if (g <= 0.75 * cap) return 6;
+  if (placed_bytes(D.G) <= 0.75 * cap) return 2;
   return 0;
 }
 
