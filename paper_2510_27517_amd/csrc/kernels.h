@@ -71,7 +71,7 @@ inline int lds_cap(int vec_dtype) { return kLdsBytes / (int)dtype_size(vec_dtype
 enum Fmt : int32_t {
   FMT_CSR = 0,   // CSR with a row-block partition (any row lengths)
   FMT_SELL = 1,  // sliced ELL, slices of 64 rows (rows of similar length)
-  FMT_BSR3 = 2,  // sliced 3x3 blocks, slices of 21 block rows (exactly 3x3-blocked matrices)
+  FMT_BSR3 = 2,  // sliced 3x3 blocks, slices of 21 block rows (3x3-blocked matrices or block covers)
 };
 
 // A sparse matrix resident on the device.
@@ -85,8 +85,8 @@ enum Fmt : int32_t {
 //   blk[c+1] - blk[c] blocks per block row; block k of block row 21c + r has
 //   block column ci[(blk[c] + k) * 21 + r] and its row s, column j value at
 //   val[((blk[c] + k) * 3 + j) * 63 + 21 s + r] for 8-byte values, at
-//   val[9 ((blk[c] + k) * 21 + r) + 3 s + j] for 4-byte values (padding: own
-//   block row, zeros).
+//   val[9 ((blk[c] + k) * 21 + r) + 3 s + j] for 4- and 2-byte values
+//   (padding: own block row, zeros; a block cover also holds explicit zeros).
 // `grid` is the system's workgroup count for products with this matrix (a
 // multiple of 8, a function of nblk only).
 struct DevCSR {

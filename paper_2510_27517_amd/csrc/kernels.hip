@@ -1,12 +1,15 @@
 // gfx950 kernels for preconditioned CG with M^-1 = G G^T + eps I.
 //
-// Every operator product is a CSR sparse matrix-vector product ("CSR
-// stream"): a workgroup owns a block of consecutive rows whose nonzeros fit
-// in LDS; its threads load the block's column indices and values with
-// coalesced loads, gather the vector entries (through L2), and stage the
-// row products in LDS; then one thread per row adds its products in CSR
-// order. The A, G^T and G products carry the CG vector updates in their
-// gathers and epilogues, so one iteration is three launches:
+// Every operator product is a sparse matrix-vector product in one of three
+// layouts (DevCSR): sliced ELL (a wave owns slices of 64 rows, one lane per
+// row, coalesced column and value loads, 32- or 16-bit column indices),
+// sliced 3x3 blocks (one index per block), or CSR row blocks (a workgroup
+// stages the products of a block of rows in LDS, then one thread per row
+// adds them). In every layout each row's products are added left to right
+// from zero in CSR order. Matrix loads are nontemporal, or ordinary for a
+// matrix kept resident in the memory-side cache (DevCSR::temporal). The A,
+// G^T and G products carry the CG vector updates in their gathers and
+// epilogues, so one iteration is three launches:
 //   A-kernel : q = A d_i,  partials of gamma = d_i^T q;
 //   G^T-kernel: alpha_i = delta_i / gamma,
 //              r_{i+1} = r_i - alpha_i q  (formed where it is gathered),
@@ -28,9 +31,9 @@
 // kernel itself does not read.
 //
 // Work placement: each of the 8 XCDs (workgroup b runs on XCD b % 8) owns a
-// contiguous eighth of the row blocks, and its workgroups take those blocks
-// interleaved, so at any moment an XCD works on one window of consecutive
-// rows whose gathered neighbourhoods stay in that XCD's L2.
+// contiguous eighth of the slices (or row blocks), and its workgroups take
+// them interleaved, so at any moment an XCD works on one window of
+// consecutive rows whose gathered neighbourhoods stay in that XCD's L2.
 //
 // Built with floating-point contraction off: every product and sum rounds
 // separately, in the order written (rows summed left to right from zero),
@@ -291,7 +294,7 @@ __device__ __forceinline__ TACC slice_row(GLOBAL const TM *vv, GLOBAL const TI *
 // lane loads its row's entries with coalesced loads across the slice, gathers,
 // and adds the products left to right from zero, the CSR order. No LDS and no
 // barrier. The XCD slab split is the one of the row blocks.
-// UW: loads in flight per lane for rows of 32 entries or more (8 pays where a
+// UW: loads in flight per lane for rows longer than 4 entries (8 pays where a
 // row product gathers one vector and the epilogue holds few operands; under
 // the 64-register budget kernels with two gathers per entry do better with 4).
 template <typename TACC, int UW, bool NT, typename TM, typename Pre, typename Gather, typename Epi>
