@@ -279,7 +279,8 @@ int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double
  * `iters_per_step` iterations per step (0: 20). pcg_wait drives pcg_progress
  * (graph_iters iterations per step, 0: 20) until every one of `count`
  * tickets has finished, then collects them as pcg_poll does (results may be
- * NULL); timeout_s < 0 waits without limit. It returns PCG_PENDING, with no
+ * NULL; a ticket listed twice is reported twice); timeout_s < 0 waits
+ * without limit. It returns PCG_PENDING, with no
  * ticket collected, when the time runs out first, and PCG_EINVAL for an
  * unknown or already collected ticket. The per-system status is in
  * results[i].status. */
@@ -306,24 +307,29 @@ int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col
 int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, const int32_t *col,
                      const double *val, int32_t *g_rowptr, int32_t *g_col, double *g_val);
 
-/* Autotuner: times one CG iteration of the single system (its three kernels,
- * `iters` iterations on b = 1 after three warm-up iterations) for each
- * candidate storage of A (CSR row blocks, sliced ELL, 3x3 blocks: each
- * distinct format the matrix admits) and of G and G^T (CSR, sliced ELL), at
- * the configured grid, then for the best layouts at half and twice the
- * grid, then the load policy (each subset of A, G, G^T read with ordinary
- * loads and kept in the memory-side cache, besides the residency plan's
- * choice), and keeps the fastest (a candidate must beat the current best by
- * 3%).
+/* Autotuner: times one CG iteration of the single system (its three kernels
+ * on b = 1: `iters` iterations for warm-up, then the smaller of two timings
+ * of `iters` iterations) for each candidate storage of A (CSR row blocks,
+ * sliced ELL, 3x3 blocks: each distinct format the matrix admits) and of G
+ * and G^T (CSR, sliced ELL, and for a host-built G with n divisible by 3 its
+ * 3x3-block cover), at the configured grid, then for the best layouts at
+ * half and twice the grid, then the load policy (each subset of A, G, G^T
+ * read with ordinary loads and kept in the memory-side cache, besides the
+ * residency plan's choice), and keeps the fastest (a candidate must beat the
+ * current best by 3%).
  * The matrices are laid out again with the same values, so products stay
  * bit-identical; the grid changes the partial-sum order of the dot products.
- * A layout forced in the configuration is kept; only the grid is tuned then.
+ * A layout forced in the configuration is kept; only the grid and the load
+ * policy are tuned then.
  * The choice is cached per matrix signature (sizes, row-length structure, 3x3
  * blocking, storage types, options, compute units) for the process, and in
  * the file named by the environment variable PCG_TUNE_CACHE when set; a
  * cached signature is applied without search (candidates = 0). A new
  * pcg_set_matrix returns to the automatic layouts. Needs A and G set;
- * overwrites the stored right-hand side. iters <= 0: 20. */
+ * overwrites the stored right-hand side. iters <= 0: 20; above 1000:
+ * PCG_EINVAL. On an error while laying the matrices out again (out of
+ * memory, a HIP error) the context may have lost the matrix, the
+ * preconditioner or both (solves then return PCG_ESTATE): set them again. */
 typedef struct {
   int layout_a, layout_g; /* chosen PCG_LAYOUT_* (PCG_LAYOUT_AUTO: the automatic choice won) */
   int grid_mult;          /* chosen workgroups per compute unit */

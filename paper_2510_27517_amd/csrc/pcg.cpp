@@ -1068,8 +1068,6 @@ double inner_tolerance(double cfg_inner_tol, double tol, double nb, double rn, i
   return base;
 }
 
-// FP64 iterative refinement: r64 = b - A64 x64 in FP64; inner PCG on
-// A c = r64 / ||r64|| to the inner tolerance; x64 += ||r64|| c.
 // The FP64 record of escalated inner solves: A's FP64 view, G and G^T as
 // stored, FP64 vectors and partial sums of its own (allocated at the first
 // escalation, kept until the system's storage is freed).
@@ -2890,7 +2888,18 @@ static int wait_tickets(pcg_ctx *ctx, int count, const uint64_t *tickets, pcg_re
     if (rc) return rc;
     if (act == 0) std::this_thread::sleep_for(std::chrono::microseconds(200));
   }
-  for (int i = 0; i < count; ++i) (void)pcg_poll(ctx, tickets[i], results ? &results[i] : nullptr);
+  // collect every result before any ticket is dropped, so that a ticket
+  // listed twice gets its result twice
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (int i = 0; i < count; ++i) {
+    auto it = ctx->by_ticket.find(tickets[i]);
+    if (it == ctx->by_ticket.end()) {  // collected by another thread meanwhile
+      ctx->err = "pcg_wait: ticket collected by another caller";
+      return PCG_EINVAL;
+    }
+    if (results) results[i] = it->second->res;
+  }
+  for (int i = 0; i < count; ++i) ctx->by_ticket.erase(tickets[i]);
   return PCG_OK;
 }
 

@@ -451,7 +451,10 @@ class Solver:
         if st == PENDING:
             return None
         self._check(st, "pcg_wait")
-        return [(self._pending.pop(t)[1], res[i].as_dict()) for i, t in enumerate(tickets)]
+        out = [(self._pending[t][1], res[i].as_dict()) for i, t in enumerate(tickets)]
+        for t in set(tickets):
+            del self._pending[t]
+        return out
 
     def solve_batch(self, systems, iters_per_step=20):
         """Solve all systems as one batch; returns [(x, result dict)]."""

@@ -211,7 +211,8 @@ def test_batch_with_blocked_systems_equals_single(gpu_lib, refine):
 def test_wait_and_timeout(gpu_lib):
     """pcg_wait: a zero time limit returns pending with nothing collected;
     without a limit it drives the scheduler until every ticket is done and
-    the results equal those of a batch solve; a collected ticket is refused."""
+    the results equal those of a batch solve; a collected ticket is refused;
+    a ticket listed twice gets its result twice."""
     pcg = gpu_lib
     systems = _mix(6, 5)
     with pcg.Solver(pcg.default_config()) as s:
@@ -223,6 +224,11 @@ def test_wait_and_timeout(gpu_lib):
         assert s.pool_info()[1] == 0
         st = s._lib.pcg_wait(s._h, 1, (pcg.ctypes.c_uint64 * 1)(tickets[0]), None, -1.0)
         assert st == pcg.EINVAL
+        t2 = s.submit(systems[:2])
+        dup = s.wait([t2[0], t2[1], t2[0]])
+        assert s.pool_info()[1] == 0 and len(dup) == 3
+        assert dup[0][1] == dup[2][1] and np.array_equal(dup[0][0], ref[0][0])
+        assert np.array_equal(dup[1][0], ref[1][0])
     for (xr, rr), (xw, rw) in zip(ref, got):
         assert rw["status"] == rr["status"] == pcg.OK and rw["iters"] == rr["iters"]
         assert np.array_equal(xw, xr)
