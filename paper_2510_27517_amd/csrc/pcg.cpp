@@ -1353,7 +1353,11 @@ void finish_request(pcg_ctx *ctx, Req &R, int status, const State &f, int restar
   R.st = RQ_DONE;
 }
 
+int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::vector<void *> &temps);
+
 // Admit ready requests (FIFO) while the pool has room; start their solves.
+// On a device error none of this step's requests starts: each finishes with
+// the error status and its storage returns to the pool.
 int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
   std::vector<std::shared_ptr<Req>> cand;
   {
@@ -1396,14 +1400,57 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
     }
   }
   if (cand.empty()) return PCG_OK;
+  std::vector<void *> temps;  // device FSAI scratch, freed once the stream has passed it
+  const int rc = place_admitted(ctx, cand, temps);
+  if (rc) (void)hipStreamSynchronize(ctx->stream);  // on success place_admitted has synchronized
+  for (void *t : temps) ctx->da.put(t);
+  if (rc) {  // none of them starts: give back their storage and finish their tickets with the error
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &R : cand) {
+      free_sys(ctx, R->sys);
+      for (int *sl : {&R->slot, &R->slot64})
+        if (*sl >= 0) {
+          ctx->dir[*sl] = SysDev{};
+          ctx->free_slots.push_back(*sl);
+          *sl = -1;
+        }
+      State z{};
+      R->t_admit = now_ms();
+      finish_request(ctx, *R, rc, z, 0);
+    }
+    return rc;
+  }
+  const double t = now_ms();
+  for (auto &R : cand) {
+    R->t_admit = t;
+    R->st = RQ_ACTIVE;
+    R->ap = APart{};
+    R->gp = GPart{};
+    std::vector<int32_t>().swap(R->fs_dpos);
+    std::vector<int32_t>().swap(R->fs_lrp);
+    std::vector<int32_t>().swap(R->a_rp);
+    std::vector<int32_t>().swap(R->a_ci);
+    std::vector<double>().swap(R->a_val);
+    std::vector<double>().swap(R->b);
+    std::vector<double>().swap(R->x0);
+    admitted.push_back(R);
+  }
+  return PCG_OK;
+}
+
+// Place the admitted requests' matrices and vectors in their pool blocks and
+// start their solves; returns once the stream has passed every copy. Device
+// FSAI scratch goes to `temps` (the caller frees it).
+int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::vector<void *> &temps) {
   hipStream_t s = ctx->stream;
   std::vector<State> inits(2 * cand.size());
   std::vector<int> slots;
-  std::vector<void *> temps;  // device FSAI scratch, freed once the stream has passed it
   auto fail_temps = [&](hipError_t e) {
-    (void)hipStreamSynchronize(s);
-    for (void *t : temps) ctx->da.put(t);
     ctx->err = std::string("admission: ") + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return PCG_ENOMEM;
+    }
     return PCG_EDEVICE;
   };
   for (size_t i = 0; i < cand.size(); ++i) {
@@ -1506,24 +1553,8 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
   } else {
     rc = enqueue_start(ctx, ctx->ty, hs.L, ctx->cfg.eps != 0.0);
   }
-  HIPCHK(hipStreamSynchronize(s));  // copies done: host staging may go
-  for (void *t : temps) ctx->da.put(t);
   if (rc) return rc;
-  const double t = now_ms();
-  for (auto &R : cand) {
-    R->t_admit = t;
-    R->st = RQ_ACTIVE;
-    R->ap = APart{};
-    R->gp = GPart{};
-    std::vector<int32_t>().swap(R->fs_dpos);
-    std::vector<int32_t>().swap(R->fs_lrp);
-    std::vector<int32_t>().swap(R->a_rp);
-    std::vector<int32_t>().swap(R->a_ci);
-    std::vector<double>().swap(R->a_val);
-    std::vector<double>().swap(R->b);
-    std::vector<double>().swap(R->x0);
-    admitted.push_back(R);
-  }
+  HIPCHK(hipStreamSynchronize(s));  // copies done: host staging may go
   return PCG_OK;
 }
 
