@@ -261,7 +261,12 @@ int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double
  * bit for bit the one it gets alone). The context owns a device memory pool
  * (pcg_config.mem_budget_mb); a request is admitted when its storage fits and
  * refused with PCG_ENOMEM only if it exceeds the whole pool. Vector and
- * storage types are the context's; refinement is not available here.
+ * storage types are the context's; with pcg_config.refine each system runs
+ * its own FP64 refinement (its outer steps taken between scheduler steps;
+ * no escalation to FP64 inner solves here). If a device call fails while a
+ * step admits requests, none of them starts: each finishes with that error
+ * (PCG_ENOMEM for refused memory, else PCG_EDEVICE), its storage goes back
+ * to the pool, and pcg_progress returns the error.
  *
  * pcg_submit_batch copies every input and returns at once with one ticket per
  * system (nothing is queued if any system is invalid). Host worker threads
