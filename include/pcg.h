@@ -181,12 +181,15 @@ typedef struct {
 } pcg_system;
 
 /* Fills cfg with the defaults: device 0, own stream, all FP64, rr_period 50,
- * eps 0, no refinement, inner_tol 1e-4, max_outer 30, graph_iters 10,
- * grid_mult 8. */
+ * eps 0, no refinement, inner_tol 1e-6, max_outer 30, graph_iters 10,
+ * grid_mult 8, automatic layouts, no autotuning, the default allocator. */
 void pcg_config_default(pcg_config *cfg);
 
 /* Creates a context on cfg->device. Returns PCG_EDEVICE if no usable GPU,
- * PCG_EINVAL for an unsupported dtype combination. *out is NULL on failure. */
+ * PCG_EINVAL for an unsupported dtype combination (FP64 vectors need FP64 A
+ * and no refinement; FP32 vectors need FP32 A and a G of FP32, BF16 or FP16),
+ * a negative rr_period, graph_iters or mem_budget_mb, eps < 0 or NaN, or
+ * only one of alloc / free. *out is NULL on failure. */
 int pcg_create(const pcg_config *cfg, pcg_ctx **out);
 void pcg_destroy(pcg_ctx *ctx);
 
