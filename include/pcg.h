@@ -24,7 +24,9 @@
  *   - Vectors at the boundary are float64 (length n). The solution pointer x
  *     is owned by the caller; it is read as x0 and written before return.
  *   - One context serves one device and one HIP stream; calls on one context
- *     must not overlap.
+ *     must not overlap, except that pcg_submit_batch, pcg_poll and
+ *     pcg_pool_info may run on other threads while pcg_progress or pcg_wait
+ *     runs.
  */
 #ifndef PCG_H
 #define PCG_H
@@ -126,16 +128,19 @@ typedef struct {
   void *alloc_user; /* passed to alloc and free */
 } pcg_config;
 
-/* Matrix storage layouts (pcg_config.layout). Both give bit-identical
+/* Matrix storage layouts (pcg_config.layout). All give bit-identical
  * products (each row is summed left to right in CSR order).
  *  CSR:  CSR plus a partition into blocks of up to 256 rows whose products
  *        fit the workgroup's LDS; any row lengths.
  *  SELL: sliced ELL, slices of 64 consecutive rows stored column-major and
  *        padded to the slice's longest row; coalesced loads without LDS.
- *  BSR3: for A only, when it is exactly 3x3-blocked (n % 3 == 0, each block
+ *  BSR3: for a matrix that is exactly 3x3-blocked (n % 3 == 0, each block
  *        row's three rows store the same complete column triples, as in
  *        node-major 3-dof systems): slices of 21 block rows, one column index
- *        per 3x3 block; products are still summed in CSR order.
+ *        per 3x3 block; products are still summed in CSR order. G and G^T,
+ *        whose diagonal blocks are triangular, are stored as their 3x3-block
+ *        cover (explicit zeros fill the missing entries) when the cover adds
+ *        at most 1/8 of their nonzeros (at most 2x when BSR3 is forced).
  *  AUTO: BSR3 for such an A whose block padding stays within 1/8; otherwise
  *        SELL for a matrix whose padding stays within 1/8 of its nonzeros,
  *        CSR otherwise. PCG_LAYOUT_SELL (BSR3) still falls back above 2x. */
@@ -200,14 +205,16 @@ int pcg_set_matrix(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, 
 
 /* Sets G of M^-1 = G G^T + eps I (Eq. "major"), any sparsity pattern
  * (the paper's learned G uses A's full pattern, Sec. 3.2.2). The library also
- * stores G^T as CSR so both products are row-wise. n must equal A's n. */
+ * stores G^T explicitly, so both products are row-wise, each matrix in its
+ * own layout. n must equal A's n. */
 int pcg_set_precond(pcg_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
                     const double *val, int on_device);
 
-/* Builds G from the current A on the host (PCG_G_FSAI, PCG_G_FIXED,
- * PCG_G_JACOBI, PCG_G_IDENTITY, PCG_G_SEEDED with `seed`; the seed is ignored
- * by the other kinds) and sets it. A must have been set from host memory or
- * will be downloaded once. */
+/* Builds G from the current A (PCG_G_FSAI, PCG_G_FIXED, PCG_G_JACOBI,
+ * PCG_G_IDENTITY, PCG_G_SEEDED with `seed`; the seed is ignored by the other
+ * kinds) and sets it: on the host, or for PCG_G_FSAI with g_device = 1 on the
+ * device (same G bit for bit). A must have been set from host memory or will
+ * be downloaded once. */
 int pcg_build_precond(pcg_ctx *ctx, int kind, uint64_t seed);
 
 /* Solves A x = b by PCG (Algorithm 1) to ||b - A x|| <= tol ||b||, at most

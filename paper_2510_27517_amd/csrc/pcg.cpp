@@ -1868,16 +1868,16 @@ int progress(pcg_ctx *ctx, int iters) {
   return PCG_OK;
 }
 
-int copy_request(pcg_ctx *ctx, const pcg_system &S, std::shared_ptr<Req> &out) {
+int copy_request(const pcg_system &S, std::shared_ptr<Req> &out, std::string &err) {
   if (S.n <= 0 || !S.a_rowptr || !S.a_col || !S.a_val || !S.b || !(S.tol >= 0.0) || S.maxit < 0) {
-    ctx->err = "pcg_submit_batch: bad system (n, arrays, tol or maxit)";
+    err = "pcg_submit_batch: bad system (n, arrays, tol or maxit)";
     return PCG_EINVAL;
   }
   if (S.a_rowptr[S.n] != S.nnz_a) {
-    ctx->err = "pcg_submit_batch: a_rowptr[n] != nnz_a";
+    err = "pcg_submit_batch: a_rowptr[n] != nnz_a";
     return PCG_EINVAL;
   }
-  int rc = pcgh::validate_csr(S.n, S.nnz_a, S.a_rowptr, S.a_col, 1, &ctx->err);
+  int rc = pcgh::validate_csr(S.n, S.nnz_a, S.a_rowptr, S.a_col, 1, &err);
   if (rc) return rc;
   auto R = std::make_shared<Req>();
   R->n = S.n;
@@ -1890,8 +1890,11 @@ int copy_request(pcg_ctx *ctx, const pcg_system &S, std::shared_ptr<Req> &out) {
   R->tol = S.tol;
   R->maxit = S.maxit;
   if (S.g_rowptr) {
-    if (!S.g_col || !S.g_val || S.g_rowptr[S.n] != S.nnz_g) return PCG_EINVAL;
-    rc = pcgh::validate_csr(S.n, S.nnz_g, S.g_rowptr, S.g_col, 0, &ctx->err);
+    if (!S.g_col || !S.g_val || S.g_rowptr[S.n] != S.nnz_g) {
+      err = "pcg_submit_batch: bad preconditioner arrays (g_col, g_val, or g_rowptr[n] != nnz_g)";
+      return PCG_EINVAL;
+    }
+    rc = pcgh::validate_csr(S.n, S.nnz_g, S.g_rowptr, S.g_col, 0, &err);
     if (rc) return rc;
     R->g_given = true;
     R->g_rp.assign(S.g_rowptr, S.g_rowptr + S.n + 1);
@@ -1899,7 +1902,7 @@ int copy_request(pcg_ctx *ctx, const pcg_system &S, std::shared_ptr<Req> &out) {
     R->g_val.assign(S.g_val, S.g_val + S.nnz_g);
   } else {
     if (pcgh::g_nnz(S.g_kind, S.n, S.a_rowptr, S.a_col) < 0) {
-      ctx->err = "pcg_submit_batch: unknown preconditioner kind";
+      err = "pcg_submit_batch: unknown preconditioner kind";
       return PCG_EINVAL;
     }
     R->g_kind = S.g_kind;
@@ -2852,8 +2855,13 @@ int pcg_submit_batch(pcg_ctx *ctx, int count, const pcg_system *sys, uint64_t *t
   if (count < 0 || (count > 0 && (!sys || !tickets))) return PCG_EINVAL;
   std::vector<std::shared_ptr<Req>> reqs(count);
   for (int i = 0; i < count; ++i) {
-    int rc = copy_request(ctx, sys[i], reqs[i]);
-    if (rc) return rc;  // nothing queued on error
+    std::string err;
+    const int rc = copy_request(sys[i], reqs[i], err);
+    if (rc) {  // nothing queued on error
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->err = err;
+      return rc;
+    }
   }
   const double t = now_ms();
   {

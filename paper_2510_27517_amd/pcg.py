@@ -305,8 +305,8 @@ class Solver:
 
     def _check(self, st, what, allow=(OK,)):
         if st not in allow:
-            msg = self._lib.pcg_last_error(self._h).decode()
-            raise PCGError(st, f"{what}: {msg or self._lib.pcg_strerror(st).decode()}")
+            msg = self._lib.pcg_last_error(self._h).decode() or self._lib.pcg_strerror(st).decode()
+            raise PCGError(st, msg if msg.startswith(what + ":") else f"{what}: {msg}")
         return st
 
     def _csr_args(self, rowptr, col, val):

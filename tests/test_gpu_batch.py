@@ -293,3 +293,26 @@ def _random_spd_long(n, seed):
     m.eliminate_zeros()
     m = m + sp.diags(np.asarray(abs(m).sum(axis=1)).ravel() + 1.0)
     return CSR.from_scipy(m)
+
+
+def test_submit_rejects_bad_systems(gpu_lib):
+    """pcg_submit_batch checks every system before queueing any: a column out
+    of range, or G arrays that disagree with nnz_g, give PCG_EINVAL with a
+    message from the submission, nothing is queued, and the context then
+    solves a good system."""
+    pcg = gpu_lib
+    A = inputs.poisson(2, 8, 0.5, 0)
+    good = dict(A=A, b=inputs.rhs(A.n, 0), tol=1e-8, maxit=500)
+    col = A.col.copy()
+    col[-1] = A.n
+    bad_a = dict(good, A=inputs.CSR(A.rowptr, col, A.val))
+    bad_g = dict(good, G=inputs.CSR(A.rowptr, A.col[:-1].copy(), A.val[:-1].copy()))
+    with pcg.Solver(pcg.default_config(mem_budget_mb=64)) as s:
+        for bad in (bad_a, bad_g):
+            with pytest.raises(pcg.PCGError) as e:
+                s.submit([good, bad])
+            say("rejected:", e.value)
+            assert e.value.status == pcg.EINVAL and "pcg_submit_batch" in str(e.value)
+            assert s.progress(1) == (0, 0)
+        (x, r), = s.solve_batch([good])
+    assert r["status"] == pcg.OK and r["relres_true"] <= 1e-8
