@@ -297,14 +297,16 @@ __device__ __forceinline__ TACC slice_row(GLOBAL const TM *vv, GLOBAL const TI *
 // UW: loads in flight per lane for rows longer than 4 entries (8 pays where a
 // row product gathers one vector and the epilogue holds few operands; under
 // the 64-register budget kernels with two gathers per entry do better with 4).
-template <typename TACC, int UW, bool NT, typename TM, typename Pre, typename Gather, typename Epi>
+// REV: each die walks its range of slices from the top down.
+template <typename TACC, int UW, bool NT, bool REV, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi) {
   constexpr int NW = kBlock / 64;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int W = G >> 3, x = l & 7, w = l >> 3;
   const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
-  for (int c = s0 + w * NW + wv; c < s1; c += W * NW) {
+  for (int k = w * NW + wv; k < s1 - s0; k += W * NW) {
+    const int c = REV ? s1 - 1 - k : s0 + k;
     const int o0 = M.blk[c], wd = M.blk[c + 1] - o0;
     const int row = c * kSliceRows + lane;
     const bool has = row < M.n;
@@ -379,11 +381,11 @@ __device__ __forceinline__ void bsr_rows(const Mat<TM> &M, int l, int G, Pre pre
 
 // All rows of this workgroup (local index l of the system's G workgroups),
 // in any layout, with the matrix's load policy.
-template <typename TACC, int UW, bool NT, typename TM, typename Pre, typename Gather, typename Epi>
+template <typename TACC, int UW, bool NT, bool REV, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void for_rows_as(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather,
                                             Epi epi) {
   if (M.fmt == FMT_SELL) {
-    sell_rows<TACC, UW, NT>(M, l, G, pre, gather, epi);
+    sell_rows<TACC, UW, NT, REV>(M, l, G, pre, gather, epi);
   } else if (M.fmt == FMT_BSR3) {
     bsr_rows<TACC, NT>(M, l, G, pre, gather, epi);
   } else {
@@ -392,12 +394,12 @@ __device__ __forceinline__ void for_rows_as(const Mat<TM> &M, int l, int G, TACC
   }
 }
 
-template <typename TACC, int UW = 4, typename TM, typename Pre, typename Gather, typename Epi>
+template <typename TACC, int UW = 4, bool REV = false, typename TM, typename Pre, typename Gather, typename Epi>
 __device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather, Epi epi) {
   if (M.temporal)
-    for_rows_as<TACC, UW, false>(M, l, G, lds, pre, gather, epi);
+    for_rows_as<TACC, UW, false, REV>(M, l, G, lds, pre, gather, epi);
   else
-    for_rows_as<TACC, UW, true>(M, l, G, lds, pre, gather, epi);
+    for_rows_as<TACC, UW, true, REV>(M, l, G, lds, pre, gather, epi);
 }
 
 template <int NV>
@@ -539,8 +541,10 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
   GLOBAL const TV *__restrict__ src = gl((const TV *)((((mode == 1) ? it + 1 : it) & 1) ? D.r1 : D.r0));
   GLOBAL TV *__restrict__ dst = gl((TV *)(((it + 1) & 1) ? D.r1 : D.r0));
   double part[2] = {0.0, 0.0};
+  // G^T rows gather ahead of themselves (upper triangle): walking the slices
+  // down makes the gathered lines ones that the streams already brought in
   if (mode == 0) {
-    for_rows<TV>(
+    for_rows<TV, 4, true>(
         GT, m.y, D.GT.grid, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
         [&](int j) -> TV { return src[j] - al * q[j]; },
         [&](int row, TV sum, const RowVals<TV> &pv) {
@@ -551,7 +555,7 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
           part[1] += (double)sum * (double)sum;
         });
   } else {
-    for_rows<TV>(
+    for_rows<TV, 4, true>(
         GT, m.y, D.GT.grid, lds, [&](int row) { return RowVals<TV>{src[row], (TV)0, (TV)0}; },
         [&](int j) -> TV { return src[j]; },
         [&](int row, TV sum, const RowVals<TV> &pv) {
