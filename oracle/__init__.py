@@ -421,7 +421,9 @@ def identity(n: int) -> Mat:
 
 
 def diag_inv_sqrt(A) -> Mat:
-    """G = D^-1/2 (Jacobi: M^-1 = D^-1)."""
+    """G = D^-1/2 (Jacobi: M^-1 = D^-1), D the stored diagonal of A. Pinned
+    to 1/2 on constant 2D Poisson (A_ii = 4) and to the dense diagonal of a
+    variable-coefficient matrix."""
     A = _mat(A)
     d = np.zeros(A.n)
     for i in range(A.n):

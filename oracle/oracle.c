@@ -16,7 +16,11 @@
  * the paper's two-hop locality formula for the apply (Eq. "spai-locality"),
  * finite termination, one-iteration convergence with G = L^-T, monotone
  * A-norm error, agreement with scipy's CG for G = I and G = D^-1/2,
- * power-of-two scale invariance, and the FSAI invariants.
+ * power-of-two scale invariance, and the FSAI invariants. The FP32 products
+ * (or_spmv_f32, or_spmv_t_f32) are pinned bit for bit against a float32
+ * brute force that adds each row's products one at a time in numpy binary32
+ * scalars, on data whose sums change with the order or with a wider
+ * accumulator, and exactly on small integers.
  */
 #include <math.h>
 #include <stdint.h>

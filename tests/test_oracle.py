@@ -655,3 +655,120 @@ def test_ir_edge_cases():
     H = inputs.poisson(2, 40, 2.0, 8)
     hb = oracle.pcg_ir(H, oracle.fsai_g(H), inputs.rhs(H.n, 8), tol=1e-12, a_dtype="bf16")
     assert hb.status == oracle.EBREAKDOWN and np.all(hb.x == 0)
+
+
+# -------------------------------------------- FP32 products (mixed-precision path)
+
+def _f32_rows_brute(d32, x32, reverse=False, wide=False):
+    """y_i = sum over the stored columns j of row i of f32(d_ij * x_j), added
+    one at a time from 0 in float32 (numpy float32 scalars: every product and
+    sum rounded to binary32), columns ascending (descending with reverse);
+    wide: products exact and sums in float64, rounded to float32 once (a
+    wrong accumulator the pins must reject)."""
+    n, m = d32.shape
+    y = np.zeros(n, np.float32)
+    for i in range(n):
+        cols = [j for j in range(m) if d32[i, j] != 0]
+        if reverse:
+            cols = cols[::-1]
+        if wide:
+            y[i] = np.float32(sum(float(d32[i, j]) * float(x32[j]) for j in cols))
+            continue
+        s = np.float32(0.0)
+        for j in cols:
+            s = np.float32(s + np.float32(d32[i, j] * x32[j]))
+        y[i] = s
+    return y
+
+
+def _mixed_scale_csr(n, density, seed):
+    """Random pattern with values spread over many binades, so that float32
+    sums depend on the order and the accumulator width."""
+    A, d = _random_csr(n, n, density, seed)
+    rng = np.random.default_rng(seed + 7)
+    scale = np.exp2(rng.integers(-12, 13, A.nnz))
+    A.val[:] = A.val * scale
+    return A
+
+
+@pytest.mark.parametrize("n,density,seed", [(1, 1.0, 0), (40, 0.3, 1), (120, 0.15, 2)])
+def test_spmv_f32_matches_float32_brute_force(n, density, seed):
+    A = _mixed_scale_csr(n, density, seed)
+    v32 = A.val.astype(np.float32)
+    d32 = CSR(A.rowptr, A.col, v32.astype(np.float64)).to_dense().astype(np.float32)
+    x32 = (np.random.default_rng(seed + 50).standard_normal(n) * 3.0).astype(np.float32)
+    got = oracle.spmv_f32(A.rowptr, A.col, v32, x32)
+    assert got.dtype == np.float32
+    ref = _f32_rows_brute(d32, x32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    if n > 1:  # the data tells the wrong orders and accumulators apart
+        assert not np.array_equal(ref, _f32_rows_brute(d32, x32, reverse=True))
+        assert not np.array_equal(ref, _f32_rows_brute(d32, x32, wide=True))
+
+
+@pytest.mark.parametrize("n,density,seed", [(1, 1.0, 3), (40, 0.3, 4), (120, 0.15, 5)])
+def test_spmv_t_f32_matches_float32_brute_force(n, density, seed):
+    """(G^T x)_j = sum over i ascending of f32(G_ij x_i), in float32: the order
+    in which scattering the rows of G delivers the terms of column j."""
+    G = _mixed_scale_csr(n, density, seed)
+    v32 = G.val.astype(np.float32)
+    d32 = CSR(G.rowptr, G.col, v32.astype(np.float64)).to_dense().astype(np.float32)
+    x32 = (np.random.default_rng(seed + 60).standard_normal(n) * 3.0).astype(np.float32)
+    got = oracle.spmv_t_f32(G.rowptr, G.col, v32, x32)
+    assert got.dtype == np.float32
+    ref = _f32_rows_brute(np.ascontiguousarray(d32.T), x32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    if n > 1:
+        assert not np.array_equal(ref, _f32_rows_brute(np.ascontiguousarray(d32.T), x32, reverse=True))
+        assert not np.array_equal(ref, _f32_rows_brute(np.ascontiguousarray(d32.T), x32, wide=True))
+
+
+def test_spmv_f32_exact_on_small_integers():
+    """Small integers: every product and partial sum is below 2^24, so float32
+    arithmetic is exact in any order and equals the integer product."""
+    A, _ = _random_csr(60, 60, 0.25, 11)
+    A.val[:] = np.round(A.val * 50)
+    d = A.to_dense()
+    x = np.arange(60, dtype=np.float64) - 25
+    v32, x32 = A.val.astype(np.float32), x.astype(np.float32)
+    assert np.array_equal(oracle.spmv_f32(A.rowptr, A.col, v32, x32).astype(np.float64), d @ x)
+    assert np.array_equal(oracle.spmv_t_f32(A.rowptr, A.col, v32, x32).astype(np.float64), d.T @ x)
+
+
+def test_spmv_f32_rounds_each_operation_to_binary32():
+    """One row [2^24, 1, 1] times ones: float32 adds lose each 1 (2^24 + 1 is a
+    tie rounded to even), so the sum stays 2^24; an FP64 accumulator gives
+    2^24 + 2. The reversed order gives 1 + 1 + 2^24 = 2^24 + 2 exactly."""
+    rp, ci = np.array([0, 3], np.int32), np.array([0, 1, 2], np.int32)
+    v = np.array([2.0 ** 24, 1.0, 1.0], np.float32)
+    y = oracle.spmv_f32(rp, ci, v, np.ones(3, np.float32))
+    assert float(y[0]) == 2.0 ** 24
+    # transpose: column 0 of [[1],[1],[2^24]] (rows 0, 1, 2 scattered in order)
+    rp3, ci3 = np.array([0, 1, 2, 3], np.int32), np.zeros(3, np.int32)
+    vt = np.array([1.0, 1.0, 2.0 ** 24], np.float32)
+    yt = oracle.spmv_t_f32(rp3, ci3, vt, np.ones(3, np.float32))
+    assert float(yt[0]) == 2.0 ** 24 + 2.0
+    vt2 = np.array([2.0 ** 24, 1.0, 1.0], np.float32)
+    assert float(oracle.spmv_t_f32(rp3, ci3, vt2, np.ones(3, np.float32))[0]) == 2.0 ** 24
+
+
+# ------------------------------------------------------- Jacobi factor D^-1/2
+
+def test_diag_inv_sqrt_closed_form_constant_poisson():
+    """Constant 2D Poisson has A_ii = 4, so G = D^-1/2 = I / 2 exactly."""
+    A = inputs.poisson(2, 9)
+    G = oracle.diag_inv_sqrt(A)
+    assert np.array_equal(G.rowptr, np.arange(A.n + 1)) and np.array_equal(G.col, np.arange(A.n))
+    assert np.all(G.val == 0.5)
+
+
+def test_diag_inv_sqrt_matches_dense_diagonal():
+    """Variable coefficients: G = diag(1 / sqrt(A_ii)) of the dense matrix, and
+    G A G has a unit diagonal."""
+    A = inputs.poisson(3, 5, sigma=1.0, seed=4)
+    Ad = A.to_dense()
+    G = oracle.diag_inv_sqrt(A)
+    Gd = CSR(G.rowptr, G.col, G.val).to_dense()
+    assert np.array_equal(np.diag(Gd), 1.0 / np.sqrt(np.diag(Ad)))
+    assert np.count_nonzero(Gd - np.diag(np.diag(Gd))) == 0
+    assert np.allclose(np.diag(Gd @ Ad @ Gd), 1.0, rtol=4e-16, atol=0)
