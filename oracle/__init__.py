@@ -8,7 +8,8 @@ arrays and shares no code with the HIP path.
 
 Every function names the passage it follows; see ``oracle.c`` for the
 readings of Algorithm 1 (replacement branch, stopping rule, restart on a
-failed true-residual check). ``pcg_ir`` emulates the mixed-precision solve
+failed true-residual check) and of the inner products (exact sums of
+products rounded once, so that no summation order is implied). ``pcg_ir`` emulates the mixed-precision solve
 (FP64 iterative refinement around a PCG on rounded operands) in FP64.
 """
 from __future__ import annotations
@@ -71,6 +72,8 @@ def _load():
     lib.or_spmv_t_f32.argtypes = [i32, i32, P, P, P, P, P]
     lib.or_dot.restype = ctypes.c_double
     lib.or_dot.argtypes = [i32, P, P]
+    lib.or_dot_threads.restype = ctypes.c_double
+    lib.or_dot_threads.argtypes = [i32, P, P, ctypes.c_int]
     lib.or_apply_precond.argtypes = [i32, P, P, P, ctypes.c_double, P, P]
     lib.or_pcg.restype = ctypes.c_int
     lib.or_pcg.argtypes = [i32, P, P, P, P, P, P, P, P, ctypes.POINTER(_Opts), ctypes.POINTER(_Res), P, P]
@@ -160,10 +163,12 @@ def transpose(G, ncols: int | None = None) -> Mat:
     return Mat(trp, tci, tv)
 
 
-def dot(a, b) -> float:
+def dot(a, b, threads: int = 1) -> float:
+    """sum_i a_i b_i computed exactly and rounded once to the nearest double
+    (ties to even), the same for every thread count."""
     a = _c(a, np.float64)
     b = _c(b, np.float64)
-    return float(_load().or_dot(a.shape[0], _p(a), _p(b)))
+    return float(_load().or_dot_threads(a.shape[0], _p(a), _p(b), int(threads)))
 
 
 def apply_precond(G, r, eps: float = 0.0) -> np.ndarray:

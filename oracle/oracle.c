@@ -11,6 +11,10 @@
  *
  * Build with floating-point contraction off (-ffp-contract=off), so each
  * product and each sum is rounded on its own, in the order written here.
+ * Inner products (dot products and norms) are the exception: each is the
+ * exact sum of its products, rounded once (the reading is stated where the
+ * accumulator is defined), so they do not depend on the order or on the
+ * thread count.
  *
  * Pins (tests/test_oracle.py): dense brute-force matvec, adjoint identity,
  * the paper's two-hop locality formula for the apply (Eq. "spai-locality"),
@@ -20,7 +24,11 @@
  * (or_spmv_f32, or_spmv_t_f32) are pinned bit for bit against a float32
  * brute force that adds each row's products one at a time in numpy binary32
  * scalars, on data whose sums change with the order or with a wider
- * accumulator, and exactly on small integers.
+ * accumulator, and exactly on small integers. The exact inner product is
+ * pinned against rational arithmetic (Python's Fraction) on cancelling,
+ * wide-range, subnormal and overflowing data, ties to even and a sticky bit,
+ * a subnormal result that a double rounding would get wrong, and for
+ * independence from order and thread count.
  */
 #include <math.h>
 #include <stdint.h>
@@ -93,20 +101,162 @@ void or_transpose(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t
   free(pos);
 }
 
+/* ------------------------------------------------- exact inner products */
+
+/*
+ * Inner products are the exact value of sum_i a_i b_i rounded once to the
+ * nearest double, ties to even (a reading: the paper fixes neither the
+ * precision nor the order of its dot products, and the correctly rounded
+ * value is the one that does not depend on the order). Every finite double
+ * is m 2^e with an integer 0 <= m < 2^53 and -1074 <= e <= 971, so every
+ * product of two is an integer below 2^106 times 2^E, -2148 <= E <= 1942.
+ * The accumulator is a fixed-point integer whose bit k weighs
+ * 2^(k + XA_LSB): limb i holds the 32 bits [32 i, 32 i + 32) as a signed
+ * 64-bit count, so each product adds at most 2^33 to a limb and 2^29
+ * products fit before carries are propagated. Products with an infinite or
+ * NaN factor are tracked apart and give the IEEE result of the sum (NaN,
+ * +Inf or -Inf); finite factors are accumulated exactly even where their
+ * product exceeds the largest double.
+ */
+#define XA_LSB (-2304)
+#define XA_LIMBS 140 /* weights 2^-2304 .. 2^2175 */
+#define XA_SPAN (1L << 29)
+
+typedef struct {
+  int64_t d[XA_LIMBS];
+  int64_t adds;
+  int nan, pinf, ninf;
+} xacc;
+
+static void xacc_init(xacc *a) { memset(a, 0, sizeof(*a)); }
+
+/* carries: every limb but the top in [0, 2^32); the top keeps the sign */
+static void xacc_carry(xacc *a) {
+  for (int i = 0; i < XA_LIMBS - 1; ++i) {
+    const int64_t c = a->d[i] >> 32; /* floor(d / 2^32) (gcc: arithmetic shift) */
+    a->d[i] -= c * ((int64_t)1 << 32);
+    a->d[i + 1] += c;
+  }
+  a->adds = 0;
+}
+
+/* v = (-1)^sign m 2^e for a finite double */
+static void split_double(double v, int *sign, uint64_t *m, int *e) {
+  uint64_t u;
+  memcpy(&u, &v, 8);
+  *sign = (int)(u >> 63);
+  const int ex = (int)((u >> 52) & 0x7FF);
+  const uint64_t fr = u & (((uint64_t)1 << 52) - 1);
+  if (ex == 0) {
+    *m = fr;
+    *e = -1074;
+  } else {
+    *m = fr | ((uint64_t)1 << 52);
+    *e = ex - 1075;
+  }
+}
+
+/* a += x y, exactly (an infinite or NaN factor: the IEEE product) */
+static void xacc_add_prod(xacc *a, double x, double y) {
+  if (!isfinite(x) || !isfinite(y)) {
+    const double p = x * y;
+    if (isnan(p)) a->nan = 1;
+    else if (p > 0) a->pinf = 1;
+    else a->ninf = 1;
+    return;
+  }
+  int sx, sy, ex, ey;
+  uint64_t mx, my;
+  split_double(x, &sx, &mx, &ex);
+  split_double(y, &sy, &my, &ey);
+  if (mx == 0 || my == 0) return;
+  const unsigned __int128 P = (unsigned __int128)mx * my; /* < 2^106 */
+  const int off = ex + ey - XA_LSB;                        /* >= 156 */
+  const int li = off / 32, sh = off % 32;
+  const int64_t sg = (sx ^ sy) ? -1 : 1;
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t c = (uint64_t)(P >> (32 * k)) & 0xFFFFFFFFu; /* digit k of P */
+    const uint64_t w = c << sh;                                 /* < 2^63 */
+    a->d[li + k] += sg * (int64_t)(w & 0xFFFFFFFFu);
+    a->d[li + k + 1] += sg * (int64_t)(w >> 32);
+  }
+  if (++a->adds >= XA_SPAN) xacc_carry(a);
+}
+
+/* a += b, exactly */
+static void xacc_merge(xacc *a, const xacc *b) {
+  xacc_carry(a);
+  xacc t = *b;
+  xacc_carry(&t);
+  for (int i = 0; i < XA_LIMBS; ++i) a->d[i] += t.d[i];
+  a->nan |= t.nan;
+  a->pinf |= t.pinf;
+  a->ninf |= t.ninf;
+  xacc_carry(a);
+}
+
+/* the accumulated value rounded to the nearest double, ties to even */
+static double xacc_round(const xacc *in) {
+  if (in->nan || (in->pinf && in->ninf)) return NAN;
+  if (in->pinf) return INFINITY;
+  if (in->ninf) return -INFINITY;
+  xacc a = *in;
+  xacc_carry(&a);
+  double sign = 1.0;
+  if (a.d[XA_LIMBS - 1] < 0) { /* magnitude of a negative value */
+    for (int i = 0; i < XA_LIMBS; ++i) a.d[i] = -a.d[i];
+    xacc_carry(&a);
+    sign = -1.0;
+  }
+  int t = XA_LIMBS - 1;
+  while (t >= 0 && a.d[t] == 0) --t;
+  if (t < 0) return 0.0; /* exactly zero */
+  /* the top three limbs as one integer V, its weight 2^E, and whether any
+   * lower bit is set (sticky); the top limb is nonzero, so V >= 2^64 */
+  unsigned __int128 V = 0;
+  for (int i = t; i >= t - 2; --i) V = (V << 32) | (uint64_t)(i >= 0 ? a.d[i] : 0);
+  const int E = 32 * (t - 2) + XA_LSB;
+  int sticky = 0;
+  for (int i = 0; i < t - 2; ++i) sticky |= a.d[i] != 0;
+  int L = 0; /* bit length of V */
+  for (unsigned __int128 w = V; w; w >>= 1) ++L;
+  if (L + E - 1 > 1023) return sign * INFINITY;
+  int lsb = L + E - 53; /* weight of the last kept bit */
+  if (lsb < -1074) lsb = -1074;
+  const int shift = lsb - E; /* >= L - 53 >= 12 */
+  uint64_t mant = (uint64_t)(V >> shift);
+  const unsigned __int128 rem = V & ((((unsigned __int128)1) << shift) - 1);
+  const unsigned __int128 half = ((unsigned __int128)1) << (shift - 1);
+  if (rem > half || (rem == half && (sticky || (mant & 1)))) ++mant;
+  return sign * ldexp((double)mant, lsb); /* mant <= 2^53: exact, or overflow to Inf */
+}
+
 /* ------------------------------------------------------------ vectors */
 
+/* sum_i a_i b_i, exact, rounded once; threads only split the work (each
+ * adds its part exactly, the parts are merged exactly), so the result is the
+ * same for every thread count */
 static double dot(int32_t n, const double *a, const double *b, int threads) {
-  double s = 0.0;
+  xacc acc;
+  xacc_init(&acc);
   if (threads <= 1) {
-    for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
-    return s;
+    for (int32_t i = 0; i < n; ++i) xacc_add_prod(&acc, a[i], b[i]);
+    return xacc_round(&acc);
   }
-#pragma omp parallel for num_threads(threads) reduction(+ : s) schedule(static)
-  for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
-  return s;
+#pragma omp parallel num_threads(threads)
+  {
+    xacc part;
+    xacc_init(&part);
+#pragma omp for schedule(static)
+    for (int32_t i = 0; i < n; ++i) xacc_add_prod(&part, a[i], b[i]);
+#pragma omp critical
+    xacc_merge(&acc, &part);
+  }
+  return xacc_round(&acc);
 }
 
 double or_dot(int32_t n, const double *a, const double *b) { return dot(n, a, b, 1); }
+double or_dot_threads(int32_t n, const double *a, const double *b, int threads) { return dot(n, a, b, threads); }
 
 /* s = G (G^T r) + eps r, with t = G^T r returned too (Eq. "major"). */
 static void apply_precond(int32_t n, const int32_t *grp, const int32_t *gci, const double *gv, double eps,

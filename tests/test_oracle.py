@@ -772,3 +772,86 @@ def test_diag_inv_sqrt_matches_dense_diagonal():
     assert np.array_equal(np.diag(Gd), 1.0 / np.sqrt(np.diag(Ad)))
     assert np.count_nonzero(Gd - np.diag(np.diag(Gd))) == 0
     assert np.allclose(np.diag(Gd @ Ad @ Gd), 1.0, rtol=4e-16, atol=0)
+
+
+# ------------------------------------------- exact inner products (reading)
+
+def _exact_dot(a, b):
+    """The exact sum of products in rational arithmetic, rounded once to the
+    nearest double with ties to even (Python's int / int true division)."""
+    return float(sum((Fraction(float(x)) * Fraction(float(y)) for x, y in zip(a, b)), Fraction(0)))
+
+
+def _same_bits(x, y):
+    return np.array([x]).view(np.uint64)[0] == np.array([y]).view(np.uint64)[0]
+
+
+@pytest.mark.parametrize("kind", ["normal", "cancel", "binades", "tiny", "huge"])
+def test_dot_is_the_exact_value_rounded_once(kind):
+    rng = np.random.default_rng({"normal": 1, "cancel": 2, "binades": 3, "tiny": 4, "huge": 5}[kind])
+    for n in (1, 2, 3, 17, 200):
+        a, b = rng.standard_normal(n), rng.standard_normal(n)
+        if kind == "cancel":  # pairs that cancel up to a small remainder
+            a = np.concatenate([a, -a * (1 + 2.0 ** -40 * rng.standard_normal(n))])
+            b = np.concatenate([b, b])
+        elif kind == "binades":
+            a = a * np.exp2(rng.integers(-300, 300, n))
+        elif kind == "tiny":  # products in the subnormal range and below
+            a = a * 2.0 ** -540
+            b = b * 2.0 ** -530
+        elif kind == "huge":  # products beyond the largest double that cancel
+            a = np.concatenate([a * 2.0 ** 600, -a * 2.0 ** 600])
+            b = np.concatenate([b * 2.0 ** 500, b * 2.0 ** 500 + 2.0 ** 380])
+        got = oracle.dot(a, b)
+        assert _same_bits(got, _exact_dot(a, b)), (n, got, _exact_dot(a, b))
+
+
+def test_dot_ties_round_to_even_and_order_does_not_matter():
+    u = 2.0 ** -53
+    # 1 + u lies halfway between 1 and 1 + 2u: the even neighbour is 1
+    assert oracle.dot([1.0, u], [1.0, 1.0]) == 1.0
+    # (1 + 2u) + u lies halfway between 1 + 2u and 1 + 4u: the even one is 1 + 4u
+    assert oracle.dot([1.0 + 2 * u, u], [1.0, 1.0]) == 1.0 + 4 * u
+    # a tie broken by a far smaller term (sticky bit): rounds up
+    assert oracle.dot([1.0, u, 2.0 ** -200], [1.0, 1.0, 1.0]) == 1.0 + 2 * u
+    # a subnormal result is rounded once at the subnormal quantum: 2^-1074
+    # (1.5 - 2^-60) gives 2^-1074 (rounding first to 53 bits would make it
+    # the tie 1.5 2^-1074 and then round it to even, 2^-1073)
+    t = 2.0 ** -537
+    assert oracle.dot([t, t, -(2.0 ** -600)], [t, 2.0 ** -538, 2.0 ** -534]) == 2.0 ** -1074
+    assert _exact_dot([t, t, -(2.0 ** -600)], [t, 2.0 ** -538, 2.0 ** -534]) == 2.0 ** -1074
+    # cancellation a plain left-to-right sum gets wrong
+    a, b = [1e16, 1.0, -1e16], [1.0, 1.0, 1.0]
+    assert float(np.float64(1e16) + 1.0 - 1e16) != 1.0 and oracle.dot(a, b) == 1.0
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(5000) * np.exp2(rng.integers(-60, 60, 5000))
+    y = rng.standard_normal(5000)
+    ref = oracle.dot(x, y)
+    for perm in (rng.permutation(5000), np.arange(5000)[::-1]):
+        assert _same_bits(oracle.dot(x[perm], y[perm]), ref)
+    for th in (2, 3, 16):
+        assert _same_bits(oracle.dot(x, y, threads=th), ref)
+    assert _same_bits(ref, _exact_dot(x, y))
+
+
+def test_dot_overflow_and_non_finite():
+    big = 2.0 ** 1000
+    assert oracle.dot([big, big], [2.0 ** 23, 2.0 ** 23]) == np.inf
+    assert oracle.dot([-big, -big], [2.0 ** 23, 2.0 ** 23]) == -np.inf
+    assert oracle.dot([np.inf, 1.0], [1.0, 2.0]) == np.inf
+    assert np.isnan(oracle.dot([np.inf, -np.inf], [1.0, 1.0]))
+    assert np.isnan(oracle.dot([np.nan, 1.0], [1.0, 1.0]))
+    assert np.isnan(oracle.dot([np.inf], [0.0]))
+    assert oracle.dot([0.0, -0.0], [1.0, 1.0]) == 0.0
+
+
+def test_pcg_is_independent_of_the_thread_count():
+    """With exact inner products the whole iteration is independent of how
+    the dot products are split: x, iterations and residuals bit for bit."""
+    A = inputs.poisson(3, 14, sigma=1.0, seed=3)
+    b = inputs.rhs(A.n, 3)
+    G = oracle.fsai_g(A)
+    r1 = oracle.pcg(A, G, b, tol=1e-10, maxit=500, delta_form=1, threads=1)
+    for th in (3, 8):
+        rt = oracle.pcg(A, G, b, tol=1e-10, maxit=500, delta_form=1, threads=th)
+        assert rt.iters == r1.iters and np.array_equal(rt.x, r1.x)
