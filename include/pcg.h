@@ -246,7 +246,10 @@ int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device);
  * PCG_EINVAL (k < 1, null W), PCG_ESTATE (A or G unset), PCG_ENOMEM. */
 int pcg_sai_loss(pcg_ctx *ctx, int32_t k, const double *W, int on_device, double *sai, double *l2, double *cs);
 
-/* Measurement. Runs `iters` CG iterations of the stored system (a fresh
+/* Measurement (not an operation of the paper, whose evaluation times whole
+ * solves and splits them into construction, apply and CG time, Sec. 4.2 and
+ * Tab. "time-decomposition": a facility of this library for per-kernel
+ * bandwidth figures). Runs `iters` CG iterations of the stored system (a fresh
  * solve of the last right-hand side from x0 = 0 that never stops; the
  * context's vectors are overwritten) as plain launches on the context's
  * stream, each with start/stop events attached to its dispatch (the
@@ -258,14 +261,23 @@ int pcg_sai_loss(pcg_ctx *ctx, int32_t k, const double *W, int on_device, double
  * eps). Needs one prior pcg_solve with b != 0 (or a nonzero stored b). */
 int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes);
 
-/* Device-to-device copy of `bytes` (rounded down to 16) repeated `reps`
- * times with a plain 16-byte-access kernel; *gbps = 2 bytes reps / time (read
- * plus write), *ms_per_copy the average launch (may be NULL). Allocates and
- * frees its own buffers. The measured HBM ceiling and the reference for
- * calibrating memory-traffic counters. */
+/* Measurement (not in the paper): the device's streaming ceilings.
+ * pcg_copy_bandwidth: device-to-device copy of `bytes` (rounded down to 16)
+ * repeated `reps` times (after two untimed copies) with 16-byte nontemporal
+ * loads and stores, four in flight per lane; *gbps = 2 bytes reps / time
+ * (read plus write), *ms_per_copy the average launch (may be NULL).
+ * pcg_read_bandwidth: the same kernel shape reading `bytes` only;
+ * *gbps = bytes reps / time. Both allocate and free their own buffers.
+ * The measured HBM ceiling and the reference for calibrating memory-traffic
+ * counters. PCG_EINVAL (bytes < 16, reps < 1, null gbps), PCG_ENOMEM,
+ * PCG_EDEVICE. */
 int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double *ms_per_copy);
+int pcg_read_bandwidth(int device, int64_t bytes, int reps, double *gbps, double *ms_per_read);
 
-/* Batching and serving. Independent systems of any sizes are solved
+/* Batching and serving. The paper solves one system at a time (Sec. 4.1);
+ * it defines no batched or served operation. These entry points are this
+ * library's way to run many independent PCG solves (Algorithm 1 each) on one
+ * GPU. Independent systems of any sizes are solved
  * together: each CG kernel is one launch over all admitted systems (each
  * system keeps its own row blocks, reductions and scalars, so its result is
  * bit for bit the one it gets alone). The context owns a device memory pool
@@ -305,7 +317,8 @@ int pcg_poll(pcg_ctx *ctx, uint64_t ticket, pcg_result *res);
 int pcg_wait(pcg_ctx *ctx, int count, const uint64_t *tickets, pcg_result *results, double timeout_s);
 int pcg_solve_batch(pcg_ctx *ctx, int count, const pcg_system *sys, pcg_result *results, int iters_per_step);
 
-/* Capacity and bytes in use of the batch pool (0 before first use). */
+/* Capacity and bytes in use of the batch pool (0 before first use). Not in
+ * the paper: part of the batching facility above. */
 int pcg_pool_info(pcg_ctx *ctx, size_t *capacity, size_t *in_use);
 
 /* Host-only helpers (no GPU needed). */
@@ -322,7 +335,8 @@ int64_t pcg_g_nnz(int kind, int32_t n, const int32_t *rowptr, const int32_t *col
 int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, const int32_t *col,
                      const double *val, int32_t *g_rowptr, int32_t *g_col, double *g_val);
 
-/* Autotuner: times one CG iteration of the single system (its three kernels
+/* Autotuner (not in the paper: a facility of this library that picks storage
+ * layouts, launch grid and load policy for the paper's iteration). Times one CG iteration of the single system (its three kernels
  * on b = 1: `iters` iterations for warm-up, then the smaller of two timings
  * of `iters` iterations) for each candidate storage of A (CSR row blocks,
  * sliced ELL, 3x3 blocks: each distinct format the matrix admits) and of G
@@ -357,7 +371,7 @@ typedef struct {
 } pcg_tune_result;
 int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res);
 
-/* Upper estimate of the device memory one system (n unknowns, nnz_a entries
+/* Admission planning for the batching facility (not in the paper). Upper estimate of the device memory one system (n unknowns, nnz_a entries
  * of A, nnz_g of G) takes from the serving pool of a context configured by
  * cfg: A, G and G^T as the automatic layout stores them (sliced layouts are
  * chosen only while their padding stays within 1/8; a forced sliced layout
@@ -366,7 +380,7 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res);
  * Returns PCG_EINVAL for a NULL pointer, n <= 0 or negative counts. */
 int pcg_estimate_bytes(const pcg_config *cfg, int32_t n, int64_t nnz_a, int64_t nnz_g, size_t *bytes);
 
-/* Algorithmic device bytes of one PCG iteration over int32 CSR: A, G^T and G
+/* Measurement (not in the paper, which reports no bandwidth). Algorithmic device bytes of one PCG iteration over int32 CSR: A, G^T and G
  * read once (values and 4-byte column indices), their row pointers, and 11
  * vector streams of n entries (vec bytes each). Results report the bytes of
  * the layouts actually used (pcg_result.bytes_per_iter), which store 16-bit

@@ -80,7 +80,7 @@ def _load():
     lib.or_tril_nnz.restype = ctypes.c_int64
     lib.or_tril_nnz.argtypes = [i32, P, P]
     lib.or_fsai_lower.restype = ctypes.c_int
-    lib.or_fsai_lower.argtypes = [i32, P, P, P, P, P, P]
+    lib.or_fsai_lower.argtypes = [i32, P, P, P, P, P, P, ctypes.c_int]
     lib.or_g_cfg1.restype = ctypes.c_int
     lib.or_g_cfg1.argtypes = [i32, P, P, P, P, P, P]
     lib.or_max_threads.restype = ctypes.c_int
@@ -217,22 +217,25 @@ def tril_nnz(A) -> int:
     return int(_load().or_tril_nnz(A.n, _p(A.rowptr), _p(A.col)))
 
 
-def fsai_lower(A) -> Mat:
-    """Classic FSAI G_L on tril(A)'s pattern (A^-1 ~ G_L^T G_L)."""
+def fsai_lower(A, threads: int | None = None) -> Mat:
+    """Classic FSAI G_L on tril(A)'s pattern (A^-1 ~ G_L^T G_L). Rows are
+    independent; the thread count (default: all available) does not change
+    the result."""
     A = _mat(A)
     m = tril_nnz(A)
     grp = np.empty(A.n + 1, np.int32)
     gci = np.empty(m, np.int32)
     gv = np.empty(m, np.float64)
-    rc = _load().or_fsai_lower(A.n, _p(A.rowptr), _p(A.col), _p(A.val), _p(grp), _p(gci), _p(gv))
+    th = max_threads() if threads is None else int(threads)
+    rc = _load().or_fsai_lower(A.n, _p(A.rowptr), _p(A.col), _p(A.val), _p(grp), _p(gci), _p(gv), th)
     if rc != OK:
         raise ValueError(f"or_fsai_lower failed with {rc}")
     return Mat(grp, gci, gv)
 
 
-def fsai_g(A) -> Mat:
+def fsai_g(A, threads: int | None = None) -> Mat:
     """G = G_L^T, so that M^-1 = G G^T = G_L^T G_L ~ A^-1."""
-    return transpose(fsai_lower(A))
+    return transpose(fsai_lower(A, threads))
 
 
 def g_cfg1(A) -> Mat:

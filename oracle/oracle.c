@@ -416,11 +416,15 @@ int or_pcg(int32_t n, const int32_t *arp, const int32_t *aci, const double *av, 
 
 /* -------------------------------------------------- preconditioner builders */
 
-/* Entry A_ij of a CSR matrix with sorted columns, or 0. */
+/* Entry A_ij of a CSR matrix with sorted columns, or 0 (binary search). */
 static double csr_get(const int32_t *rp, const int32_t *ci, const double *v, int32_t i, int32_t j) {
-  for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
-    if (ci[k] == j) return v[k];
-  return 0.0;
+  int32_t lo = rp[i], hi = rp[i + 1];
+  while (lo < hi) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    if (ci[mid] < j) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < rp[i + 1] && ci[lo] == j) ? v[lo] : 0.0;
 }
 
 /* Number of entries with column <= row: the size of tril(A)'s pattern. */
@@ -439,65 +443,77 @@ int64_t or_tril_nnz(int32_t n, const int32_t *rp, const int32_t *ci) {
  * J = { j <= i : A_ij != 0 } (ascending, so i is last), solve A[J,J] y = e_i
  * by dense Cholesky and set row i of G_L on J to y / sqrt(y_i).
  * Output arrays are sized n+1 / or_tril_nnz. Returns OR_OK, or OR_EBREAKDOWN
- * when a local matrix is not positive definite.
+ * when a local matrix is not positive definite (OR_EINVAL: no diagonal).
+ * Rows are independent; `threads` only splits them (same result).
  */
+static int fsai_row(int32_t i, const int32_t *rp, const int32_t *ci, const double *v, int32_t *gci, double *gv,
+                    int32_t *J, double *S, double *y) {
+  int m = 0;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] <= i) J[m++] = ci[k];
+  if (m == 0 || J[m - 1] != i) return OR_EINVAL;
+  for (int a = 0; a < m; ++a)
+    for (int c = 0; c < m; ++c) S[a * m + c] = csr_get(rp, ci, v, J[a], J[c]);
+  /* Cholesky S = L L^T, L stored in the lower triangle of S */
+  for (int c = 0; c < m; ++c) {
+    double dsum = S[c * m + c];
+    for (int k = 0; k < c; ++k) dsum -= S[c * m + k] * S[c * m + k];
+    if (!(dsum > 0.0)) return OR_EBREAKDOWN;
+    double l = sqrt(dsum);
+    S[c * m + c] = l;
+    for (int a = c + 1; a < m; ++a) {
+      double e = S[a * m + c];
+      for (int k = 0; k < c; ++k) e -= S[a * m + k] * S[c * m + k];
+      S[a * m + c] = e / l;
+    }
+  }
+  /* forward: L z = e_last ; backward: L^T y = z */
+  for (int a = 0; a < m; ++a) {
+    double e = (a == m - 1) ? 1.0 : 0.0;
+    for (int k = 0; k < a; ++k) e -= S[a * m + k] * y[k];
+    y[a] = e / S[a * m + a];
+  }
+  for (int a = m - 1; a >= 0; --a) {
+    double e = y[a];
+    for (int k = a + 1; k < m; ++k) e -= S[k * m + a] * y[k];
+    y[a] = e / S[a * m + a];
+  }
+  if (!(y[m - 1] > 0.0)) return OR_EBREAKDOWN;
+  const double sc = sqrt(y[m - 1]);
+  for (int a = 0; a < m; ++a) {
+    gci[a] = J[a];
+    gv[a] = y[a] / sc;
+  }
+  return OR_OK;
+}
+
 int or_fsai_lower(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *grp, int32_t *gci,
-                  double *gv) {
-  int cap = 64;
-  int32_t *J = (int32_t *)malloc(sizeof(int32_t) * cap);
-  double *S = (double *)malloc(sizeof(double) * cap * cap);
-  double *y = (double *)malloc(sizeof(double) * cap);
-  int rc = OR_OK;
+                  double *gv, int threads) {
+  int32_t mmax = 1;
   grp[0] = 0;
-  for (int32_t i = 0; i < n && rc == OR_OK; ++i) {
-    int m = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t m = 0;
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
-      if (ci[k] <= i) {
-        if (m == cap) {
-          cap *= 2;
-          J = (int32_t *)realloc(J, sizeof(int32_t) * cap);
-          S = (double *)realloc(S, sizeof(double) * cap * cap);
-          y = (double *)realloc(y, sizeof(double) * cap);
-        }
-        J[m++] = ci[k];
-      }
-    if (m == 0 || J[m - 1] != i) { rc = OR_EINVAL; break; }
-    for (int a = 0; a < m; ++a)
-      for (int c = 0; c < m; ++c) S[a * m + c] = csr_get(rp, ci, v, J[a], J[c]);
-    /* Cholesky S = L L^T, L stored in the lower triangle of S */
-    for (int c = 0; c < m && rc == OR_OK; ++c) {
-      double dsum = S[c * m + c];
-      for (int k = 0; k < c; ++k) dsum -= S[c * m + k] * S[c * m + k];
-      if (!(dsum > 0.0)) { rc = OR_EBREAKDOWN; break; }
-      double l = sqrt(dsum);
-      S[c * m + c] = l;
-      for (int a = c + 1; a < m; ++a) {
-        double e = S[a * m + c];
-        for (int k = 0; k < c; ++k) e -= S[a * m + k] * S[c * m + k];
-        S[a * m + c] = e / l;
-      }
-    }
-    if (rc != OR_OK) break;
-    /* forward: L z = e_last ; backward: L^T y = z */
-    for (int a = 0; a < m; ++a) {
-      double e = (a == m - 1) ? 1.0 : 0.0;
-      for (int k = 0; k < a; ++k) e -= S[a * m + k] * y[k];
-      y[a] = e / S[a * m + a];
-    }
-    for (int a = m - 1; a >= 0; --a) {
-      double e = y[a];
-      for (int k = a + 1; k < m; ++k) e -= S[k * m + a] * y[k];
-      y[a] = e / S[a * m + a];
-    }
-    if (!(y[m - 1] > 0.0)) { rc = OR_EBREAKDOWN; break; }
-    const double sc = sqrt(y[m - 1]);
-    for (int a = 0; a < m; ++a) {
-      gci[grp[i] + a] = J[a];
-      gv[grp[i] + a] = y[a] / sc;
-    }
+      if (ci[k] <= i) m++;
+    if (m > mmax) mmax = m;
     grp[i + 1] = grp[i] + m;
   }
-  free(J); free(S); free(y);
+  int rc = OR_OK;
+#pragma omp parallel num_threads(threads > 0 ? threads : 1)
+  {
+    int32_t *J = (int32_t *)malloc(sizeof(int32_t) * mmax);
+    double *S = (double *)malloc(sizeof(double) * (size_t)mmax * mmax);
+    double *y = (double *)malloc(sizeof(double) * mmax);
+    int my = OR_OK;
+#pragma omp for schedule(dynamic, 256)
+    for (int32_t i = 0; i < n; ++i) {
+      const int r = fsai_row(i, rp, ci, v, gci + grp[i], gv + grp[i], J, S, y);
+      if (r != OR_OK && my == OR_OK) my = r;
+    }
+#pragma omp critical
+    if (my != OR_OK && rc == OR_OK) rc = my;
+    free(J); free(S); free(y);
+  }
   return rc;
 }
 

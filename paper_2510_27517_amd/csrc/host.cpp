@@ -447,7 +447,7 @@ int pcg_estimate_bytes(const pcg_config *cfg, int32_t n, int64_t nnz_a, int64_t 
   double b = pad * (double)nnz_a * (sa + 4.0) + 4.0 * (n + 1.0) + blocks;        // A
   b += 2.0 * (pad * (double)nnz_g * (sg + 4.0) + 4.0 * (n + 1.0) + blocks);      // G, G^T
   b += (8.0 + 2.0) * (double)n * sv + 8.0 * (double)n;                           // vectors, staging
-  b += 8.0 * 6.0 * 256.0 * std::max(cfg->grid_mult, 8);                         // partial sums
+  b += 8.0 * 6.0 * 2.0 * 256.0 * std::max(cfg->grid_mult, 8);                         // partial sums
   if (cfg->refine) b += pad * 8.0 * (double)nnz_a + blocks + 3.0 * 8.0 * (double)n;  // FP64 view of A
   b += 256.0 * 32.0;                                                             // alignment of the carved arrays
   *bytes = (size_t)b;

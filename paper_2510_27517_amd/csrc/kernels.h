@@ -107,12 +107,17 @@ struct DevCSR {
 constexpr int kSliceRows = 64;
 constexpr int kBSliceRows = 21;
 
-// One system in the directory (device-resident, POD).
+// Doubles per partial sum of an inner product (a double-double hi, lo).
+constexpr int kAccWords = 2;
+
+// One system in the directory (device-resident, POD). Partial sums: value j
+// of a kernel with G workgroups keeps its workgroup L's hi at [2j G + L] and
+// its lo at [(2j + 1) G + L].
 struct SysDev {
   DevCSR A, GT, G;
   void *x, *r0, *r1, *d0, *d1, *q, *t, *s, *b;  // n entries of the vector type (s: FP64 views only)
   State *st;                                    // two slots
-  double *pg;   // A.grid partials: d^T A d
+  double *pg;   // A.grid partials: d^T A d (kAccWords doubles each)
   double *prt;  // 2 * GT.grid partials: ||r||^2, ||t||^2
   double *pb;   // gB partials: ||b||^2
   double *ptr;  // A.grid partials: ||b - A x||^2
@@ -241,7 +246,11 @@ constexpr int kLossGrid = 512;
 hipError_t launch_loss_partials(int32_t n, int32_t k, const double *W, const double *Y, double na, double *part,
                                 hipStream_t s);
 
-// dst = src, `bytes` a multiple of 16.
+// dst = src, `bytes` a multiple of 16 (nontemporal 16-byte accesses).
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int grid, hipStream_t s);
+// Reads `bytes` (a multiple of 16) of src; sink has `grid` words and is
+// written only for data no probe uses.
+hipError_t launch_read(const void *src, int64_t bytes, uint32_t *sink, int grid, hipStream_t s);
+
 
 }  // namespace pcgk

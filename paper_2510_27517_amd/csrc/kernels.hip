@@ -402,12 +402,68 @@ __device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *l
     for_rows_as<TACC, UW, true, REV>(M, l, G, lds, pre, gather, epi);
 }
 
+// ---- inner products
+//
+// Every dot product and norm is its exact value rounded once to FP64, the
+// value that does not depend on how the sum is split over lanes, waves and
+// workgroups. Each lane accumulates its products as an unevaluated double-
+// double hi + lo (the product's rounding error from an FMA, the additions'
+// from TwoSum: Ogita, Rump and Oishi's Dot2); partial sums are combined as
+// double-doubles in any order and rounded once at the end. The result is the
+// correctly rounded inner product unless the exact value lies within about
+// n u^2 sum|a_i b_i| of a rounding boundary (u = 2^-53), which for the sizes
+// here is far below one chance in a billion per dot product.
+struct Acc {
+  double hi, lo;
+};
+
+// s + e = a + b exactly, s = fl(a + b) (Knuth's TwoSum; needs no ordering
+// of |a|, |b|, and no contraction or reassociation, which the build forbids)
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// x += a b: the product's exact error from an FMA (FP64 operands); the
+// product of two FP32 values is exact in FP64
+__device__ __forceinline__ void acc_prod(Acc &x, double a, double b) {
+  const double p = a * b;
+  const double pe = __builtin_fma(a, b, -p);
+  double s, e;
+  two_sum(x.hi, p, s, e);
+  x.hi = s;
+  x.lo = x.lo + (e + pe);
+}
+__device__ __forceinline__ void acc_prod(Acc &x, float a, float b) {
+  const double p = (double)a * (double)b;
+  double s, e;
+  two_sum(x.hi, p, s, e);
+  x.hi = s;
+  x.lo = x.lo + e;
+}
+
+// a + b, normalised (hi = fl(hi + lo))
+__device__ __forceinline__ Acc acc_add(Acc a, Acc b) {
+  double s, e;
+  two_sum(a.hi, b.hi, s, e);
+  const double t = (a.lo + b.lo) + e;
+  Acc r;
+  two_sum(s, t, r.hi, r.lo);
+  return r;
+}
+
+__device__ __forceinline__ Acc acc_shfl_xor(Acc a, int off) {
+  return Acc{__shfl_xor(a.hi, off), __shfl_xor(a.lo, off)};
+}
+
+// Workgroup total of each value, in thread 0 (normalised).
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
+__device__ __forceinline__ void block_sum(Acc (&v)[NV], Acc *sh) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] += __shfl_xor(v[j], off);
+    for (int j = 0; j < NV; ++j) v[j] = acc_add(v[j], acc_shfl_xor(v[j], off));
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int NW = kBlock / 64;
   if (lane == 0)
@@ -417,42 +473,47 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
   if (threadIdx.x == 0)
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-      double a = sh[j * NW];
-      for (int q = 1; q < NW; ++q) a += sh[j * NW + q];
+      Acc a = sh[j * NW];
+      for (int q = 1; q < NW; ++q) a = acc_add(a, sh[j * NW + q]);
       v[j] = a;
     }
   __syncthreads();
 }
 
-// Write this workgroup's partial sums (value j at p[j * G + L]).
+// Write this workgroup's partial sums: value j's hi at p[2j G + L], its lo at
+// p[(2j + 1) G + L] (kAccWords doubles per partial).
 template <int NV>
-__device__ __forceinline__ void put_partials(double (&v)[NV], GLOBAL double *p, int L, int G, double *sh) {
+__device__ __forceinline__ void put_partials(Acc (&v)[NV], GLOBAL double *p, int L, int G, Acc *sh) {
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int j = 0; j < NV; ++j) p[(int64_t)j * G + L] = v[j];
+    for (int j = 0; j < NV; ++j) {
+      p[(int64_t)(2 * j) * G + L] = v[j].hi;
+      p[(int64_t)(2 * j + 1) * G + L] = v[j].lo;
+    }
 }
 
-// Sum the P partials of each value in a fixed order; every thread gets the
-// totals. load_partials adds this thread's share (no barrier, so a kernel can
-// issue it before it reads its state); reduce_partials finishes the sums.
+// Total of the P partials of each value; every thread gets the totals,
+// rounded once to FP64. load_partials adds this thread's share (no barrier,
+// so a kernel can issue it before it reads its state); reduce_partials
+// finishes the sums.
 template <int NV>
-__device__ __forceinline__ void load_partials(GLOBAL const double *__restrict__ p, int P, double (&acc)[NV]) {
+__device__ __forceinline__ void load_partials(GLOBAL const double *__restrict__ p, int P, Acc (&acc)[NV]) {
 #pragma unroll
-  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-#pragma unroll 8
+  for (int j = 0; j < NV; ++j) acc[j] = Acc{0.0, 0.0};
+#pragma unroll 4
   for (int k = threadIdx.x; k < P; k += kBlock)
 #pragma unroll
-    for (int j = 0; j < NV; ++j) acc[j] += p[(int64_t)j * P + k];
+    for (int j = 0; j < NV; ++j) acc[j] = acc_add(acc[j], Acc{p[(int64_t)(2 * j) * P + k], p[(int64_t)(2 * j + 1) * P + k]});
 }
 
 template <int NV>
-__device__ __forceinline__ void reduce_partials(double (&acc)[NV], double (&out)[NV], double *sh) {
+__device__ __forceinline__ void reduce_partials(Acc (&acc)[NV], double (&out)[NV], Acc *sh) {
   block_sum<NV>(acc, sh);
   __shared__ double tot[NV];
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int j = 0; j < NV; ++j) tot[j] = acc[j];
+    for (int j = 0; j < NV; ++j) tot[j] = acc[j].hi + acc[j].lo;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < NV; ++j) out[j] = tot[j];
@@ -460,8 +521,8 @@ __device__ __forceinline__ void reduce_partials(double (&acc)[NV], double (&out)
 
 template <int NV>
 __device__ __forceinline__ void sum_partials(GLOBAL const double *__restrict__ p, int P, double (&out)[NV],
-                                             double *sh) {
-  double acc[NV];
+                                             Acc *sh) {
+  Acc acc[NV];
   load_partials<NV>(p, P, acc);
   reduce_partials<NV>(acc, out, sh);
 }
@@ -478,7 +539,7 @@ __device__ __forceinline__ void ew_rows(int n, int l, int G, int64_t &i0, int64_
 template <typename TV, typename TA>
 __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_A(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
-  __shared__ double sh[4 * (kBlock / 64)];
+  __shared__ Acc sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
   GLOBAL const State &S = gl(D.st)[0];
@@ -487,13 +548,13 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_A(const SysDev *_
   const int it = S.iter;
   GLOBAL TV *__restrict__ q = gl((TV *)D.q);
   GLOBAL const TV *__restrict__ dcur = gl((const TV *)((it & 1) ? D.d1 : D.d0));  // d_i
-  double part[1] = {0.0};
+  Acc part[1] = {{0.0, 0.0}};
   for_rows<TV, 8>(
       A, m.y, D.A.grid, lds, [&](int row) { return RowVals<TV>{dcur[row], (TV)0, (TV)0}; },
       [&](int j) -> TV { return dcur[j]; },
       [&](int row, TV sum, const RowVals<TV> &pv) {
         q[row] = sum;
-        part[0] += (double)pv.a * (double)sum;
+        acc_prod(part[0], pv.a, sum);
       });
   put_partials<1>(part, gl(D.pg), part_slot(m.y, D.A.grid), D.A.grid, sh);
 }
@@ -502,12 +563,12 @@ template <typename TV, typename TG>
 __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                     int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
-  __shared__ double sh[4 * (kBlock / 64)];
+  __shared__ Acc sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
   GLOBAL State *st = gl(D.st);
   GLOBAL const State &S = st[0];
-  double g[1];
+  Acc g[1];
   load_partials<1>(gl(D.pg), D.A.grid, g);  // in flight while the state is read
   if (S.done) {  // stopped earlier: st[1] mirrors st[0], so the G-kernel need not read st[0]
     if (m.y == 0 && threadIdx.x == 0) st_state(st + 1, ld_state(&S));
@@ -518,8 +579,9 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
   double alpha = S.alpha, gamma = S.gamma;
   bool brk = false;
   if (mode != 2) {
-    reduce_partials<1>(g, g, sh);
-    gamma = g[0];
+    double gv[1];
+    reduce_partials<1>(g, gv, sh);
+    gamma = gv[0];
     brk = !(gamma > 0.0) || !isfinite(gamma);
     alpha = brk ? 0.0 : S.delta / gamma;  // on breakdown x already holds x_i
   }
@@ -540,9 +602,8 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
   const TV al = (mode == 0) ? (TV)alpha : (TV)0;
   GLOBAL const TV *__restrict__ src = gl((const TV *)((((mode == 1) ? it + 1 : it) & 1) ? D.r1 : D.r0));
   GLOBAL TV *__restrict__ dst = gl((TV *)(((it + 1) & 1) ? D.r1 : D.r0));
-  double part[2] = {0.0, 0.0};
-  // G^T rows gather ahead of themselves (upper triangle): walking the slices
-  // down makes the gathered lines ones that the streams already brought in
+  Acc part[2] = {{0.0, 0.0}, {0.0, 0.0}};
+  // each die walks its slices from the top down (measured slightly faster)
   if (mode == 0) {
     for_rows<TV, 4, true>(
         GT, m.y, D.GT.grid, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
@@ -551,8 +612,8 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
           const TV rn = pv.a - al * pv.b;
           dst[row] = rn;
           t[row] = sum;
-          part[0] += (double)rn * (double)rn;
-          part[1] += (double)sum * (double)sum;
+          acc_prod(part[0], rn, rn);
+          acc_prod(part[1], sum, sum);
         });
   } else {
     for_rows<TV, 4, true>(
@@ -560,8 +621,8 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
         [&](int j) -> TV { return src[j]; },
         [&](int row, TV sum, const RowVals<TV> &pv) {
           t[row] = sum;
-          part[0] += (double)pv.a * (double)pv.a;
-          part[1] += (double)sum * (double)sum;
+          acc_prod(part[0], pv.a, pv.a);
+          acc_prod(part[1], sum, sum);
         });
   }
   put_partials<2>(part, gl(D.prt), part_slot(m.y, D.GT.grid), D.GT.grid, sh);
@@ -571,21 +632,22 @@ template <typename TV, typename TG, bool HAS_EPS>
 __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_G(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                    int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
-  __shared__ double sh[4 * (kBlock / 64)];
+  __shared__ Acc sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
   GLOBAL State *st = gl(D.st);
   // st[1] is the G^T-kernel's publication for this iteration; st[0] is written
   // below by workgroup 0 and must not be read by the others
   GLOBAL const State &S = st[1];
-  double v[2];
-  load_partials<2>(gl(D.prt), D.GT.grid, v);  // in flight while the state is read
+  Acc va[2];
+  load_partials<2>(gl(D.prt), D.GT.grid, va);  // in flight while the state is read
   if (S.done) {  // stopped earlier, or the G^T-kernel flagged a breakdown
     if (m.y == 0 && threadIdx.x == 0) st_state(st, ld_state(&S));
     return;
   }
   const int it = S.iter;
-  reduce_partials<2>(v, v, sh);
+  double v[2];
+  reduce_partials<2>(va, v, sh);
   const double rr = v[0], tt = v[1];
   const double dn = tt + S.eps * rr;
   const int i1 = (mode == 2) ? it : it + 1;
@@ -657,7 +719,7 @@ template <typename TV, typename TA>
 __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_resid(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                   int slot_sel, int with_d, int reduce, int respect_done) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
-  __shared__ double sh[4 * (kBlock / 64)];
+  __shared__ Acc sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
   GLOBAL const State &S = gl(D.st)[0];
@@ -679,12 +741,12 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_resid(const SysDev *__
     if (!(g[0] > 0.0) || !isfinite(g[0])) return;  // the G^T-kernel reports the breakdown
     al = (TV)(S.delta / g[0]);
   }
-  double part[1] = {0.0};
+  Acc part[1] = {{0.0, 0.0}};
   auto pre = [&](int row) { return RowVals<TV>{b[row], (TV)0, (TV)0}; };
   auto epi = [&](int row, TV sum, const RowVals<TV> &pv) {
     const TV rv = pv.a - sum;
     rout[row] = rv;
-    part[0] += (double)rv * (double)rv;
+    acc_prod(part[0], rv, rv);
   };
   if (with_d)
     for_rows<TV>(A, m.y, D.A.grid, lds, pre, [&](int j) -> TV { return x[j] + al * dc[j]; }, epi);
@@ -767,16 +829,16 @@ __global__ void k_state_restart(const SysDev *__restrict__ dir, const int32_t *_
 
 template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_norm_b(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
-  __shared__ double sh[4 * (kBlock / 64)];
+  __shared__ Acc sh[4 * (kBlock / 64)];
   const int2 m = map[blockIdx.x];
   const SysDev &D = dir[m.x];
   GLOBAL const TV *__restrict__ b = gl((const TV *)D.b);
-  double part[1] = {0.0};
-  // local workgroup l adds the contiguous slice l of b; the order is fixed
+  Acc part[1] = {{0.0, 0.0}};
+  // local workgroup l adds the contiguous slice l of b
   const int G = D.gB, l = m.y;
   const int64_t i0 = (int64_t)l * D.n / G, i1 = (int64_t)(l + 1) * D.n / G;
-#pragma unroll 8
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) part[0] += (double)b[i] * (double)b[i];
+#pragma unroll 4
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) acc_prod(part[0], b[i], b[i]);
   put_partials<1>(part, gl(D.pb), l, G, sh);
 }
 
@@ -784,7 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_b(const SysDev *__restrict__ di
 // and the b = 0 test) or ||b - A x||^2 (what = 1) from its partials into st[0].
 __global__ __launch_bounds__(kBlock) void k_reduce_state(const SysDev *__restrict__ dir,
                                                          const int32_t *__restrict__ set, int what) {
-  __shared__ double sh[4 * (kBlock / 64)];
+  __shared__ Acc sh[4 * (kBlock / 64)];
   const SysDev &D = dir[set[blockIdx.x]];
   double v[1];
   if (what == 0)
@@ -838,11 +900,46 @@ __global__ void k_refine_update(int32_t n, double *__restrict__ x64, const TC *_
     x64[i] = x64[i] + scale * (double)c[i];
 }
 
-// Plain streaming copy (16-byte accesses): the reference for the HBM ceiling
-// and for calibrating the memory-traffic counters.
-__global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16) {
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock)
-    dst[i] = src[i];
+// Streaming probes of the HBM ceiling (and the reference for calibrating the
+// memory-traffic counters): 16-byte nontemporal accesses, four per lane in
+// flight (all loads of a round issued before its stores), grid-stride rounds.
+constexpr int kStreamUnroll = 4;
+
+__global__ __launch_bounds__(kBlock) void k_copy(const u32x4 *__restrict__ src_, u32x4 *__restrict__ dst_, int64_t n16) {
+  GLOBAL const u32x4 *src = gl(src_);
+  GLOBAL u32x4 *dst = gl(dst_);
+  constexpr int U = kStreamUnroll;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+  }
+  for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// Read-only stream: the words are folded with xor, and a workgroup writes its
+// fold only if it equals a value no test data produces (so the loads stay).
+__global__ __launch_bounds__(kBlock) void k_read(const u32x4 *__restrict__ src_, int64_t n16,
+                                                 uint32_t *__restrict__ sink_) {
+  GLOBAL const u32x4 *src = gl(src_);
+  constexpr int U = kStreamUnroll;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  u32x4 acc = {0u, 0u, 0u, 0u};
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc ^= v[u];
+  }
+  for (; i < n16; i += stride) acc ^= __builtin_nontemporal_load(src + i);
+  if (acc.x == 0x9e3779b9u && acc.y == 0x7f4a7c15u && acc.z == 0x85ebca6bu && acc.w == 0xc2b2ae35u)
+    gl(sink_)[blockIdx.x] = acc.x;
 }
 
 // ------------------------------------------------ FSAI construction on the device
@@ -1372,7 +1469,12 @@ hipError_t launch_loss_partials(int32_t n, int32_t k, const double *W, const dou
 }
 
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kBlock), 0, s, (const uint4 *)src, (uint4 *)dst, bytes / 16);
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kBlock), 0, s, (const u32x4 *)src, (u32x4 *)dst, bytes / 16);
+  return hipGetLastError();
+}
+
+hipError_t launch_read(const void *src, int64_t bytes, uint32_t *sink, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_read, dim3(grid), dim3(kBlock), 0, s, (const u32x4 *)src, bytes / 16, sink);
   return hipGetLastError();
 }
 

@@ -431,7 +431,8 @@ void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const 
   if (P.refine) b += b64 + 3 * db;
   if (P.staging) b += 2 * vb + db;
   const int gtr = std::max(P.A.grid, P.refine ? P.grid64 : 0);
-  b += align_up(8 * (size_t)P.A.grid) + align_up(8 * (size_t)gtr) + align_up(8 * (size_t)P.gB);
+  constexpr size_t W = 8 * pcgk::kAccWords;  // bytes per partial sum
+  b += align_up(W * (size_t)P.A.grid) + align_up(W * (size_t)gtr) + align_up(W * (size_t)P.gB);
   P.bytes = b;
 }
 
@@ -458,7 +459,7 @@ void prep_g(const pcg_config &cfg, int cus, int32_t n, std::vector<int32_t> &grp
   }
   make_mat(cfg, cus, n, grp.data(), gci.data(), gv.data(), P.gdt, P.scale, P.vdt, P.G, 2);
   make_mat(cfg, cus, n, trp.data(), tci.data(), tv.data(), P.gdt, P.scale, P.vdt, P.GT, 2);
-  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * (size_t)P.GT.grid);
+  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * pcgk::kAccWords * (size_t)P.GT.grid);
 }
 
 struct Carver {
@@ -525,9 +526,10 @@ hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
   S.dev.gB = P.gB;
   S.n = n;
   S.nnz_a = P.nnz;
-  S.dev.pg = (double *)c.take(8 * (size_t)P.A.grid);
-  S.dev.ptr = (double *)c.take(8 * (size_t)std::max(P.A.grid, P.refine ? P.grid64 : 0));
-  S.dev.pb = (double *)c.take(8 * (size_t)P.gB);
+  constexpr size_t W = 8 * pcgk::kAccWords;  // bytes per partial sum
+  S.dev.pg = (double *)c.take(W * (size_t)P.A.grid);
+  S.dev.ptr = (double *)c.take(W * (size_t)std::max(P.A.grid, P.refine ? P.grid64 : 0));
+  S.dev.pb = (double *)c.take(W * (size_t)P.gB);
   if (P.refine) {
     SysDev &D = S.dev64;
     D = SysDev{};
@@ -569,7 +571,7 @@ hipError_t place_g(const GPart &P, void *block, Sys &S, hipStream_t s) {
   hipError_t e = put_mat(c, P.G, S.dev.G, s);
   hipError_t e2 = put_mat(c, P.GT, S.dev.GT, s);
   if (e == hipSuccess) e = e2;
-  S.dev.prt = (double *)c.take(16 * (size_t)P.GT.grid);
+  S.dev.prt = (double *)c.take(16 * pcgk::kAccWords * (size_t)P.GT.grid);
   S.nnz_g = P.nnz;
   S.g_scale = P.scale;
   return e;
@@ -1068,16 +1070,38 @@ double inner_tolerance(double cfg_inner_tol, double tol, double nb, double rn, i
   return base;
 }
 
+// Row blocks of a stored CSR matrix for products in FP64 vectors: the
+// blocks a matrix was laid out with hold up to lds_cap(vec type) nonzeros,
+// twice what an FP64 product's LDS window takes when the vectors are FP32.
+// The row pointers are read back from the device.
+int f64_row_blocks(pcg_ctx *ctx, const DevCSR &M, std::vector<int32_t> &blk) {
+  std::vector<int32_t> rp((size_t)M.n + 1);
+  HIPCHK(hipMemcpy(rp.data(), M.rp, 4 * rp.size(), hipMemcpyDeviceToHost));
+  blk = pcgh::row_blocks(M.n, rp.data(), pcgk::lds_cap(pcgk::F64));
+  return PCG_OK;
+}
+
 // The FP64 record of escalated inner solves: A's FP64 view, G and G^T as
 // stored, FP64 vectors and partial sums of its own (allocated at the first
-// escalation, kept until the system's storage is freed).
+// escalation, kept until the system's storage is freed). G or G^T stored as
+// CSR row blocks get blocks of their own, sized for FP64 products.
 int prepare_escalation(pcg_ctx *ctx) {
   Sys &S = ctx->single;
   if (S.blkX) return PCG_OK;
   const int32_t n = S.n;
-  const int ga = S.dev64.A.grid, gt = S.dev.GT.grid, gb = S.dev.gB;
+  std::vector<int32_t> bg, bgt;
+  int rc0;
+  if (S.dev.G.fmt == pcgk::FMT_CSR && (rc0 = f64_row_blocks(ctx, S.dev.G, bg))) return rc0;
+  if (S.dev.GT.fmt == pcgk::FMT_CSR && (rc0 = f64_row_blocks(ctx, S.dev.GT, bgt))) return rc0;
+  const pcg_config gcfg = eff_cfg(ctx, true);
+  const int gm = gcfg.grid_mult;
+  auto nunits = [](const std::vector<int32_t> &b) { return (int32_t)(b.size() / 2 - 1); };
+  const int ga = S.dev64.A.grid, gb = S.dev.gB;
+  const int gt = bgt.empty() ? S.dev.GT.grid : grid_for(ctx->cus, gm, nunits(bgt));
   const size_t vb = align_up(8 * (size_t)n);
-  const size_t bytes = 8 * vb + align_up(8 * (size_t)ga) * 2 + align_up(16 * (size_t)gt) + align_up(8 * (size_t)gb);
+  constexpr size_t W = 8 * pcgk::kAccWords;  // bytes per partial sum
+  const size_t bytes = 8 * vb + align_up(W * (size_t)ga) * 2 + align_up(2 * W * (size_t)gt) + align_up(W * (size_t)gb) +
+                       align_up(4 * bg.size()) + align_up(4 * bgt.size());
   void *blk = nullptr;
   if (ctx->da.get(&blk, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -1094,10 +1118,20 @@ int prepare_escalation(pcg_ctx *ctx) {
   void **vecs[] = {&D.x, &D.r0, &D.r1, &D.d0, &D.d1, &D.q, &D.t, &D.b};
   for (void **v : vecs) *v = c.take(8 * (size_t)n);
   D.s = nullptr;
-  D.pg = (double *)c.take(8 * (size_t)ga);
-  D.ptr = (double *)c.take(8 * (size_t)ga);
-  D.prt = (double *)c.take(16 * (size_t)gt);
-  D.pb = (double *)c.take(8 * (size_t)gb);
+  D.pg = (double *)c.take(W * (size_t)ga);
+  D.ptr = (double *)c.take(W * (size_t)ga);
+  D.prt = (double *)c.take(2 * W * (size_t)gt);
+  D.pb = (double *)c.take(W * (size_t)gb);
+  auto put_blocks = [&](const std::vector<int32_t> &b, DevCSR &M) -> hipError_t {
+    if (b.empty()) return hipSuccess;
+    int32_t *d = (int32_t *)c.take(4 * b.size());
+    M.blk = d;
+    M.nblk = nunits(b);
+    M.grid = grid_for(ctx->cus, gm, M.nblk);
+    return hipMemcpy(d, b.data(), 4 * b.size(), hipMemcpyHostToDevice);
+  };
+  HIPCHK(put_blocks(bg, D.G));
+  HIPCHK(put_blocks(bgt, D.GT));
   D.n = n;
   D.gB = gb;
   D.st = ctx->d_states + 2 * kSlotX;
@@ -1249,7 +1283,7 @@ bool prep_fsai_pattern(const pcg_config &cfg, int cus, Req &R) {
   P.vdt = cfg.vec_dtype;
   make_pattern(cfg, cus, n, grp.data(), gci.data(), P.gdt, P.vdt, P.G);
   make_pattern(cfg, cus, n, lrp.data(), lci.data(), P.gdt, P.vdt, P.GT);
-  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * (size_t)P.GT.grid);
+  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * pcgk::kAccWords * (size_t)P.GT.grid);
   R.fs_dpos.swap(dpos);
   R.fs_lrp.swap(lrp);
   R.fs_mmax = mmax;
@@ -2215,7 +2249,7 @@ static int build_fsai_device(pcg_ctx *ctx) {
   const pcg_config gcfg = eff_cfg(ctx, true);
   make_pattern(gcfg, ctx->cus, n, grp.data(), gci.data(), P.gdt, P.vdt, P.G);
   make_pattern(gcfg, ctx->cus, n, lrp.data(), lci.data(), P.gdt, P.vdt, P.GT);
-  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * (size_t)P.GT.grid);
+  P.bytes = P.G.bytes() + P.GT.bytes() + align_up(16 * pcgk::kAccWords * (size_t)P.GT.grid);
   // temporaries: A (CSR, FP64), dpos, lrp, G_L's values, flags, partial maxima
   const int64_t nnz = rp[n], nl = lrp[n];
   const size_t tb = align_up(4 * (size_t)(n + 1)) + align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) +
@@ -2807,7 +2841,9 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
   return PCG_OK;
 }
 
-int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double *ms_per_copy) {
+// Copy (kind 0: read and write `bytes`) or read-only (kind 1) stream over
+// freshly allocated buffers, `reps` timed launches after two warm-up ones.
+static int stream_bandwidth(int device, int kind, int64_t bytes, int reps, double *gbps, double *ms_per_launch) {
   if (bytes < 16 || reps < 1 || !gbps) return PCG_EINVAL;
   bytes &= ~int64_t(15);
   if (hipSetDevice(device) != hipSuccess) return PCG_EDEVICE;
@@ -2818,26 +2854,31 @@ int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double
   hipDeviceProp_t prop;
   int cus = 256;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
-  if (hipMalloc(&src, bytes) != hipSuccess || hipMalloc(&dst, bytes) != hipSuccess) rc = PCG_ENOMEM;
+  const int grid = cus * 8;  // one full-occupancy round of 256-thread workgroups
+  const size_t dbytes = kind == 0 ? (size_t)bytes : sizeof(uint32_t) * (size_t)grid;
+  if (hipMalloc(&src, bytes) != hipSuccess || hipMalloc(&dst, dbytes) != hipSuccess) rc = PCG_ENOMEM;
   if (!rc && (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
               hipEventCreate(&e1) != hipSuccess))
     rc = PCG_EDEVICE;
   if (!rc && hipMemsetAsync(src, 0, bytes, s) != hipSuccess) rc = PCG_EDEVICE;
   float ms = 0.0f;
   if (!rc) {
-    const int grid = cus * 16;
+    auto launch = [&]() {
+      return kind == 0 ? pcgk::launch_copy(src, dst, bytes, grid, s)
+                       : pcgk::launch_read(src, bytes, (uint32_t *)dst, grid, s);
+    };
     hipError_t e = hipSuccess;
-    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = pcgk::launch_copy(src, dst, bytes, grid, s);
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = pcgk::launch_copy(src, dst, bytes, grid, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) rc = PCG_EDEVICE;
   }
   if (!rc) {
-    *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
-    if (ms_per_copy) *ms_per_copy = ms / reps;
+    *gbps = (kind == 0 ? 2.0 : 1.0) * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    if (ms_per_launch) *ms_per_launch = ms / reps;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -2846,6 +2887,14 @@ int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double
   if (dst) (void)hipFree(dst);
   (void)hipGetLastError();
   return rc;
+}
+
+int pcg_copy_bandwidth(int device, int64_t bytes, int reps, double *gbps, double *ms_per_copy) {
+  return stream_bandwidth(device, 0, bytes, reps, gbps, ms_per_copy);
+}
+
+int pcg_read_bandwidth(int device, int64_t bytes, int reps, double *gbps, double *ms_per_read) {
+  return stream_bandwidth(device, 1, bytes, reps, gbps, ms_per_read);
 }
 
 // ------------------------------------------------------------ batching / serving

@@ -31,7 +31,8 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 EXPORTS = [
     "pcg_config_default", "pcg_create", "pcg_destroy", "pcg_set_matrix", "pcg_set_precond", "pcg_build_precond",
     "pcg_solve", "pcg_matvec", "pcg_sai_loss", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
-    "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth", "pcg_submit_batch",
+    "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth", "pcg_read_bandwidth",
+    "pcg_submit_batch",
     "pcg_progress", "pcg_poll", "pcg_wait", "pcg_solve_batch", "pcg_pool_info", "pcg_estimate_bytes",
     "pcg_autotune",
 ]
@@ -151,6 +152,7 @@ def load():
     lib.pcg_bytes_per_iter.restype = dbl
     lib.pcg_time_kernels.argtypes = [P, c_int, P, P]
     lib.pcg_copy_bandwidth.argtypes = [c_int, i64, c_int, P, P]
+    lib.pcg_read_bandwidth.argtypes = [c_int, i64, c_int, P, P]
     lib.pcg_submit_batch.argtypes = [P, c_int, ctypes.POINTER(System), ctypes.POINTER(ctypes.c_uint64)]
     lib.pcg_progress.argtypes = [P, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     lib.pcg_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
@@ -228,12 +230,22 @@ def build_g_host(kind: int, A, seed: int = 0):
 
 
 def copy_bandwidth(bytes_: int, reps: int = 20, device: int = 0):
-    """(GB/s, ms per copy) of the library's plain device copy kernel."""
+    """(GB/s, ms per copy) of the library's device copy kernel."""
     g = np.zeros(1)
     m = np.zeros(1)
     st = load().pcg_copy_bandwidth(device, int(bytes_), int(reps), g.ctypes.data, m.ctypes.data)
     if st != OK:
         raise PCGError(st, "pcg_copy_bandwidth")
+    return float(g[0]), float(m[0])
+
+
+def read_bandwidth(bytes_: int, reps: int = 20, device: int = 0):
+    """(GB/s, ms per read) of the library's read-only stream kernel."""
+    g = np.zeros(1)
+    m = np.zeros(1)
+    st = load().pcg_read_bandwidth(device, int(bytes_), int(reps), g.ctypes.data, m.ctypes.data)
+    if st != OK:
+        raise PCGError(st, "pcg_read_bandwidth")
     return float(g[0]), float(m[0])
 
 

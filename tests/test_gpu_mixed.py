@@ -244,3 +244,50 @@ def test_refinement_escalates_to_fp64_inner_solves(gpu_lib):
         s.build_precond(pcg.G_FSAI)
         got = s.solve(inputs.rhs(A.n, 4), tol=1e-10, maxit=3000)
     assert got.status == pcg.OK and got.escalated == 0
+
+
+def _two_hop_laplacian(n, seed, shift):
+    """Laplacian of an RGG's edges plus its two-hop edges (weights: products
+    of the edge weights), plus shift I: about 20 nonzeros per row."""
+    import scipy.sparse as sp
+
+    A = inputs.rgg_laplacian(n, seed, 1e-3).to_scipy().tocsr()
+    W = -A.copy()
+    W.setdiag(0)
+    W.eliminate_zeros()
+    W2 = (W @ W).tocsr()
+    W2.setdiag(0)
+    W2.eliminate_zeros()
+    W2 = W2 + W
+    L = (sp.diags(np.asarray(W2.sum(axis=1)).ravel() + shift) - W2).tocsr()
+    L.sort_indices()
+    return CSR.from_scipy(L)
+
+
+def test_escalation_with_csr_row_blocks_of_long_g_rows(gpu_lib):
+    """Regression: the escalated FP64 inner solves reuse G and G^T, whose CSR
+    row blocks were cut for FP32 products (twice the nonzeros an FP64
+    product's LDS window holds). With about 11 nonzeros per row of G, a
+    256-row block holds more than an FP64 window; the escalated record must
+    carry blocks of its own. The system (shift 1e-7) breaks down in FP32, so
+    the solve escalates; x must still reach the tolerance in FP64."""
+    pcg = gpu_lib
+    A = _two_hop_laplacian(3000, 5, 1e-7)
+    G = oracle.fsai_g(A)
+    rp = G.rowptr
+    assert max(rp[min(i + 256, A.n)] - rp[i] for i in range(0, A.n, 16)) > 2048
+    b = inputs.rhs(A.n, 3)
+    ref = oracle.pcg(A, G, b, tol=1e-6, maxit=20000)
+    assert ref.status == oracle.OK
+    for layout in ("csr", "auto"):
+        cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1,
+                                 layout=pcg.LAYOUTS[layout])
+        with pcg.Solver(cfg) as s:
+            s.set_matrix(A)
+            s.build_precond(pcg.G_FSAI)
+            got = s.solve(b, tol=1e-6, maxit=20000)
+        r64 = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+        err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
+        say(f"escalation, {layout} layout: status {got.status} escalated {got.escalated} outer {got.outer_iters} "
+            f"inner {got.iters} fp64 relres {r64:.2e}, error vs FP64 oracle {err:.2e} (oracle {ref.iters} it)")
+        assert got.status == pcg.OK and got.escalated == 1 and r64 <= 1.0001e-6

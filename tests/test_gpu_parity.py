@@ -2,10 +2,12 @@
 
 Operator products are bit-identical to the oracle's (both add each row's
 products left to right from zero, contraction off, and the transposed
-product sums rows of G in ascending order on both sides). Whole solves
-differ only in the order of the dot-product sums, so they are held to
-trajectory parity: relative difference in x <= 1e-10 and iteration counts
-within one."""
+product sums rows of G in ascending order on both sides). Inner products are
+the exact value rounded once on both sides (the oracle with an exact
+accumulator, the kernels with double-double partial sums, correctly rounded
+unless the exact value lies within about n u^2 sum|a_i b_i| of a rounding
+boundary), so whole solves are held to the strictest bar: the same status,
+iteration count and restart count, and x equal bit for bit."""
 import sys
 
 import numpy as np
@@ -17,7 +19,6 @@ from paper_2510_27517_amd.inputs import CSR
 
 pytestmark = pytest.mark.gpu
 
-XTOL = 1e-10
 
 
 def say(*a):
@@ -95,22 +96,33 @@ def test_operator_products_bitwise(gpu_lib, case, layout):
 
 
 def _parity(pcg, A, kind, b, *, tol=1e-8, maxit=2000, eps=0.0, rr=50, graph=10, x0=None, seed=0, layout="auto"):
-    with _solver(pcg, eps=eps, rr_period=rr, graph_iters=graph, layout=layout) as s:
-        s.set_matrix(A)
-        s.build_precond(kind, seed)
-        got = s.solve(b, x0, tol=tol, maxit=maxit)
+    """The library's solve and the oracle's on the same G. The fixed, Jacobi,
+    identity and seeded G the library builds equal the oracle's bit for bit
+    (tests/test_boundary.py); its FSAI agrees with the oracle's to 1e-13
+    row-normwise only (another order of the same local solves), so FSAI cases
+    hand the oracle's G to the library."""
     G = {pcg.G_FSAI: oracle.fsai_g, pcg.G_FIXED: oracle.g_cfg1, pcg.G_JACOBI: oracle.diag_inv_sqrt,
          pcg.G_IDENTITY: lambda A: oracle.identity(A.n),
          pcg.G_SEEDED: lambda A: oracle.seeded_g(A, seed)}[kind](A)
+    with _solver(pcg, eps=eps, rr_period=rr, graph_iters=graph, layout=layout) as s:
+        s.set_matrix(A)
+        if kind == pcg.G_FSAI:
+            s.set_precond(G)
+        else:
+            s.build_precond(kind, seed)
+        got = s.solve(b, x0, tol=tol, maxit=maxit)
     ref = oracle.pcg(A, G, b, x0, eps=eps, tol=tol, maxit=maxit, rr_period=rr, delta_form=1)
     return got, ref
 
 
 def _check(got, ref):
-    assert got.status == ref.status
-    assert abs(got.iters - ref.iters) <= 1, (got.iters, ref.iters)
-    err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
-    assert err <= XTOL, err
+    """Trajectory parity, bit for bit; returns ||x - x_oracle|| / ||x_oracle||
+    (0 when it holds)."""
+    err = float(np.linalg.norm(got.x - ref.x) / max(np.linalg.norm(ref.x), 1e-300))
+    assert got.status == ref.status, (got.status, ref.status)
+    assert got.iters == ref.iters, (got.iters, ref.iters, err)
+    assert got.restarts == ref.restarts, (got.restarts, ref.restarts)
+    assert np.array_equal(got.x, ref.x), err
     return err
 
 
@@ -156,34 +168,21 @@ def test_pcg_seeded_full_pattern_g_with_shift(gpu_lib, case):
     b = inputs.rhs(A.n, 6)
     eps = oracle.eps_shift(A)
     say("pcg seeded G", case, A.n, "eps", eps)
-    # A random (unlearned) G makes the iteration sensitive to rounding order:
-    # on the RGG system the oracle's two algebraically equal delta formulas
-    # already differ by 2e-12 in x after 20 iterations and 3.4e-10 after 25
-    # (3.4e-15 after 10). Parity is binding at a fixed count of 10; the
-    # converged solves are held to what the residual bound allows,
-    # ||x - x*|| <= kappa(A) ||r||/||b|| ||x*|| for each, with kappa bounded by
-    # Gershgorin over lambda_min.
+    # a random (unlearned) G makes the iteration sensitive to rounding order
+    # (with summation-order-dependent dot products the oracle's two delta
+    # formulas differ by 3.4e-10 in x after 25 iterations on the RGG system);
+    # with exact inner products the trajectories agree bit for bit, at a fixed
+    # iteration count and converged
     got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=0.0, maxit=10)
     _check(got, ref)
     assert got.status == pcg.NOT_CONVERGED and got.iters == 10
     tol = 1e-11
     got, ref = _parity(pcg, A, pcg.G_SEEDED, b, eps=eps, seed=77, tol=tol, maxit=5000)
-    assert got.status == ref.status == pcg.OK
-    # the iteration count is as sensitive: the oracle's own count moves under
-    # its other delta formula and under a 1e-16 relative change of b
-    alt = [oracle.pcg(A, oracle.seeded_g(A, 77), bb, eps=eps, tol=tol, maxit=5000, delta_form=df).iters
-           for bb, df in ((b, 0), (b * (1 + 1e-16 * np.sign(np.sin(np.arange(A.n)))), 1))]
-    spread = max(abs(k - ref.iters) for k in alt)
-    assert abs(got.iters - ref.iters) <= max(1, spread + 1), (got.iters, ref.iters, alt)
+    _check(got, ref)
+    assert got.status == pcg.OK
     r = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
+    say(f"  iters {got.iters}/{ref.iters} relres {r:.2e}")
     assert r <= 1.0001 * tol
-    lam_max = max(np.abs(A.val[A.rowptr[i]:A.rowptr[i + 1]]).sum() for i in range(A.n))
-    import scipy.sparse.linalg as spla
-
-    lam_min = float(spla.eigsh(A.to_scipy(), k=1, sigma=0, which="LM", return_eigenvectors=False)[0])
-    err = np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x)
-    say(f"  iters {got.iters}/{ref.iters} relres {r:.2e} xdiff {err:.2e} bound {2 * lam_max / lam_min * tol:.2e}")
-    assert err <= 2 * lam_max / lam_min * tol
 
 
 @pytest.mark.parametrize("layout", ["bsr3", "sell"])
@@ -313,37 +312,38 @@ def test_device_pointers_torch(gpu_lib):
 def test_full_size_poisson3d_128(gpu_lib):
     """3D lognormal (sigma 1) Poisson on 128^3 with FSAI, the benchmark's
     single-system workload and launch configuration: A x bit-identical to the
-    oracle, the first iterations match the oracle's, and the converged
-    solution's residual, recomputed by the oracle's SpMV, meets 1e-8."""
+    oracle, and the converged solve (about 300 iterations to 1e-8) equal to
+    the oracle's bit for bit: status, iteration count and x. (With dot
+    products summed in different orders the oracle alone, 1 against 16
+    threads, already differs by 2.4e-9 in x after 300 iterations.)"""
     pcg = gpu_lib
     A = inputs.poisson(3, 128, 1.0, 0)
     b = inputs.rhs(A.n, 0)
-    say("full size 128^3", A.n, A.nnz)
+    th = max(1, min(16, len(__import__("os").sched_getaffinity(0))))
+    say("full size 128^3", A.n, A.nnz, "oracle threads", th)
+    G = oracle.fsai_g(A)
     with _solver(pcg) as s:
         s.set_matrix(A)
-        s.build_precond(pcg.G_FSAI)
+        s.set_precond(G)
         xs = np.random.default_rng(0).standard_normal(A.n)
-        assert np.array_equal(s.matvec(pcg.OP_A, xs), oracle.spmv(A, xs, threads=8))
-        few = s.solve(b, maxit=4)
+        assert np.array_equal(s.matvec(pcg.OP_A, xs), oracle.spmv(A, xs, threads=th))
         full = s.solve(b, tol=1e-8, maxit=5000)
-    G = oracle.fsai_g(A)
-    ref = oracle.pcg(A, G, b, maxit=4, delta_form=1, threads=8)
-    assert few.iters == ref.iters == 4
-    assert np.linalg.norm(few.x - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+    say("gpu iters", full.iters, "ms", full.t_solve_ms)
+    ref = oracle.pcg(A, G, b, tol=1e-8, maxit=5000, delta_form=1, threads=th)
+    say("oracle iters", ref.iters)
+    _check(full, ref)
     assert full.status == pcg.OK
-    r = b - oracle.spmv(A, full.x, threads=8)
+    r = b - oracle.spmv(A, full.x, threads=th)
     assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(b)
-    say("iters", full.iters, "ms", full.t_solve_ms)
 
 
 def test_pcg_synthetic_ppt(gpu_lib):
     """The paper's synthetic system A = P P^T + 1e-4 I (n = 12000, P density
-    3e-4) with FSAI. Its trajectory is very sensitive to rounding order (the
-    oracle's own two delta formulas differ by 2.8e-13 in x after 25
-    iterations, 5e-9 after 50, 3e-5 after 100, and 3.1e-11 at convergence
-    after 1459/1460 iterations): parity binds at 25 iterations; the converged
-    solve must meet the tolerance by the oracle's own residual and stay within
-    the oracle's iteration spread plus one."""
+    3e-4) with FSAI. Its trajectory is very sensitive to rounding order (with
+    order-dependent dot products the oracle's own two delta formulas differ
+    by 5e-9 in x after 50 iterations and 3e-5 after 100); with exact inner
+    products the GPU solve equals the oracle's bit for bit, after 25
+    iterations and converged (about 1460 iterations)."""
     pcg = gpu_lib
     A = inputs.synthetic_ppt(12000, 1)
     b = inputs.rhs(A.n, 1)
@@ -351,12 +351,10 @@ def test_pcg_synthetic_ppt(gpu_lib):
     got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=0.0, maxit=25)
     _check(got, ref)
     got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=1e-8, maxit=20000)
-    alt = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-8, maxit=20000, delta_form=0).iters
-    assert got.status == ref.status == pcg.OK
-    assert abs(got.iters - ref.iters) <= abs(alt - ref.iters) + 1, (got.iters, ref.iters, alt)
+    say(f"  iters {got.iters}/{ref.iters}")
+    _check(got, ref)
+    assert got.status == pcg.OK
     r = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
-    say(f"  iters {got.iters}/{ref.iters}/{alt} relres {r:.2e} xdiff "
-        f"{np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x):.2e}")
     assert r <= 1.0001e-8
 
 
@@ -369,12 +367,13 @@ def test_index_width_in_bytes_and_results(gpu_lib):
     A = inputs.poisson(3, 30, 1.0, 3)
     b = inputs.rhs(A.n, 3)
     g = oracle.tril_nnz(A)
-    ref = oracle.pcg(A, oracle.fsai_g(A), b, tol=1e-8, maxit=2000, delta_form=1)
+    G = oracle.fsai_g(A)
+    ref = oracle.pcg(A, G, b, tol=1e-8, maxit=2000, delta_form=1)
     xs = []
     for wide in (0, 1):
         with _solver(pcg, wide_index=wide) as s:
             s.set_matrix(A)
-            s.build_precond(pcg.G_FSAI)
+            s.set_precond(G)
             got = s.solve(b, tol=1e-8, maxit=2000)
         ib = 4 if wide else 2
         want = A.nnz * (8 + ib) + g * (16 + 2 * ib) + 12 * (A.n + 1) + 11 * A.n * 8
@@ -414,3 +413,28 @@ def test_fsai_g_in_padded_blocks(gpu_lib, layout, N):
     assert abs(kt["bytes"][2] - want) <= 1e-9 * want
     ref = oracle.pcg(A, G, b, tol=1e-10, maxit=3000, delta_form=1)
     _check(got, ref)
+
+
+RESTART_CASES = [(3, 16, 2.0, 1, 1e-13), (2, 48, 2.0, 2, 1e-13)]
+
+
+@pytest.mark.parametrize("case", RESTART_CASES)
+def test_restart_on_failed_true_residual(gpu_lib, case):
+    """Stopping rule with confirmation: with no residual replacement and a
+    tolerance near the attainable floor, the recurrence residual drifts below
+    the true one and claims convergence first; the true residual fails the
+    test, r is replaced by it and the iteration restarts from it (the oracle
+    restarts at least once on these systems). Near the floor the restart
+    count depends on every rounding; the GPU's equals the oracle's, with the
+    same iterations and x bit for bit."""
+    pcg = gpu_lib
+    dim, N, sigma, seed, tol = case
+    A = inputs.poisson(dim, N, sigma, seed)
+    b = inputs.rhs(A.n, seed)
+    got, ref = _parity(pcg, A, pcg.G_FSAI, b, tol=tol, maxit=5000, rr=0)
+    say(f"restart {dim}D {N}: gpu {got.iters} it, {got.restarts} restarts, relres {got.relres_true:.2e}; "
+        f"oracle {ref.iters} it, {ref.restarts} restarts")
+    assert ref.restarts >= 1
+    assert got.restarts == ref.restarts
+    _check(got, ref)
+    assert got.status == pcg.OK and got.relres_true <= tol
