@@ -24,8 +24,12 @@ Further sections, each under its own key of the same JSON line:
   elasticity Q1 elasticity, 64^3 free nodes x 3 dof (n = 786,432, 61.7M
              nonzeros): BF16/FP16 G with FP64 refinement to 1e-10 against the
              plain FP64 solve.
-The FP64 CPU oracle is timed on the host cores on the headline solve and also
-states each GPU solution's error against its own solution.
+The oracle leg (cpu_baseline) times the FP64 CPU oracle on the host cores on
+the headline solve, checks the GPU solve against it at full size (the oracle's
+FSAI G handed to the library: both trajectories bit for bit), and states every
+result's error against an oracle solution converged to 1e-12: the headline,
+the mixed-precision solves, the elasticity solves, and samples of the batched
+and served systems.
 """
 from __future__ import annotations
 
@@ -49,7 +53,7 @@ N_SIDE = 128
 TOL = 1e-8
 MAXIT = 5000
 KERNEL_SOURCES = ["paper_2510_27517_amd/csrc/kernels.hip", "paper_2510_27517_amd/csrc/kernels.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iter_A_poisson3d_128_f64_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
 SECTIONS = ["mixed", "sai_loss", "autotune", "batched", "serving", "elasticity", "synthetic"]
 
 
@@ -65,12 +69,13 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic():
-    """HBM bytes per A-kernel launch from the committed counter summary, if it
-    was taken on the current kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` on the headline system from the
+    committed counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(PROFILES, f"{kernel}_poisson3d_128_f64_traffic.md")
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_FILE).read()
+    text = open(path).read()
     m_sha = re.search(r"kernel_sources_sha:\s*([0-9a-f]+)", text)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_sha or not m_b or m_sha.group(1) != kernel_sha():
@@ -78,19 +83,45 @@ def stored_traffic():
     return float(m_b.group(1))
 
 
+def survey_bytes(n, a, g, sa, sg, sv, eps=False):
+    """Algorithmic bytes per launch of the three iteration kernels over int32
+    CSR (4-byte column indices and row pointers): A-kernel a(sa + 4) + 4(n+1)
+    + 2 n sv (reads d, writes q); G^T-kernel g(sg + 4) + 4(n+1) + 4 n sv
+    (reads r and q, writes r and t); G-kernel g(sg + 4) + 4(n+1) + 5 n sv
+    (reads t, d, x, writes d, x; one more with eps). Their sum is one
+    iteration with 11 vector streams."""
+    rp = 4.0 * (n + 1)
+    k = [a * (sa + 4) + rp + 2 * n * sv, g * (sg + 4) + rp + 4 * n * sv, g * (sg + 4) + rp + (6 if eps else 5) * n * sv]
+    return k + [sum(k)]
+
+
 def pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
-def cpu_baseline(A, b, gpu_iters, budget_s, gpu_solutions):
-    """The FP64 oracle (as it stands) on the host cores: the same solve, cut
-    to a bounded number of iterations when a full solve would exceed the
-    budget, scaled to the GPU's iteration count. When it runs to the
-    tolerance its solution also gives the GPU solutions' errors."""
+def _err(x, ref):
+    return float(np.linalg.norm(np.asarray(x) - ref) / np.linalg.norm(ref))
+
+
+def oracle_leg(pcg, torch, A, b, gpu, budget_s, extra_refs):
+    """The FP64 oracle as it stands, on the host cores:
+    - timing (the `cpu_baseline` figures): the headline solve with the oracle's
+      own FSAI G, as many iterations as the budget allows (all, normally),
+      scaled to the GPU's iteration count;
+    - parity at full size: the library solves the same system with the
+      oracle's G (its own FSAI agrees with the oracle's to 1e-13 row-normwise
+      only); with exact inner products on both sides the trajectories must be
+      identical: status, iterations and x bit for bit;
+    - accuracy: every result's error against an oracle solution converged to
+      1e-12 (the headline and mixed solves, elasticity, and samples of the
+      batched and served systems, each against its own reference).
+    The oracle's results do not depend on its thread count."""
     import oracle
 
     threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
     G = oracle.fsai_g(A)
+    t_fsai = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.pcg(A, G, b, tol=TOL, maxit=3, delta_form=1, threads=threads)
     per = (time.perf_counter() - t0) / 3
@@ -99,13 +130,43 @@ def cpu_baseline(A, b, gpu_iters, budget_s, gpu_solutions):
     r = oracle.pcg(A, G, b, tol=TOL, maxit=m, delta_form=1, threads=threads)
     el = time.perf_counter() - t0
     per_it = el / max(r.iters, 1)
+    gpu_iters = gpu["iters"]
     out = {"value": 1.0 / (per_it * gpu_iters), "unit": "solves/s", "cores": threads, "kind": "oracle",
-           "sample": f"{r.iters} FP64 oracle PCG iterations of the same 128^3 FSAI solve on {threads} host threads "
-                     f"({el:.1f} s, {per_it * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations",
-           "ms_per_iteration": per_it * 1e3, "oracle_iters": r.iters, "oracle_status": r.status}
+           "sample": f"{r.iters} FP64 oracle PCG iterations of the same 128^3 FSAI solve (oracle FSAI G) on "
+                     f"{threads} host threads ({el:.1f} s, {per_it * 1e3:.1f} ms/iteration), scaled to the GPU's "
+                     f"{gpu_iters} iterations",
+           "ms_per_iteration": per_it * 1e3, "oracle_iters": r.iters, "oracle_status": r.status,
+           "oracle_fsai_s": round(t_fsai, 2)}
+    # full-size parity: the library on the oracle's G, the launch configuration timed above
     if r.status == oracle.OK:
-        nx = float(np.linalg.norm(r.x))
-        out["gpu_error_vs_oracle"] = {k: float(np.linalg.norm(x - r.x) / nx) for k, x in gpu_solutions.items()}
+        with pcg.Solver(pcg.default_config()) as s:
+            s.set_matrix(A)
+            s.set_precond(rowptr=G.rowptr, col=G.col, val=G.val)
+            got = s.solve(torch.from_numpy(b).to("cuda:0"), tol=TOL, maxit=MAXIT)
+        xg = got.x.cpu().numpy()
+        out["parity_full_size"] = {
+            "workload": "the headline system solved by the library with the oracle's FSAI G",
+            "gpu_iters": got.iters, "oracle_iters": r.iters, "gpu_status": got.status,
+            "x_bitwise_equal": bool(np.array_equal(xg, r.x)), "rel_diff_x": _err(xg, r.x),
+            "max_abs_diff_x": float(np.max(np.abs(xg - r.x)))}
+    # accuracy against solutions converged to 1e-12
+    ref = oracle.pcg(A, G, b, tol=1e-12, maxit=4 * MAXIT, delta_form=1, threads=threads)
+    acc = {"reference": f"oracle FSAI PCG to 1e-12 ({ref.iters} iterations, status {ref.status})"}
+    for k, x in gpu["solutions"].items():
+        acc[k] = _err(x, ref.x)
+    for name, items in extra_refs.items():
+        got = {}
+        for tag, (Ak, bk, xs) in items.items():
+            t1 = time.perf_counter()
+            Gk = oracle.fsai_g(Ak)
+            rk = oracle.pcg(Ak, Gk, bk, tol=1e-12, maxit=50000, delta_form=1, threads=threads)
+            e = {"n": Ak.n, "oracle_iters": rk.iters, "oracle_status": rk.status,
+                 "oracle_s": round(time.perf_counter() - t1, 1)}
+            for sol, xk in xs.items():
+                e[sol] = _err(xk, rk.x)
+            got[tag] = e
+        acc[name] = got
+    out["error_vs_oracle_1e-12"] = acc
     return out
 
 
@@ -277,6 +338,9 @@ def section_batched(pcg, inputs, count):
     st = [r["status"] for _, r in res]
     lat = [r["t_latency_ms"] for _, r in res]
     solve = [r["t_solve_ms"] for _, r in res]
+    order = np.argsort([sd["A"].n for sd in systems])
+    samples = {f"system{int(i)}": (systems[i]["A"], systems[i]["b"], {"x": res[i][0]})
+               for i in order[np.linspace(0, count - 1, min(6, count)).astype(int)]}
     return {"workload": f"{count} systems: 2D side U[16,256] / 3D side U[8,64] lognormal sigma 0.5 Poisson, "
                         "FSAI G built on the host, A/vectors/G f32, FP64 refinement, tol 1e-6",
             "systems": count, "rows_total": n_tot, "nnz_total": nnz_tot,
@@ -287,7 +351,7 @@ def section_batched(pcg, inputs, count):
             "max_relres_true_fp64": max(r["relres_true"] for _, r in res),
             "inner_iters_max": max(r["iters"] for _, r in res),
             "note": "wall time from submission to the last completion, including host FSAI construction and "
-                    "uploads"}
+                    "uploads"}, samples
 
 
 def serving_requests(inputs, count):
@@ -358,6 +422,9 @@ def section_serving(pcg, inputs, count, iters_per_step):
         wall = time.perf_counter() - t0
     mu = count / wall
     ns = [r["A"].n for r in reqs]
+    order = np.argsort(ns)
+    samples = {f"request{int(i)}": (reqs[i]["A"], reqs[i]["b"], {"x": res[i][0]})
+               for i in order[(np.array([0.1, 0.3, 0.5, 0.7, 0.9]) * (count - 1)).astype(int)]}
     out = {"workload": f"{count} RGG Laplacian + 1e-3 I requests, n log-uniform [1e3,1e6] (mean {np.mean(ns):.0f}), "
                        "mean degree ~8, weights U[0.1,10]; f32 A/vectors, bf16 FSAI G, FP64 refinement, tol 1e-6; "
                        "Poisson arrivals at 0.5/0.8/0.95 of the closed-loop rate",
@@ -393,7 +460,7 @@ def section_serving(pcg, inputs, count, iters_per_step):
         "ok": sum(1 for _, r in res_d if r["status"] == pcg.OK),
         "note": "the scheduler thread uploads A in FP64 CSR and factors each G at admission, serially; the "
                 "host builder runs on worker threads alongside the GPU"}
-    return out
+    return out, samples
 
 
 def section_elasticity(pcg, inputs, N):
@@ -411,6 +478,7 @@ def section_elasticity(pcg, inputs, N):
     out = {"workload": f"Q1 elasticity {N}^3 free nodes x 3 dof, E lognormal sigma 1, nu 0.3, FSAI G, tol 1e-10",
            "n": A.n, "nnz": A.nnz, "t_construct_fsai_s": round(t_fsai, 2), "t_construct_fsai_device_s": round(t_dev, 3)}
     x64 = None
+    xs = {}
     for name, kw in [("fp64", dict()), ("f32_bf16_refined", dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16",
                                                                    refine=1)),
                      ("f32_f16_refined", dict(vec_dtype="f32", a_dtype="f32", g_dtype="f16", refine=1))]:
@@ -423,13 +491,14 @@ def section_elasticity(pcg, inputs, N):
             ms = (time.perf_counter() - t0) * 1e3
         d = {"time_to_tol_ms": round(ms, 2), "status": r.status, "iters": r.iters, "outer_iters": r.outer_iters,
              "relres_true_fp64": r.relres_true}
+        xs[name] = r.x
         if x64 is None:
             x64 = r.x
             out["ms_per_iter_fp64"] = round(ms / max(r.iters, 1), 4)
         else:
             d["error_vs_fp64_gpu"] = float(np.linalg.norm(r.x - x64) / np.linalg.norm(x64))
         out[name] = d
-    return out
+    return out, {f"{N}^3x3": (A, b, xs)}
 
 
 # ---------------------------------------------------------------- main
@@ -500,21 +569,52 @@ def main():
 
     log("kernel timing")
     kt = solver.time_kernels(args.kernel_iters)
-    ms_a, bytes_a = kt["ms"][0], kt["bytes"][0]
-    achieved = bytes_a / (ms_a * 1e-3) / 1e9
-    traffic = stored_traffic()
+    names = ["k_iter_A", "k_iter_GT", "k_iter_G"]
+    sv = survey_bytes(A.n, A.nnz, int(G[1].shape[0]), 8, 8, 8)
+    kernels = {name: {"avg_ms": kt["ms"][k], "layout_bytes": kt["bytes"][k], "alg_bytes": sv[k],
+                      "alg_gbps": sv[k] / (kt["ms"][k] * 1e-3) / 1e9,
+                      "layout_gbps": kt["bytes"][k] / (kt["ms"][k] * 1e-3) / 1e9}
+               for k, name in enumerate(names)}
+    dom = max(range(3), key=lambda k: kt["ms"][k])
+    achieved = sv[dom] / (kt["ms"][dom] * 1e-3) / 1e9
+    traffic = stored_traffic(names[dom])
+    ms_iter = ms_per_step / iters
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "k_iter_A (q = A d with the partial sums of d^T q)",
-                "bytes_per_launch": bytes_a, "avg_launch_ms": ms_a}
-    kernels = {name: {"avg_ms": kt["ms"][k], "alg_bytes": kt["bytes"][k],
-                      "gbps": kt["bytes"][k] / (kt["ms"][k] * 1e-3) / 1e9}
-               for k, name in enumerate(["k_iter_A", "k_iter_GT", "k_iter_G"])}
+                "kernel": names[dom], "alg_bytes_per_launch": sv[dom], "avg_launch_ms": kt["ms"][dom],
+                "bytes_basis": "int32 CSR indices and row pointers, 8-byte values, the vector streams the kernel "
+                               "needs (the kernel stores 16-bit column differences, so it moves fewer)",
+                "per_iteration": {"alg_bytes": sv[3], "ms": round(ms_iter, 5),
+                                  "achieved_gbps": round(sv[3] / (ms_iter * 1e-3) / 1e9, 1),
+                                  "frac": round(sv[3] / (ms_iter * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                  "note": "one iteration's algorithmic bytes (11 vector streams) over the timed "
+                                          "solve's time per iteration (graph gaps and replacement steps "
+                                          "included)"}}
+    # the same kernels with every matrix read nontemporally (nothing kept in
+    # the memory-side cache): the HBM-only figures
+    log("kernel timing, nontemporal loads only")
+    with pcg.Solver(pcg.default_config(device=0, cache_mb=-1)) as snt:
+        snt.set_matrix(A)
+        snt.set_precond(rowptr=G[0], col=G[1], val=G[2])
+        snt.solve(b_dev, tol=TOL, maxit=MAXIT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rnt = snt.solve(b_dev, tol=TOL, maxit=MAXIT)
+        ms_nt = (time.perf_counter() - t0) * 1e3
+        ktn = snt.time_kernels(args.kernel_iters)
+    hbm_only = {name: {"avg_ms": ktn["ms"][k], "alg_gbps": sv[k] / (ktn["ms"][k] * 1e-3) / 1e9,
+                       "frac": sv[k] / (ktn["ms"][k] * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+                for k, name in enumerate(names)}
+    hbm_only["solve"] = {"time_to_tol_ms": round(ms_nt, 3), "iters": rnt.iters,
+                         "alg_gbps_per_iter": round(sv[3] / (ms_nt / rnt.iters * 1e-3) / 1e9, 1),
+                         "frac_per_iter": round(sv[3] / (ms_nt / rnt.iters * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
     copy = None
     if not args.no_copy_probe:
-        log("copy probe")
+        log("copy and read probes")
         gb, ms = pcg.copy_bandwidth(4 << 30, reps=10)
-        copy = {"gbps": round(gb, 1), "bytes": 4 << 30, "ms_per_copy": ms}
+        gr, msr = pcg.read_bandwidth(4 << 30, reps=10)
+        copy = {"copy_gbps": round(gb, 1), "read_gbps": round(gr, 1), "bytes": 4 << 30, "ms_per_copy": ms,
+                "ms_per_read": msr}
     relres = last.relres_true  # ||b - A x|| / ||b|| from the library's FP64 residual kernel
     solver.close()
     # the same FSAI factored on the device (pattern work on the host, rows on
@@ -527,7 +627,7 @@ def main():
         s2.build_precond(pcg.G_FSAI)
         t_construct_dev = time.perf_counter() - t0
 
-    extra, sols = {}, {"fp64": x_fp64}
+    extra, sols, refs = {}, {"fp64": x_fp64}, {}
     if "mixed" in sections:
         log("mixed precision")
         extra["mixed"], sols["mixed_f32_bf16_refined"] = section_mixed(pcg, torch, A, G, b_dev, max(3, args.steps // 2),
@@ -538,19 +638,19 @@ def main():
     if "autotune" in sections:
         log("autotune")
         extra["autotune"] = section_autotune(pcg, torch, A, G, b_dev, max(3, args.steps // 2), ms_per_step)
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        cpu = cpu_baseline(A, b, iters, args.cpu_budget_s, sols)
-    del b_dev
     if "batched" in sections and args.batch_systems > 0:
-        extra["batched"] = section_batched(pcg, inputs, args.batch_systems)
+        extra["batched"], refs["batched_sample"] = section_batched(pcg, inputs, args.batch_systems)
     if "serving" in sections and args.serve_requests > 0:
-        extra["serving"] = section_serving(pcg, inputs, args.serve_requests, args.serve_step)
+        extra["serving"], refs["served_sample"] = section_serving(pcg, inputs, args.serve_requests, args.serve_step)
     if "elasticity" in sections and args.elasticity_n > 0:
-        extra["elasticity"] = section_elasticity(pcg, inputs, args.elasticity_n)
+        extra["elasticity"], refs["elasticity"] = section_elasticity(pcg, inputs, args.elasticity_n)
     if "synthetic" in sections and args.synthetic_batch > 0:
         extra["synthetic"] = section_synthetic(pcg, inputs, args.synthetic_batch)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("oracle leg: cpu baseline, full-size parity, errors against converged oracle solutions")
+        cpu = oracle_leg(pcg, torch, A, b, {"iters": iters, "solutions": sols}, args.cpu_budget_s, refs)
+    del b_dev
 
     line = {
         "metric": METRIC, "value": round(1e3 / ms_per_step, 3), "unit": "solves/s", "n_gpus": 1,
@@ -562,7 +662,8 @@ def main():
         "hbm_gbps_per_iter": round(gbps_iter, 1), "alg_bytes_per_iter": bpi,
         "relres_true_fp64": relres, "t_construct_s": round(t_construct, 3),
         "t_construct_host_total_s": round(t_construct + t_place, 4), "t_construct_device_s": round(t_construct_dev, 4),
-        "roofline": roofline, "kernels": kernels, "copy_probe": copy, "cpu_baseline": cpu,
+        "roofline": roofline, "kernels": kernels, "hbm_only": hbm_only, "stream_probes": copy,
+        "cpu_baseline": cpu,
         "kernel_sources_sha": kernel_sha(),
     }
     line.update(extra)
