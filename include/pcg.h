@@ -246,6 +246,20 @@ int pcg_matvec(pcg_ctx *ctx, int op, const double *x, double *y, int on_device);
  * PCG_EINVAL (k < 1, null W), PCG_ESTATE (A or G unset), PCG_ENOMEM. */
 int pcg_sai_loss(pcg_ctx *ctx, int32_t k, const double *W, int on_device, double *sai, double *l2, double *cs);
 
+/* Allocation-free variant of pcg_sai_loss, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation). Same losses, same kernels and summation order as
+ * pcg_sai_loss, so the same values. W must be device memory of the context's
+ * GPU (n x k row-major FP64, borrowed for the call); sai, l2, cs are host
+ * arrays of k doubles, each may be NULL. Scratch (2 n k + 2563 k doubles,
+ * each part 256-byte aligned) comes from the library's file-scope device
+ * array of 64 MiB, one per GPU, held until the process ends; a larger need
+ * returns PCG_EINVAL with a message, and nothing is allocated. Every call on
+ * one GPU (from any context) shares that GPU's array, and it keeps the last
+ * call's contents: calls that overlap on one GPU race. PCG_ESTATE (A or G
+ * unset), PCG_EINVAL (k < 1, null W, too large), PCG_EDEVICE. */
+int pcg_sai_loss_noalloc(pcg_ctx *ctx, int32_t k, const double *W, double *sai, double *l2, double *cs);
+
 /* Measurement (not an operation of the paper, whose evaluation times whole
  * solves and splits them into construction, apply and CG time, Sec. 4.2 and
  * Tab. "time-decomposition": a facility of this library for per-kernel

@@ -252,5 +252,20 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int grid, hipS
 // written only for data no probe uses.
 hipError_t launch_read(const void *src, int64_t bytes, uint32_t *sink, int grid, hipStream_t s);
 
+// ---- the allocation-free loss entry point
+//
+// The library's file-scope device scratch: kStaticScratchBytes on every device
+// the library runs on, held until the process ends, shared by every call on
+// that device. static_scratch looks its address up on `device` (which must be
+// the current device) the first time and returns the cached address after;
+// the array's host-side name is never a device address.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+hipError_t static_scratch(int device, void **ptr);
+
+// Final sums of the loss partials (kLossGrid x 5 x k, as launch_loss_partials
+// writes them): for each probe p, the five sums over the workgroups in
+// ascending order, then out[p] = sai, out[k + p] = l2 and
+// out[2k + p] = cs = (w^T y) / (sqrt(w^T w) sqrt(y^T y)).
+hipError_t launch_loss_final(int32_t k, const double *part, double *out, hipStream_t s);
 
 }  // namespace pcgk

@@ -42,6 +42,7 @@
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -1255,6 +1256,49 @@ __global__ __launch_bounds__(kBlock) void k_loss_partials(int32_t n, int32_t k, 
   }
 }
 
+// One thread per probe: the workgroups' partial sums added in ascending
+// workgroup order, then the three losses.
+__global__ __launch_bounds__(kBlock) void k_loss_final(int32_t k, const double *__restrict__ part_,
+                                                       double *__restrict__ out_) {
+  const int32_t p = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+  if (p >= k) return;
+  GLOBAL const double *part = gl(part_);
+  GLOBAL double *out = gl(out_);
+  double q[5] = {0, 0, 0, 0, 0};
+  for (int b = 0; b < kLossGrid; ++b)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) q[j] += part[((int64_t)b * 5 + j) * k + p];
+  out[p] = q[0];
+  out[(int64_t)k + p] = q[1];
+  out[2 * (int64_t)k + p] = q[2] / (sqrt(q[4]) * sqrt(q[3]));
+}
+
+// The allocation-free entry point's scratch: one copy per device, allocated
+// by the runtime with the code object. Host code uses only the per-device
+// address that hipGetSymbolAddress returns for it.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(int device, void **ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline int ew_grid(int64_t n) {
@@ -1465,6 +1509,12 @@ hipError_t launch_loss_partials(int32_t n, int32_t k, const double *W, const dou
                                 hipStream_t s) {
   if (n <= 0 || k <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_loss_partials, dim3(kLossGrid), dim3(kBlock), 0, s, n, k, W, Y, na, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_final(int32_t k, const double *part, double *out, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loss_final, dim3((k + kBlock - 1) / kBlock), dim3(kBlock), 0, s, k, part, out);
   return hipGetLastError();
 }
 

@@ -639,6 +639,7 @@ struct pcg_ctx {
   SysDev *d_dir = nullptr;
   void *loss_buf = nullptr;  // scratch of pcg_sai_loss, kept between calls
   size_t loss_bytes = 0;
+  void *static_scratch = nullptr;  // this device's copy of the library's file-scope scratch
   State *d_states = nullptr;  // kDirCap * 2
   State *h_states = nullptr;  // pinned mirror
   State *h_init = nullptr;    // pinned upload staging (2 slots)
@@ -1993,6 +1994,11 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
     return rc;
   };
   if (hipSetDevice(cfg->device) != hipSuccess) return fail(PCG_EDEVICE);
+  // the device address of the file-scope scratch (looked up once per device)
+  if (pcgk::static_scratch(cfg->device, &ctx->static_scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->static_scratch = nullptr;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->cus = prop.multiProcessorCount;
@@ -2750,6 +2756,61 @@ int pcg_sai_loss(pcg_ctx *ctx, int32_t k, const double *W, int on_device, double
     if (sai) sai[p] = q[0];
     if (l2) l2[p] = q[1];
     if (cs) cs[p] = q[2] / (std::sqrt(q[4]) * std::sqrt(q[3]));
+  }
+  return PCG_OK;
+}
+
+int pcg_sai_loss_noalloc(pcg_ctx *ctx, int32_t k, const double *W, double *sai, double *l2, double *cs) {
+  if (!ctx) return PCG_EINVAL;
+  if (k < 1 || !W) {
+    ctx->err = "pcg_sai_loss_noalloc: need k >= 1 probes and W";
+    return PCG_EINVAL;
+  }
+  if (!ctx->have_a || !ctx->have_g) {
+    ctx->err = "pcg_sai_loss_noalloc: matrix and preconditioner must be set";
+    return PCG_ESTATE;
+  }
+  if (!ctx->static_scratch) {
+    ctx->err = "pcg_sai_loss_noalloc: the device address of the static scratch is unknown";
+    return PCG_EDEVICE;
+  }
+  Sys &S = ctx->single;
+  const int32_t n = S.n;
+  const size_t nk = (size_t)n * (size_t)k;
+  const size_t pb = sizeof(double) * (size_t)pcgk::kLossGrid * 5 * (size_t)k;
+  const size_t need = 2 * align_up(8 * nk) + align_up(pb) + align_up(8 * 3 * (size_t)k);
+  if (need > pcgk::kStaticScratchBytes) {
+    char m[200];
+    std::snprintf(m, sizeof m,
+                  "pcg_sai_loss_noalloc: n = %d with k = %d probes needs %zu bytes of scratch, above the %zu of "
+                  "the static scratch",
+                  n, k, need, pcgk::kStaticScratchBytes);
+    ctx->err = m;
+    return PCG_EINVAL;
+  }
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  Carver c{(uint8_t *)ctx->static_scratch};
+  double *T = (double *)c.take(8 * nk), *U = (double *)c.take(8 * nk);
+  double *part = (double *)c.take(pb), *out = (double *)c.take(8 * 3 * (size_t)k);
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chain(hipDeviceSynchronize());  // W may come from work queued on another stream
+  const double eps = ctx->cfg.eps;
+  chain(pcgk::launch_spmm(S.dev.GT, k, W, 1.0, nullptr, 0.0, T, s));  // T = G^T W
+  chain(pcgk::launch_spmm(S.dev.G, k, T, 1.0 / (S.g_scale * S.g_scale), eps != 0.0 ? W : nullptr, eps, U, s));
+  chain(pcgk::launch_spmm(S.dev.A, k, U, 1.0, nullptr, 0.0, T, s));  // Y = A M^-1 W
+  chain(pcgk::launch_loss_partials(n, k, W, T, ctx->a_mean_abs, part, s));
+  chain(pcgk::launch_loss_final(k, part, out, s));
+  double *dst[3] = {sai, l2, cs};
+  for (int j = 0; j < 3; ++j)
+    if (dst[j]) chain(hipMemcpyAsync(dst[j], out + (size_t)j * k, 8 * (size_t)k, hipMemcpyDeviceToHost, s));
+  chain(hipStreamSynchronize(s));
+  if (e != hipSuccess) {
+    ctx->err = std::string("pcg_sai_loss_noalloc: ") + hipGetErrorString(e);
+    return PCG_EDEVICE;
   }
   return PCG_OK;
 }

@@ -30,7 +30,7 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 # every symbol include/pcg.h declares
 EXPORTS = [
     "pcg_config_default", "pcg_create", "pcg_destroy", "pcg_set_matrix", "pcg_set_precond", "pcg_build_precond",
-    "pcg_solve", "pcg_matvec", "pcg_sai_loss", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
+    "pcg_solve", "pcg_matvec", "pcg_sai_loss", "pcg_sai_loss_noalloc", "pcg_validate_csr", "pcg_g_nnz", "pcg_build_g_host", "pcg_bytes_per_iter",
     "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth", "pcg_read_bandwidth",
     "pcg_submit_batch",
     "pcg_progress", "pcg_poll", "pcg_wait", "pcg_solve_batch", "pcg_pool_info", "pcg_estimate_bytes",
@@ -142,6 +142,7 @@ def load():
     lib.pcg_set_precond.argtypes = [P, i32, i64, P, P, P, c_int]
     lib.pcg_build_precond.argtypes = [P, c_int, ctypes.c_uint64]
     lib.pcg_sai_loss.argtypes = [P, i32, P, c_int, P, P, P]
+    lib.pcg_sai_loss_noalloc.argtypes = [P, i32, P, P, P, P]
     lib.pcg_solve.argtypes = [P, P, P, dbl, c_int, c_int, ctypes.POINTER(Result)]
     lib.pcg_matvec.argtypes = [P, c_int, P, P, c_int]
     lib.pcg_validate_csr.argtypes = [i32, i64, P, P, c_int]
@@ -378,6 +379,19 @@ class Solver:
         out = {name: np.zeros(k) for name in ("sai", "l2", "cs")}
         self._check(self._lib.pcg_sai_loss(self._h, k, pw, dev, out["sai"].ctypes.data, out["l2"].ctypes.data,
                                            out["cs"].ctypes.data), "pcg_sai_loss")
+        return out
+
+    def sai_loss_noalloc(self, W):
+        """sai_loss with the library's static device scratch (no device
+        allocation); W must be a contiguous FP64 n x k tensor on the GPU."""
+        if not _is_torch(W) or not W.is_cuda or W.dtype != __import__("torch").float64 or W.ndim != 2 \
+                or not W.is_contiguous():
+            raise PCGError(EINVAL, "sai_loss_noalloc: W must be a contiguous float64 n x k GPU tensor")
+        k = int(W.shape[1])
+        out = {name: np.zeros(k) for name in ("sai", "l2", "cs")}
+        self._check(self._lib.pcg_sai_loss_noalloc(self._h, k, W.data_ptr(), out["sai"].ctypes.data,
+                                                   out["l2"].ctypes.data, out["cs"].ctypes.data),
+                    "pcg_sai_loss_noalloc")
         return out
 
     def autotune(self, iters: int = 20):
