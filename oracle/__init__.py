@@ -81,6 +81,10 @@ def _load():
     lib.or_tril_nnz.argtypes = [i32, P, P]
     lib.or_fsai_lower.restype = ctypes.c_int
     lib.or_fsai_lower.argtypes = [i32, P, P, P, P, P, P, ctypes.c_int]
+    lib.or_bfsai_pattern.restype = ctypes.c_int64
+    lib.or_bfsai_pattern.argtypes = [i32, P, P, ctypes.c_int, P]
+    lib.or_fsai_block_lower.restype = ctypes.c_int
+    lib.or_fsai_block_lower.argtypes = [i32, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int]
     lib.or_g_cfg1.restype = ctypes.c_int
     lib.or_g_cfg1.argtypes = [i32, P, P, P, P, P, P]
     lib.or_max_threads.restype = ctypes.c_int
@@ -236,6 +240,28 @@ def fsai_lower(A, threads: int | None = None) -> Mat:
 def fsai_g(A, threads: int | None = None) -> Mat:
     """G = G_L^T, so that M^-1 = G G^T = G_L^T G_L ~ A^-1."""
     return transpose(fsai_lower(A, threads))
+
+
+def fsai_block_lower(A, b: int = 3, threads: int | None = None) -> Mat:
+    """Block FSAI G_L (b x b blocks, block-lower on tril(A)'s block pattern,
+    every block full) for an exactly b x b blocked A; A^-1 ~ G_L^T G_L."""
+    A = _mat(A)
+    grp = np.empty(A.n + 1, np.int32)
+    m = int(_load().or_bfsai_pattern(A.n, _p(A.rowptr), _p(A.col), int(b), _p(grp)))
+    if m < 0:
+        raise ValueError("block FSAI needs an exactly b x b blocked matrix")
+    gci = np.empty(m, np.int32)
+    gv = np.empty(m, np.float64)
+    th = max_threads() if threads is None else int(threads)
+    rc = _load().or_fsai_block_lower(A.n, _p(A.rowptr), _p(A.col), _p(A.val), int(b), _p(grp), _p(gci), _p(gv), th)
+    if rc != OK:
+        raise ValueError(f"or_fsai_block_lower failed with {rc}")
+    return Mat(grp, gci, gv)
+
+
+def fsai_block_g(A, b: int = 3, threads: int | None = None) -> Mat:
+    """G = G_L^T of the block FSAI, so that M^-1 = G G^T = G_L^T G_L."""
+    return transpose(fsai_block_lower(A, b, threads))
 
 
 def g_cfg1(A) -> Mat:

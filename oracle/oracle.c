@@ -518,6 +518,132 @@ int or_fsai_lower(int32_t n, const int32_t *rp, const int32_t *ci, const double 
 }
 
 /*
+ * Block FSAI for systems with b unknowns per node (the paper's blocked
+ * systems, Sec. 3.1, whose learned G carries one b x b block per nonzero
+ * block of A, Sec. 3.2.2). A must be exactly b x b blocked: n = b N and the b
+ * rows of block row I store the same complete column blocks. G_L is block
+ * lower triangular on the block pattern of tril(A), every block full (zeros
+ * included), with A^-1 ~ G_L^T G_L:
+ *   for block row I with block columns J = { J <= I : A_IJ != 0 } (I last),
+ *   solve A[J,J] X = E (E: the last b columns of the identity of size b|J|)
+ *   by dense Cholesky; with X_II = C C^T (C lower, the Cholesky factor of
+ *   X's last b x b block), block row I of G_L is C^-1 X^T.
+ * Then each diagonal block of G_L A G_L^T is the identity, and
+ * G_L^T G_L = sum_I X X_II^-1 X^T does not depend on the choice of C. With
+ * b = 1 this is the scalar FSAI above. Output: CSR sized n+1 / b^2 times the
+ * block count of tril (rows of a block row list the same columns).
+ */
+static int bfsai_blockrow(int32_t I, int b, const int32_t *rp, const int32_t *ci, const double *v, int32_t *gci,
+                          double *gv, int32_t rowlen, int32_t *J, double *S, double *X, double *C) {
+  const int32_t r = b * I;
+  int m = 0; /* block columns of the tril part of block row I */
+  for (int32_t k = rp[r]; k < rp[r + 1]; k += b)
+    if (ci[k] / b <= I) J[m++] = ci[k] / b;
+  if (m == 0 || J[m - 1] != I) return OR_EINVAL;
+  const int M = b * m;
+  for (int a = 0; a < M; ++a)
+    for (int c = 0; c < M; ++c) S[a * M + c] = csr_get(rp, ci, v, b * J[a / b] + a % b, b * J[c / b] + c % b);
+  for (int c = 0; c < M; ++c) { /* S = L L^T, L in the lower triangle */
+    double dsum = S[c * M + c];
+    for (int k = 0; k < c; ++k) dsum -= S[c * M + k] * S[c * M + k];
+    if (!(dsum > 0.0)) return OR_EBREAKDOWN;
+    const double l = sqrt(dsum);
+    S[c * M + c] = l;
+    for (int a = c + 1; a < M; ++a) {
+      double e = S[a * M + c];
+      for (int k = 0; k < c; ++k) e -= S[a * M + k] * S[c * M + k];
+      S[a * M + c] = e / l;
+    }
+  }
+  for (int q = 0; q < b; ++q) { /* column q of X: L z = e_(M-b+q), L^T x = z */
+    double *x = X + (size_t)q * M;
+    for (int a = 0; a < M; ++a) {
+      double e = (a == M - b + q) ? 1.0 : 0.0;
+      for (int k = 0; k < a; ++k) e -= S[a * M + k] * x[k];
+      x[a] = e / S[a * M + a];
+    }
+    for (int a = M - 1; a >= 0; --a) {
+      double e = x[a];
+      for (int k = a + 1; k < M; ++k) e -= S[k * M + a] * x[k];
+      x[a] = e / S[a * M + a];
+    }
+  }
+  for (int p = 0; p < b; ++p) /* X_II = C C^T (C lower) */
+    for (int q = 0; q <= p; ++q) {
+      double e = X[(size_t)q * M + M - b + p];
+      for (int k = 0; k < q; ++k) e -= C[p * b + k] * C[q * b + k];
+      if (p == q) {
+        if (!(e > 0.0)) return OR_EBREAKDOWN;
+        C[p * b + p] = sqrt(e);
+      } else {
+        C[p * b + q] = e / C[q * b + q];
+      }
+    }
+  for (int a = 0; a < M; ++a) /* W = C^-1 X^T, column a by forward substitution */
+    for (int p = 0; p < b; ++p) {
+      double e = X[(size_t)p * M + a];
+      for (int k = 0; k < p; ++k) e -= C[p * b + k] * gv[(size_t)k * rowlen + a];
+      gv[(size_t)p * rowlen + a] = e / C[p * b + p];
+    }
+  for (int p = 0; p < b; ++p)
+    for (int a = 0; a < M; ++a) gci[(size_t)p * rowlen + a] = b * J[a / b] + a % b;
+  return OR_OK;
+}
+
+/* Row pointers of the block FSAI's pattern (b^2 per tril block); -1 when A
+ * is not exactly b x b blocked. */
+int64_t or_bfsai_pattern(int32_t n, const int32_t *rp, const int32_t *ci, int b, int32_t *grp) {
+  if (b < 1 || n % b) return -1;
+  grp[0] = 0;
+  for (int32_t I = 0; I < n / b; ++I) {
+    const int32_t r = b * I, len = rp[r + 1] - rp[r];
+    if (len % b) return -1;
+    int32_t m = 0;
+    for (int s = 0; s < b; ++s) {
+      if (rp[r + s + 1] - rp[r + s] != len) return -1;
+      for (int32_t k = 0; k < len; k += b) {
+        const int32_t c0 = ci[rp[r + s] + k];
+        if (c0 % b) return -1;
+        for (int j = 0; j < b; ++j)
+          if (ci[rp[r + s] + k + j] != c0 + j || ci[rp[r] + k + j] != c0 + j) return -1;
+        if (s == 0 && c0 / b <= I) m++;
+      }
+    }
+    for (int s = 0; s < b; ++s) grp[r + s + 1] = grp[r + s] + b * m;
+  }
+  return grp[n];
+}
+
+int or_fsai_block_lower(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int b, const int32_t *grp,
+                        int32_t *gci, double *gv, int threads) {
+  int32_t mmax = 1;
+  for (int32_t I = 0; I < n / b; ++I) {
+    const int32_t m = (grp[b * I + 1] - grp[b * I]) / b;
+    if (m > mmax) mmax = m;
+  }
+  const int Mx = b * mmax;
+  int rc = OR_OK;
+#pragma omp parallel num_threads(threads > 0 ? threads : 1)
+  {
+    int32_t *J = (int32_t *)malloc(sizeof(int32_t) * mmax);
+    double *S = (double *)malloc(sizeof(double) * (size_t)Mx * Mx);
+    double *X = (double *)malloc(sizeof(double) * (size_t)Mx * b);
+    double *C = (double *)malloc(sizeof(double) * (size_t)b * b);
+    int my = OR_OK;
+#pragma omp for schedule(dynamic, 64)
+    for (int32_t I = 0; I < n / b; ++I) {
+      const int32_t r = b * I, rowlen = grp[r + 1] - grp[r];
+      const int e = bfsai_blockrow(I, b, rp, ci, v, gci + grp[r], gv + grp[r], rowlen, J, S, X, C);
+      if (e != OR_OK && my == OR_OK) my = e;
+    }
+#pragma omp critical
+    if (my != OR_OK && rc == OR_OK) rc = my;
+    free(J); free(S); free(X); free(C);
+  }
+  return rc;
+}
+
+/*
  * The fixed lower-triangular G of the small 2D Poisson workload: on tril(A)'s
  * pattern, G_ii = 1/sqrt(A_ii) and G_ij = -0.25 A_ij / sqrt(A_ii A_jj) for
  * j < i. Output arrays sized n+1 / or_tril_nnz.

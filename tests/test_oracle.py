@@ -855,3 +855,102 @@ def test_pcg_is_independent_of_the_thread_count():
     for th in (3, 8):
         rt = oracle.pcg(A, G, b, tol=1e-10, maxit=500, delta_form=1, threads=th)
         assert rt.iters == r1.iters and np.array_equal(rt.x, r1.x)
+
+
+# ------------------------------------------------------------- block FSAI
+
+def _kaporin_log(B):
+    n = B.shape[0]
+    sign, logdet = np.linalg.slogdet(B)
+    assert sign > 0
+    return n * np.log(np.trace(B) / n) - logdet
+
+
+def test_block_fsai_with_b1_is_the_scalar_fsai():
+    for A in (inputs.poisson(2, 9, 1.0, 2), inputs.poisson(3, 5, 1.0, 3)):
+        G1, B1 = oracle.fsai_lower(A), oracle.fsai_block_lower(A, b=1)
+        assert np.array_equal(G1.rowptr, B1.rowptr) and np.array_equal(G1.col, B1.col)
+        assert np.array_equal(G1.val, B1.val)
+
+
+def test_block_fsai_invariants_on_elasticity():
+    """Blocked 3-dof system: G_L is block lower with full 3x3 blocks on the
+    block pattern of tril(A); each diagonal block of G_L A G_L^T is I_3; and
+    (G_L A)_IJ = 0 for every other block J of row I's pattern."""
+    A = inputs.elasticity(3, 1.0, 0.3, 1)
+    GL = oracle.fsai_block_lower(A)
+    Gd, Ad = CSR(GL.rowptr, GL.col, GL.val).to_dense(), A.to_dense()
+    n = A.n
+    assert np.count_nonzero(np.triu(Gd[:, :], 3)) == 0  # no block above the diagonal block
+    P = Gd @ Ad @ Gd.T
+    GA = Gd @ Ad
+    for I in range(n // 3):
+        assert np.allclose(P[3 * I:3 * I + 3, 3 * I:3 * I + 3], np.eye(3), rtol=0, atol=1e-13)
+        blocks = sorted({int(c) // 3 for c in GL.col[GL.rowptr[3 * I]:GL.rowptr[3 * I + 1]]})
+        assert blocks[-1] == I and all(np.sum(np.abs(Ad[3 * I:3 * I + 3, 3 * J:3 * J + 3])) > 0 for J in blocks)
+        for J in blocks[:-1]:
+            scale = np.abs(Gd[3 * I:3 * I + 3]).sum() * np.abs(Ad).max()
+            assert np.abs(GA[3 * I:3 * I + 3, 3 * J:3 * J + 3]).max() <= 1e-13 * scale
+    assert GL.nnz == 9 * sum(1 for I in range(n // 3) for J in range(I + 1)
+                             if np.any(Ad[3 * I:3 * I + 3, 3 * J:3 * J + 3]))
+
+
+def test_block_fsai_full_pattern_is_the_inverse():
+    """All blocks of A nonzero: the block FSAI reproduces A^-1 = G_L^T G_L, and
+    PCG with G = G_L^T converges in one iteration."""
+    n = 12
+    Ad = _dense_spd(n, 21, cond=200.0)
+    A = CSR.from_dense(Ad)
+    GL = oracle.fsai_block_lower(A)
+    Gd = CSR(GL.rowptr, GL.col, GL.val).to_dense()
+    assert np.allclose(Gd.T @ Gd, np.linalg.inv(Ad), rtol=0, atol=1e-11 * np.abs(np.linalg.inv(Ad)).max())
+    b = np.random.default_rng(3).standard_normal(n)
+    res = oracle.pcg(A, oracle.transpose(GL), b, tol=1e-10, maxit=10)
+    assert res.status == oracle.OK and res.iters == 1
+
+
+def test_block_fsai_kaporin_no_worse_than_block_jacobi():
+    """The block FSAI minimises the Kaporin number of G_L A G_L^T over its
+    pattern; block Jacobi (the block FSAI of A's block diagonal) has a pattern
+    inside it, so its Kaporin number cannot be smaller."""
+    A = inputs.elasticity(3, 1.0, 0.3, 4)
+    Ad = A.to_dense()
+    n = A.n
+    Bd = np.zeros_like(Ad)
+    for I in range(n // 3):
+        Bd[3 * I:3 * I + 3, 3 * I:3 * I + 3] = Ad[3 * I:3 * I + 3, 3 * I:3 * I + 3]
+    rp, ci, vals = [0], [], []
+    for r in range(n):
+        I = r // 3
+        for c in range(3 * I, 3 * I + 3):
+            ci.append(c)
+            vals.append(Bd[r, c])
+        rp.append(len(ci))
+    B = CSR(np.array(rp, np.int32), np.array(ci, np.int32), np.array(vals))
+    GJ = oracle.fsai_block_lower(B)
+    GL = oracle.fsai_block_lower(A)
+    kj = _kaporin_log(CSR(GJ.rowptr, GJ.col, GJ.val).to_dense() @ Ad @ CSR(GJ.rowptr, GJ.col, GJ.val).to_dense().T)
+    kl = _kaporin_log(CSR(GL.rowptr, GL.col, GL.val).to_dense() @ Ad @ CSR(GL.rowptr, GL.col, GL.val).to_dense().T)
+    assert kl < kj
+
+
+def test_block_fsai_equals_scalar_fsai_as_a_preconditioner():
+    """On an exactly blocked matrix the scalar tril pattern of each row of a
+    block row is a prefix of the block row's column set, and row k of the
+    inverse Cholesky factor of A[J,J] is the FSAI row of the leading k x k
+    part: the block FSAI and the scalar FSAI give the same M^-1 = G_L^T G_L
+    (they differ in the basis within each block row and in the explicit
+    zeros of the diagonal blocks)."""
+    A = inputs.elasticity(3, 1.0, 0.3, 6)
+    B, S = oracle.fsai_block_lower(A), oracle.fsai_lower(A)
+    Bd, Sd = CSR(B.rowptr, B.col, B.val).to_dense(), CSR(S.rowptr, S.col, S.val).to_dense()
+    MB, MS = Bd.T @ Bd, Sd.T @ Sd
+    assert np.abs(MB - MS).max() <= 1e-14 * np.abs(MS).max()
+    assert B.nnz == S.nnz + A.n  # the three entries above the diagonal of each diagonal block
+
+
+def test_block_fsai_rejects_unblocked_patterns():
+    with pytest.raises(ValueError):
+        oracle.fsai_block_lower(inputs.poisson(2, 5, 0.0, 0), b=3)  # n = 25, not a multiple of 3
+    with pytest.raises(ValueError):
+        oracle.fsai_block_lower(inputs.poisson(2, 6, 0.0, 0), b=3)  # n = 36, rows not in complete triples
