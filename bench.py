@@ -54,7 +54,7 @@ TOL = 1e-8
 MAXIT = 5000
 KERNEL_SOURCES = ["paper_2510_27517_amd/csrc/kernels.hip", "paper_2510_27517_amd/csrc/kernels.h"]
 PROFILES = os.path.join(ROOT, "profiles")
-SECTIONS = ["mixed", "sai_loss", "autotune", "batched", "serving", "elasticity", "synthetic"]
+SECTIONS = ["mixed", "sai_loss", "autotune", "small", "batched", "serving", "elasticity", "synthetic"]
 
 
 def log(*a):
@@ -307,6 +307,34 @@ def section_synthetic(pcg, inputs, count):
     return out
 
 
+def section_small(pcg, inputs):
+    """Small systems, where launches and not bytes bound the iteration: 2D
+    lognormal (sigma 1) Poisson with FSAI, FP64, tol 1e-8, solved with the
+    three-kernel iteration and with the one-workgroup solver (the whole solve
+    in one launch), microseconds per iteration; and the three-kernel floor on
+    a tiny system (kernels with almost no work)."""
+    out = {"workload": "2D lognormal Poisson (sigma 1), FSAI G, FP64, tol 1e-8: three kernels per iteration "
+                       "against one persistent workgroup per solve", "sizes": {}}
+    for N in (8, 32, 64, 91, 128, 181):
+        A = inputs.poisson(2, N, 1.0, N)
+        b = inputs.rhs(A.n, N)
+        row = {"n": A.n}
+        for tag, wg in (("three_kernels", -1), ("one_workgroup", 1 << 30)):
+            with pcg.Solver(pcg.default_config(wg_max_n=wg)) as s:
+                s.set_matrix(A)
+                s.build_precond(pcg.G_FSAI)
+                s.solve(b, tol=1e-8, maxit=20000)
+                reps = 5
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    r = s.solve(b, tol=1e-8, maxit=20000)
+                ms = (time.perf_counter() - t0) * 1e3 / reps
+            row[tag] = {"time_to_tol_ms": round(ms, 3), "iters": r.iters, "status": r.status,
+                        "us_per_iter": round(ms * 1e3 / max(r.iters, 1), 2)}
+        out["sizes"][f"{N}^2"] = row
+    return out
+
+
 def batch_systems(inputs, count):
     """2D (side U{16..256}) or 3D (side U{8..64}) lognormal (sigma 0.5) Poisson
     with probability 1/2 each, b ~ N(0,1); system i uses seed i."""
@@ -338,11 +366,28 @@ def section_batched(pcg, inputs, count):
     st = [r["status"] for _, r in res]
     lat = [r["t_latency_ms"] for _, r in res]
     solve = [r["t_solve_ms"] for _, r in res]
+    # plain FP32 (no refinement; FP32 reaches 1e-6 here): small systems solved
+    # whole by one persistent workgroup each, and the same without
+    plain = {}
+    for tag, wgb in (("one_workgroup_small", 0), ("three_kernels_only", -1)):
+        cfgp = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="f32", wg_max_n_batch=wgb)
+        log(f"batched: plain FP32, {tag}")
+        with pcg.Solver(cfgp) as s:
+            t0 = time.perf_counter()
+            rp = s.solve_batch(systems, iters_per_step=10)
+            wp = time.perf_counter() - t0
+        plain[tag] = {"solves_per_s": round(count / wp, 2), "wall_s": round(wp, 3),
+                      "ok": sum(1 for _, r in rp if r["status"] == pcg.OK),
+                      "latency_ms_p50": pct([r["t_latency_ms"] for _, r in rp], 50),
+                      "latency_ms_p99": pct([r["t_latency_ms"] for _, r in rp], 99),
+                      "max_relres_true_fp32": max(r["relres_true"] for _, r in rp)}
+    plain["small_systems"] = int(sum(1 for sd in systems if sd["A"].n <= 16384))
     order = np.argsort([sd["A"].n for sd in systems])
     samples = {f"system{int(i)}": (systems[i]["A"], systems[i]["b"], {"x": res[i][0]})
                for i in order[np.linspace(0, count - 1, min(6, count)).astype(int)]}
     return {"workload": f"{count} systems: 2D side U[16,256] / 3D side U[8,64] lognormal sigma 0.5 Poisson, "
                         "FSAI G built on the host, A/vectors/G f32, FP64 refinement, tol 1e-6",
+            "fp32_plain": plain,
             "systems": count, "rows_total": n_tot, "nnz_total": nnz_tot,
             "solves_per_s": round(count / wall, 2), "wall_s": round(wall, 3),
             "ok": st.count(pcg.OK), "statuses": sorted(set(st)),
@@ -395,7 +440,7 @@ def _open_loop(pcg, cfg, reqs, arrive, iters_per_step):
                 for i, t in zip(batch, tk):
                     tickets.append(t)
                     sub_lag[t] = (now - arrive[i]) * 1e3
-            if active or queued or batch:
+            if active or queued or batch or len(got) < len(tickets):
                 active, queued = s.progress(iters_per_step)
                 depth.append(active + queued)
                 used.append(s.pool_info()[1])
@@ -475,17 +520,24 @@ def section_elasticity(pcg, inputs, N):
         t0 = time.perf_counter()
         s.build_precond(pcg.G_FSAI)
         t_dev = time.perf_counter() - t0
-    out = {"workload": f"Q1 elasticity {N}^3 free nodes x 3 dof, E lognormal sigma 1, nu 0.3, FSAI G, tol 1e-10",
-           "n": A.n, "nnz": A.nnz, "t_construct_fsai_s": round(t_fsai, 2), "t_construct_fsai_device_s": round(t_dev, 3)}
+    t0 = time.perf_counter()
+    GB = pcg.build_g_host(pcg.G_BFSAI, A)
+    t_bfsai = time.perf_counter() - t0
+    out = {"workload": f"Q1 elasticity {N}^3 free nodes x 3 dof, E lognormal sigma 1, nu 0.3, scalar FSAI G "
+                       f"(and block FSAI, 3x3 blocks), tol 1e-10",
+           "n": A.n, "nnz": A.nnz, "nnz_g_fsai": int(G[1].shape[0]), "nnz_g_block_fsai": int(GB[1].shape[0]),
+           "t_construct_fsai_s": round(t_fsai, 2), "t_construct_fsai_device_s": round(t_dev, 3),
+           "t_construct_block_fsai_s": round(t_bfsai, 2)}
     x64 = None
     xs = {}
-    for name, kw in [("fp64", dict()), ("f32_bf16_refined", dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16",
-                                                                   refine=1)),
-                     ("f32_f16_refined", dict(vec_dtype="f32", a_dtype="f32", g_dtype="f16", refine=1))]:
+    mixed = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    for name, kw, GG in [("fp64", dict(), G), ("f32_bf16_refined", mixed, G),
+                         ("f32_f16_refined", dict(vec_dtype="f32", a_dtype="f32", g_dtype="f16", refine=1), G),
+                         ("fp64_block_fsai", dict(), GB), ("f32_bf16_refined_block_fsai", mixed, GB)]:
         log(f"elasticity: {name}")
         with pcg.Solver(pcg.default_config(**kw)) as s:
             s.set_matrix(A)
-            s.set_precond(rowptr=G[0], col=G[1], val=G[2])
+            s.set_precond(rowptr=GG[0], col=GG[1], val=GG[2])
             t0 = time.perf_counter()
             r = s.solve(b, tol=1e-10, maxit=20000)
             ms = (time.perf_counter() - t0) * 1e3
@@ -638,6 +690,9 @@ def main():
     if "autotune" in sections:
         log("autotune")
         extra["autotune"] = section_autotune(pcg, torch, A, G, b_dev, max(3, args.steps // 2), ms_per_step)
+    if "small" in sections:
+        log("small systems")
+        extra["small"] = section_small(pcg, inputs)
     if "batched" in sections and args.batch_systems > 0:
         extra["batched"], refs["batched_sample"] = section_batched(pcg, inputs, args.batch_systems)
     if "serving" in sections and args.serve_requests > 0:

@@ -67,6 +67,15 @@ extern "C" {
  * draw k = mix(key + (k + 1) GAMMA), U = ((draw >> 11) + 1) 2^-53). G G^T is
  * not guaranteed SPD for every A: use it with eps > 0, e.g. 1e-4 / mean|A_ij|. */
 #define PCG_G_SEEDED 5
+/* Block FSAI for 3-dof systems (the blocked systems of Sec. 3.1, whose G has
+ * one 3x3 block per nonzero block, Sec. 3.2.2): A must be exactly 3x3-blocked
+ * (see PCG_LAYOUT_BSR3; else PCG_EINVAL). G = G_L^T with G_L block lower on
+ * the block pattern of tril(A), every 3x3 block stored whole: for block row
+ * I with tril blocks J, A[J,J] = L L^T and block row I of G_L is the last
+ * three rows of L^-1, so each diagonal block of G_L A G_L^T is the identity
+ * (M^-1 = G G^T does not depend on that choice within the block row).
+ * G and G^T are then exactly 3x3-blocked and take the 3x3-block layout. */
+#define PCG_G_BFSAI 6
 
 /* operators for pcg_matvec */
 #define PCG_OP_A 0    /* y = A x */
@@ -99,7 +108,7 @@ typedef struct {
   int graph_iters;   /* iterations per captured HIP graph replay (default 10; 0 = plain launches) */
   int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */
   int mem_budget_mb; /* device memory pool for batched / served systems, MiB (0: half the free memory at first use) */
-  int layout;        /* storage of A, G, G^T: PCG_LAYOUT_AUTO (default), _CSR, _SELL or _BSR3 */
+  int layout;        /* storage of A, G, G^T: PCG_LAYOUT_AUTO (default), _CSR, _SELL, _BSR3 or _SDIA */
   int g_device;      /* 1: FSAI factored on the device (one wave per row; same arithmetic as the host
                         builder, bit-identical G): in pcg_build_precond(PCG_G_FSAI), and for batched
                         systems with FSAI at admission (the host lays out only the patterns; F16 G
@@ -115,7 +124,16 @@ typedef struct {
                         with G^T, G that fits in 75%; else none (nontemporal loads). Negative: always
                         nontemporal. Batched and served systems keep theirs while the whole active
                         set fits in 90% */
-  int reserved[2];
+  int wg_max_n;      /* single solves of at most this many rows (FP64, or FP32 vectors and A with an
+                        FP32/BF16/FP16 G, no refinement) run as one persistent workgroup: the whole
+                        solve in one launch, with no per-iteration launches or host round trips, and
+                        results bit for bit those of the three-kernel iteration. One workgroup has
+                        far less memory parallelism than a full launch, so this pays only for tiny
+                        systems. 0: the default (see pcg_config_default); -1: never */
+  int wg_max_n_batch; /* the same for batched and served systems: those admitted in one scheduler
+                        step run together, one workgroup each, in one launch on a second stream,
+                        beside the iterations of the larger ones (many small systems keep the GPU
+                        busy where one would not). 0: the default; -1: never */
   /* Optional device allocator (for example a framework's caching allocator),
    * used for every device allocation of the context (matrices, vectors,
    * directory, serving pool, scratch): alloc returns at least `bytes` bytes of
@@ -129,11 +147,17 @@ typedef struct {
 } pcg_config;
 
 /* Matrix storage layouts (pcg_config.layout). All give bit-identical
- * products (each row is summed left to right in CSR order).
+ * products (each row is summed left to right in CSR order; stored zeros add
+ * +0 to a sum that can never be -0, which changes nothing).
  *  CSR:  CSR plus a partition into blocks of up to 256 rows whose products
  *        fit the workgroup's LDS; any row lengths.
  *  SELL: sliced ELL, slices of 64 consecutive rows stored column-major and
  *        padded to the slice's longest row; coalesced loads without LDS.
+ *  SDIA: sliced diagonals: slices of 64 rows store one int32 column offset
+ *        (column - row) per distinct offset of the slice, and for each row
+ *        one value per offset (0 where the row has none), in ascending
+ *        column order. No per-entry index and contiguous gathers: for stencil
+ *        and banded matrices.
  *  BSR3: for a matrix that is exactly 3x3-blocked (n % 3 == 0, each block
  *        row's three rows store the same complete column triples, as in
  *        node-major 3-dof systems): slices of 21 block rows, one column index
@@ -142,12 +166,14 @@ typedef struct {
  *        cover (explicit zeros fill the missing entries) when the cover adds
  *        at most 1/8 of their nonzeros (at most 2x when BSR3 is forced).
  *  AUTO: BSR3 for such an A whose block padding stays within 1/8; otherwise
- *        SELL for a matrix whose padding stays within 1/8 of its nonzeros,
- *        CSR otherwise. PCG_LAYOUT_SELL (BSR3) still falls back above 2x. */
+ *        SDIA when its stored values stay within 1/8 of the nonzeros, then
+ *        SELL under the same rule, CSR otherwise. PCG_LAYOUT_SELL, _SDIA and
+ *        _BSR3 still fall back above 2x. */
 #define PCG_LAYOUT_AUTO 0
 #define PCG_LAYOUT_CSR 1
 #define PCG_LAYOUT_SELL 2
 #define PCG_LAYOUT_BSR3 3
+#define PCG_LAYOUT_SDIA 4
 
 typedef struct {
   int status;          /* PCG_OK, PCG_NOT_CONVERGED or a negative code */
@@ -187,7 +213,8 @@ typedef struct {
 
 /* Fills cfg with the defaults: device 0, own stream, all FP64, rr_period 50,
  * eps 0, no refinement, inner_tol 1e-6, max_outer 30, graph_iters 10,
- * grid_mult 8, automatic layouts, no autotuning, the default allocator. */
+ * grid_mult 8, automatic layouts, no autotuning, wg_max_n 512,
+ * wg_max_n_batch 16384, the default allocator. */
 void pcg_config_default(pcg_config *cfg);
 
 /* Creates a context on cfg->device. Returns PCG_EDEVICE if no usable GPU,
@@ -311,7 +338,8 @@ int pcg_read_bandwidth(int device, int64_t bytes, int reps, double *gbps, double
  * while the pool has room, run `iters` CG iterations over all admitted systems
  * (iteration-level continuous batching), and retire finished systems (x
  * written to the caller's pointer, device storage freed). *active and *queued
- * (may be NULL) report the systems admitted and waiting. pcg_poll returns
+ * (may be NULL) report the systems admitted and those submitted but not yet
+ * admitted (in host preparation or waiting for room). pcg_poll returns
  * PCG_PENDING until the ticket's request has finished, then its final status
  * (and fills *res); a finished ticket is released by the poll that reports
  * it. Submission may run concurrently with pcg_progress from another thread;
@@ -377,7 +405,8 @@ typedef struct {
   int layout_a, layout_g; /* chosen PCG_LAYOUT_* (PCG_LAYOUT_AUTO: the automatic choice won) */
   int grid_mult;          /* chosen workgroups per compute unit */
   int candidates;         /* configurations timed (0: taken from the cache) */
-  int fmt_a, fmt_g, fmt_gt; /* resulting storage: 0 CSR row blocks, 1 sliced ELL, 2 sliced 3x3 blocks */
+  int fmt_a, fmt_g, fmt_gt; /* resulting storage: 0 CSR row blocks, 1 sliced ELL, 2 sliced 3x3 blocks,
+                              3 sliced diagonals */
   int idx16;              /* bit 0/1/2: A / G / G^T keep 16-bit column differences */
   int temporal;           /* bit 0/1/2: A / G / G^T read with ordinary loads (cache-resident) */
   double ms_per_iter;      /* chosen configuration, one iteration */

@@ -99,9 +99,23 @@ uint16_t to_f16_bits(double v) {
 
 // ---------------------------------------------- preconditioner builders (host)
 
+// 3x3 blocks of block row I on or left of the diagonal block (from row 3I,
+// whose columns come in complete triples in an exactly 3x3-blocked matrix).
+static int32_t tril_blocks(int32_t I, const int32_t *rp, const int32_t *ci) {
+  int32_t m = 0;
+  for (int32_t k = rp[3 * I]; k < rp[3 * I + 1] && ci[k] <= 3 * I + 2; k += 3) ++m;
+  return m;
+}
+
 int64_t g_nnz(int kind, int32_t n, const int32_t *rp, const int32_t *ci) {
   if (kind == PCG_G_JACOBI || kind == PCG_G_IDENTITY) return n;
   if (kind == PCG_G_SEEDED) return rp[n];
+  if (kind == PCG_G_BFSAI) {
+    if (!is_block3(n, rp, ci, nullptr)) return -1;
+    int64_t c = 0;
+    for (int32_t I = 0; I < n / 3; ++I) c += 9 * (int64_t)tril_blocks(I, rp, ci);
+    return c;
+  }
   if (kind != PCG_G_FSAI && kind != PCG_G_FIXED) return -1;
   int64_t c = 0;
   for (int32_t i = 0; i < n; ++i)
@@ -158,6 +172,64 @@ int fsai_rows(int32_t r0, int32_t r1, const int32_t *rp, const int32_t *ci, cons
     for (int a = 0; a < m; ++a) {
       lci[lrp[i] + a] = J[a];
       lv[lrp[i] + a] = g[a];
+    }
+  }
+  return PCG_OK;
+}
+
+// Block FSAI rows of the lower factor G_L for block rows [I0, I1) of an
+// exactly 3x3-blocked A: with J the tril blocks of block row I (I last),
+// A[J,J] = L L^T (3|J| x 3|J|), block row I of G_L is the last three rows of
+// L^-1 (three back substitutions L^T w = e), so that its diagonal block is
+// the inverse of L's trailing 3x3 block and each diagonal block of
+// G_L A G_L^T is the identity. Every 3x3 block is stored whole (zeros above
+// the diagonal of the diagonal block included).
+int bfsai_rows(int32_t I0, int32_t I1, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *lrp,
+               int32_t *lci, double *lv, int32_t n) {
+  std::vector<int32_t> where(n / 3, -1), J;
+  std::vector<double> S, w;
+  for (int32_t I = I0; I < I1; ++I) {
+    J.clear();
+    for (int32_t k = rp[3 * I]; k < rp[3 * I + 1] && ci[k] <= 3 * I + 2; k += 3) J.push_back(ci[k] / 3);
+    const int m = (int)J.size(), M = 3 * m;
+    if (m == 0 || J.back() != I) return PCG_EINVAL;
+    for (int a = 0; a < m; ++a) where[J[a]] = a;
+    S.assign((size_t)M * M, 0.0);
+    for (int a = 0; a < m; ++a)
+      for (int s = 0; s < 3; ++s) {
+        const int32_t row = 3 * J[a] + s;
+        for (int32_t k = rp[row]; k < rp[row + 1]; ++k) {
+          const int32_t c = ci[k];
+          if (c > 3 * I + 2) break;
+          const int b = where[c / 3];
+          if (b >= 0) S[(size_t)(3 * a + s) * M + 3 * b + c % 3] = v[k];
+        }
+      }
+    for (int a = 0; a < m; ++a) where[J[a]] = -1;
+    for (int c = 0; c < M; ++c) {  // Cholesky (lower) in place
+      double dsum = S[(size_t)c * M + c];
+      for (int k = 0; k < c; ++k) dsum -= S[(size_t)c * M + k] * S[(size_t)c * M + k];
+      if (!(dsum > 0.0)) return PCG_EBREAKDOWN;
+      const double l = std::sqrt(dsum);
+      S[(size_t)c * M + c] = l;
+      for (int a = c + 1; a < M; ++a) {
+        double e = S[(size_t)a * M + c];
+        for (int k = 0; k < c; ++k) e -= S[(size_t)a * M + k] * S[(size_t)c * M + k];
+        S[(size_t)a * M + c] = e / l;
+      }
+    }
+    for (int p = 0; p < 3; ++p) {  // row p of the block row: L^T w = e_(M-3+p)
+      w.assign(M, 0.0);
+      for (int a = M - 1; a >= 0; --a) {
+        double e = (a == M - 3 + p) ? 1.0 : 0.0;
+        for (int k = a + 1; k < M; ++k) e -= S[(size_t)k * M + a] * w[k];
+        w[a] = e / S[(size_t)a * M + a];
+      }
+      const int32_t r = 3 * I + p;
+      for (int a = 0; a < M; ++a) {
+        lci[lrp[r] + a] = 3 * J[a / 3] + a % 3;
+        lv[lrp[r] + a] = w[a];
+      }
     }
   }
   return PCG_OK;
@@ -232,6 +304,24 @@ int build_g(int kind, uint64_t seed, int32_t n, const int32_t *rp, const int32_t
   if (m < 0) return PCG_EINVAL;
   std::vector<int32_t> lrp(n + 1, 0), lci(m);
   std::vector<double> lv(m);
+  if (kind == PCG_G_BFSAI) {
+    for (int32_t I = 0; I < n / 3; ++I)
+      for (int p = 0; p < 3; ++p) lrp[3 * I + p + 1] = lrp[3 * I + p] + 3 * tril_blocks(I, rp, ci);
+    const int32_t nb = n / 3;
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (nb < 2000) nt = 1;
+    std::vector<int> rcs(nt, PCG_OK);
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nt; ++w) {
+      const int32_t a = (int32_t)((int64_t)nb * w / nt), b = (int32_t)((int64_t)nb * (w + 1) / nt);
+      th.emplace_back([&, a, b, w] { rcs[w] = bfsai_rows(a, b, rp, ci, v, lrp.data(), lci.data(), lv.data(), n); });
+    }
+    for (auto &t : th) t.join();
+    for (int rc : rcs)
+      if (rc != PCG_OK) return rc;
+    transpose_csr(n, lrp, lci, lv, grp, gci, gv);
+    return PCG_OK;
+  }
   for (int32_t i = 0; i < n; ++i) {
     int32_t c = 0;
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] <= i);
@@ -335,6 +425,53 @@ void sell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, con
     const int32_t c = r / kSlice, l = r % kSlice;
     for (int32_t k = 0; k < rp[r + 1] - rp[r]; ++k)
       std::memcpy(&out[(((size_t)so[c] + k) * kSlice + l) * esz], in + (size_t)(rp[r] + k) * esz, esz);
+  }
+}
+
+// The distinct offsets of slice c's entries, ascending.
+static void slice_offsets(int32_t n, const int32_t *rp, const int32_t *ci, int32_t c, std::vector<int32_t> &d) {
+  d.clear();
+  for (int32_t r = c * kSlice; r < std::min(n, (c + 1) * kSlice); ++r)
+    for (int32_t k = rp[r]; k < rp[r + 1]; ++k) d.push_back(ci[k] - r);
+  std::sort(d.begin(), d.end());
+  d.erase(std::unique(d.begin(), d.end()), d.end());
+}
+
+int64_t sdia_entries(int32_t n, const int32_t *rp, const int32_t *ci, int64_t stop) {
+  const int32_t ns = (n + kSlice - 1) / kSlice;
+  std::vector<int32_t> d;
+  int64_t tot = 0;
+  for (int32_t c = 0; c < ns && tot <= stop; ++c) {
+    slice_offsets(n, rp, ci, c, d);
+    tot += (int64_t)d.size() * kSlice;
+  }
+  return tot;
+}
+
+void sdia_pattern(int32_t n, const int32_t *rp, const int32_t *ci, std::vector<int32_t> &so,
+                  std::vector<int32_t> &offs) {
+  const int32_t ns = (n + kSlice - 1) / kSlice;
+  so.assign(ns + 1, 0);
+  offs.clear();
+  std::vector<int32_t> d;
+  for (int32_t c = 0; c < ns; ++c) {
+    slice_offsets(n, rp, ci, c, d);
+    offs.insert(offs.end(), d.begin(), d.end());
+    so[c + 1] = (int32_t)offs.size();
+  }
+}
+
+void sdia_bytes(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *in, size_t esz,
+                const std::vector<int32_t> &so, const std::vector<int32_t> &offs, std::vector<uint8_t> &out) {
+  const int32_t ns = (int32_t)so.size() - 1;
+  out.assign((size_t)so[ns] * kSlice * esz, 0);
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t c = r / kSlice, l = r % kSlice;
+    int32_t k = so[c];
+    for (int32_t q = rp[r]; q < rp[r + 1]; ++q) {  // both ascending: one merge pass
+      while (offs[k] != ci[q] - r) ++k;
+      std::memcpy(&out[((size_t)k * kSlice + l) * esz], in + (size_t)q * esz, esz);
+    }
   }
 }
 

@@ -2,6 +2,7 @@
 // rounding to the half storage formats, preconditioner construction, and the
 // row-block partition used by the kernels. No GPU calls.
 #pragma once
+#include <climits>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -52,6 +53,29 @@ void sell_columns(int32_t n, const int32_t *rp, const int32_t *ci, const std::ve
 // is all-zero bytes (+0 in every floating-point format).
 void sell_bytes(int32_t n, const int32_t *rp, const uint8_t *in, size_t esz, const std::vector<int32_t> &so,
                 std::vector<uint8_t> &out);
+
+// Sliced diagonal layout (SDIA): slices of kSlice rows as in sliced ELL, but
+// the column of an entry is stored once per slice as its offset from the
+// row: slice c lists the distinct offsets (column - row) of its entries in
+// ascending order, offs[so[c] .. so[c+1]), and stores for every row one value
+// per listed offset, at (so[c] + k) * kSlice + l for row kSlice c + l (0 where
+// the row has no entry at that offset; rows past n hold zeros). Each row's
+// values stay in ascending column order, the CSR order, with zeros between.
+// Good for stencil and banded matrices, where a slice's rows share offsets.
+
+// Stored values (kSlice per listed offset) of the SDIA layout of a pattern;
+// the count stops growing past `stop` (it is then only known to exceed it).
+int64_t sdia_entries(int32_t n, const int32_t *rp, const int32_t *ci, int64_t stop = INT64_MAX);
+
+// Slice offsets into offs (nslice + 1, in units of listed offsets) and the
+// listed offsets, slice by slice.
+void sdia_pattern(int32_t n, const int32_t *rp, const int32_t *ci, std::vector<int32_t> &so,
+                  std::vector<int32_t> &offs);
+
+// Elements of `esz` bytes in CSR order moved to the SDIA order (all other
+// bytes zero).
+void sdia_bytes(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *in, size_t esz,
+                const std::vector<int32_t> &so, const std::vector<int32_t> &offs, std::vector<uint8_t> &out);
 
 // Sliced 3x3-block layout: the matrix is exactly 3x3-blocked when n % 3 == 0
 // and rows 3R, 3R+1, 3R+2 store the same columns, all in complete groups

@@ -42,7 +42,9 @@ struct alignas(64) State {
   int32_t status;     // Status below
   int32_t done;       // nonzero: every iteration kernel returns at once
   int32_t rr_period;  // residual replacement period (0 = off)
-  int32_t pad1[3];
+  int32_t restarts;   // restarts from the true residual (one-workgroup solver)
+  int32_t confirm;    // one-workgroup solver: confirm a converged recurrence on b - A x
+  int32_t pad1;
 };
 
 enum Status : int32_t {
@@ -72,6 +74,7 @@ enum Fmt : int32_t {
   FMT_CSR = 0,   // CSR with a row-block partition (any row lengths)
   FMT_SELL = 1,  // sliced ELL, slices of 64 rows (rows of similar length)
   FMT_BSR3 = 2,  // sliced 3x3 blocks, slices of 21 block rows (3x3-blocked matrices or block covers)
+  FMT_SDIA = 3,  // sliced diagonals: slices of 64 rows, one column offset per slice entry (stencils)
 };
 
 // A sparse matrix resident on the device.
@@ -87,8 +90,14 @@ enum Fmt : int32_t {
 //   val[((blk[c] + k) * 3 + j) * 63 + 21 s + r] for 8-byte values, at
 //   val[9 ((blk[c] + k) * 21 + r) + 3 s + j] for 4- and 2-byte values
 //   (padding: own block row, zeros; a block cover also holds explicit zeros).
+// FMT_SDIA: rp is unused; nblk slices of 64 rows; slice c lists blk[c+1] -
+//   blk[c] column offsets ci[blk[c] .. blk[c+1]) (ascending, column - row) and
+//   holds the value of row 64c + l at offset k in val[(blk[c] + k) * 64 + l]
+//   (0 where the row has no such entry; its column, clamped to [0, n), is
+//   still gathered).
 // `grid` is the system's workgroup count for products with this matrix (a
-// multiple of 8, a function of nblk only).
+// multiple of 8, a function of nblk only). `nidx` counts the stored column
+// indices (or offsets).
 struct DevCSR {
   const int32_t *rp = nullptr, *ci = nullptr;
   const void *val = nullptr;
@@ -101,7 +110,17 @@ struct DevCSR {
   int32_t fmt = FMT_CSR;
   int32_t idx16 = 0;     // FMT_SELL only: ci holds int16 column - row differences
   int32_t temporal = 0;  // 1: ordinary loads (kept in the memory-side cache); 0: nontemporal
+  int64_t nidx = 0;
 };
+
+// Bytes of stored column information per nonzero of a placed matrix: int32
+// CSR 4, 16-bit differences 2, one index per 3x3 block 4/9, sliced diagonals
+// 4 per listed offset spread over the nonzeros.
+inline double index_bytes_per_nnz(const DevCSR &M) {
+  if (M.fmt == FMT_BSR3) return 4.0 / 9.0;
+  if (M.fmt == FMT_SDIA) return M.nnz > 0 ? 4.0 * (double)M.nidx / (double)M.nnz : 0.0;
+  return M.idx16 ? 2.0 : 4.0;
+}
 
 // Rows per slice of FMT_SELL; block rows per slice of FMT_BSR3.
 constexpr int kSliceRows = 64;
@@ -172,6 +191,21 @@ hipError_t launch_iter_GT(const Types &ty, const LaunchSet &L, int mode, hipStre
 // system stops at this iteration). Reads st[1] only.
 hipError_t launch_iter_G(const Types &ty, const LaunchSet &L, bool has_eps, int mode, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
+// Whole PCG solves, one workgroup per system of the set (persistent: the
+// iteration loop, the residual replacement, the stopping test and, when
+// st[0].confirm is set, the confirmation on b - A x with restarts all run in
+// the kernel; no host round trip, no other launch). The states are set up as
+// for the iteration kernels (tol, maxit, eps, rr_period, x holding x0); on
+// return st[0] holds what the iteration kernels and the true-residual kernel
+// would leave: iter, status, rr, tt, bb, tol_nb, true_rr, restarts, done = 1.
+// Every row and every inner product is computed as by the iteration kernels
+// (same row sums; exact inner products), so the results are theirs bit for
+// bit. For small systems, where three launches per iteration dominate.
+// Storage types it is built for: all FP64, or FP32 vectors and A with an
+// FP32, BF16 or FP16 G (others: hipErrorInvalidValue).
+bool solve_wg_supported(const Types &ty);
+hipError_t launch_solve_wg(const Types &ty, const LaunchSet &L, bool has_eps, hipStream_t s);
 
 // x += alpha d_{iter-1} if an update is still pending (alpha != 0), then
 // alpha = 0. The G-kernel applies every update itself and leaves alpha = 0, so

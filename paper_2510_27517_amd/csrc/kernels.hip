@@ -321,6 +321,63 @@ __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pr
   }
 }
 
+// One lane's row of a sliced-diagonal slice: value k of the row multiplies
+// the gathered entry at column row + off[k] (clamped into [0, n): a stored
+// zero's column may fall outside), added left to right from zero; loads
+// issued UNR at a time as in slice_row_sum. off[] is the same for the whole
+// wave (scalar loads).
+template <typename TACC, int UNR, bool NT, typename TM, typename Gather>
+__device__ __forceinline__ TACC sdia_row_sum(GLOBAL const TM *vv, GLOBAL const int32_t *off, int32_t row, int32_t nmax,
+                                             int wd, Gather gather) {
+  TACC sum = 0;
+  int k = 0;
+  for (; k + UNR <= wd; k += UNR) {
+    TACC p[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      p[u] = (TACC)ldval<NT>(vv, (k + u) * kSliceRows) * gather(min(max(row + off[k + u], 0), nmax));
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) sum += p[u];
+  }
+  const int rem = wd - k;
+  if (rem > 0) {
+    TACC p[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = k + min(u, rem - 1);
+      p[u] = (TACC)ldval<NT>(vv, e * kSliceRows) * gather(min(max(row + off[e], 0), nmax));
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      if (u < rem) sum += p[u];
+  }
+  return sum;
+}
+
+// Sliced-diagonal rows: the walk of sell_rows (whole slices per wave, one
+// lane per row, each die's eighth of the slices), with one column offset per
+// slice entry instead of one index per lane.
+template <typename TACC, int UW, bool NT, bool REV, typename TM, typename Pre, typename Gather, typename Epi>
+__device__ __forceinline__ void sdia_rows(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi) {
+  constexpr int NW = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = G >> 3, x = l & 7, w = l >> 3;
+  const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
+  for (int k = w * NW + wv; k < s1 - s0; k += W * NW) {
+    const int c = REV ? s1 - 1 - k : s0 + k;
+    const int o0 = M.blk[c], wd = M.blk[c + 1] - o0;
+    const int row = c * kSliceRows + lane;
+    const bool has = row < M.n;
+    RowVals<TACC> pv{};
+    if (has) pv = pre(row);
+    GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lane;
+    const TACC sum = (UW > 4 && wd > 4) ? sdia_row_sum<TACC, UW, NT>(vv, M.ci + o0, row, M.n - 1, wd, gather)
+                                        : sdia_row_sum<TACC, 4, NT>(vv, M.ci + o0, row, M.n - 1, wd, gather);
+    if (has) epi(row, sum, pv);
+  }
+}
+
 // Sliced 3x3-block rows: each wave takes whole slices of 21 block rows, one
 // lane per row (lane 63 idle); the three lanes of a block row read the same
 // block column. 8-byte values are stored column-major within the slice (lane
@@ -387,6 +444,8 @@ __device__ __forceinline__ void for_rows_as(const Mat<TM> &M, int l, int G, TACC
                                             Epi epi) {
   if (M.fmt == FMT_SELL) {
     sell_rows<TACC, UW, NT, REV>(M, l, G, pre, gather, epi);
+  } else if (M.fmt == FMT_SDIA) {
+    sdia_rows<TACC, UW, NT, REV>(M, l, G, pre, gather, epi);
   } else if (M.fmt == FMT_BSR3) {
     bsr_rows<TACC, NT>(M, l, G, pre, gather, epi);
   } else {
@@ -757,6 +816,233 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_resid(const SysDev *__
 }
 
 
+// ------------------------------------------------ one-workgroup solver
+
+// Totals of a workgroup's double-double sums, rounded once, in every thread.
+template <int NV>
+__device__ __forceinline__ void wg_totals(Acc (&v)[NV], double (&out)[NV], Acc *sh) {
+  reduce_partials<NV>(v, out, sh);
+}
+
+// Every row of M by this one workgroup: the eight die-slabs of the
+// iteration kernels' partition, one after the other, then a barrier (the
+// vector written is read by the next phase). Ordinary loads: a small
+// system's matrices stay in L2 from one iteration to the next.
+template <typename TACC, int UW, bool REV, typename TM, typename Pre, typename Gather, typename Epi>
+__device__ __forceinline__ void wg_rows(const Mat<TM> &M, TACC *lds, Pre pre, Gather gather, Epi epi) {
+  for (int l = 0; l < 8; ++l) for_rows_as<TACC, UW, false, REV>(M, l, 8, lds, pre, gather, epi);
+  __syncthreads();
+}
+
+// Elementwise over all rows by this workgroup, then a barrier.
+template <typename F>
+__device__ __forceinline__ void wg_elementwise(int n, F f) {
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) f(i);
+  __syncthreads();
+}
+
+template <typename TV, typename TA, typename TG, bool HAS_EPS>
+__global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ dir, const int32_t *__restrict__ set) {
+  __shared__ TV lds[kLdsBytes / sizeof(TV)];
+  __shared__ Acc sh[4 * (kBlock / 64)];
+  const SysDev &D = dir[set[blockIdx.x]];
+  GLOBAL State *st = gl(D.st);
+  const State S0 = ld_state(st);
+  const int n = D.n;
+  const Mat<TA> A = mat<TA>(D.A);
+  const Mat<TG> GT = mat<TG>(D.GT), G = mat<TG>(D.G);
+  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
+  GLOBAL const TV *__restrict__ b = gl((const TV *)D.b);
+  GLOBAL TV *__restrict__ q = gl((TV *)D.q);
+  GLOBAL TV *__restrict__ t = gl((TV *)D.t);
+  GLOBAL TV *__restrict__ rv[2] = {gl((TV *)D.r0), gl((TV *)D.r1)};
+  GLOBAL TV *__restrict__ dv[2] = {gl((TV *)D.d0), gl((TV *)D.d1)};
+  const double eps = S0.eps;
+  const TV epsv = (TV)eps;
+  // ||b||^2, tol ||b||
+  double bb;
+  {
+    Acc a[1] = {{0.0, 0.0}};
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) acc_prod(a[0], b[i], b[i]);
+    double v[1];
+    wg_totals<1>(a, v, sh);
+    bb = v[0];
+  }
+  const double tol_nb = S0.tol * sqrt(bb);
+  State o = S0;
+  o.bb = bb;
+  o.tol_nb = tol_nb;
+  o.alpha = o.beta = 0.0;
+  o.restarts = 0;
+  if (bb == 0.0) {
+    wg_elementwise(n, [&](int64_t i) { x[i] = (TV)0; });
+    o.status = ST_ZERO_B;
+    o.done = 1;
+    o.iter = 0;
+    o.rr = o.tt = o.true_rr = 0.0;
+    if (threadIdx.x == 0) st_state(st, o);
+    return;
+  }
+  wg_elementwise(n, [&](int64_t i) { dv[0][i] = (TV)0; dv[1][i] = (TV)0; });
+  int it = 0;
+  int status = ST_RUNNING;
+  double delta = 0.0, rr = 0.0, tt = 0.0, true_rr = 0.0;
+  // r_it = b - A x (true residual), its norm when `reduce`
+  auto residual = [&](GLOBAL TV *rout, bool reduce) {
+    Acc a[1] = {{0.0, 0.0}};
+    wg_rows<TV, 4, false>(
+        A, lds, [&](int row) { return RowVals<TV>{b[row], (TV)0, (TV)0}; }, [&](int j) -> TV { return x[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          const TV r = pv.a - sum;
+          rout[row] = r;
+          acc_prod(a[0], r, r);
+        });
+    double v[1];
+    wg_totals<1>(a, v, sh);
+    if (reduce) true_rr = v[0];
+  };
+  // start or restart from r_it: t = G^T r, rr, tt, delta, d_it = G t + eps r
+  // (beta = 0 against the zeroed or previous direction buffer), stop tests
+  auto restart = [&]() {
+    GLOBAL const TV *src = rv[it & 1];
+    Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    wg_rows<TV, 4, true>(
+        GT, lds, [&](int row) { return RowVals<TV>{src[row], (TV)0, (TV)0}; }, [&](int j) -> TV { return src[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          t[row] = sum;
+          acc_prod(a[0], pv.a, pv.a);
+          acc_prod(a[1], sum, sum);
+        });
+    double v[2];
+    wg_totals<2>(a, v, sh);
+    rr = v[0];
+    tt = v[1];
+    const double dn = tt + eps * rr;
+    if (sqrt(rr) <= tol_nb)
+      status = ST_CONV_REC;
+    else if (it >= S0.maxit)
+      status = ST_MAXIT;
+    delta = dn;
+    if (status != ST_RUNNING) return;
+    GLOBAL TV *dnext = dv[it & 1];
+    GLOBAL const TV *dprev = dv[(it + 1) & 1];
+    const TV beta = (TV)0.0;
+    wg_rows<TV, 4, false>(
+        G, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? src[row] : (TV)0, dprev[row], (TV)0}; },
+        [&](int j) -> TV { return t[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          const TV sv = HAS_EPS ? sum + epsv * pv.a : sum;
+          dnext[row] = sv + beta * pv.b;
+        });
+  };
+  residual(rv[0], false);
+  restart();
+  for (;;) {
+    while (status == ST_RUNNING) {
+      GLOBAL const TV *dcur = dv[it & 1];
+      // q = A d_i, gamma = d_i^T q
+      double gamma;
+      {
+        Acc a[1] = {{0.0, 0.0}};
+        wg_rows<TV, 8, false>(
+            A, lds, [&](int row) { return RowVals<TV>{dcur[row], (TV)0, (TV)0}; },
+            [&](int j) -> TV { return dcur[j]; },
+            [&](int row, TV sum, const RowVals<TV> &pv) {
+              q[row] = sum;
+              acc_prod(a[0], pv.a, sum);
+            });
+        double v[1];
+        wg_totals<1>(a, v, sh);
+        gamma = v[0];
+      }
+      if (!(gamma > 0.0) || !isfinite(gamma)) {  // x stays x_i
+        status = ST_BREAK_GAMMA;
+        break;
+      }
+      const double alpha = delta / gamma;
+      const TV al = (TV)alpha;
+      GLOBAL TV *rnext = rv[(it + 1) & 1];
+      const bool replace = S0.rr_period > 0 && it > 0 && it % S0.rr_period == 0;
+      Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
+      if (replace) {  // r_{i+1} = b - A (x_i + alpha_i d_i), then t = G^T r_{i+1}
+        wg_rows<TV, 4, false>(
+            A, lds, [&](int row) { return RowVals<TV>{b[row], (TV)0, (TV)0}; },
+            [&](int j) -> TV { return x[j] + al * dcur[j]; },
+            [&](int row, TV sum, const RowVals<TV> &pv) { rnext[row] = pv.a - sum; });
+        wg_rows<TV, 4, true>(
+            GT, lds, [&](int row) { return RowVals<TV>{rnext[row], (TV)0, (TV)0}; },
+            [&](int j) -> TV { return rnext[j]; },
+            [&](int row, TV sum, const RowVals<TV> &pv) {
+              t[row] = sum;
+              acc_prod(a[0], pv.a, pv.a);
+              acc_prod(a[1], sum, sum);
+            });
+      } else {  // r_{i+1} = r_i - alpha_i q, formed where it is gathered
+        GLOBAL const TV *src = rv[it & 1];
+        wg_rows<TV, 4, true>(
+            GT, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
+            [&](int j) -> TV { return src[j] - al * q[j]; },
+            [&](int row, TV sum, const RowVals<TV> &pv) {
+              const TV rn = pv.a - al * pv.b;
+              rnext[row] = rn;
+              t[row] = sum;
+              acc_prod(a[0], rn, rn);
+              acc_prod(a[1], sum, sum);
+            });
+      }
+      double v[2];
+      wg_totals<2>(a, v, sh);
+      rr = v[0];
+      tt = v[1];
+      const double dn = tt + eps * rr;
+      const int i1 = it + 1;
+      if (!(dn >= 0.0) || !isfinite(dn))
+        status = ST_BREAK_DELTA;
+      else if (sqrt(rr) <= tol_nb)
+        status = ST_CONV_REC;
+      else if (i1 >= S0.maxit)
+        status = ST_MAXIT;
+      const TV ap = (TV)alpha;
+      if (status != ST_RUNNING) {  // x_{i+1} = x_i + alpha_i d_i
+        wg_elementwise(n, [&](int64_t i) { x[i] = x[i] + ap * dcur[i]; });
+        if (status != ST_BREAK_DELTA) delta = dn;
+        it = i1;
+        break;
+      }
+      const TV beta = (TV)(dn / delta);
+      delta = dn;
+      GLOBAL TV *dnext = dv[i1 & 1];
+      wg_rows<TV, 4, false>(
+          G, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rnext[row] : (TV)0, dcur[row], x[row]}; },
+          [&](int j) -> TV { return t[j]; },
+          [&](int row, TV sum, const RowVals<TV> &pv) {
+            const TV sv = HAS_EPS ? sum + epsv * pv.a : sum;
+            dnext[row] = sv + beta * pv.b;
+            x[row] = pv.c + ap * pv.b;
+          });
+      it = i1;
+    }
+    if (status == ST_BREAK_GAMMA || status == ST_BREAK_DELTA) break;
+    // the true residual b - A x into the current r slot
+    residual(rv[it & 1], true);
+    if (status == ST_CONV_REC && S0.confirm && !(sqrt(true_rr) <= tol_nb)) {
+      ++o.restarts;  // the recurrence drifted: restart from the true residual
+      status = ST_RUNNING;
+      restart();
+      continue;
+    }
+    break;
+  }
+  o.iter = it;
+  o.status = status;
+  o.done = 1;
+  o.rr = rr;
+  o.tt = tt;
+  o.delta = delta;
+  o.true_rr = true_rr;
+  if (threadIdx.x == 0) st_state(st, o);
+}
+
 template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_finalize(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
   const int2 m = map[blockIdx.x];
@@ -1070,10 +1356,27 @@ __device__ uint16_t f16_bits(double v) {
   return sign | (uint16_t)rint(a * 16777216.0);  // subnormal: multiples of 2^-24
 }
 
-__device__ __forceinline__ void store_val(const DevCSR &M, int32_t row, int32_t idx, double x) {
-  const int64_t p = (M.fmt == FMT_SELL)
-                        ? ((int64_t)gl(M.blk)[row / kSliceRows] + idx) * kSliceRows + row % kSliceRows
-                        : (int64_t)gl(M.rp)[row] + idx;
+// Store entry idx of `row` (column col) in M's layout: CSR, sliced ELL, or
+// sliced diagonals (the slot of offset col - row among the slice's offsets).
+__device__ __forceinline__ void store_val(const DevCSR &M, int32_t row, int32_t idx, int32_t col, double x) {
+  int64_t p;
+  if (M.fmt == FMT_SELL) {
+    p = ((int64_t)gl(M.blk)[row / kSliceRows] + idx) * kSliceRows + row % kSliceRows;
+  } else if (M.fmt == FMT_SDIA) {
+    GLOBAL const int32_t *off = gl(M.ci);
+    int32_t lo = gl(M.blk)[row / kSliceRows], hi = gl(M.blk)[row / kSliceRows + 1] - 1;
+    const int32_t d = col - row;
+    while (lo < hi) {  // the slice lists every offset of its rows, so d is found
+      const int32_t mid = lo + (hi - lo) / 2;
+      if (off[mid] < d)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    p = (int64_t)lo * kSliceRows + row % kSliceRows;
+  } else {
+    p = (int64_t)gl(M.rp)[row] + idx;
+  }
   switch (M.dtype) {
     case F64: gl((double *)M.val)[p] = x; break;
     case F32: gl((float *)M.val)[p] = (float)x; break;
@@ -1094,7 +1397,7 @@ __global__ __launch_bounds__(kBlock) void k_fsai_place(const int32_t *__restrict
     for (int32_t k = 0; k < m; ++k) {
       const int32_t j = ci[r0 + k];
       const double x = lv[base + k] * scale;
-      store_val(GT, i, k, x);
+      store_val(GT, i, k, j, x);
       // entry (j, i) of G = G_L^T: its rank in the upper part of A's row j
       int32_t lo = dpos[j], hi = rp[j + 1] - 1;
       while (lo < hi) {
@@ -1108,7 +1411,7 @@ __global__ __launch_bounds__(kBlock) void k_fsai_place(const int32_t *__restrict
         gl(err_)[0] = 2;
         continue;
       }
-      store_val(G, j, lo - dpos[j], x);
+      store_val(G, j, lo - dpos[j], i, x);
     }
   }
 }
@@ -1144,6 +1447,24 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_spmm(DevCSR Md, int32_
     const int32_t row = has ? (int32_t)r : 0;
     int64_t e0 = 0, stride = 1;
     int32_t len = 0;
+    if (has && M.fmt == FMT_SDIA) {  // one offset per slice entry; stored zeros add +0
+      const int32_t sl = row / kSliceRows, o0 = M.blk[sl], wd = M.blk[sl + 1] - o0;
+      GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + row % kSliceRows;
+      for (int32_t p0 = 0; p0 < k; p0 += LPR) {
+        const int32_t p = p0 + pl;
+        double sum = 0.0;
+        for (int32_t e = 0; e < wd; ++e) {
+          const int32_t col = min(max(row + M.ci[o0 + e], 0), M.n - 1);
+          sum += ld64(vv, (int64_t)e * kSliceRows) * (p < k ? X[(int64_t)col * k + p] : 0.0);
+        }
+        if (p < k) {
+          double y = c * sum;
+          if (Z) y = y + d * Z[(int64_t)row * k + p];
+          Y[(int64_t)row * k + p] = y;
+        }
+      }
+      continue;
+    }
     if (has && M.fmt == FMT_BSR3) {  // whole blocks: three entries of the row per block
       const int32_t R = row / 3, sub = row % 3, sl = R / kBSliceRows, rr = R % kBSliceRows;
       const int32_t o0 = M.blk[sl], wd = M.blk[sl + 1] - o0;
@@ -1378,6 +1699,33 @@ hipError_t launch_resid(const Types &ty, const LaunchSet &L, int slot_sel, bool 
     return hipErrorInvalidValue;
   }
   if (reduce) hipLaunchKernelGGL(k_reduce_state, dim3(L.nset), dim3(kBlock), 0, s, L.dir, L.set, 1);
+  return hipGetLastError();
+}
+
+bool solve_wg_supported(const Types &ty) {
+  return (ty.vec == F64 && ty.a == F64 && ty.g == F64) ||
+         (ty.vec == F32 && ty.a == F32 && (ty.g == F32 || ty.g == BF16 || ty.g == F16));
+}
+
+hipError_t launch_solve_wg(const Types &ty, const LaunchSet &L, bool has_eps, hipStream_t s) {
+  if (L.nset == 0) return hipSuccess;
+#define PCG_SOLVE_WG(TV, TG)                                                                                   \
+  do {                                                                                                         \
+    if (has_eps)                                                                                               \
+      hipLaunchKernelGGL((k_solve_wg<TV, TV, TG, true>), dim3(L.nset), dim3(kBlock), 0, s, L.dir, L.set);     \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_solve_wg<TV, TV, TG, false>), dim3(L.nset), dim3(kBlock), 0, s, L.dir, L.set);    \
+  } while (0)
+  if (!solve_wg_supported(ty)) return hipErrorInvalidValue;
+  if (ty.vec == F64)
+    PCG_SOLVE_WG(double, double);
+  else if (ty.g == F32)
+    PCG_SOLVE_WG(float, float);
+  else if (ty.g == BF16)
+    PCG_SOLVE_WG(float, bf16_t);
+  else
+    PCG_SOLVE_WG(float, _Float16);
+#undef PCG_SOLVE_WG
   return hipGetLastError();
 }
 

@@ -40,6 +40,11 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDirCap = 4096;  // systems per context (directory and state slots)
+// defaults of pcg_config.wg_max_n and wg_max_n_batch: rows of a system solved
+// by one persistent workgroup, alone (measured crossover with the three-kernel
+// iteration near 500 rows) and in a batch (many systems at once)
+constexpr int kWgMaxN = 512;
+constexpr int kWgMaxNBatch = 16384;
 constexpr int kSlotMain = 0, kSlot64 = 1, kSlotX = 2, kFirstBatchSlot = 3;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -159,14 +164,17 @@ struct HostMat {
   std::vector<int32_t> rp;   // CSR row pointers (FMT_CSR only)
   std::vector<int32_t> ci;   // columns in storage order
   std::vector<uint8_t> val;  // values in dt, in storage order (empty: written on the device)
-  std::vector<int32_t> blk;  // row-block pairs (FMT_CSR) or slice offsets (FMT_SELL)
+  std::vector<int32_t> blk;  // row-block pairs (FMT_CSR) or slice offsets (sliced layouts)
   std::vector<int16_t> ci16; // FMT_SELL with idx16: column - row of each stored entry (ci then empty)
   int64_t stored = 0;        // stored indices (padding included)
   int32_t idx16 = 0;
   int32_t nunits = 0, grid = 8;
   int vpi = 1;  // values per stored index (9 for 3x3 blocks)
   size_t val_bytes() const { return pcgk::dtype_size(dt) * (size_t)vpi * (size_t)std::max<int64_t>(stored, 1); }
-  size_t idx_bytes() const { return (idx16 ? 2 : 4) * (size_t)std::max<int64_t>(stored, 1); }
+  size_t idx_bytes() const {
+    if (fmt == pcgk::FMT_SDIA) return 4 * std::max<size_t>(ci.size(), 1);
+    return (idx16 ? 2 : 4) * (size_t)std::max<int64_t>(stored, 1);
+  }
   size_t bytes() const {
     return align_up(4 * rp.size()) + align_up(idx_bytes()) + align_up(val_bytes()) + align_up(4 * blk.size());
   }
@@ -266,6 +274,25 @@ bool use_sell(int layout, int32_t n, const int32_t *rp) {
   return stored <= nnz + nnz / 8;
 }
 
+// The sliced diagonal layout when a slice's rows share their column offsets:
+// its stored values (zeros included) within 1/8 of the nonzeros (2x when
+// asked for explicitly).
+bool sdia_fits(int layout, int64_t nnz, int64_t stored) {
+  if (stored >= ((int64_t)1 << 31)) return false;
+  return layout == PCG_LAYOUT_SDIA ? stored <= 2 * nnz + pcgh::kSlice : stored <= nnz + nnz / 8;
+}
+
+bool sdia_allowed(int layout) {
+  return layout == PCG_LAYOUT_AUTO || layout == PCG_LAYOUT_SDIA || layout == PCG_LAYOUT_BSR3;
+}
+
+bool use_sdia(int layout, int32_t n, const int32_t *rp, const int32_t *ci) {
+  if (n <= 0 || !sdia_allowed(layout)) return false;
+  const int64_t nnz = rp[n];
+  const int64_t cap = layout == PCG_LAYOUT_SDIA ? 2 * nnz + pcgh::kSlice : nnz + nnz / 8;
+  return sdia_fits(layout, nnz, pcgh::sdia_entries(n, rp, ci, cap));
+}
+
 // The sliced 3x3-block layout for an exactly 3x3-blocked matrix whose block
 // padding stays within 1/8 (at most 2x when asked for explicitly).
 bool use_bsr3(int layout, int32_t n, const int32_t *rp, const int32_t *ci) {
@@ -277,8 +304,21 @@ bool use_bsr3(int layout, int32_t n, const int32_t *rp, const int32_t *ci) {
   return layout == PCG_LAYOUT_BSR3 ? stored <= 2 * nb : stored <= nb + nb / 8;
 }
 
+// The slice offsets and listed offsets of the sliced diagonal layout into M
+// (blk, ci), when the layout is allowed and fits. Irregular patterns are
+// turned down after their first slices (the stored count only grows).
+bool sdia_layout(int layout, int32_t n, const int32_t *rp, const int32_t *ci, HostMat &M) {
+  if (n <= 0 || !sdia_allowed(layout)) return false;
+  const int64_t nnz = rp[n];
+  const int64_t cap = layout == PCG_LAYOUT_SDIA ? 2 * nnz + pcgh::kSlice : nnz + nnz / 8;
+  if (pcgh::sdia_entries(n, rp, ci, cap) > cap) return false;
+  pcgh::sdia_pattern(n, rp, ci, M.blk, M.ci);
+  return sdia_fits(layout, nnz, (int64_t)M.ci.size() * pcgh::kSlice);
+}
+
 // Lay out one matrix's pattern (no values); the row blocks (CSR) are sized for
 // products in vector type vdt. `blocks`: the 3x3-block layout may be used.
+// Preference: 3x3 blocks, sliced diagonals, sliced ELL, CSR row blocks.
 void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const int32_t *ci, int dt, int vdt,
                   HostMat &M, bool blocks = false) {
   M.n = n;
@@ -296,6 +336,14 @@ void make_pattern(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, 
     M.nunits = (int32_t)M.blk.size() - 1;
     const int32_t rounds = (M.nunits + pcgk::kBlock / 64 - 1) / (pcgk::kBlock / 64);
     M.grid = grid_for(cus, cfg.grid_mult, rounds);
+  } else if (sdia_layout(cfg.layout, n, rp, ci, M)) {
+    M.fmt = pcgk::FMT_SDIA;
+    M.rp.clear();
+    M.nunits = (int32_t)M.blk.size() - 1;
+    const int32_t rounds = (M.nunits + pcgk::kBlock / 64 - 1) / (pcgk::kBlock / 64);
+    M.grid = grid_for(cus, cfg.grid_mult, rounds);
+    M.stored = (int64_t)M.ci.size() * pcgh::kSlice;
+    return;
   } else if (use_sell(cfg.layout, n, rp)) {
     M.fmt = pcgk::FMT_SELL;
     M.rp.clear();
@@ -392,6 +440,8 @@ void make_mat(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, cons
   cast_values(v, M.nnz, dt, scale, csr_val);
   if (M.fmt == pcgk::FMT_BSR3)
     pcgh::bsell_bytes(n, rp, csr_val.data(), pcgk::dtype_size(dt), M.blk, M.val);
+  else if (M.fmt == pcgk::FMT_SDIA)
+    pcgh::sdia_bytes(n, rp, ci, csr_val.data(), pcgk::dtype_size(dt), M.blk, M.ci, M.val);
   else if (M.fmt == pcgk::FMT_SELL)
     pcgh::sell_bytes(n, rp, csr_val.data(), pcgk::dtype_size(dt), M.blk, M.val);
   else
@@ -413,6 +463,8 @@ void prep_a(const pcg_config &cfg, int cus, int32_t n, const int32_t *rp, const 
     if (P.A.fmt != pcgk::FMT_CSR) {
       if (P.A.fmt == pcgk::FMT_BSR3)
         pcgh::bsell_bytes(n, rp, (const uint8_t *)v, 8, P.A.blk, P.sliced64);
+      else if (P.A.fmt == pcgk::FMT_SDIA)
+        pcgh::sdia_bytes(n, rp, ci, (const uint8_t *)v, 8, P.A.blk, P.A.ci, P.sliced64);
       else
         pcgh::sell_bytes(n, rp, (const uint8_t *)v, 8, P.A.blk, P.sliced64);
       P.nunits64 = P.A.nunits;
@@ -505,6 +557,7 @@ hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, hipStream_t s) {
   M.dtype = H.dt;
   M.fmt = H.fmt;
   M.idx16 = H.idx16;
+  M.nidx = H.idx16 ? (int64_t)H.ci16.size() : (int64_t)H.ci.size();
   return e;
 }
 
@@ -617,6 +670,7 @@ struct Req {
   int restarts = 0;
   int outer = 0, inner_total = 0;
   int iter_host = 0;  // the system's iteration count at the start of the next scheduler step
+  bool wg = false;    // solved whole by the one-workgroup solver (small system)
   double prev_rn = INFINITY, relres64 = NAN, last_rec = NAN;
   double t_submit = 0, t_admit = 0, t_done = 0;
   pcg_result res{};
@@ -673,6 +727,7 @@ struct pcg_ctx {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<std::shared_ptr<Req>> prep_q;   // awaiting host preparation
+  int preparing = 0;                         // taken from prep_q by a worker, not yet ready
   std::deque<std::shared_ptr<Req>> ready_q;  // prepared, awaiting admission
   std::vector<std::shared_ptr<Req>> active;  // admitted
   std::unordered_map<uint64_t, std::shared_ptr<Req>> by_ticket;
@@ -680,6 +735,16 @@ struct pcg_ctx {
   std::vector<std::thread> workers;
   bool stop = false;
   HostSet set_active, set_done, set_tmp, set_tmp64;  // device buffers reused from step to step
+  // small admitted systems solved whole by the one-workgroup solver, each
+  // launch over a group of them on the side stream (own, default priority)
+  struct WgGroup {
+    std::vector<std::shared_ptr<Req>> reqs;
+    HostSet set;
+    hipEvent_t done = nullptr;
+  };
+  std::vector<WgGroup> wg_groups;
+  hipStream_t side = nullptr;
+  int wg_inflight = 0;
   bool active_dirty = true;
   // the scheduler step (K iterations over the active set) as a HIP graph,
   // valid until the active set changes
@@ -812,7 +877,7 @@ pcg_config eff_cfg(const pcg_ctx *ctx, bool for_g) {
 // Bytes of one placed matrix (values and indices at their stored widths, row
 // pointers; sliced padding not counted).
 double placed_bytes(const pcgk::DevCSR &M) {
-  const double ib = M.fmt == pcgk::FMT_BSR3 ? 4.0 / 9.0 : M.idx16 ? 2.0 : 4.0;
+  const double ib = pcgk::index_bytes_per_nnz(M);
   return (double)M.nnz * ((double)pcgk::dtype_size(M.dtype) + ib) + 4.0 * (M.n + 1.0);
 }
 
@@ -931,6 +996,14 @@ int enqueue_start(pcg_ctx *ctx, const Types &ty, const LaunchSet &L, bool has_ep
 // residual meets tol, check b - A x and restart from it if that fails (the
 // inner solves of refinement skip this: the FP64 outer residual is the check,
 // and an FP32 iterate's true residual has a floor near u32 ||A|| ||x||).
+// The single system goes to the one-workgroup solver: small enough, and a
+// storage-type combination it is built for.
+bool use_solve_wg(const pcg_ctx *ctx, const Types &ty, int32_t n, bool batch = false) {
+  const int cf = batch ? ctx->cfg.wg_max_n_batch : ctx->cfg.wg_max_n;
+  const int lim = cf == 0 ? (batch ? kWgMaxNBatch : kWgMaxN) : cf;
+  return lim > 0 && n <= lim && pcgk::solve_wg_supported(ty);
+}
+
 int solve_core(pcg_ctx *ctx, const Core &c, double tol, int maxit, CoreOut &out, bool confirm = true) {
   const Types &ty = c.ty;
   const LaunchSet &L = *c.L;
@@ -938,9 +1011,28 @@ int solve_core(pcg_ctx *ctx, const Core &c, double tol, int maxit, CoreOut &out,
   hipStream_t s = ctx->stream;
   State init = init_state(ctx, tol, maxit, ctx->single.g_scale, !confirm);
   const bool has_eps = init.eps != 0.0;
+  init.confirm = confirm ? 1 : 0;
   ctx->h_init[0] = init;
   ctx->h_init[1] = init;
   HIPCHK(hipMemcpyAsync(D.st, ctx->h_init, 2 * sizeof(State), hipMemcpyHostToDevice, s));
+  if (use_solve_wg(ctx, ty, D.n)) {  // the whole solve in one launch
+    HIPCHK(pcgk::launch_solve_wg(ty, L, has_eps, s));
+    State *hst = ctx->h_states + 2 * c.slot;
+    HIPCHK(hipMemcpyAsync(hst, D.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const State f = *hst;
+    out = CoreOut{};
+    if (f.status == pcgk::ST_ZERO_B) return PCG_OK;
+    out.iters = f.iter;
+    out.rr = f.rr;
+    out.true_rr = f.true_rr;
+    out.bb = f.bb;
+    out.restarts = f.restarts;
+    out.status = f.status == pcgk::ST_CONV_REC ? PCG_OK
+                 : f.status == pcgk::ST_MAXIT  ? PCG_NOT_CONVERGED
+                                               : PCG_EBREAKDOWN;
+    return PCG_OK;
+  }
   {
     int rc = enqueue_start(ctx, ty, L, has_eps);
     if (rc) return rc;
@@ -1332,12 +1424,14 @@ void worker_main(pcg_ctx *ctx) {
       if (ctx->stop) return;
       R = ctx->prep_q.front();
       ctx->prep_q.pop_front();
+      ++ctx->preparing;
     }
     prep_request(ctx->cfg, ctx->cus, *R);
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
       R->st = RQ_READY;
       ctx->ready_q.push_back(R);
+      --ctx->preparing;
     }
     ctx->cv.notify_all();
   }
@@ -1367,7 +1461,7 @@ void start_workers(pcg_ctx *ctx) {
 // values; 16-bit column differences: two bytes), its row pointers, and the
 // 11 vector streams.
 double layout_bytes_per_iter(const SysDev &D, int64_t nnz_a, int64_t nnz_g, const pcg_config &cfg) {
-  auto ib = [](const pcgk::DevCSR &M) { return M.fmt == pcgk::FMT_BSR3 ? 4.0 / 9.0 : M.idx16 ? 2.0 : 4.0; };
+  auto ib = [](const pcgk::DevCSR &M) { return pcgk::index_bytes_per_nnz(M); };
   const double sa = (double)pcgk::dtype_size(cfg.a_dtype), sg = (double)pcgk::dtype_size(cfg.g_dtype),
                sv = (double)pcgk::dtype_size(cfg.vec_dtype), rp = 4.0 * (D.n + 1.0);
   return (double)nnz_a * (sa + ib(D.A)) + (double)nnz_g * (2.0 * sg + ib(D.G) + ib(D.GT)) + 3.0 * rp +
@@ -1479,7 +1573,7 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
 int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::vector<void *> &temps) {
   hipStream_t s = ctx->stream;
   std::vector<State> inits(2 * cand.size());
-  std::vector<int> slots;
+  std::vector<int> slots, wg_slots;
   auto fail_temps = [&](hipError_t e) {
     ctx->err = std::string("admission: ") + hipGetErrorString(e);
     if (e == hipErrorOutOfMemory) {
@@ -1554,7 +1648,13 @@ int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::v
       HIPCHK(h2d(ctx->d_states + 2 * R.slot64, &inits[2 * i], 2 * sizeof(State), s));
       continue;
     }
-    slots.push_back(R.slot);
+    R.wg = use_solve_wg(ctx, ctx->ty, R.n, true);
+    if (R.wg) {
+      inits[2 * i].confirm = inits[2 * i + 1].confirm = 1;
+      wg_slots.push_back(R.slot);
+    } else {
+      slots.push_back(R.slot);
+    }
     // b and x0 (zeros when not given). FP64 vectors load directly; FP32
     // vectors stage FP64 through r0 and r1, which are adjacent and together
     // hold n doubles, then convert.
@@ -1581,7 +1681,9 @@ int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::v
   HostSet &hs = ctx->set_tmp;
   int rc = build_set(ctx, hs, slots);
   if (rc) return rc;
-  if (ctx->cfg.refine) {  // first FP64 residual of every new system
+  if (slots.empty()) {
+    // only one-workgroup systems: they start in their own launch
+  } else if (ctx->cfg.refine) {  // first FP64 residual of every new system
     const Types t64{pcgk::F64, pcgk::F64, pcgk::F64};
     HIPCHK(pcgk::launch_norm_b(t64, hs.L, s));
     HIPCHK(pcgk::launch_resid(t64, hs.L, 0, false, true, false, s));
@@ -1729,6 +1831,53 @@ int batch_residency(pcg_ctx *ctx, hipStream_t s) {
   return PCG_OK;
 }
 
+// Small admitted systems: one launch of the one-workgroup solver over all of
+// them on the side stream (the uploads are complete: admission synchronised).
+int launch_wg_group(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &reqs) {
+  if (!ctx->side) HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  pcg_ctx::WgGroup g;
+  std::vector<int> slots;
+  for (auto &R : reqs) slots.push_back(R->slot);
+  int rc = build_set(ctx, g.set, slots);
+  if (rc) return rc;
+  g.reqs = reqs;
+  HIPCHK(hipEventCreateWithFlags(&g.done, hipEventDisableTiming));
+  HIPCHK(pcgk::launch_solve_wg(ctx->ty, g.set.L, ctx->cfg.eps != 0.0, ctx->side));
+  HIPCHK(hipEventRecord(g.done, ctx->side));
+  ctx->wg_inflight += (int)reqs.size();
+  ctx->wg_groups.push_back(std::move(g));
+  return PCG_OK;
+}
+
+// Retire the systems of every finished one-workgroup launch.
+int collect_wg_groups(pcg_ctx *ctx) {
+  for (size_t k = 0; k < ctx->wg_groups.size();) {
+    pcg_ctx::WgGroup &g = ctx->wg_groups[k];
+    const hipError_t q = hipEventQuery(g.done);
+    if (q == hipErrorNotReady) {
+      ++k;
+      continue;
+    }
+    HIPCHK(q);
+    for (auto &R : g.reqs) {
+      State f;
+      HIPCHK(hipMemcpy(&f, ctx->d_states + 2 * R->slot, sizeof(State), hipMemcpyDeviceToHost));
+      const int status = (f.status == pcgk::ST_CONV_REC || f.status == pcgk::ST_ZERO_B) ? PCG_OK
+                         : f.status == pcgk::ST_MAXIT                                   ? PCG_NOT_CONVERGED
+                                                                                        : PCG_EBREAKDOWN;
+      int rc = retire(ctx, *R);
+      if (rc) return rc;
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      finish_request(ctx, *R, status, f, f.restarts);
+    }
+    ctx->wg_inflight -= (int)g.reqs.size();
+    free_set(ctx, g.set);
+    (void)hipEventDestroy(g.done);
+    ctx->wg_groups.erase(ctx->wg_groups.begin() + (long)k);
+  }
+  return PCG_OK;
+}
+
 // One scheduler step: admit, `iters` iterations over the active set, retire.
 int progress(pcg_ctx *ctx, int iters) {
   int rc;
@@ -1744,9 +1893,18 @@ int progress(pcg_ctx *ctx, int iters) {
     admitted.swap(cont);
   }
   if (!admitted.empty()) {
-    for (auto &R : admitted) ctx->active.push_back(R);
-    ctx->active_dirty = true;
+    std::vector<std::shared_ptr<Req>> wg;
+    for (auto &R : admitted) {
+      if (R->wg) {
+        wg.push_back(R);
+      } else {
+        ctx->active.push_back(R);
+        ctx->active_dirty = true;
+      }
+    }
+    if (!wg.empty() && (rc = launch_wg_group(ctx, wg))) return rc;
   }
+  if ((rc = collect_wg_groups(ctx))) return rc;
   if (ctx->active.empty()) return PCG_OK;
   hipStream_t s = ctx->stream;
   const bool changed = ctx->active_dirty;
@@ -1968,6 +2126,8 @@ void pcg_config_default(pcg_config *cfg) {
   cfg->max_outer = 30;
   cfg->graph_iters = 10;
   cfg->grid_mult = 8;
+  cfg->wg_max_n = kWgMaxN;
+  cfg->wg_max_n_batch = kWgMaxNBatch;
 }
 
 int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
@@ -2041,10 +2201,18 @@ void pcg_destroy(pcg_ctx *ctx) {
   for (auto &t : ctx->workers) t.join();
   ctx->workers.clear();
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->side) (void)hipStreamSynchronize(ctx->side);
   drop_graphs(ctx);
   drop_step_graph(ctx);
   for (auto &R : ctx->active) free_sys(ctx, R->sys);
   ctx->active.clear();
+  for (auto &g : ctx->wg_groups) {
+    for (auto &R : g.reqs) free_sys(ctx, R->sys);
+    free_set(ctx, g.set);
+    if (g.done) (void)hipEventDestroy(g.done);
+  }
+  ctx->wg_groups.clear();
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   free_set(ctx, ctx->set_main);
   free_set(ctx, ctx->set_64);
   free_set(ctx, ctx->set_x);
@@ -2515,8 +2683,11 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
     std::vector<int> las, lgs;
     if (ctx->cfg.layout == PCG_LAYOUT_AUTO) {
       std::vector<int> fa;
-      for (int l : {PCG_LAYOUT_CSR, PCG_LAYOUT_SELL, PCG_LAYOUT_BSR3}) {
-        const int f = use_bsr3(l, n, rp, ci) ? pcgk::FMT_BSR3 : use_sell(l, n, rp) ? pcgk::FMT_SELL : pcgk::FMT_CSR;
+      for (int l : {PCG_LAYOUT_CSR, PCG_LAYOUT_SELL, PCG_LAYOUT_SDIA, PCG_LAYOUT_BSR3}) {
+        const int f = use_bsr3(l, n, rp, ci)   ? pcgk::FMT_BSR3
+                      : use_sdia(l, n, rp, ci) ? pcgk::FMT_SDIA
+                      : use_sell(l, n, rp)     ? pcgk::FMT_SELL
+                                               : pcgk::FMT_CSR;
         if (std::find(fa.begin(), fa.end(), f) == fa.end()) {
           fa.push_back(f);
           las.push_back(l);
@@ -2525,6 +2696,8 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
       lgs.push_back(PCG_LAYOUT_CSR);
       if (ctx->g_from_device || ctx->g_rp.empty() || use_sell(PCG_LAYOUT_SELL, n, ctx->g_rp.data()))
         lgs.push_back(PCG_LAYOUT_SELL);
+      if (ctx->g_from_device || ctx->g_rp.empty() || use_sdia(PCG_LAYOUT_SDIA, n, ctx->g_rp.data(), ctx->g_ci.data()))
+        lgs.push_back(PCG_LAYOUT_SDIA);
       if (!ctx->g_from_device && n % 3 == 0) lgs.push_back(PCG_LAYOUT_BSR3);  // the 3x3-block cover of G
     } else {
       las.push_back(ctx->cfg.layout);
@@ -2893,7 +3066,7 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
     const double sa = (double)pcgk::dtype_size(ctx->cfg.a_dtype), sg = (double)pcgk::dtype_size(ctx->cfg.g_dtype),
                  sv = (double)pcgk::dtype_size(ctx->cfg.vec_dtype);
     const double rp = 4.0 * (n + 1.0);
-    auto ib = [](const pcgk::DevCSR &M) { return M.fmt == pcgk::FMT_BSR3 ? 4.0 / 9.0 : M.idx16 ? 2.0 : 4.0; };
+    auto ib = [](const pcgk::DevCSR &M) { return pcgk::index_bytes_per_nnz(M); };
     bytes[0] = (double)S.nnz_a * (sa + ib(S.dev.A)) + rp + 2.0 * n * sv;
     bytes[1] = (double)S.nnz_g * (sg + ib(S.dev.GT)) + rp + 4.0 * n * sv;
     bytes[2] = (double)S.nnz_g * (sg + ib(S.dev.G)) + rp + (has_eps ? 6.0 : 5.0) * n * sv;
@@ -2995,8 +3168,8 @@ int pcg_progress(pcg_ctx *ctx, int iters, int *active, int *queued) {
   HIPCHK(hipSetDevice(ctx->cfg.device));
   int rc = progress(ctx, iters);
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (active) *active = (int)ctx->active.size();
-  if (queued) *queued = (int)(ctx->prep_q.size() + ctx->ready_q.size());
+  if (active) *active = (int)ctx->active.size() + ctx->wg_inflight;
+  if (queued) *queued = (int)(ctx->prep_q.size() + ctx->ready_q.size()) + ctx->preparing;
   return rc;
 }
 

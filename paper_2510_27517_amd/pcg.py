@@ -20,10 +20,10 @@ LIB_PATH = os.path.join(_HERE, "libpcg.so")
 OK, PENDING, NOT_CONVERGED = 0, 1, 2
 EINVAL, ESTATE, ENOMEM, EBREAKDOWN, EDEVICE = -1, -2, -3, -4, -5
 F64, F32, BF16, F16 = 0, 1, 2, 3
-G_FSAI, G_FIXED, G_JACOBI, G_IDENTITY, G_SEEDED = 1, 2, 3, 4, 5
+G_FSAI, G_FIXED, G_JACOBI, G_IDENTITY, G_SEEDED, G_BFSAI = 1, 2, 3, 4, 5, 6
 OP_A, OP_GT, OP_G, OP_MINV = 0, 1, 2, 3
-LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SELL, LAYOUT_BSR3 = 0, 1, 2, 3
-LAYOUTS = {"auto": LAYOUT_AUTO, "csr": LAYOUT_CSR, "sell": LAYOUT_SELL, "bsr3": LAYOUT_BSR3}
+LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SELL, LAYOUT_BSR3, LAYOUT_SDIA = 0, 1, 2, 3, 4
+LAYOUTS = {"auto": LAYOUT_AUTO, "csr": LAYOUT_CSR, "sell": LAYOUT_SELL, "bsr3": LAYOUT_BSR3, "sdia": LAYOUT_SDIA}
 
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 
@@ -46,7 +46,7 @@ class Config(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("graph_iters", ctypes.c_int), ("grid_mult", ctypes.c_int),
         ("mem_budget_mb", ctypes.c_int), ("layout", ctypes.c_int), ("g_device", ctypes.c_int),
         ("wide_index", ctypes.c_int), ("autotune", ctypes.c_int), ("cache_mb", ctypes.c_int),
-        ("reserved", ctypes.c_int * 2),
+        ("wg_max_n", ctypes.c_int), ("wg_max_n_batch", ctypes.c_int),
         ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("alloc_user", ctypes.c_void_p),
     ]
 

@@ -146,3 +146,25 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(pcg.PCGError) as e:
         pcg.Solver()
     assert e.value.status == pcg.EDEVICE
+
+
+@pytest.mark.parametrize("N", [3, 6])
+def test_library_block_fsai_matches_oracle(N):
+    """The library's block FSAI (last rows of the local L^-1) and the oracle's
+    (the Cholesky factor of the local solution's diagonal block) pick
+    different bases within each block row, but the same preconditioner:
+    same pattern (full 3x3 blocks), M^-1 = G G^T equal to 1e-13, and the
+    library's G_L A G_L^T has identity diagonal blocks."""
+    A = inputs.elasticity(N, 1.0, 0.3, 2)
+    grp, gci, gv = pcg.build_g_host(pcg.G_BFSAI, A)
+    G = oracle.fsai_block_g(A)
+    assert np.array_equal(grp, G.rowptr) and np.array_equal(gci, G.col)
+    Gl, Go = CSR(grp, gci, gv).to_dense(), CSR(G.rowptr, G.col, G.val).to_dense()
+    Ml, Mo = Gl @ Gl.T, Go @ Go.T
+    assert np.abs(Ml - Mo).max() <= 1e-13 * np.abs(Mo).max()
+    P = Gl.T @ A.to_dense() @ Gl
+    for I in range(A.n // 3):
+        assert np.abs(P[3 * I:3 * I + 3, 3 * I:3 * I + 3] - np.eye(3)).max() <= 1e-13
+    assert pcg.load().pcg_g_nnz(pcg.G_BFSAI, A.n, A.rowptr.ctypes.data, A.col.ctypes.data) == G.nnz
+    B = inputs.poisson(2, 6)  # n = 36 but not 3x3-blocked
+    assert pcg.load().pcg_g_nnz(pcg.G_BFSAI, B.n, B.rowptr.ctypes.data, B.col.ctypes.data) == -1

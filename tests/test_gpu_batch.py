@@ -243,7 +243,9 @@ def test_wait_and_timeout(gpu_lib):
 @pytest.mark.parametrize("refine", [0, 1])
 def test_estimate_bytes_covers_admitted_storage(gpu_lib, refine):
     """The host-only estimate is an upper bound of what admission takes from
-    the pool, for A in CSR, sliced ELL and 3x3 blocks."""
+    the pool, for A in CSR, sliced diagonals and 3x3 blocks (it knows only n
+    and the nonzero counts, so it cannot tell that a stencil needs no column
+    indices in the sliced-diagonal layout: up to about 1.7x there)."""
     pcg = gpu_lib
     kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1) if refine else {}
     cfg = pcg.default_config(**kw)
@@ -261,7 +263,7 @@ def test_estimate_bytes_covers_admitted_storage(gpu_lib, refine):
                 time.sleep(0.002)
             s.wait(t)
         say(f"estimate n={A.n} nnz={A.nnz} refine={refine}: used {used} estimate {est}")
-        assert 0 < used <= est <= 1.4 * used + (512 << 10)
+        assert 0 < used <= est <= 1.8 * used + (512 << 10)
 
 
 @pytest.mark.parametrize("mixed", [0, 1])
@@ -351,3 +353,46 @@ def test_batched_restart_equals_single(gpu_lib):
             assert rb["iters"] == single.iters == ref.iters
             assert np.array_equal(xb, single.x) and np.array_equal(xb, ref.x)
     assert sum(r.restarts for r in refs) >= 2
+
+
+def test_block_fsai_in_a_batch_equals_single(gpu_lib):
+    """Systems with the block FSAI built by the library at admission (host
+    worker) solve bit for bit as alone, next to scalar-FSAI systems."""
+    pcg = gpu_lib
+    systems = []
+    for k, N in enumerate((4, 7, 5)):
+        A = inputs.elasticity(N, 1.0, 0.3, 30 + k)
+        systems.append(dict(A=A, b=inputs.rhs(A.n, 30 + k), g_kind=pcg.G_BFSAI, tol=1e-9, maxit=4000))
+    A = inputs.poisson(3, 12, 0.5, 33)
+    systems.append(dict(A=A, b=inputs.rhs(A.n, 33), tol=1e-9, maxit=4000))
+    with pcg.Solver(pcg.default_config()) as s:
+        batch = s.solve_batch(systems, iters_per_step=5)
+    with pcg.Solver(pcg.default_config()) as s:
+        for sd, (xb, rb) in zip(systems, batch):
+            s.set_matrix(sd["A"])
+            s.build_precond(sd.get("g_kind", pcg.G_FSAI))
+            single = s.solve(sd["b"], tol=sd["tol"], maxit=sd["maxit"])
+            assert rb["status"] == single.status == pcg.OK
+            assert rb["iters"] == single.iters and np.array_equal(xb, single.x)
+
+
+def test_one_workgroup_systems_in_a_batch(gpu_lib):
+    """Batched systems below the one-workgroup limit are solved whole, one
+    workgroup each, in one launch per admission step beside the iterations of
+    the larger ones: every result equals its single solve and the oracle's
+    bit for bit, with the limit on or off."""
+    pcg = gpu_lib
+    systems = []
+    for k, (dim, N) in enumerate([(2, 20), (3, 9), (2, 100), (3, 24), (2, 45), (3, 6)]):
+        A = inputs.poisson(dim, N, 1.0, 40 + k)
+        systems.append(dict(A=A, b=inputs.rhs(A.n, 40 + k), G=oracle.fsai_g(A), tol=1e-9, maxit=4000))
+    out = {}
+    for wg in (-1, 5000):
+        with pcg.Solver(pcg.default_config(wg_max_n_batch=wg)) as s:
+            out[wg] = s.solve_batch(systems, iters_per_step=7)
+    for sd, (x1, r1), (x2, r2) in zip(systems, out[-1], out[5000]):
+        ref = oracle.pcg(sd["A"], sd["G"], sd["b"], tol=1e-9, maxit=4000, delta_form=1)
+        say(f"batch n={sd['A'].n}: three-kernel {r1['iters']} it, one-workgroup {r2['iters']} it, oracle {ref.iters}")
+        assert r1["status"] == r2["status"] == ref.status == pcg.OK
+        assert r1["iters"] == r2["iters"] == ref.iters
+        assert np.array_equal(x1, x2) and np.array_equal(x2, ref.x)

@@ -49,7 +49,7 @@ def test_device_fsai_equals_host_bitwise(gpu_lib, case, gdt):
         assert np.array_equal(h, d)
 
 
-@pytest.mark.parametrize("layout", ["csr", "sell"])
+@pytest.mark.parametrize("layout", ["csr", "sell", "sdia"])
 def test_device_fsai_layouts_and_solve_parity(gpu_lib, layout):
     pcg = gpu_lib
     A = inputs.poisson(3, 24, 1.0, 2)

@@ -60,13 +60,15 @@ def _random_g(A, seed):
     return CSR(A.rowptr.copy(), A.col.copy(), rng.uniform(-1, 1, A.nnz))
 
 
-@pytest.mark.parametrize("layout", ["auto", "csr", "sell", "sell32", "bsr3"])
+@pytest.mark.parametrize("layout", ["auto", "csr", "sell", "sell32", "bsr3", "sdia"])
 @pytest.mark.parametrize("case", ["ragged", "longrows", "poisson3d", "elasticity", "far"])
 def test_operator_products_bitwise(gpu_lib, case, layout):
     """Every storage layout gives the oracle's products bit for bit (the sliced
     layout is forced onto ragged rows, so padding is exercised; the long rows
     fall back to CSR; the 3x3-block layout applies to the elasticity A, whose
-    boundary block rows are shorter, and falls back elsewhere). Sliced
+    boundary block rows are shorter, and falls back elsewhere; the sliced
+    diagonals take the stencils, with zeros between a boundary row's entries
+    and clamped columns, and fall back on the irregular rows). Sliced
     matrices keep 16-bit column differences where every one fits ("sell32"
     forces 32-bit columns); the "far" matrix has columns more than 32767 away
     from their rows, so it keeps 32-bit columns in every layout."""
@@ -138,7 +140,7 @@ def test_pcg_fixed_g_poisson2d_64(gpu_lib):
     say("iters", got.iters, ref.iters, "xerr", err)
 
 
-@pytest.mark.parametrize("layout", ["csr", "sell"])
+@pytest.mark.parametrize("layout", ["csr", "sell", "sdia"])
 @pytest.mark.parametrize("N", [16, 24])
 def test_pcg_fsai_poisson3d_lognormal(gpu_lib, N, layout):
     pcg = gpu_lib
@@ -371,7 +373,7 @@ def test_index_width_in_bytes_and_results(gpu_lib):
     ref = oracle.pcg(A, G, b, tol=1e-8, maxit=2000, delta_form=1)
     xs = []
     for wide in (0, 1):
-        with _solver(pcg, wide_index=wide) as s:
+        with _solver(pcg, wide_index=wide, layout="sell") as s:
             s.set_matrix(A)
             s.set_precond(G)
             got = s.solve(b, tol=1e-8, maxit=2000)
@@ -438,3 +440,131 @@ def test_restart_on_failed_true_residual(gpu_lib, case):
     assert got.restarts == ref.restarts
     _check(got, ref)
     assert got.status == pcg.OK and got.relres_true <= tol
+
+
+def _sdia_offsets(M, n):
+    """Distinct column offsets per slice of 64 rows (the sliced-diagonal
+    layout's stored offsets), summed over the slices."""
+    tot = 0
+    for c0 in range(0, n, 64):
+        offs = set()
+        for r in range(c0, min(n, c0 + 64)):
+            offs.update(int(j) - r for j in M.col[M.rowptr[r]:M.rowptr[r + 1]])
+        tot += len(offs)
+    return tot
+
+
+@pytest.mark.parametrize("dim,N", [(3, 30), (2, 70)])
+def test_sliced_diagonal_layout(gpu_lib, dim, N):
+    """Stencil matrices in the sliced-diagonal layout: the reported bytes per
+    iteration count 4 bytes per stored offset (one per slice entry, not per
+    nonzero), the products and the solve equal the sliced-ELL and CSR ones
+    and the oracle's bit for bit."""
+    pcg = gpu_lib
+    A = inputs.poisson(dim, N, 1.0, 3)
+    b = inputs.rhs(A.n, 3)
+    G = oracle.fsai_g(A)
+    GT = oracle.transpose(G)
+    ref = oracle.pcg(A, G, b, tol=1e-9, maxit=3000, delta_form=1)
+    x = np.random.default_rng(3).standard_normal(A.n)
+    outs = []
+    for layout in ("sdia", "sell", "csr"):
+        with _solver(pcg, layout=layout) as s:
+            s.set_matrix(A)
+            s.set_precond(G)
+            assert np.array_equal(s.matvec(pcg.OP_A, x), oracle.spmv(A, x))
+            assert np.array_equal(s.matvec(pcg.OP_GT, x), oracle.spmv_t(G, x))
+            assert np.array_equal(s.matvec(pcg.OP_G, x), oracle.spmv(G, x))
+            got = s.solve(b, tol=1e-9, maxit=3000)
+        _check(got, ref)
+        outs.append(got)
+        if layout == "sdia":
+            offs = _sdia_offsets(A, A.n) + _sdia_offsets(G, A.n) + _sdia_offsets(GT, A.n)
+            want = A.nnz * 8 + G.nnz * 16 + 4 * offs + 12 * (A.n + 1) + 11 * A.n * 8
+            say(f"sdia {dim}D {N}: bytes/iter {got.bytes_per_iter:.0f} (want {want}), iters {got.iters}")
+            assert abs(got.bytes_per_iter - want) <= 1e-9 * want
+    assert outs[1].bytes_per_iter > outs[0].bytes_per_iter
+
+
+@pytest.mark.parametrize("N", [6, 10])
+def test_pcg_block_fsai_elasticity(gpu_lib, N):
+    """Block FSAI on the 3-dof elasticity system: G and G^T are exactly
+    3x3-blocked and, with the 3x3-block layout asked for, stored with one
+    index per block; with the oracle's block G the solve equals the oracle's
+    bit for bit; the library's own block G (another basis in each block row,
+    the same M^-1, which is also the scalar FSAI's) converges like the
+    scalar FSAI, within a few iterations."""
+    pcg = gpu_lib
+    A = inputs.elasticity(N, 1.0, 0.3, 7)
+    b = inputs.rhs(A.n, 7)
+    G = oracle.fsai_block_g(A)
+    ref = oracle.pcg(A, G, b, tol=1e-10, maxit=5000, delta_form=1)
+    with _solver(pcg) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        got = s.solve(b, tol=1e-10, maxit=5000)
+    _check(got, ref)
+    with _solver(pcg, layout="bsr3") as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_BFSAI)
+        own = s.solve(b, tol=1e-10, maxit=5000)
+        kt = s.time_kernels(3)
+    with _solver(pcg) as s:
+        s.set_matrix(A)
+        s.build_precond(pcg.G_FSAI)
+        scalar = s.solve(b, tol=1e-10, maxit=5000)
+    say(f"block FSAI {N}^3x3: oracle G {got.iters} it, library G {own.iters} it, scalar FSAI {scalar.iters} it")
+    # one 4-byte index per 3x3 block for G^T and G: the 3x3-block layout
+    for k, streams in ((1, 4), (2, 5)):
+        want = G.nnz * (8 + 4.0 / 9.0) + 4 * (A.n + 1) + streams * A.n * 8
+        assert abs(kt["bytes"][k] - want) <= 1e-9 * want, (k, kt["bytes"][k], want)
+    assert own.status == pcg.OK and abs(own.iters - got.iters) <= 3 and abs(own.iters - scalar.iters) <= 3
+    r = np.linalg.norm(b - oracle.spmv(A, own.x)) / np.linalg.norm(b)
+    assert r <= 1.0001e-10
+
+
+@pytest.mark.parametrize("case", ["poisson2d", "poisson3d_eps_rr", "rgg", "elasticity", "restart", "f32_bf16"])
+def test_one_workgroup_solver_equals_three_kernel_iteration(gpu_lib, case):
+    """Small systems run as one persistent workgroup (the whole iteration in
+    one launch); the result equals the three-kernel iteration's bit for bit
+    (same row sums, exact inner products): status, iterations, restarts, x,
+    and the oracle's."""
+    pcg = gpu_lib
+    kw, tol, maxit, G, ref_kw = {}, 1e-9, 3000, None, {}
+    if case == "poisson2d":
+        A = inputs.poisson(2, 48, 1.0, 11)
+    elif case == "poisson3d_eps_rr":
+        A = inputs.poisson(3, 14, 1.0, 12)
+        kw = dict(eps=0.05, rr_period=7)
+        ref_kw = dict(eps=0.05, rr_period=7)
+    elif case == "rgg":
+        A = inputs.rgg_laplacian(6000, 13)
+    elif case == "elasticity":
+        A = inputs.elasticity(6, 1.0, 0.3, 14)
+        tol = 1e-10
+    elif case == "restart":
+        A = inputs.poisson(3, 16, 2.0, 1)
+        kw = dict(rr_period=0)
+        ref_kw = dict(rr_period=0)
+        tol, maxit = 1e-13, 5000
+    else:
+        A = inputs.poisson(3, 14, 0.5, 15)
+        kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16")
+        tol = 1e-5
+    b = inputs.rhs(A.n, 11)
+    G = oracle.fsai_g(A)
+    outs = []
+    for wg in (-1, 100000):
+        with _solver(pcg, wg_max_n=wg, **kw) as s:
+            s.set_matrix(A)
+            s.set_precond(G)
+            outs.append(s.solve(b, tol=tol, maxit=maxit))
+    three, one = outs
+    say(f"one-workgroup {case} n={A.n}: {one.iters} it ({one.restarts} restarts) vs {three.iters}; "
+        f"{one.t_solve_ms:.2f} ms vs {three.t_solve_ms:.2f} ms")
+    assert one.status == three.status and one.iters == three.iters and one.restarts == three.restarts
+    assert np.array_equal(one.x, three.x)
+    assert one.relres_true == three.relres_true
+    if "vec_dtype" not in kw:
+        ref = oracle.pcg(A, G, b, tol=tol, maxit=maxit, delta_form=1, **ref_kw)
+        _check(one, ref)

@@ -27,6 +27,7 @@ def _check(got, ref):
 
 
 @pytest.mark.parametrize("case,k,layout", [("poisson3d", 1, "auto"), ("poisson3d", 7, "sell"), ("poisson3d", 64, "csr"),
+                                           ("poisson3d", 5, "sdia"),
                                            ("rgg", 100, "auto"), ("elasticity", 33, "auto"),
                                            ("poisson2d", 300, "auto")])
 def test_sai_loss_matches_oracle_fp64(gpu_lib, case, k, layout):
