@@ -106,7 +106,8 @@ typedef struct {
                         inner_tol / 10, runs to min(1/2, that target) instead */
   int max_outer;     /* refinement steps at most (default 30) */
   int graph_iters;   /* iterations per captured HIP graph replay (default 10; 0 = plain launches) */
-  int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 8) */
+  int grid_mult;     /* workgroups per compute unit for the SpMV kernels (default 4: every consumer of a
+                        kernel's partial sums reads all of them, so fewer, fuller workgroups pay) */
   int mem_budget_mb; /* device memory pool for batched / served systems, MiB (0: half the free memory at first use) */
   int layout;        /* storage of A, G, G^T: PCG_LAYOUT_AUTO (default), _CSR, _SELL, _BSR3 or _SDIA */
   int g_device;      /* 1: FSAI factored on the device (one wave per row; same arithmetic as the host
@@ -213,7 +214,7 @@ typedef struct {
 
 /* Fills cfg with the defaults: device 0, own stream, all FP64, rr_period 50,
  * eps 0, no refinement, inner_tol 1e-6, max_outer 30, graph_iters 10,
- * grid_mult 8, automatic layouts, no autotuning, wg_max_n 512,
+ * grid_mult 4, automatic layouts, no autotuning, wg_max_n 512,
  * wg_max_n_batch 16384, the default allocator. */
 void pcg_config_default(pcg_config *cfg);
 

@@ -44,6 +44,9 @@ constexpr int kDirCap = 4096;  // systems per context (directory and state slots
 // by one persistent workgroup, alone (measured crossover with the three-kernel
 // iteration near 500 rows) and in a batch (many systems at once)
 constexpr int kWgMaxN = 512;
+// default pcg_config.grid_mult: workgroups per CU of the iteration kernels
+// (128^3 FP64: 94 us per iteration at 4, 102 at 8, 139 at 16)
+constexpr int kGridMult = 4;
 constexpr int kWgMaxNBatch = 16384;
 constexpr int kSlotMain = 0, kSlot64 = 1, kSlotX = 2, kFirstBatchSlot = 3;
 
@@ -238,7 +241,7 @@ struct Sys {
 };
 
 int grid_for(int cus, int mult, int32_t units) {
-  if (mult <= 0) mult = 8;
+  if (mult <= 0) mult = kGridMult;
   int64_t g = std::min<int64_t>(units, (int64_t)cus * mult);
   g = (g + 7) & ~int64_t(7);
   return (int)std::max<int64_t>(g, 8);
@@ -2125,7 +2128,7 @@ void pcg_config_default(pcg_config *cfg) {
   cfg->inner_tol = 1e-6;
   cfg->max_outer = 30;
   cfg->graph_iters = 10;
-  cfg->grid_mult = 8;
+  cfg->grid_mult = kGridMult;
   cfg->wg_max_n = kWgMaxN;
   cfg->wg_max_n_batch = kWgMaxNBatch;
 }
@@ -2678,7 +2681,7 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
     ++ncand;
     const int32_t n = ctx->single.n;
     const int32_t *rp = ctx->a_rp.data(), *ci = ctx->a_ci.data();
-    const int gm0 = ctx->cfg.grid_mult > 0 ? ctx->cfg.grid_mult : 8;
+    const int gm0 = ctx->cfg.grid_mult > 0 ? ctx->cfg.grid_mult : kGridMult;
     // layouts of A (distinct by the format they give) and of G
     std::vector<int> las, lgs;
     if (ctx->cfg.layout == PCG_LAYOUT_AUTO) {
@@ -2762,7 +2765,7 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
   if (res) {
     res->layout_a = best.on ? best.la : ctx->cfg.layout;
     res->layout_g = best.on ? best.lg : ctx->cfg.layout;
-    res->grid_mult = best.on ? best.gm : (ctx->cfg.grid_mult > 0 ? ctx->cfg.grid_mult : 8);
+    res->grid_mult = best.on ? best.gm : (ctx->cfg.grid_mult > 0 ? ctx->cfg.grid_mult : kGridMult);
     res->candidates = ncand;
     res->ms_per_iter = t_best;
     res->ms_per_iter_auto = t_auto;

@@ -51,8 +51,9 @@ def test_autotune_search_cache_and_parity(gpu_lib, tmp_path):
         got = s.solve(b, tol=1e-8, maxit=5000)
         err = _parity(s, got, A, b, 1e-8)
     say(f"  untuned {pre.iters}, tuned {got.iters} iterations, 10-iterate error {err:.2e}")
-    if (t["layout_a"], t["layout_g"], t["grid_mult"]) == (pcg.LAYOUT_AUTO, pcg.LAYOUT_AUTO, 8):
-        assert np.array_equal(got.x, pre.x)  # the automatic choice won: the same solve
+    # layouts give the same products and the inner products are exact, so any
+    # choice of layouts, grid and load policy gives the same solve bit for bit
+    assert got.iters == pre.iters and np.array_equal(got.x, pre.x)
     with pcg.Solver(pcg.default_config()) as s:
         s.set_matrix(A)
         s.build_precond(pcg.G_FSAI)
@@ -125,5 +126,4 @@ def test_autotune_mixed_precision_with_refinement(gpu_lib):
     say("mixed tuned:", t)
     r64 = np.linalg.norm(b - oracle.spmv(A, got.x)) / np.linalg.norm(b)
     assert got.status == pcg.OK and r64 <= 1.0001e-10 and t["candidates"] >= 5
-    if (t["layout_a"], t["layout_g"], t["grid_mult"]) == (pcg.LAYOUT_AUTO, pcg.LAYOUT_AUTO, 8):
-        assert np.array_equal(got.x, pre.x)
+    assert got.iters == pre.iters and np.array_equal(got.x, pre.x)
