@@ -635,7 +635,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": names[dom], "alg_bytes_per_launch": sv[dom], "avg_launch_ms": kt["ms"][dom],
                 "bytes_basis": "int32 CSR indices and row pointers, 8-byte values, the vector streams the kernel "
-                               "needs (the kernel stores 16-bit column differences, so it moves fewer)",
+                               "needs; the stored layouts move fewer (kernels[...].layout_bytes: sliced "
+                               "diagonals keep one offset per slice entry, sliced ELL 16-bit differences)",
                 "per_iteration": {"alg_bytes": sv[3], "ms": round(ms_iter, 5),
                                   "achieved_gbps": round(sv[3] / (ms_iter * 1e-3) / 1e9, 1),
                                   "frac": round(sv[3] / (ms_iter * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),

@@ -185,8 +185,9 @@ typedef struct {
   double relres_rec;   /* recurrence ||r|| / ||b|| at exit */
   double t_solve_ms;   /* single solve: device time; batched: admission to completion (host clock) */
   double bytes_per_iter; /* device bytes of one iteration in the layouts in use: A, G^T and G once
-                            (values, and column indices at their stored width: 4, 2 for 16-bit
-                            differences, 4/9 per value in 3x3 blocks), row pointers, 11 vector streams */
+                            as stored (values with their padding; column information at its stored
+                            width: 4 or 2 bytes per slot, one index per 3x3 block, one offset per
+                            sliced-diagonal entry; row or slice pointers), 11 vector streams */
   double t_latency_ms; /* batched: submission to completion (host clock) */
   double t_queue_ms;   /* batched: submission to admission (host clock) */
   int escalated;       /* single solve under refinement: 1 when the inner solves switched to FP64 */
@@ -428,7 +429,8 @@ int pcg_estimate_bytes(const pcg_config *cfg, int32_t n, int64_t nnz_a, int64_t 
  * read once (values and 4-byte column indices), their row pointers, and 11
  * vector streams of n entries (vec bytes each). Results report the bytes of
  * the layouts actually used (pcg_result.bytes_per_iter), which store 16-bit
- * column differences or one index per 3x3 block where they can. */
+ * column differences, one index per 3x3 block or one offset per sliced-
+ * diagonal entry where they can. */
 double pcg_bytes_per_iter(int32_t n, int64_t nnz_a, int64_t nnz_g, int a_dtype, int g_dtype, int vec_dtype);
 
 const char *pcg_last_error(const pcg_ctx *ctx);

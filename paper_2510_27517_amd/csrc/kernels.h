@@ -113,15 +113,6 @@ struct DevCSR {
   int64_t nidx = 0;
 };
 
-// Bytes of stored column information per nonzero of a placed matrix: int32
-// CSR 4, 16-bit differences 2, one index per 3x3 block 4/9, sliced diagonals
-// 4 per listed offset spread over the nonzeros.
-inline double index_bytes_per_nnz(const DevCSR &M) {
-  if (M.fmt == FMT_BSR3) return 4.0 / 9.0;
-  if (M.fmt == FMT_SDIA) return M.nnz > 0 ? 4.0 * (double)M.nidx / (double)M.nnz : 0.0;
-  return M.idx16 ? 2.0 : 4.0;
-}
-
 // Rows per slice of FMT_SELL; block rows per slice of FMT_BSR3.
 constexpr int kSliceRows = 64;
 constexpr int kBSliceRows = 21;

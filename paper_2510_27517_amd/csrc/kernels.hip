@@ -55,6 +55,11 @@ namespace pcgk {
 #define PCG_WAVES_PER_EU 8
 #endif
 #define PCG_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PCG_WAVES_PER_EU)))
+// The G^T-kernel takes two rows per lane over sliced diagonals (twice the
+// operands per lane): compiled for 4 waves per SIMD (at most 128 VGPRs, no
+// spills), the occupancy its default grid of 4 workgroups of 4 waves per CU
+// gives anyway.
+#define PCG_GT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4)))
 
 #ifndef PCG_UNROLL
 #define PCG_UNROLL 4
@@ -378,6 +383,149 @@ __device__ __forceinline__ void sdia_rows(const Mat<TM> &M, int l, int G, Pre pr
   }
 }
 
+// ---- two rows per lane over sliced diagonals
+//
+// Rows r and r + 1 of a slice read their operands at one offset o from the
+// adjacent entries r + o and r + 1 + o, their values from adjacent slots,
+// and write adjacent results: a lane that owns both rows makes one access of
+// twice the width for each, half the memory instructions of one row per
+// lane (gathers, the bulk of them, are unaligned 8- or 16-byte loads).
+
+// Two adjacent entries of a vector (any alignment of the element type).
+template <typename T>
+struct Pair {
+  T x, y;
+};
+template <typename T>
+__device__ __forceinline__ Pair<T> ld_pair(GLOBAL const T *p, int64_t i) {
+  Pair<T> v;
+  __builtin_memcpy(&v, p + i, sizeof(v));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ void st_pair(GLOBAL T *p, int64_t i, T a, T b) {
+  const Pair<T> v{a, b};
+  __builtin_memcpy(p + i, &v, sizeof(v));
+}
+
+// The operands of rows r0 and r0 + 1 at column offset o, j0 = r0 + o: the
+// entries at j0 and j0 + 1, each clamped into [0, n) as the one-row walk
+// clamps it, from one load of [lo, lo + 1] (n >= 2).
+template <typename T>
+__device__ __forceinline__ Pair<T> gather_pair(GLOBAL const T *x, int32_t j0, int32_t n) {
+  const int32_t lo = min(max(j0, 0), n - 2);
+  const Pair<T> v = ld_pair(x, lo);
+  return Pair<T>{j0 > n - 2 ? v.y : v.x, j0 < 0 ? v.x : v.y};
+}
+
+// Values of two adjacent slots (an even slot of a 64-slot slice entry:
+// aligned to twice the value size), with the matrix's load policy.
+typedef double v2f64 __attribute__((ext_vector_type(2)));
+typedef float v2f32 __attribute__((ext_vector_type(2)));
+typedef _Float16 v2f16 __attribute__((ext_vector_type(2)));
+template <bool NT, typename V>
+__device__ __forceinline__ V ld_aligned(GLOBAL const V *p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+template <bool NT, typename TACC>
+__device__ __forceinline__ void ldval_pair(GLOBAL const double *p, int64_t k, TACC &a, TACC &b) {
+  const v2f64 v = ld_aligned<NT>((GLOBAL const v2f64 *)(p + k));
+  a = (TACC)v.x;
+  b = (TACC)v.y;
+}
+template <bool NT, typename TACC>
+__device__ __forceinline__ void ldval_pair(GLOBAL const float *p, int64_t k, TACC &a, TACC &b) {
+  const v2f32 v = ld_aligned<NT>((GLOBAL const v2f32 *)(p + k));
+  a = (TACC)v.x;
+  b = (TACC)v.y;
+}
+template <bool NT, typename TACC>
+__device__ __forceinline__ void ldval_pair(GLOBAL const bf16_t *p, int64_t k, TACC &a, TACC &b) {
+  const uint32_t v = ld_aligned<NT>((GLOBAL const uint32_t *)(p + k));
+  a = (TACC)__uint_as_float(v << 16);
+  b = (TACC)__uint_as_float(v & 0xffff0000u);
+}
+template <bool NT, typename TACC>
+__device__ __forceinline__ void ldval_pair(GLOBAL const _Float16 *p, int64_t k, TACC &a, TACC &b) {
+  const v2f16 v = ld_aligned<NT>((GLOBAL const v2f16 *)(p + k));
+  a = (TACC)(float)v.x;
+  b = (TACC)(float)v.y;
+}
+
+// Sliced-diagonal rows, two per lane: a wave takes two slices at once (lanes
+// 0-31 the first, 32-63 the second; in each die's range, pairs of slices
+// from the bottom up, or the top down with REV), lane L rows 2 (L mod 32)
+// and 2 (L mod 32) + 1 of its slice. Each row's products are added left to
+// right from zero, as in the one-row walk, so both walks give the same bits.
+// The kernel's functors work on row pairs:
+//   pre2(r0, h0, h1) -> the pair's own operands (rows r0, r0 + 1; h0, h1:
+//                       whether each row exists),
+//   gather2(j0)      -> Pair<TACC>, the operands at columns j0, j0 + 1
+//                       (clamped, gather_pair),
+//   epi2(r0, h0, h1, sum0, sum1, pre_values).
+// n >= 2.
+template <typename TACC, bool NT, bool REV, typename TM, typename Pre2, typename Gather2, typename Epi2>
+__device__ __forceinline__ void sdia_rows2(const Mat<TM> &M, int l, int G, Pre2 pre2, Gather2 gather2, Epi2 epi2) {
+  constexpr int NW = kBlock / 64, U = 4;
+  const int lane = threadIdx.x & 63, half = lane >> 5, lr = 2 * (lane & 31);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = G >> 3, x = l & 7, w = l >> 3;
+  const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
+  const int npairs = (s1 - s0 + 1) / 2;
+  for (int p = w * NW + wv; p < npairs; p += W * NW) {
+    // slices ca (lanes 0-31) and cb = ca + 1 (lanes 32-63); at an odd end of
+    // the range one of them lies outside it and its lanes idle on the other
+    const int ca = REV ? s1 - 2 - 2 * p : s0 + 2 * p, cb = ca + 1;
+    const bool va = ca >= s0, vb = cb < s1;
+    const int cs = half ? (vb ? cb : ca) : (va ? ca : cb);
+    const bool live = half ? vb : va;
+    const int wa = va ? M.blk[ca + 1] - M.blk[ca] : 0, wb = vb ? M.blk[cb + 1] - M.blk[cb] : 0;
+    const int wmax = max(wa, wb);
+    const int o0 = M.blk[cs], wd = M.blk[cs + 1] - o0;
+    const int r0 = cs * kSliceRows + lr;
+    const bool h0 = live && r0 < M.n, h1 = live && r0 + 1 < M.n;
+    const auto pv = pre2(r0, h0, h1);
+    GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lr;
+    GLOBAL const int32_t *off = M.ci + o0;
+    TACC sa = 0, sb = 0;
+    for (int e0 = 0; e0 < wmax; e0 += U) {
+      Pair<TACC> g[U];
+      TACC va_[U], vb_[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // entries past this slice's width repeat its last (in bounds) and are not added
+        const int e = max(min(e0 + u, wd - 1), 0);
+        g[u] = gather2(r0 + off[e]);
+        ldval_pair<NT>(vv, (int64_t)e * kSliceRows, va_[u], vb_[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e0 + u < wd) {
+          sa += va_[u] * g[u].x;
+          sb += vb_[u] * g[u].y;
+        }
+    }
+    epi2(r0, h0, h1, sa, sb, pv);
+  }
+}
+
+// The two-row walk applies to a sliced-diagonal matrix of at least 2 rows.
+template <typename TM>
+__device__ __forceinline__ bool rows2(const Mat<TM> &M) {
+  return M.fmt == FMT_SDIA && M.n >= 2;
+}
+
+template <typename TACC, bool REV = false, typename TM, typename Pre2, typename Gather2, typename Epi2>
+__device__ __forceinline__ void for_rows2(const Mat<TM> &M, int l, int G, Pre2 pre2, Gather2 gather2, Epi2 epi2) {
+  if (M.temporal)
+    sdia_rows2<TACC, false, REV>(M, l, G, pre2, gather2, epi2);
+  else
+    sdia_rows2<TACC, true, REV>(M, l, G, pre2, gather2, epi2);
+}
+
 // Sliced 3x3-block rows: each wave takes whole slices of 21 block rows, one
 // lane per row (lane 63 idle); the three lanes of a block row read the same
 // block column. 8-byte values are stored column-major within the slice (lane
@@ -620,7 +768,7 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_A(const SysDev *_
 }
 
 template <typename TV, typename TG>
-__global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+__global__ __launch_bounds__(kBlock) PCG_GT_OCCUPANCY void k_iter_GT(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                     int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ Acc sh[4 * (kBlock / 64)];
@@ -663,8 +811,49 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_GT(const SysDev *
   GLOBAL const TV *__restrict__ src = gl((const TV *)((((mode == 1) ? it + 1 : it) & 1) ? D.r1 : D.r0));
   GLOBAL TV *__restrict__ dst = gl((TV *)(((it + 1) & 1) ? D.r1 : D.r0));
   Acc part[2] = {{0.0, 0.0}, {0.0, 0.0}};
-  // each die walks its slices from the top down (measured slightly faster)
-  if (mode == 0) {
+  // each die walks its slices from the top down (measured slightly faster);
+  // two rows per lane over sliced diagonals where the operand is the
+  // difference of two gathered vectors (the other kernels, with one, are
+  // faster one row per lane)
+  if (mode == 0 && rows2(GT)) {
+    const int32_t n = GT.n;
+    struct PV {
+      Pair<TV> s, q;
+    };
+    for_rows2<TV, true>(
+        GT, m.y, D.GT.grid,
+        [&](int r0, bool h0, bool h1) -> PV {
+          PV o{{(TV)0, (TV)0}, {(TV)0, (TV)0}};
+          if (h1) {
+            o.s = ld_pair(src, r0);
+            o.q = ld_pair(q, r0);
+          } else if (h0) {
+            o.s.x = src[r0];
+            o.q.x = q[r0];
+          }
+          return o;
+        },
+        [&](int32_t j0) -> Pair<TV> {
+          const Pair<TV> a = gather_pair(src, j0, n), c = gather_pair(q, j0, n);
+          return Pair<TV>{a.x - al * c.x, a.y - al * c.y};
+        },
+        [&](int r0, bool h0, bool h1, TV s0, TV s1, const PV &pv) {
+          const TV ra = pv.s.x - al * pv.q.x, rb = pv.s.y - al * pv.q.y;
+          if (h1) {
+            st_pair(dst, r0, ra, rb);
+            st_pair(t, r0, s0, s1);
+            acc_prod(part[0], ra, ra);
+            acc_prod(part[1], s0, s0);
+            acc_prod(part[0], rb, rb);
+            acc_prod(part[1], s1, s1);
+          } else if (h0) {
+            dst[r0] = ra;
+            t[r0] = s0;
+            acc_prod(part[0], ra, ra);
+            acc_prod(part[1], s0, s0);
+          }
+        });
+  } else if (mode == 0) {
     for_rows<TV, 4, true>(
         GT, m.y, D.GT.grid, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
         [&](int j) -> TV { return src[j] - al * q[j]; },

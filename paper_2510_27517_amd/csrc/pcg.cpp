@@ -877,11 +877,25 @@ pcg_config eff_cfg(const pcg_ctx *ctx, bool for_g) {
   return c;
 }
 
-// Bytes of one placed matrix (values and indices at their stored widths, row
-// pointers; sliced padding not counted).
+// Bytes a product with a placed matrix reads from it, as stored: values
+// (padding included), column information and row or slice pointers.
+// vsize: bytes per stored value.
+double stored_matrix_bytes(const DevCSR &M, double vsize) {
+  switch (M.fmt) {
+    case pcgk::FMT_SELL:  // one value and one index per slot
+      return (double)M.nidx * (vsize + (M.idx16 ? 2.0 : 4.0)) + 4.0 * (M.nblk + 1.0);
+    case pcgk::FMT_SDIA:  // 64 values and one offset per slice entry
+      return (double)M.nidx * (pcgk::kSliceRows * vsize + 4.0) + 4.0 * (M.nblk + 1.0);
+    case pcgk::FMT_BSR3:  // nine values and one index per stored block
+      return (double)M.nidx * (9.0 * vsize + 4.0) + 4.0 * (M.nblk + 1.0);
+    default:  // CSR with row blocks
+      return (double)M.nnz * (vsize + 4.0) + 4.0 * (M.n + 1.0) + 8.0 * (M.nblk + 1.0);
+  }
+}
+
+// Bytes of one placed matrix as stored (padding included).
 double placed_bytes(const pcgk::DevCSR &M) {
-  const double ib = pcgk::index_bytes_per_nnz(M);
-  return (double)M.nnz * ((double)pcgk::dtype_size(M.dtype) + ib) + 4.0 * (M.n + 1.0);
+  return stored_matrix_bytes(M, (double)pcgk::dtype_size(M.dtype));
 }
 
 // Residency plan of the single system: which matrices are read with ordinary
@@ -1463,12 +1477,11 @@ void start_workers(pcg_ctx *ctx) {
 // column indices at their stored widths (3x3 blocks: one index per nine
 // values; 16-bit column differences: two bytes), its row pointers, and the
 // 11 vector streams.
-double layout_bytes_per_iter(const SysDev &D, int64_t nnz_a, int64_t nnz_g, const pcg_config &cfg) {
-  auto ib = [](const pcgk::DevCSR &M) { return pcgk::index_bytes_per_nnz(M); };
+double layout_bytes_per_iter(const SysDev &D, const pcg_config &cfg) {
   const double sa = (double)pcgk::dtype_size(cfg.a_dtype), sg = (double)pcgk::dtype_size(cfg.g_dtype),
-               sv = (double)pcgk::dtype_size(cfg.vec_dtype), rp = 4.0 * (D.n + 1.0);
-  return (double)nnz_a * (sa + ib(D.A)) + (double)nnz_g * (2.0 * sg + ib(D.G) + ib(D.GT)) + 3.0 * rp +
-         11.0 * D.n * sv;
+               sv = (double)pcgk::dtype_size(cfg.vec_dtype);
+  return stored_matrix_bytes(D.A, sa) + stored_matrix_bytes(D.G, sg) +
+         stored_matrix_bytes(D.GT, sg) + 11.0 * D.n * sv;
 }
 
 void finish_request(pcg_ctx *ctx, Req &R, int status, const State &f, int restarts) {
@@ -1627,7 +1640,7 @@ int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::v
     }
     R.sys.dev.st = ctx->d_states + 2 * R.slot;
     ctx->dir[R.slot] = R.sys.dev;
-    R.res.bytes_per_iter = layout_bytes_per_iter(R.sys.dev, R.sys.nnz_a, R.sys.nnz_g, ctx->cfg);
+    R.res.bytes_per_iter = layout_bytes_per_iter(R.sys.dev, ctx->cfg);
     inits[2 * i] = inits[2 * i + 1] = init_state(ctx, R.tol, R.maxit, R.sys.g_scale);
     R.iter_host = 0;
     if (ctx->cfg.refine) {
@@ -2797,7 +2810,7 @@ int pcg_solve(pcg_ctx *ctx, const double *b, double *x, double tol, int maxit, i
   HIPCHK(hipSetDevice(ctx->cfg.device));
   if (on_device) HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipEventRecord(ctx->t0, ctx->stream));
-  const double bpi = layout_bytes_per_iter(S.dev, S.nnz_a, S.nnz_g, ctx->cfg);
+  const double bpi = layout_bytes_per_iter(S.dev, ctx->cfg);
   if (ctx->cfg.refine) {
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpyAsync(S.dev64.b, b, sizeof(double) * n, kind, ctx->stream));
@@ -3068,11 +3081,9 @@ int pcg_time_kernels(pcg_ctx *ctx, int iters, double *ms, double *bytes) {
   if (bytes) {
     const double sa = (double)pcgk::dtype_size(ctx->cfg.a_dtype), sg = (double)pcgk::dtype_size(ctx->cfg.g_dtype),
                  sv = (double)pcgk::dtype_size(ctx->cfg.vec_dtype);
-    const double rp = 4.0 * (n + 1.0);
-    auto ib = [](const pcgk::DevCSR &M) { return pcgk::index_bytes_per_nnz(M); };
-    bytes[0] = (double)S.nnz_a * (sa + ib(S.dev.A)) + rp + 2.0 * n * sv;
-    bytes[1] = (double)S.nnz_g * (sg + ib(S.dev.GT)) + rp + 4.0 * n * sv;
-    bytes[2] = (double)S.nnz_g * (sg + ib(S.dev.G)) + rp + (has_eps ? 6.0 : 5.0) * n * sv;
+    bytes[0] = stored_matrix_bytes(S.dev.A, sa) + 2.0 * n * sv;
+    bytes[1] = stored_matrix_bytes(S.dev.GT, sg) + 4.0 * n * sv;
+    bytes[2] = stored_matrix_bytes(S.dev.G, sg) + (has_eps ? 6.0 : 5.0) * n * sv;
     bytes[3] = bytes[0] + bytes[1] + bytes[2];
   }
   return PCG_OK;

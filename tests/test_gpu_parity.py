@@ -362,13 +362,12 @@ def test_pcg_synthetic_ppt(gpu_lib):
 
 def test_index_width_in_bytes_and_results(gpu_lib):
     """3D Poisson in the sliced layout: with 16-bit column differences the
-    reported bytes per iteration count two bytes per stored index of A, G and
-    G^T, with 32-bit columns four; the two solves are bit-identical and hold
-    parity with the oracle."""
+    reported bytes per iteration (the layouts as stored, padding included)
+    count two bytes per stored index of A, G and G^T, with 32-bit columns
+    four; the two solves are bit-identical and hold parity with the oracle."""
     pcg = gpu_lib
     A = inputs.poisson(3, 30, 1.0, 3)
     b = inputs.rhs(A.n, 3)
-    g = oracle.tril_nnz(A)
     G = oracle.fsai_g(A)
     ref = oracle.pcg(A, G, b, tol=1e-8, maxit=2000, delta_form=1)
     xs = []
@@ -378,7 +377,8 @@ def test_index_width_in_bytes_and_results(gpu_lib):
             s.set_precond(G)
             got = s.solve(b, tol=1e-8, maxit=2000)
         ib = 4 if wide else 2
-        want = A.nnz * (8 + ib) + g * (16 + 2 * ib) + 12 * (A.n + 1) + 11 * A.n * 8
+        GT = oracle.transpose(G)
+        want = _sell_bytes(A, 8, ib) + _sell_bytes(G, 8, ib) + _sell_bytes(GT, 8, ib) + 11 * A.n * 8
         say(f"index width {ib}: bytes/iter {got.bytes_per_iter:.0f} (want {want}), iters {got.iters}")
         assert got.bytes_per_iter == want
         _check(got, ref)
@@ -392,7 +392,8 @@ def test_fsai_g_in_padded_blocks(gpu_lib, layout, N):
     diagonal blocks are triangular); the automatic and the forced block
     layouts store its 3x3-block cover with explicit zeros. Products equal the
     oracle's (the zeros add +0 to each row's sum, in the same order), the
-    kernels count one 4-byte index per block, and the solve holds parity.
+    kernels count the cover as stored (nine values and one 4-byte index per
+    block), and the solve holds parity.
     The automatic choice takes the cover where its slices pad little (the
     20^3-node system; the 6^3 one is mostly boundary)."""
     pcg = gpu_lib
@@ -409,8 +410,8 @@ def test_fsai_g_in_padded_blocks(gpu_lib, layout, N):
         assert np.array_equal(s.matvec(pcg.OP_MINV, x), oracle.apply_precond(G, x, 0.0))
         got = s.solve(b, tol=1e-10, maxit=3000)
         kt = s.time_kernels(3)
-    ib = 4.0 / 9.0 if layout != "sell" else 2.0
-    want = G.nnz * (8 + ib) + 4 * (A.n + 1) + 5 * A.n * 8
+    gb = _sell_bytes(G, 8, 2) if layout == "sell" else _bsr_bytes(G, 8)
+    want = gb + 5 * A.n * 8
     say(f"  G-kernel bytes {kt['bytes'][2]:.0f} (want {want:.0f})")
     assert abs(kt["bytes"][2] - want) <= 1e-9 * want
     ref = oracle.pcg(A, G, b, tol=1e-10, maxit=3000, delta_form=1)
@@ -442,6 +443,43 @@ def test_restart_on_failed_true_residual(gpu_lib, case):
     assert got.status == pcg.OK and got.relres_true <= tol
 
 
+def _rowlen(M):
+    return np.diff(M.rowptr)
+
+
+def _sell_bytes(M, vs, ib):
+    """Bytes of M in the sliced-ELL layout: every slice of 64 rows stores 64
+    slots per entry of its longest row (values and column indices), plus the
+    slice pointers."""
+    ln = _rowlen(M)
+    ns = (M.n + 63) // 64
+    stored = sum(64 * int(ln[c * 64:(c + 1) * 64].max()) for c in range(ns))
+    return stored * (vs + ib) + 4 * (ns + 1)
+
+
+def _sdia_bytes(M, vs):
+    """Bytes of M in the sliced-diagonal layout: 64 values and one 4-byte
+    offset per distinct offset of each slice, plus the slice pointers."""
+    ns = (M.n + 63) // 64
+    return _sdia_offsets(M, M.n) * (64 * vs + 4) + 4 * (ns + 1)
+
+
+def _bsr_bytes(M, vs):
+    """Bytes of the 3x3-block cover of M in the sliced block layout: slices
+    of 21 block rows store 21 blocks (nine values, one index) per block
+    column of their widest block row, plus the slice pointers."""
+    nbr = M.n // 3
+    widths = []
+    for R in range(nbr):
+        cols = set()
+        for r in range(3 * R, 3 * R + 3):
+            cols.update(int(j) // 3 for j in M.col[M.rowptr[r]:M.rowptr[r + 1]])
+        widths.append(len(cols))
+    ns = (nbr + 20) // 21
+    blocks = sum(21 * max(widths[c * 21:(c + 1) * 21]) for c in range(ns))
+    return blocks * (9 * vs + 4) + 4 * (ns + 1)
+
+
 def _sdia_offsets(M, n):
     """Distinct column offsets per slice of 64 rows (the sliced-diagonal
     layout's stored offsets), summed over the slices."""
@@ -454,12 +492,56 @@ def _sdia_offsets(M, n):
     return tot
 
 
+def _banded_spd(n, offsets, seed):
+    """Symmetric banded matrix with entries at the given distances from the
+    diagonal (those inside the matrix), uniform off-diagonal values in
+    (-1, 0) and a dominant diagonal: SPD, every row a different length near
+    the ends."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for o in (o for o in offsets if o < n):
+        i = np.arange(0, n - o)
+        v = -rng.uniform(0.05, 1.0, n - o)
+        rows += [i, i + o]
+        cols += [i + o, i]
+        vals += [v, v]
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    m = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    d = np.asarray(abs(m).sum(axis=1)).ravel() + rng.uniform(0.5, 1.5, n)
+    m = (m + sp.diags(d)).tocsr()
+    m.sort_indices()
+    return CSR.from_scipy(m)
+
+
+@pytest.mark.parametrize("gm", [1, 4])
+@pytest.mark.parametrize("n", [2, 3, 5, 64, 65, 127, 129, 1000, 4097, 20001])
+def test_two_row_walk_sizes(gpu_lib, n, gm):
+    """The G^T-kernel takes two rows per lane over sliced diagonals: pairs of
+    slices per wave, an odd last row, an odd count of slices in a die's
+    range, operand columns clamped at both ends of the vector. Solves
+    of banded matrices of every size and parity (three-kernel path forced
+    for the tiny ones) equal the oracle's bit for bit, on two grid sizes."""
+    pcg = gpu_lib
+    A = _banded_spd(n, (1, 2, 7), n)
+    b = inputs.rhs(n, 5)
+    G = oracle.fsai_g(A)
+    ref = oracle.pcg(A, G, b, tol=1e-10, maxit=400, delta_form=1)
+    say("two-row walk", n, gm, A.nnz)
+    with _solver(pcg, layout="sdia", grid_mult=gm, wg_max_n=0, wg_max_n_batch=0) as s:
+        s.set_matrix(A)
+        s.set_precond(G)
+        got = s.solve(b, tol=1e-10, maxit=400)
+    _check(got, ref)
+
+
 @pytest.mark.parametrize("dim,N", [(3, 30), (2, 70)])
 def test_sliced_diagonal_layout(gpu_lib, dim, N):
     """Stencil matrices in the sliced-diagonal layout: the reported bytes per
-    iteration count 4 bytes per stored offset (one per slice entry, not per
-    nonzero), the products and the solve equal the sliced-ELL and CSR ones
-    and the oracle's bit for bit."""
+    iteration count 64 values and one 4-byte offset per slice entry (no index
+    per nonzero), the products and the solve equal the sliced-ELL and CSR
+    ones and the oracle's bit for bit."""
     pcg = gpu_lib
     A = inputs.poisson(dim, N, 1.0, 3)
     b = inputs.rhs(A.n, 3)
@@ -479,8 +561,7 @@ def test_sliced_diagonal_layout(gpu_lib, dim, N):
         _check(got, ref)
         outs.append(got)
         if layout == "sdia":
-            offs = _sdia_offsets(A, A.n) + _sdia_offsets(G, A.n) + _sdia_offsets(GT, A.n)
-            want = A.nnz * 8 + G.nnz * 16 + 4 * offs + 12 * (A.n + 1) + 11 * A.n * 8
+            want = _sdia_bytes(A, 8) + _sdia_bytes(G, 8) + _sdia_bytes(GT, 8) + 11 * A.n * 8
             say(f"sdia {dim}D {N}: bytes/iter {got.bytes_per_iter:.0f} (want {want}), iters {got.iters}")
             assert abs(got.bytes_per_iter - want) <= 1e-9 * want
     assert outs[1].bytes_per_iter > outs[0].bytes_per_iter
@@ -515,8 +596,9 @@ def test_pcg_block_fsai_elasticity(gpu_lib, N):
         scalar = s.solve(b, tol=1e-10, maxit=5000)
     say(f"block FSAI {N}^3x3: oracle G {got.iters} it, library G {own.iters} it, scalar FSAI {scalar.iters} it")
     # one 4-byte index per 3x3 block for G^T and G: the 3x3-block layout
-    for k, streams in ((1, 4), (2, 5)):
-        want = G.nnz * (8 + 4.0 / 9.0) + 4 * (A.n + 1) + streams * A.n * 8
+    GT = oracle.transpose(G)
+    for k, M, streams in ((1, GT, 4), (2, G, 5)):
+        want = _bsr_bytes(M, 8) + streams * A.n * 8
         assert abs(kt["bytes"][k] - want) <= 1e-9 * want, (k, kt["bytes"][k], want)
     assert own.status == pcg.OK and abs(own.iters - got.iters) <= 3 and abs(own.iters - scalar.iters) <= 3
     r = np.linalg.norm(b - oracle.spmv(A, own.x)) / np.linalg.norm(b)
