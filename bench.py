@@ -228,7 +228,8 @@ def section_autotune(pcg, torch, A, G, b_dev, steps, t_auto_ms):
     names = {v: k for k, v in pcg.LAYOUTS.items()}
     return {"workload": "poisson3d_128^3_sigma1_fsai, FP64, tol 1e-8", "tune_s": round(t_tune, 2),
             "candidates": t["candidates"], "layout_a": names.get(t["layout_a"]), "layout_g": names.get(t["layout_g"]),
-            "grid_mult": t["grid_mult"], "ms_per_iter_tuned": round(t["ms_per_iter"], 5),
+            "grid_mult": t["grid_mult"], "temporal": t["temporal"], "rows_per_lane_gt": t["rows_per_lane_gt"],
+            "loads_in_flight_a": t["loads_in_flight_a"], "ms_per_iter_tuned": round(t["ms_per_iter"], 5),
             "ms_per_iter_auto": round(t["ms_per_iter_auto"], 5), "time_to_tol_ms": round(ms, 3),
             "time_to_tol_ms_auto": round(t_auto_ms, 3), "iters": r.iters, "status": r.status}
 
@@ -287,6 +288,8 @@ def section_synthetic(pcg, inputs, count):
         out[tag]["autotuned"] = {"time_to_tol_ms": round(ms, 2), "iters": r.iters, "status": r.status,
                                  "layout_a": names.get(t["layout_a"]), "layout_g": names.get(t["layout_g"]),
                                  "grid_mult": t["grid_mult"], "temporal": t["temporal"],
+                                 "rows_per_lane_gt": t["rows_per_lane_gt"],
+                                 "loads_in_flight_a": t["loads_in_flight_a"],
                                  "ms_per_iter_tuned": round(t["ms_per_iter"], 5),
                                  "ms_per_iter_auto": round(t["ms_per_iter_auto"], 5)}
     log(f"synthetic: batch of {count}")

@@ -135,6 +135,11 @@ typedef struct {
                         step run together, one workgroup each, in one launch on a second stream,
                         beside the iterations of the larger ones (many small systems keep the GPU
                         busy where one would not). 0: the default; -1: never */
+  int rows_per_lane; /* rows per lane of the G^T-kernel over sliced diagonals: 2 (every operand,
+                        value and result access twice as wide; the default) or 1. 0: the default.
+                        Results are the same bit for bit either way */
+  int loads_in_flight; /* loads in flight per lane in the A-kernel's sliced rows of more than 4
+                        entries: 8 (the default) or 4. 0: the default. Same results either way */
   /* Optional device allocator (for example a framework's caching allocator),
    * used for every device allocation of the context (matrices, vectors,
    * directory, serving pool, scratch): alloc returns at least `bytes` bytes of
@@ -216,13 +221,15 @@ typedef struct {
 /* Fills cfg with the defaults: device 0, own stream, all FP64, rr_period 50,
  * eps 0, no refinement, inner_tol 1e-6, max_outer 30, graph_iters 10,
  * grid_mult 4, automatic layouts, no autotuning, wg_max_n 512,
- * wg_max_n_batch 16384, the default allocator. */
+ * wg_max_n_batch 16384, rows_per_lane 2, loads_in_flight 8, the default
+ * allocator. */
 void pcg_config_default(pcg_config *cfg);
 
 /* Creates a context on cfg->device. Returns PCG_EDEVICE if no usable GPU,
  * PCG_EINVAL for an unsupported dtype combination (FP64 vectors need FP64 A
  * and no refinement; FP32 vectors need FP32 A and a G of FP32, BF16 or FP16),
- * a negative rr_period, graph_iters or mem_budget_mb, eps < 0 or NaN, or
+ * a negative rr_period, graph_iters or mem_budget_mb, eps < 0 or NaN,
+ * rows_per_lane other than 0, 1, 2, loads_in_flight other than 0, 4, 8, or
  * only one of alloc / free. *out is NULL on failure. */
 int pcg_create(const pcg_config *cfg, pcg_ctx **out);
 void pcg_destroy(pcg_ctx *ctx);
@@ -388,12 +395,15 @@ int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, 
  * 3x3-block cover), at the configured grid, then for the best layouts at
  * half and twice the grid, then the load policy (each subset of A, G, G^T
  * read with ordinary loads and kept in the memory-side cache, besides the
- * residency plan's choice), and keeps the fastest (a candidate must beat the
- * current best by 3%).
+ * residency plan's choice), then two kernel knobs: rows per lane of the
+ * G^T-kernel over sliced diagonals (two rows make every access twice as
+ * wide, or one) and loads in flight per lane in the A-kernel's sliced rows
+ * (8 or 4), and keeps the fastest (a candidate must beat the current best
+ * by 3%).
  * The matrices are laid out again with the same values, so products stay
- * bit-identical; the grid changes the partial-sum order of the dot products.
- * A layout forced in the configuration is kept; only the grid and the load
- * policy are tuned then.
+ * bit-identical, and inner products are exact: every candidate gives the
+ * same solve bit for bit. A layout forced in the configuration is kept; only
+ * the grid, the load policy and the kernel knobs are tuned then.
  * The choice is cached per matrix signature (sizes, row-length structure, 3x3
  * blocking, storage types, options, compute units) for the process, and in
  * the file named by the environment variable PCG_TUNE_CACHE when set; a
@@ -411,6 +421,8 @@ typedef struct {
                               3 sliced diagonals */
   int idx16;              /* bit 0/1/2: A / G / G^T keep 16-bit column differences */
   int temporal;           /* bit 0/1/2: A / G / G^T read with ordinary loads (cache-resident) */
+  int rows_per_lane_gt;   /* rows per lane of the G^T-kernel over sliced diagonals: 2 (default) or 1 */
+  int loads_in_flight_a;  /* loads in flight per lane of the A-kernel's sliced rows: 8 (default) or 4 */
   double ms_per_iter;      /* chosen configuration, one iteration */
   double ms_per_iter_auto; /* the automatic choice (NaN when taken from the cache) */
 } pcg_tune_result;

@@ -111,6 +111,7 @@ struct DevCSR {
   int32_t idx16 = 0;     // FMT_SELL only: ci holds int16 column - row differences
   int32_t temporal = 0;  // 1: ordinary loads (kept in the memory-side cache); 0: nontemporal
   int64_t nidx = 0;
+  int32_t rpl = 2;  // rows per lane over sliced diagonals where the kernel offers two (the G^T-kernel): 1 or 2
 };
 
 // Rows per slice of FMT_SELL; block rows per slice of FMT_BSR3.
@@ -151,6 +152,7 @@ struct LaunchSet {
   const int2 *mapA = nullptr, *mapGT = nullptr, *mapG = nullptr, *mapB = nullptr;
   const int32_t *set = nullptr;
   int32_t nA = 0, nGT = 0, nG = 0, nB = 0, nset = 0;  // workgroups of each kind, systems
+  int32_t uw_a = 8;  // loads in flight per lane in the A-kernel's one-row sliced walks: 4 or 8
 };
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------

@@ -143,11 +143,13 @@ struct Mat {
   int32_t fmt;
   int32_t idx16;
   int32_t temporal;
+  int32_t rpl;
 };
 
 template <typename TM>
 __device__ __forceinline__ Mat<TM> mat(const DevCSR &m) {
-  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk, m.n, m.fmt, m.idx16, m.temporal};
+  return Mat<TM>{gl(m.rp), gl(m.ci), gl((const TM *)m.val), gl(m.blk), m.nblk, m.n, m.fmt, m.idx16, m.temporal,
+                 m.rpl};
 }
 
 // Column of stored entry q of `row`: an absolute int32 index, or (sliced
@@ -512,10 +514,11 @@ __device__ __forceinline__ void sdia_rows2(const Mat<TM> &M, int l, int G, Pre2 
   }
 }
 
-// The two-row walk applies to a sliced-diagonal matrix of at least 2 rows.
+// The two-row walk applies to a sliced-diagonal matrix of at least 2 rows
+// placed with two rows per lane.
 template <typename TM>
 __device__ __forceinline__ bool rows2(const Mat<TM> &M) {
-  return M.fmt == FMT_SDIA && M.n >= 2;
+  return M.fmt == FMT_SDIA && M.n >= 2 && M.rpl == 2;
 }
 
 template <typename TACC, bool REV = false, typename TM, typename Pre2, typename Gather2, typename Epi2>
@@ -744,7 +747,9 @@ __device__ __forceinline__ void ew_rows(int n, int l, int G, int64_t &i0, int64_
   i1 = (int64_t)(l + 1) * n / G;
 }
 
-template <typename TV, typename TA>
+// UW: loads in flight per lane in the one-row sliced walks (rows longer
+// than 4 entries), a tuning knob.
+template <typename TV, typename TA, int UW>
 __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_A(const SysDev *__restrict__ dir, const int2 *__restrict__ map) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ Acc sh[4 * (kBlock / 64)];
@@ -757,7 +762,7 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_A(const SysDev *_
   GLOBAL TV *__restrict__ q = gl((TV *)D.q);
   GLOBAL const TV *__restrict__ dcur = gl((const TV *)((it & 1) ? D.d1 : D.d0));  // d_i
   Acc part[1] = {{0.0, 0.0}};
-  for_rows<TV, 8>(
+  for_rows<TV, UW>(
       A, m.y, D.A.grid, lds, [&](int row) { return RowVals<TV>{dcur[row], (TV)0, (TV)0}; },
       [&](int j) -> TV { return dcur[j]; },
       [&](int row, TV sum, const RowVals<TV> &pv) {
@@ -1844,10 +1849,17 @@ static inline int ew_grid(int64_t n) {
 
 hipError_t launch_iter_A(const Types &ty, const LaunchSet &L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (L.nA == 0) return hipSuccess;
+  const bool u4 = L.uw_a == 4;
   if (ty.vec == F64 && ty.a == F64) {
-    PCG_LAUNCH((k_iter_A<double, double>), L.nA, s, e0, e1, L.dir, L.mapA);
+    if (u4)
+      PCG_LAUNCH((k_iter_A<double, double, 4>), L.nA, s, e0, e1, L.dir, L.mapA);
+    else
+      PCG_LAUNCH((k_iter_A<double, double, 8>), L.nA, s, e0, e1, L.dir, L.mapA);
   } else if (ty.vec == F32 && ty.a == F32) {
-    PCG_LAUNCH((k_iter_A<float, float>), L.nA, s, e0, e1, L.dir, L.mapA);
+    if (u4)
+      PCG_LAUNCH((k_iter_A<float, float, 4>), L.nA, s, e0, e1, L.dir, L.mapA);
+    else
+      PCG_LAUNCH((k_iter_A<float, float, 8>), L.nA, s, e0, e1, L.dir, L.mapA);
   } else {
     return hipErrorInvalidValue;
   }

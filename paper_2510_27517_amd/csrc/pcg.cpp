@@ -717,6 +717,8 @@ struct pcg_ctx {
     bool on = false;
     int la = PCG_LAYOUT_AUTO, lg = PCG_LAYOUT_AUTO, gm = 8;
     int res = -1;  // matrices read with ordinary loads (bit 0 A, 1 G, 2 G^T); -1: the residency plan
+    int gt_rows = 2;  // rows per lane of the G^T-kernel over sliced diagonals (1 or 2)
+    int a_uw = 8;     // loads in flight per lane of the A-kernel's one-row sliced walks (4 or 8)
   } tune;
   Sys single;
   HostSet set_main, set_64;
@@ -834,6 +836,10 @@ int build_set(pcg_ctx *ctx, HostSet &hs, const std::vector<int> &slots) {
   return PCG_OK;
 }
 
+// Kernel knobs of the configuration (0: the defaults).
+int cfg_rows_per_lane(const pcg_config &c) { return c.rows_per_lane == 1 ? 1 : 2; }
+int cfg_loads_in_flight(const pcg_config &c) { return c.loads_in_flight == 4 ? 4 : 8; }
+
 int upload_dir_entry(pcg_ctx *ctx, int slot) {
   HIPCHK(hipMemcpy(ctx->d_dir + slot, &ctx->dir[slot], sizeof(SysDev), hipMemcpyHostToDevice));
   return PCG_OK;
@@ -931,6 +937,7 @@ int single_sets(pcg_ctx *ctx) {
     ctx->single.dev.G.temporal = (r >> 1) & 1;
     ctx->single.dev.GT.temporal = (r >> 2) & 1;
     ctx->single.dev64.A.temporal = 0;
+    ctx->single.dev.GT.rpl = ctx->tune.on ? ctx->tune.gt_rows : cfg_rows_per_lane(ctx->cfg);
   }
   ctx->single.dev.st = ctx->d_states + 2 * kSlotMain;
   ctx->dir[kSlotMain] = ctx->single.dev;
@@ -942,7 +949,9 @@ int single_sets(pcg_ctx *ctx) {
     if ((rc = upload_dir_entry(ctx, kSlot64))) return rc;
     if ((rc = build_set(ctx, ctx->set_64, {kSlot64}))) return rc;
   }
-  return build_set(ctx, ctx->set_main, {kSlotMain});
+  if ((rc = build_set(ctx, ctx->set_main, {kSlotMain}))) return rc;
+  ctx->set_main.L.uw_a = ctx->tune.on ? ctx->tune.a_uw : cfg_loads_in_flight(ctx->cfg);
+  return PCG_OK;
 }
 
 void enqueue_iteration(pcg_ctx *ctx, const Types &ty, const LaunchSet &L, bool replace, double eps, hipError_t &e) {
@@ -2144,6 +2153,8 @@ void pcg_config_default(pcg_config *cfg) {
   cfg->grid_mult = kGridMult;
   cfg->wg_max_n = kWgMaxN;
   cfg->wg_max_n_batch = kWgMaxNBatch;
+  cfg->rows_per_lane = 2;
+  cfg->loads_in_flight = 8;
 }
 
 int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
@@ -2154,8 +2165,9 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
   const bool g_ok = g == PCG_F64 || g == PCG_F32 || g == PCG_BF16 || g == PCG_F16;
   const bool ok = (v == PCG_F64 && a == PCG_F64 && g_ok && !cfg->refine) ||
                   (v == PCG_F32 && a == PCG_F32 && g_ok && g != PCG_F64);
+  const int rpl = cfg->rows_per_lane, uw = cfg->loads_in_flight;
   if (!ok || cfg->rr_period < 0 || cfg->graph_iters < 0 || !(cfg->eps >= 0.0) || cfg->mem_budget_mb < 0 ||
-      (cfg->alloc == nullptr) != (cfg->free == nullptr))
+      (cfg->alloc == nullptr) != (cfg->free == nullptr) || rpl < 0 || rpl > 2 || (uw != 0 && uw != 4 && uw != 8))
     return PCG_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= cfg->device || cfg->device < 0) {
@@ -2565,15 +2577,18 @@ static void tune_cache_load() {
   if (!path || !*path) return;
   FILE *f = std::fopen(path, "r");
   if (!f) return;
-  char key[512];
-  int la, lg, gm, res;
-  while (std::fscanf(f, "%511s %d %d %d %d", key, &la, &lg, &gm, &res) == 5) {
+  char line[768], key[512];
+  while (std::fgets(line, sizeof line, f)) {
+    int la, lg, gm, res, rows, uw;
+    if (std::sscanf(line, "%511s %d %d %d %d %d %d", key, &la, &lg, &gm, &res, &rows, &uw) != 7) continue;
     pcg_ctx::Tune t;
     t.on = true;
     t.la = la;
     t.lg = lg;
     t.gm = gm;
     t.res = res;
+    t.gt_rows = rows == 1 ? 1 : 2;
+    t.a_uw = uw == 4 ? 4 : 8;
     g_tune_cache[key] = t;
   }
   std::fclose(f);
@@ -2585,7 +2600,7 @@ static void tune_cache_store(const std::string &key, const pcg_ctx::Tune &t) {
   if (!path || !*path) return;
   FILE *f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), t.la, t.lg, t.gm, t.res);
+  std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), t.la, t.lg, t.gm, t.res, t.gt_rows, t.a_uw);
   std::fclose(f);
 }
 
@@ -2651,10 +2666,12 @@ static int time_iteration(pcg_ctx *ctx, int iters, double *ms) {
 static int apply_tune(pcg_ctx *ctx, const pcg_ctx::Tune &t) {
   const bool same = ctx->tune.on == t.on && (!t.on || (ctx->tune.la == t.la && ctx->tune.lg == t.lg &&
                                                        ctx->tune.gm == t.gm));
-  const bool same_res = same && (!t.on || ctx->tune.res == t.res);
+  const bool same_rest = same && (!t.on || (ctx->tune.res == t.res && ctx->tune.gt_rows == t.gt_rows &&
+                                             ctx->tune.a_uw == t.a_uw));
   ctx->tune = t;
   if (!same) return relayout(ctx);
-  return same_res ? PCG_OK : single_sets(ctx);  // load policy only: new directory entries
+  // load policy or kernel knobs only: new directory entries and launch sets
+  return same_rest ? PCG_OK : single_sets(ctx);
 }
 
 int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
@@ -2689,6 +2706,8 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
   } else {
     // the automatic choice first (the default to beat)
     pcg_ctx::Tune a;
+    a.gt_rows = cfg_rows_per_lane(ctx->cfg);
+    a.a_uw = cfg_loads_in_flight(ctx->cfg);
     if ((rc = apply_tune(ctx, a))) return rc;
     if ((rc = time_iteration(ctx, iters, &t_auto))) return rc;
     ++ncand;
@@ -2736,7 +2755,7 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
     };
     for (int la : las)
       for (int lg : lgs) {
-        pcg_ctx::Tune t;
+        pcg_ctx::Tune t = a;  // the configured kernel knobs
         t.on = true;
         t.la = la;
         t.lg = lg;
@@ -2771,6 +2790,27 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
       t.res = r;
       if ((rc = consider(t))) return rc;
     }
+    // kernel knobs for the best of the above: rows per lane of the G^T-kernel
+    // (vector width of its accesses over sliced diagonals), then loads in
+    // flight per lane in the A-kernel
+    base = best;
+    if (!base.on) {
+      base.on = true;
+      base.la = ctx->cfg.layout;
+      base.lg = ctx->cfg.layout;
+      base.gm = gm0;
+    }
+    {
+      pcg_ctx::Tune t = base;
+      t.gt_rows = base.gt_rows == 2 ? 1 : 2;
+      if ((rc = consider(t))) return rc;
+    }
+    base = best.on ? best : base;
+    {
+      pcg_ctx::Tune t = base;
+      t.a_uw = base.a_uw == 8 ? 4 : 8;
+      if ((rc = consider(t))) return rc;
+    }
     if ((rc = apply_tune(ctx, best))) return rc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_store(key, best);
@@ -2789,6 +2829,8 @@ int pcg_autotune(pcg_ctx *ctx, int iters, pcg_tune_result *res) {
                  (ctx->single.dev.GT.idx16 ? 4 : 0);
     res->temporal = ctx->single.dev.A.temporal | (ctx->single.dev.G.temporal << 1) |
                     (ctx->single.dev.GT.temporal << 2);
+    res->rows_per_lane_gt = ctx->single.dev.GT.rpl;
+    res->loads_in_flight_a = ctx->set_main.L.uw_a;
   }
   return PCG_OK;
 }

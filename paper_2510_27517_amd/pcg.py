@@ -46,7 +46,8 @@ class Config(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("graph_iters", ctypes.c_int), ("grid_mult", ctypes.c_int),
         ("mem_budget_mb", ctypes.c_int), ("layout", ctypes.c_int), ("g_device", ctypes.c_int),
         ("wide_index", ctypes.c_int), ("autotune", ctypes.c_int), ("cache_mb", ctypes.c_int),
-        ("wg_max_n", ctypes.c_int), ("wg_max_n_batch", ctypes.c_int),
+        ("wg_max_n", ctypes.c_int), ("wg_max_n_batch", ctypes.c_int), ("rows_per_lane", ctypes.c_int),
+        ("loads_in_flight", ctypes.c_int),
         ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("alloc_user", ctypes.c_void_p),
     ]
 
@@ -90,7 +91,8 @@ class TuneResult(ctypes.Structure):
     _fields_ = [
         ("layout_a", ctypes.c_int), ("layout_g", ctypes.c_int), ("grid_mult", ctypes.c_int),
         ("candidates", ctypes.c_int), ("fmt_a", ctypes.c_int), ("fmt_g", ctypes.c_int), ("fmt_gt", ctypes.c_int),
-        ("idx16", ctypes.c_int), ("temporal", ctypes.c_int), ("ms_per_iter", ctypes.c_double),
+        ("idx16", ctypes.c_int), ("temporal", ctypes.c_int), ("rows_per_lane_gt", ctypes.c_int),
+        ("loads_in_flight_a", ctypes.c_int), ("ms_per_iter", ctypes.c_double),
         ("ms_per_iter_auto", ctypes.c_double),
     ]
 

@@ -138,6 +138,16 @@ def test_allocator_callbacks_come_in_pairs():
     assert e.value.status == pcg.EINVAL
 
 
+@pytest.mark.parametrize("kw", [dict(rows_per_lane=3), dict(rows_per_lane=-1), dict(loads_in_flight=6),
+                                dict(loads_in_flight=16)])
+def test_kernel_knobs_validated(kw):
+    """Knob values outside {0, 1, 2} rows per lane and {0, 4, 8} loads in
+    flight are refused before any device work."""
+    with pytest.raises(pcg.PCGError) as e:
+        pcg.Solver(pcg.default_config(**kw))
+    assert e.value.status == pcg.EINVAL
+
+
 def test_create_without_gpu_fails_cleanly():
     import torch
 

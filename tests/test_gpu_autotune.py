@@ -59,7 +59,8 @@ def test_autotune_search_cache_and_parity(gpu_lib, tmp_path):
         s.build_precond(pcg.G_FSAI)
         t2 = s.autotune(10)
         assert t2["candidates"] == 0
-        for k in ("layout_a", "layout_g", "grid_mult", "fmt_a", "fmt_g", "fmt_gt", "idx16", "temporal"):
+        for k in ("layout_a", "layout_g", "grid_mult", "fmt_a", "fmt_g", "fmt_gt", "idx16", "temporal",
+                  "rows_per_lane_gt", "loads_in_flight_a"):
             assert t2[k] == t[k], k
         got2 = s.solve(b, tol=1e-8, maxit=5000)
     assert np.array_equal(got2.x, got.x)
@@ -104,7 +105,7 @@ def test_autotune_keeps_forced_layout(gpu_lib):
         s.set_matrix(A)
         s.build_precond(pcg.G_FSAI)
         t = s.autotune(10)
-        assert t["fmt_a"] == 0 and t["fmt_g"] == 0 and t["fmt_gt"] == 0 and t["candidates"] == 11
+        assert t["fmt_a"] == 0 and t["fmt_g"] == 0 and t["fmt_gt"] == 0 and t["candidates"] == 13
         got = s.solve(b, tol=1e-8, maxit=5000)
         _parity(s, got, A, b, 1e-8)
 

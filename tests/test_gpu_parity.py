@@ -518,22 +518,26 @@ def _banded_spd(n, offsets, seed):
 @pytest.mark.parametrize("gm", [1, 4])
 @pytest.mark.parametrize("n", [2, 3, 5, 64, 65, 127, 129, 1000, 4097, 20001])
 def test_two_row_walk_sizes(gpu_lib, n, gm):
-    """The G^T-kernel takes two rows per lane over sliced diagonals: pairs of
-    slices per wave, an odd last row, an odd count of slices in a die's
-    range, operand columns clamped at both ends of the vector. Solves
-    of banded matrices of every size and parity (three-kernel path forced
-    for the tiny ones) equal the oracle's bit for bit, on two grid sizes."""
+    """The G^T-kernel takes two rows per lane over sliced diagonals (by
+    default; rows_per_lane = 1 takes one): pairs of slices per wave, an odd
+    last row, an odd count of slices in a die's range, operand columns
+    clamped at both ends of the vector. Solves of banded matrices of every
+    size and parity (the three-kernel path forced for the tiny ones) equal the
+    oracle's bit for bit on two grid sizes, with either knob setting (and 4
+    or 8 loads in flight in the A-kernel)."""
     pcg = gpu_lib
     A = _banded_spd(n, (1, 2, 7), n)
     b = inputs.rhs(n, 5)
     G = oracle.fsai_g(A)
     ref = oracle.pcg(A, G, b, tol=1e-10, maxit=400, delta_form=1)
-    say("two-row walk", n, gm, A.nnz)
-    with _solver(pcg, layout="sdia", grid_mult=gm, wg_max_n=0, wg_max_n_batch=0) as s:
-        s.set_matrix(A)
-        s.set_precond(G)
-        got = s.solve(b, tol=1e-10, maxit=400)
-    _check(got, ref)
+    for rpl, uw in ((2, 8), (1, 4)):
+        say("two-row walk", n, gm, rpl, uw, A.nnz)
+        with _solver(pcg, layout="sdia", grid_mult=gm, wg_max_n=-1, wg_max_n_batch=-1, rows_per_lane=rpl,
+                     loads_in_flight=uw) as s:
+            s.set_matrix(A)
+            s.set_precond(G)
+            got = s.solve(b, tol=1e-10, maxit=400)
+        _check(got, ref)
 
 
 @pytest.mark.parametrize("dim,N", [(3, 30), (2, 70)])
