@@ -366,15 +366,43 @@ def section_batched(pcg, inputs, count):
         t0 = time.perf_counter()
         res = s.solve_batch(systems, iters_per_step=10)
         wall = time.perf_counter() - t0
+        gs = s.batch_stats()
+    # the same batch with every G built beforehand (the host FSAI outside the
+    # clock): what remains on the host is layout, staging and scheduling
+    log("batched: G built beforehand")
+    pre = [dict(sd, G=inputs.CSR(*pcg.build_g_host(pcg.G_FSAI, sd["A"]))) for sd in systems]
+    with pcg.Solver(cfg) as s:
+        t0 = time.perf_counter()
+        rpre = s.solve_batch(pre, iters_per_step=10)
+        wall_pre = time.perf_counter() - t0
+        gs_pre = s.batch_stats()
+    gpu = {"iteration_steps": gs["steps"], "step_device_ms": round(gs["step_ms"], 2),
+           "step_bytes": gs["step_bytes"],
+           "aggregate_gbps_over_active_set": round(gs["step_bytes"] / (gs["step_ms"] * 1e-3) / 1e9, 1)
+           if gs["step_ms"] > 0 else None,
+           "one_workgroup_launches": gs["wg_launches"], "one_workgroup_device_ms": round(gs["wg_ms"], 2),
+           "one_workgroup_bytes": gs["wg_bytes"],
+           "gpu_only_solves_per_s": round(count / ((gs["step_ms"]) * 1e-3), 1) if gs["step_ms"] > 0 else None,
+           "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire")},
+           "g_prebuilt": {"wall_s": round(wall_pre, 3), "solves_per_s": round(count / wall_pre, 2),
+                          "ok": sum(1 for _, r in rpre if r["status"] == pcg.OK),
+                          "step_device_ms": round(gs_pre["step_ms"], 2),
+                          "bitwise_equal_to_host_fsai_run": bool(all(np.array_equal(a[0], c[0])
+                                                                     for a, c in zip(res, rpre)))},
+           "note": "device time of the scheduler's iteration steps (events around each step's launches on the "
+                   "library stream; refinement's FP64 steps, uploads and readbacks outside), bytes = per system "
+                   "iterations run x bytes_per_iter of its stored layouts; one-workgroup launches of small "
+                   "systems run on a second stream beside the steps. gpu_only_solves_per_s = systems / step "
+                   "device time"}
     st = [r["status"] for _, r in res]
     lat = [r["t_latency_ms"] for _, r in res]
     solve = [r["t_solve_ms"] for _, r in res]
-    # plain FP32 (no refinement; FP32 reaches 1e-6 here): small systems solved
-    # whole by one persistent workgroup each, and the same without
+    # plain FP64 (no refinement): small systems solved whole by one
+    # persistent workgroup each, and the same batch without
     plain = {}
     for tag, wgb in (("one_workgroup_small", 0), ("three_kernels_only", -1)):
-        cfgp = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="f32", wg_max_n_batch=wgb)
-        log(f"batched: plain FP32, {tag}")
+        cfgp = pcg.default_config(wg_max_n_batch=wgb)
+        log(f"batched: plain FP64, {tag}")
         with pcg.Solver(cfgp) as s:
             t0 = time.perf_counter()
             rp = s.solve_batch(systems, iters_per_step=10)
@@ -383,14 +411,14 @@ def section_batched(pcg, inputs, count):
                       "ok": sum(1 for _, r in rp if r["status"] == pcg.OK),
                       "latency_ms_p50": pct([r["t_latency_ms"] for _, r in rp], 50),
                       "latency_ms_p99": pct([r["t_latency_ms"] for _, r in rp], 99),
-                      "max_relres_true_fp32": max(r["relres_true"] for _, r in rp)}
+                      "max_relres_true_fp64": max(r["relres_true"] for _, r in rp)}
     plain["small_systems"] = int(sum(1 for sd in systems if sd["A"].n <= 16384))
     order = np.argsort([sd["A"].n for sd in systems])
     samples = {f"system{int(i)}": (systems[i]["A"], systems[i]["b"], {"x": res[i][0]})
                for i in order[np.linspace(0, count - 1, min(6, count)).astype(int)]}
     return {"workload": f"{count} systems: 2D side U[16,256] / 3D side U[8,64] lognormal sigma 0.5 Poisson, "
                         "FSAI G built on the host, A/vectors/G f32, FP64 refinement, tol 1e-6",
-            "fp32_plain": plain,
+            "fp64_plain": plain, "gpu": gpu,
             "systems": count, "rows_total": n_tot, "nnz_total": nnz_tot,
             "solves_per_s": round(count / wall, 2), "wall_s": round(wall, 3),
             "ok": st.count(pcg.OK), "statuses": sorted(set(st)),
@@ -468,6 +496,7 @@ def section_serving(pcg, inputs, count, iters_per_step):
         t0 = time.perf_counter()
         res = s.solve_batch(reqs, iters_per_step=iters_per_step)
         wall = time.perf_counter() - t0
+        gs = s.batch_stats()
     mu = count / wall
     ns = [r["A"].n for r in reqs]
     order = np.argsort(ns)
@@ -477,7 +506,14 @@ def section_serving(pcg, inputs, count, iters_per_step):
                        "mean degree ~8, weights U[0.1,10]; f32 A/vectors, bf16 FSAI G, FP64 refinement, tol 1e-6; "
                        "Poisson arrivals at 0.5/0.8/0.95 of the closed-loop rate",
            "requests": count, "closed_loop_solves_per_s": round(mu, 2),
-           "closed_loop_latency_ms_p99": pct([r["t_latency_ms"] for _, r in res], 99), "loads": {}}
+           "closed_loop_latency_ms_p99": pct([r["t_latency_ms"] for _, r in res], 99),
+           "closed_loop_gpu": {"step_device_ms": round(gs["step_ms"], 1), "wall_ms": round(wall * 1e3, 1),
+                               "busy_fraction_iteration_steps": round(gs["step_ms"] / (wall * 1e3), 3),
+                               "one_workgroup_device_ms": round(gs["wg_ms"], 1),
+                               "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire")},
+                               "aggregate_gbps_over_active_set": round(gs["step_bytes"] / (gs["step_ms"] * 1e-3) / 1e9,
+                                                                       1) if gs["step_ms"] > 0 else None},
+           "loads": {}}
     # open loop: Poisson arrivals (exponential gaps from the arrivals stream)
     gaps01 = -np.log(inputs.u01(7, inputs.STREAM_ARRIVALS, count))
     for f in (0.5, 0.8, 0.95):

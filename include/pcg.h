@@ -372,6 +372,32 @@ int pcg_solve_batch(pcg_ctx *ctx, int count, const pcg_system *sys, pcg_result *
  * the paper: part of the batching facility above. */
 int pcg_pool_info(pcg_ctx *ctx, size_t *capacity, size_t *in_use);
 
+/* Measurement of the batching facility (not in the paper). Device time and
+ * bytes of the scheduler's work since the context was created or the last
+ * reset: each step's iterations over the active set are timed by events on
+ * the context's stream around their launches (admission uploads and state
+ * readbacks fall outside), and their bytes are, per system, the iterations
+ * it ran in the step times its pcg_result.bytes_per_iter. One-workgroup
+ * launches of small systems (second stream, overlapping the steps) are timed
+ * from launch to completion, with each system's iterations times its bytes
+ * per iteration. step_bytes / step_ms is the aggregate bandwidth over the
+ * active set. reset != 0 zeroes the counters after reading them. Returns
+ * PCG_EINVAL for a NULL pointer. */
+typedef struct {
+  int64_t steps;       /* scheduler steps that ran iterations */
+  double step_ms;      /* their device time */
+  double step_bytes;   /* bytes their iterations moved (layouts as stored) */
+  int64_t wg_launches; /* one-workgroup launches */
+  double wg_ms;        /* their device time */
+  double wg_bytes;     /* bytes of their iterations */
+  /* host time (wall clock) of the scheduler's phases and of the workers */
+  double host_prep_ms;   /* worker threads preparing systems (G, layouts, images), summed over threads */
+  double host_admit_ms;  /* scheduler: admission (pool blocks, uploads, first kernels) */
+  double host_step_ms;   /* scheduler: launching the steps' iterations and reading the states back */
+  double host_retire_ms; /* scheduler: finishing stopped systems (final residual, solution copies, refinement steps) */
+} pcg_batch_stats;
+int pcg_batch_stats_get(pcg_ctx *ctx, pcg_batch_stats *out, int reset);
+
 /* Host-only helpers (no GPU needed). */
 
 /* Checks a CSR matrix against the conventions above; require_diag = 1 also

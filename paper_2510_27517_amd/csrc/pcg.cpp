@@ -18,9 +18,11 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <optional>
 #include <string>
 #include <thread>
 
+#include <sched.h>
 #include <sys/resource.h>
 #include <sys/syscall.h>
 #include <unistd.h>
@@ -48,6 +50,9 @@ constexpr int kWgMaxN = 512;
 // (128^3 FP64: 94 us per iteration at 4, 102 at 8, 139 at 16)
 constexpr int kGridMult = 4;
 constexpr int kWgMaxNBatch = 16384;
+// page-locked host memory per context for the device images of systems
+// waiting for admission (larger or further images go to ordinary memory)
+constexpr size_t kStagingBytes = size_t(256) << 20;
 constexpr int kSlotMain = 0, kSlot64 = 1, kSlotX = 2, kFirstBatchSlot = 3;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -83,50 +88,34 @@ struct DevAlloc {
   }
 };
 
-// ---------------------------------------------------------------- device pool
+// ------------------------------------------------------------- range allocator
 
-// First-fit sub-allocator over one device allocation (the admission budget
-// of the batch/serving scheduler). Free blocks coalesce with neighbours.
-class DevPool {
+// First-fit allocation of byte ranges (offsets) of one region; free ranges
+// coalesce with their neighbours. The region's memory belongs to the user.
+class FirstFit {
  public:
-  DevAlloc da;
-  ~DevPool() { reset(); }
-  int init(size_t cap) {
-    reset();
-    cap = align_up(cap);
-    if (da.get(&base_, cap) != hipSuccess) {
-      (void)hipGetLastError();
-      base_ = nullptr;
-      return PCG_ENOMEM;
-    }
-    cap_ = cap;
-    free_[0] = cap;
-    return PCG_OK;
-  }
-  void reset() {
-    if (base_) da.put(base_);
-    base_ = nullptr;
-    cap_ = used_bytes_ = 0;
+  void reset(size_t cap) {
     free_.clear();
     used_.clear();
+    cap_ = cap;
+    used_bytes_ = 0;
+    if (cap) free_[0] = cap;
   }
-  bool ready() const { return base_ != nullptr; }
-  void *alloc(size_t bytes) {
+  bool alloc(size_t bytes, size_t *off) {
     bytes = align_up(std::max<size_t>(bytes, 1));
     for (auto it = free_.begin(); it != free_.end(); ++it) {
       if (it->second < bytes) continue;
-      const size_t off = it->first, sz = it->second;
+      const size_t o = it->first, sz = it->second;
       free_.erase(it);
-      if (sz > bytes) free_[off + bytes] = sz - bytes;
-      used_[off] = bytes;
+      if (sz > bytes) free_[o + bytes] = sz - bytes;
+      used_[o] = bytes;
       used_bytes_ += bytes;
-      return (uint8_t *)base_ + off;
+      *off = o;
+      return true;
     }
-    return nullptr;
+    return false;
   }
-  void release(void *p) {
-    if (!p || !base_) return;
-    const size_t off = (size_t)((uint8_t *)p - (uint8_t *)base_);
+  void release(size_t off) {
     auto u = used_.find(off);
     if (u == used_.end()) return;
     size_t start = off, sz = u->second;
@@ -151,9 +140,90 @@ class DevPool {
   size_t in_use() const { return used_bytes_; }
 
  private:
-  void *base_ = nullptr;
   size_t cap_ = 0, used_bytes_ = 0;
   std::map<size_t, size_t> free_, used_;
+};
+
+// ---------------------------------------------------------------- device pool
+
+// First-fit sub-allocator over one device allocation (the admission budget
+// of the batch/serving scheduler).
+class DevPool {
+ public:
+  DevAlloc da;
+  ~DevPool() { reset(); }
+  int init(size_t cap) {
+    reset();
+    cap = align_up(cap);
+    if (da.get(&base_, cap) != hipSuccess) {
+      (void)hipGetLastError();
+      base_ = nullptr;
+      return PCG_ENOMEM;
+    }
+    ff_.reset(cap);
+    return PCG_OK;
+  }
+  void reset() {
+    if (base_) da.put(base_);
+    base_ = nullptr;
+    ff_.reset(0);
+  }
+  bool ready() const { return base_ != nullptr; }
+  void *alloc(size_t bytes) {
+    size_t off;
+    return base_ && ff_.alloc(bytes, &off) ? (uint8_t *)base_ + off : nullptr;
+  }
+  void release(void *p) {
+    if (p && base_) ff_.release((size_t)((uint8_t *)p - (uint8_t *)base_));
+  }
+  size_t capacity() const { return ff_.capacity(); }
+  size_t in_use() const { return ff_.in_use(); }
+
+ private:
+  void *base_ = nullptr;
+  FirstFit ff_;
+};
+
+// ------------------------------------------------------------- pinned staging
+
+// Page-locked host memory in which the worker threads lay out each admitted
+// system's device image (matrices and vectors at their offsets in the pool
+// block), so that admission uploads a system with one DMA copy per block
+// instead of one pageable copy per array. Thread-safe; when it is full the
+// image goes to ordinary memory (still one copy per block).
+class PinnedArena {
+ public:
+  ~PinnedArena() {
+    if (base_) (void)hipHostFree(base_);
+  }
+  // allocate the region once (false: no pinned memory, images go to the heap)
+  bool init(size_t cap) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (base_ || tried_) return base_ != nullptr;
+    tried_ = true;
+    if (hipHostMalloc(&base_, cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      base_ = nullptr;
+      return false;
+    }
+    ff_.reset(cap);
+    return true;
+  }
+  void *alloc(size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    size_t off;
+    return base_ && ff_.alloc(bytes, &off) ? (uint8_t *)base_ + off : nullptr;
+  }
+  void release(void *p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (p && base_) ff_.release((size_t)((uint8_t *)p - (uint8_t *)base_));
+  }
+
+ private:
+  std::mutex mu_;
+  void *base_ = nullptr;
+  bool tried_ = false;
+  FirstFit ff_;
 };
 
 // ------------------------------------------------------- host staging of a system
@@ -532,8 +602,26 @@ hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
   return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
 }
 
+// Where placement sends the host data of a system: straight to the device
+// on a stream (Device); into a host image of the block, which the carver
+// then walks in place of the device block (Image: the carved pointers are
+// image addresses); or nowhere (Bind: the carved pointers are the device
+// block's, whose contents arrive as one copy of the image).
+struct Copier {
+  enum Mode { Device, Image, Bind } mode = Device;
+  hipStream_t s = nullptr;
+  hipError_t put(void *dst, const void *src, size_t bytes) const {
+    if (!bytes || mode == Bind) return hipSuccess;
+    if (mode == Image) {
+      std::memcpy(dst, src, bytes);
+      return hipSuccess;
+    }
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  }
+};
+
 // Carve one matrix out of `c` and upload it into M.
-hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, hipStream_t s) {
+hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, const Copier &cp) {
   hipError_t e = hipSuccess;
   auto chain = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
@@ -542,13 +630,13 @@ hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, hipStream_t s) {
   int32_t *dci = (int32_t *)c.take(H.idx_bytes());
   void *dval = c.take(H.val_bytes());
   int32_t *dblk = (int32_t *)c.take(4 * H.blk.size());
-  if (drp) chain(h2d(drp, H.rp.data(), 4 * H.rp.size(), s));
+  if (drp) chain(cp.put(drp, H.rp.data(), 4 * H.rp.size()));
   if (H.idx16)
-    chain(h2d(dci, H.ci16.data(), 2 * H.ci16.size(), s));
+    chain(cp.put(dci, H.ci16.data(), 2 * H.ci16.size()));
   else
-    chain(h2d(dci, H.ci.data(), 4 * H.ci.size(), s));
-  if (!H.val.empty()) chain(h2d(dval, H.val.data(), H.val.size(), s));
-  chain(h2d(dblk, H.blk.data(), 4 * H.blk.size(), s));
+    chain(cp.put(dci, H.ci.data(), 4 * H.ci.size()));
+  if (!H.val.empty()) chain(cp.put(dval, H.val.data(), H.val.size()));
+  chain(cp.put(dblk, H.blk.data(), 4 * H.blk.size()));
   M.rp = drp;
   M.ci = dci;
   M.val = dval;
@@ -566,12 +654,12 @@ hipError_t put_mat(Carver &c, const HostMat &H, DevCSR &M, hipStream_t s) {
 
 // Carve the A part into `block` and upload it (asynchronously: P must live
 // until the stream has passed the copies).
-hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
+hipError_t place_a(const APart &P, void *block, Sys &S, const Copier &cp) {
   Carver c{(uint8_t *)block};
   const int32_t n = P.n;
   const size_t vb = pcgk::dtype_size(P.vdt) * (size_t)n;
   DevCSR &A = S.dev.A;
-  hipError_t e = put_mat(c, P.A, A, s);
+  hipError_t e = put_mat(c, P.A, A, cp);
   auto chain = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
@@ -593,13 +681,13 @@ hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
     D.A.dtype = pcgk::F64;
     if (P.A.fmt != pcgk::FMT_CSR) {  // same slices and columns, FP64 values
       void *v64 = c.take(P.sliced64.size());
-      chain(h2d(v64, P.sliced64.data(), P.sliced64.size(), s));
+      chain(cp.put(v64, P.sliced64.data(), P.sliced64.size()));
       D.A.val = v64;
     } else {  // same CSR pattern, FP64 values, row blocks for FP64 products
       void *v64 = c.take(8 * (size_t)std::max<int64_t>(P.nnz, 1));
       int32_t *b64k = (int32_t *)c.take(4 * P.blk64.size());
-      chain(h2d(v64, P.val64, 8 * (size_t)P.nnz, s));
-      chain(h2d(b64k, P.blk64.data(), 4 * P.blk64.size(), s));
+      chain(cp.put(v64, P.val64, 8 * (size_t)P.nnz));
+      chain(cp.put(b64k, P.blk64.data(), 4 * P.blk64.size()));
       D.A.val = v64;
       D.A.blk = b64k;
     }
@@ -622,10 +710,10 @@ hipError_t place_a(const APart &P, void *block, Sys &S, hipStream_t s) {
   return e;
 }
 
-hipError_t place_g(const GPart &P, void *block, Sys &S, hipStream_t s) {
+hipError_t place_g(const GPart &P, void *block, Sys &S, const Copier &cp) {
   Carver c{(uint8_t *)block};
-  hipError_t e = put_mat(c, P.G, S.dev.G, s);
-  hipError_t e2 = put_mat(c, P.GT, S.dev.GT, s);
+  hipError_t e = put_mat(c, P.G, S.dev.G, cp);
+  hipError_t e2 = put_mat(c, P.GT, S.dev.GT, cp);
   if (e == hipSuccess) e = e2;
   S.dev.prt = (double *)c.take(16 * pcgk::kAccWords * (size_t)P.GT.grid);
   S.nnz_g = P.nnz;
@@ -664,6 +752,11 @@ struct Req {
   bool dev_fsai = false;
   std::vector<int32_t> fs_dpos, fs_lrp;
   int32_t fs_mmax = 0;
+  // device images of the A and G blocks laid out on the host (pinned when the
+  // context's arena has room, else in heap); admission copies each in one go
+  uint8_t *img_a = nullptr, *img_g = nullptr;
+  bool img_pinned = false;
+  std::vector<uint8_t> img_heap;
   size_t bytes = 0;
   int prep_rc = PCG_OK;
   ReqState st = RQ_PREP;
@@ -729,6 +822,7 @@ struct pcg_ctx {
 
   // batching / serving
   DevPool pool;
+  PinnedArena staging;  // host images of admitted systems (see build_images)
   std::mutex mu;
   std::condition_variable cv;
   std::deque<std::shared_ptr<Req>> prep_q;   // awaiting host preparation
@@ -745,8 +839,11 @@ struct pcg_ctx {
   struct WgGroup {
     std::vector<std::shared_ptr<Req>> reqs;
     HostSet set;
-    hipEvent_t done = nullptr;
+    hipEvent_t start = nullptr, done = nullptr;
   };
+  // device-time accounting of the batching facility (pcg_batch_stats_get)
+  hipEvent_t step_ev[2] = {nullptr, nullptr};
+  pcg_batch_stats stats{};
   std::vector<WgGroup> wg_groups;
   hipStream_t side = nullptr;
   int wg_inflight = 0;
@@ -1410,7 +1507,61 @@ bool prep_fsai_pattern(const pcg_config &cfg, int cus, Req &R) {
   return true;
 }
 
-void prep_request(const pcg_config &cfg, int cus, Req &R) {
+void prep_parts(const pcg_config &cfg, int cus, Req &R);
+
+// Lay out the device images of the request's two pool blocks on the host:
+// matrices, and the right-hand side and starting guess in the vector type
+// (FP32 by round-to-nearest, as the device conversion rounds), or their FP64
+// view under refinement. The image holds what the placement would copy, at
+// the same offsets; the rest of the block (work vectors, partial sums) is
+// left as it comes.
+void build_images(const pcg_config &cfg, PinnedArena *arena, Req &R) {
+  const size_t na = align_up(R.ap.bytes), ng = align_up(R.gp.bytes);
+  uint8_t *img = arena ? (uint8_t *)arena->alloc(na + ng) : nullptr;
+  R.img_pinned = img != nullptr;
+  if (!img) {
+    R.img_heap.resize(na + ng);
+    img = R.img_heap.data();
+  }
+  R.img_a = img;
+  R.img_g = img + na;
+  Sys tmp;
+  (void)place_a(R.ap, R.img_a, tmp, Copier{Copier::Image});
+  (void)place_g(R.gp, R.img_g, tmp, Copier{Copier::Image});
+  const int32_t n = R.n;
+  auto put_vec = [&](void *dst, const std::vector<double> &v, int dt) {
+    if (dt == pcgk::F64) {
+      if (v.empty())
+        std::memset(dst, 0, 8 * (size_t)n);
+      else
+        std::memcpy(dst, v.data(), 8 * (size_t)n);
+    } else {
+      float *f = (float *)dst;
+      for (int32_t i = 0; i < n; ++i) f[i] = v.empty() ? 0.0f : (float)v[i];
+    }
+  };
+  if (cfg.refine) {
+    put_vec(tmp.dev64.b, R.b, pcgk::F64);
+    put_vec(tmp.dev64.x, R.x0, pcgk::F64);
+  } else {
+    put_vec(tmp.dev.b, R.b, cfg.vec_dtype);
+    put_vec(tmp.dev.x, R.x0, cfg.vec_dtype);
+  }
+}
+
+void release_images(PinnedArena *arena, Req &R) {
+  if (R.img_pinned && arena) arena->release(R.img_a);
+  std::vector<uint8_t>().swap(R.img_heap);
+  R.img_a = R.img_g = nullptr;
+  R.img_pinned = false;
+}
+
+void prep_request(const pcg_config &cfg, int cus, PinnedArena *arena, Req &R) {
+  prep_parts(cfg, cus, R);
+  if (R.prep_rc == PCG_OK) build_images(cfg, arena, R);
+}
+
+void prep_parts(const pcg_config &cfg, int cus, Req &R) {
   R.ap = APart{};
   prep_a(cfg, cus, R.n, R.a_rp.data(), R.a_ci.data(), R.a_val.data(), false, R.ap);
   if (!R.g_given && R.g_kind == PCG_G_FSAI && cfg.g_device && cfg.g_dtype != PCG_F16 &&
@@ -1452,9 +1603,12 @@ void worker_main(pcg_ctx *ctx) {
       ctx->prep_q.pop_front();
       ++ctx->preparing;
     }
-    prep_request(ctx->cfg, ctx->cus, *R);
+    const double t0 = now_ms();
+    prep_request(ctx->cfg, ctx->cus, &ctx->staging, *R);
+    const double t1 = now_ms();
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->stats.host_prep_ms += t1 - t0;
       R->st = RQ_READY;
       ctx->ready_q.push_back(R);
       --ctx->preparing;
@@ -1478,7 +1632,12 @@ int ensure_pool(pcg_ctx *ctx) {
 
 void start_workers(pcg_ctx *ctx) {
   if (!ctx->workers.empty()) return;
-  unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency() / 2));
+  // the CPUs this process may run on, less two (the scheduler and the
+  // caller's thread), at most 32
+  unsigned ncpu = std::max(1u, std::thread::hardware_concurrency());
+  cpu_set_t cs;
+  if (sched_getaffinity(0, sizeof cs, &cs) == 0) ncpu = (unsigned)std::max(1, CPU_COUNT(&cs));
+  const unsigned nt = std::max(1u, std::min(32u, ncpu > 2 ? ncpu - 2 : 1u));
   for (unsigned i = 0; i < nt; ++i) ctx->workers.emplace_back(worker_main, ctx);
 }
 
@@ -1533,6 +1692,7 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
         ctx->pool.release(bA);
         if (ctx->active.empty() && cand.empty() && ctx->pool.in_use() == 0) {
           ctx->ready_q.pop_front();  // larger than the whole pool: refuse
+          release_images(&ctx->staging, *R);
           State z{};
           R->t_admit = now_ms();
           finish_request(ctx, *R, PCG_ENOMEM, z, 0);
@@ -1558,6 +1718,7 @@ int admit(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &admitted) {
   const int rc = place_admitted(ctx, cand, temps);
   if (rc) (void)hipStreamSynchronize(ctx->stream);  // on success place_admitted has synchronized
   for (void *t : temps) ctx->da.put(t);
+  for (auto &R : cand) release_images(&ctx->staging, *R);  // the stream has passed the copies
   if (rc) {  // none of them starts: give back their storage and finish their tickets with the error
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto &R : cand) {
@@ -1609,8 +1770,12 @@ int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::v
   };
   for (size_t i = 0; i < cand.size(); ++i) {
     Req &R = *cand[i];
-    HIPCHK(place_a(R.ap, R.sys.blkA, R.sys, s));
-    HIPCHK(place_g(R.gp, R.sys.blkG, R.sys, s));
+    // the blocks' host images (matrices, b and x0, see build_images): the
+    // pointers, then one copy per block
+    HIPCHK(place_a(R.ap, R.sys.blkA, R.sys, Copier{Copier::Bind}));
+    HIPCHK(place_g(R.gp, R.sys.blkG, R.sys, Copier{Copier::Bind}));
+    HIPCHK(h2d(R.sys.blkA, R.img_a, R.ap.bytes, s));
+    HIPCHK(h2d(R.sys.blkG, R.img_g, R.gp.bytes, s));
     if (R.dev_fsai) {  // G_L's rows on the device, written into both layouts
       const int32_t n = R.n;
       const int64_t nnz = (int64_t)R.a_ci.size(), nl = R.fs_lrp[n];
@@ -1659,11 +1824,6 @@ int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::v
       V.s = R.sys.dev.x;
       V.t = R.sys.dev.b;
       ctx->dir[R.slot64] = V;
-      HIPCHK(h2d(V.b, R.b.data(), 8 * (size_t)R.n, s));
-      if (R.x0.empty())
-        HIPCHK(pcgk::launch_fill(pcgk::F64, V.x, R.n, 0.0, s));
-      else
-        HIPCHK(h2d(V.x, R.x0.data(), 8 * (size_t)R.n, s));
       State o{};
       o.tol = R.tol;
       inits[2 * i] = inits[2 * i + 1] = o;
@@ -1679,26 +1839,6 @@ int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::v
       wg_slots.push_back(R.slot);
     } else {
       slots.push_back(R.slot);
-    }
-    // b and x0 (zeros when not given). FP64 vectors load directly; FP32
-    // vectors stage FP64 through r0 and r1, which are adjacent and together
-    // hold n doubles, then convert.
-    if (ctx->ty.vec == pcgk::F64) {
-      HIPCHK(h2d(R.sys.dev.b, R.b.data(), 8 * (size_t)R.n, s));
-      if (R.x0.empty())
-        HIPCHK(pcgk::launch_fill(pcgk::F64, R.sys.dev.x, R.n, 0.0, s));
-      else
-        HIPCHK(h2d(R.sys.dev.x, R.x0.data(), 8 * (size_t)R.n, s));
-    } else {
-      double *stage = (double *)R.sys.dev.r0;
-      HIPCHK(h2d(stage, R.b.data(), 8 * (size_t)R.n, s));
-      HIPCHK(pcgk::launch_convert(pcgk::F64, stage, ctx->ty.vec, R.sys.dev.b, R.n, 1.0, s));
-      if (R.x0.empty()) {
-        HIPCHK(pcgk::launch_fill(ctx->ty.vec, R.sys.dev.x, R.n, 0.0, s));
-      } else {
-        HIPCHK(h2d(stage, R.x0.data(), 8 * (size_t)R.n, s));
-        HIPCHK(pcgk::launch_convert(pcgk::F64, stage, ctx->ty.vec, R.sys.dev.x, R.n, 1.0, s));
-      }
     }
     HIPCHK(h2d(ctx->d_dir + R.slot, &ctx->dir[R.slot], sizeof(SysDev), s));
     HIPCHK(h2d(ctx->d_states + 2 * R.slot, &inits[2 * i], 2 * sizeof(State), s));
@@ -1720,29 +1860,78 @@ int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::v
   return PCG_OK;
 }
 
-// Copy x of a finished system to the caller (host FP64) and free its storage.
-int retire(pcg_ctx *ctx, Req &R) {
-  if (R.x_out && R.slot64 >= 0) {
-    HIPCHK(hipMemcpy(R.x_out, R.sys.dev64.x, 8 * (size_t)R.n, hipMemcpyDeviceToHost));
-  } else if (R.x_out) {
-    if (ctx->ty.vec == pcgk::F64) {
-      HIPCHK(hipMemcpy(R.x_out, R.sys.dev.x, 8 * (size_t)R.n, hipMemcpyDeviceToHost));
-    } else {
-      std::vector<float> tmp(R.n);
-      HIPCHK(hipMemcpy(tmp.data(), R.sys.dev.x, 4 * (size_t)R.n, hipMemcpyDeviceToHost));
-      for (int32_t i = 0; i < R.n; ++i) R.x_out[i] = (double)tmp[i];
+void finish_refined(pcg_ctx *ctx, Req &R, int status);
+
+// A stopped system waiting for its solution to reach the caller.
+struct Retiring {
+  std::shared_ptr<Req> R;
+  int status;
+  State f;       // its final state (single-level solves)
+  bool refined;  // finish with the refinement totals
+  int restarts;
+};
+
+// Copy the solutions of the stopped systems to their callers (host FP64):
+// asynchronous copies into pinned staging, one wait for all of them, then
+// on the host into the callers' arrays; free their storage and complete
+// their tickets. Clears `list`.
+int retire_all(pcg_ctx *ctx, std::vector<Retiring> &list) {
+  if (list.empty()) return PCG_OK;
+  hipStream_t s = ctx->stream;
+  std::vector<void *> buf(list.size(), nullptr);
+  std::vector<bool> pinned(list.size(), false);
+  std::vector<std::vector<uint8_t>> heap(list.size());
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < list.size() && e == hipSuccess; ++i) {
+    Req &R = *list[i].R;
+    if (!R.x_out) continue;
+    const bool f64 = R.slot64 >= 0 || ctx->ty.vec == pcgk::F64;
+    const void *src = R.slot64 >= 0 ? R.sys.dev64.x : R.sys.dev.x;
+    const size_t bytes = (f64 ? 8 : 4) * (size_t)R.n;
+    buf[i] = ctx->staging.alloc(bytes);
+    pinned[i] = buf[i] != nullptr;
+    if (!buf[i]) {
+      heap[i].resize(bytes);
+      buf[i] = heap[i].data();
     }
+    e = hipMemcpyAsync(buf[i], src, bytes, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (size_t i = 0; i < list.size(); ++i) {
+    Req &R = *list[i].R;
+    if (e == hipSuccess && R.x_out) {
+      if (R.slot64 >= 0 || ctx->ty.vec == pcgk::F64) {
+        std::memcpy(R.x_out, buf[i], 8 * (size_t)R.n);
+      } else {
+        const float *f = (const float *)buf[i];
+        for (int32_t k = 0; k < R.n; ++k) R.x_out[k] = (double)f[k];
+      }
+    }
+    if (pinned[i]) ctx->staging.release(buf[i]);
+  }
+  if (e != hipSuccess) {
+    ctx->err = std::string("retire: ") + hipGetErrorString(e);
+    list.clear();
+    return PCG_EDEVICE;
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
-  free_sys(ctx, R.sys);
-  ctx->dir[R.slot] = SysDev{};
-  ctx->free_slots.push_back(R.slot);
-  R.slot = -1;
-  if (R.slot64 >= 0) {
-    ctx->dir[R.slot64] = SysDev{};
-    ctx->free_slots.push_back(R.slot64);
-    R.slot64 = -1;
+  for (auto &T : list) {
+    Req &R = *T.R;
+    free_sys(ctx, R.sys);
+    ctx->dir[R.slot] = SysDev{};
+    ctx->free_slots.push_back(R.slot);
+    R.slot = -1;
+    if (R.slot64 >= 0) {
+      ctx->dir[R.slot64] = SysDev{};
+      ctx->free_slots.push_back(R.slot64);
+      R.slot64 = -1;
+    }
+    if (T.refined)
+      finish_refined(ctx, R, T.status);
+    else
+      finish_request(ctx, R, T.status, T.f, T.restarts);
   }
+  list.clear();
   return PCG_OK;
 }
 
@@ -1769,13 +1958,13 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
   std::vector<int> slots, slots64;
   std::vector<std::shared_ptr<Req>> go;
   std::vector<double> itol;
+  std::vector<Retiring> retiring;
   for (auto &R : list) {
     const State h = ctx->h_states[2 * R->slot64];
     int status = 1;  // continue
     double next_tol = 0.0;
     if (h.bb == 0.0) {
       HIPCHK(pcgk::launch_fill(pcgk::F64, R->sys.dev64.x, R->n, 0.0, s));
-      HIPCHK(hipStreamSynchronize(s));
       R->relres64 = 0.0;
       status = PCG_OK;
     } else {
@@ -1792,10 +1981,7 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
       next_tol = inner_tolerance(ctx->cfg.inner_tol, R->tol, nb, rn, R->outer);
     }
     if (status != 1) {
-      int rc = retire(ctx, *R);
-      if (rc) return rc;
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      finish_refined(ctx, *R, status);
+      retiring.push_back(Retiring{R, status, State{}, true, R->restarts});
       continue;
     }
     go.push_back(R);
@@ -1803,6 +1989,8 @@ int outer_decide(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &list, std::vec
     slots.push_back(R->slot);
     slots64.push_back(R->slot64);
   }
+  int rc0 = retire_all(ctx, retiring);
+  if (rc0) return rc0;
   if (go.empty()) return PCG_OK;
   HostSet &h64 = ctx->set_tmp64, &hin = ctx->set_tmp;
   int rc = build_set(ctx, h64, slots64);
@@ -1866,7 +2054,9 @@ int launch_wg_group(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &reqs) {
   int rc = build_set(ctx, g.set, slots);
   if (rc) return rc;
   g.reqs = reqs;
-  HIPCHK(hipEventCreateWithFlags(&g.done, hipEventDisableTiming));
+  HIPCHK(hipEventCreate(&g.start));
+  HIPCHK(hipEventCreate(&g.done));
+  HIPCHK(hipEventRecord(g.start, ctx->side));
   HIPCHK(pcgk::launch_solve_wg(ctx->ty, g.set.L, ctx->cfg.eps != 0.0, ctx->side));
   HIPCHK(hipEventRecord(g.done, ctx->side));
   ctx->wg_inflight += (int)reqs.size();
@@ -1884,19 +2074,31 @@ int collect_wg_groups(pcg_ctx *ctx) {
       continue;
     }
     HIPCHK(q);
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, g.start, g.done));
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->stats.wg_launches += 1;
+      ctx->stats.wg_ms += ms;
+    }
+    std::vector<Retiring> retiring;
     for (auto &R : g.reqs) {
       State f;
       HIPCHK(hipMemcpy(&f, ctx->d_states + 2 * R->slot, sizeof(State), hipMemcpyDeviceToHost));
+      {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->stats.wg_bytes += (double)f.iter * R->res.bytes_per_iter;
+      }
       const int status = (f.status == pcgk::ST_CONV_REC || f.status == pcgk::ST_ZERO_B) ? PCG_OK
                          : f.status == pcgk::ST_MAXIT                                   ? PCG_NOT_CONVERGED
                                                                                         : PCG_EBREAKDOWN;
-      int rc = retire(ctx, *R);
-      if (rc) return rc;
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      finish_request(ctx, *R, status, f, f.restarts);
+      retiring.push_back(Retiring{R, status, f, false, f.restarts});
     }
+    int rc = retire_all(ctx, retiring);
+    if (rc) return rc;
     ctx->wg_inflight -= (int)g.reqs.size();
     free_set(ctx, g.set);
+    (void)hipEventDestroy(g.start);
     (void)hipEventDestroy(g.done);
     ctx->wg_groups.erase(ctx->wg_groups.begin() + (long)k);
   }
@@ -1904,11 +2106,28 @@ int collect_wg_groups(pcg_ctx *ctx) {
 }
 
 // One scheduler step: admit, `iters` iterations over the active set, retire.
+// Adds the wall time since construction to one host-time counter of the
+// batch statistics.
+struct PhaseTimer {
+  pcg_ctx *ctx;
+  double pcg_batch_stats::*field;
+  double t0;
+  PhaseTimer(pcg_ctx *c, double pcg_batch_stats::*f) : ctx(c), field(f), t0(now_ms()) {}
+  ~PhaseTimer() {
+    const double t = now_ms() - t0;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stats.*field += t;
+  }
+};
+
 int progress(pcg_ctx *ctx, int iters) {
   int rc;
   if ((rc = ensure_pool(ctx))) return rc;
   std::vector<std::shared_ptr<Req>> admitted;
-  if ((rc = admit(ctx, admitted))) return rc;
+  {
+    PhaseTimer pt(ctx, &pcg_batch_stats::host_admit_ms);
+    if ((rc = admit(ctx, admitted))) return rc;
+  }
   if (!admitted.empty() && ctx->cfg.refine) {
     int mx = 0;
     for (auto &R : admitted) mx = std::max(mx, R->slot64);
@@ -1931,6 +2150,8 @@ int progress(pcg_ctx *ctx, int iters) {
   }
   if ((rc = collect_wg_groups(ctx))) return rc;
   if (ctx->active.empty()) return PCG_OK;
+  std::optional<PhaseTimer> phase;
+  phase.emplace(ctx, &pcg_batch_stats::host_step_ms);
   hipStream_t s = ctx->stream;
   const bool changed = ctx->active_dirty;
   if (ctx->active_dirty) {
@@ -1956,6 +2177,11 @@ int progress(pcg_ctx *ctx, int iters) {
     }
     return false;
   };
+  if (!ctx->step_ev[0]) {
+    HIPCHK(hipEventCreate(&ctx->step_ev[0]));
+    HIPCHK(hipEventCreate(&ctx->step_ev[1]));
+  }
+  HIPCHK(hipEventRecord(ctx->step_ev[0], s));
   if (ctx->cfg.graph_iters > 0 && !changed) {
     // one graph per active set, captured once the set has stayed the same
     // for a step (a set that changes every step is cheaper to launch plainly
@@ -1994,16 +2220,30 @@ int progress(pcg_ctx *ctx, int iters) {
       HIPCHK(pcgk::launch_iter_G(ctx->ty, L, has_eps, 3, s));
     }
   }
+  HIPCHK(hipEventRecord(ctx->step_ev[1], s));
   int maxslot = 0;
   for (auto &R : ctx->active) maxslot = std::max(maxslot, R->slot);
   const size_t sb = 2 * sizeof(State) * (size_t)(maxslot + 1);
   HIPCHK(hipMemcpyAsync(ctx->h_states, ctx->d_states, sb, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->step_ev[0], ctx->step_ev[1]));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stats.steps += 1;
+    ctx->stats.step_ms += ms;
+    for (auto &R : ctx->active) {  // iterations each system ran in this step (an inner solve restarts at 0)
+      const int it0 = R->iter_host, it1 = ctx->h_states[2 * R->slot].iter;
+      ctx->stats.step_bytes += (double)(it1 >= it0 ? it1 - it0 : it1) * R->res.bytes_per_iter;
+    }
+  }
   for (auto &R : ctx->active) R->iter_host = ctx->h_states[2 * R->slot].iter;
   std::vector<int> done_slots;
   for (auto &R : ctx->active)
     if (ctx->h_states[2 * R->slot].done) done_slots.push_back(R->slot);
   if (done_slots.empty()) return PCG_OK;
+  phase.reset();
+  phase.emplace(ctx, &pcg_batch_stats::host_retire_ms);
   // finish the stopped systems: any pending x update, true residual
   HostSet &hs = ctx->set_done;
   if ((rc = build_set(ctx, hs, done_slots))) return rc;
@@ -2013,6 +2253,7 @@ int progress(pcg_ctx *ctx, int iters) {
   HIPCHK(hipStreamSynchronize(s));
   std::vector<int> restart_slots;
   std::vector<std::shared_ptr<Req>> keep, outer_list;
+  std::vector<Retiring> retiring;
   for (auto &R : ctx->active) {
     const State f = ctx->h_states[2 * R->slot];
     if (!f.done) {
@@ -2030,9 +2271,7 @@ int progress(pcg_ctx *ctx, int iters) {
       R->inner_total += f.iter;
       R->last_rec = f.bb > 0 ? std::sqrt(f.rr / f.bb) : 0.0;
       if (f.status == pcgk::ST_BREAK_GAMMA || f.status == pcgk::ST_BREAK_DELTA) {
-        if ((rc = retire(ctx, *R))) return rc;
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        finish_refined(ctx, *R, PCG_EBREAKDOWN);
+        retiring.push_back(Retiring{R, PCG_EBREAKDOWN, f, true, R->restarts});
         continue;
       }
       outer_list.push_back(R);
@@ -2041,18 +2280,16 @@ int progress(pcg_ctx *ctx, int iters) {
     if (f.status == pcgk::ST_CONV_REC) {
       status = PCG_OK;
     } else if (f.status == pcgk::ST_ZERO_B) {
-      HIPCHK(pcgk::launch_fill(ctx->ty.vec, R->sys.dev.x, R->n, 0.0, s));
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(pcgk::launch_fill(ctx->ty.vec, R->sys.dev.x, R->n, 0.0, s));  // before its copy, in stream order
       status = PCG_OK;
     } else if (f.status == pcgk::ST_MAXIT) {
       status = PCG_NOT_CONVERGED;
     } else {
       status = PCG_EBREAKDOWN;
     }
-    if ((rc = retire(ctx, *R))) return rc;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    finish_request(ctx, *R, status, f, R->restarts);
+    retiring.push_back(Retiring{R, status, f, false, R->restarts});
   }
+  if ((rc = retire_all(ctx, retiring))) return rc;
   if (!restart_slots.empty()) {
     if ((rc = build_set(ctx, hs, restart_slots))) return rc;
     HIPCHK(pcgk::launch_state_restart(hs.L, s));
@@ -2252,6 +2489,8 @@ void pcg_destroy(pcg_ctx *ctx) {
   ctx->pool.reset();
   for (auto &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->step_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->t0) (void)hipEventDestroy(ctx->t0);
   if (ctx->t1) (void)hipEventDestroy(ctx->t1);
   if (ctx->h_states) (void)hipHostFree(ctx->h_states);
@@ -2275,7 +2514,7 @@ static int place_single_a(pcg_ctx *ctx) {
     return PCG_ENOMEM;
   }
   ctx->single.blkA = blk;
-  HIPCHK(place_a(P, blk, ctx->single, ctx->stream));
+  HIPCHK(place_a(P, blk, ctx->single, Copier{Copier::Device, ctx->stream}));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->have_a = true;
   return PCG_OK;
@@ -2358,7 +2597,7 @@ static int set_g_from_host(pcg_ctx *ctx, std::vector<int32_t> &grp, std::vector<
     return PCG_ENOMEM;
   }
   ctx->single.blkG = blk;
-  HIPCHK(place_g(P, blk, ctx->single, ctx->stream));
+  HIPCHK(place_g(P, blk, ctx->single, Copier{Copier::Device, ctx->stream}));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   int rc = single_sets(ctx);
   if (rc) return rc;
@@ -2483,7 +2722,7 @@ static int build_fsai_device(pcg_ctx *ctx) {
     auto chain = [&](hipError_t x) {
       if (e == hipSuccess) e = x;
     };
-    chain(place_g(P, blk, S, s));  // patterns (no values yet)
+    chain(place_g(P, blk, S, Copier{Copier::Device, s}));  // patterns (no values yet)
     // the sliced layout's padding must hold zeros (outside any graph capture)
     chain(hipMemsetAsync((void *)S.dev.G.val, 0, P.G.val_bytes(), s));
     chain(hipMemsetAsync((void *)S.dev.GT.val, 0, P.GT.val_bytes(), s));
@@ -3202,6 +3441,10 @@ int pcg_submit_batch(pcg_ctx *ctx, int count, const pcg_system *sys, uint64_t *t
       return rc;
     }
   }
+  if (count > 0) {  // pinned staging for the device images (once; without it images use the heap)
+    (void)hipSetDevice(ctx->cfg.device);
+    (void)ctx->staging.init(kStagingBytes);
+  }
   const double t = now_ms();
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -3293,6 +3536,14 @@ int pcg_solve_batch(pcg_ctx *ctx, int count, const pcg_system *sys, pcg_result *
   int rc = pcg_submit_batch(ctx, count, sys, t.data());
   if (rc) return rc;
   return wait_tickets(ctx, count, t.data(), results, -1.0, iters_per_step);
+}
+
+int pcg_batch_stats_get(pcg_ctx *ctx, pcg_batch_stats *out, int reset) {
+  if (!ctx || !out) return PCG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  *out = ctx->stats;
+  if (reset) ctx->stats = pcg_batch_stats{};
+  return PCG_OK;
 }
 
 int pcg_pool_info(pcg_ctx *ctx, size_t *capacity, size_t *in_use) {

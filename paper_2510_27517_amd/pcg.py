@@ -34,7 +34,7 @@ EXPORTS = [
     "pcg_last_error", "pcg_strerror", "pcg_time_kernels", "pcg_copy_bandwidth", "pcg_read_bandwidth",
     "pcg_submit_batch",
     "pcg_progress", "pcg_poll", "pcg_wait", "pcg_solve_batch", "pcg_pool_info", "pcg_estimate_bytes",
-    "pcg_autotune",
+    "pcg_autotune", "pcg_batch_stats_get",
 ]
 
 
@@ -94,6 +94,18 @@ class TuneResult(ctypes.Structure):
         ("idx16", ctypes.c_int), ("temporal", ctypes.c_int), ("rows_per_lane_gt", ctypes.c_int),
         ("loads_in_flight_a", ctypes.c_int), ("ms_per_iter", ctypes.c_double),
         ("ms_per_iter_auto", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int64), ("step_ms", ctypes.c_double), ("step_bytes", ctypes.c_double),
+        ("wg_launches", ctypes.c_int64), ("wg_ms", ctypes.c_double), ("wg_bytes", ctypes.c_double),
+        ("host_prep_ms", ctypes.c_double), ("host_admit_ms", ctypes.c_double), ("host_step_ms", ctypes.c_double),
+        ("host_retire_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -164,6 +176,7 @@ def load():
     lib.pcg_autotune.argtypes = [P, c_int, ctypes.POINTER(TuneResult)]
     lib.pcg_solve_batch.argtypes = [P, c_int, ctypes.POINTER(System), ctypes.POINTER(Result), c_int]
     lib.pcg_pool_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    lib.pcg_batch_stats_get.argtypes = [P, ctypes.POINTER(BatchStats), c_int]
     lib.pcg_last_error.argtypes = [P]
     lib.pcg_last_error.restype = ctypes.c_char_p
     lib.pcg_strerror.argtypes = [c_int]
@@ -491,6 +504,13 @@ class Solver:
         res = (Result * len(built))()
         self._check(self._lib.pcg_solve_batch(self._h, len(built), arr, res, int(iters_per_step)), "pcg_solve_batch")
         return [(b[2], res[i].as_dict()) for i, b in enumerate(built)]
+
+    def batch_stats(self, reset: bool = False):
+        """Device time and bytes of the batching scheduler's work (see
+        pcg_batch_stats_get); reset zeroes the counters after reading."""
+        out = BatchStats()
+        self._check(self._lib.pcg_batch_stats_get(self._h, ctypes.byref(out), int(reset)), "pcg_batch_stats_get")
+        return out.as_dict()
 
     def pool_info(self):
         cap, used = ctypes.c_size_t(), ctypes.c_size_t()

@@ -396,3 +396,29 @@ def test_one_workgroup_systems_in_a_batch(gpu_lib):
         assert r1["status"] == r2["status"] == ref.status == pcg.OK
         assert r1["iters"] == r2["iters"] == ref.iters
         assert np.array_equal(x1, x2) and np.array_equal(x2, ref.x)
+
+
+def test_batch_stats_device_time_and_bytes(gpu_lib):
+    """pcg_batch_stats_get: the scheduler's iteration steps are timed on the
+    device and their bytes are each system's iterations times its bytes per
+    iteration, so over a whole batch they add up to the results' own
+    iterations x bytes_per_iter (split between the steps and the
+    one-workgroup launches when small systems take those); a reset zeroes
+    the counters."""
+    pcg = gpu_lib
+    systems = _mix(3, 9)
+    for wgb in (-1, 0):
+        with pcg.Solver(pcg.default_config(wg_max_n_batch=wgb)) as s:
+            res = s.solve_batch(systems, iters_per_step=10)
+            st = s.batch_stats(reset=True)
+            st2 = s.batch_stats()
+        want = sum(r["iters"] * r["bytes_per_iter"] for _, r in res)
+        say("batch stats", wgb, st, want)
+        assert all(r["status"] == pcg.OK for _, r in res)
+        got = st["step_bytes"] + st["wg_bytes"]
+        assert abs(got - want) <= 1e-9 * want
+        if wgb == -1:
+            assert st["wg_launches"] == 0 and st["steps"] > 0 and st["step_ms"] > 0
+        else:
+            assert st["wg_launches"] >= 1 and st["wg_ms"] > 0
+        assert st2["steps"] == 0 and st2["step_bytes"] == 0 and st2["wg_launches"] == 0
