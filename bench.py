@@ -55,6 +55,8 @@ MAXIT = 5000
 KERNEL_SOURCES = ["paper_2510_27517_amd/csrc/kernels.hip", "paper_2510_27517_amd/csrc/kernels.h"]
 PROFILES = os.path.join(ROOT, "profiles")
 SECTIONS = ["mixed", "sai_loss", "autotune", "small", "batched", "serving", "elasticity", "synthetic"]
+# long runs, only when named: the serving workload at its configured length
+OPTIONAL_SECTIONS = ["serving_stream"]
 
 
 def log(*a):
@@ -475,9 +477,10 @@ def _open_loop(pcg, cfg, reqs, arrive, iters_per_step):
                 active, queued = s.progress(iters_per_step)
                 depth.append(active + queued)
                 used.append(s.pool_info()[1])
+                if active + queued < len(tickets) - len(got):  # completions wait to be collected
+                    _drain(s, tickets, got)
             elif nxt < count:
                 time.sleep(max(0.0, min(0.01, arrive[nxt] - now)))
-            _drain(s, tickets, got)
         span = time.perf_counter() - t0
     lat = [got[t][1]["t_latency_ms"] + sub_lag[t] for t in tickets]
     st = [got[t][1]["status"] for t in tickets]
@@ -485,6 +488,113 @@ def _open_loop(pcg, cfg, reqs, arrive, iters_per_step):
     split = {"queue_ms_p50": pct([got[t][1]["t_queue_ms"] for t in tickets], 50),
              "solve_ms_p50": pct([got[t][1]["t_solve_ms"] for t in tickets], 50)}
     return lat, st, span, depth, used, rel, split
+
+
+def _stream(pcg, cfg, make_req, count, arrive, window, iters_per_step):
+    """Serve `count` requests made on demand by make_req(i), at their arrival
+    times (open loop) or, with arrive None, keeping `window` in flight
+    (closed loop). Only statistics are kept: each solution is dropped when
+    its ticket completes."""
+    lat, st, qms, sms, depth, used = [], [], [], [], [], []
+    rel = 0.0
+    outstanding = {}  # ticket -> submission lag behind the arrival (ms)
+    with pcg.Solver(cfg) as s:
+        t0 = time.perf_counter()
+        nxt = done = 0
+        last_log = t0
+        while done < count:
+            now = time.perf_counter() - t0
+            batch = []
+            if arrive is None:
+                while nxt < count and len(outstanding) + len(batch) < window:
+                    batch.append(nxt)
+                    nxt += 1
+            else:
+                while nxt < count and arrive[nxt] <= now:
+                    batch.append(nxt)
+                    nxt += 1
+            if batch:
+                tk = s.submit([make_req(i) for i in batch])
+                for i, t in zip(batch, tk):
+                    outstanding[t] = 0.0 if arrive is None else (now - arrive[i]) * 1e3
+            finished = False
+            if outstanding:
+                a, q = s.progress(iters_per_step)
+                depth.append(a + q)
+                used.append(s.pool_info()[1])
+                finished = a + q < len(outstanding)  # some ticket completed and waits to be collected
+            elif nxt < count:
+                time.sleep(max(0.0, min(0.01, arrive[nxt] - now)))
+            for t in (list(outstanding) if finished else ()):
+                r = s.poll(t)
+                if r is not None:
+                    res = r[1]
+                    lat.append(res["t_latency_ms"] + outstanding.pop(t))
+                    st.append(res["status"])
+                    rel = max(rel, res["relres_true"])
+                    qms.append(res["t_queue_ms"])
+                    sms.append(res["t_solve_ms"])
+                    done += 1
+            if time.perf_counter() - last_log > 30:
+                last_log = time.perf_counter()
+                log(f"serving stream: {done}/{count} done, {len(outstanding)} outstanding")
+        span = time.perf_counter() - t0
+        gs = s.batch_stats()
+    return dict(lat=lat, st=st, span=span, depth=depth, used=used, rel=rel, qms=qms, sms=sms, gs=gs)
+
+
+def section_serving_stream(pcg, inputs, count, pool, window, iters_per_step, loads, mu_given=0.0):
+    """The serving workload at its configured length: `count` requests whose
+    matrices come from a pool of `pool` generated RGG Laplacians (sizes
+    log-uniform in [1e3, 1e6], the serving recipe), request i taking pool
+    matrix i mod pool with a right-hand side of its own, generated at
+    submission. A closed loop with `window` requests in flight gives the
+    sustainable rate mu (or mu_given, from an earlier run); then Poisson
+    arrivals at the given fractions of mu."""
+    log(f"serving stream: generating {pool} pool matrices")
+    mats = [r["A"] for r in serving_requests(inputs, pool)]
+
+    def make_req(i):
+        A = mats[i % pool]
+        return dict(A=A, b=inputs.rhs(A.n, 30_000 + i), tol=1e-6, maxit=20000)
+
+    cfg = pcg.default_config(vec_dtype="f32", a_dtype="f32", g_dtype="bf16", refine=1)
+    ns = [mats[i % pool].n for i in range(count)]
+    out = {"workload": f"{count} RGG Laplacian + 1e-3 I requests from a pool of {pool} matrices (n log-uniform "
+                       f"[1e3,1e6], mean over the stream {np.mean(ns):.0f}), right-hand side per request; f32 "
+                       "A/vectors, bf16 FSAI G, FP64 refinement, tol 1e-6",
+           "requests": count, "pool_matrices": pool, "closed_loop_window": window, "loads": {}}
+
+    def summary(r):
+        gs = r["gs"]
+        return {"solves_per_s": round(count / r["span"], 2), "span_s": round(r["span"], 1),
+                "latency_ms_p50": pct(r["lat"], 50), "latency_ms_p99": pct(r["lat"], 99),
+                "latency_ms_p999": pct(r["lat"], 99.9), "ok": r["st"].count(pcg.OK),
+                "max_relres_true_fp64": r["rel"], "queue_ms_p50": pct(r["qms"], 50),
+                "solve_ms_p50": pct(r["sms"], 50),
+                "queue_depth_mean": float(np.mean(r["depth"])) if r["depth"] else 0.0,
+                "queue_depth_max": int(max(r["depth"])) if r["depth"] else 0,
+                "admitted_mb_max": float(max(r["used"])) / 2**20 if r["used"] else 0.0,
+                "gpu_busy_fraction_iteration_steps": round(gs["step_ms"] / (r["span"] * 1e3), 3),
+                "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire")}}
+
+    if mu_given > 0:
+        mu = mu_given
+        out["closed_loop_solves_per_s"] = mu
+        out["closed_loop"] = "rate given (measured in an earlier run of this section)"
+    else:
+        log(f"serving stream: closed loop, {count} requests, {window} in flight")
+        closed = _stream(pcg, cfg, make_req, count, None, window, iters_per_step)
+        mu = count / closed["span"]
+        out["closed_loop"] = summary(closed)
+        out["closed_loop_solves_per_s"] = round(mu, 2)
+    gaps01 = -np.log(inputs.u01(7, inputs.STREAM_ARRIVALS, count))
+    for f in loads:
+        lam = f * mu
+        log(f"serving stream: open loop at {lam:.1f} requests/s ({f} mu)")
+        r = _stream(pcg, cfg, make_req, count, np.cumsum(gaps01 / lam), window, iters_per_step)
+        out["loads"][str(f)] = {"arrival_rate": round(lam, 2), **summary(r)}
+    return out
 
 
 def section_serving(pcg, inputs, count, iters_per_step):
@@ -608,6 +718,12 @@ def main():
     ap.add_argument("--batch-systems", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-step", type=int, default=10)
+    ap.add_argument("--serve-pool", type=int, default=500, help="pool matrices of the serving_stream section")
+    ap.add_argument("--serve-window", type=int, default=200, help="requests in flight in its closed loop")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95", help="arrival rates of the serving_stream section, "
+                    "as fractions of its closed-loop rate")
+    ap.add_argument("--serve-mu", type=float, default=0.0, help="closed-loop rate of the serving_stream section "
+                    "from an earlier run (0: measure it)")
     ap.add_argument("--elasticity-n", type=int, default=64)
     ap.add_argument("--synthetic-batch", type=int, default=64)
     args = ap.parse_args()
@@ -615,7 +731,7 @@ def main():
         print("bench.py measures one GPU: the library runs each solve on one GPU (independent systems would "
               "shard by request across GPUs, a single system by row slabs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    sections = [x for x in args.sections.split(",") if x in SECTIONS]
+    sections = [x for x in args.sections.split(",") if x in SECTIONS + OPTIONAL_SECTIONS]
 
     import torch
 
@@ -735,6 +851,10 @@ def main():
         extra["small"] = section_small(pcg, inputs)
     if "batched" in sections and args.batch_systems > 0:
         extra["batched"], refs["batched_sample"] = section_batched(pcg, inputs, args.batch_systems)
+    if "serving_stream" in sections and args.serve_requests > 0:
+        extra["serving_stream"] = section_serving_stream(
+            pcg, inputs, args.serve_requests, args.serve_pool, args.serve_window, args.serve_step,
+            [float(f) for f in args.serve_loads.split(",") if f], args.serve_mu)
     if "serving" in sections and args.serve_requests > 0:
         extra["serving"], refs["served_sample"] = section_serving(pcg, inputs, args.serve_requests, args.serve_step)
     if "elasticity" in sections and args.elasticity_n > 0:

@@ -7,6 +7,8 @@
 #include <cstring>
 #include <thread>
 
+#include <sched.h>
+
 #include "kernels.h"
 #include "pcg.h"
 
@@ -278,8 +280,15 @@ int build_seeded(uint64_t seed, int32_t n, const int32_t *rp, const int32_t *ci,
 }
 
 // Builds G (CSR) for `kind`; for the lower kinds also returns G^T directly.
+unsigned available_cpus() {
+  cpu_set_t cs;
+  if (sched_getaffinity(0, sizeof cs, &cs) == 0) return (unsigned)std::max(1, CPU_COUNT(&cs));
+  return std::max(1u, std::thread::hardware_concurrency());
+}
+
 int build_g(int kind, uint64_t seed, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
-            std::vector<int32_t> &grp, std::vector<int32_t> &gci, std::vector<double> &gv) {
+            std::vector<int32_t> &grp, std::vector<int32_t> &gci, std::vector<double> &gv, int threads) {
+  const unsigned nthreads = std::min(32u, threads > 0 ? (unsigned)threads : available_cpus());
   if (kind == PCG_G_SEEDED) return build_seeded(seed, n, rp, ci, v, grp, gci, gv);
   if (kind == PCG_G_JACOBI || kind == PCG_G_IDENTITY) {
     grp.resize(n + 1);
@@ -308,8 +317,7 @@ int build_g(int kind, uint64_t seed, int32_t n, const int32_t *rp, const int32_t
     for (int32_t I = 0; I < n / 3; ++I)
       for (int p = 0; p < 3; ++p) lrp[3 * I + p + 1] = lrp[3 * I + p] + 3 * tril_blocks(I, rp, ci);
     const int32_t nb = n / 3;
-    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-    if (nb < 2000) nt = 1;
+    const unsigned nt = nb < 2000 ? 1u : nthreads;
     std::vector<int> rcs(nt, PCG_OK);
     std::vector<std::thread> th;
     for (unsigned w = 0; w < nt; ++w) {
@@ -349,8 +357,7 @@ int build_g(int kind, uint64_t seed, int32_t n, const int32_t *rp, const int32_t
     return PCG_OK;  // this G is lower-triangular itself
   }
   // FSAI: G_L rows in parallel, then G = G_L^T
-  unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-  if (n < 20000) nt = 1;
+  const unsigned nt = n < 20000 ? 1u : nthreads;
   std::vector<int> rcs(nt, PCG_OK);
   std::vector<std::thread> th;
   for (unsigned w = 0; w < nt; ++w) {

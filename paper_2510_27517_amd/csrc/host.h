@@ -25,9 +25,14 @@ uint16_t to_f16_bits(double v);
 // Nonzeros of G for a preconditioner kind on A's pattern (-1: unknown kind).
 int64_t g_nnz(int kind, int32_t n, const int32_t *rp, const int32_t *ci);
 
-// G (CSR) for a preconditioner kind built from A (seed: PCG_G_SEEDED).
+// CPUs this process may run on (its affinity mask), at least 1.
+unsigned available_cpus();
+
+// G (CSR) for a preconditioner kind built from A (seed: PCG_G_SEEDED). The
+// FSAI rows are built on `threads` threads (0: available_cpus(), at most 32;
+// systems too small to pay for threads use one).
 int build_g(int kind, uint64_t seed, int32_t n, const int32_t *rp, const int32_t *ci, const double *v, std::vector<int32_t> &grp,
-            std::vector<int32_t> &gci, std::vector<double> &gv);
+            std::vector<int32_t> &gci, std::vector<double> &gv, int threads = 0);
 
 // Row-block partition: (row start, nonzero start) pairs, nblk + 1 of them.
 std::vector<int32_t> row_blocks(int32_t n, const int32_t *rp, int cap);

@@ -1577,7 +1577,8 @@ void prep_parts(const pcg_config &cfg, int cus, Req &R) {
     gci.swap(R.g_ci);
     gv.swap(R.g_val);
   } else {
-    int rc = pcgh::build_g(R.g_kind, R.g_seed, R.n, R.a_rp.data(), R.a_ci.data(), R.a_val.data(), grp, gci, gv);
+    // one thread: the workers already prepare several systems at once
+    int rc = pcgh::build_g(R.g_kind, R.g_seed, R.n, R.a_rp.data(), R.a_ci.data(), R.a_val.data(), grp, gci, gv, 1);
     if (rc) {
       R.prep_rc = rc;
       return;
@@ -1634,9 +1635,7 @@ void start_workers(pcg_ctx *ctx) {
   if (!ctx->workers.empty()) return;
   // the CPUs this process may run on, less two (the scheduler and the
   // caller's thread), at most 32
-  unsigned ncpu = std::max(1u, std::thread::hardware_concurrency());
-  cpu_set_t cs;
-  if (sched_getaffinity(0, sizeof cs, &cs) == 0) ncpu = (unsigned)std::max(1, CPU_COUNT(&cs));
+  const unsigned ncpu = pcgh::available_cpus();
   const unsigned nt = std::max(1u, std::min(32u, ncpu > 2 ? ncpu - 2 : 1u));
   for (unsigned i = 0; i < nt; ++i) ctx->workers.emplace_back(worker_main, ctx);
 }
