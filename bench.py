@@ -40,6 +40,7 @@ import math
 import os
 import re
 import sys
+import threading
 import time
 
 import numpy as np
@@ -385,7 +386,7 @@ def section_batched(pcg, inputs, count):
            "one_workgroup_launches": gs["wg_launches"], "one_workgroup_device_ms": round(gs["wg_ms"], 2),
            "one_workgroup_bytes": gs["wg_bytes"],
            "gpu_only_solves_per_s": round(count / ((gs["step_ms"]) * 1e-3), 1) if gs["step_ms"] > 0 else None,
-           "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire")},
+           "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire", "progress", "idle")},
            "g_prebuilt": {"wall_s": round(wall_pre, 3), "solves_per_s": round(count / wall_pre, 2),
                           "ok": sum(1 for _, r in rpre if r["status"] == pcg.OK),
                           "step_device_ms": round(gs_pre["step_ms"], 2),
@@ -443,104 +444,79 @@ def serving_requests(inputs, count):
     return out
 
 
-def _drain(s, tickets, got):
-    for t in tickets:
-        if t not in got:
-            r = s.poll(t)
-            if r is not None:
-                got[t] = r
-
-
-def _open_loop(pcg, cfg, reqs, arrive, iters_per_step):
-    """Submit each request at its arrival time (to the step granularity) and
-    drive the scheduler; returns latencies (arrival to completion), statuses,
-    the span, and the queue depth and admitted bytes seen after each step."""
-    count = len(reqs)
-    got, tickets, sub_lag = {}, [], {}
-    depth, used = [], []
-    with pcg.Solver(cfg) as s:
-        t0 = time.perf_counter()
-        nxt = 0
-        active = queued = 0
-        while len(got) < count:
-            now = time.perf_counter() - t0
-            batch = []
-            while nxt < count and arrive[nxt] <= now:
-                batch.append(nxt)
-                nxt += 1
-            if batch:
-                tk = s.submit([reqs[i] for i in batch])
-                for i, t in zip(batch, tk):
-                    tickets.append(t)
-                    sub_lag[t] = (now - arrive[i]) * 1e3
-            if active or queued or batch or len(got) < len(tickets):
-                active, queued = s.progress(iters_per_step)
-                depth.append(active + queued)
-                used.append(s.pool_info()[1])
-                if active + queued < len(tickets) - len(got):  # completions wait to be collected
-                    _drain(s, tickets, got)
-            elif nxt < count:
-                time.sleep(max(0.0, min(0.01, arrive[nxt] - now)))
-        span = time.perf_counter() - t0
-    lat = [got[t][1]["t_latency_ms"] + sub_lag[t] for t in tickets]
-    st = [got[t][1]["status"] for t in tickets]
-    rel = max(got[t][1]["relres_true"] for t in tickets)
-    split = {"queue_ms_p50": pct([got[t][1]["t_queue_ms"] for t in tickets], 50),
-             "solve_ms_p50": pct([got[t][1]["t_solve_ms"] for t in tickets], 50)}
-    return lat, st, span, depth, used, rel, split
-
-
-def _stream(pcg, cfg, make_req, count, arrive, window, iters_per_step):
-    """Serve `count` requests made on demand by make_req(i), at their arrival
-    times (open loop) or, with arrive None, keeping `window` in flight
-    (closed loop). Only statistics are kept: each solution is dropped when
-    its ticket completes."""
+def _serve(pcg, cfg, make_req, count, arrive, window, iters_per_step):
+    """Serve `count` requests made on demand by make_req(i): submitted by a
+    thread of their own at their arrival times (open loop), or, with arrive
+    None, whenever fewer than `window` are in flight (closed loop), while
+    this thread drives the scheduler and collects finished tickets. Only
+    statistics are kept: each solution is dropped when its ticket completes.
+    Latency runs from arrival (or, in the closed loop, submission) to
+    completion."""
     lat, st, qms, sms, depth, used = [], [], [], [], [], []
-    rel = 0.0
+    rel = [0.0]
+    lock = threading.Lock()
     outstanding = {}  # ticket -> submission lag behind the arrival (ms)
     with pcg.Solver(cfg) as s:
         t0 = time.perf_counter()
-        nxt = done = 0
-        last_log = t0
-        while done < count:
-            now = time.perf_counter() - t0
-            batch = []
-            if arrive is None:
-                while nxt < count and len(outstanding) + len(batch) < window:
-                    batch.append(nxt)
-                    nxt += 1
-            else:
-                while nxt < count and arrive[nxt] <= now:
-                    batch.append(nxt)
-                    nxt += 1
-            if batch:
+
+        def submitter():
+            nxt = 0
+            while nxt < count:
+                now = time.perf_counter() - t0
+                if arrive is None:
+                    with lock:
+                        room = window - len(outstanding)
+                    if room <= 0:
+                        time.sleep(0.0005)
+                        continue
+                    batch = list(range(nxt, min(count, nxt + room)))
+                else:
+                    if arrive[nxt] > now:
+                        time.sleep(min(0.005, arrive[nxt] - now))
+                        continue
+                    batch = []
+                    while nxt + len(batch) < count and arrive[nxt + len(batch)] <= now:
+                        batch.append(nxt + len(batch))
+                nxt += len(batch)
                 tk = s.submit([make_req(i) for i in batch])
-                for i, t in zip(batch, tk):
-                    outstanding[t] = 0.0 if arrive is None else (now - arrive[i]) * 1e3
-            finished = False
-            if outstanding:
-                a, q = s.progress(iters_per_step)
-                depth.append(a + q)
-                used.append(s.pool_info()[1])
-                finished = a + q < len(outstanding)  # some ticket completed and waits to be collected
-            elif nxt < count:
-                time.sleep(max(0.0, min(0.01, arrive[nxt] - now)))
-            for t in (list(outstanding) if finished else ()):
-                r = s.poll(t)
-                if r is not None:
-                    res = r[1]
-                    lat.append(res["t_latency_ms"] + outstanding.pop(t))
-                    st.append(res["status"])
-                    rel = max(rel, res["relres_true"])
-                    qms.append(res["t_queue_ms"])
-                    sms.append(res["t_solve_ms"])
-                    done += 1
+                with lock:
+                    for i, t in zip(batch, tk):
+                        outstanding[t] = 0.0 if arrive is None else (now - arrive[i]) * 1e3
+
+        th = threading.Thread(target=submitter, daemon=True)
+        th.start()
+        done, last_log = 0, t0
+        while done < count:
+            with lock:
+                waiting = len(outstanding)
+            if waiting == 0:
+                time.sleep(0.0005)
+                continue
+            a, q = s.progress(iters_per_step)
+            depth.append(a + q)
+            used.append(s.pool_info()[1])
+            if a + q < waiting:  # some ticket completed and waits to be collected
+                with lock:
+                    tks = list(outstanding)
+                for t in tks:
+                    r = s.poll(t)
+                    if r is not None:
+                        res = r[1]
+                        with lock:
+                            lag = outstanding.pop(t)
+                        lat.append(res["t_latency_ms"] + lag)
+                        st.append(res["status"])
+                        rel[0] = max(rel[0], res["relres_true"])
+                        qms.append(res["t_queue_ms"])
+                        sms.append(res["t_solve_ms"])
+                        done += 1
             if time.perf_counter() - last_log > 30:
                 last_log = time.perf_counter()
-                log(f"serving stream: {done}/{count} done, {len(outstanding)} outstanding")
+                log(f"serving: {done}/{count} done, {waiting} in flight")
         span = time.perf_counter() - t0
+        th.join()
         gs = s.batch_stats()
-    return dict(lat=lat, st=st, span=span, depth=depth, used=used, rel=rel, qms=qms, sms=sms, gs=gs)
+    return dict(lat=lat, st=st, span=span, depth=depth, used=used, rel=rel[0], qms=qms, sms=sms, gs=gs)
 
 
 def section_serving_stream(pcg, inputs, count, pool, window, iters_per_step, loads, mu_given=0.0):
@@ -576,7 +552,7 @@ def section_serving_stream(pcg, inputs, count, pool, window, iters_per_step, loa
                 "queue_depth_max": int(max(r["depth"])) if r["depth"] else 0,
                 "admitted_mb_max": float(max(r["used"])) / 2**20 if r["used"] else 0.0,
                 "gpu_busy_fraction_iteration_steps": round(gs["step_ms"] / (r["span"] * 1e3), 3),
-                "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire")}}
+                "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire", "progress", "idle")}}
 
     if mu_given > 0:
         mu = mu_given
@@ -584,7 +560,7 @@ def section_serving_stream(pcg, inputs, count, pool, window, iters_per_step, loa
         out["closed_loop"] = "rate given (measured in an earlier run of this section)"
     else:
         log(f"serving stream: closed loop, {count} requests, {window} in flight")
-        closed = _stream(pcg, cfg, make_req, count, None, window, iters_per_step)
+        closed = _serve(pcg, cfg, make_req, count, None, window, iters_per_step)
         mu = count / closed["span"]
         out["closed_loop"] = summary(closed)
         out["closed_loop_solves_per_s"] = round(mu, 2)
@@ -592,7 +568,7 @@ def section_serving_stream(pcg, inputs, count, pool, window, iters_per_step, loa
     for f in loads:
         lam = f * mu
         log(f"serving stream: open loop at {lam:.1f} requests/s ({f} mu)")
-        r = _stream(pcg, cfg, make_req, count, np.cumsum(gaps01 / lam), window, iters_per_step)
+        r = _serve(pcg, cfg, make_req, count, np.cumsum(gaps01 / lam), window, iters_per_step)
         out["loads"][str(f)] = {"arrival_rate": round(lam, 2), **summary(r)}
     return out
 
@@ -620,7 +596,7 @@ def section_serving(pcg, inputs, count, iters_per_step):
            "closed_loop_gpu": {"step_device_ms": round(gs["step_ms"], 1), "wall_ms": round(wall * 1e3, 1),
                                "busy_fraction_iteration_steps": round(gs["step_ms"] / (wall * 1e3), 3),
                                "one_workgroup_device_ms": round(gs["wg_ms"], 1),
-                               "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire")},
+                               "host_ms": {k: round(gs["host_" + k + "_ms"], 1) for k in ("prep", "admit", "step", "retire", "progress", "idle")},
                                "aggregate_gbps_over_active_set": round(gs["step_bytes"] / (gs["step_ms"] * 1e-3) / 1e9,
                                                                        1) if gs["step_ms"] > 0 else None},
            "loads": {}}
@@ -629,16 +605,19 @@ def section_serving(pcg, inputs, count, iters_per_step):
     for f in (0.5, 0.8, 0.95):
         lam = f * mu
         log(f"serving: open loop at {lam:.1f} requests/s ({f} mu)")
-        lat, st, span, depth, used, rel, split = _open_loop(pcg, cfg, reqs, np.cumsum(gaps01 / lam), iters_per_step)
+        r = _serve(pcg, cfg, lambda i: reqs[i], count, np.cumsum(gaps01 / lam), 0, iters_per_step)
+        depth, used = r["depth"], r["used"]
         out["loads"][str(f)] = {
-            "arrival_rate": round(lam, 2), "solves_per_s": round(count / span, 2),
-            "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99), "ok": st.count(pcg.OK),
-            "max_relres_true_fp64": rel, "queue_depth_mean": float(np.mean(depth)) if depth else 0.0,
+            "arrival_rate": round(lam, 2), "solves_per_s": round(count / r["span"], 2),
+            "latency_ms_p50": pct(r["lat"], 50), "latency_ms_p99": pct(r["lat"], 99), "ok": r["st"].count(pcg.OK),
+            "max_relres_true_fp64": r["rel"], "queue_depth_mean": float(np.mean(depth)) if depth else 0.0,
             "queue_depth_max": int(max(depth)) if depth else 0,
             "admitted_mb_mean": float(np.mean(used)) / 2**20 if used else 0.0,
             "admitted_mb_max": float(max(used)) / 2**20 if used else 0.0,
+            "queue_ms_p50": pct(r["qms"], 50), "solve_ms_p50": pct(r["sms"], 50),
             "note": "queue = submission to admission (host G construction, staging, waiting for memory); "
-                    "solve = admission to completion", **split}
+                    "solve = admission to completion; requests submitted by a thread of their own at their "
+                    "arrival times"}
     main = out["loads"]["0.8"]
     out["latency_ms_p50"], out["latency_ms_p99"] = main["latency_ms_p50"], main["latency_ms_p99"]
     # the same requests with each FSAI factored on the device at admission

@@ -395,6 +395,8 @@ typedef struct {
   double host_admit_ms;  /* scheduler: admission (pool blocks, uploads, first kernels) */
   double host_step_ms;   /* scheduler: launching the steps' iterations and reading the states back */
   double host_retire_ms; /* scheduler: finishing stopped systems (final residual, solution copies, refinement steps) */
+  double host_progress_ms; /* scheduler: all of its steps (the three phases above and the rest of each step) */
+  double host_idle_ms;     /* waiting callers (pcg_wait, pcg_solve_batch) asleep with nothing active */
 } pcg_batch_stats;
 int pcg_batch_stats_get(pcg_ctx *ctx, pcg_batch_stats *out, int reset);
 

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -844,6 +845,7 @@ struct pcg_ctx {
   // device-time accounting of the batching facility (pcg_batch_stats_get)
   hipEvent_t step_ev[2] = {nullptr, nullptr};
   pcg_batch_stats stats{};
+  uint64_t completed = 0;  // tickets finished so far (under mu)
   std::vector<WgGroup> wg_groups;
   hipStream_t side = nullptr;
   int wg_inflight = 0;
@@ -1663,6 +1665,7 @@ void finish_request(pcg_ctx *ctx, Req &R, int status, const State &f, int restar
   R.res.t_latency_ms = R.t_done - R.t_submit;
   R.res.t_queue_ms = R.t_admit - R.t_submit;
   R.st = RQ_DONE;
+  ++ctx->completed;
 }
 
 int place_admitted(pcg_ctx *ctx, std::vector<std::shared_ptr<Req>> &cand, std::vector<void *> &temps);
@@ -1946,6 +1949,7 @@ void finish_refined(pcg_ctx *ctx, Req &R, int status) {
   R.res.t_latency_ms = R.t_done - R.t_submit;
   R.res.t_queue_ms = R.t_admit - R.t_submit;
   R.st = RQ_DONE;
+  ++ctx->completed;
 }
 
 // Refinement decision after the FP64 residual of each system in `list` (its
@@ -2126,14 +2130,14 @@ int progress(pcg_ctx *ctx, int iters) {
   {
     PhaseTimer pt(ctx, &pcg_batch_stats::host_admit_ms);
     if ((rc = admit(ctx, admitted))) return rc;
-  }
-  if (!admitted.empty() && ctx->cfg.refine) {
-    int mx = 0;
-    for (auto &R : admitted) mx = std::max(mx, R->slot64);
-    HIPCHK(hipMemcpy(ctx->h_states, ctx->d_states, 2 * sizeof(State) * (size_t)(mx + 1), hipMemcpyDeviceToHost));
-    std::vector<std::shared_ptr<Req>> cont;
-    if ((rc = outer_decide(ctx, admitted, cont))) return rc;
-    admitted.swap(cont);
+    if (!admitted.empty() && ctx->cfg.refine) {  // the first refinement step of the new systems
+      int mx = 0;
+      for (auto &R : admitted) mx = std::max(mx, R->slot64);
+      HIPCHK(hipMemcpy(ctx->h_states, ctx->d_states, 2 * sizeof(State) * (size_t)(mx + 1), hipMemcpyDeviceToHost));
+      std::vector<std::shared_ptr<Req>> cont;
+      if ((rc = outer_decide(ctx, admitted, cont))) return rc;
+      admitted.swap(cont);
+    }
   }
   if (!admitted.empty()) {
     std::vector<std::shared_ptr<Req>> wg;
@@ -3430,16 +3434,28 @@ int pcg_read_bandwidth(int device, int64_t bytes, int reps, double *gbps, double
 int pcg_submit_batch(pcg_ctx *ctx, int count, const pcg_system *sys, uint64_t *tickets) {
   if (!ctx) return PCG_EINVAL;
   if (count < 0 || (count > 0 && (!sys || !tickets))) return PCG_EINVAL;
+  // validate and copy the systems, on several threads for a large batch
   std::vector<std::shared_ptr<Req>> reqs(count);
-  for (int i = 0; i < count; ++i) {
-    std::string err;
-    const int rc = copy_request(sys[i], reqs[i], err);
-    if (rc) {  // nothing queued on error
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      ctx->err = err;
-      return rc;
-    }
+  std::vector<int> rcs(count, PCG_OK);
+  std::vector<std::string> errs(count);
+  const unsigned nt = count < 8 ? 1u : std::min(16u, std::min(pcgh::available_cpus(), (unsigned)count));
+  if (nt <= 1) {
+    for (int i = 0; i < count; ++i) rcs[i] = copy_request(sys[i], reqs[i], errs[i]);
+  } else {
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nt; ++w)
+      th.emplace_back([&] {
+        for (int i; (i = next.fetch_add(1)) < count;) rcs[i] = copy_request(sys[i], reqs[i], errs[i]);
+      });
+    for (auto &t : th) t.join();
   }
+  for (int i = 0; i < count; ++i)
+    if (rcs[i]) {  // nothing queued on error
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->err = errs[i];
+      return rcs[i];
+    }
   if (count > 0) {  // pinned staging for the device images (once; without it images use the heap)
     (void)hipSetDevice(ctx->cfg.device);
     (void)ctx->staging.init(kStagingBytes);
@@ -3464,7 +3480,11 @@ int pcg_progress(pcg_ctx *ctx, int iters, int *active, int *queued) {
   if (!ctx) return PCG_EINVAL;
   if (iters < 0) return PCG_EINVAL;
   HIPCHK(hipSetDevice(ctx->cfg.device));
-  int rc = progress(ctx, iters);
+  int rc;
+  {
+    PhaseTimer pt(ctx, &pcg_batch_stats::host_progress_ms);
+    rc = progress(ctx, iters);
+  }
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (active) *active = (int)ctx->active.size() + ctx->wg_inflight;
   if (queued) *queued = (int)(ctx->prep_q.size() + ctx->ready_q.size()) + ctx->preparing;
@@ -3488,10 +3508,14 @@ static int wait_tickets(pcg_ctx *ctx, int count, const uint64_t *tickets, pcg_re
                         int iters_per_step) {
   const int step = iters_per_step > 0 ? iters_per_step : 20;
   const double t_end = now_ms() + (timeout_s < 0 ? 1e300 : timeout_s * 1e3);
+  uint64_t seen = UINT64_MAX;  // completions counted at the last look at the tickets
   for (;;) {
     bool all = true;
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
+      // the tickets are looked at again only after some ticket has finished
+      if (ctx->completed == seen) all = false;
+      seen = ctx->completed;
       for (int i = 0; i < count && all; ++i) {
         auto it = ctx->by_ticket.find(tickets[i]);
         if (it == ctx->by_ticket.end()) {
@@ -3506,7 +3530,10 @@ static int wait_tickets(pcg_ctx *ctx, int count, const uint64_t *tickets, pcg_re
     int act = 0, q = 0;
     const int rc = pcg_progress(ctx, step, &act, &q);
     if (rc) return rc;
-    if (act == 0) std::this_thread::sleep_for(std::chrono::microseconds(200));
+    if (act == 0) {
+      PhaseTimer pt(ctx, &pcg_batch_stats::host_idle_ms);
+      std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
   }
   // collect every result before any ticket is dropped, so that a ticket
   // listed twice gets its result twice

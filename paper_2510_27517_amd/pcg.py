@@ -105,7 +105,7 @@ class BatchStats(ctypes.Structure):
         ("steps", ctypes.c_int64), ("step_ms", ctypes.c_double), ("step_bytes", ctypes.c_double),
         ("wg_launches", ctypes.c_int64), ("wg_ms", ctypes.c_double), ("wg_bytes", ctypes.c_double),
         ("host_prep_ms", ctypes.c_double), ("host_admit_ms", ctypes.c_double), ("host_step_ms", ctypes.c_double),
-        ("host_retire_ms", ctypes.c_double),
+        ("host_retire_ms", ctypes.c_double), ("host_progress_ms", ctypes.c_double), ("host_idle_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
