@@ -43,6 +43,7 @@
 #include <cmath>
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -60,6 +61,10 @@ namespace pcgk {
 // spills), the occupancy its default grid of 4 workgroups of 4 waves per CU
 // gives anyway.
 #define PCG_GT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4)))
+// The G-kernel holds its first slice's operands and products while its
+// workgroup reduces the partial sums of the G^T-kernel: compiled for 6 waves
+// per SIMD (at most 80 VGPRs, no spills), above what its default grid fills.
+#define PCG_G_OCCUPANCY __attribute__((amdgpu_waves_per_eu(6)))
 
 #ifndef PCG_UNROLL
 #define PCG_UNROLL 4
@@ -76,6 +81,17 @@ struct bf16_t { uint16_t bits; };
 template <typename T>
 __device__ __forceinline__ GLOBAL T *gl(T *p) {
   return (GLOBAL T *)p;
+}
+
+// Layout metadata that a whole wave reads at one address (slice pointers,
+// per-slice column offsets) is read through the constant address space, so
+// that those reads compile to scalar loads: they wait on their own counter
+// instead of behind the wave's outstanding vector loads and stores. Valid
+// because no kernel writes a layout's metadata while it is being read.
+#define CONSTANT __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ CONSTANT const T *ro(GLOBAL const T *p) {
+  return (CONSTANT const T *)p;
 }
 
 // Matrix values and column indices are read once per product. NT = true:
@@ -315,7 +331,7 @@ __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pr
   const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
   for (int k = w * NW + wv; k < s1 - s0; k += W * NW) {
     const int c = REV ? s1 - 1 - k : s0 + k;
-    const int o0 = M.blk[c], wd = M.blk[c + 1] - o0;
+    const int o0 = ro(M.blk)[c], wd = ro(M.blk)[c + 1] - o0;
     const int row = c * kSliceRows + lane;
     const bool has = row < M.n;
     RowVals<TACC> pv{};
@@ -334,7 +350,7 @@ __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pr
 // issued UNR at a time as in slice_row_sum. off[] is the same for the whole
 // wave (scalar loads).
 template <typename TACC, int UNR, bool NT, typename TM, typename Gather>
-__device__ __forceinline__ TACC sdia_row_sum(GLOBAL const TM *vv, GLOBAL const int32_t *off, int32_t row, int32_t nmax,
+__device__ __forceinline__ TACC sdia_row_sum(GLOBAL const TM *vv, CONSTANT const int32_t *off, int32_t row, int32_t nmax,
                                              int wd, Gather gather) {
   TACC sum = 0;
   int k = 0;
@@ -373,16 +389,54 @@ __device__ __forceinline__ void sdia_rows(const Mat<TM> &M, int l, int G, Pre pr
   const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
   for (int k = w * NW + wv; k < s1 - s0; k += W * NW) {
     const int c = REV ? s1 - 1 - k : s0 + k;
-    const int o0 = M.blk[c], wd = M.blk[c + 1] - o0;
+    const int o0 = ro(M.blk)[c], wd = ro(M.blk)[c + 1] - o0;
     const int row = c * kSliceRows + lane;
     const bool has = row < M.n;
     RowVals<TACC> pv{};
     if (has) pv = pre(row);
     GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lane;
-    const TACC sum = (UW > 4 && wd > 4) ? sdia_row_sum<TACC, UW, NT>(vv, M.ci + o0, row, M.n - 1, wd, gather)
-                                        : sdia_row_sum<TACC, 4, NT>(vv, M.ci + o0, row, M.n - 1, wd, gather);
+    const TACC sum = (UW > 4 && wd > 4) ? sdia_row_sum<TACC, UW, NT>(vv, ro(M.ci) + o0, row, M.n - 1, wd, gather)
+                                        : sdia_row_sum<TACC, 4, NT>(vv, ro(M.ci) + o0, row, M.n - 1, wd, gather);
     if (has) epi(row, sum, pv);
   }
+}
+
+// sdia_rows with a workgroup step between the first slice's products and its
+// epilogue: every wave calls hook() exactly once (after the loop when it has
+// no slice), so hook may hold barriers; its result, the same in every thread,
+// says whether the walk goes on. A kernel that needs a reduction before its
+// epilogue (the G-kernel's beta) issues its first slice's loads and products
+// under that reduction's latency instead of after it.
+template <typename TACC, int UW, bool NT, bool REV, typename TM, typename Pre, typename Gather, typename Epi,
+          typename Hook>
+__device__ __forceinline__ bool sdia_rows_h(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi,
+                                            Hook hook) {
+  constexpr int NW = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = G >> 3, x = l & 7, w = l >> 3;
+  const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
+  // the first slice is peeled so that what hook needs is dead in the loop
+  auto slice = [&](int k, auto first) -> bool {
+    const int c = REV ? s1 - 1 - k : s0 + k;
+    const int o0 = ro(M.blk)[c], wd = ro(M.blk)[c + 1] - o0;
+    const int row = c * kSliceRows + lane;
+    const bool has = row < M.n;
+    RowVals<TACC> pv{};
+    if (has) pv = pre(row);
+    GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lane;
+    const TACC sum = (UW > 4 && wd > 4) ? sdia_row_sum<TACC, UW, NT>(vv, ro(M.ci) + o0, row, M.n - 1, wd, gather)
+                                        : sdia_row_sum<TACC, 4, NT>(vv, ro(M.ci) + o0, row, M.n - 1, wd, gather);
+    if constexpr (decltype(first)::value)
+      if (!hook()) return false;
+    if (has) epi(row, sum, pv);
+    return true;
+  };
+  int k = w * NW + wv;
+  if (k >= s1 - s0) return hook();
+  if (!slice(k, std::true_type{})) return false;
+  for (k += W * NW; k < s1 - s0; k += W * NW) slice(k, std::false_type{});
+  return true;
 }
 
 // ---- two rows per lane over sliced diagonals
@@ -465,53 +519,89 @@ __device__ __forceinline__ void ldval_pair(GLOBAL const _Float16 *p, int64_t k, 
 // The kernel's functors work on row pairs:
 //   pre2(r0, h0, h1) -> the pair's own operands (rows r0, r0 + 1; h0, h1:
 //                       whether each row exists),
-//   gather2(j0)      -> Pair<TACC>, the operands at columns j0, j0 + 1
-//                       (clamped, gather_pair),
-//   epi2(r0, h0, h1, sum0, sum1, pre_values).
+//   load2(j0)        -> what the operands at columns j0, j0 + 1 are made of
+//                       (clamped loads, gather_pair),
+//   comb2(loaded)    -> Pair<TACC>, those operands,
+//   epi2(r0, h0, h1, sum0, sum1, pre_values),
+//   hook()           -> a workgroup step, called by every wave exactly once:
+//                       after its first slice pair's loads are issued and
+//                       before anything uses them (after the loop when the
+//                       wave has no slice), so it may hold barriers and
+//                       compute what comb2 needs; its result, the same in
+//                       every thread, says whether the walk goes on.
 // n >= 2.
-template <typename TACC, bool NT, bool REV, typename TM, typename Pre2, typename Gather2, typename Epi2>
-__device__ __forceinline__ void sdia_rows2(const Mat<TM> &M, int l, int G, Pre2 pre2, Gather2 gather2, Epi2 epi2) {
+template <typename TACC, bool NT, bool REV, typename TM, typename Pre2, typename Load2, typename Comb2,
+          typename Epi2, typename Hook>
+__device__ __forceinline__ bool sdia_rows2(const Mat<TM> &M, int l, int G, Pre2 pre2, Load2 load2, Comb2 comb2,
+                                           Epi2 epi2, Hook hook) {
   constexpr int NW = kBlock / 64, U = 4;
   const int lane = threadIdx.x & 63, half = lane >> 5, lr = 2 * (lane & 31);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int W = G >> 3, x = l & 7, w = l >> 3;
   const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
   const int npairs = (s1 - s0 + 1) / 2;
-  for (int p = w * NW + wv; p < npairs; p += W * NW) {
+  // the first pair and its first chunk of entries are peeled so that what
+  // hook needs is dead in the loops
+  auto pair = [&](int p, auto first) -> bool {
     // slices ca (lanes 0-31) and cb = ca + 1 (lanes 32-63); at an odd end of
     // the range one of them lies outside it and its lanes idle on the other
     const int ca = REV ? s1 - 2 - 2 * p : s0 + 2 * p, cb = ca + 1;
     const bool va = ca >= s0, vb = cb < s1;
-    const int cs = half ? (vb ? cb : ca) : (va ? ca : cb);
+    // both slices' pointers and offsets are read whole-wave (scalar loads);
+    // each half selects its own slice (cb <= s1 <= nblk, so blk[cb] exists)
+    CONSTANT const int32_t *blk = ro(M.blk), *ci = ro(M.ci);
+    const int ob = blk[cb], oa = va ? blk[ca] : ob, oe = vb ? blk[cb + 1] : ob;
+    const int wa = ob - oa, wb = oe - ob;
+    const bool useb = half ? vb : !va;
     const bool live = half ? vb : va;
-    const int wa = va ? M.blk[ca + 1] - M.blk[ca] : 0, wb = vb ? M.blk[cb + 1] - M.blk[cb] : 0;
+    const int cs = useb ? cb : ca, o0 = useb ? ob : oa, wd = useb ? wb : wa;
     const int wmax = max(wa, wb);
-    const int o0 = M.blk[cs], wd = M.blk[cs + 1] - o0;
     const int r0 = cs * kSliceRows + lr;
     const bool h0 = live && r0 < M.n, h1 = live && r0 + 1 < M.n;
     const auto pv = pre2(r0, h0, h1);
     GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lr;
-    GLOBAL const int32_t *off = M.ci + o0;
     TACC sa = 0, sb = 0;
-    for (int e0 = 0; e0 < wmax; e0 += U) {
-      Pair<TACC> g[U];
+    auto chunk = [&](int e0, auto hk) -> bool {
+      decltype(load2(0)) g[U];
       TACC va_[U], vb_[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         // entries past this slice's width repeat its last (in bounds) and are not added
         const int e = max(min(e0 + u, wd - 1), 0);
-        g[u] = gather2(r0 + off[e]);
+        const int offa = wa > 0 ? ci[oa + max(min(e0 + u, wa - 1), 0)] : 0;
+        const int offb = wb > 0 ? ci[ob + max(min(e0 + u, wb - 1), 0)] : 0;
+        g[u] = load2(r0 + (useb ? offb : offa));
         ldval_pair<NT>(vv, (int64_t)e * kSliceRows, va_[u], vb_[u]);
       }
+      if constexpr (decltype(hk)::value)
+        if (!hook()) return false;
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (e0 + u < wd) {
-          sa += va_[u] * g[u].x;
-          sb += vb_[u] * g[u].y;
+          const Pair<TACC> o = comb2(g[u]);
+          sa += va_[u] * o.x;
+          sb += vb_[u] * o.y;
         }
+      return true;
+    };
+    int e0 = 0;
+    if constexpr (decltype(first)::value) {
+      if (wmax > 0) {
+        if (!chunk(0, std::true_type{})) return false;
+        e0 = U;
+      } else if (!hook()) {
+        return false;
+      }
     }
+    for (; e0 < wmax; e0 += U) chunk(e0, std::false_type{});
     epi2(r0, h0, h1, sa, sb, pv);
-  }
+    return true;
+  };
+  int p = w * NW + wv;
+  if (p >= npairs) return hook();
+  if (!pair(p, std::true_type{})) return false;
+  for (p += W * NW; p < npairs; p += W * NW) pair(p, std::false_type{});
+  return true;
 }
 
 // The two-row walk applies to a sliced-diagonal matrix of at least 2 rows
@@ -521,12 +611,12 @@ __device__ __forceinline__ bool rows2(const Mat<TM> &M) {
   return M.fmt == FMT_SDIA && M.n >= 2 && M.rpl == 2;
 }
 
-template <typename TACC, bool REV = false, typename TM, typename Pre2, typename Gather2, typename Epi2>
-__device__ __forceinline__ void for_rows2(const Mat<TM> &M, int l, int G, Pre2 pre2, Gather2 gather2, Epi2 epi2) {
-  if (M.temporal)
-    sdia_rows2<TACC, false, REV>(M, l, G, pre2, gather2, epi2);
-  else
-    sdia_rows2<TACC, true, REV>(M, l, G, pre2, gather2, epi2);
+template <typename TACC, bool REV = false, typename TM, typename Pre2, typename Load2, typename Comb2, typename Epi2,
+          typename Hook>
+__device__ __forceinline__ bool for_rows2(const Mat<TM> &M, int l, int G, Pre2 pre2, Load2 load2, Comb2 comb2,
+                                          Epi2 epi2, Hook hook) {
+  if (M.temporal) return sdia_rows2<TACC, false, REV>(M, l, G, pre2, load2, comb2, epi2, hook);
+  return sdia_rows2<TACC, true, REV>(M, l, G, pre2, load2, comb2, epi2, hook);
 }
 
 // Sliced 3x3-block rows: each wave takes whole slices of 21 block rows, one
@@ -559,7 +649,7 @@ __device__ __forceinline__ void bsr_rows(const Mat<TM> &M, int l, int G, Pre pre
   const int s0 = (int)((int64_t)x * M.nblk / 8), s1 = (int)((int64_t)(x + 1) * M.nblk / 8);
   const int sub = BL::sub(lane), r = BL::blockrow(lane);
   for (int c = s0 + w * NW + wv; c < s1; c += W * NW) {
-    const int o0 = M.blk[c], wd = M.blk[c + 1] - o0;
+    const int o0 = ro(M.blk)[c], wd = ro(M.blk)[c + 1] - o0;
     const int row = (c * kBSliceRows + r) * 3 + sub;
     const bool has = lane < SR && row < M.n;
     if (!has) continue;
@@ -611,6 +701,21 @@ __device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *l
     for_rows_as<TACC, UW, false, REV>(M, l, G, lds, pre, gather, epi);
   else
     for_rows_as<TACC, UW, true, REV>(M, l, G, lds, pre, gather, epi);
+}
+
+// for_rows with a workgroup step (hook, as in sdia_rows_h) before the first
+// epilogue: over sliced diagonals after the first slice's products, in the
+// other layouts before the walk. Returns hook's result.
+template <typename TACC, int UW = 4, typename TM, typename Pre, typename Gather, typename Epi, typename Hook>
+__device__ __forceinline__ bool for_rows_h(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather,
+                                           Epi epi, Hook hook) {
+  if (M.fmt == FMT_SDIA) {
+    if (M.temporal) return sdia_rows_h<TACC, UW, false, false>(M, l, G, pre, gather, epi, hook);
+    return sdia_rows_h<TACC, UW, true, false>(M, l, G, pre, gather, epi, hook);
+  }
+  if (!hook()) return false;
+  for_rows<TACC, UW>(M, l, G, lds, pre, gather, epi);
+  return true;
 }
 
 // ---- inner products
@@ -718,6 +823,13 @@ __device__ __forceinline__ void load_partials(GLOBAL const double *__restrict__ 
     for (int j = 0; j < NV; ++j) acc[j] = acc_add(acc[j], Acc{p[(int64_t)(2 * j) * P + k], p[(int64_t)(2 * j + 1) * P + k]});
 }
 
+// A value every lane holds alike, as a wave-uniform (scalar) value.
+__device__ __forceinline__ double uniform(double v) {
+  const uint64_t b = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b), hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 template <int NV>
 __device__ __forceinline__ void reduce_partials(Acc (&acc)[NV], double (&out)[NV], Acc *sh) {
   block_sum<NV>(acc, sh);
@@ -727,7 +839,7 @@ __device__ __forceinline__ void reduce_partials(Acc (&acc)[NV], double (&out)[NV
     for (int j = 0; j < NV; ++j) tot[j] = acc[j].hi + acc[j].lo;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < NV; ++j) out[j] = tot[j];
+  for (int j = 0; j < NV; ++j) out[j] = uniform(tot[j]);
 }
 
 template <int NV>
@@ -789,43 +901,52 @@ __global__ __launch_bounds__(kBlock) PCG_GT_OCCUPANCY void k_iter_GT(const SysDe
   }
   const int it = S.iter;
   if (mode == 3) mode = (S.rr_period > 0 && it > 0 && it % S.rr_period == 0) ? 1 : 0;
-  double alpha = S.alpha, gamma = S.gamma;
-  bool brk = false;
-  if (mode != 2) {
-    double gv[1];
-    reduce_partials<1>(g, gv, sh);
-    gamma = gv[0];
-    brk = !(gamma > 0.0) || !isfinite(gamma);
-    alpha = brk ? 0.0 : S.delta / gamma;  // on breakdown x already holds x_i
-  }
-  if (m.y == 0 && threadIdx.x == 0) {
-    State o = ld_state(&S);
-    o.gamma = gamma;
-    o.alpha = alpha;
-    if (brk) {
-      o.status = ST_BREAK_GAMMA;
-      o.done = 1;
-    }
-    st_state(st + 1, o);
-  }
-  if (brk) return;
+  const double delta = S.delta, alpha0 = S.alpha, gamma0 = S.gamma;
   const Mat<TG> GT = mat<TG>(D.GT);
   GLOBAL const TV *__restrict__ q = gl((const TV *)D.q);
   GLOBAL TV *__restrict__ t = gl((TV *)D.t);
-  const TV al = (mode == 0) ? (TV)alpha : (TV)0;
   GLOBAL const TV *__restrict__ src = gl((const TV *)((((mode == 1) ? it + 1 : it) & 1) ? D.r1 : D.r0));
   GLOBAL TV *__restrict__ dst = gl((TV *)(((it + 1) & 1) ? D.r1 : D.r0));
+  // alpha_i = delta_i / gamma_i (published in st[1] after the walk); false
+  // on breakdown
+  double alpha = alpha0, gamma = gamma0;
+  bool brk = false;
+  TV al = (TV)0;
+  auto step = [&]() -> bool {
+    if (mode != 2) {
+      double gv[1];
+      reduce_partials<1>(g, gv, sh);
+      gamma = gv[0];
+      brk = !(gamma > 0.0) || !isfinite(gamma);
+      alpha = brk ? 0.0 : delta / gamma;  // on breakdown x already holds x_i
+    }
+    al = (mode == 0) ? (TV)alpha : (TV)0;
+    return !brk;
+  };
+  auto publish = [&]() {
+    if (m.y == 0 && threadIdx.x == 0) {
+      State o = ld_state(&S);
+      o.gamma = gamma;
+      o.alpha = alpha;
+      if (brk) {
+        o.status = ST_BREAK_GAMMA;
+        o.done = 1;
+      }
+      st_state(st + 1, o);
+    }
+  };
   Acc part[2] = {{0.0, 0.0}, {0.0, 0.0}};
   // each die walks its slices from the top down (measured slightly faster);
   // two rows per lane over sliced diagonals where the operand is the
   // difference of two gathered vectors (the other kernels, with one, are
-  // faster one row per lane)
+  // faster one row per lane), with the first slice pair's loads in flight
+  // while alpha is reduced
   if (mode == 0 && rows2(GT)) {
     const int32_t n = GT.n;
     struct PV {
       Pair<TV> s, q;
     };
-    for_rows2<TV, true>(
+    const bool go = for_rows2<TV, true>(
         GT, m.y, D.GT.grid,
         [&](int r0, bool h0, bool h1) -> PV {
           PV o{{(TV)0, (TV)0}, {(TV)0, (TV)0}};
@@ -838,10 +959,8 @@ __global__ __launch_bounds__(kBlock) PCG_GT_OCCUPANCY void k_iter_GT(const SysDe
           }
           return o;
         },
-        [&](int32_t j0) -> Pair<TV> {
-          const Pair<TV> a = gather_pair(src, j0, n), c = gather_pair(q, j0, n);
-          return Pair<TV>{a.x - al * c.x, a.y - al * c.y};
-        },
+        [&](int32_t j0) -> PV { return PV{gather_pair(src, j0, n), gather_pair(q, j0, n)}; },
+        [&](const PV &v) -> Pair<TV> { return Pair<TV>{v.s.x - al * v.q.x, v.s.y - al * v.q.y}; },
         [&](int r0, bool h0, bool h1, TV s0, TV s1, const PV &pv) {
           const TV ra = pv.s.x - al * pv.q.x, rb = pv.s.y - al * pv.q.y;
           if (h1) {
@@ -857,8 +976,15 @@ __global__ __launch_bounds__(kBlock) PCG_GT_OCCUPANCY void k_iter_GT(const SysDe
             acc_prod(part[0], ra, ra);
             acc_prod(part[1], s0, s0);
           }
-        });
+        },
+        step);
+    publish();
+    if (!go) return;
+  } else if (!step()) {
+    publish();
+    return;
   } else if (mode == 0) {
+    publish();
     for_rows<TV, 4, true>(
         GT, m.y, D.GT.grid, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
         [&](int j) -> TV { return src[j] - al * q[j]; },
@@ -870,6 +996,7 @@ __global__ __launch_bounds__(kBlock) PCG_GT_OCCUPANCY void k_iter_GT(const SysDe
           acc_prod(part[1], sum, sum);
         });
   } else {
+    publish();
     for_rows<TV, 4, true>(
         GT, m.y, D.GT.grid, lds, [&](int row) { return RowVals<TV>{src[row], (TV)0, (TV)0}; },
         [&](int j) -> TV { return src[j]; },
@@ -883,7 +1010,7 @@ __global__ __launch_bounds__(kBlock) PCG_GT_OCCUPANCY void k_iter_GT(const SysDe
 }
 
 template <typename TV, typename TG, bool HAS_EPS>
-__global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_G(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
+__global__ __launch_bounds__(kBlock) PCG_G_OCCUPANCY void k_iter_G(const SysDev *__restrict__ dir, const int2 *__restrict__ map,
                                                    int mode) {
   __shared__ TV lds[kLdsBytes / sizeof(TV)];
   __shared__ Acc sh[4 * (kBlock / 64)];
@@ -900,26 +1027,71 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_G(const SysDev *_
     return;
   }
   const int it = S.iter;
-  double v[2];
-  reduce_partials<2>(va, v, sh);
-  const double rr = v[0], tt = v[1];
-  const double dn = tt + S.eps * rr;
+  const double delta = S.delta, eps_d = S.eps, tol_nb = S.tol_nb;
+  const int maxit = S.maxit;
   const int i1 = (mode == 2) ? it : it + 1;
+  // x_{i+1} = x_i + alpha_i d_i (not at a start or restart, mode 2)
+  const bool upd = mode != 2;
+  const TV ap = (TV)S.alpha;
+  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
+  GLOBAL const TV *__restrict__ dprev = gl((const TV *)((i1 & 1) ? D.d0 : D.d1));  // d_i
+  // s = G t + eps r, and the next direction d_{i+1} = s + beta d_i (at a
+  // start or restart beta = 0, d = s)
+  const Mat<TG> G = mat<TG>(D.G);
+  GLOBAL const TV *__restrict__ t = gl((const TV *)D.t);
+  GLOBAL const TV *__restrict__ rc = gl((const TV *)((i1 & 1) ? D.r1 : D.r0));
+  GLOBAL TV *__restrict__ dnext = gl((TV *)((i1 & 1) ? D.d1 : D.d0));
+  const TV eps = (TV)eps_d;
+  // delta_{i+1}, beta_i and the stopping tests, published in st[0]; false
+  // once the solve stops (then only x is updated)
+  TV beta = (TV)0;
+  double rr = 0.0, tt = 0.0, dn = 0.0;
   int status = ST_RUNNING;
-  if (mode != 2 && (!(dn >= 0.0) || !isfinite(dn)))
-    status = ST_BREAK_DELTA;
-  else if (sqrt(rr) <= S.tol_nb)
-    status = ST_CONV_REC;
-  else if (i1 >= S.maxit)
-    status = ST_MAXIT;
+  auto step = [&]() -> bool {
+    double v[2];
+    reduce_partials<2>(va, v, sh);
+    rr = v[0];
+    tt = v[1];
+    dn = tt + eps_d * rr;
+    if (mode != 2 && (!(dn >= 0.0) || !isfinite(dn)))
+      status = ST_BREAK_DELTA;
+    else if (sqrt(rr) <= tol_nb)
+      status = ST_CONV_REC;
+    else if (i1 >= maxit)
+      status = ST_MAXIT;
+    beta = (TV)((mode == 2) ? 0.0 : dn / delta);
+    return status == ST_RUNNING;
+  };
+  // the first slice's products are formed while the partials are reduced
+  bool go;
+  if (upd)
+    go = for_rows_h<TV>(
+        G, m.y, D.G.grid, lds,
+        [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], x[row]}; },
+        [&](int j) -> TV { return t[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          const TV sv = HAS_EPS ? sum + eps * pv.a : sum;
+          dnext[row] = sv + beta * pv.b;
+          x[row] = pv.c + ap * pv.b;
+        },
+        step);
+  else
+    go = for_rows_h<TV>(
+        G, m.y, D.G.grid, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], (TV)0}; },
+        [&](int j) -> TV { return t[j]; },
+        [&](int row, TV sum, const RowVals<TV> &pv) {
+          const TV sv = HAS_EPS ? sum + eps * pv.a : sum;
+          dnext[row] = sv + beta * pv.b;
+        },
+        step);
   if (m.y == 0 && threadIdx.x == 0) {
     State o = ld_state(&S);
     o.rr = rr;
     o.tt = tt;
     o.iter = i1;
-    o.alpha = 0.0;  // x += alpha_i d_i is applied below, whatever the status
+    o.alpha = 0.0;  // x += alpha_i d_i is applied in this kernel, whatever the status
     if (status != ST_BREAK_DELTA) {
-      o.beta = (mode == 2) ? 0.0 : dn / S.delta;
+      o.beta = (mode == 2) ? 0.0 : dn / delta;
       o.delta = dn;
     }
     if (status != ST_RUNNING) {
@@ -928,45 +1100,11 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_G(const SysDev *_
     }
     st_state(st, o);
   }
-  // x_{i+1} = x_i + alpha_i d_i (not at a start or restart, mode 2)
-  const bool upd = mode != 2;
-  const TV ap = (TV)S.alpha;
-  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
-  GLOBAL const TV *__restrict__ dprev = gl((const TV *)((i1 & 1) ? D.d0 : D.d1));  // d_i
-  if (status != ST_RUNNING) {
-    if (upd) {
-      int64_t i0, i1r;
-      ew_rows(D.n, m.y, D.G.grid, i0, i1r);
-      for (int64_t i = i0 + threadIdx.x; i < i1r; i += kBlock) x[i] = x[i] + ap * dprev[i];
-    }
-    return;
+  if (!go && upd) {  // stopped: x_{i+1} only
+    int64_t i0, i1r;
+    ew_rows(D.n, m.y, D.G.grid, i0, i1r);
+    for (int64_t i = i0 + threadIdx.x; i < i1r; i += kBlock) x[i] = x[i] + ap * dprev[i];
   }
-  // s = G t + eps r, and the next direction d_{i+1} = s + beta d_i (at a
-  // start or restart beta = 0, d = s)
-  const Mat<TG> G = mat<TG>(D.G);
-  GLOBAL const TV *__restrict__ t = gl((const TV *)D.t);
-  GLOBAL const TV *__restrict__ rc = gl((const TV *)((i1 & 1) ? D.r1 : D.r0));
-  GLOBAL TV *__restrict__ dnext = gl((TV *)((i1 & 1) ? D.d1 : D.d0));
-  const TV eps = (TV)S.eps;
-  const TV beta = (TV)((mode == 2) ? 0.0 : dn / S.delta);
-  if (upd)
-    for_rows<TV>(
-        G, m.y, D.G.grid, lds,
-        [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], x[row]}; },
-        [&](int j) -> TV { return t[j]; },
-        [&](int row, TV sum, const RowVals<TV> &pv) {
-          const TV sv = HAS_EPS ? sum + eps * pv.a : sum;
-          dnext[row] = sv + beta * pv.b;
-          x[row] = pv.c + ap * pv.b;
-        });
-  else
-    for_rows<TV>(
-        G, m.y, D.G.grid, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], (TV)0}; },
-        [&](int j) -> TV { return t[j]; },
-        [&](int row, TV sum, const RowVals<TV> &pv) {
-          const TV sv = HAS_EPS ? sum + eps * pv.a : sum;
-          dnext[row] = sv + beta * pv.b;
-        });
 }
 
 template <typename TV, typename TA>
