@@ -321,7 +321,7 @@ def section_small(pcg, inputs):
     a tiny system (kernels with almost no work)."""
     out = {"workload": "2D lognormal Poisson (sigma 1), FSAI G, FP64, tol 1e-8: three kernels per iteration "
                        "against one persistent workgroup per solve", "sizes": {}}
-    for N in (8, 32, 64, 91, 128, 181):
+    for N in (8, 16, 32, 45, 64, 91, 128, 181):
         A = inputs.poisson(2, N, 1.0, N)
         b = inputs.rhs(A.n, N)
         row = {"n": A.n}

@@ -66,6 +66,13 @@ enum Status : int32_t {
 #endif
 constexpr int kBlock = PCG_BLOCK_THREADS;  // threads per workgroup (waves of 64); also max rows per row block
 constexpr int kLdsBytes = PCG_LDS_BYTES;   // LDS staging for row products per workgroup
+// LDS the one-workgroup solver may take for a system's seven iteration
+// vectors: in a launch of many systems (FP64 up to 512 rows, FP32 up to
+// 1024), and for a single system (FP64 up to 2048 rows, FP32 up to 4096)
+// where the device allows it beside the kernel's static LDS (below 20 KiB)
+constexpr int kWgLdsVecBytes = 7 * 512 * 8;
+constexpr int kWgLdsVecBytesOne = 7 * 2048 * 8;
+constexpr int kWgStaticLdsBytes = 20480;
 
 inline int lds_cap(int vec_dtype) { return kLdsBytes / (int)dtype_size(vec_dtype); }
 
@@ -153,6 +160,10 @@ struct LaunchSet {
   const int32_t *set = nullptr;
   int32_t nA = 0, nGT = 0, nG = 0, nB = 0, nset = 0;  // workgroups of each kind, systems
   int32_t uw_a = 8;  // loads in flight per lane in the A-kernel's one-row sliced walks: 4 or 8
+  // rows of the set's largest system whose seven iteration vectors fit in
+  // the LDS cap with 8-byte and with 4-byte values (0: none): the
+  // one-workgroup solver's dynamic LDS
+  int32_t wg_lds_rows8 = 0, wg_lds_rows4 = 0;
 };
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------

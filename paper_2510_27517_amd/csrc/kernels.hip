@@ -1173,22 +1173,20 @@ __device__ __forceinline__ void wg_elementwise(int n, F f) {
   __syncthreads();
 }
 
-template <typename TV, typename TA, typename TG, bool HAS_EPS>
-__global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ dir, const int32_t *__restrict__ set) {
-  __shared__ TV lds[kLdsBytes / sizeof(TV)];
-  __shared__ Acc sh[4 * (kBlock / 64)];
-  const SysDev &D = dir[set[blockIdx.x]];
-  GLOBAL State *st = gl(D.st);
-  const State S0 = ld_state(st);
+// The solve of one system by this workgroup. The iteration vectors x, q, t,
+// r (two slots) and d (two slots) are reached through VP: global memory, or
+// the workgroup's LDS for a system small enough (then x is copied in and out
+// by the kernel). b, the matrices and the state stay in global memory. Both
+// placements run the same operations in the same order.
+template <typename TV, typename TA, typename TG, bool HAS_EPS, typename VP>
+__device__ __forceinline__ void solve_wg(const SysDev &D, GLOBAL State *st, const State &S0, TV *lds, Acc *sh, VP __restrict__ x,
+                                         VP __restrict__ q, VP __restrict__ t, VP r0, VP r1, VP d0, VP d1) {
   const int n = D.n;
   const Mat<TA> A = mat<TA>(D.A);
   const Mat<TG> GT = mat<TG>(D.GT), G = mat<TG>(D.G);
-  GLOBAL TV *__restrict__ x = gl((TV *)D.x);
   GLOBAL const TV *__restrict__ b = gl((const TV *)D.b);
-  GLOBAL TV *__restrict__ q = gl((TV *)D.q);
-  GLOBAL TV *__restrict__ t = gl((TV *)D.t);
-  GLOBAL TV *__restrict__ rv[2] = {gl((TV *)D.r0), gl((TV *)D.r1)};
-  GLOBAL TV *__restrict__ dv[2] = {gl((TV *)D.d0), gl((TV *)D.d1)};
+  VP rv[2] = {r0, r1};
+  VP dv[2] = {d0, d1};
   const double eps = S0.eps;
   const TV epsv = (TV)eps;
   // ||b||^2, tol ||b||
@@ -1220,7 +1218,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ 
   int status = ST_RUNNING;
   double delta = 0.0, rr = 0.0, tt = 0.0, true_rr = 0.0;
   // r_it = b - A x (true residual), its norm when `reduce`
-  auto residual = [&](GLOBAL TV *rout, bool reduce) {
+  auto residual = [&](VP rout, bool reduce) {
     Acc a[1] = {{0.0, 0.0}};
     wg_rows<TV, 4, false>(
         A, lds, [&](int row) { return RowVals<TV>{b[row], (TV)0, (TV)0}; }, [&](int j) -> TV { return x[j]; },
@@ -1236,7 +1234,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ 
   // start or restart from r_it: t = G^T r, rr, tt, delta, d_it = G t + eps r
   // (beta = 0 against the zeroed or previous direction buffer), stop tests
   auto restart = [&]() {
-    GLOBAL const TV *src = rv[it & 1];
+    const VP src = rv[it & 1];
     Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
     wg_rows<TV, 4, true>(
         GT, lds, [&](int row) { return RowVals<TV>{src[row], (TV)0, (TV)0}; }, [&](int j) -> TV { return src[j]; },
@@ -1256,8 +1254,8 @@ __global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ 
       status = ST_MAXIT;
     delta = dn;
     if (status != ST_RUNNING) return;
-    GLOBAL TV *dnext = dv[it & 1];
-    GLOBAL const TV *dprev = dv[(it + 1) & 1];
+    const VP dnext = dv[it & 1];
+    const VP dprev = dv[(it + 1) & 1];
     const TV beta = (TV)0.0;
     wg_rows<TV, 4, false>(
         G, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? src[row] : (TV)0, dprev[row], (TV)0}; },
@@ -1271,7 +1269,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ 
   restart();
   for (;;) {
     while (status == ST_RUNNING) {
-      GLOBAL const TV *dcur = dv[it & 1];
+      const VP dcur = dv[it & 1];
       // q = A d_i, gamma = d_i^T q
       double gamma;
       {
@@ -1293,7 +1291,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ 
       }
       const double alpha = delta / gamma;
       const TV al = (TV)alpha;
-      GLOBAL TV *rnext = rv[(it + 1) & 1];
+      const VP rnext = rv[(it + 1) & 1];
       const bool replace = S0.rr_period > 0 && it > 0 && it % S0.rr_period == 0;
       Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
       if (replace) {  // r_{i+1} = b - A (x_i + alpha_i d_i), then t = G^T r_{i+1}
@@ -1310,7 +1308,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ 
               acc_prod(a[1], sum, sum);
             });
       } else {  // r_{i+1} = r_i - alpha_i q, formed where it is gathered
-        GLOBAL const TV *src = rv[it & 1];
+        const VP src = rv[it & 1];
         wg_rows<TV, 4, true>(
             GT, lds, [&](int row) { return RowVals<TV>{src[row], q[row], (TV)0}; },
             [&](int j) -> TV { return src[j] - al * q[j]; },
@@ -1343,7 +1341,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ 
       }
       const TV beta = (TV)(dn / delta);
       delta = dn;
-      GLOBAL TV *dnext = dv[i1 & 1];
+      const VP dnext = dv[i1 & 1];
       wg_rows<TV, 4, false>(
           G, lds, [&](int row) { return RowVals<TV>{HAS_EPS ? rnext[row] : (TV)0, dcur[row], x[row]}; },
           [&](int j) -> TV { return t[j]; },
@@ -1373,6 +1371,41 @@ __global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ 
   o.delta = delta;
   o.true_rr = true_rr;
   if (threadIdx.x == 0) st_state(st, o);
+}
+
+// Iteration vectors in LDS: 7 n values (x, q, t, r0, r1, d0, d1).
+#define LDSP __attribute__((address_space(3)))
+constexpr int kWgVectors = 7;
+// the host sizes the dynamic LDS assuming at most this much static LDS
+static_assert(kLdsBytes + 4 * (kBlock / 64) * sizeof(Acc) + 2 * 8 * sizeof(double) <= kWgStaticLdsBytes,
+              "static LDS of the one-workgroup solver");
+
+// One workgroup per system of the set solves it whole. lds_vec_bytes: the
+// dynamic LDS of the launch; a system whose seven iteration vectors fit in it
+// keeps them there (a phase's gathers and stores then stay on the CU instead
+// of going through L2), any other keeps them in global memory.
+template <typename TV, typename TA, typename TG, bool HAS_EPS>
+__global__ __launch_bounds__(kBlock) void k_solve_wg(const SysDev *__restrict__ dir, const int32_t *__restrict__ set,
+                                                     int lds_vec_bytes) {
+  __shared__ TV lds[kLdsBytes / sizeof(TV)];
+  __shared__ Acc sh[4 * (kBlock / 64)];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  const SysDev &D = dir[set[blockIdx.x]];
+  GLOBAL State *st = gl(D.st);
+  const State S0 = ld_state(st);
+  const int n = D.n;
+  GLOBAL TV *__restrict__ xg = gl((TV *)D.x);
+  if ((int64_t)kWgVectors * n * (int64_t)sizeof(TV) <= lds_vec_bytes) {
+    LDSP TV *v = (LDSP TV *)dyn_lds;
+    wg_elementwise(n, [&](int64_t i) { v[i] = xg[i]; });
+    solve_wg<TV, TA, TG, HAS_EPS>(D, st, S0, lds, sh, v, v + n, v + 2 * n, v + 3 * n, v + 4 * n, v + 5 * n,
+                                  v + 6 * n);
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) xg[i] = v[i];
+  } else {
+    solve_wg<TV, TA, TG, HAS_EPS>(D, st, S0, lds, sh, xg, gl((TV *)D.q), gl((TV *)D.t), gl((TV *)D.r0),
+                                  gl((TV *)D.r1), gl((TV *)D.d0), gl((TV *)D.d1));
+  }
 }
 
 template <typename TV>
@@ -2051,11 +2084,14 @@ hipError_t launch_solve_wg(const Types &ty, const LaunchSet &L, bool has_eps, hi
 #define PCG_SOLVE_WG(TV, TG)                                                                                   \
   do {                                                                                                         \
     if (has_eps)                                                                                               \
-      hipLaunchKernelGGL((k_solve_wg<TV, TV, TG, true>), dim3(L.nset), dim3(kBlock), 0, s, L.dir, L.set);     \
+      hipLaunchKernelGGL((k_solve_wg<TV, TV, TG, true>), dim3(L.nset), dim3(kBlock), vec_bytes, s, L.dir,      \
+                         L.set, vec_bytes);                                                                    \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_solve_wg<TV, TV, TG, false>), dim3(L.nset), dim3(kBlock), 0, s, L.dir, L.set);    \
+      hipLaunchKernelGGL((k_solve_wg<TV, TV, TG, false>), dim3(L.nset), dim3(kBlock), vec_bytes, s, L.dir,     \
+                         L.set, vec_bytes);                                                                    \
   } while (0)
   if (!solve_wg_supported(ty)) return hipErrorInvalidValue;
+  const int vec_bytes = ty.vec == F64 ? kWgVectors * 8 * L.wg_lds_rows8 : kWgVectors * 4 * L.wg_lds_rows4;
   if (ty.vec == F64)
     PCG_SOLVE_WG(double, double);
   else if (ty.g == F32)

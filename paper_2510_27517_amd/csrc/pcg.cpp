@@ -783,6 +783,7 @@ struct pcg_ctx {
   bool own_stream = true;  // created here (destroyed with the context)
   DevAlloc da;
   int cus = 256;
+  int lds_per_block = 65536;  // the device's LDS bytes per workgroup
   std::string err;
   Types ty{};
 
@@ -932,6 +933,17 @@ int build_set(pcg_ctx *ctx, HostSet &hs, const std::vector<int> &slots) {
   L.nB = (int32_t)nB;
   L.set = (const int32_t *)(p + nmap);
   L.nset = (int32_t)slots.size();
+  // LDS for the one-workgroup solver's vectors: a set of one system may take
+  // what the device gives a workgroup beyond the kernel's static LDS; a set
+  // of many keeps to a share that leaves room for several workgroups per CU
+  const int64_t cap = slots.size() == 1
+                          ? std::min<int64_t>(pcgk::kWgLdsVecBytesOne, ctx->lds_per_block - pcgk::kWgStaticLdsBytes)
+                          : pcgk::kWgLdsVecBytes;
+  for (int sl : slots) {
+    const int32_t n = ctx->dir[sl].n;
+    if (7 * 8 * (int64_t)n <= cap) L.wg_lds_rows8 = std::max(L.wg_lds_rows8, n);
+    if (7 * 4 * (int64_t)n <= cap) L.wg_lds_rows4 = std::max(L.wg_lds_rows4, n);
+  }
   return PCG_OK;
 }
 
@@ -2428,8 +2440,10 @@ int pcg_create(const pcg_config *cfg, pcg_ctx **out) {
     ctx->static_scratch = nullptr;
   }
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess && prop.multiProcessorCount > 0)
+  if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess && prop.multiProcessorCount > 0) {
     ctx->cus = prop.multiProcessorCount;
+    ctx->lds_per_block = (int)prop.sharedMemPerBlock;
+  }
   if (cfg->stream) {
     ctx->stream = (hipStream_t)cfg->stream;
     ctx->own_stream = false;

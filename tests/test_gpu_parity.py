@@ -609,6 +609,56 @@ def test_pcg_block_fsai_elasticity(gpu_lib, N):
     assert r <= 1.0001e-10
 
 
+@pytest.mark.parametrize("case", ["band2", "band3", "band2048", "band2049", "restart1728", "eps_rr1000", "f32_4096",
+                                  "f32_4225"])
+def test_one_workgroup_lds_resident_vectors(gpu_lib, case):
+    """A single system whose seven iteration vectors fit in the workgroup's
+    LDS (FP64 up to 2048 rows, FP32 up to 4096, where the device gives a
+    workgroup that much) keeps them there for the whole one-workgroup solve.
+    On both sides of that bound, through restarts from the true residual,
+    residual replacement with the eps shift, and at 2 and 3 rows, the result
+    equals the three-kernel iteration's bit for bit, and the oracle's."""
+    import torch
+
+    pcg = gpu_lib
+    kw, ref_kw, tol, maxit = {}, {}, 1e-9, 3000
+    if case.startswith("band"):
+        n = int(case[4:])
+        A = _banded_spd(n, (1, 2, 7), n)
+    elif case == "restart1728":
+        A = inputs.poisson(3, 12, 2.5, 1)  # the oracle restarts once
+        kw = dict(rr_period=0)
+        ref_kw = dict(rr_period=0)
+        tol, maxit = 1e-13, 5000
+    elif case == "eps_rr1000":
+        A = inputs.poisson(3, 10, 1.0, 12)
+        kw = dict(eps=0.05, rr_period=7)
+        ref_kw = dict(eps=0.05, rr_period=7)
+    else:
+        A = inputs.poisson(2, 64 if case == "f32_4096" else 65, 0.5, 15)
+        kw = dict(vec_dtype="f32", a_dtype="f32", g_dtype="bf16")
+        tol = 1e-5
+    b = inputs.rhs(A.n, 11)
+    G = oracle.fsai_g(A)
+    outs = []
+    for wg in (-1, 100000):
+        with _solver(pcg, wg_max_n=wg, **kw) as s:
+            s.set_matrix(A)
+            s.set_precond(G)
+            outs.append(s.solve(b, tol=tol, maxit=maxit))
+    three, one = outs
+    lds = getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", None)
+    say(f"one-workgroup {case} n={A.n} (LDS per workgroup {lds}): {one.iters} it ({one.restarts} restarts) vs "
+        f"{three.iters}; {one.t_solve_ms:.2f} ms vs {three.t_solve_ms:.2f} ms")
+    assert one.status == three.status and one.iters == three.iters and one.restarts == three.restarts
+    assert np.array_equal(one.x, three.x)
+    if "vec_dtype" not in kw:
+        ref = oracle.pcg(A, G, b, tol=tol, maxit=maxit, delta_form=1, **ref_kw)
+        _check(one, ref)
+    if case == "restart1728":
+        assert one.restarts >= 1
+
+
 @pytest.mark.parametrize("case", ["poisson2d", "poisson3d_eps_rr", "rgg", "elasticity", "restart", "f32_bf16"])
 def test_one_workgroup_solver_equals_three_kernel_iteration(gpu_lib, case):
     """Small systems run as one persistent workgroup (the whole iteration in
