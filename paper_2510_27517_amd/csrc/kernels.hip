@@ -769,20 +769,42 @@ __device__ __forceinline__ Acc acc_add(Acc a, Acc b) {
   return r;
 }
 
-__device__ __forceinline__ Acc acc_shfl_xor(Acc a, int off) {
-  return Acc{__shfl_xor(a.hi, off), __shfl_xor(a.lo, off)};
+// One DPP move of a double (two 32-bit moves); lanes of rows outside
+// ROW_MASK receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ Acc acc_dpp(Acc a) {
+  return Acc{dpp_f64<CTRL, ROW_MASK>(a.hi), dpp_f64<CTRL, ROW_MASK>(a.lo)};
 }
 
-// Workgroup total of each value, in thread 0 (normalised).
+// Wave total of a double-double by DPP row operations, with no LDS traffic.
+// The two quad exchanges, the half-row mirror and the row mirror leave each
+// 16-lane row's total in all of its lanes. Two row broadcasts then carry
+// rows 0 to 2 into row 3, so lanes 48-63 hold the total.
+__device__ __forceinline__ Acc wave_total(Acc v) {
+  v = acc_add(v, acc_dpp<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+  v = acc_add(v, acc_dpp<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+  v = acc_add(v, acc_dpp<0x141, 0xF>(v));  // row_half_mirror
+  v = acc_add(v, acc_dpp<0x140, 0xF>(v));  // row_mirror
+  v = acc_add(v, acc_dpp<0x142, 0xA>(v));  // row_bcast:15 into rows 1 and 3
+  v = acc_add(v, acc_dpp<0x143, 0xC>(v));  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// Workgroup total of each value, in thread 0 (normalised); sh[0, NV NW).
 template <int NV>
 __device__ __forceinline__ void block_sum(Acc (&v)[NV], Acc *sh) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = acc_add(v[j], acc_shfl_xor(v[j], off));
+  for (int j = 0; j < NV; ++j) v[j] = wave_total(v[j]);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int NW = kBlock / 64;
-  if (lane == 0)
+  if (lane == 63)
 #pragma unroll
     for (int j = 0; j < NV; ++j) sh[j * NW + w] = v[j];
   __syncthreads();
@@ -830,16 +852,29 @@ __device__ __forceinline__ double uniform(double v) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// The wave totals meet in LDS after one barrier, and every thread adds them
+// in the same order. They sit in sh[2 NW, 2 NW + NV NW), apart from
+// block_sum's slots, so that a block_sum later in the kernel cannot
+// overwrite them while a slower wave still reads them; callers put a barrier
+// between two calls.
 template <int NV>
 __device__ __forceinline__ void reduce_partials(Acc (&acc)[NV], double (&out)[NV], Acc *sh) {
-  block_sum<NV>(acc, sh);
-  __shared__ double tot[NV];
-  if (threadIdx.x == 0)
+  static_assert(NV <= 2, "reduction slots");
+  constexpr int NW = kBlock / 64;
+  Acc *shr = sh + 2 * NW;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) tot[j] = acc[j].hi + acc[j].lo;
+  for (int j = 0; j < NV; ++j) acc[j] = wave_total(acc[j]);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 63)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) shr[j * NW + w] = acc[j];
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < NV; ++j) out[j] = uniform(tot[j]);
+  for (int j = 0; j < NV; ++j) {
+    Acc a = shr[j * NW];
+    for (int q = 1; q < NW; ++q) a = acc_add(a, shr[j * NW + q]);
+    out[j] = uniform(a.hi + a.lo);
+  }
 }
 
 template <int NV>
