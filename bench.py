@@ -212,9 +212,10 @@ def section_mixed(pcg, torch, A, G, b_dev, steps, t_fp64_ms):
                            "alg_bytes_per_iter": r32.bytes_per_iter}}, r.x.cpu().numpy()
 
 
-def section_autotune(pcg, torch, A, G, b_dev, steps, t_auto_ms):
+def section_autotune(pcg, torch, inputs, A, G, b_dev, steps, t_auto_ms):
     """The autotuner on the 128^3 FP64 system: layouts and grid it keeps, the
-    time it took, and timed solves with its choice."""
+    time it took, and timed solves with its choice; and the same on a
+    launch-bound 2D system of 32761 rows."""
     with pcg.Solver(pcg.default_config()) as s:
         s.set_matrix(A)
         s.set_precond(rowptr=G[0], col=G[1], val=G[2])
@@ -229,12 +230,40 @@ def section_autotune(pcg, torch, A, G, b_dev, steps, t_auto_ms):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
     names = {v: k for k, v in pcg.LAYOUTS.items()}
-    return {"workload": "poisson3d_128^3_sigma1_fsai, FP64, tol 1e-8", "tune_s": round(t_tune, 2),
-            "candidates": t["candidates"], "layout_a": names.get(t["layout_a"]), "layout_g": names.get(t["layout_g"]),
-            "grid_mult": t["grid_mult"], "temporal": t["temporal"], "rows_per_lane_gt": t["rows_per_lane_gt"],
-            "loads_in_flight_a": t["loads_in_flight_a"], "ms_per_iter_tuned": round(t["ms_per_iter"], 5),
-            "ms_per_iter_auto": round(t["ms_per_iter_auto"], 5), "time_to_tol_ms": round(ms, 3),
-            "time_to_tol_ms_auto": round(t_auto_ms, 3), "iters": r.iters, "status": r.status}
+    out = {"workload": "poisson3d_128^3_sigma1_fsai, FP64, tol 1e-8", "tune_s": round(t_tune, 2),
+           "candidates": t["candidates"], "layout_a": names.get(t["layout_a"]), "layout_g": names.get(t["layout_g"]),
+           "grid_mult": t["grid_mult"], "temporal": t["temporal"], "rows_per_lane_gt": t["rows_per_lane_gt"],
+           "loads_in_flight_a": t["loads_in_flight_a"], "ms_per_iter_tuned": round(t["ms_per_iter"], 5),
+           "ms_per_iter_auto": round(t["ms_per_iter_auto"], 5), "time_to_tol_ms": round(ms, 3),
+           "time_to_tol_ms_auto": round(t_auto_ms, 3), "iters": r.iters, "status": r.status}
+    # a launch-bound size, where fewer rows per lane (more busy waves) or
+    # fewer loads in flight can pay
+    As = inputs.poisson(2, 181, 1.0, 181)
+    bs = torch.from_numpy(inputs.rhs(As.n, 181)).to("cuda:0")
+    times = {}
+    for tag, tune in (("auto", False), ("tuned", True)):
+        with pcg.Solver(pcg.default_config(wg_max_n=-1)) as s:
+            s.set_matrix(As)
+            s.build_precond(pcg.G_FSAI)
+            if tune:
+                t0 = time.perf_counter()
+                ts = s.autotune(20)
+                t_tune_s = time.perf_counter() - t0
+            s.solve(bs, tol=TOL, maxit=MAXIT)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                rs = s.solve(bs, tol=TOL, maxit=MAXIT)
+            torch.cuda.synchronize()
+            times[tag] = (time.perf_counter() - t0) * 1e3 / 10
+    out["small"] = {"workload": "poisson2d_181^2_sigma1_fsai (32761 rows), FP64, tol 1e-8", "tune_s": round(t_tune_s, 2),
+                    "candidates": ts["candidates"], "layout_a": names.get(ts["layout_a"]),
+                    "layout_g": names.get(ts["layout_g"]), "grid_mult": ts["grid_mult"], "temporal": ts["temporal"],
+                    "rows_per_lane_gt": ts["rows_per_lane_gt"], "loads_in_flight_a": ts["loads_in_flight_a"],
+                    "ms_per_iter_tuned": round(ts["ms_per_iter"], 5), "ms_per_iter_auto": round(ts["ms_per_iter_auto"], 5),
+                    "time_to_tol_ms": round(times["tuned"], 3), "time_to_tol_ms_auto": round(times["auto"], 3),
+                    "iters": rs.iters, "status": rs.status}
+    return out
 
 
 def section_sai_loss(pcg, inputs, A, G, k, reps=3):
@@ -824,7 +853,7 @@ def main():
         extra["sai_loss"] = section_sai_loss(pcg, inputs, A, G, args.probes)
     if "autotune" in sections:
         log("autotune")
-        extra["autotune"] = section_autotune(pcg, torch, A, G, b_dev, max(3, args.steps // 2), ms_per_step)
+        extra["autotune"] = section_autotune(pcg, torch, inputs, A, G, b_dev, max(3, args.steps // 2), ms_per_step)
     if "small" in sections:
         log("small systems")
         extra["small"] = section_small(pcg, inputs)
