@@ -86,7 +86,7 @@ def stored_traffic(kernel):
     return float(m_b.group(1))
 
 
-def survey_bytes(n, a, g, sa, sg, sv, eps=False):
+def algorithmic_bytes(n, a, g, sa, sg, sv, eps=False):
     """Algorithmic bytes per launch of the three iteration kernels over int32
     CSR (4-byte column indices and row pointers): A-kernel a(sa + 4) + 4(n+1)
     + 2 n sv (reads d, writes q); G^T-kernel g(sg + 4) + 4(n+1) + 4 n sv
@@ -785,7 +785,7 @@ def main():
     log("kernel timing")
     kt = solver.time_kernels(args.kernel_iters)
     names = ["k_iter_A", "k_iter_GT", "k_iter_G"]
-    sv = survey_bytes(A.n, A.nnz, int(G[1].shape[0]), 8, 8, 8)
+    sv = algorithmic_bytes(A.n, A.nnz, int(G[1].shape[0]), 8, 8, 8)
     kernels = {name: {"avg_ms": kt["ms"][k], "layout_bytes": kt["bytes"][k], "alg_bytes": sv[k],
                       "alg_gbps": sv[k] / (kt["ms"][k] * 1e-3) / 1e9,
                       "layout_gbps": kt["bytes"][k] / (kt["ms"][k] * 1e-3) / 1e9}
