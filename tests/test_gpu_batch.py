@@ -398,6 +398,55 @@ def test_one_workgroup_systems_in_a_batch(gpu_lib):
         assert np.array_equal(x1, x2) and np.array_equal(x2, ref.x)
 
 
+def _banded(n, seed):
+    """Symmetric banded SPD matrix (offsets 1, 2, 7; uniform off-diagonal
+    values in (-1, -0.05); a dominant diagonal)."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for o in (o for o in (1, 2, 7) if o < n):
+        i = np.arange(0, n - o)
+        v = -rng.uniform(0.05, 1.0, n - o)
+        rows += [i, i + o]
+        cols += [i + o, i]
+        vals += [v, v]
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    m = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    d = np.asarray(abs(m).sum(axis=1)).ravel() + 0.5
+    return CSR.from_scipy((m + sp.diags(d)).tocsr())
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_one_workgroup_lds_bound_in_a_batch(gpu_lib, dt):
+    """In a batch the one-workgroup solver keeps a system's seven iteration
+    vectors in LDS up to 28,672 bytes (512 FP64 rows, 1024 FP32 rows) and in
+    global memory above that, both in the same launch. Systems on both sides
+    of the bound (and far from it) give their single solves' results bit for
+    bit, and in FP64 the oracle's."""
+    pcg = gpu_lib
+    ns = (300, 511, 512, 513, 1024, 1025, 3000)
+    kw = {} if dt == "f64" else dict(vec_dtype="f32", a_dtype="f32", g_dtype="f32")
+    tol = 1e-9 if dt == "f64" else 1e-5
+    systems = []
+    for k, n in enumerate(ns):
+        A = _banded(n, 70 + k)
+        systems.append(dict(A=A, b=inputs.rhs(n, 70 + k), G=oracle.fsai_g(A), tol=tol, maxit=2000))
+    with pcg.Solver(pcg.default_config(wg_max_n_batch=5000, **kw)) as s:
+        batch = s.solve_batch(systems, iters_per_step=5)
+    with pcg.Solver(pcg.default_config(wg_max_n=5000, **kw)) as s:
+        for sd, (xb, rb) in zip(systems, batch):
+            s.set_matrix(sd["A"])
+            s.set_precond(sd["G"])
+            single = s.solve(sd["b"], tol=sd["tol"], maxit=sd["maxit"])
+            say(f"lds bound {dt} n={sd['A'].n}: batch {rb['iters']} it, single {single.iters} it")
+            assert rb["status"] == single.status == pcg.OK
+            assert rb["iters"] == single.iters and np.array_equal(xb, single.x)
+            if dt == "f64":
+                ref = oracle.pcg(sd["A"], sd["G"], sd["b"], tol=tol, maxit=2000, delta_form=1)
+                assert ref.iters == single.iters and np.array_equal(ref.x, single.x)
+
+
 def test_batch_stats_device_time_and_bytes(gpu_lib):
     """pcg_batch_stats_get: the scheduler's iteration steps are timed on the
     device and their bytes are each system's iterations times its bytes per
