@@ -523,6 +523,9 @@ __device__ __forceinline__ void ldval_pair(GLOBAL const _Float16 *p, int64_t k, 
 //                       (clamped loads, gather_pair),
 //   comb2(loaded)    -> Pair<TACC>, those operands,
 //   epi2(r0, h0, h1, sum0, sum1, pre_values),
+// PRE_AT_DIAG: pre2 returns what load2(r0) would, on every row the epilogue
+// keeps, so a leading entry at offset 0 (a diagonal) reuses it instead of
+// loading the same operands again.
 //   hook()           -> a workgroup step, called by every wave exactly once:
 //                       after its first slice pair's loads are issued and
 //                       before anything uses them (after the loop when the
@@ -530,8 +533,8 @@ __device__ __forceinline__ void ldval_pair(GLOBAL const _Float16 *p, int64_t k, 
 //                       compute what comb2 needs; its result, the same in
 //                       every thread, says whether the walk goes on.
 // n >= 2.
-template <typename TACC, bool NT, bool REV, typename TM, typename Pre2, typename Load2, typename Comb2,
-          typename Epi2, typename Hook>
+template <typename TACC, bool NT, bool REV, bool PRE_AT_DIAG, typename TM, typename Pre2, typename Load2,
+          typename Comb2, typename Epi2, typename Hook>
 __device__ __forceinline__ bool sdia_rows2(const Mat<TM> &M, int l, int G, Pre2 pre2, Load2 load2, Comb2 comb2,
                                            Epi2 epi2, Hook hook) {
   constexpr int NW = kBlock / 64, U = 4;
@@ -570,7 +573,15 @@ __device__ __forceinline__ bool sdia_rows2(const Mat<TM> &M, int l, int G, Pre2 
         const int e = max(min(e0 + u, wd - 1), 0);
         const int offa = wa > 0 ? ci[oa + max(min(e0 + u, wa - 1), 0)] : 0;
         const int offb = wb > 0 ? ci[ob + max(min(e0 + u, wb - 1), 0)] : 0;
-        g[u] = load2(r0 + (useb ? offb : offa));
+        const int o = useb ? offb : offa;
+        if constexpr (PRE_AT_DIAG) {
+          if (e0 + u == 0 && o == 0)
+            g[u] = pv;  // a leading diagonal: the pair's own operands, already loaded
+          else
+            g[u] = load2(r0 + o);
+        } else {
+          g[u] = load2(r0 + o);
+        }
         ldval_pair<NT>(vv, (int64_t)e * kSliceRows, va_[u], vb_[u]);
       }
       if constexpr (decltype(hk)::value)
@@ -611,12 +622,12 @@ __device__ __forceinline__ bool rows2(const Mat<TM> &M) {
   return M.fmt == FMT_SDIA && M.n >= 2 && M.rpl == 2;
 }
 
-template <typename TACC, bool REV = false, typename TM, typename Pre2, typename Load2, typename Comb2, typename Epi2,
-          typename Hook>
+template <typename TACC, bool REV = false, bool PRE_AT_DIAG = false, typename TM, typename Pre2, typename Load2,
+          typename Comb2, typename Epi2, typename Hook>
 __device__ __forceinline__ bool for_rows2(const Mat<TM> &M, int l, int G, Pre2 pre2, Load2 load2, Comb2 comb2,
                                           Epi2 epi2, Hook hook) {
-  if (M.temporal) return sdia_rows2<TACC, false, REV>(M, l, G, pre2, load2, comb2, epi2, hook);
-  return sdia_rows2<TACC, true, REV>(M, l, G, pre2, load2, comb2, epi2, hook);
+  if (M.temporal) return sdia_rows2<TACC, false, REV, PRE_AT_DIAG>(M, l, G, pre2, load2, comb2, epi2, hook);
+  return sdia_rows2<TACC, true, REV, PRE_AT_DIAG>(M, l, G, pre2, load2, comb2, epi2, hook);
 }
 
 // Sliced 3x3-block rows: each wave takes whole slices of 21 block rows, one
@@ -981,7 +992,8 @@ __global__ __launch_bounds__(kBlock) PCG_GT_OCCUPANCY void k_iter_GT(const SysDe
     struct PV {
       Pair<TV> s, q;
     };
-    const bool go = for_rows2<TV, true>(
+    // pre2's pair equals gather_pair at offset 0 on every row that exists
+    const bool go = for_rows2<TV, true, true>(
         GT, m.y, D.GT.grid,
         [&](int r0, bool h0, bool h1) -> PV {
           PV o{{(TV)0, (TV)0}, {(TV)0, (TV)0}};
