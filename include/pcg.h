@@ -128,9 +128,11 @@ typedef struct {
   int wg_max_n;      /* single solves of at most this many rows (FP64, or FP32 vectors and A with an
                         FP32/BF16/FP16 G, no refinement) run as one persistent workgroup: the whole
                         solve in one launch, with no per-iteration launches or host round trips, and
-                        results bit for bit those of the three-kernel iteration. One workgroup has
-                        far less memory parallelism than a full launch, so this pays only for tiny
-                        systems. 0: the default (see pcg_config_default); -1: never */
+                        results bit for bit those of the three-kernel iteration. The iteration
+                        vectors stay in the workgroup's LDS when they fit (up to 2048 FP64 or 4096
+                        FP32 rows here, 512 or 1024 in a batch, where the device allows it). One
+                        workgroup has far less memory parallelism than a full launch, so this pays
+                        only for tiny systems. 0: the default (see pcg_config_default); -1: never */
   int wg_max_n_batch; /* the same for batched and served systems: those admitted in one scheduler
                         step run together, one workgroup each, in one launch on a second stream,
                         beside the iterations of the larger ones (many small systems keep the GPU
