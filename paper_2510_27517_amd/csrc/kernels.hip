@@ -349,16 +349,23 @@ __device__ __forceinline__ void sell_rows(const Mat<TM> &M, int l, int G, Pre pr
 // zero's column may fall outside), added left to right from zero; loads
 // issued UNR at a time as in slice_row_sum. off[] is the same for the whole
 // wave (scalar loads).
-template <typename TACC, int UNR, bool NT, typename TM, typename Gather>
+template <typename TACC, int UNR, bool NT, bool DIAG = false, typename TM, typename Gather>
 __device__ __forceinline__ TACC sdia_row_sum(GLOBAL const TM *vv, CONSTANT const int32_t *off, int32_t row, int32_t nmax,
-                                             int wd, Gather gather) {
+                                             int wd, Gather gather, TACC dg = 0) {
+  // DIAG: dg is the operand at the row's own column (offset 0), already
+  // loaded by the caller, so that entry is not gathered again
+  auto operand = [&](int32_t o) -> TACC {
+    if constexpr (DIAG) {
+      if (o == 0) return dg;
+    }
+    return gather(min(max(row + o, 0), nmax));
+  };
   TACC sum = 0;
   int k = 0;
   for (; k + UNR <= wd; k += UNR) {
     TACC p[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u)
-      p[u] = (TACC)ldval<NT>(vv, (k + u) * kSliceRows) * gather(min(max(row + off[k + u], 0), nmax));
+    for (int u = 0; u < UNR; ++u) p[u] = (TACC)ldval<NT>(vv, (k + u) * kSliceRows) * operand(off[k + u]);
 #pragma unroll
     for (int u = 0; u < UNR; ++u) sum += p[u];
   }
@@ -368,7 +375,7 @@ __device__ __forceinline__ TACC sdia_row_sum(GLOBAL const TM *vv, CONSTANT const
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int e = k + min(u, rem - 1);
-      p[u] = (TACC)ldval<NT>(vv, e * kSliceRows) * gather(min(max(row + off[e], 0), nmax));
+      p[u] = (TACC)ldval<NT>(vv, e * kSliceRows) * operand(off[e]);
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
@@ -380,7 +387,8 @@ __device__ __forceinline__ TACC sdia_row_sum(GLOBAL const TM *vv, CONSTANT const
 // Sliced-diagonal rows: the walk of sell_rows (whole slices per wave, one
 // lane per row, each die's eighth of the slices), with one column offset per
 // slice entry instead of one index per lane.
-template <typename TACC, int UW, bool NT, bool REV, typename TM, typename Pre, typename Gather, typename Epi>
+template <typename TACC, int UW, bool NT, bool REV, bool DIAG = false, typename TM, typename Pre, typename Gather,
+          typename Epi>
 __device__ __forceinline__ void sdia_rows(const Mat<TM> &M, int l, int G, Pre pre, Gather gather, Epi epi) {
   constexpr int NW = kBlock / 64;
   const int lane = threadIdx.x & 63;
@@ -395,8 +403,9 @@ __device__ __forceinline__ void sdia_rows(const Mat<TM> &M, int l, int G, Pre pr
     RowVals<TACC> pv{};
     if (has) pv = pre(row);
     GLOBAL const TM *vv = M.val + (int64_t)o0 * kSliceRows + lane;
-    const TACC sum = (UW > 4 && wd > 4) ? sdia_row_sum<TACC, UW, NT>(vv, ro(M.ci) + o0, row, M.n - 1, wd, gather)
-                                        : sdia_row_sum<TACC, 4, NT>(vv, ro(M.ci) + o0, row, M.n - 1, wd, gather);
+    const TACC sum = (UW > 4 && wd > 4)
+                         ? sdia_row_sum<TACC, UW, NT, DIAG>(vv, ro(M.ci) + o0, row, M.n - 1, wd, gather, pv.a)
+                         : sdia_row_sum<TACC, 4, NT, DIAG>(vv, ro(M.ci) + o0, row, M.n - 1, wd, gather, pv.a);
     if (has) epi(row, sum, pv);
   }
 }
@@ -691,13 +700,16 @@ __device__ __forceinline__ void bsr_rows(const Mat<TM> &M, int l, int G, Pre pre
 
 // All rows of this workgroup (local index l of the system's G workgroups),
 // in any layout, with the matrix's load policy.
-template <typename TACC, int UW, bool NT, bool REV, typename TM, typename Pre, typename Gather, typename Epi>
+// DIAG: pre(row).a is the gathered operand at column row (the sliced-diagonal
+// walk then reuses it for a diagonal entry).
+template <typename TACC, int UW, bool NT, bool REV, bool DIAG = false, typename TM, typename Pre, typename Gather,
+          typename Epi>
 __device__ __forceinline__ void for_rows_as(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather,
                                             Epi epi) {
   if (M.fmt == FMT_SELL) {
     sell_rows<TACC, UW, NT, REV>(M, l, G, pre, gather, epi);
   } else if (M.fmt == FMT_SDIA) {
-    sdia_rows<TACC, UW, NT, REV>(M, l, G, pre, gather, epi);
+    sdia_rows<TACC, UW, NT, REV, DIAG>(M, l, G, pre, gather, epi);
   } else if (M.fmt == FMT_BSR3) {
     bsr_rows<TACC, NT>(M, l, G, pre, gather, epi);
   } else {
@@ -706,12 +718,13 @@ __device__ __forceinline__ void for_rows_as(const Mat<TM> &M, int l, int G, TACC
   }
 }
 
-template <typename TACC, int UW = 4, bool REV = false, typename TM, typename Pre, typename Gather, typename Epi>
+template <typename TACC, int UW = 4, bool REV = false, bool DIAG = false, typename TM, typename Pre, typename Gather,
+          typename Epi>
 __device__ __forceinline__ void for_rows(const Mat<TM> &M, int l, int G, TACC *lds, Pre pre, Gather gather, Epi epi) {
   if (M.temporal)
-    for_rows_as<TACC, UW, false, REV>(M, l, G, lds, pre, gather, epi);
+    for_rows_as<TACC, UW, false, REV, DIAG>(M, l, G, lds, pre, gather, epi);
   else
-    for_rows_as<TACC, UW, true, REV>(M, l, G, lds, pre, gather, epi);
+    for_rows_as<TACC, UW, true, REV, DIAG>(M, l, G, lds, pre, gather, epi);
 }
 
 // for_rows with a workgroup step (hook, as in sdia_rows_h) before the first
@@ -920,7 +933,8 @@ __global__ __launch_bounds__(kBlock) PCG_OCCUPANCY void k_iter_A(const SysDev *_
   GLOBAL TV *__restrict__ q = gl((TV *)D.q);
   GLOBAL const TV *__restrict__ dcur = gl((const TV *)((it & 1) ? D.d1 : D.d0));  // d_i
   Acc part[1] = {{0.0, 0.0}};
-  for_rows<TV, UW>(
+  // pre's d_i[row] is the operand of A's diagonal
+  for_rows<TV, UW, false, true>(
       A, m.y, D.A.grid, lds, [&](int row) { return RowVals<TV>{dcur[row], (TV)0, (TV)0}; },
       [&](int j) -> TV { return dcur[j]; },
       [&](int row, TV sum, const RowVals<TV> &pv) {
