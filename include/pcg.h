@@ -137,9 +137,9 @@ typedef struct {
                         step run together, one workgroup each, in one launch on a second stream,
                         beside the iterations of the larger ones (many small systems keep the GPU
                         busy where one would not). 0: the default; -1: never */
-  int rows_per_lane; /* rows per lane of the G^T-kernel over sliced diagonals: 2 (every operand,
-                        value and result access twice as wide; the default) or 1. 0: the default.
-                        Results are the same bit for bit either way */
+  int rows_per_lane; /* rows per lane of the G^T- and G-kernels over sliced diagonals: 2 (every
+                        operand, value and result access twice as wide; the default) or 1. 0: the
+                        default. Results are the same bit for bit either way */
   int loads_in_flight; /* loads in flight per lane in the A-kernel's sliced rows of more than 4
                         entries: 8 (the default) or 4. 0: the default. Same results either way */
   /* Optional device allocator (for example a framework's caching allocator),
@@ -426,8 +426,8 @@ int pcg_build_g_host(int kind, uint64_t seed, int32_t n, const int32_t *rowptr, 
  * half and twice the grid, then the load policy (each subset of A, G, G^T
  * read with ordinary loads and kept in the memory-side cache, besides the
  * residency plan's choice), then two kernel knobs: rows per lane of the
- * G^T-kernel over sliced diagonals (two rows make every access twice as
- * wide, or one) and loads in flight per lane in the A-kernel's sliced rows
+ * G^T- and G-kernels over sliced diagonals (two rows make every access
+ * twice as wide, or one) and loads in flight per lane in the A-kernel's sliced rows
  * (8 or 4), and keeps the fastest (a candidate must beat the current best
  * by 3%).
  * The matrices are laid out again with the same values, so products stay
@@ -451,7 +451,8 @@ typedef struct {
                               3 sliced diagonals */
   int idx16;              /* bit 0/1/2: A / G / G^T keep 16-bit column differences */
   int temporal;           /* bit 0/1/2: A / G / G^T read with ordinary loads (cache-resident) */
-  int rows_per_lane_gt;   /* rows per lane of the G^T-kernel over sliced diagonals: 2 (default) or 1 */
+  int rows_per_lane_gt;   /* rows per lane of the G^T- and G-kernels over sliced diagonals: 2 (default)
+                             or 1 */
   int loads_in_flight_a;  /* loads in flight per lane of the A-kernel's sliced rows: 8 (default) or 4 */
   double ms_per_iter;      /* chosen configuration, one iteration */
   double ms_per_iter_auto; /* the automatic choice (NaN when taken from the cache) */

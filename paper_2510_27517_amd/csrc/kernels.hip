@@ -61,10 +61,10 @@ namespace pcgk {
 // spills), the occupancy its default grid of 4 workgroups of 4 waves per CU
 // gives anyway.
 #define PCG_GT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4)))
-// The G-kernel holds its first slice's operands and products while its
-// workgroup reduces the partial sums of the G^T-kernel: compiled for 6 waves
-// per SIMD (at most 80 VGPRs, no spills), above what its default grid fills.
-#define PCG_G_OCCUPANCY __attribute__((amdgpu_waves_per_eu(6)))
+// The G-kernel takes two rows per lane over sliced diagonals too and holds
+// its first slice pair's operands while its workgroup reduces the partial
+// sums of the G^T-kernel: compiled for 4 waves per SIMD like the G^T-kernel.
+#define PCG_G_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4)))
 
 #ifndef PCG_UNROLL
 #define PCG_UNROLL 4
@@ -1123,9 +1123,47 @@ __global__ __launch_bounds__(kBlock) PCG_G_OCCUPANCY void k_iter_G(const SysDev 
     beta = (TV)((mode == 2) ? 0.0 : dn / delta);
     return status == ST_RUNNING;
   };
-  // the first slice's products are formed while the partials are reduced
+  // the first slice's products are formed while the partials are reduced;
+  // two rows per lane over sliced diagonals (as in the G^T-kernel: one
+  // access of twice the width for each operand, value and result), one
+  // otherwise and at a start or restart
   bool go;
-  if (upd)
+  if (upd && rows2(G)) {
+    const int32_t n = G.n;
+    struct PV {
+      Pair<TV> r, d, x;
+    };
+    go = for_rows2<TV, false, false>(
+        G, m.y, D.G.grid,
+        [&](int r0, bool h0, bool h1) -> PV {
+          PV o{{(TV)0, (TV)0}, {(TV)0, (TV)0}, {(TV)0, (TV)0}};
+          if (h1) {
+            if (HAS_EPS) o.r = ld_pair(rc, r0);
+            o.d = ld_pair(dprev, r0);
+            o.x = ld_pair(x, r0);
+          } else if (h0) {
+            if (HAS_EPS) o.r.x = rc[r0];
+            o.d.x = dprev[r0];
+            o.x.x = x[r0];
+          }
+          return o;
+        },
+        [&](int32_t j0) -> Pair<TV> { return gather_pair(t, j0, n); },
+        [&](const Pair<TV> &v) -> Pair<TV> { return v; },
+        [&](int r0, bool h0, bool h1, TV s0, TV s1, const PV &pv) {
+          const TV sv0 = HAS_EPS ? s0 + eps * pv.r.x : s0, sv1 = HAS_EPS ? s1 + eps * pv.r.y : s1;
+          const TV dn0 = sv0 + beta * pv.d.x, dn1 = sv1 + beta * pv.d.y;
+          const TV x0 = pv.x.x + ap * pv.d.x, x1 = pv.x.y + ap * pv.d.y;
+          if (h1) {
+            st_pair(dnext, r0, dn0, dn1);
+            st_pair(x, r0, x0, x1);
+          } else if (h0) {
+            dnext[r0] = dn0;
+            x[r0] = x0;
+          }
+        },
+        step);
+  } else if (upd)
     go = for_rows_h<TV>(
         G, m.y, D.G.grid, lds,
         [&](int row) { return RowVals<TV>{HAS_EPS ? rc[row] : (TV)0, dprev[row], x[row]}; },

@@ -1049,6 +1049,7 @@ int single_sets(pcg_ctx *ctx) {
     ctx->single.dev.GT.temporal = (r >> 2) & 1;
     ctx->single.dev64.A.temporal = 0;
     ctx->single.dev.GT.rpl = ctx->tune.on ? ctx->tune.gt_rows : cfg_rows_per_lane(ctx->cfg);
+    ctx->single.dev.G.rpl = ctx->single.dev.GT.rpl;
   }
   ctx->single.dev.st = ctx->d_states + 2 * kSlotMain;
   ctx->dir[kSlotMain] = ctx->single.dev;
